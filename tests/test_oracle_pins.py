@@ -1,0 +1,358 @@
+"""Pins of the oracle against things other than itself.
+
+Each test checks the oracle against a value the paper prints, a closed form, a
+conservation identity, a symmetry, a textbook routine or brute force, chosen so
+that a dropped term, a wrong sign or index, or a transposed operand fails one of
+them.  CPU only.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import elder, newton, stats
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+DT = synth.MONTH_S
+
+
+def _load(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+# ---------------------------------------------------------------- counts ---
+
+def test_paper_grid_counts():
+    """Section 2.1: 524,288 hexahedra and 1,098,306 DoFs; Conclusion: 4,194,304 cells."""
+    g = _load("paper_counts.json")
+    ph = synth.physics()
+    nx, ny, nz = 129, 129, 33
+    assert (nx - 1) * (ny - 1) * (nz - 1) == g["box_coarse_hexahedra"]
+    assert 2 * nx * ny * nz == g["box_coarse_dofs"]
+    assert 256 * 256 * 64 == g["box_fine_cells"]
+    # equal spacing in all directions for the paper's box
+    box = elder.Box(5, 5, 2, ph)
+    assert box.h == (150.0, 150.0, 150.0)
+    assert math.isclose(g["box_steps"] * g["box_dt_years"], g["box_total_years"])
+
+
+def test_table1_and_rayleigh():
+    """Table 1 values; D_m = 3.565e-6 gives the Elder Rayleigh number 400."""
+    t = _load("table1.json")
+    ph = synth.physics()
+    for key in ("phi_mean", "K_mean", "g", "rho0", "rho1", "mu"):
+        assert ph[key] == t[key]
+    ra = ph["K_mean"] * (ph["rho1"] - ph["rho0"]) * ph["g"] * ph["lz"] / (
+        ph["phi_mean"] * ph["Dm"] * ph["mu"])
+    assert abs(ra - 400.0) < 0.05
+    ra_printed = ra * ph["Dm"] / t["Dm_printed"]
+    assert ra_printed > 2000  # the printed value would not be the Elder problem
+
+
+def test_kozeny_carman_normalisation():
+    """Section 2.2: the scaling constant makes K(E phi) = E K."""
+    ph = synth.physics(1)
+    assert elder.kozeny_carman(np.array(0.1), ph) == pytest.approx(4.845e-13, rel=1e-15)
+    # monotone and cubic for small phi
+    r = elder.kozeny_carman(np.array(0.02), ph) / elder.kozeny_carman(np.array(0.01), ph)
+    assert 8.0 < r < 8.2
+
+
+# -------------------------------------------------------------- jacobian ---
+
+@pytest.mark.parametrize("shape,model", [((5, 5, 2), 0), ((5, 5, 3), 2), ((7, 5, 3), 1),
+                                         ((5, 7, 4), 3)])
+def test_jacobian_is_complex_step_derivative(shape, model):
+    """Every entry of the analytic Jacobian equals the complex-step derivative of F."""
+    ph = synth.physics(model)
+    nx, ny, nz = shape
+    box = elder.Box(nx, ny, nz, ph)
+    xi = np.random.default_rng(7).uniform(-1, 1, synth.N_XI[model])
+    coef = elder.coefficients(box, xi)
+    u = synth.random_state(nx, ny, nz, ph, seed=11)
+    u_old = synth.random_state(nx, ny, nz, ph, seed=12)
+    J = elder.jacobian(box, coef, u, DT).toarray()
+    n = 2 * box.N
+    h = 1e-30
+    Jcs = np.zeros((n, n))
+    flat = u.reshape(-1).astype(complex)
+    for col in range(n):
+        uc = flat.copy()
+        uc[col] += 1j * h
+        Jcs[:, col] = elder.residual(box, coef, uc.reshape(u.shape), u_old, DT).imag.ravel() / h
+    scale = np.abs(J).max(axis=1, keepdims=True)
+    assert np.max(np.abs(J - Jcs) / scale) < 1e-13
+
+
+def test_stencil_is_27_point_2x2_block():
+    """Every row couples only the 3x3x3 vertex neighbourhood (2x2 blocks)."""
+    ph = synth.physics(2)
+    box = elder.Box(7, 7, 5, ph)
+    coef = elder.coefficients(box, [0.3, -0.2, 0.5, 0.1])
+    u = synth.random_state(7, 7, 5, ph, seed=3)
+    J = elder.jacobian(box, coef, u, DT).tocoo()
+    vr, vc = J.row // 2, J.col // 2
+    ir, jr, kr = vr % 7, (vr // 7) % 7, vr // 49
+    ic, jc, kc = vc % 7, (vc // 7) % 7, vc // 49
+    assert max(np.abs(ir - ic).max(), np.abs(jr - jc).max(), np.abs(kr - kc).max()) == 1
+    # an interior vertex row has all 27 neighbours
+    v = 3 + 7 * (3 + 7 * 2)
+    assert len(set(vc[vr == v])) == 27
+
+
+# ------------------------------------------------------- closed forms ------
+
+@pytest.mark.parametrize("model", [0, 2])
+def test_hydrostatic_state_is_a_fixed_point(model):
+    """c = 0 everywhere (patch switched off), p = rho0 g z: no flow, F = 0, and one
+    Newton-solved step returns the same state."""
+    ph = synth.physics(model, patch=(-10.0, -5.0, -10.0, -5.0))
+    nx, ny, nz = 9, 9, 3
+    box = elder.Box(nx, ny, nz, ph)
+    coef = elder.coefficients(box, [0.7, -0.4, 0.9, -1.0][:synth.N_XI[model]])
+    u = np.zeros((nz, ny, nx, 2))
+    u[..., 0] = ph["rho0"] * ph["g"] * box.z
+    F = elder.residual(box, coef, u, u, DT)
+    assert np.abs(F * elder.row_scale(box, DT)).max() < 1e-11
+    u1 = newton.newton_solve(box, coef, u, DT)
+    assert np.abs(u1[..., 1]).max() < 1e-13
+    assert np.abs(u1[..., 0] - u[..., 0]).max() < 1e-9 * ph["rho0"] * ph["g"] * ph["lz"]
+
+
+@pytest.mark.parametrize("c0", [0.0, 0.37, 1.0])
+def test_uniform_salt_is_consistent(c0):
+    """c = c0 everywhere, p = rho(c0) g z: both FV rows vanish at every vertex, i.e.
+    the salt flux is c0 times the liquid flux and gravity balances the pressure."""
+    ph = synth.physics(2)
+    box = elder.Box(9, 7, 5, ph)
+    coef = elder.coefficients(box, [0.5, 0.5, -0.5, 1.0])
+    rho = ph["rho0"] + (ph["rho1"] - ph["rho0"]) * c0
+    u = np.zeros((5, 7, 9, 2))
+    u[..., 0] = rho * ph["g"] * box.z
+    u[..., 1] = c0
+    Fl, Fs = elder.fv_rows(box, coef, u, u, DT)
+    s = elder.row_scale(box, DT)[..., 0]
+    assert np.abs(Fl * s).max() < 1e-11
+    assert np.abs(Fs * s).max() < 1e-11
+
+
+def _thomas(a, b, c, d):
+    """Textbook tridiagonal (Thomas) solve: a sub-, b main, c super-diagonal."""
+    n = len(b)
+    cp, dp = np.zeros(n), np.zeros(n)
+    cp[0], dp[0] = c[0] / b[0], d[0] / b[0]
+    for i in range(1, n):
+        m = b[i] - a[i] * cp[i - 1]
+        cp[i] = c[i] / m if i < n - 1 else 0.0
+        dp[i] = (d[i] - a[i] * dp[i - 1]) / m
+    x = np.zeros(n)
+    x[-1] = dp[-1]
+    for i in range(n - 2, -1, -1):
+        x[i] = dp[i] - cp[i] * x[i + 1]
+    return x
+
+
+def _heat_1d(nz, H, D, dt, n_steps):
+    """Implicit-Euler 3-point scheme (hz/dt)(c_k - c_k^old) = D (c_{k+1} - 2c_k + c_{k-1})/hz,
+    c_0 = 1, c_{nz-1} = 0, c = 0 initially inside."""
+    hz = H / (nz - 1)
+    c = np.zeros(nz)
+    c[0] = 1.0
+    r = D * dt / hz ** 2
+    n = nz - 2
+    for _ in range(n_steps):
+        rhs = c[1:-1].copy()
+        rhs[0] += r * 1.0
+        c[1:-1] = _thomas(np.full(n, -r), np.full(n, 1 + 2 * r), np.full(n, -r), rhs)
+    return c
+
+
+def test_thomas_heat_matches_fourier_series():
+    """The 1D reference converges to c = 1 - z/H - sum 2/(n pi) sin(n pi z/H) e^{-D n^2 pi^2 t/H^2}
+    at first order in dt (h^2 is negligible here)."""
+    H, D, T = 150.0, 1e-4, 4.0e7
+    z = np.linspace(0.0, H, 201)
+    exact = 1.0 - z / H
+    for n in range(1, 400):
+        exact -= 2.0 / (n * np.pi) * np.sin(n * np.pi * z / H) * np.exp(-D * n * n * np.pi ** 2 * T / H ** 2)
+    errs = []
+    for steps in (100, 200, 400):
+        c = _heat_1d(201, H, D, T / steps, steps)
+        errs.append(np.abs(c - exact).max())
+    assert errs[2] < 2e-3
+    assert 1.7 < errs[0] / errs[1] < 2.3 and 1.7 < errs[1] / errs[2] < 2.3
+
+
+@pytest.mark.parametrize("shape", [(5, 5, 9), (7, 5, 17)])
+def test_pure_diffusion_reduces_to_1d_scheme(shape):
+    """g = 0, rho1 = rho0, uniform phi, c = 1 on the whole top: the 3D solution is
+    independent of x, y and equals the 1D implicit-Euler three-point scheme."""
+    nx, ny, nz = shape
+    D, dt, steps = 1e-4, 2.0e6, 4
+    ph = synth.physics(0, g=0.0, rho1=1000.0, Dm=D, patch=(0.0, 600.0, 0.0, 600.0))
+    box = elder.Box(nx, ny, nz, ph)
+    coef = elder.coefficients(box, [])
+    u = np.zeros((nz, ny, nx, 2))
+    u[0, :, :, 1] = 1.0
+    for _ in range(steps):
+        u = newton.newton_solve(box, coef, u, dt)
+    ref = _heat_1d(nz, ph["lz"], D, dt, steps)
+    assert np.abs(u[..., 1] - ref[:, None, None]).max() < 1e-12
+    assert np.abs(u[..., 0]).max() < 1e-6
+
+
+# ------------------------------------------------------- conservation ------
+
+@pytest.mark.parametrize("model", [0, 2])
+def test_global_mass_balance(model):
+    """Interior face fluxes cancel and boundary faces carry none, so the change of
+    total salt (liquid) mass over a step equals dt times the FV rows summed over the
+    salt-Dirichlet (pressure-pinned) vertices, whose rows are not solved."""
+    ph = synth.physics(model)
+    nx, ny, nz = 9, 9, 5
+    box = elder.Box(nx, ny, nz, ph)
+    coef = elder.coefficients(box, [0.4, -0.9, 0.3, 0.8][:synth.N_XI[model]])
+    u0 = synth.initial_state(nx, ny, nz, ph)
+    u1 = newton.newton_solve(box, coef, u0, DT)
+    u2 = newton.newton_solve(box, coef, u1, DT)
+    Fl, Fs = elder.fv_rows(box, coef, u2, u1, DT)
+    m = elder.storage_weight(box, coef[0])
+    rho = lambda c: ph["rho0"] + (ph["rho1"] - ph["rho0"]) * c
+    c1, c2 = u1[..., 1], u2[..., 1]
+    dsalt = np.sum(m * (rho(c2) * c2 - rho(c1) * c1))
+    dliq = np.sum(m * (rho(c2) - rho(c1)))
+    cmask, _ = box.dirichlet_c()
+    pmask = box.pinned_p()
+    assert dsalt > 0  # brine enters through the patch
+    assert abs(DT * Fs[cmask].sum() - dsalt) <= 1e-9 * abs(dsalt)
+    assert abs(DT * Fl[pmask].sum() - dliq) <= 1e-9 * abs(dliq)
+    # the solved rows are zero
+    s = elder.row_scale(box, DT)[..., 0]
+    assert np.abs((Fs * s)[~cmask]).max() < 1e-11
+    assert np.abs((Fl * s)[~pmask]).max() < 1e-11
+
+
+# ------------------------------------------------------------- symmetry ----
+
+def test_box_symmetry_at_mean_parameters():
+    """At xi = 0 the box, the patch and the boundary data are invariant under
+    x -> 600 - x, y -> 600 - y and x <-> y; so is the solution after two steps."""
+    ph = synth.physics(0)
+    n = 9
+    box = elder.Box(n, n, 5, ph)
+    coef = elder.coefficients(box, [])
+    u = synth.initial_state(n, n, 5, ph)
+    for _ in range(2):
+        u = newton.newton_solve(box, coef, u, DT)
+    scale = np.array([ph["rho0"] * ph["g"] * ph["lz"], 1.0])
+    v = u / scale
+    assert np.abs(v - v[:, :, ::-1]).max() < 1e-10
+    assert np.abs(v - v[:, ::-1, :]).max() < 1e-10
+    assert np.abs(v - v.transpose(0, 2, 1, 3)).max() < 1e-10
+    assert u[..., 1].max() > 0.0 and np.abs(u[1, :, :, 1]).max() > 1e-3  # not trivial
+
+
+def test_cosine_field_symmetry():
+    """The one-mode field phi = 0.1(1 + 0.2 xi cos(pi x/600) cos(pi y/600)) is invariant
+    under the half-turn (x, y) -> (600 - x, 600 - y) and under x <-> y."""
+    ph = synth.physics(1)
+    n = 9
+    box = elder.Box(n, n, 5, ph)
+    coef = elder.coefficients(box, [0.8])
+    assert np.abs(coef[0] - coef[0][:, ::-1, ::-1]).max() < 1e-15
+    u = synth.initial_state(n, n, 5, ph)
+    for _ in range(2):
+        u = newton.newton_solve(box, coef, u, DT)
+    v = u / np.array([ph["rho0"] * ph["g"] * ph["lz"], 1.0])
+    assert np.abs(v - v[:, ::-1, ::-1]).max() < 1e-10
+    assert np.abs(v - v.transpose(0, 2, 1, 3)).max() < 1e-10
+    assert np.abs(v - v[:, :, ::-1]).max() > 1e-8  # the field breaks the single mirror
+
+
+# ------------------------------------------------------ linear algebra -----
+
+@pytest.mark.parametrize("shape", [(5, 5, 2), (5, 5, 3), (9, 9, 3)])
+def test_dense_and_sparse_newton_agree(shape):
+    """Newton with numpy.linalg.solve equals Newton with the sparse LU."""
+    ph = synth.physics(2)
+    nx, ny, nz = shape
+    box = elder.Box(nx, ny, nz, ph)
+    coef = elder.coefficients(box, [0.2, 0.6, -0.3, 0.9])
+    u0 = synth.initial_state(nx, ny, nz, ph)
+    a = newton.newton_solve(box, coef, u0, DT, dense=True)
+    b = newton.newton_solve(box, coef, u0, DT)
+    sc = np.array([ph["rho0"] * ph["g"] * ph["lz"], 1.0])
+    assert np.abs((a - b) / sc).max() < 1e-12
+
+
+def test_root_does_not_depend_on_start():
+    """The step's root near u^{n-1} is reached from different starting guesses."""
+    ph = synth.physics(2)
+    box = elder.Box(9, 9, 3, ph)
+    coef = elder.coefficients(box, [0.2, 0.6, -0.3, 0.9])
+    u0 = synth.initial_state(9, 9, 3, ph)
+    a = newton.newton_solve(box, coef, u0, DT)
+    start = u0.copy()
+    start[..., 0] += 500.0 * np.random.default_rng(1).standard_normal(start.shape[:3])
+    b = newton.newton_solve(box, coef, u0, DT, u0=start)
+    sc = np.array([ph["rho0"] * ph["g"] * ph["lz"], 1.0])
+    assert np.abs((a - b) / sc).max() < 1e-11
+
+
+# ---------------------------------------------------- upwinding ------------
+
+def _elder_extremes(nx, ny, nz, dt, steps):
+    ph = synth.physics(0)
+    box = elder.Box(nx, ny, nz, ph)
+    coef = elder.coefficients(box, [])
+    u = synth.initial_state(nx, ny, nz, ph)
+    for _ in range(steps):
+        u = newton.newton_solve(box, coef, u, dt, max_it=60)
+    return u[..., 1].min(), u[..., 1].max()
+
+
+def test_upwinding_keeps_salt_in_range():
+    """Implicit Euler with full upwinding keeps 0 <= c <= 1 (discrete maximum
+    principle), here over three 3-month steps."""
+    lo, hi = _elder_extremes(17, 17, 5, 3 * DT, 3)
+    assert lo > -1e-9 and hi < 1.0 + 1e-9
+
+
+def test_downwinding_would_violate_range(monkeypatch):
+    """Sensitivity of the previous pin: swapping upstream and downstream vertices
+    breaks the range after one 1-month step, so that pin detects the direction of
+    upwinding."""
+    monkeypatch.setattr(elder, "upwind_is_start", lambda Q: np.real(Q) < 0.0)
+    lo, hi = _elder_extremes(17, 17, 5, DT, 1)
+    assert lo < -1e-2 or hi > 1.0 + 1e-2
+
+
+# --------------------------------------------------------------- stats -----
+
+def test_moments_reduce_to_numpy():
+    """Equal weights: mean and population variance are numpy's mean and var, the
+    exceedance probability is the fraction of samples strictly above the threshold."""
+    rng = np.random.default_rng(5)
+    f = rng.random((37, 4, 5, 6))
+    f[3, 0, 0, 0] = 0.5  # a tie at the threshold counts as not exceeding
+    mean, var, exc = stats.moments(f, threshold=0.5)
+    assert np.allclose(mean, f.mean(0), rtol=1e-14, atol=0)
+    assert np.allclose(var, f.var(0), rtol=1e-12, atol=1e-16)
+    assert np.array_equal(np.round(exc * 37), (f > 0.5).sum(0))
+    assert exc[0, 0, 0] == pytest.approx(np.sum(np.delete(f[:, 0, 0, 0], 3) > 0.5) / 37, rel=1e-14)
+    w = rng.random(37)
+    w /= w.sum()
+    mean_w, var_w, _ = stats.moments(f, weights=w)
+    assert np.allclose(mean_w, np.average(f, axis=0, weights=w), rtol=1e-13)
+    assert np.allclose(var_w, np.average((f - mean_w) ** 2, axis=0, weights=w), rtol=1e-12)
+
+
+def test_injection_picks_nested_vertices():
+    f = np.arange(17 * 65 * 65, dtype=float).reshape(17, 65, 65)
+    g = stats.inject(f, (33, 33, 9))
+    assert g.shape == (9, 33, 33)
+    assert g[1, 2, 3] == f[2, 4, 6]
