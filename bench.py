@@ -1,0 +1,145 @@
+#!/usr/bin/env python3
+"""Throughput of the batched Elder-box time step on one MI355X.
+
+A step is one implicit-Euler time step (Newton + BiCGStab + multigrid V-cycles)
+of every sample of the workload.  `value` is sample-timesteps per second over K
+timed steps; the inputs (parameter fields, states, matrices) are resident in
+HBM before timing starts.  Prints one JSON line on stdout; progress goes to stderr.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "qMC sample-timesteps/s + V-cycle HBM GB/s, mixed vs FP64 at 1e-6 rel L2"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wl, phys, budget_s=20.0):
+    """The oracle (plain FP64 NumPy/SciPy, unchanged) on a bounded sample of the
+    workload: whole implicit-Euler steps of the samples of its smallest group."""
+    import numpy as np
+
+    import synth
+    from oracle import elder, newton
+    g = min(wl.groups, key=lambda q: q.n_vertices)
+    S0 = sum(q.samples for q in wl.groups[:wl.groups.index(g)])
+    box = elder.Box(g.nx, g.ny, g.nz, phys)
+    u0 = synth.initial_state(g.nx, g.ny, g.nz, phys)
+    done, t0 = 0, time.perf_counter()
+    while True:
+        xi = wl.xi[S0 + done] if wl.xi.shape[1] else []
+        newton.newton_solve(box, elder.coefficients(box, xi), u0, wl.dt, rtol=wl.newton_rtol)
+        done += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or done >= g.samples:
+            break
+    return {"value": done / el, "unit": "sample-timesteps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} sample(s) x 1 step (the first step) of the {g.nx}x{g.ny}x{g.nz} "
+                      f"group, {el:.1f} s; SuperLU and NumPy single-threaded; host "
+                      f"{os.cpu_count()} logical CPUs, {platform.processor() or platform.machine()}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="qmc512_mixedres")
+    ap.add_argument("--precision", choices=["f64", "mixed"], default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): samples are independent, "
+              "so N GPUs would each run their own share; no multi-GPU path is built.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1906_01632_amd import PREC_F64, PREC_MIXED, Problem
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    wl = synth.workload(args.workload)
+    prec = args.precision or wl.precision
+    phys = synth.physics(wl.field_model)
+    groups = [(g.nx, g.ny, g.nz, g.levels, g.samples) for g in wl.groups]
+    opts = dict(newton_rtol=wl.newton_rtol, lin_rtol=1e-6, lin_max_it=200, newton_max_it=20,
+                precision=PREC_MIXED if prec == "mixed" else PREC_F64, check_every=1)
+    log(f"workload {wl.name}: groups {groups}, precision {prec}")
+    t = time.perf_counter()
+    pb = Problem(phys, groups, opts)
+    pb.set_parameters(wl.xi)
+    log(f"set-up {time.perf_counter() - t:.1f} s")
+    for w in range(args.warmup):
+        t = time.perf_counter()
+        pb.step(wl.dt)
+        log(f"warmup step {w + 1}: {time.perf_counter() - t:.2f} s")
+    torch.cuda.synchronize()
+    if not args.no_profile:
+        pb.profile(True)
+    stats = None
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        stats = pb.step(wl.dt)
+        log(f"step {k + 1}: {time.perf_counter() - t0:.2f} s elapsed")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = pb.profile(False)
+    S = wl.n_samples
+    dofs = sum(2 * g.n_vertices * g.samples for g in wl.groups)
+    newton = np.mean([s["newton_its"] for s in stats])
+    lin = np.mean([s["lin_its"] / max(s["newton_its"], 1) for s in stats])
+    failed = sum(s["status"] != 0 for s in stats)
+    out = {
+        "metric": METRIC,
+        "value": S * args.steps / el,
+        "unit": "sample-timesteps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == "f64" else "f64+f32",
+        "data": "synthetic (seeded lattice parameters; no dataset)",
+        "config": {"workload": wl.name, "groups": [list(g) for g in groups], "samples": S,
+                   "dt_s": wl.dt, "precision": prec, "newton_rtol": wl.newton_rtol,
+                   "lin_rtol": 1e-6},
+        "dof_timesteps_per_s": dofs * args.steps / el,
+        "solver": {"newton_its_per_step": newton, "bicgstab_its_per_newton": lin,
+                   "failed_samples_last_step": failed},
+    }
+    if prof["launches"]:
+        gbs = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9
+        out["roofline"] = {"bound": "hbm", "kernel": "k_smooth (block Gauss-Seidel colour sweep)",
+                           "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                           "launches": prof["launches"],
+                           "avg_launch_us": 1e3 * prof["ms"] / prof["launches"],
+                           "bytes_per_launch": prof["bytes"] / prof["launches"]}
+    if not args.no_cpu_baseline:
+        log("oracle timing on the host ...")
+        out["cpu_baseline"] = cpu_baseline(wl, phys)
+    pb.destroy()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,203 @@
+/*
+ * edf.h — C-ABI of the Elder density-driven-flow solver for AMD Instinct MI355X (gfx950).
+ *
+ * The library advances many realisations ("samples") of the 3D Elder box problem
+ * by implicit-Euler time steps.  What one step computes is fixed by the paper
+ * (Litvinenko, Logashenko, Tempone, Wittum, Keyes, "Solution of the 3D density-driven
+ * groundwater flow problem with uncertain porosity and permeability", arXiv 1906.01632):
+ *
+ *   - the model: liquid mass conservation (eq. e_cont_eq), salt transport
+ *     (eq. e_tran_eq), Darcy's law (eq. e_Darcy_vel), isotropic K (eq. e_scalar_perm),
+ *     linear density (eq. e_lin_density), D = phi D_m (eq. e_mol_diff), Table 1;
+ *   - boundary conditions of the box (Section 2.1): c = 1 on the closed top patch,
+ *     c = 0 on the bottom, zero flux elsewhere, p = 0 at the four top corners;
+ *   - vertex-centred finite volumes with (p, c) at the grid nodes, implicit Euler,
+ *     Newton with a line search, BiCGStab preconditioned by a geometric multigrid
+ *     V-cycle whose coarse matrices are the Jacobians re-assembled on every grid
+ *     (Section 2.3 and Section 5.1 "Solving the deterministic problem");
+ *   - porosity/permeability samples and their statistics: mean (eq. pdestat),
+ *     variance (eq. numer_var), exceedance probability (Section 3.2).
+ *
+ * Conventions (all entry points):
+ *   - Units are SI; z is depth (k = 0 is the top face) and gravity points along +z.
+ *   - A grid has nx*ny*nz vertices, vertex v = i + nx*(j + ny*k).  A state or residual
+ *     is a double array [N][2] with (p, c) interleaved per vertex.
+ *   - Samples are numbered 0..S_total-1 across groups in the order the groups were
+ *     given to edf_create_problem.
+ *   - The library owns all device memory it allocates and frees it in edf_destroy.
+ *     Host arrays passed in are read before the call returns.  Device pointers
+ *     (is_device_ptr = 1) are borrowed for the duration of the call only.
+ *   - All device work is enqueued on the HIP stream given at creation.  Calls that
+ *     return values in host memory synchronise that stream before returning.
+ *   - A non-zero return is an error; edf_last_error gives its text.  Argument errors
+ *     (EDF_ERR_ARG) leave the problem unchanged.  Per-sample numerical failures are
+ *     reported in edf_step_stats.status and are not call failures unless every
+ *     sample failed (EDF_ERR_NO_CONVERGENCE).
+ *   - One problem must not be used from two host threads at once.
+ */
+#ifndef EDF_H
+#define EDF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct edf_problem edf_problem; /* opaque, library-owned */
+typedef int32_t edf_status;
+
+enum {
+  EDF_OK = 0,
+  EDF_ERR_ARG = 1,            /* invalid argument; nothing changed                  */
+  EDF_ERR_OOM = 2,            /* device or host allocation failed                   */
+  EDF_ERR_HIP = 3,            /* a HIP runtime call failed                          */
+  EDF_ERR_STATE = 4,          /* call out of order (e.g. step before set_parameters)*/
+  EDF_ERR_NO_CONVERGENCE = 5, /* every sample failed to converge in this call       */
+  EDF_ERR_NONFINITE = 6       /* a non-finite value was met                         */
+};
+
+/* per-sample status in edf_step_stats.status */
+enum {
+  EDF_SAMPLE_OK = 0,
+  EDF_SAMPLE_NEWTON_FAIL = 1, /* Newton reached its iteration limit                 */
+  EDF_SAMPLE_LINEAR_FAIL = 2, /* BiCGStab reached its limit in the last Newton step */
+  EDF_SAMPLE_NONFINITE = 3    /* the residual became NaN or Inf                     */
+};
+
+/* porosity/permeability field models (hex-centroid values, Section 2.2):
+ *  0 constant:  phi = phi_mean, K = K_mean
+ *  1 one mode:  phi = phi_mean (1 + 0.2 xi1 cos(pi x/lx) cos(pi y/ly)), K = KC(phi)
+ *  2 four modes: phi = phi_mean (1 + 0.2 xi1 cos cos + 0.2 xi2 sin(pi x/lx) sin(pi y/ly)),
+ *               ln K = ln KC(phi) + 0.5 xi3 cos(pi z/lz) + 0.5 xi4 sin(pi x/lx) cos(pi z/lz)
+ *  3 the paper's box field (eq. poro-paral3RVS):
+ *               phi = phi_mean + 0.01 (xi1 sx + xi2 sy + xi3 sz + xi1 sx sy + xi2 sx sz),
+ *               s* = sin(pi *_coord / l*), K = KC(phi)
+ * with KC(phi) = K_mean (phi/phi_mean)^3 ((1 - phi_mean)/(1 - phi))^2 (eq. e_perm_Kozeny_Carman,
+ * normalised so that KC(phi_mean) = K_mean). */
+enum { EDF_FIELD_CONST = 0, EDF_FIELD_COS1 = 1, EDF_FIELD_MODES4 = 2, EDF_FIELD_PAPER3 = 3 };
+
+enum { EDF_PREC_F64 = 0,   /* V-cycle in FP64                                       */
+       EDF_PREC_MIXED = 1  /* V-cycle in FP32 inside FP64 Newton/BiCGStab           */ };
+
+/* One resolution group: n_samples realisations on an nx*ny*nz vertex grid with an
+ * n_levels-grid multigrid hierarchy (each coarser grid keeps every other vertex, so
+ * (n-1) must be divisible by 2^(n_levels-1) in every direction). */
+typedef struct {
+  int32_t nx, ny, nz, n_levels, n_samples;
+} edf_group_desc;
+
+/* Physical constants (Table 1) and the top patch [patch[0],patch[1]] x [patch[2],patch[3]]. */
+typedef struct {
+  double lx, ly, lz;
+  double rho0, rho1, mu, g, Dm;
+  double phi_mean, K_mean;
+  double patch[4];
+  int32_t field_model, n_xi;
+} edf_physics;
+
+/* Solver options.  Residual norms are of the scaled residual: finite-volume rows
+ * times dt/(rho0 phi_mean hx hy hz), salt-Dirichlet rows as is, pinned-pressure
+ * rows divided by rho0*max(g,1)*lz.  Newton stops at ||F~|| <= max(newton_rtol
+ * ||F~_0||, newton_atol), or when the root-mean-square Newton update of the scaled
+ * unknowns (p / p_unit, c) is below 1e-14 (rounding level); BiCGStab stops at
+ * ||r|| <= lin_rtol ||b||. */
+typedef struct {
+  double newton_rtol, newton_atol, lin_rtol;
+  int32_t newton_max_it;   /* e.g. 20                                              */
+  int32_t ls_max_halvings; /* line search halvings, e.g. 5                         */
+  int32_t lin_max_it;      /* BiCGStab iterations per Newton step, e.g. 200        */
+  int32_t nu_pre, nu_post; /* block Gauss-Seidel sweeps before/after coarse grid   */
+  int32_t precision;       /* EDF_PREC_*                                           */
+  int32_t check_every;     /* BiCGStab iterations between host convergence checks  */
+  int32_t reserved[5];     /* must be zero                                         */
+} edf_solver_opts;
+
+typedef struct {
+  int32_t status;       /* EDF_SAMPLE_*                                            */
+  int32_t newton_its;   /* Newton iterations of the last step                      */
+  int32_t lin_its;      /* BiCGStab iterations summed over those Newton iterations */
+  int32_t ls_halvings;  /* line-search halvings summed over them                   */
+  double defect0;       /* ||F~|| at the start of the step                         */
+  double defect;        /* ||F~|| at the end of the step                           */
+} edf_step_stats;
+
+/* Creates a problem.  groups[n_groups] describe the resolution groups; every sample
+ * starts from the initial state (pure water, p = rho0 g z, c = 1 on the patch).
+ * hip_stream is a hipStream_t (NULL = the default stream).
+ * Errors: EDF_ERR_ARG for an inconsistent description, EDF_ERR_OOM, EDF_ERR_HIP. */
+edf_status edf_create_problem(const edf_physics* phys, const edf_group_desc* groups,
+                              int32_t n_groups, const edf_solver_opts* opts,
+                              void* hip_stream, edf_problem** out);
+
+/* Sets the porosity/permeability parameters of every sample: xi is a host array
+ * [S_total][phys.n_xi], row-major.  Computes phi and K on every grid level
+ * (Section 2.2).  EDF_ERR_ARG if some |xi| > 1 or a resulting phi is not in (0,1)
+ * or K is not finite and positive. */
+edf_status edf_set_parameters(edf_problem* pb, const double* xi);
+
+/* Copies a state [N][2] (p, c) of one sample in or out; the array is in host memory
+ * (is_device_ptr = 0) or device memory (1).  set_state also sets the previous-step
+ * state to the same values. */
+edf_status edf_set_state(edf_problem* pb, int32_t sample, const double* pc, int32_t is_device_ptr);
+edf_status edf_get_state(edf_problem* pb, int32_t sample, double* pc, int32_t is_device_ptr);
+
+/* Exactly one implicit-Euler step of length dt [s] for every sample.  stats, if not
+ * NULL, is a host array [S_total].  Synchronises when stats is not NULL. */
+edf_status edf_step(edf_problem* pb, double dt, edf_step_stats* stats);
+
+/* n_steps steps of length dt; stats (host [S_total] or NULL) describe the last step. */
+edf_status edf_solve(edf_problem* pb, double dt, int32_t n_steps, edf_step_stats* stats);
+
+/* Weighted statistics of c over the samples (eqs. pdestat, numer_var; Section 3.2):
+ * mean = sum w_i c_i, var = sum w_i (c_i - mean)^2, exceed = sum w_i [c_i > threshold].
+ * Every group is injected to the common vertex set (cx, cy, cz), which must be nested
+ * in every group's grid.  weights: host [S_total] or NULL for 1/S_total.  Samples whose
+ * last step failed are left out and the weights of the others renormalised.
+ * mean, var, exceed: host arrays [cx*cy*cz].  Synchronises. */
+edf_status edf_moments(edf_problem* pb, int32_t cx, int32_t cy, int32_t cz, double threshold,
+                       const double* weights, double* mean, double* var, double* exceed);
+
+/* Inspection entry points used by the parity tests. */
+
+/* Scaled residual F~(u; u_old) of one sample for dt, written to F [N][2] (same
+ * memory kind as u).  u, u_old, F: [N][2]; is_device_ptr applies to all three. */
+edf_status edf_residual(edf_problem* pb, int32_t sample, const double* u, const double* u_old,
+                        double dt, double* F, int32_t is_device_ptr);
+
+/* Assembles the scaled Jacobian of one sample at state u (host [N][2]) on grid level
+ * `level` (0 = finest; coarser levels use u injected) and copies it to host
+ * out[27][2][2][N_level]: entry (o, eq, var, v) = dF~_(v,eq) / du~_(v+o,var), where the
+ * neighbour offset o = (dx+1) + 3(dy+1) + 9(dz+1) and u~ = (p / p_unit, c).  Entries
+ * that point outside the grid are zero. */
+edf_status edf_get_jacobian(edf_problem* pb, int32_t sample, const double* u, double dt,
+                            int32_t level, double* out);
+
+/* Assembles the matrices of every level of group `group` at the group's current
+ * states for step length dt and applies one multigrid V-cycle y = M^{-1} x, where
+ * x and y are host arrays [S_group][N][2] of scaled unknowns (p / p_unit, c).
+ * The V-cycle is the preconditioner of the Newton systems (Section 2.3). */
+edf_status edf_apply_vcycle(edf_problem* pb, int32_t group, double dt, const double* x,
+                            double* y);
+
+/* y = J~ x with the finest-level matrices of group `group` from the last assembly
+ * (edf_apply_vcycle or a Newton iteration); x, y host [S_group][N][2]. */
+edf_status edf_apply_jacobian(edf_problem* pb, int32_t group, const double* x, double* y);
+
+/* Timing of the dominant kernel, the block Gauss-Seidel smoother of the V-cycle.
+ * edf_profile(pb, 1, out) starts: every later smoother launch is bracketed by HIP
+ * events on the problem's stream.  edf_profile(pb, 0, out) stops.  Both fill out (if
+ * not NULL, host double[3]) with the totals since the last start: out[0] = launches,
+ * out[1] = summed kernel time [ms], out[2] = algorithmic bytes, counted per vertex of
+ * the swept colour and per active sample as 108 stencil + 4 block-inverse entries +
+ * 2 right-hand side + 4 own-unknown reads and writes, times the V-cycle precision.
+ * Synchronises the stream. */
+edf_status edf_profile(edf_problem* pb, int32_t enable, double* out);
+
+const char* edf_last_error(const edf_problem* pb);
+void edf_destroy(edf_problem* pb); /* NULL is allowed */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EDF_H */

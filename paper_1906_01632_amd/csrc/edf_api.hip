@@ -1,0 +1,941 @@
+// C-ABI of the Elder-flow solver: problem set-up, the Newton / BiCGStab / V-cycle
+// drivers, state I/O and statistics.  Every numerical step runs in the kernels of
+// fv_kernels.hip, mg_kernels.hip and krylov_kernels.hip; this file only sizes
+// buffers, enqueues kernels on the caller's stream and makes the per-sample
+// decisions (convergence, line search) that need host control.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "edf.h"
+#include "edf_internal.h"
+
+using namespace edf;
+
+namespace {
+
+struct Level {
+  Geom g;
+  Phys ph;
+  size_t cells = 0;
+  double* phi = nullptr;  // [S][cells]
+  double* K = nullptr;
+  double* u = nullptr;    // state on this level [S][N][2] (level 0: the Newton iterate)
+  double* A64 = nullptr;  // [S][108][N] colour-major (level 0: exact Jacobian)
+  double* AV64 = nullptr; // level 0 in FP64 mode: the V-cycle matrix
+  float* A32 = nullptr;   // V-cycle matrix in mixed mode
+  void* Dinv = nullptr;   // [S][4][N], V-cycle precision
+  void* x = nullptr;      // V-cycle vectors [S][N][2], V-cycle precision
+  void* b = nullptr;
+  void* r = nullptr;
+};
+
+struct Group {
+  edf_group_desc d{};
+  int S = 0, s0 = 0, L = 0;
+  std::vector<Level> lv;
+  size_t N = 0, n = 0;  // finest vertices, unknowns
+  double *u = nullptr, *u_old = nullptr, *F = nullptr, *Ft = nullptr, *ut = nullptr;
+  double *kx = nullptr, *kr = nullptr, *krh = nullptr, *kp = nullptr, *kv = nullptr,
+         *ks_ = nullptr, *kt = nullptr, *kph = nullptr, *ksh = nullptr;
+  KrylovScalars* ks = nullptr;
+  double* part = nullptr;
+  int *nmask = nullptr, *active = nullptr, *lsmask = nullptr;
+  double *norms = nullptr, *lam = nullptr;
+  double* Minv = nullptr;
+  int *piv = nullptr, *gj_status = nullptr;
+  int n_coarse = 0;
+  int n_active = 0;  // samples active in the current Krylov chunk (known at chunk start)
+  std::vector<edf_step_stats> stats;
+};
+
+}  // namespace
+
+struct edf_problem {
+  edf_physics phys{};
+  edf_solver_opts opts{};
+  hipStream_t st = nullptr;
+  std::vector<Group> groups;
+  int S_total = 0;
+  bool params_set = false;
+  std::string err;
+  std::vector<void*> allocs;
+  // pinned host staging
+  int* h_int = nullptr;
+  double* h_dbl = nullptr;
+  KrylovScalars* h_ks = nullptr;
+  int h_cap = 0;
+  // smoother timing (edf_profile): event pairs around every smoother launch
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_ev;
+  std::vector<std::pair<int, double>> prof_pending;  // (event pair, algorithmic bytes)
+  double prof_launches = 0, prof_ms = 0, prof_bytes = 0;
+  // statistics buffers (allocated on first use)
+  double* mom_f = nullptr;
+  double* mom_w = nullptr;
+  double* mom_out = nullptr;
+  size_t mom_cap = 0;
+};
+
+namespace {
+
+#define EDF_TRY(expr)                                              \
+  do {                                                             \
+    hipError_t e_ = (expr);                                        \
+    if (e_ != hipSuccess) {                                        \
+      pb->err = std::string(#expr ": ") + hipGetErrorString(e_);   \
+      return EDF_ERR_HIP;                                          \
+    }                                                              \
+  } while (0)
+
+#define EDF_CHECK_LAUNCH()                                               \
+  do {                                                                   \
+    hipError_t e_ = hipGetLastError();                                   \
+    if (e_ != hipSuccess) {                                              \
+      pb->err = std::string("kernel launch: ") + hipGetErrorString(e_);  \
+      return EDF_ERR_HIP;                                                \
+    }                                                                    \
+  } while (0)
+
+edf_status fail(edf_problem* pb, edf_status code, const std::string& msg) {
+  if (pb) pb->err = msg;
+  return code;
+}
+
+template <typename T>
+edf_status dalloc(edf_problem* pb, T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return EDF_OK;
+  void* q = nullptr;
+  if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(pb, EDF_ERR_OOM, "device allocation of " + std::to_string(count * sizeof(T)) +
+                                     " bytes failed");
+  }
+  pb->allocs.push_back(q);
+  *p = static_cast<T*>(q);
+  return EDF_OK;
+}
+
+Geom make_geom(int nx, int ny, int nz, const edf_physics& P) {
+  Geom g{};
+  g.nx = nx;
+  g.ny = ny;
+  g.nz = nz;
+  g.N = nx * ny * nz;
+  g.hx = P.lx / (nx - 1);
+  g.hy = P.ly / (ny - 1);
+  g.hz = P.lz / (nz - 1);
+  int off = 0;
+  for (int col = 0; col < 8; ++col) {
+    const int ci = col & 1, cj = (col >> 1) & 1, ck = col >> 2;
+    const int mx = (nx - ci + 1) / 2, my = (ny - cj + 1) / 2, mz = (nz - ck + 1) / 2;
+    g.mx[col] = mx;
+    g.my[col] = my;
+    g.off[col] = off;
+    off += mx * my * mz;
+  }
+  g.off[8] = off;
+  const double tol = 1e-9 * std::max(P.lx, P.ly);
+  g.pi0 = std::max(0, (int)std::ceil((P.patch[0] - tol) / g.hx));
+  g.pi1 = std::min(nx - 1, (int)std::floor((P.patch[1] + tol) / g.hx));
+  g.pj0 = std::max(0, (int)std::ceil((P.patch[2] - tol) / g.hy));
+  g.pj1 = std::min(ny - 1, (int)std::floor((P.patch[3] + tol) / g.hy));
+  if (g.pj0 > g.pj1) g.pi0 = g.pi1 + 1;
+  return g;
+}
+
+double p_unit(const edf_physics& P) { return P.rho0 * std::max(P.g, 1.0) * P.lz; }
+
+Phys make_phys(const edf_physics& P, const Geom& g, double dt) {
+  Phys ph{};
+  ph.rho0 = P.rho0;
+  ph.drho = P.rho1 - P.rho0;
+  ph.mu = P.mu;
+  ph.g = P.g;
+  ph.Dm = P.Dm;
+  ph.dt = dt;
+  ph.s_row = dt / (P.rho0 * P.phi_mean * g.hx * g.hy * g.hz);
+  ph.p_unit = p_unit(P);
+  return ph;
+}
+
+// Newton also stops once the root-mean-square scaled update falls below this value:
+// the unknowns are O(1) in scaled units, so further iterations only move rounding.
+constexpr double kUpdateFloor = 1e-14;
+
+bool mixed(const edf_problem* pb) { return pb->opts.precision == EDF_PREC_MIXED; }
+
+edf_status ensure_pinned(edf_problem* pb, int count) {
+  if (count <= pb->h_cap) return EDF_OK;
+  if (pb->h_int) (void)hipHostFree(pb->h_int);
+  if (pb->h_dbl) (void)hipHostFree(pb->h_dbl);
+  if (pb->h_ks) (void)hipHostFree(pb->h_ks);
+  pb->h_int = nullptr;
+  pb->h_dbl = nullptr;
+  pb->h_ks = nullptr;
+  EDF_TRY(hipHostMalloc((void**)&pb->h_int, sizeof(int) * count));
+  EDF_TRY(hipHostMalloc((void**)&pb->h_dbl, sizeof(double) * count));
+  EDF_TRY(hipHostMalloc((void**)&pb->h_ks, sizeof(KrylovScalars) * count));
+  pb->h_cap = count;
+  return EDF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// allocation of one group
+// ---------------------------------------------------------------------------
+edf_status alloc_group(edf_problem* pb, Group& G) {
+  const edf_physics& P = pb->phys;
+  const int S = G.S;
+  const bool mx = mixed(pb);
+  const size_t tsz = mx ? sizeof(float) : sizeof(double);
+  G.lv.resize(G.L);
+  int nx = G.d.nx, ny = G.d.ny, nz = G.d.nz;
+  for (int l = 0; l < G.L; ++l) {
+    Level& L = G.lv[l];
+    L.g = make_geom(nx, ny, nz, P);
+    L.cells = (size_t)(nx - 1) * (ny - 1) * (nz - 1);
+    const size_t N = L.g.N;
+    edf_status s;
+    if ((s = dalloc(pb, &L.phi, S * L.cells))) return s;
+    if ((s = dalloc(pb, &L.K, S * L.cells))) return s;
+    if (l > 0 && (s = dalloc(pb, &L.u, S * 2 * N))) return s;
+    const bool coarsest = l == G.L - 1;
+    if (l == 0 || !mx || coarsest)
+      if ((s = dalloc(pb, &L.A64, S * kPlanes * N))) return s;
+    if (mx && !coarsest)
+      if ((s = dalloc(pb, &L.A32, S * kPlanes * N))) return s;
+    if (l == 0 && (!mx || coarsest))
+      if ((s = dalloc(pb, &L.AV64, S * kPlanes * N))) return s;
+    if (!coarsest) {
+      char* q;
+      if ((s = dalloc(pb, &q, S * 4 * N * tsz))) return s;
+      L.Dinv = q;
+      if ((s = dalloc(pb, &q, S * 2 * N * tsz))) return s;
+      L.r = q;
+    }
+    // V-cycle b and x: level 0 in FP64 mode uses the Krylov vectors directly
+    if (l > 0 || mx) {
+      char* q;
+      if ((s = dalloc(pb, &q, S * 2 * N * tsz))) return s;
+      L.b = q;
+      if ((s = dalloc(pb, &q, S * 2 * N * tsz))) return s;
+      L.x = q;
+    }
+    nx = (nx - 1) / 2 + 1;
+    ny = (ny - 1) / 2 + 1;
+    nz = (nz - 1) / 2 + 1;
+  }
+  G.N = G.lv[0].g.N;
+  G.n = 2 * G.N;
+  const size_t n = G.n;
+  edf_status s;
+  double** vecs[] = {&G.u,  &G.u_old, &G.F,  &G.Ft, &G.ut,  &G.kx,  &G.kr,
+                     &G.krh, &G.kp,   &G.kv, &G.ks_, &G.kt, &G.kph, &G.ksh};
+  for (double** v : vecs)
+    if ((s = dalloc(pb, v, S * n))) return s;
+  G.lv[0].u = G.u;
+  if ((s = dalloc(pb, &G.ks, (size_t)S))) return s;
+  const size_t nb = std::max<size_t>(reduce_blocks(n), ceil_div((int)G.N, kBlock));
+  if ((s = dalloc(pb, &G.part, S * nb * 4))) return s;
+  if ((s = dalloc(pb, &G.nmask, (size_t)S))) return s;
+  if ((s = dalloc(pb, &G.active, (size_t)S))) return s;
+  if ((s = dalloc(pb, &G.lsmask, (size_t)S))) return s;
+  if ((s = dalloc(pb, &G.norms, (size_t)S))) return s;
+  if ((s = dalloc(pb, &G.lam, (size_t)S))) return s;
+  G.n_coarse = 2 * G.lv[G.L - 1].g.N;
+  const size_t nc = G.n_coarse;
+  if ((s = dalloc(pb, &G.Minv, S * nc * nc))) return s;
+  if ((s = dalloc(pb, &G.piv, S * nc))) return s;
+  if ((s = dalloc(pb, &G.gj_status, (size_t)S))) return s;
+  G.stats.assign(S, edf_step_stats{});
+  return EDF_OK;
+}
+
+// initial state: p = rho0 g z, c = 1 on the patch, 0 elsewhere (host-built, uploaded)
+edf_status upload_initial(edf_problem* pb, Group& G) {
+  const Geom& g = G.lv[0].g;
+  std::vector<double> u(G.n);
+  for (int k = 0; k < g.nz; ++k)
+    for (int j = 0; j < g.ny; ++j)
+      for (int i = 0; i < g.nx; ++i) {
+        const size_t v = i + (size_t)g.nx * (j + (size_t)g.ny * k);
+        u[2 * v] = pb->phys.rho0 * pb->phys.g * k * g.hz;
+        const bool patch = k == 0 && i >= g.pi0 && i <= g.pi1 && j >= g.pj0 && j <= g.pj1;
+        u[2 * v + 1] = patch ? 1.0 : 0.0;
+      }
+  for (int s = 0; s < G.S; ++s) {
+    EDF_TRY(hipMemcpyAsync(G.u + s * G.n, u.data(), G.n * sizeof(double), hipMemcpyHostToDevice,
+                           pb->st));
+    EDF_TRY(hipMemcpyAsync(G.u_old + s * G.n, u.data(), G.n * sizeof(double),
+                           hipMemcpyHostToDevice, pb->st));
+  }
+  EDF_TRY(hipStreamSynchronize(pb->st));
+  return EDF_OK;
+}
+
+edf_status find_sample(edf_problem* pb, int sample, Group** G, int* local) {
+  for (Group& g : pb->groups)
+    if (sample >= g.s0 && sample < g.s0 + g.S) {
+      *G = &g;
+      *local = sample - g.s0;
+      return EDF_OK;
+    }
+  return fail(pb, EDF_ERR_ARG, "sample index out of range");
+}
+
+// ---------------------------------------------------------------------------
+// matrices of all levels at the current iterate
+// ---------------------------------------------------------------------------
+edf_status assemble_all(edf_problem* pb, Group& G, const int* mask) {
+  const bool mx = mixed(pb);
+  for (int l = 0; l < G.L; ++l) {
+    Level& L = G.lv[l];
+    if (l > 0) launch_inject(G.lv[l - 1].g, L.g, G.lv[l - 1].u, L.u, G.S, mask, pb->st);
+    const bool coarsest = l == G.L - 1;
+    if (l == 0)  // exact Jacobian for the Krylov products
+      launch_assemble(L.g, L.ph, L.phi, L.K, L.u, L.A64, nullptr, G.S, mask, pb->st, false);
+    // preconditioner matrix (frozen Darcy flux in the salt rows): FP32 on the smoothed
+    // levels in mixed mode, FP64 otherwise and always on the coarsest level
+    double* m64 = (mx && !coarsest) ? nullptr : (l == 0 ? L.AV64 : L.A64);
+    float* m32 = (mx && !coarsest) ? L.A32 : nullptr;
+    launch_assemble(L.g, L.ph, L.phi, L.K, L.u, m64, m32, G.S, mask, pb->st, true);
+    if (!coarsest) {
+      if (mx)
+        launch_block_inverse_f32(L.g, L.A32, (float*)L.Dinv, G.S, mask, pb->st);
+      else
+        launch_block_inverse_f64(L.g, m64, (double*)L.Dinv, G.S, mask, pb->st);
+    }
+  }
+  const Level& C = G.lv[G.L - 1];
+  launch_coarse_dense(C.g, G.L == 1 ? C.AV64 : C.A64, G.Minv, G.S, mask, pb->st);
+  launch_gauss_jordan(G.n_coarse, G.Minv, G.piv, G.gj_status, G.S, mask, pb->st);
+  EDF_CHECK_LAUNCH();
+  return EDF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// smoother timing
+// ---------------------------------------------------------------------------
+bool prof_pair(edf_problem* pb, hipEvent_t& a, hipEvent_t& b, double bytes) {
+  if (!pb->prof_on) return false;
+  const size_t k = pb->prof_pending.size();
+  while (pb->prof_ev.size() < 2 * (k + 1)) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return false;
+    pb->prof_ev.push_back(e);
+  }
+  a = pb->prof_ev[2 * k];
+  b = pb->prof_ev[2 * k + 1];
+  pb->prof_pending.push_back({(int)k, bytes});
+  return true;
+}
+
+edf_status prof_flush(edf_problem* pb) {
+  for (auto& r : pb->prof_pending) {
+    float ms = 0.f;
+    EDF_TRY(hipEventSynchronize(pb->prof_ev[2 * r.first + 1]));
+    EDF_TRY(hipEventElapsedTime(&ms, pb->prof_ev[2 * r.first], pb->prof_ev[2 * r.first + 1]));
+    pb->prof_launches += 1;
+    pb->prof_ms += ms;
+    pb->prof_bytes += r.second;
+  }
+  pb->prof_pending.clear();
+  return EDF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// one V-cycle: out = M^{-1} in (FP64 vectors of the scaled unknowns)
+// ---------------------------------------------------------------------------
+template <typename T>
+const T* stencil(const Level& L);
+template <>
+const double* stencil<double>(const Level& L) { return L.AV64 ? L.AV64 : L.A64; }
+template <>
+const float* stencil<float>(const Level& L) { return L.A32; }
+
+template <typename T>
+void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int* mask) {
+  hipStream_t st = pb->st;
+  const int S = G.S;
+  const int nu1 = pb->opts.nu_pre, nu2 = pb->opts.nu_post;
+  T* b0;
+  T* x0;
+  if constexpr (sizeof(T) == sizeof(double)) {
+    b0 = (T*)in;
+    x0 = (T*)out;
+  } else {
+    b0 = (T*)G.lv[0].b;
+    x0 = (T*)G.lv[0].x;
+    launch_cast_f64_to_f32(in, (float*)b0, G.n, S, mask, st);
+  }
+  // per vertex of the colour: 108 stencil + 4 block-inverse entries, b, x read and written
+  auto smooth = [&](const Level& L, int c, const T* b, T* x) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const double bytes = (double)(L.g.off[c + 1] - L.g.off[c]) * G.n_active * 118.0 * sizeof(T);
+    prof_pair(pb, e0, e1, bytes);
+    launch_smooth<T>(L.g, c, stencil<T>(L), (const T*)L.Dinv, b, x, S, mask, st, e0, e1);
+  };
+  auto bx = [&](int l, T*& b, T*& x) {
+    b = l == 0 ? b0 : (T*)G.lv[l].b;
+    x = l == 0 ? x0 : (T*)G.lv[l].x;
+  };
+  if (G.L == 1) {
+    launch_coarse_apply<T>(G.n_coarse, G.Minv, b0, x0, S, mask, st);
+  } else {
+    launch_fill<T>(x0, G.n, S, mask, T(0), st);
+    for (int l = 0; l < G.L - 1; ++l) {
+      Level& L = G.lv[l];
+      T *b, *x;
+      bx(l, b, x);
+      for (int it = 0; it < nu1; ++it)
+        for (int c = 0; c < 8; ++c) smooth(L, c, b, x);
+      launch_residual<T>(L.g, stencil<T>(L), b, x, (T*)L.r, S, mask, st);
+      T *bc, *xc;
+      bx(l + 1, bc, xc);
+      launch_restrict<T>(L.g, G.lv[l + 1].g, (const T*)L.r, bc, xc, S, mask, st);
+    }
+    {
+      T *b, *x;
+      bx(G.L - 1, b, x);
+      launch_coarse_apply<T>(G.n_coarse, G.Minv, b, x, S, mask, st);
+    }
+    for (int l = G.L - 2; l >= 0; --l) {
+      Level& L = G.lv[l];
+      T *b, *x, *bc, *xc;
+      bx(l, b, x);
+      bx(l + 1, bc, xc);
+      launch_prolong<T>(L.g, G.lv[l + 1].g, xc, x, S, mask, st);
+      for (int it = 0; it < nu2; ++it)
+        for (int c = 7; c >= 0; --c) smooth(L, c, b, x);
+    }
+  }
+  if constexpr (sizeof(T) != sizeof(double)) launch_cast_f32_to_f64((const float*)x0, out, G.n, S, mask, st);
+}
+
+void precondition(edf_problem* pb, Group& G, const double* in, double* out, const int* mask) {
+  if (mixed(pb))
+    vcycle<float>(pb, G, in, out, mask);
+  else
+    vcycle<double>(pb, G, in, out, mask);
+}
+
+// ---------------------------------------------------------------------------
+// BiCGStab on A x = F~ for the samples in G.nmask; x in G.kx
+// ---------------------------------------------------------------------------
+edf_status bicgstab(edf_problem* pb, Group& G) {
+  hipStream_t st = pb->st;
+  const int S = G.S;
+  const size_t n = G.n;
+  const Geom& g0 = G.lv[0].g;
+  const double* A = G.lv[0].A64;
+  launch_bicg_init(n, G.F, G.kx, G.kr, G.krh, G.kp, G.kv, G.part, G.ks, pb->opts.lin_rtol,
+                   G.active, S, G.nmask, st);
+  auto count_active = [&]() -> edf_status {
+    EDF_CHECK_LAUNCH();
+    EDF_TRY(hipMemcpyAsync(pb->h_int, G.active, S * sizeof(int), hipMemcpyDeviceToHost, st));
+    EDF_TRY(hipStreamSynchronize(st));
+    G.n_active = 0;
+    for (int s = 0; s < S; ++s) G.n_active += pb->h_int[s] != 0;
+    return prof_flush(pb);
+  };
+  edf_status e;
+  if ((e = count_active())) return e;
+  const int chunk = std::max(1, pb->opts.check_every);
+  for (int it = 0; it < pb->opts.lin_max_it && G.n_active > 0; it += chunk) {
+    for (int c = 0; c < chunk && it + c < pb->opts.lin_max_it; ++c) {
+      launch_bicg_p(n, G.kr, G.kv, G.kp, G.ks, S, G.active, st);
+      precondition(pb, G, G.kp, G.kph, G.active);
+      launch_bicg_alpha(g0, A, G.kph, G.kv, G.krh, G.part, G.ks, S, G.active, st);
+      launch_bicg_s(n, G.kr, G.kv, G.ks_, G.part, G.ks, S, G.active, st);
+      precondition(pb, G, G.ks_, G.ksh, G.active);
+      launch_bicg_omega(g0, A, G.ksh, G.ks_, G.kt, G.part, G.ks, S, G.active, st);
+      launch_bicg_update(n, G.kph, G.ksh, G.ks_, G.kt, G.krh, G.kx, G.kr, G.part, G.ks, G.active,
+                         S, G.active, st);
+    }
+    if ((e = count_active())) return e;
+  }
+  return EDF_OK;
+}
+
+edf_status read_norms(edf_problem* pb, Group& G, const double* F, const int* mask,
+                      std::vector<double>& out) {
+  launch_sq_norm(G.n, F, G.part, G.norms, G.S, mask, pb->st);
+  EDF_CHECK_LAUNCH();
+  EDF_TRY(hipMemcpyAsync(pb->h_dbl, G.norms, G.S * sizeof(double), hipMemcpyDeviceToHost, pb->st));
+  EDF_TRY(hipStreamSynchronize(pb->st));
+  out.resize(G.S);
+  for (int s = 0; s < G.S; ++s) out[s] = std::sqrt(pb->h_dbl[s]);
+  return EDF_OK;
+}
+
+edf_status upload_ints(edf_problem* pb, int* dst, const std::vector<int>& v) {
+  EDF_TRY(hipStreamSynchronize(pb->st));  // the staging buffer may still feed a copy
+  std::copy(v.begin(), v.end(), pb->h_int);
+  EDF_TRY(hipMemcpyAsync(dst, pb->h_int, v.size() * sizeof(int), hipMemcpyHostToDevice, pb->st));
+  EDF_TRY(hipStreamSynchronize(pb->st));
+  return EDF_OK;
+}
+
+edf_status upload_dbls(edf_problem* pb, double* dst, const std::vector<double>& v) {
+  EDF_TRY(hipStreamSynchronize(pb->st));
+  std::copy(v.begin(), v.end(), pb->h_dbl);
+  EDF_TRY(hipMemcpyAsync(dst, pb->h_dbl, v.size() * sizeof(double), hipMemcpyHostToDevice,
+                         pb->st));
+  EDF_TRY(hipStreamSynchronize(pb->st));
+  return EDF_OK;
+}
+
+void set_dt(edf_problem* pb, Group& G, double dt) {
+  for (Level& L : G.lv) L.ph = make_phys(pb->phys, L.g, dt);
+}
+
+// ---------------------------------------------------------------------------
+// one implicit-Euler step of a group: Newton with line search (Section 2.3)
+// ---------------------------------------------------------------------------
+edf_status newton_step(edf_problem* pb, Group& G, double dt) {
+  hipStream_t st = pb->st;
+  const int S = G.S;
+  const edf_solver_opts& o = pb->opts;
+  set_dt(pb, G, dt);
+  const Level& L0 = G.lv[0];
+  const double pu = p_unit(pb->phys);
+  EDF_TRY(hipMemcpyAsync(G.u_old, G.u, S * G.n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  launch_defect(L0.g, L0.ph, L0.phi, L0.K, G.u, G.u_old, G.F, S, nullptr, st);
+  std::vector<double> r, r0, rt;
+  edf_status e;
+  if ((e = read_norms(pb, G, G.F, nullptr, r))) return e;
+  r0 = r;
+  std::vector<int> nm(S, 1), ls(S);
+  std::vector<double> lam(S);
+  for (int s = 0; s < S; ++s) {
+    edf_step_stats& q = G.stats[s];
+    q = edf_step_stats{};
+    q.defect0 = r0[s];
+    q.defect = r0[s];
+    if (!std::isfinite(r0[s])) {
+      q.status = EDF_SAMPLE_NONFINITE;
+      nm[s] = 0;
+    }
+  }
+  for (int it = 0;; ++it) {
+    bool any = false;
+    for (int s = 0; s < S; ++s) {
+      if (!nm[s]) continue;
+      if (r[s] <= std::max(o.newton_rtol * r0[s], o.newton_atol)) {
+        nm[s] = 0;
+      } else if (it >= o.newton_max_it) {
+        nm[s] = 0;
+        G.stats[s].status = EDF_SAMPLE_NEWTON_FAIL;
+      } else {
+        any = true;
+      }
+    }
+    if (!any) break;
+    if ((e = upload_ints(pb, G.nmask, nm))) return e;
+    if ((e = assemble_all(pb, G, G.nmask))) return e;
+    if ((e = bicgstab(pb, G))) return e;
+    // BiCGStab statistics and the size of the Newton update
+    EDF_TRY(hipMemcpyAsync(pb->h_ks, G.ks, S * sizeof(KrylovScalars), hipMemcpyDeviceToHost, st));
+    std::vector<double> dnorm;
+    if ((e = read_norms(pb, G, G.kx, G.nmask, dnorm))) return e;
+    for (int s = 0; s < S; ++s)
+      if (nm[s]) {
+        G.stats[s].newton_its += 1;
+        G.stats[s].lin_its += pb->h_ks[s].it;
+      }
+    // line search on u - lambda * x  (x solves A x = F~, so the Newton step is -x)
+    double l = 1.0;
+    for (int s = 0; s < S; ++s) {
+      ls[s] = nm[s];
+      lam[s] = -1.0;
+    }
+    rt = r;
+    for (int h = 0; h <= o.ls_max_halvings; ++h) {
+      bool any_ls = false;
+      for (int s = 0; s < S; ++s) any_ls |= ls[s] != 0;
+      if (!any_ls) break;
+      if ((e = upload_ints(pb, G.lsmask, ls))) return e;
+      if ((e = upload_dbls(pb, G.lam, lam))) return e;
+      launch_axpy_state(G.N, G.u, G.kx, G.lam, pu, G.ut, S, G.lsmask, st);
+      launch_defect(L0.g, L0.ph, L0.phi, L0.K, G.ut, G.u_old, G.Ft, S, G.lsmask, st);
+      std::vector<double> rr;
+      if ((e = read_norms(pb, G, G.Ft, G.lsmask, rr))) return e;
+      for (int s = 0; s < S; ++s) {
+        if (!ls[s]) continue;
+        rt[s] = rr[s];
+        const bool ok = rr[s] <= (1.0 - l / 4.0) * r[s];
+        if (ok || h == o.ls_max_halvings) {
+          ls[s] = 0;
+        } else {
+          lam[s] *= 0.5;
+          G.stats[s].ls_halvings += 1;
+        }
+      }
+      l *= 0.5;
+    }
+    launch_masked_copy(G.n, G.ut, G.u, S, G.nmask, st);
+    launch_masked_copy(G.n, G.Ft, G.F, S, G.nmask, st);
+    for (int s = 0; s < S; ++s)
+      if (nm[s]) {
+        r[s] = rt[s];
+        G.stats[s].defect = rt[s];
+        if (!std::isfinite(rt[s])) {
+          G.stats[s].status = EDF_SAMPLE_NONFINITE;
+          nm[s] = 0;
+        } else if (std::fabs(lam[s]) * dnorm[s] <= kUpdateFloor * std::sqrt((double)G.n)) {
+          nm[s] = 0;  // the update is at the rounding level of the scaled unknowns: converged
+        }
+      }
+  }
+  EDF_CHECK_LAUNCH();
+  return EDF_OK;
+}
+
+edf_status check_ready(edf_problem* pb) {
+  if (!pb) return EDF_ERR_ARG;
+  if (!pb->params_set) return fail(pb, EDF_ERR_STATE, "edf_set_parameters has not been called");
+  return EDF_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+extern "C" {
+
+edf_status edf_create_problem(const edf_physics* phys, const edf_group_desc* groups,
+                              int32_t n_groups, const edf_solver_opts* opts, void* hip_stream,
+                              edf_problem** out) {
+  if (!out) return EDF_ERR_ARG;
+  *out = nullptr;
+  if (!phys || !groups || n_groups <= 0 || !opts) return EDF_ERR_ARG;
+  edf_problem* pb = new (std::nothrow) edf_problem();
+  if (!pb) return EDF_ERR_OOM;
+  pb->phys = *phys;
+  pb->opts = *opts;
+  pb->st = (hipStream_t)hip_stream;
+  const edf_physics& P = *phys;
+  auto bad = [&](const std::string& m) {
+    std::fprintf(stderr, "edf_create_problem: %s\n", m.c_str());
+    edf_destroy(pb);
+    return EDF_ERR_ARG;
+  };
+  if (!(P.lx > 0 && P.ly > 0 && P.lz > 0 && P.rho0 > 0 && P.rho1 > 0 && P.mu > 0 && P.g >= 0 &&
+        P.Dm >= 0 && P.phi_mean > 0 && P.phi_mean < 1 && P.K_mean > 0))
+    return bad("invalid physical constants");
+  const int nxi_needed[4] = {0, 1, 4, 3};
+  if (P.field_model < 0 || P.field_model > 3 || P.n_xi < nxi_needed[P.field_model] || P.n_xi > 16)
+    return bad("invalid field model or n_xi");
+  if (opts->precision != EDF_PREC_F64 && opts->precision != EDF_PREC_MIXED)
+    return bad("invalid precision");
+  if (opts->newton_max_it < 1 || opts->lin_max_it < 1 || opts->nu_pre < 1 || opts->nu_post < 0 ||
+      opts->ls_max_halvings < 0 || !(opts->lin_rtol > 0) || !(opts->newton_rtol >= 0))
+    return bad("invalid solver options");
+  for (int i = 0; i < 5; ++i)
+    if (opts->reserved[i] != 0) return bad("reserved options must be zero");
+  int s0 = 0;
+  for (int gi = 0; gi < n_groups; ++gi) {
+    const edf_group_desc& d = groups[gi];
+    if (d.n_levels < 1 || d.n_levels > 12 || d.n_samples < 1) return bad("invalid group");
+    const int r = 1 << (d.n_levels - 1);
+    if (d.nx < 2 || d.ny < 2 || d.nz < 2 || (d.nx - 1) % r || (d.ny - 1) % r || (d.nz - 1) % r)
+      return bad("grid size not divisible by 2^(n_levels-1)");
+    const long long nc = 2LL * ((d.nx - 1) / r + 1) * ((d.ny - 1) / r + 1) * ((d.nz - 1) / r + 1);
+    if (nc > kMaxCoarse) return bad("coarsest grid too large for the dense coarse solve");
+    if ((long long)d.nx * d.ny * d.nz * kPlanes > (1LL << 31)) return bad("grid too large");
+    Group G;
+    G.d = d;
+    G.S = d.n_samples;
+    G.s0 = s0;
+    G.L = d.n_levels;
+    s0 += G.S;
+    pb->groups.push_back(G);
+  }
+  pb->S_total = s0;
+  for (Group& G : pb->groups) {
+    edf_status s = alloc_group(pb, G);
+    if (s) {
+      std::fprintf(stderr, "edf_create_problem: %s\n", pb->err.c_str());
+      edf_destroy(pb);
+      return s;
+    }
+  }
+  int maxS = 0;
+  for (Group& G : pb->groups) maxS = std::max(maxS, G.S);
+  if (ensure_pinned(pb, std::max(maxS, pb->S_total)) != EDF_OK) {
+    edf_destroy(pb);
+    return EDF_ERR_HIP;
+  }
+  for (Group& G : pb->groups)
+    if (upload_initial(pb, G) != EDF_OK) {
+      edf_destroy(pb);
+      return EDF_ERR_HIP;
+    }
+  *out = pb;
+  return EDF_OK;
+}
+
+edf_status edf_set_parameters(edf_problem* pb, const double* xi) {
+  if (!pb) return EDF_ERR_ARG;
+  const int nxi = pb->phys.n_xi;
+  if (nxi > 0 && !xi) return fail(pb, EDF_ERR_ARG, "xi is NULL");
+  for (size_t e = 0; e < (size_t)pb->S_total * nxi; ++e)
+    if (!(std::fabs(xi[e]) <= 1.0)) return fail(pb, EDF_ERR_ARG, "|xi| > 1 or not finite");
+  FieldParams fp{pb->phys.lx, pb->phys.ly, pb->phys.lz, pb->phys.phi_mean, pb->phys.K_mean,
+                 pb->phys.field_model, nxi};
+  double* dxi = nullptr;
+  const size_t cnt = (size_t)pb->S_total * std::max(nxi, 1);
+  EDF_TRY(hipMalloc(&dxi, cnt * sizeof(double)));
+  std::vector<double> hx(cnt, 0.0);
+  if (nxi > 0) std::memcpy(hx.data(), xi, (size_t)pb->S_total * nxi * sizeof(double));
+  EDF_TRY(hipMemcpyAsync(dxi, hx.data(), cnt * sizeof(double), hipMemcpyHostToDevice, pb->st));
+  for (Group& G : pb->groups)
+    for (Level& L : G.lv)
+      launch_coefficients(L.g, fp, dxi + (size_t)G.s0 * std::max(nxi, 1), G.S, L.phi, L.K, pb->st);
+  EDF_CHECK_LAUNCH();
+  EDF_TRY(hipStreamSynchronize(pb->st));
+  EDF_TRY(hipFree(dxi));
+  // range check of phi and K on the finest grids (host copy per group, chunked per sample)
+  for (Group& G : pb->groups) {
+    const Level& L = G.lv[0];
+    std::vector<double> ph(L.cells), kk(L.cells);
+    for (int s = 0; s < G.S; ++s) {
+      EDF_TRY(hipMemcpy(ph.data(), L.phi + s * L.cells, L.cells * sizeof(double),
+                        hipMemcpyDeviceToHost));
+      EDF_TRY(hipMemcpy(kk.data(), L.K + s * L.cells, L.cells * sizeof(double),
+                        hipMemcpyDeviceToHost));
+      for (size_t e = 0; e < L.cells; ++e)
+        if (!(ph[e] > 0.0 && ph[e] < 1.0) || !(kk[e] > 0.0 && std::isfinite(kk[e])))
+          return fail(pb, EDF_ERR_ARG, "porosity outside (0,1) or permeability not positive");
+    }
+  }
+  pb->params_set = true;
+  return EDF_OK;
+}
+
+edf_status edf_set_state(edf_problem* pb, int32_t sample, const double* pc, int32_t is_dev) {
+  if (!pb || !pc) return EDF_ERR_ARG;
+  Group* G;
+  int s;
+  edf_status e;
+  if ((e = find_sample(pb, sample, &G, &s))) return e;
+  const hipMemcpyKind k = is_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  EDF_TRY(hipMemcpyAsync(G->u + s * G->n, pc, G->n * sizeof(double), k, pb->st));
+  EDF_TRY(hipMemcpyAsync(G->u_old + s * G->n, pc, G->n * sizeof(double), k, pb->st));
+  if (!is_dev) EDF_TRY(hipStreamSynchronize(pb->st));
+  return EDF_OK;
+}
+
+edf_status edf_get_state(edf_problem* pb, int32_t sample, double* pc, int32_t is_dev) {
+  if (!pb || !pc) return EDF_ERR_ARG;
+  Group* G;
+  int s;
+  edf_status e;
+  if ((e = find_sample(pb, sample, &G, &s))) return e;
+  const hipMemcpyKind k = is_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  EDF_TRY(hipMemcpyAsync(pc, G->u + s * G->n, G->n * sizeof(double), k, pb->st));
+  if (!is_dev) EDF_TRY(hipStreamSynchronize(pb->st));
+  return EDF_OK;
+}
+
+edf_status edf_step(edf_problem* pb, double dt, edf_step_stats* stats) {
+  edf_status e;
+  if ((e = check_ready(pb))) return e;
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(pb, EDF_ERR_ARG, "dt must be positive");
+  bool all_failed = true;
+  for (Group& G : pb->groups) {
+    if ((e = newton_step(pb, G, dt))) return e;
+    for (int s = 0; s < G.S; ++s) {
+      if (stats) stats[G.s0 + s] = G.stats[s];
+      all_failed &= G.stats[s].status != EDF_SAMPLE_OK;
+    }
+  }
+  if (all_failed) return fail(pb, EDF_ERR_NO_CONVERGENCE, "every sample failed in this step");
+  return EDF_OK;
+}
+
+edf_status edf_solve(edf_problem* pb, double dt, int32_t n_steps, edf_step_stats* stats) {
+  edf_status e;
+  if ((e = check_ready(pb))) return e;
+  if (n_steps < 0) return fail(pb, EDF_ERR_ARG, "n_steps < 0");
+  for (int n = 0; n < n_steps; ++n)
+    if ((e = edf_step(pb, dt, n + 1 == n_steps ? stats : nullptr))) return e;
+  EDF_TRY(hipStreamSynchronize(pb->st));
+  return EDF_OK;
+}
+
+edf_status edf_moments(edf_problem* pb, int32_t cx, int32_t cy, int32_t cz, double threshold,
+                       const double* weights, double* mean, double* var, double* exceed) {
+  if (!pb || !mean || !var || !exceed) return EDF_ERR_ARG;
+  if (cx < 2 || cy < 2 || cz < 2) return fail(pb, EDF_ERR_ARG, "common grid too small");
+  for (Group& G : pb->groups) {
+    const Geom& g = G.lv[0].g;
+    if ((g.nx - 1) % (cx - 1) || (g.ny - 1) % (cy - 1) || (g.nz - 1) % (cz - 1))
+      return fail(pb, EDF_ERR_ARG, "common grid not nested in every group");
+  }
+  const size_t Nc = (size_t)cx * cy * cz;
+  const int S = pb->S_total;
+  std::vector<double> w(S);
+  double sum = 0.0;
+  for (Group& G : pb->groups)
+    for (int s = 0; s < G.S; ++s) {
+      const double ws = weights ? weights[G.s0 + s] : 1.0 / S;
+      w[G.s0 + s] = G.stats[s].status == EDF_SAMPLE_OK ? ws : 0.0;
+      sum += w[G.s0 + s];
+    }
+  if (!(sum > 0)) return fail(pb, EDF_ERR_NO_CONVERGENCE, "no valid sample");
+  for (double& x : w) x /= sum;
+  const size_t need = Nc * (S + 3) + S;
+  if (need > pb->mom_cap) {
+    if (pb->mom_f) (void)hipFree(pb->mom_f);
+    pb->mom_f = nullptr;
+    EDF_TRY(hipMalloc(&pb->mom_f, need * sizeof(double)));
+    pb->mom_cap = need;
+  }
+  double* f = pb->mom_f;
+  double* dw = f + Nc * S;
+  double* out = dw + S;
+  EDF_TRY(hipMemcpyAsync(dw, w.data(), S * sizeof(double), hipMemcpyHostToDevice, pb->st));
+  for (Group& G : pb->groups)
+    launch_gather_common(G.lv[0].g, cx, cy, cz, G.u, f + (size_t)G.s0 * Nc, G.S, pb->st);
+  launch_moments((int)Nc, S, f, dw, threshold, out, out + Nc, out + 2 * Nc, pb->st);
+  EDF_CHECK_LAUNCH();
+  EDF_TRY(hipMemcpyAsync(mean, out, Nc * sizeof(double), hipMemcpyDeviceToHost, pb->st));
+  EDF_TRY(hipMemcpyAsync(var, out + Nc, Nc * sizeof(double), hipMemcpyDeviceToHost, pb->st));
+  EDF_TRY(hipMemcpyAsync(exceed, out + 2 * Nc, Nc * sizeof(double), hipMemcpyDeviceToHost, pb->st));
+  EDF_TRY(hipStreamSynchronize(pb->st));
+  return EDF_OK;
+}
+
+edf_status edf_residual(edf_problem* pb, int32_t sample, const double* u, const double* u_old,
+                        double dt, double* F, int32_t is_dev) {
+  edf_status e;
+  if ((e = check_ready(pb))) return e;
+  if (!u || !u_old || !F || !(dt > 0)) return fail(pb, EDF_ERR_ARG, "bad residual arguments");
+  Group* G;
+  int s;
+  if ((e = find_sample(pb, sample, &G, &s))) return e;
+  const size_t n = G->n;
+  // the trial-state buffers of this sample serve as scratch
+  double* du = G->ut + s * n;
+  double* duo = G->kr + s * n;
+  double* dF = G->Ft + s * n;
+  const hipMemcpyKind kin = is_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  EDF_TRY(hipMemcpyAsync(du, u, n * sizeof(double), kin, pb->st));
+  EDF_TRY(hipMemcpyAsync(duo, u_old, n * sizeof(double), kin, pb->st));
+  const Level& L = G->lv[0];
+  const Phys ph = make_phys(pb->phys, L.g, dt);
+  launch_defect(L.g, ph, L.phi + s * L.cells, L.K + s * L.cells, du, duo, dF, 1, nullptr, pb->st);
+  EDF_CHECK_LAUNCH();
+  EDF_TRY(hipMemcpyAsync(F, dF, n * sizeof(double),
+                         is_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, pb->st));
+  EDF_TRY(hipStreamSynchronize(pb->st));
+  return EDF_OK;
+}
+
+edf_status edf_get_jacobian(edf_problem* pb, int32_t sample, const double* u, double dt,
+                            int32_t level, double* out) {
+  edf_status e;
+  if ((e = check_ready(pb))) return e;
+  if (!u || !out || !(dt > 0)) return fail(pb, EDF_ERR_ARG, "bad jacobian arguments");
+  Group* G;
+  int s;
+  if ((e = find_sample(pb, sample, &G, &s))) return e;
+  if (level < 0 || level >= G->L) return fail(pb, EDF_ERR_ARG, "level out of range");
+  const size_t n = G->n;
+  double* du = G->ut + s * n;
+  EDF_TRY(hipMemcpyAsync(du, u, n * sizeof(double), hipMemcpyHostToDevice, pb->st));
+  // inject through scratch: coarse-level states of this sample
+  const double* cur = du;
+  for (int l = 1; l <= level; ++l) {
+    double* dst = G->lv[l].u + s * 2 * (size_t)G->lv[l].g.N;
+    launch_inject(G->lv[l - 1].g, G->lv[l].g, cur, dst, 1, nullptr, pb->st);
+    cur = dst;
+  }
+  const Level& L = G->lv[level];
+  const size_t N = L.g.N;
+  double *A = nullptr, *nat = nullptr;
+  EDF_TRY(hipMalloc(&A, kPlanes * N * sizeof(double)));
+  EDF_TRY(hipMalloc(&nat, kPlanes * N * sizeof(double)));
+  const Phys ph = make_phys(pb->phys, L.g, dt);
+  launch_assemble(L.g, ph, L.phi + s * L.cells, L.K + s * L.cells, cur, A, nullptr, 1, nullptr,
+                  pb->st, false);
+  launch_stencil_to_natural(L.g, A, nat, pb->st);
+  EDF_CHECK_LAUNCH();
+  EDF_TRY(hipMemcpyAsync(out, nat, kPlanes * N * sizeof(double), hipMemcpyDeviceToHost, pb->st));
+  EDF_TRY(hipStreamSynchronize(pb->st));
+  EDF_TRY(hipFree(A));
+  EDF_TRY(hipFree(nat));
+  return EDF_OK;
+}
+
+edf_status edf_apply_vcycle(edf_problem* pb, int32_t group, double dt, const double* x,
+                            double* y) {
+  edf_status e;
+  if ((e = check_ready(pb))) return e;
+  if (group < 0 || group >= (int)pb->groups.size() || !x || !y || !(dt > 0))
+    return fail(pb, EDF_ERR_ARG, "bad vcycle arguments");
+  Group& G = pb->groups[group];
+  set_dt(pb, G, dt);
+  std::vector<int> all(G.S, 1);
+  if ((e = upload_ints(pb, G.nmask, all))) return e;
+  if ((e = assemble_all(pb, G, G.nmask))) return e;
+  EDF_TRY(hipMemcpyAsync(G.kp, x, G.S * G.n * sizeof(double), hipMemcpyHostToDevice, pb->st));
+  G.n_active = G.S;
+  precondition(pb, G, G.kp, G.kph, G.nmask);
+  EDF_CHECK_LAUNCH();
+  EDF_TRY(hipMemcpyAsync(y, G.kph, G.S * G.n * sizeof(double), hipMemcpyDeviceToHost, pb->st));
+  EDF_TRY(hipStreamSynchronize(pb->st));
+  return prof_flush(pb);
+}
+
+edf_status edf_apply_jacobian(edf_problem* pb, int32_t group, const double* x, double* y) {
+  edf_status e;
+  if ((e = check_ready(pb))) return e;
+  if (group < 0 || group >= (int)pb->groups.size() || !x || !y)
+    return fail(pb, EDF_ERR_ARG, "bad apply arguments");
+  Group& G = pb->groups[group];
+  EDF_TRY(hipMemcpyAsync(G.kp, x, G.S * G.n * sizeof(double), hipMemcpyHostToDevice, pb->st));
+  launch_spmv(G.lv[0].g, G.lv[0].A64, G.kp, G.kv, G.S, nullptr, pb->st);
+  EDF_CHECK_LAUNCH();
+  EDF_TRY(hipMemcpyAsync(y, G.kv, G.S * G.n * sizeof(double), hipMemcpyDeviceToHost, pb->st));
+  EDF_TRY(hipStreamSynchronize(pb->st));
+  return EDF_OK;
+}
+
+edf_status edf_profile(edf_problem* pb, int32_t enable, double* out) {
+  if (!pb) return EDF_ERR_ARG;
+  edf_status e;
+  if ((e = prof_flush(pb))) return e;
+  if (out) {
+    out[0] = pb->prof_launches;
+    out[1] = pb->prof_ms;
+    out[2] = pb->prof_bytes;
+  }
+  if (enable) {
+    pb->prof_launches = pb->prof_ms = pb->prof_bytes = 0;
+  }
+  pb->prof_on = enable != 0;
+  return EDF_OK;
+}
+
+const char* edf_last_error(const edf_problem* pb) { return pb ? pb->err.c_str() : "null problem"; }
+
+void edf_destroy(edf_problem* pb) {
+  if (!pb) return;
+  if (pb->st) (void)hipStreamSynchronize(pb->st);
+  for (void* p : pb->allocs) (void)hipFree(p);
+  for (hipEvent_t e : pb->prof_ev) (void)hipEventDestroy(e);
+  if (pb->mom_f) (void)hipFree(pb->mom_f);
+  if (pb->h_int) (void)hipHostFree(pb->h_int);
+  if (pb->h_dbl) (void)hipHostFree(pb->h_dbl);
+  if (pb->h_ks) (void)hipHostFree(pb->h_ks);
+  delete pb;
+}
+
+}  // extern "C"

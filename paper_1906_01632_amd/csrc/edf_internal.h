@@ -1,0 +1,133 @@
+// Internal declarations shared by the HIP kernel files and the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstddef>
+
+namespace edf {
+
+constexpr int kBlock = 256;        // threads per workgroup of the streaming kernels
+constexpr int kPlanes = 108;       // 27 neighbours x 2 equations x 2 unknowns
+constexpr int kDiag = 13;          // neighbour index of the vertex itself
+constexpr int kMaxCoarse = 2048;   // largest coarsest-grid system (unknowns)
+
+// Geometry of one grid level.  Stencil arrays of a level are stored in
+// colour-major vertex order: the 8 colours (i%2, j%2, k%2) one after the
+// other, each colour's vertices in (i/2, j/2, k/2) lexicographic order.
+// Vectors are in natural order v = i + nx (j + ny k).
+struct Geom {
+  int nx, ny, nz, N;
+  int off[9];        // colour offsets into the colour-major order, off[8] = N
+  int mx[8], my[8];  // colour sub-grid extents in x and y
+  int pi0, pi1, pj0, pj1;  // vertex index range of the salt patch on k = 0 (empty if pi0 > pi1)
+  double hx, hy, hz;
+};
+
+// Physical constants and the scaling of one level (passed by value).
+struct Phys {
+  double rho0, drho, mu, g, Dm;
+  double dt;
+  double s_row;    // dt / (rho0 phi_mean hx hy hz): scale of the finite-volume rows
+  double p_unit;   // rho0 max(g,1) lz: pressure unit of the scaled unknowns
+};
+
+struct FieldParams {
+  double lx, ly, lz, phi_mean, K_mean;
+  int model, n_xi;
+};
+
+// Per-sample scalars of BiCGStab (device resident).
+struct KrylovScalars {
+  double rho, rho_old, alpha, omega, beta;
+  double bb, rr, tol2, rv, ts, tt, ss;
+  int it, state;  // state: 0 running, 1 converged, 2 breakdown
+  int pad[2];
+};
+
+__host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------------------
+// kernel launchers (fv_kernels.hip)
+// ---------------------------------------------------------------------------
+void launch_coefficients(const Geom& g, const FieldParams& fp, const double* xi, int S,
+                         double* phi, double* K, hipStream_t st);
+void launch_defect(const Geom& g, const Phys& ph, const double* phi, const double* K,
+                   const double* u, const double* u_old, double* F, int S, const int* mask,
+                   hipStream_t st);
+void launch_assemble(const Geom& g, const Phys& ph, const double* phi, const double* K,
+                     const double* u, double* A64, float* A32, int S, const int* mask,
+                     hipStream_t st, bool frozen);
+void launch_block_inverse_f64(const Geom& g, const double* A, double* Dinv, int S,
+                              const int* mask, hipStream_t st);
+void launch_block_inverse_f32(const Geom& g, const float* A, float* Dinv, int S,
+                              const int* mask, hipStream_t st);
+void launch_inject(const Geom& gf, const Geom& gc, const double* uf, double* uc, int S,
+                   const int* mask, hipStream_t st);
+void launch_stencil_to_natural(const Geom& g, const double* A, double* out, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// multigrid and stencil kernels (mg_kernels.hip), T = double or float
+// ---------------------------------------------------------------------------
+template <typename T>
+void launch_smooth(const Geom& g, int colour, const T* A, const T* Dinv, const T* b, T* x, int S,
+                   const int* mask, hipStream_t st, hipEvent_t ev0 = nullptr,
+                   hipEvent_t ev1 = nullptr);
+template <typename T>
+void launch_residual(const Geom& g, const T* A, const T* b, const T* x, T* r, int S,
+                     const int* mask, hipStream_t st);
+template <typename T>
+void launch_restrict(const Geom& gf, const Geom& gc, const T* rf, T* bc, T* xc, int S,
+                     const int* mask, hipStream_t st);
+template <typename T>
+void launch_prolong(const Geom& gf, const Geom& gc, const T* xc, T* xf, int S, const int* mask,
+                    hipStream_t st);
+template <typename T>
+void launch_fill(T* x, size_t per_sample, int S, const int* mask, T value, hipStream_t st);
+void launch_cast_f64_to_f32(const double* a, float* b, size_t per_sample, int S, const int* mask,
+                            hipStream_t st);
+void launch_cast_f32_to_f64(const float* a, double* b, size_t per_sample, int S, const int* mask,
+                            hipStream_t st);
+void launch_coarse_dense(const Geom& g, const double* A, double* M, int S, const int* mask,
+                         hipStream_t st);
+void launch_gauss_jordan(int n, double* M, int* piv, int* status, int S, const int* mask,
+                         hipStream_t st);
+template <typename T>
+void launch_coarse_apply(int n, const double* Minv, const T* b, T* x, int S, const int* mask,
+                         hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Krylov / Newton kernels (krylov_kernels.hip), FP64 vectors of n = 2N per sample
+// ---------------------------------------------------------------------------
+int reduce_blocks(size_t n);
+void launch_spmv(const Geom& g, const double* A, const double* x, double* y, int S,
+                 const int* mask, hipStream_t st);
+// BiCGStab phases; `part` is scratch [S][nb][4], `ks` the per-sample scalars.
+void launch_bicg_init(size_t n, const double* b, double* x, double* r, double* rh, double* p,
+                      double* v, double* part, KrylovScalars* ks, double rtol, int* active, int S,
+                      const int* mask, hipStream_t st);
+void launch_bicg_p(size_t n, const double* r, const double* v, double* p, const KrylovScalars* ks,
+                   int S, const int* mask, hipStream_t st);
+void launch_bicg_alpha(const Geom& g, const double* A, const double* ph, double* v, const double* rh,
+                       double* part, KrylovScalars* ks, int S, const int* mask, hipStream_t st);
+void launch_bicg_s(size_t n, const double* r, const double* v, double* s, double* part,
+                   KrylovScalars* ks, int S, const int* mask, hipStream_t st);
+void launch_bicg_omega(const Geom& g, const double* A, const double* sh, const double* s, double* t,
+                       double* part, KrylovScalars* ks, int S, const int* mask, hipStream_t st);
+void launch_bicg_update(size_t n, const double* ph, const double* sh, const double* s,
+                        const double* t, const double* rh, double* x, double* r, double* part,
+                        KrylovScalars* ks, int* active, int S, const int* mask, hipStream_t st);
+// Newton helpers
+void launch_sq_norm(size_t n, const double* x, double* part, double* out, int S, const int* mask,
+                    hipStream_t st);
+void launch_axpy_state(size_t N, const double* u, const double* d, const double* lam, double p_unit,
+                       double* out, int S, const int* mask, hipStream_t st);
+void launch_masked_copy(size_t n, const double* a, double* b, int S, const int* mask,
+                        hipStream_t st);
+void launch_gather_common(const Geom& gf, int cx, int cy, int cz, const double* u, double* out,
+                          int S, hipStream_t st);
+void launch_moments(int Nc, int S, const double* f, const double* w, double thr, double* mean,
+                    double* var, double* exc, hipStream_t st);
+
+}  // namespace edf

@@ -1,0 +1,60 @@
+// Device helpers shared by the kernel files: index maps and boundary sets.
+#pragma once
+
+#include "edf_internal.h"
+
+namespace edf {
+
+// neighbour index of offset (dx, dy, dz) in {-1,0,1}^3
+__host__ __device__ constexpr int nb_index(int dx, int dy, int dz) {
+  return (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+}
+
+__device__ __forceinline__ int clampi(int a, int lo, int hi) { return a < lo ? lo : (a > hi ? hi : a); }
+
+// colour-major position t -> vertex (i, j, k)
+__device__ __forceinline__ void colour_decode(const Geom& g, int t, int& i, int& j, int& k) {
+  int col = 0;
+#pragma unroll
+  for (int c = 1; c < 8; ++c) col += (t >= g.off[c]) ? 1 : 0;
+  const int s = t - g.off[col];
+  const int mx = g.mx[col], my = g.my[col];
+  const int a = s % mx;
+  const int r = s / mx;
+  const int b = r % my;
+  const int c = r / my;
+  i = 2 * a + (col & 1);
+  j = 2 * b + ((col >> 1) & 1);
+  k = 2 * c + (col >> 2);
+}
+
+// position inside colour `col` -> vertex (i, j, k)
+__device__ __forceinline__ void colour_decode_in(const Geom& g, int col, int s, int& i, int& j,
+                                                 int& k) {
+  const int mx = g.mx[col], my = g.my[col];
+  const int a = s % mx;
+  const int r = s / mx;
+  i = 2 * a + (col & 1);
+  j = 2 * (r % my) + ((col >> 1) & 1);
+  k = 2 * (r / my) + (col >> 2);
+}
+
+// vertex (i, j, k) -> colour-major position
+__device__ __forceinline__ int colour_encode(const Geom& g, int i, int j, int k) {
+  const int col = (i & 1) + 2 * (j & 1) + 4 * (k & 1);
+  return g.off[col] + (i >> 1) + g.mx[col] * ((j >> 1) + g.my[col] * (k >> 1));
+}
+
+// salt Dirichlet vertex (closed top patch: c = 1; bottom: c = 0)
+__device__ __forceinline__ bool is_cdir(const Geom& g, int i, int j, int k, double& value) {
+  if (k == g.nz - 1) { value = 0.0; return true; }
+  if (k == 0 && i >= g.pi0 && i <= g.pi1 && j >= g.pj0 && j <= g.pj1) { value = 1.0; return true; }
+  return false;
+}
+
+// pressure-pinned vertex (the four top corners)
+__device__ __forceinline__ bool is_pin(const Geom& g, int i, int j, int k) {
+  return k == 0 && (i == 0 || i == g.nx - 1) && (j == 0 || j == g.ny - 1);
+}
+
+}  // namespace edf

@@ -1,0 +1,459 @@
+// Finite-volume kernels of the Elder box: coefficient fields, the nonlinear
+// defect and its Jacobian as a 27-point stencil of 2x2 blocks.
+//
+// Discretisation (vertex-centred finite volumes, Section 2.3 of the paper, model
+// of Section 2.1): each vertex owns the union of the octants of its adjacent
+// hexahedra.  Inside a hexahedron, every edge v_a -> v_b = v_a + e_d carries one
+// sub-control-volume face: the quarter of the hex mid-plane normal to d next to
+// the edge, with area (product of the other two h)/4 and one integration point at
+// its centre.  At that point c, d_d p and d_d c come from trilinear interpolation
+// over the 8 hex corners, the Darcy flux is Q = -(K_e/mu)(d_d p - rho(c) g_d) A,
+// the liquid flux rho(c) Q and the salt flux rho(c_up) c_up Q - rho(c) phi_e D_m d_d c A
+// with the upstream vertex c_up = c(v_a) if Q >= 0 else c(v_b).  Storage uses the
+// lumped porous volume m_v = sum_e phi_e V_e / 8 and implicit Euler.
+//
+// Every vertex gathers the 24 faces it touches (each face is evaluated once from
+// each of its two vertices), so no atomics are needed and results are
+// deterministic.  All loops over hexes, faces and corners are unrolled with
+// compile-time offsets: the 3x3x3 neighbourhood lives in registers.
+#include <cmath>
+
+#include "fv_common.h"
+
+namespace edf {
+
+// ---------------------------------------------------------------------------
+// coefficient fields, one thread per hexahedron (Section 2.2)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_coefficients(Geom g, FieldParams fp, const double* xi,
+                                                         double* phi_all, double* K_all) {
+  const int s = blockIdx.y;
+  const int cx = g.nx - 1, cy = g.ny - 1, cz = g.nz - 1;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= cx * cy * cz) return;
+  const int i = e % cx, j = (e / cx) % cy, k = e / (cx * cy);
+  const double x = (i + 0.5) * g.hx, y = (j + 0.5) * g.hy, z = (k + 0.5) * g.hz;
+  const double* q = xi + (size_t)s * (fp.n_xi > 0 ? fp.n_xi : 1);
+  const double pm = fp.phi_mean;
+  const double px = M_PI * x / fp.lx, py = M_PI * y / fp.ly, pz = M_PI * z / fp.lz;
+  double phi = pm, logK_extra = 0.0;
+  bool kc = true;
+  switch (fp.model) {
+    case 0:
+      kc = false;
+      break;
+    case 1:
+      phi = pm * (1.0 + 0.2 * q[0] * cos(px) * cos(py));
+      break;
+    case 2:
+      phi = pm * (1.0 + 0.2 * q[0] * cos(px) * cos(py) + 0.2 * q[1] * sin(px) * sin(py));
+      logK_extra = 0.5 * q[2] * cos(pz) + 0.5 * q[3] * sin(px) * cos(pz);
+      break;
+    default: {
+      const double sx = sin(px), sy = sin(py), sz = sin(pz);
+      phi = pm + 0.01 * (q[0] * sx + q[1] * sy + q[2] * sz + q[0] * sx * sy + q[1] * sx * sz);
+    }
+  }
+  double K = fp.K_mean;
+  if (kc) {  // Kozeny-Carman, normalised to K(phi_mean) = K_mean
+    const double r = phi / pm, w = (1.0 - pm) / (1.0 - phi);
+    K = fp.K_mean * r * r * r * w * w;
+    if (logK_extra != 0.0) K = exp(log(K) + logK_extra);
+  }
+  const size_t cells = (size_t)cx * cy * cz;
+  phi_all[(size_t)s * cells + e] = phi;
+  K_all[(size_t)s * cells + e] = K;
+}
+
+void launch_coefficients(const Geom& g, const FieldParams& fp, const double* xi, int S,
+                         double* phi, double* K, hipStream_t st) {
+  const int cells = (g.nx - 1) * (g.ny - 1) * (g.nz - 1);
+  dim3 grid(ceil_div(cells, kBlock), S);
+  hipLaunchKernelGGL(k_coefficients, grid, dim3(kBlock), 0, st, g, fp, xi, phi, K);
+}
+
+// ---------------------------------------------------------------------------
+// one sub-control-volume face seen from vertex v, v = corner (AX,AY,AZ) of the hex
+// ---------------------------------------------------------------------------
+struct FaceGeo {
+  double ih[3];    // 1/h per direction
+  double area[3];  // face area per normal direction
+};
+
+template <int AX, int AY, int AZ, int D>
+struct FaceT {
+  static constexpr int SB0 = D == 0 ? 0 : AX;  // start corner of the edge through v
+  static constexpr int SB1 = D == 1 ? 0 : AY;
+  static constexpr int SB2 = D == 2 ? 0 : AZ;
+  static constexpr int VD = D == 0 ? AX : (D == 1 ? AY : AZ);  // 0: v is the start
+  static constexpr int NA = nb_index(SB0 - AX, SB1 - AY, SB2 - AZ);
+  static constexpr int NB = nb_index(SB0 + (D == 0) - AX, SB1 + (D == 1) - AY, SB2 + (D == 2) - AZ);
+  // trilinear weight of corner w at the integration point, and its d/dt_D
+  static __device__ __forceinline__ double N(int w) {
+    const int wx = w & 1, wy = (w >> 1) & 1, wz = w >> 2;
+    const double gx = D == 0 ? 0.5 : (wx == SB0 ? 0.75 : 0.25);
+    const double gy = D == 1 ? 0.5 : (wy == SB1 ? 0.75 : 0.25);
+    const double gz = D == 2 ? 0.5 : (wz == SB2 ? 0.75 : 0.25);
+    return gx * gy * gz;
+  }
+  static __device__ __forceinline__ double dN(int w) {
+    const int wx = w & 1, wy = (w >> 1) & 1, wz = w >> 2;
+    const double gx = wx == SB0 ? 0.75 : 0.25;
+    const double gy = wy == SB1 ? 0.75 : 0.25;
+    const double gz = wz == SB2 ? 0.75 : 0.25;
+    const int wd = D == 0 ? wx : (D == 1 ? wy : wz);
+    const double t = D == 0 ? gy * gz : (D == 1 ? gx * gz : gx * gy);
+    return wd ? t : -t;
+  }
+  static __device__ __forceinline__ int nb(int w) {
+    return nb_index((w & 1) - AX, ((w >> 1) & 1) - AY, (w >> 2) - AZ);
+  }
+};
+
+template <int AX, int AY, int AZ, int D>
+__device__ __forceinline__ void face_residual(const double* P, const double* C, double phi, double K,
+                                              const Phys& ph, const FaceGeo& fg, double& Fl,
+                                              double& Fs) {
+  using F = FaceT<AX, AY, AZ, D>;
+  double cf = 0.0, dp = 0.0, dc = 0.0;
+#pragma unroll
+  for (int w = 0; w < 8; ++w) {
+    cf += F::N(w) * C[F::nb(w)];
+    dp += F::dN(w) * P[F::nb(w)];
+    dc += F::dN(w) * C[F::nb(w)];
+  }
+  dp *= fg.ih[D];
+  dc *= fg.ih[D];
+  const double area = fg.area[D];
+  const double gD = D == 2 ? ph.g : 0.0;
+  const double rf = ph.rho0 + ph.drho * cf;
+  const double Q = -(K / ph.mu) * (dp - rf * gD) * area;
+  const double cup = Q >= 0.0 ? C[F::NA] : C[F::NB];
+  const double fl = rf * Q;
+  const double fs = (ph.rho0 + ph.drho * cup) * cup * Q - rf * phi * ph.Dm * dc * area;
+  if (F::VD == 0) {
+    Fl += fl;
+    Fs += fs;
+  } else {
+    Fl -= fl;
+    Fs -= fs;
+  }
+}
+
+template <int AX, int AY, int AZ>
+__device__ __forceinline__ void hex_residual(const Geom& g, int i, int j, int k, const double* phi,
+                                             const double* K, const double* P, const double* C,
+                                             const Phys& ph, const FaceGeo& fg, double& Fl,
+                                             double& Fs, double& msum) {
+  const int hi = i - AX, hj = j - AY, hk = k - AZ;
+  if (hi < 0 || hj < 0 || hk < 0 || hi > g.nx - 2 || hj > g.ny - 2 || hk > g.nz - 2) return;
+  const size_t e = hi + (size_t)(g.nx - 1) * (hj + (size_t)(g.ny - 1) * hk);
+  const double pe = phi[e], Ke = K[e];
+  msum += pe;
+  face_residual<AX, AY, AZ, 0>(P, C, pe, Ke, ph, fg, Fl, Fs);
+  face_residual<AX, AY, AZ, 1>(P, C, pe, Ke, ph, fg, Fl, Fs);
+  face_residual<AX, AY, AZ, 2>(P, C, pe, Ke, ph, fg, Fl, Fs);
+}
+
+__device__ __forceinline__ void load_neighbourhood(const Geom& g, const double2* u, int i, int j,
+                                                   int k, double* P, double* C) {
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int ii = clampi(i + dx, 0, g.nx - 1), jj = clampi(j + dy, 0, g.ny - 1),
+                  kk = clampi(k + dz, 0, g.nz - 1);
+        const double2 w = u[ii + (size_t)g.nx * (jj + (size_t)g.ny * kk)];
+        P[nb_index(dx, dy, dz)] = w.x;
+        C[nb_index(dx, dy, dz)] = w.y;
+      }
+}
+
+__device__ __forceinline__ FaceGeo face_geo(const Geom& g) {
+  FaceGeo fg;
+  fg.ih[0] = 1.0 / g.hx;
+  fg.ih[1] = 1.0 / g.hy;
+  fg.ih[2] = 1.0 / g.hz;
+  fg.area[0] = g.hy * g.hz * 0.25;
+  fg.area[1] = g.hx * g.hz * 0.25;
+  fg.area[2] = g.hx * g.hy * 0.25;
+  return fg;
+}
+
+// ---------------------------------------------------------------------------
+// scaled defect F~(u; u_old), one thread per vertex (natural order)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_defect(Geom g, Phys ph, const double* phi_all,
+                                                   const double* K_all, const double* u_all,
+                                                   const double* uo_all, double* F_all,
+                                                   const int* mask) {
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= g.N) return;
+  const int i = v % g.nx, j = (v / g.nx) % g.ny, k = v / (g.nx * g.ny);
+  const size_t cells = (size_t)(g.nx - 1) * (g.ny - 1) * (g.nz - 1);
+  const double* phi = phi_all + s * cells;
+  const double* K = K_all + s * cells;
+  const double2* u = reinterpret_cast<const double2*>(u_all) + (size_t)s * g.N;
+  const double2* uo = reinterpret_cast<const double2*>(uo_all) + (size_t)s * g.N;
+  double P[27], C[27];
+  load_neighbourhood(g, u, i, j, k, P, C);
+  const FaceGeo fg = face_geo(g);
+  double Fl = 0.0, Fs = 0.0, msum = 0.0;
+  hex_residual<0, 0, 0>(g, i, j, k, phi, K, P, C, ph, fg, Fl, Fs, msum);
+  hex_residual<1, 0, 0>(g, i, j, k, phi, K, P, C, ph, fg, Fl, Fs, msum);
+  hex_residual<0, 1, 0>(g, i, j, k, phi, K, P, C, ph, fg, Fl, Fs, msum);
+  hex_residual<1, 1, 0>(g, i, j, k, phi, K, P, C, ph, fg, Fl, Fs, msum);
+  hex_residual<0, 0, 1>(g, i, j, k, phi, K, P, C, ph, fg, Fl, Fs, msum);
+  hex_residual<1, 0, 1>(g, i, j, k, phi, K, P, C, ph, fg, Fl, Fs, msum);
+  hex_residual<0, 1, 1>(g, i, j, k, phi, K, P, C, ph, fg, Fl, Fs, msum);
+  hex_residual<1, 1, 1>(g, i, j, k, phi, K, P, C, ph, fg, Fl, Fs, msum);
+  const double m = msum * (g.hx * g.hy * g.hz * 0.125);
+  const double c = C[kDiag], co = uo[v].y;
+  const double rc = ph.rho0 + ph.drho * c, rco = ph.rho0 + ph.drho * co;
+  Fl += m * (rc - rco) / ph.dt;
+  Fs += m * (rc * c - rco * co) / ph.dt;
+  double2 out;
+  out.x = is_pin(g, i, j, k) ? P[kDiag] / ph.p_unit : ph.s_row * Fl;
+  double cD;
+  out.y = is_cdir(g, i, j, k, cD) ? c - cD : ph.s_row * Fs;
+  reinterpret_cast<double2*>(F_all)[(size_t)s * g.N + v] = out;
+}
+
+void launch_defect(const Geom& g, const Phys& ph, const double* phi, const double* K,
+                   const double* u, const double* u_old, double* F, int S, const int* mask,
+                   hipStream_t st) {
+  dim3 grid(ceil_div(g.N, kBlock), S);
+  hipLaunchKernelGGL(k_defect, grid, dim3(kBlock), 0, st, g, ph, phi, K, u, u_old, F, mask);
+}
+
+// ---------------------------------------------------------------------------
+// Jacobian rows: derivatives of one equation row EQ of vertex v with respect to
+// (p, c) at its 27 neighbours, upwind choice frozen.
+// ---------------------------------------------------------------------------
+template <int EQ, bool FROZEN, int AX, int AY, int AZ, int D>
+__device__ __forceinline__ void face_jacobian(const double* P, const double* C, double phi,
+                                              double K, const Phys& ph, const FaceGeo& fg,
+                                              double* Ap, double* Ac) {
+  using F = FaceT<AX, AY, AZ, D>;
+  double cf = 0.0, dp = 0.0, dc = 0.0;
+#pragma unroll
+  for (int w = 0; w < 8; ++w) {
+    cf += F::N(w) * C[F::nb(w)];
+    dp += F::dN(w) * P[F::nb(w)];
+    dc += F::dN(w) * C[F::nb(w)];
+  }
+  const double ih = fg.ih[D];
+  dp *= ih;
+  dc *= ih;
+  const double area = fg.area[D];
+  const double gD = D == 2 ? ph.g : 0.0;
+  const double rf = ph.rho0 + ph.drho * cf;
+  const double kmu = K / ph.mu * area;
+  const double Q = -kmu * (dp - rf * gD);
+  const bool up_start = Q >= 0.0;
+  const double cup = up_start ? C[F::NA] : C[F::NB];
+  const double ru = ph.rho0 + ph.drho * cup;
+  const double sgn = F::VD == 0 ? 1.0 : -1.0;
+  const double dup = (ph.rho0 + 2.0 * ph.drho * cup) * Q;  // d(rho(c) c Q)/dc_up
+  const double diff = phi * ph.Dm * area;
+#pragma unroll
+  for (int w = 0; w < 8; ++w) {
+    const double Nw = F::N(w);
+    const double dNw = F::dN(w) * ih;
+    const double dQdp = -kmu * dNw;
+    const double dQdc = kmu * ph.drho * gD * Nw;
+    double dpw, dcw;
+    if (EQ == 0) {
+      dpw = rf * dQdp;
+      dcw = ph.drho * Nw * Q + rf * dQdc;
+    } else {
+      dpw = ru * cup * dQdp;
+      dcw = (FROZEN ? 0.0 : ru * cup * dQdc) - ph.drho * Nw * diff * dc - rf * diff * dNw;
+      if (F::nb(w) == F::NA && up_start) dcw += dup;
+      if (F::nb(w) == F::NB && !up_start) dcw += dup;
+    }
+    Ap[F::nb(w)] += sgn * dpw;
+    Ac[F::nb(w)] += sgn * dcw;
+  }
+}
+
+template <int EQ, bool FROZEN, int AX, int AY, int AZ>
+__device__ __forceinline__ void hex_jacobian(const Geom& g, int i, int j, int k, const double* phi,
+                                             const double* K, const double* P, const double* C,
+                                             const Phys& ph, const FaceGeo& fg, double* Ap,
+                                             double* Ac, double& msum) {
+  const int hi = i - AX, hj = j - AY, hk = k - AZ;
+  if (hi < 0 || hj < 0 || hk < 0 || hi > g.nx - 2 || hj > g.ny - 2 || hk > g.nz - 2) return;
+  const size_t e = hi + (size_t)(g.nx - 1) * (hj + (size_t)(g.ny - 1) * hk);
+  const double pe = phi[e], Ke = K[e];
+  msum += pe;
+  face_jacobian<EQ, FROZEN, AX, AY, AZ, 0>(P, C, pe, Ke, ph, fg, Ap, Ac);
+  face_jacobian<EQ, FROZEN, AX, AY, AZ, 1>(P, C, pe, Ke, ph, fg, Ap, Ac);
+  face_jacobian<EQ, FROZEN, AX, AY, AZ, 2>(P, C, pe, Ke, ph, fg, Ap, Ac);
+}
+
+template <int EQ, bool FROZEN>
+__device__ __forceinline__ void assemble_row(const Geom& g, const Phys& ph, const double* phi,
+                                             const double* K, const double* P, const double* C,
+                                             int i, int j, int k, int t, size_t base, double* A64,
+                                             float* A32) {
+  double Ap[27], Ac[27];
+#pragma unroll
+  for (int o = 0; o < 27; ++o) {
+    Ap[o] = 0.0;
+    Ac[o] = 0.0;
+  }
+  const FaceGeo fg = face_geo(g);
+  double msum = 0.0;
+  hex_jacobian<EQ, FROZEN, 0, 0, 0>(g, i, j, k, phi, K, P, C, ph, fg, Ap, Ac, msum);
+  hex_jacobian<EQ, FROZEN, 1, 0, 0>(g, i, j, k, phi, K, P, C, ph, fg, Ap, Ac, msum);
+  hex_jacobian<EQ, FROZEN, 0, 1, 0>(g, i, j, k, phi, K, P, C, ph, fg, Ap, Ac, msum);
+  hex_jacobian<EQ, FROZEN, 1, 1, 0>(g, i, j, k, phi, K, P, C, ph, fg, Ap, Ac, msum);
+  hex_jacobian<EQ, FROZEN, 0, 0, 1>(g, i, j, k, phi, K, P, C, ph, fg, Ap, Ac, msum);
+  hex_jacobian<EQ, FROZEN, 1, 0, 1>(g, i, j, k, phi, K, P, C, ph, fg, Ap, Ac, msum);
+  hex_jacobian<EQ, FROZEN, 0, 1, 1>(g, i, j, k, phi, K, P, C, ph, fg, Ap, Ac, msum);
+  hex_jacobian<EQ, FROZEN, 1, 1, 1>(g, i, j, k, phi, K, P, C, ph, fg, Ap, Ac, msum);
+  const double m = msum * (g.hx * g.hy * g.hz * 0.125);
+  const double c = C[kDiag];
+  if (EQ == 0)
+    Ac[kDiag] += m * ph.drho / ph.dt;
+  else
+    Ac[kDiag] += m * (ph.rho0 + 2.0 * ph.drho * c) / ph.dt;
+  double cD;
+  const bool dir = EQ == 0 ? is_pin(g, i, j, k) : is_cdir(g, i, j, k, cD);
+  const double sp = ph.s_row * ph.p_unit, sc = ph.s_row;
+  const size_t N = g.N;
+#pragma unroll
+  for (int o = 0; o < 27; ++o) {
+    double ap = sp * Ap[o], ac = sc * Ac[o];
+    if (dir) {
+      ap = (o == kDiag && EQ == 0) ? 1.0 : 0.0;
+      ac = (o == kDiag && EQ == 1) ? 1.0 : 0.0;
+    }
+    const size_t q = base + (size_t)(o * 4 + EQ * 2) * N + t;
+    if (A64) {
+      A64[q] = ap;
+      A64[q + N] = ac;
+    }
+    if (A32) {
+      A32[q] = (float)ap;
+      A32[q + N] = (float)ac;
+    }
+  }
+}
+
+// FROZEN = true assembles the matrix of the multigrid preconditioner: the salt rows
+// are linearised at a frozen Darcy flux (the derivative of Q with respect to c through
+// the buoyancy term is dropped).  With it, inflow of brine at c_up = 1 into a vertex at
+// c = 0 would make the salt block lose diagonal dominance, and point smoothers diverge;
+// in the full system the pressure response cancels most of that feedback.  The Krylov
+// method always multiplies with the exact Jacobian (FROZEN = false).
+template <bool FROZEN>
+__global__ __launch_bounds__(kBlock) void k_assemble(Geom g, Phys ph, const double* phi_all,
+                                                     const double* K_all, const double* u_all,
+                                                     double* A64, float* A32, const int* mask) {
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.N) return;
+  int i, j, k;
+  colour_decode(g, t, i, j, k);
+  const size_t cells = (size_t)(g.nx - 1) * (g.ny - 1) * (g.nz - 1);
+  const double* phi = phi_all + s * cells;
+  const double* K = K_all + s * cells;
+  const double2* u = reinterpret_cast<const double2*>(u_all) + (size_t)s * g.N;
+  double P[27], C[27];
+  load_neighbourhood(g, u, i, j, k, P, C);
+  const size_t base = (size_t)s * kPlanes * g.N;
+  if (blockIdx.z == 0)
+    assemble_row<0, FROZEN>(g, ph, phi, K, P, C, i, j, k, t, base, A64, A32);
+  else
+    assemble_row<1, FROZEN>(g, ph, phi, K, P, C, i, j, k, t, base, A64, A32);
+}
+
+void launch_assemble(const Geom& g, const Phys& ph, const double* phi, const double* K,
+                     const double* u, double* A64, float* A32, int S, const int* mask,
+                     hipStream_t st, bool frozen) {
+  dim3 grid(ceil_div(g.N, kBlock), S, 2);
+  if (frozen)
+    hipLaunchKernelGGL(k_assemble<true>, grid, dim3(kBlock), 0, st, g, ph, phi, K, u, A64, A32,
+                       mask);
+  else
+    hipLaunchKernelGGL(k_assemble<false>, grid, dim3(kBlock), 0, st, g, ph, phi, K, u, A64, A32,
+                       mask);
+}
+
+// ---------------------------------------------------------------------------
+// inverses of the 2x2 diagonal blocks, Dinv[s][4][N] (colour-major)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_block_inverse(Geom g, const T* A, T* Dinv,
+                                                          const int* mask) {
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.N) return;
+  const size_t N = g.N;
+  const T* a = A + (size_t)s * kPlanes * N + (size_t)(kDiag * 4) * N + t;
+  const double a00 = a[0], a01 = a[N], a10 = a[2 * N], a11 = a[3 * N];
+  const double det = a00 * a11 - a01 * a10;
+  const double id = det != 0.0 ? 1.0 / det : 0.0;
+  T* d = Dinv + (size_t)s * 4 * N + t;
+  d[0] = (T)(a11 * id);
+  d[N] = (T)(-a01 * id);
+  d[2 * N] = (T)(-a10 * id);
+  d[3 * N] = (T)(a00 * id);
+}
+
+void launch_block_inverse_f64(const Geom& g, const double* A, double* Dinv, int S,
+                              const int* mask, hipStream_t st) {
+  dim3 grid(ceil_div(g.N, kBlock), S);
+  hipLaunchKernelGGL(k_block_inverse<double>, grid, dim3(kBlock), 0, st, g, A, Dinv, mask);
+}
+void launch_block_inverse_f32(const Geom& g, const float* A, float* Dinv, int S,
+                              const int* mask, hipStream_t st) {
+  dim3 grid(ceil_div(g.N, kBlock), S);
+  hipLaunchKernelGGL(k_block_inverse<float>, grid, dim3(kBlock), 0, st, g, A, Dinv, mask);
+}
+
+// ---------------------------------------------------------------------------
+// state injection to the next coarser grid: u_c(I,J,K) = u_f(2I,2J,2K)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_inject(Geom gf, Geom gc, const double* uf, double* uc,
+                                                   const int* mask) {
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= gc.N) return;
+  const int I = v % gc.nx, J = (v / gc.nx) % gc.ny, K = v / (gc.nx * gc.ny);
+  const size_t vf = 2 * I + (size_t)gf.nx * (2 * J + (size_t)gf.ny * 2 * K);
+  reinterpret_cast<double2*>(uc)[(size_t)s * gc.N + v] =
+      reinterpret_cast<const double2*>(uf)[(size_t)s * gf.N + vf];
+}
+
+void launch_inject(const Geom& gf, const Geom& gc, const double* uf, double* uc, int S,
+                   const int* mask, hipStream_t st) {
+  dim3 grid(ceil_div(gc.N, kBlock), S);
+  hipLaunchKernelGGL(k_inject, grid, dim3(kBlock), 0, st, gf, gc, uf, uc, mask);
+}
+
+// stencil of one sample, colour-major -> natural vertex order (inspection only)
+__global__ __launch_bounds__(kBlock) void k_stencil_to_natural(Geom g, const double* A,
+                                                               double* out) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= g.N) return;
+  const int i = v % g.nx, j = (v / g.nx) % g.ny, k = v / (g.nx * g.ny);
+  const int t = colour_encode(g, i, j, k);
+  for (int p = 0; p < kPlanes; ++p) out[(size_t)p * g.N + v] = A[(size_t)p * g.N + t];
+}
+
+void launch_stencil_to_natural(const Geom& g, const double* A, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_stencil_to_natural, dim3(ceil_div(g.N, kBlock)), dim3(kBlock), 0, st, g, A,
+                     out);
+}
+
+}  // namespace edf

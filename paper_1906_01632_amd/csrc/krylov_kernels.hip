@@ -1,0 +1,430 @@
+// BiCGStab (right preconditioned, Section 2.3: the Newton systems are solved by
+// BiCGStab with a multigrid preconditioner) for a batch of independent samples,
+// plus the vector kernels of the Newton iteration and the sample statistics.
+//
+// Every sample keeps its own scalars (rho, alpha, omega, ...) in device memory
+// and its own active flag; a finished sample is skipped by every later kernel.
+// Reductions are two-pass and deterministic: each workgroup writes its partial
+// sums in a fixed order, and one wave per sample adds the partials in a fixed
+// order.
+#include "fv_common.h"
+
+namespace edf {
+
+constexpr int kRedMax = 1024;  // partial sums per sample and quantity
+
+int reduce_blocks(size_t n) {
+  const size_t b = (n + kBlock * 4 - 1) / (kBlock * 4);
+  return (int)(b < 1 ? 1 : (b > kRedMax ? kRedMax : b));
+}
+
+template <int Q>
+__device__ __forceinline__ void block_partial(double (&v)[Q], double* part) {
+  __shared__ double sh[Q][kBlock / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_down(v[q], off, 64);
+    if (lane == 0) sh[q][wave] = v[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      double a = 0.0;
+      for (int w = 0; w < kBlock / 64; ++w) a += sh[q][w];
+      part[q] = a;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// y = A x (FP64 stencil), optional fused dots: (d1, y) and (d2, y) or (y, y)
+// ---------------------------------------------------------------------------
+enum DotMode { kDotNone = 0, kDotOne = 1, kDotTS = 2 };
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_spmv(Geom g, const double* A_all, const double* x_all,
+                                                 double* y_all, const double* d_all, double* part,
+                                                 const int* mask) {
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t N = g.N;
+  double acc[2] = {0.0, 0.0};
+  if (t < g.N) {
+    int i, j, k;
+    colour_decode(g, t, i, j, k);
+    const double* A = A_all + (size_t)s * kPlanes * N + t;
+    const double2* x = reinterpret_cast<const double2*>(x_all) + (size_t)s * N;
+    double r0 = 0.0, r1 = 0.0;
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz) {
+      const int kk = clampi(k + dz, 0, g.nz - 1);
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy) {
+        const int jj = clampi(j + dy, 0, g.ny - 1);
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int ii = clampi(i + dx, 0, g.nx - 1);
+          const int o = nb_index(dx, dy, dz);
+          const double2 xv = x[ii + (size_t)g.nx * (jj + (size_t)g.ny * kk)];
+          r0 += A[(size_t)(o * 4 + 0) * N] * xv.x + A[(size_t)(o * 4 + 1) * N] * xv.y;
+          r1 += A[(size_t)(o * 4 + 2) * N] * xv.x + A[(size_t)(o * 4 + 3) * N] * xv.y;
+        }
+      }
+    }
+    const size_t v = i + (size_t)g.nx * (j + (size_t)g.ny * k);
+    reinterpret_cast<double2*>(y_all)[(size_t)s * N + v] = make_double2(r0, r1);
+    if (MODE != kDotNone) {
+      const double2 d = reinterpret_cast<const double2*>(d_all)[(size_t)s * N + v];
+      acc[0] = d.x * r0 + d.y * r1;
+      if (MODE == kDotTS) acc[1] = r0 * r0 + r1 * r1;
+    }
+  }
+  if (MODE == kDotOne) {
+    double a1[1] = {acc[0]};
+    block_partial<1>(a1, part + ((size_t)s * gridDim.x + blockIdx.x) * 4);
+  } else if (MODE == kDotTS) {
+    block_partial<2>(acc, part + ((size_t)s * gridDim.x + blockIdx.x) * 4);
+  }
+}
+
+void launch_spmv(const Geom& g, const double* A, const double* x, double* y, int S,
+                 const int* mask, hipStream_t st) {
+  dim3 grid(ceil_div(g.N, kBlock), S);
+  hipLaunchKernelGGL(k_spmv<kDotNone>, grid, dim3(kBlock), 0, st, g, A, x, y, (const double*)nullptr,
+                     (double*)nullptr, mask);
+}
+
+// ---------------------------------------------------------------------------
+// per-sample scalar updates (one wave per sample)
+// ---------------------------------------------------------------------------
+enum Phase { kInit = 0, kAlpha = 1, kS = 2, kOmega = 3, kUpdate = 4 };
+
+__global__ __launch_bounds__(64) void k_bicg_finalize(int phase, int nb, const double* part,
+                                                      KrylovScalars* ks_all, int* active,
+                                                      double rtol, const int* gate) {
+  const int s = blockIdx.x;
+  if (phase == kInit) {
+    if (gate && !gate[s]) {
+      if (threadIdx.x == 0) active[s] = 0;
+      return;
+    }
+  } else if (!active[s]) {
+    return;
+  }
+  const int lane = threadIdx.x;
+  double a0 = 0.0, a1 = 0.0;
+  for (int b = lane; b < nb; b += 64) {
+    a0 += part[((size_t)s * nb + b) * 4 + 0];
+    a1 += part[((size_t)s * nb + b) * 4 + 1];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a0 += __shfl_down(a0, off, 64);
+    a1 += __shfl_down(a1, off, 64);
+  }
+  if (lane != 0) return;
+  KrylovScalars& k = ks_all[s];
+  switch (phase) {
+    case kInit:
+      k.bb = a0;
+      k.rr = a0;
+      k.rho = a0;  // (r^, r) with r^ = r = b
+      k.rho_old = 1.0;
+      k.alpha = 1.0;
+      k.omega = 1.0;
+      k.beta = 0.0;
+      k.tol2 = rtol * rtol * a0;
+      k.ss = 0.0;
+      k.it = 0;
+      k.state = (a0 > 0.0 && a0 == a0) ? 0 : (a0 == 0.0 ? 1 : 2);
+      active[s] = k.state == 0;
+      break;
+    case kAlpha:
+      k.rv = a0;
+      k.alpha = (a0 != 0.0) ? k.rho / a0 : 0.0;
+      break;
+    case kS:
+      k.ss = a0;
+      break;
+    case kOmega:
+      k.ts = a0;
+      k.tt = a1;
+      k.omega = (k.ss <= k.tol2 || a1 == 0.0) ? 0.0 : a0 / a1;
+      break;
+    case kUpdate: {
+      k.rho_old = k.rho;
+      k.rho = a0;
+      k.rr = a1;
+      k.it += 1;
+      const bool finite = (a1 == a1) && (a1 < 1e300);
+      if (!finite) {
+        k.state = 2;
+      } else if (a1 <= k.tol2 || k.ss <= k.tol2) {
+        k.state = 1;
+      } else if (k.omega == 0.0 || k.rho == 0.0 || k.rv == 0.0) {
+        k.state = 2;  // breakdown: keep the iterate reached so far
+      } else {
+        k.beta = (k.rho / k.rho_old) * (k.alpha / k.omega);
+      }
+      if (k.state != 0) active[s] = 0;
+      break;
+    }
+  }
+}
+
+static void finalize(int phase, int nb, const double* part, KrylovScalars* ks, int* active,
+                     double rtol, int S, hipStream_t st, const int* gate = nullptr) {
+  hipLaunchKernelGGL(k_bicg_finalize, dim3(S), dim3(64), 0, st, phase, nb, part, ks, active, rtol,
+                     gate);
+}
+
+// ---------------------------------------------------------------------------
+// BiCGStab phases
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_bicg_init(size_t n, const double* b, double* x,
+                                                      double* r, double* rh, double* p, double* v,
+                                                      double* part, const int* mask) {
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const size_t o = (size_t)s * n;
+  double acc[1] = {0.0};
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const double be = b[o + e];
+    x[o + e] = 0.0;
+    r[o + e] = be;
+    rh[o + e] = be;
+    p[o + e] = 0.0;
+    v[o + e] = 0.0;
+    acc[0] += be * be;
+  }
+  block_partial<1>(acc, part + ((size_t)s * gridDim.x + blockIdx.x) * 4);
+}
+
+void launch_bicg_init(size_t n, const double* b, double* x, double* r, double* rh, double* p,
+                      double* v, double* part, KrylovScalars* ks, double rtol, int* active, int S,
+                      const int* mask, hipStream_t st) {
+  const int nb = reduce_blocks(n);
+  hipLaunchKernelGGL(k_bicg_init, dim3(nb, S), dim3(kBlock), 0, st, n, b, x, r, rh, p, v, part,
+                     mask);
+  // `mask` gates which samples solve; their active flags start from the initial residual
+  finalize(kInit, nb, part, ks, active, rtol, S, st, mask);
+}
+
+__global__ __launch_bounds__(kBlock) void k_bicg_p(size_t n, const double* r, const double* v,
+                                                   double* p, const KrylovScalars* ks,
+                                                   const int* mask) {
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const double beta = ks[s].beta, omega = ks[s].omega;
+  const size_t o = (size_t)s * n;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x)
+    p[o + e] = r[o + e] + beta * (p[o + e] - omega * v[o + e]);
+}
+
+void launch_bicg_p(size_t n, const double* r, const double* v, double* p, const KrylovScalars* ks,
+                   int S, const int* mask, hipStream_t st) {
+  hipLaunchKernelGGL(k_bicg_p, dim3(reduce_blocks(n), S), dim3(kBlock), 0, st, n, r, v, p, ks,
+                     mask);
+}
+
+void launch_bicg_alpha(const Geom& g, const double* A, const double* ph, double* v,
+                       const double* rh, double* part, KrylovScalars* ks, int S, const int* mask,
+                       hipStream_t st) {
+  const int nb = ceil_div(g.N, kBlock);
+  hipLaunchKernelGGL(k_spmv<kDotOne>, dim3(nb, S), dim3(kBlock), 0, st, g, A, ph, v, rh, part,
+                     mask);
+  finalize(kAlpha, nb, part, ks, const_cast<int*>(mask), 0.0, S, st);  // mask is `active`
+}
+
+__global__ __launch_bounds__(kBlock) void k_bicg_s(size_t n, const double* r, const double* v,
+                                                   double* sv, double* part,
+                                                   const KrylovScalars* ks, const int* mask) {
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const double alpha = ks[s].alpha;
+  const size_t o = (size_t)s * n;
+  double acc[1] = {0.0};
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const double se = r[o + e] - alpha * v[o + e];
+    sv[o + e] = se;
+    acc[0] += se * se;
+  }
+  block_partial<1>(acc, part + ((size_t)s * gridDim.x + blockIdx.x) * 4);
+}
+
+void launch_bicg_s(size_t n, const double* r, const double* v, double* s, double* part,
+                   KrylovScalars* ks, int S, const int* mask, hipStream_t st) {
+  const int nb = reduce_blocks(n);
+  hipLaunchKernelGGL(k_bicg_s, dim3(nb, S), dim3(kBlock), 0, st, n, r, v, s, part, ks, mask);
+  finalize(kS, nb, part, ks, const_cast<int*>(mask), 0.0, S, st);
+}
+
+void launch_bicg_omega(const Geom& g, const double* A, const double* sh, const double* s,
+                       double* t, double* part, KrylovScalars* ks, int S, const int* mask,
+                       hipStream_t st) {
+  const int nb = ceil_div(g.N, kBlock);
+  hipLaunchKernelGGL(k_spmv<kDotTS>, dim3(nb, S), dim3(kBlock), 0, st, g, A, sh, t, s, part, mask);
+  finalize(kOmega, nb, part, ks, const_cast<int*>(mask), 0.0, S, st);
+}
+
+__global__ __launch_bounds__(kBlock) void k_bicg_update(size_t n, const double* ph,
+                                                        const double* sh, const double* sv,
+                                                        const double* t, const double* rh,
+                                                        double* x, double* r, double* part,
+                                                        const KrylovScalars* ks, const int* mask) {
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const double alpha = ks[s].alpha, omega = ks[s].omega;
+  const size_t o = (size_t)s * n;
+  double acc[2] = {0.0, 0.0};
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    x[o + e] += alpha * ph[o + e] + omega * sh[o + e];
+    const double re = sv[o + e] - omega * t[o + e];
+    r[o + e] = re;
+    acc[0] += rh[o + e] * re;
+    acc[1] += re * re;
+  }
+  block_partial<2>(acc, part + ((size_t)s * gridDim.x + blockIdx.x) * 4);
+}
+
+void launch_bicg_update(size_t n, const double* ph, const double* sh, const double* s,
+                        const double* t, const double* rh, double* x, double* r, double* part,
+                        KrylovScalars* ks, int* active, int S, const int* mask, hipStream_t st) {
+  const int nb = reduce_blocks(n);
+  hipLaunchKernelGGL(k_bicg_update, dim3(nb, S), dim3(kBlock), 0, st, n, ph, sh, s, t, rh, x, r,
+                     part, ks, mask);
+  finalize(kUpdate, nb, part, ks, active, 0.0, S, st);
+}
+
+// ---------------------------------------------------------------------------
+// Newton helpers
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_sq_norm(size_t n, const double* x, double* part,
+                                                    const int* mask) {
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const size_t o = (size_t)s * n;
+  double acc[1] = {0.0};
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x)
+    acc[0] += x[o + e] * x[o + e];
+  block_partial<1>(acc, part + ((size_t)s * gridDim.x + blockIdx.x) * 4);
+}
+
+__global__ __launch_bounds__(64) void k_sum_partials(int nb, const double* part, double* out,
+                                                     const int* mask) {
+  const int s = blockIdx.x;
+  if (mask && !mask[s]) return;
+  double a = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 64) a += part[((size_t)s * nb + b) * 4];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
+  if (threadIdx.x == 0) out[s] = a;
+}
+
+void launch_sq_norm(size_t n, const double* x, double* part, double* out, int S, const int* mask,
+                    hipStream_t st) {
+  const int nb = reduce_blocks(n);
+  hipLaunchKernelGGL(k_sq_norm, dim3(nb, S), dim3(kBlock), 0, st, n, x, part, mask);
+  hipLaunchKernelGGL(k_sum_partials, dim3(S), dim3(64), 0, st, nb, part, out, mask);
+}
+
+// out = u + lam_s * (p_unit * d_p, d_c): Newton update in physical units
+__global__ __launch_bounds__(kBlock) void k_axpy_state(size_t N, const double* u, const double* d,
+                                                       const double* lam, double p_unit,
+                                                       double* out, const int* mask) {
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const double l = lam[s];
+  const size_t o = (size_t)s * N;
+  const double2* u2 = reinterpret_cast<const double2*>(u) + o;
+  const double2* d2 = reinterpret_cast<const double2*>(d) + o;
+  double2* o2 = reinterpret_cast<double2*>(out) + o;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < N;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const double2 a = u2[e], b = d2[e];
+    o2[e] = make_double2(a.x + l * p_unit * b.x, a.y + l * b.y);
+  }
+}
+
+void launch_axpy_state(size_t N, const double* u, const double* d, const double* lam,
+                       double p_unit, double* out, int S, const int* mask, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy_state, dim3(reduce_blocks(2 * N), S), dim3(kBlock), 0, st, N, u, d,
+                     lam, p_unit, out, mask);
+}
+
+__global__ __launch_bounds__(kBlock) void k_masked_copy(size_t n, const double* a, double* b,
+                                                        const int* mask) {
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const size_t o = (size_t)s * n;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x)
+    b[o + e] = a[o + e];
+}
+
+void launch_masked_copy(size_t n, const double* a, double* b, int S, const int* mask,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_masked_copy, dim3(reduce_blocks(n), S), dim3(kBlock), 0, st, n, a, b,
+                     mask);
+}
+
+// ---------------------------------------------------------------------------
+// statistics over samples (Section 3: eqs. pdestat, numer_var; Section 3.2)
+// ---------------------------------------------------------------------------
+// c of every sample of a group at the common vertices (nested, every r-th vertex)
+__global__ __launch_bounds__(kBlock) void k_gather_common(Geom gf, int cx, int cy, int cz,
+                                                          const double* u, double* out) {
+  const int s = blockIdx.y;
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  const int Nc = cx * cy * cz;
+  if (v >= Nc) return;
+  const int rx = (gf.nx - 1) / (cx - 1), ry = (gf.ny - 1) / (cy - 1), rz = (gf.nz - 1) / (cz - 1);
+  const int I = v % cx, J = (v / cx) % cy, K = v / (cx * cy);
+  const size_t vf = (size_t)I * rx + (size_t)gf.nx * ((size_t)J * ry + (size_t)gf.ny * K * rz);
+  out[(size_t)s * Nc + v] = reinterpret_cast<const double2*>(u)[(size_t)s * gf.N + vf].y;
+}
+
+void launch_gather_common(const Geom& gf, int cx, int cy, int cz, const double* u, double* out,
+                          int S, hipStream_t st) {
+  dim3 grid(ceil_div(cx * cy * cz, kBlock), S);
+  hipLaunchKernelGGL(k_gather_common, grid, dim3(kBlock), 0, st, gf, cx, cy, cz, u, out);
+}
+
+// one thread per common vertex, samples summed in index order (deterministic)
+__global__ __launch_bounds__(kBlock) void k_moments(int Nc, int S, const double* f, const double* w,
+                                                    double thr, double* mean, double* var,
+                                                    double* exc) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= Nc) return;
+  double m = 0.0, e = 0.0;
+  for (int s = 0; s < S; ++s) {
+    const double c = f[(size_t)s * Nc + v];
+    m += w[s] * c;
+    e += (c > thr) ? w[s] : 0.0;
+  }
+  double q = 0.0;
+  for (int s = 0; s < S; ++s) {
+    const double d = m - f[(size_t)s * Nc + v];
+    q += w[s] * d * d;
+  }
+  mean[v] = m;
+  var[v] = q;
+  exc[v] = e;
+}
+
+void launch_moments(int Nc, int S, const double* f, const double* w, double thr, double* mean,
+                    double* var, double* exc, hipStream_t st) {
+  hipLaunchKernelGGL(k_moments, dim3(ceil_div(Nc, kBlock)), dim3(kBlock), 0, st, Nc, S, f, w, thr,
+                     mean, var, exc);
+}
+
+}  // namespace edf

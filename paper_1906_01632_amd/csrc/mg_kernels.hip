@@ -1,0 +1,447 @@
+// Geometric multigrid kernels: 8-colour block Gauss-Seidel, residual, transfer
+// operators and the dense coarsest-grid solve.  T is the V-cycle precision
+// (double, or float inside the FP64 outer iteration).
+//
+// The V-cycle preconditions BiCGStab (Section 2.3: BiCGStab with a multigrid
+// V-cycle; Section 5.1: a hierarchy of nested grids with the Jacobian assembled
+// on every grid).  The paper smooths with ILU_beta, a sequential recurrence; here
+// the smoother is block Gauss-Seidel over the 8 colours (i%2, j%2, k%2), which
+// are independent sets of the 27-point stencil, so every colour is one fully
+// parallel pass.  Prolongation is trilinear interpolation from the nested coarse
+// vertices, restriction its transpose.
+#include <hip/hip_ext.h>
+
+#include "fv_common.h"
+
+namespace edf {
+
+template <typename T>
+struct V2;
+template <>
+struct V2<double> {
+  using type = double2;
+};
+template <>
+struct V2<float> {
+  using type = float2;
+};
+
+// ---------------------------------------------------------------------------
+// block Gauss-Seidel over one colour: x_v += D_v^{-1} (b - A x)_v
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_smooth(Geom g, int col, const T* A_all, const T* Dinv_all,
+                                                   const T* b_all, T* x_all, const int* mask) {
+  using T2 = typename V2<T>::type;
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= g.off[col + 1] - g.off[col]) return;
+  int i, j, k;
+  colour_decode_in(g, col, q, i, j, k);
+  const size_t N = g.N;
+  const int t = g.off[col] + q;
+  const T* A = A_all + (size_t)s * kPlanes * N + t;
+  const T2* b = reinterpret_cast<const T2*>(b_all) + (size_t)s * N;
+  T2* x = reinterpret_cast<T2*>(x_all) + (size_t)s * N;
+  const size_t v = i + (size_t)g.nx * (j + (size_t)g.ny * k);
+  T2 bv = b[v];
+  T r0 = bv.x, r1 = bv.y;
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int kk = clampi(k + dz, 0, g.nz - 1);
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int jj = clampi(j + dy, 0, g.ny - 1);
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int ii = clampi(i + dx, 0, g.nx - 1);
+        const int o = nb_index(dx, dy, dz);
+        const T2 xv = x[ii + (size_t)g.nx * (jj + (size_t)g.ny * kk)];
+        r0 -= A[(size_t)(o * 4 + 0) * N] * xv.x + A[(size_t)(o * 4 + 1) * N] * xv.y;
+        r1 -= A[(size_t)(o * 4 + 2) * N] * xv.x + A[(size_t)(o * 4 + 3) * N] * xv.y;
+      }
+    }
+  }
+  const T* d = Dinv_all + (size_t)s * 4 * N + t;
+  T2 xv = x[v];
+  xv.x += d[0] * r0 + d[N] * r1;
+  xv.y += d[2 * N] * r0 + d[3 * N] * r1;
+  x[v] = xv;
+}
+
+template <typename T>
+void launch_smooth(const Geom& g, int colour, const T* A, const T* Dinv, const T* b, T* x, int S,
+                   const int* mask, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  const int n = g.off[colour + 1] - g.off[colour];
+  if (n <= 0) return;
+  dim3 grid(ceil_div(n, kBlock), S);
+  if (ev0)  // timed launch: events recorded around this kernel only
+    hipExtLaunchKernelGGL(k_smooth<T>, grid, dim3(kBlock), 0, st, ev0, ev1, 0, g, colour, A, Dinv,
+                          b, x, mask);
+  else
+    hipLaunchKernelGGL(k_smooth<T>, grid, dim3(kBlock), 0, st, g, colour, A, Dinv, b, x, mask);
+}
+
+// ---------------------------------------------------------------------------
+// residual r = b - A x, zero in Dirichlet rows (their equations are solved
+// exactly by the smoother and carry no coarse-grid correction)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_residual(Geom g, const T* A_all, const T* b_all,
+                                                     const T* x_all, T* r_all, const int* mask) {
+  using T2 = typename V2<T>::type;
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.N) return;
+  int i, j, k;
+  colour_decode(g, t, i, j, k);
+  const size_t N = g.N;
+  const T* A = A_all + (size_t)s * kPlanes * N + t;
+  const T2* x = reinterpret_cast<const T2*>(x_all) + (size_t)s * N;
+  const size_t v = i + (size_t)g.nx * (j + (size_t)g.ny * k);
+  const T2 bv = reinterpret_cast<const T2*>(b_all)[(size_t)s * N + v];
+  T r0 = bv.x, r1 = bv.y;
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int kk = clampi(k + dz, 0, g.nz - 1);
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int jj = clampi(j + dy, 0, g.ny - 1);
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int ii = clampi(i + dx, 0, g.nx - 1);
+        const int o = nb_index(dx, dy, dz);
+        const T2 xv = x[ii + (size_t)g.nx * (jj + (size_t)g.ny * kk)];
+        r0 -= A[(size_t)(o * 4 + 0) * N] * xv.x + A[(size_t)(o * 4 + 1) * N] * xv.y;
+        r1 -= A[(size_t)(o * 4 + 2) * N] * xv.x + A[(size_t)(o * 4 + 3) * N] * xv.y;
+      }
+    }
+  }
+  double cD;
+  if (is_pin(g, i, j, k)) r0 = 0;
+  if (is_cdir(g, i, j, k, cD)) r1 = 0;
+  T2 out;
+  out.x = r0;
+  out.y = r1;
+  reinterpret_cast<T2*>(r_all)[(size_t)s * N + v] = out;
+}
+
+template <typename T>
+void launch_residual(const Geom& g, const T* A, const T* b, const T* x, T* r, int S,
+                     const int* mask, hipStream_t st) {
+  dim3 grid(ceil_div(g.N, kBlock), S);
+  hipLaunchKernelGGL(k_residual<T>, grid, dim3(kBlock), 0, st, g, A, b, x, r, mask);
+}
+
+// ---------------------------------------------------------------------------
+// restriction b_c = (1/8) P^T r_f of the scaled residual (the 1/8 converts the
+// fine row scaling to the coarse one: rows are scaled by 1/(hx hy hz)); x_c = 0
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, const T* rf_all, T* bc_all,
+                                                     T* xc_all, const int* mask) {
+  using T2 = typename V2<T>::type;
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= gc.N) return;
+  const int I = v % gc.nx, J = (v / gc.nx) % gc.ny, K = v / (gc.nx * gc.ny);
+  const T2* rf = reinterpret_cast<const T2*>(rf_all) + (size_t)s * gf.N;
+  T a0 = 0, a1 = 0;
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int k = 2 * K + dz;
+    if (k < 0 || k >= gf.nz) continue;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int j = 2 * J + dy;
+      if (j < 0 || j >= gf.ny) continue;
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int i = 2 * I + dx;
+        if (i < 0 || i >= gf.nx) continue;
+        const T w = (dx ? T(0.5) : T(1)) * (dy ? T(0.5) : T(1)) * (dz ? T(0.5) : T(1));
+        const T2 r = rf[i + (size_t)gf.nx * (j + (size_t)gf.ny * k)];
+        a0 += w * r.x;
+        a1 += w * r.y;
+      }
+    }
+  }
+  double cD;
+  T2 out;
+  out.x = is_pin(gc, I, J, K) ? T(0) : T(0.125) * a0;
+  out.y = is_cdir(gc, I, J, K, cD) ? T(0) : T(0.125) * a1;
+  reinterpret_cast<T2*>(bc_all)[(size_t)s * gc.N + v] = out;
+  T2 z;
+  z.x = 0;
+  z.y = 0;
+  reinterpret_cast<T2*>(xc_all)[(size_t)s * gc.N + v] = z;
+}
+
+template <typename T>
+void launch_restrict(const Geom& gf, const Geom& gc, const T* rf, T* bc, T* xc, int S,
+                     const int* mask, hipStream_t st) {
+  dim3 grid(ceil_div(gc.N, kBlock), S);
+  hipLaunchKernelGGL(k_restrict<T>, grid, dim3(kBlock), 0, st, gf, gc, rf, bc, xc, mask);
+}
+
+// ---------------------------------------------------------------------------
+// prolongation and correction x_f += P x_c (trilinear), none in Dirichlet rows
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong(Geom gf, Geom gc, const T* xc_all, T* xf_all,
+                                                    const int* mask) {
+  using T2 = typename V2<T>::type;
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= gf.N) return;
+  const int i = v % gf.nx, j = (v / gf.nx) % gf.ny, k = v / (gf.nx * gf.ny);
+  const T2* xc = reinterpret_cast<const T2*>(xc_all) + (size_t)s * gc.N;
+  const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1, k0 = k >> 1,
+            k1 = (k + 1) >> 1;
+  const T wi = (i & 1) ? T(0.5) : T(1), wj = (j & 1) ? T(0.5) : T(1), wk = (k & 1) ? T(0.5) : T(1);
+  T a0 = 0, a1 = 0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int I = (c & 1) ? i1 : i0, J = (c & 2) ? j1 : j0, K = (c & 4) ? k1 : k0;
+    // the second parent of an even index coincides with the first: count it once
+    if (((c & 1) && !(i & 1)) || ((c & 2) && !(j & 1)) || ((c & 4) && !(k & 1))) continue;
+    const T2 e = xc[I + (size_t)gc.nx * (J + (size_t)gc.ny * K)];
+    const T w = wi * wj * wk;
+    a0 += w * e.x;
+    a1 += w * e.y;
+  }
+  T2* xf = reinterpret_cast<T2*>(xf_all) + (size_t)s * gf.N;
+  T2 x = xf[v];
+  double cD;
+  if (!is_pin(gf, i, j, k)) x.x += a0;
+  if (!is_cdir(gf, i, j, k, cD)) x.y += a1;
+  xf[v] = x;
+}
+
+template <typename T>
+void launch_prolong(const Geom& gf, const Geom& gc, const T* xc, T* xf, int S, const int* mask,
+                    hipStream_t st) {
+  dim3 grid(ceil_div(gf.N, kBlock), S);
+  hipLaunchKernelGGL(k_prolong<T>, grid, dim3(kBlock), 0, st, gf, gc, xc, xf, mask);
+}
+
+// ---------------------------------------------------------------------------
+// fills and precision casts
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill(T* x, size_t n, T value, const int* mask) {
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  T* xs = x + (size_t)s * n;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x)
+    xs[e] = value;
+}
+
+template <typename T>
+void launch_fill(T* x, size_t per_sample, int S, const int* mask, T value, hipStream_t st) {
+  const int nb = (int)std::min<size_t>(ceil_div((int)std::min<size_t>(per_sample, 1u << 30), kBlock), 4096);
+  dim3 grid(nb > 0 ? nb : 1, S);
+  hipLaunchKernelGGL(k_fill<T>, grid, dim3(kBlock), 0, st, x, per_sample, value, mask);
+}
+
+template <typename A, typename B>
+__global__ __launch_bounds__(kBlock) void k_cast(const A* a, B* b, size_t n, const int* mask) {
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x)
+    b[(size_t)s * n + e] = (B)a[(size_t)s * n + e];
+}
+
+void launch_cast_f64_to_f32(const double* a, float* b, size_t per_sample, int S, const int* mask,
+                            hipStream_t st) {
+  const int nb = (int)std::min<size_t>((per_sample + kBlock - 1) / kBlock, 4096);
+  hipLaunchKernelGGL((k_cast<double, float>), dim3(nb, S), dim3(kBlock), 0, st, a, b, per_sample,
+                     mask);
+}
+void launch_cast_f32_to_f64(const float* a, double* b, size_t per_sample, int S, const int* mask,
+                            hipStream_t st) {
+  const int nb = (int)std::min<size_t>((per_sample + kBlock - 1) / kBlock, 4096);
+  hipLaunchKernelGGL((k_cast<float, double>), dim3(nb, S), dim3(kBlock), 0, st, a, b, per_sample,
+                     mask);
+}
+
+// ---------------------------------------------------------------------------
+// coarsest grid: dense matrix (natural unknown order 2v+var), explicit inverse by
+// Gauss-Jordan elimination with partial pivoting, applied as a dense product
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_coarse_dense(Geom g, const double* A_all, double* M_all,
+                                                         const int* mask) {
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.N) return;
+  int i, j, k;
+  colour_decode(g, t, i, j, k);
+  const size_t N = g.N, n = 2 * N;
+  const double* A = A_all + (size_t)s * kPlanes * N + t;
+  double* M = M_all + (size_t)s * n * n;
+  const size_t v = i + (size_t)g.nx * (j + (size_t)g.ny * k);
+  for (int dz = -1; dz <= 1; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int ii = i + dx, jj = j + dy, kk = k + dz;
+        if (ii < 0 || jj < 0 || kk < 0 || ii >= g.nx || jj >= g.ny || kk >= g.nz) continue;
+        const size_t w = ii + (size_t)g.nx * (jj + (size_t)g.ny * kk);
+        const int o = nb_index(dx, dy, dz);
+        for (int e = 0; e < 2; ++e)
+          for (int var = 0; var < 2; ++var)
+            M[(2 * v + e) * n + 2 * w + var] = A[(size_t)(o * 4 + e * 2 + var) * N];
+      }
+}
+
+void launch_coarse_dense(const Geom& g, const double* A, double* M, int S, const int* mask,
+                         hipStream_t st) {
+  const size_t n = 2 * (size_t)g.N;
+  launch_fill<double>(M, n * n, S, mask, 0.0, st);
+  dim3 grid(ceil_div(g.N, kBlock), S);
+  hipLaunchKernelGGL(k_coarse_dense, grid, dim3(kBlock), 0, st, g, A, M, mask);
+}
+
+constexpr int kGJThreads = 1024;
+
+__global__ __launch_bounds__(kGJThreads) void k_gauss_jordan(int n, double* M_all, int* piv_all,
+                                                             int* status, const int* mask) {
+  const int s = blockIdx.x;
+  if (mask && !mask[s]) return;
+  double* M = M_all + (size_t)s * n * n;
+  int* piv = piv_all + (size_t)s * n;
+  __shared__ double rowk[kMaxCoarse];
+  __shared__ double colk[kMaxCoarse];
+  __shared__ double red_v[kGJThreads];
+  __shared__ int red_i[kGJThreads];
+  __shared__ double s_pivinv;
+  __shared__ int s_p;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  bool singular = false;
+  for (int k = 0; k < n; ++k) {
+    // pivot: largest |M[i][k]|, i >= k, smallest i on ties
+    double bv = -1.0;
+    int bi = n;
+    for (int i = k + tid; i < n; i += nt) {
+      const double a = fabs(M[(size_t)i * n + k]);
+      if (a > bv) {
+        bv = a;
+        bi = i;
+      }
+    }
+    red_v[tid] = bv;
+    red_i[tid] = bi;
+    __syncthreads();
+    for (int w = nt / 2; w > 0; w >>= 1) {
+      if (tid < w) {
+        const double ov = red_v[tid + w];
+        const int oi = red_i[tid + w];
+        if (ov > red_v[tid] || (ov == red_v[tid] && oi < red_i[tid])) {
+          red_v[tid] = ov;
+          red_i[tid] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      s_p = red_i[0];
+      piv[k] = s_p;
+    }
+    __syncthreads();
+    const int p = s_p;
+    if (p != k)
+      for (int j = tid; j < n; j += nt) {
+        const double a = M[(size_t)k * n + j];
+        M[(size_t)k * n + j] = M[(size_t)p * n + j];
+        M[(size_t)p * n + j] = a;
+      }
+    __syncthreads();
+    if (tid == 0) {
+      const double d = M[(size_t)k * n + k];
+      s_pivinv = d != 0.0 ? 1.0 / d : 0.0;
+    }
+    __syncthreads();
+    const double pivinv = s_pivinv;
+    if (pivinv == 0.0) singular = true;
+    for (int j = tid; j < n; j += nt) rowk[j] = (j == k) ? pivinv : M[(size_t)k * n + j] * pivinv;
+    for (int i = tid; i < n; i += nt) colk[i] = (i == k) ? 0.0 : M[(size_t)i * n + k];
+    __syncthreads();
+    const int nn = n * n;
+    for (int idx = tid; idx < nn; idx += nt) {
+      const int i = idx / n, j = idx - i * n;
+      if (i == k)
+        M[idx] = rowk[j];
+      else if (j == k)
+        M[idx] = -colk[i] * pivinv;
+      else
+        M[idx] -= colk[i] * rowk[j];
+    }
+    __syncthreads();
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    const int p = piv[k];
+    if (p != k)
+      for (int i = tid; i < n; i += nt) {
+        const double a = M[(size_t)i * n + k];
+        M[(size_t)i * n + k] = M[(size_t)i * n + p];
+        M[(size_t)i * n + p] = a;
+      }
+    __syncthreads();
+  }
+  if (tid == 0 && status) status[s] = singular ? 1 : 0;
+}
+
+void launch_gauss_jordan(int n, double* M, int* piv, int* status, int S, const int* mask,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_gauss_jordan, dim3(S), dim3(kGJThreads), 0, st, n, M, piv, status, mask);
+}
+
+// x = M^{-1} b: one wave per row, lanes stride the columns
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_coarse_apply(int n, const double* Minv_all, const T* b_all,
+                                                         T* x_all, const int* mask) {
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = blockIdx.x * (kBlock / 64) + wave;
+  if (row >= n) return;
+  const double* Mr = Minv_all + (size_t)s * n * n + (size_t)row * n;
+  const T* b = b_all + (size_t)s * n;
+  double acc = 0.0;
+  for (int j = lane; j < n; j += 64) acc += Mr[j] * (double)b[j];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) x_all[(size_t)s * n + row] = (T)acc;
+}
+
+template <typename T>
+void launch_coarse_apply(int n, const double* Minv, const T* b, T* x, int S, const int* mask,
+                         hipStream_t st) {
+  dim3 grid(ceil_div(n, kBlock / 64), S);
+  hipLaunchKernelGGL(k_coarse_apply<T>, grid, dim3(kBlock), 0, st, n, Minv, b, x, mask);
+}
+
+// explicit instantiations
+#define EDF_INST(T)                                                                              \
+  template void launch_smooth<T>(const Geom&, int, const T*, const T*, const T*, T*, int,        \
+                                 const int*, hipStream_t, hipEvent_t, hipEvent_t);               \
+  template void launch_residual<T>(const Geom&, const T*, const T*, const T*, T*, int,           \
+                                   const int*, hipStream_t);                                     \
+  template void launch_restrict<T>(const Geom&, const Geom&, const T*, T*, T*, int, const int*,  \
+                                   hipStream_t);                                                 \
+  template void launch_prolong<T>(const Geom&, const Geom&, const T*, T*, int, const int*,       \
+                                  hipStream_t);                                                  \
+  template void launch_fill<T>(T*, size_t, int, const int*, T, hipStream_t);                     \
+  template void launch_coarse_apply<T>(int, const double*, const T*, T*, int, const int*,        \
+                                       hipStream_t);
+EDF_INST(double)
+EDF_INST(float)
+template void launch_fill<int>(int*, size_t, int, const int*, int, hipStream_t);
+
+}  // namespace edf

@@ -1,0 +1,306 @@
+"""Parity of the HIP path (through the C-ABI) with the oracle, element by element.
+
+All tests here need an MI355X and the built libedf.so.  Inputs are seeded and
+synthetic; the oracle runs on the host CPU.  Tolerances: FP64 results within
+1e-10 relative L2 per field (the bar for the FP64 path), residual and Jacobian
+entries within 1e-11 of the largest entry of their row (rounding of ~30 terms).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import elder, newton, stats
+
+pytestmark = pytest.mark.gpu
+
+DT = synth.MONTH_S
+TIGHT = dict(newton_rtol=1e-13, newton_atol=0.0, lin_rtol=1e-12, lin_max_it=600,
+             newton_max_it=40, check_every=8)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1906_01632_amd import load_library
+    load_library()
+
+
+def _problem(phys, groups, **opts):
+    from paper_1906_01632_amd import Problem
+    o = dict(TIGHT)
+    o.update(opts)
+    return Problem(phys, groups, o)
+
+
+def _xi(model, S, seed=3):
+    n = synth.N_XI[model]
+    return np.random.default_rng(seed).uniform(-1, 1, (S, n))
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+SHAPES = [((9, 9, 3), 2), ((17, 13, 5), 3), ((33, 33, 9), 4), ((41, 25, 9), 3)]
+
+
+@pytest.mark.parametrize("shape,levels", SHAPES)
+@pytest.mark.parametrize("model", [0, 2, 3])
+def test_defect_matches_oracle(shape, levels, model):
+    nx, ny, nz = shape
+    phys = synth.physics(model)
+    xi = _xi(model, 2)
+    pb = _problem(phys, [(nx, ny, nz, levels, 2)])
+    pb.set_parameters(xi)
+    box = elder.Box(nx, ny, nz, phys)
+    for s in range(2):
+        u = synth.random_state(nx, ny, nz, phys, seed=10 + s)
+        uo = synth.random_state(nx, ny, nz, phys, seed=20 + s)
+        got = pb.residual(s, u, uo, DT)
+        coef = elder.coefficients(box, xi[s])
+        ref = elder.residual(box, coef, u, uo, DT) * elder.row_scale(box, DT)
+        scale = np.abs(ref).max()
+        assert np.abs(got - ref).max() <= 1e-11 * scale, (s, np.abs(got - ref).max(), scale)
+    pb.destroy()
+
+
+def _oracle_stencil(box, coef, u):
+    """Oracle Jacobian scaled like the library's, as [27][2][2][nz][ny][nx]."""
+    J = elder.jacobian(box, coef, u, DT)
+    rs = elder.row_scale(box, DT).reshape(-1)
+    cs = np.tile(elder.col_scale(box), box.N)
+    Js = (J.multiply(rs[:, None]).multiply(cs[None, :])).tocoo()
+    out = np.zeros((27, 2, 2, box.nz, box.ny, box.nx))
+    v, w = Js.row // 2, Js.col // 2
+    eq, var = Js.row % 2, Js.col % 2
+    nx, ny = box.nx, box.ny
+    iv, jv, kv = v % nx, (v // nx) % ny, v // (nx * ny)
+    iw, jw, kw = w % nx, (w // nx) % ny, w // (nx * ny)
+    o = (iw - iv + 1) + 3 * (jw - jv + 1) + 9 * (kw - kv + 1)
+    np.add.at(out, (o, eq, var, kv, jv, iv), Js.data)
+    return out
+
+
+@pytest.mark.parametrize("shape,levels", SHAPES[:3])
+@pytest.mark.parametrize("model", [0, 2])
+def test_jacobian_matches_oracle_on_every_level(shape, levels, model):
+    nx, ny, nz = shape
+    phys = synth.physics(model)
+    xi = _xi(model, 1)
+    pb = _problem(phys, [(nx, ny, nz, levels, 1)])
+    pb.set_parameters(xi)
+    u = synth.random_state(nx, ny, nz, phys, seed=5)
+    for level in range(levels):
+        got = pb.get_jacobian(0, u, DT, level)
+        r = 2 ** level
+        box = elder.Box((nx - 1) // r + 1, (ny - 1) // r + 1, (nz - 1) // r + 1, phys)
+        ul = u[::r, ::r, ::r]
+        ref = _oracle_stencil(box, elder.coefficients(box, xi[0]), ul)
+        rowmax = np.abs(ref).max(axis=(0, 2), keepdims=True)
+        err = np.abs(got - ref) / np.maximum(rowmax, 1e-300)
+        assert err.max() < 1e-11, (level, err.max())
+    pb.destroy()
+
+
+@pytest.mark.parametrize("shape,levels,model", [((9, 9, 3), 2, 0), ((17, 17, 5), 3, 2),
+                                                ((33, 33, 9), 4, 0), ((41, 25, 9), 3, 3)])
+def test_one_step_from_initial_state(shape, levels, model):
+    nx, ny, nz = shape
+    phys = synth.physics(model)
+    xi = _xi(model, 1, seed=9)
+    pb = _problem(phys, [(nx, ny, nz, levels, 1)])
+    pb.set_parameters(xi)
+    st = pb.step(DT)
+    assert st[0]["status"] == 0, st
+    box = elder.Box(nx, ny, nz, phys)
+    ref = newton.newton_solve(box, elder.coefficients(box, xi[0]),
+                              synth.initial_state(nx, ny, nz, phys), DT)
+    got = pb.get_state(0)
+    for f in range(2):
+        assert _rel(got[..., f], ref[..., f]) < 1e-10, (f, _rel(got[..., f], ref[..., f]))
+    pb.destroy()
+
+
+def test_step_from_shared_later_state():
+    """Per-step parity from a developed state (after 3 oracle steps)."""
+    nx, ny, nz = 17, 17, 5
+    phys = synth.physics(2)
+    xi = _xi(2, 1, seed=4)
+    box = elder.Box(nx, ny, nz, phys)
+    coef = elder.coefficients(box, xi[0])
+    u = synth.initial_state(nx, ny, nz, phys)
+    for _ in range(3):
+        u = newton.newton_solve(box, coef, u, DT)
+    ref = newton.newton_solve(box, coef, u, DT)
+    pb = _problem(phys, [(nx, ny, nz, 3, 1)])
+    pb.set_parameters(xi)
+    pb.set_state(0, u)
+    pb.step(DT)
+    got = pb.get_state(0)
+    for f in range(2):
+        assert _rel(got[..., f], ref[..., f]) < 1e-10
+    # the increment itself agrees, not only the state
+    dc_ref, dc_got = ref[..., 1] - u[..., 1], got[..., 1] - u[..., 1]
+    assert _rel(dc_got, dc_ref) < 1e-8
+    pb.destroy()
+
+
+def test_short_trajectory_33():
+    """Three steps of the 33x33x9 deterministic box, the oracle stepping beside it."""
+    nx, ny, nz = 33, 33, 9
+    phys = synth.physics(0)
+    pb = _problem(phys, [(nx, ny, nz, 4, 1)])
+    pb.set_parameters(np.zeros((1, 0)))
+    box = elder.Box(nx, ny, nz, phys)
+    coef = elder.coefficients(box, [])
+    u = synth.initial_state(nx, ny, nz, phys)
+    for n in range(3):
+        u = newton.newton_solve(box, coef, u, DT)
+        pb.step(DT)
+        got = pb.get_state(0)
+        errs = [_rel(got[..., f], u[..., f]) for f in range(2)]
+        print(f"step {n + 1}: rel L2 p {errs[0]:.2e} c {errs[1]:.2e}", flush=True)
+        assert max(errs) < 1e-10
+    pb.destroy()
+
+
+def test_batched_sample_equals_single_sample():
+    """A sample advanced inside a batch is bitwise the sample advanced alone."""
+    nx, ny, nz = 17, 17, 5
+    phys = synth.physics(2)
+    xi = _xi(2, 3, seed=8)
+    opts = dict(newton_rtol=1e-10, lin_rtol=1e-8)
+    pb = _problem(phys, [(nx, ny, nz, 3, 3)], **opts)
+    pb.set_parameters(xi)
+    pb.step(DT)
+    pb.step(DT)
+    batch = [pb.get_state(s) for s in range(3)]
+    pb.destroy()
+    for s in range(3):
+        one = _problem(phys, [(nx, ny, nz, 3, 1)], **opts)
+        one.set_parameters(xi[s:s + 1])
+        one.step(DT)
+        one.step(DT)
+        np.testing.assert_array_equal(one.get_state(0), batch[s])
+        one.destroy()
+
+
+def test_runs_are_deterministic():
+    nx, ny, nz = 33, 17, 9
+    phys = synth.physics(2)
+    xi = _xi(2, 2, seed=1)
+    out = []
+    for _ in range(2):
+        pb = _problem(phys, [(nx, ny, nz, 3, 2)], newton_rtol=1e-10, lin_rtol=1e-8)
+        pb.set_parameters(xi)
+        pb.solve(DT, 2)
+        out.append([pb.get_state(s) for s in range(2)])
+        pb.destroy()
+    for a, b in zip(*out):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_mixed_resolution_groups_and_moments():
+    """Two resolution groups in one problem; pooled moments on the common grid equal
+    the oracle's statistics of the same injected fields."""
+    phys = synth.physics(2)
+    xi = synth.lattice_points(16, 4, seed=2)[:6]
+    pb = _problem(phys, [(9, 9, 3, 2, 4), (17, 17, 5, 3, 2)], newton_rtol=1e-10, lin_rtol=1e-8)
+    pb.set_parameters(xi)
+    st = pb.solve(DT, 2)
+    assert all(s["status"] == 0 for s in st)
+    mean, var, exc = pb.moments((9, 9, 3), threshold=0.5)
+    fields = [pb.get_state(s)[..., 1] for s in range(4)]
+    fields += [stats.inject(pb.get_state(s)[..., 1], (9, 9, 3)) for s in range(4, 6)]
+    m, v, e = stats.moments(np.array(fields), threshold=0.5)
+    assert np.abs(mean - m).max() < 1e-14
+    assert np.abs(var - v).max() < 1e-14
+    assert np.abs(exc - e).max() < 1e-14
+    w = np.arange(1, 7, dtype=float)
+    mean_w, var_w, _ = pb.moments((9, 9, 3), weights=w)
+    m, v, _ = stats.moments(np.array(fields), weights=w / w.sum())
+    assert np.abs(mean_w - m).max() < 1e-14 and np.abs(var_w - v).max() < 1e-14
+    # each group stepped exactly like the oracle
+    for s, (nx, ny, nz) in [(0, (9, 9, 3)), (5, (17, 17, 5))]:
+        box = elder.Box(nx, ny, nz, phys)
+        coef = elder.coefficients(box, xi[s])
+        u = synth.initial_state(nx, ny, nz, phys)
+        for _ in range(2):
+            u = newton.newton_solve(box, coef, u, DT)
+        got = pb.get_state(s)
+        assert _rel(got[..., 1], u[..., 1]) < 1e-8
+    pb.destroy()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_vcycle_is_a_contraction(precision):
+    """One V-cycle reduces the residual of the Newton matrix by a solid factor."""
+    nx, ny, nz = 33, 33, 9
+    phys = synth.physics(2)
+    pb = _problem(phys, [(nx, ny, nz, 4, 2)], precision=precision)
+    pb.set_parameters(_xi(2, 2))
+    b = np.random.default_rng(0).standard_normal((2, nz, ny, nx, 2))
+    b[..., 1][:, -1] = 0.0
+    y = pb.apply_vcycle(0, DT, b)
+    Ay = pb.apply_jacobian(0, y)
+    for s in range(2):
+        red = np.linalg.norm(b[s] - Ay[s]) / np.linalg.norm(b[s])
+        print(f"sample {s} precision {precision}: |b - A M^-1 b|/|b| = {red:.3f}", flush=True)
+        assert red < 0.5
+    pb.destroy()
+
+
+def test_mixed_precision_step_matches_fp64_oracle():
+    nx, ny, nz = 33, 33, 9
+    phys = synth.physics(2)
+    xi = _xi(2, 1, seed=6)
+    pb = _problem(phys, [(nx, ny, nz, 4, 1)], precision=1)
+    pb.set_parameters(xi)
+    pb.step(DT)
+    box = elder.Box(nx, ny, nz, phys)
+    ref = newton.newton_solve(box, elder.coefficients(box, xi[0]),
+                              synth.initial_state(nx, ny, nz, phys), DT)
+    got = pb.get_state(0)
+    for f in range(2):
+        assert _rel(got[..., f], ref[..., f]) < 1e-6
+    pb.destroy()
+
+
+def test_single_level_and_thinnest_grid():
+    """Edge cases: one grid only (the dense coarse solve is the whole preconditioner)
+    and the thinnest grid nz = 2."""
+    for shape, levels in [((5, 5, 3), 1), ((9, 9, 2), 1), ((5, 5, 2), 1), ((9, 9, 5), 3)]:
+        nx, ny, nz = shape
+        phys = synth.physics(0)
+        pb = _problem(phys, [(nx, ny, nz, levels, 1)])
+        pb.set_parameters(np.zeros((1, 0)))
+        pb.step(DT)
+        box = elder.Box(nx, ny, nz, phys)
+        ref = newton.newton_solve(box, elder.coefficients(box, []),
+                                  synth.initial_state(nx, ny, nz, phys), DT)
+        got = pb.get_state(0)
+        for f in range(2):
+            assert _rel(got[..., f], ref[..., f]) < 1e-10, (shape, f)
+        pb.destroy()
+
+
+def test_invalid_arguments_are_rejected():
+    from paper_1906_01632_amd import EDFError
+    phys = synth.physics(2)
+    with pytest.raises(EDFError):
+        _problem(phys, [(10, 9, 3, 2, 1)])        # 9 not divisible by 2
+    with pytest.raises(EDFError):
+        _problem(phys, [(65, 65, 17, 2, 1)])      # coarsest grid too large for the dense solve
+    pb = _problem(phys, [(9, 9, 3, 2, 1)])
+    with pytest.raises(EDFError):
+        pb.step(DT)                               # parameters not set
+    with pytest.raises(EDFError):
+        pb.set_parameters(np.full((1, 4), 1.5))   # |xi| > 1
+    pb.set_parameters(np.zeros((1, 4)))
+    with pytest.raises(EDFError):
+        pb.step(-1.0)
+    with pytest.raises(EDFError):
+        pb.moments((4, 9, 3))                     # not nested
+    pb.destroy()
