@@ -62,7 +62,8 @@ enum {
   EDF_SAMPLE_OK = 0,
   EDF_SAMPLE_NEWTON_FAIL = 1, /* Newton reached its iteration limit                 */
   EDF_SAMPLE_LINEAR_FAIL = 2, /* BiCGStab reached its limit in the last Newton step */
-  EDF_SAMPLE_NONFINITE = 3    /* the residual became NaN or Inf                     */
+  EDF_SAMPLE_NONFINITE = 3,   /* the residual became NaN or Inf                     */
+  EDF_SAMPLE_INADMISSIBLE = 4 /* Newton converged to a state with c outside [0, 1]  */
 };
 
 /* porosity/permeability field models (hex-centroid values, Section 2.2):
@@ -110,16 +111,20 @@ typedef struct {
   int32_t nu_pre, nu_post; /* block Gauss-Seidel sweeps before/after coarse grid   */
   int32_t precision;       /* EDF_PREC_*                                           */
   int32_t check_every;     /* BiCGStab iterations between host convergence checks  */
-  int32_t reserved[5];     /* must be zero                                         */
+  int32_t dt_max_halvings; /* a sample whose step fails is redone as 2^h equal      */
+                           /* sub-steps, h = 1..dt_max_halvings (0: no retry)       */
+  int32_t reserved[4];     /* must be zero                                         */
 } edf_solver_opts;
 
 typedef struct {
   int32_t status;       /* EDF_SAMPLE_*                                            */
-  int32_t newton_its;   /* Newton iterations of the last step                      */
+  int32_t newton_its;   /* Newton iterations of the last step (all attempts)       */
   int32_t lin_its;      /* BiCGStab iterations summed over those Newton iterations */
   int32_t ls_halvings;  /* line-search halvings summed over them                   */
-  double defect0;       /* ||F~|| at the start of the step                         */
-  double defect;        /* ||F~|| at the end of the step                           */
+  int32_t substeps;     /* the step was taken as this many equal sub-steps (2^h)   */
+  int32_t reserved;
+  double defect0;       /* ||F~|| at the start of the step (full step length)      */
+  double defect;        /* ||F~|| at the end of the last sub-step                  */
 } edf_step_stats;
 
 /* Creates a problem.  groups[n_groups] describe the resolution groups; every sample
@@ -142,8 +147,16 @@ edf_status edf_set_parameters(edf_problem* pb, const double* xi);
 edf_status edf_set_state(edf_problem* pb, int32_t sample, const double* pc, int32_t is_device_ptr);
 edf_status edf_get_state(edf_problem* pb, int32_t sample, double* pc, int32_t is_device_ptr);
 
-/* Exactly one implicit-Euler step of length dt [s] for every sample.  stats, if not
- * NULL, is a host array [S_total].  Synchronises when stats is not NULL. */
+/* Exactly one implicit-Euler step of length dt [s] for every sample (Section 2.3),
+ * taken as 2^h equal implicit-Euler sub-steps of dt / 2^h (stats.substeps = 2^h).
+ * h starts at the value that worked for the sample in its previous step (0 at
+ * first; lowered by one after three steps without a retry).  A sample whose Newton
+ * iteration fails (iteration limit, no 100-fold residual reduction after 8
+ * iterations, a non-finite or 1e4-fold grown residual, or a converged state with c
+ * outside [-0.05, 1.05]) restarts the step from its state at the start of the call
+ * with h raised by one, up to opts.dt_max_halvings; after that its status is the
+ * failure and its state is left unchanged.  stats, if not NULL, is a host array
+ * [S_total].  Synchronises. */
 edf_status edf_step(edf_problem* pb, double dt, edf_step_stats* stats);
 
 /* n_steps steps of length dt; stats (host [S_total] or NULL) describe the last step. */

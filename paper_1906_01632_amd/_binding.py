@@ -15,6 +15,7 @@ STATUS_NAMES = {1: "EDF_ERR_ARG", 2: "EDF_ERR_OOM", 3: "EDF_ERR_HIP", 4: "EDF_ER
                 5: "EDF_ERR_NO_CONVERGENCE", 6: "EDF_ERR_NONFINITE"}
 PREC_F64, PREC_MIXED = 0, 1
 SAMPLE_OK, SAMPLE_NEWTON_FAIL, SAMPLE_LINEAR_FAIL, SAMPLE_NONFINITE = 0, 1, 2, 3
+SAMPLE_INADMISSIBLE = 4
 N_XI = {0: 0, 1: 1, 2: 4, 3: 3}
 
 
@@ -42,12 +43,14 @@ class SolverOpts(C.Structure):
                 ("lin_rtol", C.c_double), ("newton_max_it", C.c_int32),
                 ("ls_max_halvings", C.c_int32), ("lin_max_it", C.c_int32),
                 ("nu_pre", C.c_int32), ("nu_post", C.c_int32), ("precision", C.c_int32),
-                ("check_every", C.c_int32), ("reserved", C.c_int32 * 5)]
+                ("check_every", C.c_int32), ("dt_max_halvings", C.c_int32),
+                ("reserved", C.c_int32 * 4)]
 
 
 class StepStats(C.Structure):
     _fields_ = [("status", C.c_int32), ("newton_its", C.c_int32), ("lin_its", C.c_int32),
-                ("ls_halvings", C.c_int32), ("defect0", C.c_double), ("defect", C.c_double)]
+                ("ls_halvings", C.c_int32), ("substeps", C.c_int32), ("reserved", C.c_int32),
+                ("defect0", C.c_double), ("defect", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -114,7 +117,7 @@ def _physics_c(phys: dict) -> PhysicsC:
 def default_options(**over) -> dict:
     o = dict(newton_rtol=1e-10, newton_atol=0.0, lin_rtol=1e-6, newton_max_it=20,
              ls_max_halvings=5, lin_max_it=200, nu_pre=1, nu_post=1, precision=PREC_F64,
-             check_every=4)
+             check_every=4, dt_max_halvings=4)
     o.update(over)
     return o
 

@@ -44,11 +44,13 @@ struct Group {
   KrylovScalars* ks = nullptr;
   double* part = nullptr;
   int *nmask = nullptr, *active = nullptr, *lsmask = nullptr;
-  double *norms = nullptr, *lam = nullptr;
+  double *norms = nullptr, *lam = nullptr, *dts = nullptr, *crange = nullptr;
+  double* u0 = nullptr;  // state at the start of the current step (restart point)
   double* Minv = nullptr;
   int *piv = nullptr, *gj_status = nullptr;
   int n_coarse = 0;
   int n_active = 0;  // samples active in the current Krylov chunk (known at chunk start)
+  std::vector<int> h_start, clean;  // per sample: halvings to start the next step with
   std::vector<edf_step_stats> stats;
 };
 
@@ -158,7 +160,8 @@ Phys make_phys(const edf_physics& P, const Geom& g, double dt) {
   ph.g = P.g;
   ph.Dm = P.Dm;
   ph.dt = dt;
-  ph.s_row = dt / (P.rho0 * P.phi_mean * g.hx * g.hy * g.hz);
+  ph.row_c = 1.0 / (P.rho0 * P.phi_mean * g.hx * g.hy * g.hz);
+  ph.s_row = dt * ph.row_c;
   ph.p_unit = p_unit(P);
   return ph;
 }
@@ -246,6 +249,9 @@ edf_status alloc_group(edf_problem* pb, Group& G) {
   if ((s = dalloc(pb, &G.lsmask, (size_t)S))) return s;
   if ((s = dalloc(pb, &G.norms, (size_t)S))) return s;
   if ((s = dalloc(pb, &G.lam, (size_t)S))) return s;
+  if ((s = dalloc(pb, &G.dts, (size_t)S))) return s;
+  if ((s = dalloc(pb, &G.crange, 2 * (size_t)S))) return s;
+  if ((s = dalloc(pb, &G.u0, S * n))) return s;
   G.n_coarse = 2 * G.lv[G.L - 1].g.N;
   const size_t nc = G.n_coarse;
   if ((s = dalloc(pb, &G.Minv, S * nc * nc))) return s;
@@ -290,19 +296,19 @@ edf_status find_sample(edf_problem* pb, int sample, Group** G, int* local) {
 // ---------------------------------------------------------------------------
 // matrices of all levels at the current iterate
 // ---------------------------------------------------------------------------
-edf_status assemble_all(edf_problem* pb, Group& G, const int* mask) {
+edf_status assemble_all(edf_problem* pb, Group& G, const int* mask, const double* dts) {
   const bool mx = mixed(pb);
   for (int l = 0; l < G.L; ++l) {
     Level& L = G.lv[l];
     if (l > 0) launch_inject(G.lv[l - 1].g, L.g, G.lv[l - 1].u, L.u, G.S, mask, pb->st);
     const bool coarsest = l == G.L - 1;
     if (l == 0)  // exact Jacobian for the Krylov products
-      launch_assemble(L.g, L.ph, L.phi, L.K, L.u, L.A64, nullptr, G.S, mask, pb->st, false);
+      launch_assemble(L.g, L.ph, dts, L.phi, L.K, L.u, L.A64, nullptr, G.S, mask, pb->st, false);
     // preconditioner matrix (frozen Darcy flux in the salt rows): FP32 on the smoothed
     // levels in mixed mode, FP64 otherwise and always on the coarsest level
     double* m64 = (mx && !coarsest) ? nullptr : (l == 0 ? L.AV64 : L.A64);
     float* m32 = (mx && !coarsest) ? L.A32 : nullptr;
-    launch_assemble(L.g, L.ph, L.phi, L.K, L.u, m64, m32, G.S, mask, pb->st, true);
+    launch_assemble(L.g, L.ph, dts, L.phi, L.K, L.u, m64, m32, G.S, mask, pb->st, true);
     if (!coarsest) {
       if (mx)
         launch_block_inverse_f32(L.g, L.A32, (float*)L.Dinv, G.S, mask, pb->st);
@@ -494,30 +500,38 @@ void set_dt(edf_problem* pb, Group& G, double dt) {
 }
 
 // ---------------------------------------------------------------------------
-// one implicit-Euler step of a group: Newton with line search (Section 2.3)
+// Newton with line search (Section 2.3) for the samples in `run`, each with its
+// own step length in G.dts and previous state in G.u_old.  ok[s] = 1 when the
+// sample converged to an admissible state (0 <= c <= 1 up to kRangeTol).
 // ---------------------------------------------------------------------------
-edf_status newton_step(edf_problem* pb, Group& G, double dt) {
+constexpr double kRangeTol = 0.05;      // admissible overshoot of c beyond [0, 1]
+constexpr double kDivergence = 1e4;     // give up when ||F~|| grows by this factor
+constexpr int kSlowIts = 8;             // give up after this many iterations ...
+constexpr double kSlowDrop = 1e-2;      // ... without this reduction of ||F~||
+
+edf_status newton_solve(edf_problem* pb, Group& G, const std::vector<int>& run,
+                        std::vector<int>& ok, std::vector<int>& why, bool first_attempt) {
   hipStream_t st = pb->st;
   const int S = G.S;
   const edf_solver_opts& o = pb->opts;
-  set_dt(pb, G, dt);
   const Level& L0 = G.lv[0];
   const double pu = p_unit(pb->phys);
-  EDF_TRY(hipMemcpyAsync(G.u_old, G.u, S * G.n * sizeof(double), hipMemcpyDeviceToDevice, st));
-  launch_defect(L0.g, L0.ph, L0.phi, L0.K, G.u, G.u_old, G.F, S, nullptr, st);
-  std::vector<double> r, r0, rt;
   edf_status e;
-  if ((e = read_norms(pb, G, G.F, nullptr, r))) return e;
+  if ((e = upload_ints(pb, G.nmask, run))) return e;
+  launch_defect(L0.g, L0.ph, G.dts, L0.phi, L0.K, G.u, G.u_old, G.F, S, G.nmask, st);
+  std::vector<double> r, r0, rt;
+  if ((e = read_norms(pb, G, G.F, G.nmask, r))) return e;
   r0 = r;
-  std::vector<int> nm(S, 1), ls(S);
+  std::vector<int> nm(run), ls(S), acc(S);
   std::vector<double> lam(S);
+  ok.assign(S, 0);
+  why.assign(S, EDF_SAMPLE_OK);
   for (int s = 0; s < S; ++s) {
-    edf_step_stats& q = G.stats[s];
-    q = edf_step_stats{};
-    q.defect0 = r0[s];
-    q.defect = r0[s];
+    if (!run[s]) continue;
+    if (first_attempt) G.stats[s].defect0 = r0[s];
+    G.stats[s].defect = r0[s];
     if (!std::isfinite(r0[s])) {
-      q.status = EDF_SAMPLE_NONFINITE;
+      why[s] = EDF_SAMPLE_NONFINITE;
       nm[s] = 0;
     }
   }
@@ -527,16 +541,17 @@ edf_status newton_step(edf_problem* pb, Group& G, double dt) {
       if (!nm[s]) continue;
       if (r[s] <= std::max(o.newton_rtol * r0[s], o.newton_atol)) {
         nm[s] = 0;
-      } else if (it >= o.newton_max_it) {
+        ok[s] = 1;
+      } else if (it >= o.newton_max_it || (it >= kSlowIts && r[s] > kSlowDrop * r0[s])) {
         nm[s] = 0;
-        G.stats[s].status = EDF_SAMPLE_NEWTON_FAIL;
+        why[s] = EDF_SAMPLE_NEWTON_FAIL;
       } else {
         any = true;
       }
     }
     if (!any) break;
     if ((e = upload_ints(pb, G.nmask, nm))) return e;
-    if ((e = assemble_all(pb, G, G.nmask))) return e;
+    if ((e = assemble_all(pb, G, G.nmask, G.dts))) return e;
     if ((e = bicgstab(pb, G))) return e;
     // BiCGStab statistics and the size of the Newton update
     EDF_TRY(hipMemcpyAsync(pb->h_ks, G.ks, S * sizeof(KrylovScalars), hipMemcpyDeviceToHost, st));
@@ -561,14 +576,14 @@ edf_status newton_step(edf_problem* pb, Group& G, double dt) {
       if ((e = upload_ints(pb, G.lsmask, ls))) return e;
       if ((e = upload_dbls(pb, G.lam, lam))) return e;
       launch_axpy_state(G.N, G.u, G.kx, G.lam, pu, G.ut, S, G.lsmask, st);
-      launch_defect(L0.g, L0.ph, L0.phi, L0.K, G.ut, G.u_old, G.Ft, S, G.lsmask, st);
+      launch_defect(L0.g, L0.ph, G.dts, L0.phi, L0.K, G.ut, G.u_old, G.Ft, S, G.lsmask, st);
       std::vector<double> rr;
       if ((e = read_norms(pb, G, G.Ft, G.lsmask, rr))) return e;
       for (int s = 0; s < S; ++s) {
         if (!ls[s]) continue;
         rt[s] = rr[s];
-        const bool ok = rr[s] <= (1.0 - l / 4.0) * r[s];
-        if (ok || h == o.ls_max_halvings) {
+        const bool decrease = rr[s] <= (1.0 - l / 4.0) * r[s];
+        if (decrease || h == o.ls_max_halvings) {
           ls[s] = 0;
         } else {
           lam[s] *= 0.5;
@@ -577,19 +592,123 @@ edf_status newton_step(edf_problem* pb, Group& G, double dt) {
       }
       l *= 0.5;
     }
-    launch_masked_copy(G.n, G.ut, G.u, S, G.nmask, st);
-    launch_masked_copy(G.n, G.Ft, G.F, S, G.nmask, st);
+    // accept the trial states that are finite; a non-finite trial ends the attempt
+    for (int s = 0; s < S; ++s) {
+      acc[s] = 0;
+      if (!nm[s]) continue;
+      if (!std::isfinite(rt[s]) || rt[s] > kDivergence * r0[s]) {
+        nm[s] = 0;
+        why[s] = std::isfinite(rt[s]) ? EDF_SAMPLE_NEWTON_FAIL : EDF_SAMPLE_NONFINITE;
+        continue;
+      }
+      acc[s] = 1;
+    }
+    if ((e = upload_ints(pb, G.lsmask, acc))) return e;
+    launch_masked_copy(G.n, G.ut, G.u, S, G.lsmask, st);
+    launch_masked_copy(G.n, G.Ft, G.F, S, G.lsmask, st);
     for (int s = 0; s < S; ++s)
-      if (nm[s]) {
+      if (acc[s]) {
         r[s] = rt[s];
         G.stats[s].defect = rt[s];
-        if (!std::isfinite(rt[s])) {
-          G.stats[s].status = EDF_SAMPLE_NONFINITE;
-          nm[s] = 0;
-        } else if (std::fabs(lam[s]) * dnorm[s] <= kUpdateFloor * std::sqrt((double)G.n)) {
+        if (std::fabs(lam[s]) * dnorm[s] <= kUpdateFloor * std::sqrt((double)G.n)) {
           nm[s] = 0;  // the update is at the rounding level of the scaled unknowns: converged
+          ok[s] = 1;
         }
       }
+  }
+  // admissibility of the converged states: the salt mass fraction stays in [0, 1]
+  bool any_ok = false;
+  for (int s = 0; s < S; ++s) any_ok |= ok[s] != 0;
+  if (any_ok) {
+    if ((e = upload_ints(pb, G.lsmask, ok))) return e;
+    launch_c_range(L0.g, G.u, G.part, G.crange, S, G.lsmask, st);
+    EDF_CHECK_LAUNCH();
+    std::vector<double> cr(2 * S);
+    EDF_TRY(hipMemcpyAsync(cr.data(), G.crange, 2 * S * sizeof(double), hipMemcpyDeviceToHost, st));
+    EDF_TRY(hipStreamSynchronize(st));
+    for (int s = 0; s < S; ++s)
+      if (ok[s] && !(cr[2 * s] >= -kRangeTol && cr[2 * s + 1] <= 1.0 + kRangeTol)) {
+        ok[s] = 0;
+        why[s] = EDF_SAMPLE_INADMISSIBLE;
+      }
+  }
+  EDF_CHECK_LAUNCH();
+  return EDF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// one implicit-Euler step of length DT for every sample of a group.  A sample
+// whose Newton solve fails restarts the step from its saved state as 2^h equal
+// sub-steps of DT / 2^h (h <= dt_max_halvings); samples advance in lockstep, one
+// sub-step each per round, and finished samples are masked out.
+// ---------------------------------------------------------------------------
+edf_status macro_step(edf_problem* pb, Group& G, double DT) {
+  hipStream_t st = pb->st;
+  const int S = G.S;
+  set_dt(pb, G, DT);
+  edf_status e;
+  EDF_TRY(hipMemcpyAsync(G.u0, G.u, S * G.n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  if ((int)G.h_start.size() != S) {
+    G.h_start.assign(S, 0);
+    G.clean.assign(S, 0);
+  }
+  std::vector<int> h(G.h_start), done(S, 0), running(S, 1), ok, why, restore(S);
+  std::vector<double> dts(S);
+  for (int s = 0; s < S; ++s) {
+    h[s] = std::min(h[s], pb->opts.dt_max_halvings);
+    G.stats[s] = edf_step_stats{};
+    G.stats[s].substeps = 1 << h[s];
+  }
+  bool first = true;
+  for (;;) {
+    bool any = false;
+    for (int s = 0; s < S; ++s) {
+      any |= running[s] != 0;
+      dts[s] = DT / double(1 << h[s]);
+    }
+    if (!any) break;
+    if ((e = upload_dbls(pb, G.dts, dts))) return e;
+    if ((e = upload_ints(pb, G.nmask, running))) return e;
+    launch_masked_copy(G.n, G.u, G.u_old, S, G.nmask, st);
+    if ((e = newton_solve(pb, G, running, ok, why, first))) return e;
+    first = false;
+    bool any_restore = false;
+    for (int s = 0; s < S; ++s) {
+      restore[s] = 0;
+      if (!running[s]) continue;
+      if (ok[s]) {
+        if (++done[s] == (1 << h[s])) running[s] = 0;
+        continue;
+      }
+      restore[s] = 1;
+      any_restore = true;
+      done[s] = 0;
+      if (h[s] < pb->opts.dt_max_halvings) {
+        h[s] += 1;
+        G.stats[s].substeps = 1 << h[s];
+      } else {
+        running[s] = 0;
+        G.stats[s].status = why[s];
+      }
+    }
+    if (any_restore) {
+      if ((e = upload_ints(pb, G.lsmask, restore))) return e;
+      launch_masked_copy(G.n, G.u0, G.u, S, G.lsmask, st);
+    }
+  }
+  // the next step starts with the sub-step count that worked; after three steps
+  // without a retry it tries one halving less
+  for (int s = 0; s < S; ++s) {
+    if (G.stats[s].status != EDF_SAMPLE_OK) continue;
+    if (h[s] == G.h_start[s]) {
+      if (++G.clean[s] >= 3 && h[s] > 0) {
+        G.h_start[s] = h[s] - 1;
+        G.clean[s] = 0;
+      }
+    } else {
+      G.h_start[s] = h[s];
+      G.clean[s] = 0;
+    }
   }
   EDF_CHECK_LAUNCH();
   return EDF_OK;
@@ -636,8 +755,10 @@ edf_status edf_create_problem(const edf_physics* phys, const edf_group_desc* gro
   if (opts->newton_max_it < 1 || opts->lin_max_it < 1 || opts->nu_pre < 1 || opts->nu_post < 0 ||
       opts->ls_max_halvings < 0 || !(opts->lin_rtol > 0) || !(opts->newton_rtol >= 0))
     return bad("invalid solver options");
-  for (int i = 0; i < 5; ++i)
+  for (int i = 0; i < 4; ++i)
     if (opts->reserved[i] != 0) return bad("reserved options must be zero");
+  if (opts->dt_max_halvings < 0 || opts->dt_max_halvings > 12)
+    return bad("dt_max_halvings must be in [0, 12]");
   int s0 = 0;
   for (int gi = 0; gi < n_groups; ++gi) {
     const edf_group_desc& d = groups[gi];
@@ -749,7 +870,7 @@ edf_status edf_step(edf_problem* pb, double dt, edf_step_stats* stats) {
   if (!(dt > 0) || !std::isfinite(dt)) return fail(pb, EDF_ERR_ARG, "dt must be positive");
   bool all_failed = true;
   for (Group& G : pb->groups) {
-    if ((e = newton_step(pb, G, dt))) return e;
+    if ((e = macro_step(pb, G, dt))) return e;
     for (int s = 0; s < G.S; ++s) {
       if (stats) stats[G.s0 + s] = G.stats[s];
       all_failed &= G.stats[s].status != EDF_SAMPLE_OK;
@@ -830,7 +951,8 @@ edf_status edf_residual(edf_problem* pb, int32_t sample, const double* u, const 
   EDF_TRY(hipMemcpyAsync(duo, u_old, n * sizeof(double), kin, pb->st));
   const Level& L = G->lv[0];
   const Phys ph = make_phys(pb->phys, L.g, dt);
-  launch_defect(L.g, ph, L.phi + s * L.cells, L.K + s * L.cells, du, duo, dF, 1, nullptr, pb->st);
+  launch_defect(L.g, ph, nullptr, L.phi + s * L.cells, L.K + s * L.cells, du, duo, dF, 1, nullptr,
+                pb->st);
   EDF_CHECK_LAUNCH();
   EDF_TRY(hipMemcpyAsync(F, dF, n * sizeof(double),
                          is_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, pb->st));
@@ -863,8 +985,8 @@ edf_status edf_get_jacobian(edf_problem* pb, int32_t sample, const double* u, do
   EDF_TRY(hipMalloc(&A, kPlanes * N * sizeof(double)));
   EDF_TRY(hipMalloc(&nat, kPlanes * N * sizeof(double)));
   const Phys ph = make_phys(pb->phys, L.g, dt);
-  launch_assemble(L.g, ph, L.phi + s * L.cells, L.K + s * L.cells, cur, A, nullptr, 1, nullptr,
-                  pb->st, false);
+  launch_assemble(L.g, ph, nullptr, L.phi + s * L.cells, L.K + s * L.cells, cur, A, nullptr, 1,
+                  nullptr, pb->st, false);
   launch_stencil_to_natural(L.g, A, nat, pb->st);
   EDF_CHECK_LAUNCH();
   EDF_TRY(hipMemcpyAsync(out, nat, kPlanes * N * sizeof(double), hipMemcpyDeviceToHost, pb->st));
@@ -884,7 +1006,7 @@ edf_status edf_apply_vcycle(edf_problem* pb, int32_t group, double dt, const dou
   set_dt(pb, G, dt);
   std::vector<int> all(G.S, 1);
   if ((e = upload_ints(pb, G.nmask, all))) return e;
-  if ((e = assemble_all(pb, G, G.nmask))) return e;
+  if ((e = assemble_all(pb, G, G.nmask, nullptr))) return e;
   EDF_TRY(hipMemcpyAsync(G.kp, x, G.S * G.n * sizeof(double), hipMemcpyHostToDevice, pb->st));
   G.n_active = G.S;
   precondition(pb, G, G.kp, G.kph, G.nmask);

@@ -28,8 +28,9 @@ struct Geom {
 // Physical constants and the scaling of one level (passed by value).
 struct Phys {
   double rho0, drho, mu, g, Dm;
-  double dt;
+  double dt;       // time step (kernels given a per-sample dt array override it)
   double s_row;    // dt / (rho0 phi_mean hx hy hz): scale of the finite-volume rows
+  double row_c;    // 1 / (rho0 phi_mean hx hy hz), so that s_row = dt * row_c
   double p_unit;   // rho0 max(g,1) lz: pressure unit of the scaled unknowns
 };
 
@@ -53,12 +54,15 @@ __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; 
 // ---------------------------------------------------------------------------
 void launch_coefficients(const Geom& g, const FieldParams& fp, const double* xi, int S,
                          double* phi, double* K, hipStream_t st);
-void launch_defect(const Geom& g, const Phys& ph, const double* phi, const double* K,
-                   const double* u, const double* u_old, double* F, int S, const int* mask,
-                   hipStream_t st);
-void launch_assemble(const Geom& g, const Phys& ph, const double* phi, const double* K,
-                     const double* u, double* A64, float* A32, int S, const int* mask,
-                     hipStream_t st, bool frozen);
+// dts: per-sample time steps [S] in device memory, or nullptr for ph.dt
+void launch_defect(const Geom& g, const Phys& ph, const double* dts, const double* phi,
+                   const double* K, const double* u, const double* u_old, double* F, int S,
+                   const int* mask, hipStream_t st);
+void launch_assemble(const Geom& g, const Phys& ph, const double* dts, const double* phi,
+                     const double* K, const double* u, double* A64, float* A32, int S,
+                     const int* mask, hipStream_t st, bool frozen);
+void launch_c_range(const Geom& g, const double* u, double* part, double* out, int S,
+                    const int* mask, hipStream_t st);
 void launch_block_inverse_f64(const Geom& g, const double* A, double* Dinv, int S,
                               const int* mask, hipStream_t st);
 void launch_block_inverse_f32(const Geom& g, const float* A, float* Dinv, int S,

@@ -185,12 +185,22 @@ __device__ __forceinline__ FaceGeo face_geo(const Geom& g) {
 // ---------------------------------------------------------------------------
 // scaled defect F~(u; u_old), one thread per vertex (natural order)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_defect(Geom g, Phys ph, const double* phi_all,
-                                                   const double* K_all, const double* u_all,
-                                                   const double* uo_all, double* F_all,
-                                                   const int* mask) {
+__device__ __forceinline__ Phys sample_phys(const Phys& ph, const double* dts, int s) {
+  Phys p = ph;
+  if (dts) {
+    p.dt = dts[s];
+    p.s_row = p.dt * ph.row_c;
+  }
+  return p;
+}
+
+__global__ __launch_bounds__(kBlock) void k_defect(Geom g, Phys ph0, const double* dts,
+                                                   const double* phi_all, const double* K_all,
+                                                   const double* u_all, const double* uo_all,
+                                                   double* F_all, const int* mask) {
   const int s = blockIdx.y;
   if (mask && !mask[s]) return;
+  const Phys ph = sample_phys(ph0, dts, s);
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= g.N) return;
   const int i = v % g.nx, j = (v / g.nx) % g.ny, k = v / (g.nx * g.ny);
@@ -223,11 +233,11 @@ __global__ __launch_bounds__(kBlock) void k_defect(Geom g, Phys ph, const double
   reinterpret_cast<double2*>(F_all)[(size_t)s * g.N + v] = out;
 }
 
-void launch_defect(const Geom& g, const Phys& ph, const double* phi, const double* K,
-                   const double* u, const double* u_old, double* F, int S, const int* mask,
-                   hipStream_t st) {
+void launch_defect(const Geom& g, const Phys& ph, const double* dts, const double* phi,
+                   const double* K, const double* u, const double* u_old, double* F, int S,
+                   const int* mask, hipStream_t st) {
   dim3 grid(ceil_div(g.N, kBlock), S);
-  hipLaunchKernelGGL(k_defect, grid, dim3(kBlock), 0, st, g, ph, phi, K, u, u_old, F, mask);
+  hipLaunchKernelGGL(k_defect, grid, dim3(kBlock), 0, st, g, ph, dts, phi, K, u, u_old, F, mask);
 }
 
 // ---------------------------------------------------------------------------
@@ -353,11 +363,13 @@ __device__ __forceinline__ void assemble_row(const Geom& g, const Phys& ph, cons
 // in the full system the pressure response cancels most of that feedback.  The Krylov
 // method always multiplies with the exact Jacobian (FROZEN = false).
 template <bool FROZEN>
-__global__ __launch_bounds__(kBlock) void k_assemble(Geom g, Phys ph, const double* phi_all,
-                                                     const double* K_all, const double* u_all,
-                                                     double* A64, float* A32, const int* mask) {
+__global__ __launch_bounds__(kBlock) void k_assemble(Geom g, Phys ph0, const double* dts,
+                                                     const double* phi_all, const double* K_all,
+                                                     const double* u_all, double* A64, float* A32,
+                                                     const int* mask) {
   const int s = blockIdx.y;
   if (mask && !mask[s]) return;
+  const Phys ph = sample_phys(ph0, dts, s);
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= g.N) return;
   int i, j, k;
@@ -375,16 +387,16 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Geom g, Phys ph, const doub
     assemble_row<1, FROZEN>(g, ph, phi, K, P, C, i, j, k, t, base, A64, A32);
 }
 
-void launch_assemble(const Geom& g, const Phys& ph, const double* phi, const double* K,
-                     const double* u, double* A64, float* A32, int S, const int* mask,
-                     hipStream_t st, bool frozen) {
+void launch_assemble(const Geom& g, const Phys& ph, const double* dts, const double* phi,
+                     const double* K, const double* u, double* A64, float* A32, int S,
+                     const int* mask, hipStream_t st, bool frozen) {
   dim3 grid(ceil_div(g.N, kBlock), S, 2);
   if (frozen)
-    hipLaunchKernelGGL(k_assemble<true>, grid, dim3(kBlock), 0, st, g, ph, phi, K, u, A64, A32,
-                       mask);
+    hipLaunchKernelGGL(k_assemble<true>, grid, dim3(kBlock), 0, st, g, ph, dts, phi, K, u, A64,
+                       A32, mask);
   else
-    hipLaunchKernelGGL(k_assemble<false>, grid, dim3(kBlock), 0, st, g, ph, phi, K, u, A64, A32,
-                       mask);
+    hipLaunchKernelGGL(k_assemble<false>, grid, dim3(kBlock), 0, st, g, ph, dts, phi, K, u, A64,
+                       A32, mask);
 }
 
 // ---------------------------------------------------------------------------

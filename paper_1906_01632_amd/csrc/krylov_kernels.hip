@@ -337,6 +337,69 @@ void launch_sq_norm(size_t n, const double* x, double* part, double* out, int S,
   hipLaunchKernelGGL(k_sum_partials, dim3(S), dim3(64), 0, st, nb, part, out, mask);
 }
 
+// per-sample minimum and maximum of c (admissibility check of a converged step):
+// out[s] = (min c, max c); block partials in part[s][b][0..1]
+__global__ __launch_bounds__(kBlock) void k_c_range(size_t N, const double* u, double* part,
+                                                    const int* mask) {
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const double2* u2 = reinterpret_cast<const double2*>(u) + (size_t)s * N;
+  double lo = 1e300, hi = -1e300;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < N;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const double c = u2[e].y;
+    lo = fmin(lo, c);
+    hi = fmax(hi, c);
+  }
+  __shared__ double sl[kBlock / 64], shh[kBlock / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = fmin(lo, __shfl_down(lo, off, 64));
+    hi = fmax(hi, __shfl_down(hi, off, 64));
+  }
+  if (lane == 0) {
+    sl[wave] = lo;
+    shh[wave] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / 64; ++w) {
+      lo = fmin(lo, sl[w]);
+      hi = fmax(hi, shh[w]);
+    }
+    part[((size_t)s * gridDim.x + blockIdx.x) * 4 + 0] = lo;
+    part[((size_t)s * gridDim.x + blockIdx.x) * 4 + 1] = hi;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_range_finalize(int nb, const double* part, double* out,
+                                                       const int* mask) {
+  const int s = blockIdx.x;
+  if (mask && !mask[s]) return;
+  double lo = 1e300, hi = -1e300;
+  for (int b = threadIdx.x; b < nb; b += 64) {
+    lo = fmin(lo, part[((size_t)s * nb + b) * 4 + 0]);
+    hi = fmax(hi, part[((size_t)s * nb + b) * 4 + 1]);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = fmin(lo, __shfl_down(lo, off, 64));
+    hi = fmax(hi, __shfl_down(hi, off, 64));
+  }
+  if (threadIdx.x == 0) {
+    out[2 * s] = lo;
+    out[2 * s + 1] = hi;
+  }
+}
+
+void launch_c_range(const Geom& g, const double* u, double* part, double* out, int S,
+                    const int* mask, hipStream_t st) {
+  const int nb = reduce_blocks(2 * (size_t)g.N);
+  hipLaunchKernelGGL(k_c_range, dim3(nb, S), dim3(kBlock), 0, st, (size_t)g.N, u, part, mask);
+  hipLaunchKernelGGL(k_range_finalize, dim3(S), dim3(64), 0, st, nb, part, out, mask);
+}
+
 // out = u + lam_s * (p_unit * d_p, d_c): Newton update in physical units
 __global__ __launch_bounds__(kBlock) void k_axpy_state(size_t N, const double* u, const double* d,
                                                        const double* lam, double p_unit,

@@ -304,3 +304,50 @@ def test_invalid_arguments_are_rejected():
     with pytest.raises(EDFError):
         pb.moments((4, 9, 3))                     # not nested
     pb.destroy()
+
+
+def test_failed_step_is_redone_as_equal_substeps():
+    """A 4-month step of a high-permeability sample lands on a spurious root (c < 0)
+    in one Newton solve; the library redoes it as 2^h equal sub-steps, and the oracle
+    replaying the same sub-steps gives the same state.  The other sample of the batch
+    takes the step whole."""
+    nx, ny, nz = 17, 17, 5
+    phys = synth.physics(2)
+    xi = np.array([[0.0, 0.0, 0.0, 0.0], [0.9, 0.9, 0.9, 0.9]])
+    dt = 4 * DT
+    pb = _problem(phys, [(nx, ny, nz, 3, 2)], dt_max_halvings=4)
+    pb.set_parameters(xi)
+    st = pb.step(dt)
+    print("substeps", [s["substeps"] for s in st], "status", [s["status"] for s in st], flush=True)
+    assert [s["status"] for s in st] == [0, 0]
+    assert st[0]["substeps"] == 1 and st[1]["substeps"] >= 2
+    box = elder.Box(nx, ny, nz, phys)
+    for s in range(2):
+        coef = elder.coefficients(box, xi[s])
+        u = synth.initial_state(nx, ny, nz, phys)
+        m = st[s]["substeps"]
+        for _ in range(m):
+            u = newton.newton_solve(box, coef, u, dt / m)
+        got = pb.get_state(s)
+        assert got[..., 1].min() >= -1e-9
+        for f in range(2):
+            assert _rel(got[..., f], u[..., f]) < 1e-10, (s, f)
+    pb.destroy()
+
+
+def test_sample_failure_is_reported_and_left_out_of_moments():
+    """Without step halving the spurious root is rejected: that sample reports the
+    failure, keeps its state, and the moments use the other sample only."""
+    nx, ny, nz = 17, 17, 5
+    phys = synth.physics(2)
+    xi = np.array([[0.0, 0.0, 0.0, 0.0], [0.9, 0.9, 0.9, 0.9]])
+    pb = _problem(phys, [(nx, ny, nz, 3, 2)], dt_max_halvings=0)
+    pb.set_parameters(xi)
+    before = pb.get_state(1)
+    st = pb.step(4 * DT)
+    assert st[0]["status"] == 0 and st[1]["status"] != 0
+    np.testing.assert_array_equal(pb.get_state(1), before)
+    mean, var, exc = pb.moments((9, 9, 3))
+    c0 = stats.inject(pb.get_state(0)[..., 1], (9, 9, 3))
+    assert np.abs(mean - c0).max() < 1e-15 and np.abs(var).max() < 1e-30
+    pb.destroy()
