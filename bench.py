@@ -26,6 +26,19 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def roctx_region():
+    """(start, stop) of the region that `rocprofv3 --selected-regions` collects, so that
+    the profiler sees exactly the timed steps; no-ops if the marker library is absent."""
+    import ctypes
+    for name in ("librocprofiler-sdk-roctx.so.1", "librocprofiler-sdk-roctx.so"):
+        try:
+            lib = ctypes.CDLL(name)
+            return (lambda: lib.roctxProfilerResume(0)), (lambda: lib.roctxProfilerPause(0))
+        except OSError:
+            continue
+    return (lambda: None), (lambda: None)
+
+
 def cpu_baseline(wl, phys, budget_s=20.0):
     """The oracle (plain FP64 NumPy/SciPy, unchanged) on a bounded sample of the
     workload: whole implicit-Euler steps of the samples of its smallest group."""
@@ -60,7 +73,14 @@ def main():
     ap.add_argument("--precision", choices=["f64", "mixed"], default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--forcing", type=int, default=1, choices=[0, 1],
+                    help="1: Eisenstat-Walker tolerances for the Newton systems")
+    ap.add_argument("--profile-timed-region", action="store_true",
+                    help="mark the timed steps for rocprofv3 --selected-regions")
     args = ap.parse_args()
+    region_start, region_stop = roctx_region() if args.profile_timed_region else (None, None)
+    if region_stop:
+        region_stop()  # nothing before the timed steps is collected
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): samples are independent, "
               "so N GPUs would each run their own share; no multi-GPU path is built.",
@@ -80,7 +100,8 @@ def main():
     phys = synth.physics(wl.field_model)
     groups = [(g.nx, g.ny, g.nz, g.levels, g.samples) for g in wl.groups]
     opts = dict(newton_rtol=wl.newton_rtol, lin_rtol=1e-6, lin_max_it=200, newton_max_it=20,
-                precision=PREC_MIXED if prec == "mixed" else PREC_F64, check_every=1)
+                precision=PREC_MIXED if prec == "mixed" else PREC_F64, check_every=1,
+                forcing=args.forcing)
     log(f"workload {wl.name}: groups {groups}, precision {prec}")
     t = time.perf_counter()
     pb = Problem(phys, groups, opts)
@@ -94,12 +115,16 @@ def main():
     if not args.no_profile:
         pb.profile(True)
     stats = None
+    if region_start:
+        region_start()
     t0 = time.perf_counter()
     for k in range(args.steps):
         stats = pb.step(wl.dt)
         log(f"step {k + 1}: {time.perf_counter() - t0:.2f} s elapsed")
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    if region_stop:
+        region_stop()
     prof = pb.profile(False)
     S = wl.n_samples
     dofs = sum(2 * g.n_vertices * g.samples for g in wl.groups)
@@ -121,11 +146,17 @@ def main():
         "data": "synthetic (seeded lattice parameters; no dataset)",
         "config": {"workload": wl.name, "groups": [list(g) for g in groups], "samples": S,
                    "dt_s": wl.dt, "precision": prec, "newton_rtol": wl.newton_rtol,
-                   "lin_rtol": 1e-6},
+                   "lin_rtol": 1e-6, "forcing": "eisenstat-walker" if args.forcing else "fixed"},
         "dof_timesteps_per_s": dofs * args.steps / el,
         "solver": {"newton_its_per_step": newton, "bicgstab_its_per_newton": lin,
                    "failed_samples_last_step": failed},
     }
+    if prof["vcycles"]:
+        vg = prof["vcycle_bytes"] / (prof["vcycle_ms"] * 1e-3) / 1e9
+        out["vcycle"] = {"achieved": vg, "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                         "frac": vg / HBM_PEAK_GBS, "count": prof["vcycles"],
+                         "avg_ms": prof["vcycle_ms"] / prof["vcycles"],
+                         "bytes_per_vcycle": prof["vcycle_bytes"] / prof["vcycles"]}
     if prof["launches"]:
         gbs = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9
         out["roofline"] = {"bound": "hbm", "kernel": "k_smooth (block Gauss-Seidel colour sweep)",

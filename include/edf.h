@@ -113,7 +113,10 @@ typedef struct {
   int32_t check_every;     /* BiCGStab iterations between host convergence checks  */
   int32_t dt_max_halvings; /* a sample whose step fails is redone as 2^h equal      */
                            /* sub-steps, h = 1..dt_max_halvings (0: no retry)       */
-  int32_t reserved[4];     /* must be zero                                         */
+  int32_t forcing;         /* 0: every Newton system solved to lin_rtol; 1: to the  */
+                           /* Eisenstat-Walker forcing term (choice 2, gamma 0.9,   */
+                           /* at most 0.1, at least lin_rtol)                       */
+  int32_t reserved[3];     /* must be zero                                         */
 } edf_solver_opts;
 
 typedef struct {
@@ -197,14 +200,17 @@ edf_status edf_apply_vcycle(edf_problem* pb, int32_t group, double dt, const dou
  * (edf_apply_vcycle or a Newton iteration); x, y host [S_group][N][2]. */
 edf_status edf_apply_jacobian(edf_problem* pb, int32_t group, const double* x, double* y);
 
-/* Timing of the dominant kernel, the block Gauss-Seidel smoother of the V-cycle.
- * edf_profile(pb, 1, out) starts: every later smoother launch is bracketed by HIP
- * events on the problem's stream.  edf_profile(pb, 0, out) stops.  Both fill out (if
- * not NULL, host double[3]) with the totals since the last start: out[0] = launches,
- * out[1] = summed kernel time [ms], out[2] = algorithmic bytes, counted per vertex of
- * the swept colour and per active sample as 108 stencil + 4 block-inverse entries +
- * 2 right-hand side + 4 own-unknown reads and writes, times the V-cycle precision.
- * Synchronises the stream. */
+/* Timing of the multigrid preconditioner with HIP events on the problem's stream.
+ * edf_profile(pb, 1, out) starts: every later smoother launch (the dominant kernel,
+ * block Gauss-Seidel over one colour) and every whole V-cycle is bracketed by events;
+ * edf_profile(pb, 0, out) stops.  Both fill out (if not NULL, host double[6]) with
+ * totals since the last start: out[0..2] = smoother launches, summed kernel time [ms],
+ * algorithmic bytes; out[3..5] = V-cycles, summed time [ms], algorithmic bytes.
+ * Smoother bytes per vertex of the swept colour and per active sample: 108 stencil +
+ * 4 block-inverse entries + 2 right-hand side + 4 own-unknown reads and writes, times
+ * the V-cycle precision.  V-cycle bytes per active sample: on every smoothed level
+ * N_l (3 x 108 + 2 x 4 + 12 x 2) values (three stencil sweeps, two block-inverse reads,
+ * twelve vector passes) plus the dense coarse inverse.  Synchronises the stream. */
 edf_status edf_profile(edf_problem* pb, int32_t enable, double* out);
 
 const char* edf_last_error(const edf_problem* pb);

@@ -44,7 +44,7 @@ class SolverOpts(C.Structure):
                 ("ls_max_halvings", C.c_int32), ("lin_max_it", C.c_int32),
                 ("nu_pre", C.c_int32), ("nu_post", C.c_int32), ("precision", C.c_int32),
                 ("check_every", C.c_int32), ("dt_max_halvings", C.c_int32),
-                ("reserved", C.c_int32 * 4)]
+                ("forcing", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class StepStats(C.Structure):
@@ -117,7 +117,7 @@ def _physics_c(phys: dict) -> PhysicsC:
 def default_options(**over) -> dict:
     o = dict(newton_rtol=1e-10, newton_atol=0.0, lin_rtol=1e-6, newton_max_it=20,
              ls_max_halvings=5, lin_max_it=200, nu_pre=1, nu_post=1, precision=PREC_F64,
-             check_every=4, dt_max_halvings=4)
+             check_every=4, dt_max_halvings=4, forcing=0)
     o.update(over)
     return o
 
@@ -253,11 +253,12 @@ class Problem:
         return y
 
     def profile(self, enable: bool):
-        """Starts (True) or stops (False) smoother timing; returns the totals since the
-        last start: {'launches', 'ms', 'bytes'}."""
-        out = np.zeros(3)
+        """Starts (True) or stops (False) event timing of the smoother launches and of
+        whole V-cycles; returns the totals since the last start."""
+        out = np.zeros(6)
         self._check(self._lib.edf_profile(self._h, int(bool(enable)), _dptr(out)))
-        return {"launches": int(out[0]), "ms": float(out[1]), "bytes": float(out[2])}
+        return {"launches": int(out[0]), "ms": float(out[1]), "bytes": float(out[2]),
+                "vcycles": int(out[3]), "vcycle_ms": float(out[4]), "vcycle_bytes": float(out[5])}
 
     def destroy(self):
         if getattr(self, "_h", None):

@@ -44,7 +44,7 @@ struct Group {
   KrylovScalars* ks = nullptr;
   double* part = nullptr;
   int *nmask = nullptr, *active = nullptr, *lsmask = nullptr;
-  double *norms = nullptr, *lam = nullptr, *dts = nullptr, *crange = nullptr;
+  double *norms = nullptr, *lam = nullptr, *dts = nullptr, *crange = nullptr, *eta = nullptr;
   double* u0 = nullptr;  // state at the start of the current step (restart point)
   double* Minv = nullptr;
   int *piv = nullptr, *gj_status = nullptr;
@@ -73,8 +73,12 @@ struct edf_problem {
   // smoother timing (edf_profile): event pairs around every smoother launch
   bool prof_on = false;
   std::vector<hipEvent_t> prof_ev;
-  std::vector<std::pair<int, double>> prof_pending;  // (event pair, algorithmic bytes)
-  double prof_launches = 0, prof_ms = 0, prof_bytes = 0;
+  struct ProfRec {
+    int pair, kind;  // kind 0: one smoother launch, 1: one whole V-cycle
+    double bytes;    // algorithmic bytes
+  };
+  std::vector<ProfRec> prof_pending;
+  double prof_count[2] = {0, 0}, prof_ms[2] = {0, 0}, prof_bytes[2] = {0, 0};
   // statistics buffers (allocated on first use)
   double* mom_f = nullptr;
   double* mom_w = nullptr;
@@ -137,8 +141,9 @@ Geom make_geom(int nx, int ny, int nz, const edf_physics& P) {
     const int mx = (nx - ci + 1) / 2, my = (ny - cj + 1) / 2, mz = (nz - ck + 1) / 2;
     g.mx[col] = mx;
     g.my[col] = my;
+    g.cnt[col] = mx * my * mz;
     g.off[col] = off;
-    off += mx * my * mz;
+    off += ceil_div(g.cnt[col], kTile) * kTile;
   }
   g.off[8] = off;
   const double tol = 1e-9 * std::max(P.lx, P.ly);
@@ -201,21 +206,21 @@ edf_status alloc_group(edf_problem* pb, Group& G) {
     Level& L = G.lv[l];
     L.g = make_geom(nx, ny, nz, P);
     L.cells = (size_t)(nx - 1) * (ny - 1) * (nz - 1);
-    const size_t N = L.g.N;
+    const size_t N = L.g.N, Np = L.g.off[8];
     edf_status s;
     if ((s = dalloc(pb, &L.phi, S * L.cells))) return s;
     if ((s = dalloc(pb, &L.K, S * L.cells))) return s;
     if (l > 0 && (s = dalloc(pb, &L.u, S * 2 * N))) return s;
     const bool coarsest = l == G.L - 1;
     if (l == 0 || !mx || coarsest)
-      if ((s = dalloc(pb, &L.A64, S * kPlanes * N))) return s;
+      if ((s = dalloc(pb, &L.A64, S * kPlanes * Np))) return s;
     if (mx && !coarsest)
-      if ((s = dalloc(pb, &L.A32, S * kPlanes * N))) return s;
+      if ((s = dalloc(pb, &L.A32, S * kPlanes * Np))) return s;
     if (l == 0 && (!mx || coarsest))
-      if ((s = dalloc(pb, &L.AV64, S * kPlanes * N))) return s;
+      if ((s = dalloc(pb, &L.AV64, S * kPlanes * Np))) return s;
     if (!coarsest) {
       char* q;
-      if ((s = dalloc(pb, &q, S * 4 * N * tsz))) return s;
+      if ((s = dalloc(pb, &q, S * 4 * Np * tsz))) return s;
       L.Dinv = q;
       if ((s = dalloc(pb, &q, S * 2 * N * tsz))) return s;
       L.r = q;
@@ -242,7 +247,7 @@ edf_status alloc_group(edf_problem* pb, Group& G) {
     if ((s = dalloc(pb, v, S * n))) return s;
   G.lv[0].u = G.u;
   if ((s = dalloc(pb, &G.ks, (size_t)S))) return s;
-  const size_t nb = std::max<size_t>(reduce_blocks(n), ceil_div((int)G.N, kBlock));
+  const size_t nb = std::max<size_t>(reduce_blocks(n), ceil_div(G.lv[0].g.off[8], kBlock));
   if ((s = dalloc(pb, &G.part, S * nb * 4))) return s;
   if ((s = dalloc(pb, &G.nmask, (size_t)S))) return s;
   if ((s = dalloc(pb, &G.active, (size_t)S))) return s;
@@ -250,6 +255,7 @@ edf_status alloc_group(edf_problem* pb, Group& G) {
   if ((s = dalloc(pb, &G.norms, (size_t)S))) return s;
   if ((s = dalloc(pb, &G.lam, (size_t)S))) return s;
   if ((s = dalloc(pb, &G.dts, (size_t)S))) return s;
+  if ((s = dalloc(pb, &G.eta, (size_t)S))) return s;
   if ((s = dalloc(pb, &G.crange, 2 * (size_t)S))) return s;
   if ((s = dalloc(pb, &G.u0, S * n))) return s;
   G.n_coarse = 2 * G.lv[G.L - 1].g.N;
@@ -326,7 +332,7 @@ edf_status assemble_all(edf_problem* pb, Group& G, const int* mask, const double
 // ---------------------------------------------------------------------------
 // smoother timing
 // ---------------------------------------------------------------------------
-bool prof_pair(edf_problem* pb, hipEvent_t& a, hipEvent_t& b, double bytes) {
+bool prof_pair(edf_problem* pb, hipEvent_t& a, hipEvent_t& b, double bytes, int kind) {
   if (!pb->prof_on) return false;
   const size_t k = pb->prof_pending.size();
   while (pb->prof_ev.size() < 2 * (k + 1)) {
@@ -336,21 +342,33 @@ bool prof_pair(edf_problem* pb, hipEvent_t& a, hipEvent_t& b, double bytes) {
   }
   a = pb->prof_ev[2 * k];
   b = pb->prof_ev[2 * k + 1];
-  pb->prof_pending.push_back({(int)k, bytes});
+  pb->prof_pending.push_back({(int)k, kind, bytes});
   return true;
 }
 
 edf_status prof_flush(edf_problem* pb) {
   for (auto& r : pb->prof_pending) {
     float ms = 0.f;
-    EDF_TRY(hipEventSynchronize(pb->prof_ev[2 * r.first + 1]));
-    EDF_TRY(hipEventElapsedTime(&ms, pb->prof_ev[2 * r.first], pb->prof_ev[2 * r.first + 1]));
-    pb->prof_launches += 1;
-    pb->prof_ms += ms;
-    pb->prof_bytes += r.second;
+    EDF_TRY(hipEventSynchronize(pb->prof_ev[2 * r.pair + 1]));
+    EDF_TRY(hipEventElapsedTime(&ms, pb->prof_ev[2 * r.pair], pb->prof_ev[2 * r.pair + 1]));
+    pb->prof_count[r.kind] += 1;
+    pb->prof_ms[r.kind] += ms;
+    pb->prof_bytes[r.kind] += r.bytes;
   }
   pb->prof_pending.clear();
   return EDF_OK;
+}
+
+// algorithmic bytes of one V-cycle per sample: on every smoothed level, 3 stencil
+// sweeps (pre-smoothing, residual, post-smoothing), 2 block-inverse reads and 12
+// vector passes (b and x in and out per sweep, residual out and in, correction), plus
+// the coarse right-hand side and solution and the dense coarse inverse
+double vcycle_bytes(const Group& G, size_t tsz) {
+  double b = 0;
+  for (int l = 0; l + 1 < G.L; ++l)
+    b += (double)G.lv[l].g.N * (3.0 * kPlanes + 2.0 * 4 + 12.0 * 2) * tsz;
+  const double nc = G.n_coarse;
+  return b + nc * nc * 8.0 + 2.0 * nc * tsz;
 }
 
 // ---------------------------------------------------------------------------
@@ -381,52 +399,68 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
   // per vertex of the colour: 108 stencil + 4 block-inverse entries, b, x read and written
   auto smooth = [&](const Level& L, int c, const T* b, T* x) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    const double bytes = (double)(L.g.off[c + 1] - L.g.off[c]) * G.n_active * 118.0 * sizeof(T);
-    prof_pair(pb, e0, e1, bytes);
+    const double bytes = (double)L.g.cnt[c] * G.n_active * 118.0 * sizeof(T);
+    prof_pair(pb, e0, e1, bytes, 0);
     launch_smooth<T>(L.g, c, stencil<T>(L), (const T*)L.Dinv, b, x, S, mask, st, e0, e1);
   };
   auto bx = [&](int l, T*& b, T*& x) {
     b = l == 0 ? b0 : (T*)G.lv[l].b;
     x = l == 0 ? x0 : (T*)G.lv[l].x;
   };
-  if (G.L == 1) {
-    launch_coarse_apply<T>(G.n_coarse, G.Minv, b0, x0, S, mask, st);
-  } else {
-    launch_fill<T>(x0, G.n, S, mask, T(0), st);
-    for (int l = 0; l < G.L - 1; ++l) {
-      Level& L = G.lv[l];
-      T *b, *x;
-      bx(l, b, x);
-      for (int it = 0; it < nu1; ++it)
-        for (int c = 0; c < 8; ++c) smooth(L, c, b, x);
-      launch_residual<T>(L.g, stencil<T>(L), b, x, (T*)L.r, S, mask, st);
-      T *bc, *xc;
-      bx(l + 1, bc, xc);
-      launch_restrict<T>(L.g, G.lv[l + 1].g, (const T*)L.r, bc, xc, S, mask, st);
+  // levels from l0 on are small: they run in one fused launch (one workgroup per sample)
+  int l0 = G.L - 1;
+  while (l0 > 0 && G.lv[l0 - 1].g.N <= kFuseMaxN && G.L - l0 < kMaxFused) --l0;
+  if (l0 > 0) launch_fill<T>(x0, G.n, S, mask, T(0), st);
+  for (int l = 0; l < l0; ++l) {
+    Level& L = G.lv[l];
+    T *b, *x;
+    bx(l, b, x);
+    for (int it = 0; it < nu1; ++it)
+      for (int c = 0; c < 8; ++c) smooth(L, c, b, x);
+    launch_residual<T>(L.g, stencil<T>(L), b, x, (T*)L.r, S, mask, st);
+    T *bc, *xc;
+    bx(l + 1, bc, xc);
+    launch_restrict<T>(L.g, G.lv[l + 1].g, (const T*)L.r, bc, xc, S, mask, st);
+  }
+  {
+    FusedLevels<T> F{};
+    F.n = G.L - l0;
+    F.nc = G.n_coarse;
+    F.nu1 = nu1;
+    F.nu2 = nu2;
+    F.Minv = G.Minv;
+    for (int k = 0; k < F.n; ++k) {
+      const Level& L = G.lv[l0 + k];
+      F.g[k] = L.g;
+      const bool coarsest = l0 + k == G.L - 1;
+      F.A[k] = coarsest ? nullptr : stencil<T>(L);
+      F.D[k] = coarsest ? nullptr : (const T*)L.Dinv;
+      F.r[k] = coarsest ? nullptr : (T*)L.r;
+      bx(l0 + k, F.b[k], F.x[k]);
     }
-    {
-      T *b, *x;
-      bx(G.L - 1, b, x);
-      launch_coarse_apply<T>(G.n_coarse, G.Minv, b, x, S, mask, st);
-    }
-    for (int l = G.L - 2; l >= 0; --l) {
-      Level& L = G.lv[l];
-      T *b, *x, *bc, *xc;
-      bx(l, b, x);
-      bx(l + 1, bc, xc);
-      launch_prolong<T>(L.g, G.lv[l + 1].g, xc, x, S, mask, st);
-      for (int it = 0; it < nu2; ++it)
-        for (int c = 7; c >= 0; --c) smooth(L, c, b, x);
-    }
+    launch_vcycle_bottom<T>(F, S, mask, st);
+  }
+  for (int l = l0 - 1; l >= 0; --l) {
+    Level& L = G.lv[l];
+    T *b, *x, *bc, *xc;
+    bx(l, b, x);
+    bx(l + 1, bc, xc);
+    launch_prolong<T>(L.g, G.lv[l + 1].g, xc, x, S, mask, st);
+    for (int it = 0; it < nu2; ++it)
+      for (int c = 7; c >= 0; --c) smooth(L, c, b, x);
   }
   if constexpr (sizeof(T) != sizeof(double)) launch_cast_f32_to_f64((const float*)x0, out, G.n, S, mask, st);
 }
 
 void precondition(edf_problem* pb, Group& G, const double* in, double* out, const int* mask) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const size_t tsz = mixed(pb) ? sizeof(float) : sizeof(double);
+  if (prof_pair(pb, e0, e1, vcycle_bytes(G, tsz) * G.n_active, 1)) (void)hipEventRecord(e0, pb->st);
   if (mixed(pb))
     vcycle<float>(pb, G, in, out, mask);
   else
     vcycle<double>(pb, G, in, out, mask);
+  if (e1) (void)hipEventRecord(e1, pb->st);
 }
 
 // ---------------------------------------------------------------------------
@@ -438,8 +472,8 @@ edf_status bicgstab(edf_problem* pb, Group& G) {
   const size_t n = G.n;
   const Geom& g0 = G.lv[0].g;
   const double* A = G.lv[0].A64;
-  launch_bicg_init(n, G.F, G.kx, G.kr, G.krh, G.kp, G.kv, G.part, G.ks, pb->opts.lin_rtol,
-                   G.active, S, G.nmask, st);
+  launch_bicg_init(n, G.F, G.kx, G.kr, G.krh, G.kp, G.kv, G.part, G.ks, G.eta, G.active, S,
+                   G.nmask, st);
   auto count_active = [&]() -> edf_status {
     EDF_CHECK_LAUNCH();
     EDF_TRY(hipMemcpyAsync(pb->h_int, G.active, S * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -523,7 +557,7 @@ edf_status newton_solve(edf_problem* pb, Group& G, const std::vector<int>& run,
   if ((e = read_norms(pb, G, G.F, G.nmask, r))) return e;
   r0 = r;
   std::vector<int> nm(run), ls(S), acc(S);
-  std::vector<double> lam(S);
+  std::vector<double> lam(S), eta(S, o.lin_rtol), r_prev(S, 0.0);
   ok.assign(S, 0);
   why.assign(S, EDF_SAMPLE_OK);
   for (int s = 0; s < S; ++s) {
@@ -550,6 +584,25 @@ edf_status newton_solve(edf_problem* pb, Group& G, const std::vector<int>& run,
       }
     }
     if (!any) break;
+    // relative tolerance of this Newton system: fixed, or the Eisenstat-Walker forcing
+    // term (choice 2: 0.9 (r_k / r_{k-1})^2, safeguarded, at most 0.1), never asking for
+    // more than half of what is left to the Newton target
+    for (int s = 0; s < S; ++s) {
+      if (!nm[s] || o.forcing == 0) continue;
+      double et = 0.1;
+      if (it > 0) {
+        const double q = r[s] / r_prev[s];
+        et = 0.9 * q * q;
+        const double prev = 0.9 * eta[s] * eta[s];
+        if (prev > 0.1) et = std::max(et, prev);
+      }
+      et = std::min(et, 0.1);
+      const double target = std::max(o.newton_rtol * r0[s], o.newton_atol);
+      et = std::max(et, 0.5 * target / r[s]);
+      eta[s] = std::max(std::min(et, 0.1), o.lin_rtol);
+    }
+    for (int s = 0; s < S; ++s) r_prev[s] = r[s];
+    if ((e = upload_dbls(pb, G.eta, eta))) return e;
     if ((e = upload_ints(pb, G.nmask, nm))) return e;
     if ((e = assemble_all(pb, G, G.nmask, G.dts))) return e;
     if ((e = bicgstab(pb, G))) return e;
@@ -755,8 +808,9 @@ edf_status edf_create_problem(const edf_physics* phys, const edf_group_desc* gro
   if (opts->newton_max_it < 1 || opts->lin_max_it < 1 || opts->nu_pre < 1 || opts->nu_post < 0 ||
       opts->ls_max_halvings < 0 || !(opts->lin_rtol > 0) || !(opts->newton_rtol >= 0))
     return bad("invalid solver options");
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 3; ++i)
     if (opts->reserved[i] != 0) return bad("reserved options must be zero");
+  if (opts->forcing != 0 && opts->forcing != 1) return bad("forcing must be 0 or 1");
   if (opts->dt_max_halvings < 0 || opts->dt_max_halvings > 12)
     return bad("dt_max_halvings must be in [0, 12]");
   int s0 = 0;
@@ -982,7 +1036,7 @@ edf_status edf_get_jacobian(edf_problem* pb, int32_t sample, const double* u, do
   const Level& L = G->lv[level];
   const size_t N = L.g.N;
   double *A = nullptr, *nat = nullptr;
-  EDF_TRY(hipMalloc(&A, kPlanes * N * sizeof(double)));
+  EDF_TRY(hipMalloc(&A, kPlanes * (size_t)L.g.off[8] * sizeof(double)));
   EDF_TRY(hipMalloc(&nat, kPlanes * N * sizeof(double)));
   const Phys ph = make_phys(pb->phys, L.g, dt);
   launch_assemble(L.g, ph, nullptr, L.phi + s * L.cells, L.K + s * L.cells, cur, A, nullptr, 1,
@@ -1034,14 +1088,14 @@ edf_status edf_profile(edf_problem* pb, int32_t enable, double* out) {
   if (!pb) return EDF_ERR_ARG;
   edf_status e;
   if ((e = prof_flush(pb))) return e;
-  if (out) {
-    out[0] = pb->prof_launches;
-    out[1] = pb->prof_ms;
-    out[2] = pb->prof_bytes;
-  }
-  if (enable) {
-    pb->prof_launches = pb->prof_ms = pb->prof_bytes = 0;
-  }
+  if (out)
+    for (int k = 0; k < 2; ++k) {
+      out[3 * k + 0] = pb->prof_count[k];
+      out[3 * k + 1] = pb->prof_ms[k];
+      out[3 * k + 2] = pb->prof_bytes[k];
+    }
+  if (enable)
+    for (int k = 0; k < 2; ++k) pb->prof_count[k] = pb->prof_ms[k] = pb->prof_bytes[k] = 0;
   pb->prof_on = enable != 0;
   return EDF_OK;
 }

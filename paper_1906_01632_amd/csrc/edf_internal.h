@@ -13,13 +13,18 @@ constexpr int kPlanes = 108;       // 27 neighbours x 2 equations x 2 unknowns
 constexpr int kDiag = 13;          // neighbour index of the vertex itself
 constexpr int kMaxCoarse = 2048;   // largest coarsest-grid system (unknowns)
 
-// Geometry of one grid level.  Stencil arrays of a level are stored in
-// colour-major vertex order: the 8 colours (i%2, j%2, k%2) one after the
-// other, each colour's vertices in (i/2, j/2, k/2) lexicographic order.
+// Geometry of one grid level.  Stencil arrays of a level are indexed by a
+// colour-major vertex position t: the 8 colours (i%2, j%2, k%2) one after the
+// other, each colour's vertices in (i/2, j/2, k/2) lexicographic order, and each
+// colour starting at a multiple of kTile.  Positions are grouped in tiles of kTile
+// (one wavefront); a stencil array with P values per vertex is stored as
+// [tile][P][kTile], so one wavefront streams one contiguous block.
 // Vectors are in natural order v = i + nx (j + ny k).
+constexpr int kTile = 64;
 struct Geom {
   int nx, ny, nz, N;
-  int off[9];        // colour offsets into the colour-major order, off[8] = N
+  int off[9];        // colour offsets (multiples of kTile); off[8] = Np, the padded size
+  int cnt[8];        // vertices per colour
   int mx[8], my[8];  // colour sub-grid extents in x and y
   int pi0, pi1, pj0, pj1;  // vertex index range of the salt patch on k = 0 (empty if pi0 > pi1)
   double hx, hy, hz;
@@ -101,6 +106,25 @@ template <typename T>
 void launch_coarse_apply(int n, const double* Minv, const T* b, T* x, int S, const int* mask,
                          hipStream_t st);
 
+// The bottom of a V-cycle run by one workgroup per sample: levels 0..n-2 of this
+// struct are smoothed, level n-1 is solved with the dense inverse.  Array pointers
+// are the all-sample bases of the respective level.
+constexpr int kMaxFused = 6;
+constexpr int kFuseMaxN = 4096;  // levels with at most this many vertices are fused
+template <typename T>
+struct FusedLevels {
+  int n, nc, nu1, nu2;
+  Geom g[kMaxFused];
+  const T* A[kMaxFused];
+  const T* D[kMaxFused];
+  T* x[kMaxFused];
+  T* b[kMaxFused];
+  T* r[kMaxFused];
+  const double* Minv;
+};
+template <typename T>
+void launch_vcycle_bottom(const FusedLevels<T>& F, int S, const int* mask, hipStream_t st);
+
 // ---------------------------------------------------------------------------
 // Krylov / Newton kernels (krylov_kernels.hip), FP64 vectors of n = 2N per sample
 // ---------------------------------------------------------------------------
@@ -109,8 +133,8 @@ void launch_spmv(const Geom& g, const double* A, const double* x, double* y, int
                  const int* mask, hipStream_t st);
 // BiCGStab phases; `part` is scratch [S][nb][4], `ks` the per-sample scalars.
 void launch_bicg_init(size_t n, const double* b, double* x, double* r, double* rh, double* p,
-                      double* v, double* part, KrylovScalars* ks, double rtol, int* active, int S,
-                      const int* mask, hipStream_t st);
+                      double* v, double* part, KrylovScalars* ks, const double* rtol, int* active,
+                      int S, const int* mask, hipStream_t st);
 void launch_bicg_p(size_t n, const double* r, const double* v, double* p, const KrylovScalars* ks,
                    int S, const int* mask, hipStream_t st);
 void launch_bicg_alpha(const Geom& g, const double* A, const double* ph, double* v, const double* rh,

@@ -12,12 +12,18 @@ __host__ __device__ constexpr int nb_index(int dx, int dy, int dz) {
 
 __device__ __forceinline__ int clampi(int a, int lo, int hi) { return a < lo ? lo : (a > hi ? hi : a); }
 
-// colour-major position t -> vertex (i, j, k)
-__device__ __forceinline__ void colour_decode(const Geom& g, int t, int& i, int& j, int& k) {
+// index of value p (of P per vertex) at colour-major position t in a tiled array
+__host__ __device__ __forceinline__ size_t tiled(int t, int p, int P) {
+  return ((size_t)(t / kTile) * P + p) * kTile + (t % kTile);
+}
+
+// colour-major position t -> vertex (i, j, k); false for padding positions
+__device__ __forceinline__ bool colour_decode(const Geom& g, int t, int& i, int& j, int& k) {
   int col = 0;
 #pragma unroll
   for (int c = 1; c < 8; ++c) col += (t >= g.off[c]) ? 1 : 0;
   const int s = t - g.off[col];
+  if (s >= g.cnt[col]) return false;
   const int mx = g.mx[col], my = g.my[col];
   const int a = s % mx;
   const int r = s / mx;
@@ -26,6 +32,7 @@ __device__ __forceinline__ void colour_decode(const Geom& g, int t, int& i, int&
   i = 2 * a + (col & 1);
   j = 2 * b + ((col >> 1) & 1);
   k = 2 * c + (col >> 2);
+  return true;
 }
 
 // position inside colour `col` -> vertex (i, j, k)

@@ -309,7 +309,7 @@ __device__ __forceinline__ void hex_jacobian(const Geom& g, int i, int j, int k,
 template <int EQ, bool FROZEN>
 __device__ __forceinline__ void assemble_row(const Geom& g, const Phys& ph, const double* phi,
                                              const double* K, const double* P, const double* C,
-                                             int i, int j, int k, int t, size_t base, double* A64,
+                                             int i, int j, int k, size_t base, double* A64,
                                              float* A32) {
   double Ap[27], Ac[27];
 #pragma unroll
@@ -336,7 +336,6 @@ __device__ __forceinline__ void assemble_row(const Geom& g, const Phys& ph, cons
   double cD;
   const bool dir = EQ == 0 ? is_pin(g, i, j, k) : is_cdir(g, i, j, k, cD);
   const double sp = ph.s_row * ph.p_unit, sc = ph.s_row;
-  const size_t N = g.N;
 #pragma unroll
   for (int o = 0; o < 27; ++o) {
     double ap = sp * Ap[o], ac = sc * Ac[o];
@@ -344,14 +343,14 @@ __device__ __forceinline__ void assemble_row(const Geom& g, const Phys& ph, cons
       ap = (o == kDiag && EQ == 0) ? 1.0 : 0.0;
       ac = (o == kDiag && EQ == 1) ? 1.0 : 0.0;
     }
-    const size_t q = base + (size_t)(o * 4 + EQ * 2) * N + t;
+    const size_t q = base + (size_t)(o * 4 + EQ * 2) * kTile;
     if (A64) {
       A64[q] = ap;
-      A64[q + N] = ac;
+      A64[q + kTile] = ac;
     }
     if (A32) {
       A32[q] = (float)ap;
-      A32[q + N] = (float)ac;
+      A32[q + kTile] = (float)ac;
     }
   }
 }
@@ -371,26 +370,25 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Geom g, Phys ph0, const dou
   if (mask && !mask[s]) return;
   const Phys ph = sample_phys(ph0, dts, s);
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= g.N) return;
   int i, j, k;
-  colour_decode(g, t, i, j, k);
+  if (t >= g.off[8] || !colour_decode(g, t, i, j, k)) return;
   const size_t cells = (size_t)(g.nx - 1) * (g.ny - 1) * (g.nz - 1);
   const double* phi = phi_all + s * cells;
   const double* K = K_all + s * cells;
   const double2* u = reinterpret_cast<const double2*>(u_all) + (size_t)s * g.N;
   double P[27], C[27];
   load_neighbourhood(g, u, i, j, k, P, C);
-  const size_t base = (size_t)s * kPlanes * g.N;
+  const size_t base = (size_t)s * kPlanes * g.off[8] + tiled(t, 0, kPlanes);
   if (blockIdx.z == 0)
-    assemble_row<0, FROZEN>(g, ph, phi, K, P, C, i, j, k, t, base, A64, A32);
+    assemble_row<0, FROZEN>(g, ph, phi, K, P, C, i, j, k, base, A64, A32);
   else
-    assemble_row<1, FROZEN>(g, ph, phi, K, P, C, i, j, k, t, base, A64, A32);
+    assemble_row<1, FROZEN>(g, ph, phi, K, P, C, i, j, k, base, A64, A32);
 }
 
 void launch_assemble(const Geom& g, const Phys& ph, const double* dts, const double* phi,
                      const double* K, const double* u, double* A64, float* A32, int S,
                      const int* mask, hipStream_t st, bool frozen) {
-  dim3 grid(ceil_div(g.N, kBlock), S, 2);
+  dim3 grid(ceil_div(g.off[8], kBlock), S, 2);
   if (frozen)
     hipLaunchKernelGGL(k_assemble<true>, grid, dim3(kBlock), 0, st, g, ph, dts, phi, K, u, A64,
                        A32, mask);
@@ -408,27 +406,28 @@ __global__ __launch_bounds__(kBlock) void k_block_inverse(Geom g, const T* A, T*
   const int s = blockIdx.y;
   if (mask && !mask[s]) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= g.N) return;
-  const size_t N = g.N;
-  const T* a = A + (size_t)s * kPlanes * N + (size_t)(kDiag * 4) * N + t;
-  const double a00 = a[0], a01 = a[N], a10 = a[2 * N], a11 = a[3 * N];
+  int i, j, k;
+  if (t >= g.off[8] || !colour_decode(g, t, i, j, k)) return;
+  const size_t Np = g.off[8];
+  const T* a = A + (size_t)s * kPlanes * Np + tiled(t, kDiag * 4, kPlanes);
+  const double a00 = a[0], a01 = a[kTile], a10 = a[2 * kTile], a11 = a[3 * kTile];
   const double det = a00 * a11 - a01 * a10;
   const double id = det != 0.0 ? 1.0 / det : 0.0;
-  T* d = Dinv + (size_t)s * 4 * N + t;
+  T* d = Dinv + (size_t)s * 4 * Np + tiled(t, 0, 4);
   d[0] = (T)(a11 * id);
-  d[N] = (T)(-a01 * id);
-  d[2 * N] = (T)(-a10 * id);
-  d[3 * N] = (T)(a00 * id);
+  d[kTile] = (T)(-a01 * id);
+  d[2 * kTile] = (T)(-a10 * id);
+  d[3 * kTile] = (T)(a00 * id);
 }
 
 void launch_block_inverse_f64(const Geom& g, const double* A, double* Dinv, int S,
                               const int* mask, hipStream_t st) {
-  dim3 grid(ceil_div(g.N, kBlock), S);
+  dim3 grid(ceil_div(g.off[8], kBlock), S);
   hipLaunchKernelGGL(k_block_inverse<double>, grid, dim3(kBlock), 0, st, g, A, Dinv, mask);
 }
 void launch_block_inverse_f32(const Geom& g, const float* A, float* Dinv, int S,
                               const int* mask, hipStream_t st) {
-  dim3 grid(ceil_div(g.N, kBlock), S);
+  dim3 grid(ceil_div(g.off[8], kBlock), S);
   hipLaunchKernelGGL(k_block_inverse<float>, grid, dim3(kBlock), 0, st, g, A, Dinv, mask);
 }
 
@@ -460,7 +459,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil_to_natural(Geom g, const dou
   if (v >= g.N) return;
   const int i = v % g.nx, j = (v / g.nx) % g.ny, k = v / (g.nx * g.ny);
   const int t = colour_encode(g, i, j, k);
-  for (int p = 0; p < kPlanes; ++p) out[(size_t)p * g.N + v] = A[(size_t)p * g.N + t];
+  for (int p = 0; p < kPlanes; ++p) out[(size_t)p * g.N + v] = A[tiled(t, p, kPlanes)];
 }
 
 void launch_stencil_to_natural(const Geom& g, const double* A, double* out, hipStream_t st) {

@@ -51,12 +51,11 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Geom g, const double* A_all, co
   const int s = blockIdx.y;
   if (mask && !mask[s]) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t N = g.N;
+  const size_t N = g.N, Np = g.off[8];
   double acc[2] = {0.0, 0.0};
-  if (t < g.N) {
-    int i, j, k;
-    colour_decode(g, t, i, j, k);
-    const double* A = A_all + (size_t)s * kPlanes * N + t;
+  int i, j, k;
+  if (t < g.off[8] && colour_decode(g, t, i, j, k)) {
+    const double* A = A_all + (size_t)s * kPlanes * Np + tiled(t, 0, kPlanes);
     const double2* x = reinterpret_cast<const double2*>(x_all) + (size_t)s * N;
     double r0 = 0.0, r1 = 0.0;
 #pragma unroll
@@ -70,8 +69,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Geom g, const double* A_all, co
           const int ii = clampi(i + dx, 0, g.nx - 1);
           const int o = nb_index(dx, dy, dz);
           const double2 xv = x[ii + (size_t)g.nx * (jj + (size_t)g.ny * kk)];
-          r0 += A[(size_t)(o * 4 + 0) * N] * xv.x + A[(size_t)(o * 4 + 1) * N] * xv.y;
-          r1 += A[(size_t)(o * 4 + 2) * N] * xv.x + A[(size_t)(o * 4 + 3) * N] * xv.y;
+          r0 += __builtin_nontemporal_load(A + (o * 4 + 0) * kTile) * xv.x +
+                __builtin_nontemporal_load(A + (o * 4 + 1) * kTile) * xv.y;
+          r1 += __builtin_nontemporal_load(A + (o * 4 + 2) * kTile) * xv.x +
+                __builtin_nontemporal_load(A + (o * 4 + 3) * kTile) * xv.y;
         }
       }
     }
@@ -93,7 +94,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Geom g, const double* A_all, co
 
 void launch_spmv(const Geom& g, const double* A, const double* x, double* y, int S,
                  const int* mask, hipStream_t st) {
-  dim3 grid(ceil_div(g.N, kBlock), S);
+  dim3 grid(ceil_div(g.off[8], kBlock), S);
   hipLaunchKernelGGL(k_spmv<kDotNone>, grid, dim3(kBlock), 0, st, g, A, x, y, (const double*)nullptr,
                      (double*)nullptr, mask);
 }
@@ -105,7 +106,7 @@ enum Phase { kInit = 0, kAlpha = 1, kS = 2, kOmega = 3, kUpdate = 4 };
 
 __global__ __launch_bounds__(64) void k_bicg_finalize(int phase, int nb, const double* part,
                                                       KrylovScalars* ks_all, int* active,
-                                                      double rtol, const int* gate) {
+                                                      const double* rtol, const int* gate) {
   const int s = blockIdx.x;
   if (phase == kInit) {
     if (gate && !gate[s]) {
@@ -137,7 +138,7 @@ __global__ __launch_bounds__(64) void k_bicg_finalize(int phase, int nb, const d
       k.alpha = 1.0;
       k.omega = 1.0;
       k.beta = 0.0;
-      k.tol2 = rtol * rtol * a0;
+      k.tol2 = rtol[s] * rtol[s] * a0;
       k.ss = 0.0;
       k.it = 0;
       k.state = (a0 > 0.0 && a0 == a0) ? 0 : (a0 == 0.0 ? 1 : 2);
@@ -177,7 +178,7 @@ __global__ __launch_bounds__(64) void k_bicg_finalize(int phase, int nb, const d
 }
 
 static void finalize(int phase, int nb, const double* part, KrylovScalars* ks, int* active,
-                     double rtol, int S, hipStream_t st, const int* gate = nullptr) {
+                     const double* rtol, int S, hipStream_t st, const int* gate = nullptr) {
   hipLaunchKernelGGL(k_bicg_finalize, dim3(S), dim3(64), 0, st, phase, nb, part, ks, active, rtol,
                      gate);
 }
@@ -206,8 +207,8 @@ __global__ __launch_bounds__(kBlock) void k_bicg_init(size_t n, const double* b,
 }
 
 void launch_bicg_init(size_t n, const double* b, double* x, double* r, double* rh, double* p,
-                      double* v, double* part, KrylovScalars* ks, double rtol, int* active, int S,
-                      const int* mask, hipStream_t st) {
+                      double* v, double* part, KrylovScalars* ks, const double* rtol, int* active,
+                      int S, const int* mask, hipStream_t st) {
   const int nb = reduce_blocks(n);
   hipLaunchKernelGGL(k_bicg_init, dim3(nb, S), dim3(kBlock), 0, st, n, b, x, r, rh, p, v, part,
                      mask);
@@ -236,10 +237,10 @@ void launch_bicg_p(size_t n, const double* r, const double* v, double* p, const 
 void launch_bicg_alpha(const Geom& g, const double* A, const double* ph, double* v,
                        const double* rh, double* part, KrylovScalars* ks, int S, const int* mask,
                        hipStream_t st) {
-  const int nb = ceil_div(g.N, kBlock);
+  const int nb = ceil_div(g.off[8], kBlock);
   hipLaunchKernelGGL(k_spmv<kDotOne>, dim3(nb, S), dim3(kBlock), 0, st, g, A, ph, v, rh, part,
                      mask);
-  finalize(kAlpha, nb, part, ks, const_cast<int*>(mask), 0.0, S, st);  // mask is `active`
+  finalize(kAlpha, nb, part, ks, const_cast<int*>(mask), nullptr, S, st);  // mask is `active`
 }
 
 __global__ __launch_bounds__(kBlock) void k_bicg_s(size_t n, const double* r, const double* v,
@@ -263,15 +264,15 @@ void launch_bicg_s(size_t n, const double* r, const double* v, double* s, double
                    KrylovScalars* ks, int S, const int* mask, hipStream_t st) {
   const int nb = reduce_blocks(n);
   hipLaunchKernelGGL(k_bicg_s, dim3(nb, S), dim3(kBlock), 0, st, n, r, v, s, part, ks, mask);
-  finalize(kS, nb, part, ks, const_cast<int*>(mask), 0.0, S, st);
+  finalize(kS, nb, part, ks, const_cast<int*>(mask), nullptr, S, st);
 }
 
 void launch_bicg_omega(const Geom& g, const double* A, const double* sh, const double* s,
                        double* t, double* part, KrylovScalars* ks, int S, const int* mask,
                        hipStream_t st) {
-  const int nb = ceil_div(g.N, kBlock);
+  const int nb = ceil_div(g.off[8], kBlock);
   hipLaunchKernelGGL(k_spmv<kDotTS>, dim3(nb, S), dim3(kBlock), 0, st, g, A, sh, t, s, part, mask);
-  finalize(kOmega, nb, part, ks, const_cast<int*>(mask), 0.0, S, st);
+  finalize(kOmega, nb, part, ks, const_cast<int*>(mask), nullptr, S, st);
 }
 
 __global__ __launch_bounds__(kBlock) void k_bicg_update(size_t n, const double* ph,
@@ -301,7 +302,7 @@ void launch_bicg_update(size_t n, const double* ph, const double* sh, const doub
   const int nb = reduce_blocks(n);
   hipLaunchKernelGGL(k_bicg_update, dim3(nb, S), dim3(kBlock), 0, st, n, ph, sh, s, t, rh, x, r,
                      part, ks, mask);
-  finalize(kUpdate, nb, part, ks, active, 0.0, S, st);
+  finalize(kUpdate, nb, part, ks, active, nullptr, S, st);
 }
 
 // ---------------------------------------------------------------------------

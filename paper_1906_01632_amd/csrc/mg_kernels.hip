@@ -26,24 +26,34 @@ struct V2<float> {
   using type = float2;
 };
 
-// ---------------------------------------------------------------------------
-// block Gauss-Seidel over one colour: x_v += D_v^{-1} (b - A x)_v
-// ---------------------------------------------------------------------------
+// Stencil entries are read once per sweep and never reused from cache: load them
+// as streaming (non-temporal) data so that the vectors stay cached.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_smooth(Geom g, int col, const T* A_all, const T* Dinv_all,
-                                                   const T* b_all, T* x_all, const int* mask) {
+__device__ __forceinline__ T stream_load(const T* p) {
+#ifdef EDF_CACHED_STENCIL
+  return *p;
+#else
+  return __builtin_nontemporal_load(p);
+#endif
+}
+
+// ---------------------------------------------------------------------------
+// Per-vertex operations.  Pointers are those of one sample.  They serve both the
+// one-launch-per-sweep kernels (large grids) and the fused kernel that runs the
+// bottom of the V-cycle in one workgroup per sample (small grids).
+// ---------------------------------------------------------------------------
+
+// block Gauss-Seidel update of vertex q of colour col: x_v += D_v^{-1} (b - A x)_v
+template <typename T>
+__device__ __forceinline__ void smooth_vertex(const Geom& g, int col, int q, const T* A_s,
+                                              const T* D_s, const T* b_s, T* x_s) {
   using T2 = typename V2<T>::type;
-  const int s = blockIdx.y;
-  if (mask && !mask[s]) return;
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= g.off[col + 1] - g.off[col]) return;
   int i, j, k;
   colour_decode_in(g, col, q, i, j, k);
-  const size_t N = g.N;
   const int t = g.off[col] + q;
-  const T* A = A_all + (size_t)s * kPlanes * N + t;
-  const T2* b = reinterpret_cast<const T2*>(b_all) + (size_t)s * N;
-  T2* x = reinterpret_cast<T2*>(x_all) + (size_t)s * N;
+  const T* A = A_s + tiled(t, 0, kPlanes);
+  const T2* b = reinterpret_cast<const T2*>(b_s);
+  T2* x = reinterpret_cast<T2*>(x_s);
   const size_t v = i + (size_t)g.nx * (j + (size_t)g.ny * k);
   T2 bv = b[v];
   T r0 = bv.x, r1 = bv.y;
@@ -58,52 +68,32 @@ __global__ __launch_bounds__(kBlock) void k_smooth(Geom g, int col, const T* A_a
         const int ii = clampi(i + dx, 0, g.nx - 1);
         const int o = nb_index(dx, dy, dz);
         const T2 xv = x[ii + (size_t)g.nx * (jj + (size_t)g.ny * kk)];
-        r0 -= A[(size_t)(o * 4 + 0) * N] * xv.x + A[(size_t)(o * 4 + 1) * N] * xv.y;
-        r1 -= A[(size_t)(o * 4 + 2) * N] * xv.x + A[(size_t)(o * 4 + 3) * N] * xv.y;
+        r0 -= stream_load(A + (o * 4 + 0) * kTile) * xv.x +
+              stream_load(A + (o * 4 + 1) * kTile) * xv.y;
+        r1 -= stream_load(A + (o * 4 + 2) * kTile) * xv.x +
+              stream_load(A + (o * 4 + 3) * kTile) * xv.y;
       }
     }
   }
-  const T* d = Dinv_all + (size_t)s * 4 * N + t;
+  const T* d = D_s + tiled(t, 0, 4);
   T2 xv = x[v];
-  xv.x += d[0] * r0 + d[N] * r1;
-  xv.y += d[2 * N] * r0 + d[3 * N] * r1;
+  xv.x += stream_load(d) * r0 + stream_load(d + kTile) * r1;
+  xv.y += stream_load(d + 2 * kTile) * r0 + stream_load(d + 3 * kTile) * r1;
   x[v] = xv;
 }
 
+// residual r = b - A x at colour-major position t, zero in Dirichlet rows (their
+// equations are solved exactly by the smoother and carry no coarse-grid correction)
 template <typename T>
-void launch_smooth(const Geom& g, int colour, const T* A, const T* Dinv, const T* b, T* x, int S,
-                   const int* mask, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-  const int n = g.off[colour + 1] - g.off[colour];
-  if (n <= 0) return;
-  dim3 grid(ceil_div(n, kBlock), S);
-  if (ev0)  // timed launch: events recorded around this kernel only
-    hipExtLaunchKernelGGL(k_smooth<T>, grid, dim3(kBlock), 0, st, ev0, ev1, 0, g, colour, A, Dinv,
-                          b, x, mask);
-  else
-    hipLaunchKernelGGL(k_smooth<T>, grid, dim3(kBlock), 0, st, g, colour, A, Dinv, b, x, mask);
-}
-
-// ---------------------------------------------------------------------------
-// residual r = b - A x, zero in Dirichlet rows (their equations are solved
-// exactly by the smoother and carry no coarse-grid correction)
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_residual(Geom g, const T* A_all, const T* b_all,
-                                                     const T* x_all, T* r_all, const int* mask) {
+__device__ __forceinline__ void residual_vertex(const Geom& g, int t, const T* A_s,
+                                                const T* b_s, const T* x_s, T* r_s) {
   using T2 = typename V2<T>::type;
-  const int s = blockIdx.y;
-  if (mask && !mask[s]) return;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= g.N) return;
   int i, j, k;
-  colour_decode(g, t, i, j, k);
-  const size_t N = g.N;
-  const T* A = A_all + (size_t)s * kPlanes * N + t;
-  const T2* x = reinterpret_cast<const T2*>(x_all) + (size_t)s * N;
-  const size_t v = i + (size_t)g.nx * (j + (size_t)g.ny * k);
-  const T2 bv = reinterpret_cast<const T2*>(b_all)[(size_t)s * N + v];
-  T r0 = bv.x, r1 = bv.y;
-#pragma unroll
+  if (!colour_decode(g, t, i, j, k)) return;
+  const T* A = A_s + tiled(t, 0, kPlanes);
+  const T2* x = reinterpret_cast<const T2*>(x_s);
+  T a0 = 0, a1 = 0;  // (A x)_v; b is read after the sweep over the neighbours
+#pragma unroll 1  // one z-plane of neighbours at a time keeps the register count low
   for (int dz = -1; dz <= 1; ++dz) {
     const int kk = clampi(k + dz, 0, g.nz - 1);
 #pragma unroll
@@ -114,41 +104,31 @@ __global__ __launch_bounds__(kBlock) void k_residual(Geom g, const T* A_all, con
         const int ii = clampi(i + dx, 0, g.nx - 1);
         const int o = nb_index(dx, dy, dz);
         const T2 xv = x[ii + (size_t)g.nx * (jj + (size_t)g.ny * kk)];
-        r0 -= A[(size_t)(o * 4 + 0) * N] * xv.x + A[(size_t)(o * 4 + 1) * N] * xv.y;
-        r1 -= A[(size_t)(o * 4 + 2) * N] * xv.x + A[(size_t)(o * 4 + 3) * N] * xv.y;
+        a0 += stream_load(A + (o * 4 + 0) * kTile) * xv.x +
+              stream_load(A + (o * 4 + 1) * kTile) * xv.y;
+        a1 += stream_load(A + (o * 4 + 2) * kTile) * xv.x +
+              stream_load(A + (o * 4 + 3) * kTile) * xv.y;
       }
     }
   }
+  const size_t v = i + (size_t)g.nx * (j + (size_t)g.ny * k);
+  const T2 bv = reinterpret_cast<const T2*>(b_s)[v];
   double cD;
-  if (is_pin(g, i, j, k)) r0 = 0;
-  if (is_cdir(g, i, j, k, cD)) r1 = 0;
   T2 out;
-  out.x = r0;
-  out.y = r1;
-  reinterpret_cast<T2*>(r_all)[(size_t)s * N + v] = out;
+  out.x = is_pin(g, i, j, k) ? T(0) : bv.x - a0;
+  out.y = is_cdir(g, i, j, k, cD) ? T(0) : bv.y - a1;
+  reinterpret_cast<T2*>(r_s)[v] = out;
 }
 
+// restriction b_c = (1/8) P^T r_f of the scaled residual at coarse vertex v (the 1/8
+// converts the fine row scaling to the coarse one: rows are scaled by 1/(hx hy hz));
+// also clears x_c
 template <typename T>
-void launch_residual(const Geom& g, const T* A, const T* b, const T* x, T* r, int S,
-                     const int* mask, hipStream_t st) {
-  dim3 grid(ceil_div(g.N, kBlock), S);
-  hipLaunchKernelGGL(k_residual<T>, grid, dim3(kBlock), 0, st, g, A, b, x, r, mask);
-}
-
-// ---------------------------------------------------------------------------
-// restriction b_c = (1/8) P^T r_f of the scaled residual (the 1/8 converts the
-// fine row scaling to the coarse one: rows are scaled by 1/(hx hy hz)); x_c = 0
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, const T* rf_all, T* bc_all,
-                                                     T* xc_all, const int* mask) {
+__device__ __forceinline__ void restrict_vertex(const Geom& gf, const Geom& gc, int v,
+                                                const T* rf_s, T* bc_s, T* xc_s) {
   using T2 = typename V2<T>::type;
-  const int s = blockIdx.y;
-  if (mask && !mask[s]) return;
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= gc.N) return;
   const int I = v % gc.nx, J = (v / gc.nx) % gc.ny, K = v / (gc.nx * gc.ny);
-  const T2* rf = reinterpret_cast<const T2*>(rf_all) + (size_t)s * gf.N;
+  const T2* rf = reinterpret_cast<const T2*>(rf_s);
   T a0 = 0, a1 = 0;
 #pragma unroll
   for (int dz = -1; dz <= 1; ++dz) {
@@ -173,33 +153,21 @@ __global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, const T* 
   T2 out;
   out.x = is_pin(gc, I, J, K) ? T(0) : T(0.125) * a0;
   out.y = is_cdir(gc, I, J, K, cD) ? T(0) : T(0.125) * a1;
-  reinterpret_cast<T2*>(bc_all)[(size_t)s * gc.N + v] = out;
+  reinterpret_cast<T2*>(bc_s)[v] = out;
   T2 z;
   z.x = 0;
   z.y = 0;
-  reinterpret_cast<T2*>(xc_all)[(size_t)s * gc.N + v] = z;
+  reinterpret_cast<T2*>(xc_s)[v] = z;
 }
 
+// prolongation and correction x_f += P x_c (trilinear) at fine vertex v, none in
+// Dirichlet rows
 template <typename T>
-void launch_restrict(const Geom& gf, const Geom& gc, const T* rf, T* bc, T* xc, int S,
-                     const int* mask, hipStream_t st) {
-  dim3 grid(ceil_div(gc.N, kBlock), S);
-  hipLaunchKernelGGL(k_restrict<T>, grid, dim3(kBlock), 0, st, gf, gc, rf, bc, xc, mask);
-}
-
-// ---------------------------------------------------------------------------
-// prolongation and correction x_f += P x_c (trilinear), none in Dirichlet rows
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_prolong(Geom gf, Geom gc, const T* xc_all, T* xf_all,
-                                                    const int* mask) {
+__device__ __forceinline__ void prolong_vertex(const Geom& gf, const Geom& gc, int v,
+                                               const T* xc_s, T* xf_s) {
   using T2 = typename V2<T>::type;
-  const int s = blockIdx.y;
-  if (mask && !mask[s]) return;
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= gf.N) return;
   const int i = v % gf.nx, j = (v / gf.nx) % gf.ny, k = v / (gf.nx * gf.ny);
-  const T2* xc = reinterpret_cast<const T2*>(xc_all) + (size_t)s * gc.N;
+  const T2* xc = reinterpret_cast<const T2*>(xc_s);
   const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1, k0 = k >> 1,
             k1 = (k + 1) >> 1;
   const T wi = (i & 1) ? T(0.5) : T(1), wj = (j & 1) ? T(0.5) : T(1), wk = (k & 1) ? T(0.5) : T(1);
@@ -214,12 +182,87 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Geom gf, Geom gc, const T* x
     a0 += w * e.x;
     a1 += w * e.y;
   }
-  T2* xf = reinterpret_cast<T2*>(xf_all) + (size_t)s * gf.N;
+  T2* xf = reinterpret_cast<T2*>(xf_s);
   T2 x = xf[v];
   double cD;
   if (!is_pin(gf, i, j, k)) x.x += a0;
   if (!is_cdir(gf, i, j, k, cD)) x.y += a1;
   xf[v] = x;
+}
+
+// ---------------------------------------------------------------------------
+// one launch per colour sweep / transfer (large grids)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_smooth(Geom g, int col, const T* A_all, const T* Dinv_all,
+                                                   const T* b_all, T* x_all, const int* mask) {
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= g.cnt[col]) return;
+  const size_t N = g.N, Np = g.off[8];
+  smooth_vertex<T>(g, col, q, A_all + (size_t)s * kPlanes * Np, Dinv_all + (size_t)s * 4 * Np,
+                   b_all + (size_t)s * 2 * N, x_all + (size_t)s * 2 * N);
+}
+
+template <typename T>
+void launch_smooth(const Geom& g, int colour, const T* A, const T* Dinv, const T* b, T* x, int S,
+                   const int* mask, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  const int n = g.cnt[colour];
+  if (n <= 0) return;
+  dim3 grid(ceil_div(n, kBlock), S);
+  if (ev0)  // timed launch: events recorded around this kernel only
+    hipExtLaunchKernelGGL(k_smooth<T>, grid, dim3(kBlock), 0, st, ev0, ev1, 0, g, colour, A, Dinv,
+                          b, x, mask);
+  else
+    hipLaunchKernelGGL(k_smooth<T>, grid, dim3(kBlock), 0, st, g, colour, A, Dinv, b, x, mask);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_residual(Geom g, const T* A_all, const T* b_all,
+                                                     const T* x_all, T* r_all, const int* mask) {
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.off[8]) return;
+  const size_t N = g.N, Np = g.off[8];
+  residual_vertex<T>(g, t, A_all + (size_t)s * kPlanes * Np, b_all + (size_t)s * 2 * N,
+                     x_all + (size_t)s * 2 * N, r_all + (size_t)s * 2 * N);
+}
+
+template <typename T>
+void launch_residual(const Geom& g, const T* A, const T* b, const T* x, T* r, int S,
+                     const int* mask, hipStream_t st) {
+  dim3 grid(ceil_div(g.off[8], kBlock), S);
+  hipLaunchKernelGGL(k_residual<T>, grid, dim3(kBlock), 0, st, g, A, b, x, r, mask);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, const T* rf_all, T* bc_all,
+                                                     T* xc_all, const int* mask) {
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= gc.N) return;
+  restrict_vertex<T>(gf, gc, v, rf_all + (size_t)s * 2 * gf.N, bc_all + (size_t)s * 2 * gc.N,
+                     xc_all + (size_t)s * 2 * gc.N);
+}
+
+template <typename T>
+void launch_restrict(const Geom& gf, const Geom& gc, const T* rf, T* bc, T* xc, int S,
+                     const int* mask, hipStream_t st) {
+  dim3 grid(ceil_div(gc.N, kBlock), S);
+  hipLaunchKernelGGL(k_restrict<T>, grid, dim3(kBlock), 0, st, gf, gc, rf, bc, xc, mask);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong(Geom gf, Geom gc, const T* xc_all, T* xf_all,
+                                                    const int* mask) {
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= gf.N) return;
+  prolong_vertex<T>(gf, gc, v, xc_all + (size_t)s * 2 * gc.N, xf_all + (size_t)s * 2 * gf.N);
 }
 
 template <typename T>
@@ -280,11 +323,10 @@ __global__ __launch_bounds__(kBlock) void k_coarse_dense(Geom g, const double* A
   const int s = blockIdx.y;
   if (mask && !mask[s]) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= g.N) return;
   int i, j, k;
-  colour_decode(g, t, i, j, k);
+  if (t >= g.off[8] || !colour_decode(g, t, i, j, k)) return;
   const size_t N = g.N, n = 2 * N;
-  const double* A = A_all + (size_t)s * kPlanes * N + t;
+  const double* A = A_all + (size_t)s * kPlanes * g.off[8] + tiled(t, 0, kPlanes);
   double* M = M_all + (size_t)s * n * n;
   const size_t v = i + (size_t)g.nx * (j + (size_t)g.ny * k);
   for (int dz = -1; dz <= 1; ++dz)
@@ -296,7 +338,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_dense(Geom g, const double* A
         const int o = nb_index(dx, dy, dz);
         for (int e = 0; e < 2; ++e)
           for (int var = 0; var < 2; ++var)
-            M[(2 * v + e) * n + 2 * w + var] = A[(size_t)(o * 4 + e * 2 + var) * N];
+            M[(2 * v + e) * n + 2 * w + var] = A[(o * 4 + e * 2 + var) * kTile];
       }
 }
 
@@ -304,7 +346,7 @@ void launch_coarse_dense(const Geom& g, const double* A, double* M, int S, const
                          hipStream_t st) {
   const size_t n = 2 * (size_t)g.N;
   launch_fill<double>(M, n * n, S, mask, 0.0, st);
-  dim3 grid(ceil_div(g.N, kBlock), S);
+  dim3 grid(ceil_div(g.off[8], kBlock), S);
   hipLaunchKernelGGL(k_coarse_dense, grid, dim3(kBlock), 0, st, g, A, M, mask);
 }
 
@@ -427,6 +469,71 @@ void launch_coarse_apply(int n, const double* Minv, const T* b, T* x, int S, con
   hipLaunchKernelGGL(k_coarse_apply<T>, grid, dim3(kBlock), 0, st, n, Minv, b, x, mask);
 }
 
+// ---------------------------------------------------------------------------
+// bottom of the V-cycle in one launch: one workgroup per sample runs the smoothed
+// levels l0..n-2 of F and the dense coarse solve on level n-1, with workgroup
+// barriers between the sweeps (all levels are small: at most kFuseMaxN vertices)
+// ---------------------------------------------------------------------------
+constexpr int kFusedThreads = 1024;
+
+template <typename T>
+__global__ __launch_bounds__(kFusedThreads) void k_vcycle_bottom(FusedLevels<T> F, const int* mask) {
+  const int s = blockIdx.x;
+  if (mask && !mask[s]) return;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  auto A = [&](int l) { return F.A[l] + (size_t)s * kPlanes * F.g[l].off[8]; };
+  auto D = [&](int l) { return F.D[l] + (size_t)s * 4 * F.g[l].off[8]; };
+  auto X = [&](int l) { return F.x[l] + (size_t)s * 2 * F.g[l].N; };
+  auto B = [&](int l) { return F.b[l] + (size_t)s * 2 * F.g[l].N; };
+  auto Rv = [&](int l) { return F.r[l] + (size_t)s * 2 * F.g[l].N; };
+  const int last = F.n - 1;
+  // x = 0 on the first fused level (the finer levels' restriction clears the others)
+  for (int e = tid; e < 2 * F.g[0].N; e += nt) X(0)[e] = T(0);
+  __syncthreads();
+  for (int l = 0; l < last; ++l) {
+    const Geom& g = F.g[l];
+    for (int it = 0; it < F.nu1; ++it)
+      for (int c = 0; c < 8; ++c) {
+        for (int q = tid; q < g.cnt[c]; q += nt) smooth_vertex<T>(g, c, q, A(l), D(l), B(l), X(l));
+        __syncthreads();
+      }
+    for (int t = tid; t < g.off[8]; t += nt) residual_vertex<T>(g, t, A(l), B(l), X(l), Rv(l));
+    __syncthreads();
+    for (int v = tid; v < F.g[l + 1].N; v += nt)
+      restrict_vertex<T>(g, F.g[l + 1], v, Rv(l), B(l + 1), X(l + 1));
+    __syncthreads();
+  }
+  {  // coarsest level: x = M^{-1} b, one wave per row
+    const int n = F.nc, lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+    const double* Minv = F.Minv + (size_t)s * n * n;
+    const T* b = B(last);
+    T* x = X(last);
+    for (int row = wave; row < n; row += nw) {
+      double acc = 0.0;
+      for (int j = lane; j < n; j += 64) acc += Minv[(size_t)row * n + j] * (double)b[j];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+      if (lane == 0) x[row] = (T)acc;
+    }
+    __syncthreads();
+  }
+  for (int l = last - 1; l >= 0; --l) {
+    const Geom& g = F.g[l];
+    for (int v = tid; v < g.N; v += nt) prolong_vertex<T>(g, F.g[l + 1], v, X(l + 1), X(l));
+    __syncthreads();
+    for (int it = 0; it < F.nu2; ++it)
+      for (int c = 7; c >= 0; --c) {
+        for (int q = tid; q < g.cnt[c]; q += nt) smooth_vertex<T>(g, c, q, A(l), D(l), B(l), X(l));
+        __syncthreads();
+      }
+  }
+}
+
+template <typename T>
+void launch_vcycle_bottom(const FusedLevels<T>& F, int S, const int* mask, hipStream_t st) {
+  hipLaunchKernelGGL(k_vcycle_bottom<T>, dim3(S), dim3(kFusedThreads), 0, st, F, mask);
+}
+
 // explicit instantiations
 #define EDF_INST(T)                                                                              \
   template void launch_smooth<T>(const Geom&, int, const T*, const T*, const T*, T*, int,        \
@@ -439,7 +546,8 @@ void launch_coarse_apply(int n, const double* Minv, const T* b, T* x, int S, con
                                   hipStream_t);                                                  \
   template void launch_fill<T>(T*, size_t, int, const int*, T, hipStream_t);                     \
   template void launch_coarse_apply<T>(int, const double*, const T*, T*, int, const int*,        \
-                                       hipStream_t);
+                                       hipStream_t);                                             \
+  template void launch_vcycle_bottom<T>(const FusedLevels<T>&, int, const int*, hipStream_t);
 EDF_INST(double)
 EDF_INST(float)
 template void launch_fill<int>(int*, size_t, int, const int*, int, hipStream_t);
