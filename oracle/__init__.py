@@ -9,5 +9,6 @@ Modules:
   newton  - implicit Euler + Newton with line search, exact sparse solves (Section 2.3)
   stats   - weighted mean, variance and exceedance probability (Section 3, eqs. pdestat,
             numer_var; Section 3.2 exceedance estimate)
+  gradient - salt mass in a subregion and its tangent-linear gradient in xi
 """
-from . import elder, newton, stats  # noqa: F401
+from . import elder, gradient, newton, stats  # noqa: F401

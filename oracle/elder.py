@@ -174,7 +174,7 @@ def _rho(c, ph):
 def storage_weight(box: Box, phi_e):
     """m_v = sum over the hexes adjacent to v of phi_e * V/8 (R3)."""
     Vo = box.h[0] * box.h[1] * box.h[2] / 8.0
-    m = np.zeros((box.nz, box.ny, box.nx))
+    m = np.zeros((box.nz, box.ny, box.nx), dtype=np.result_type(phi_e, float))
     for bits in CORNERS:
         box.corner(m, bits)[...] += phi_e * Vo
     return m

@@ -356,3 +356,48 @@ def test_injection_picks_nested_vertices():
     g = stats.inject(f, (33, 33, 9))
     assert g.shape == (9, 33, 33)
     assert g[1, 2, 3] == f[2, 4, 6]
+
+
+# ------------------------------------------------------------- gradient ----
+
+def test_qoi_weights_are_exact_volumes():
+    """With phi = 1 the octant weights integrate the box S exactly: sum W = |S|,
+    also when S cuts hexahedra (200/75 and 100/37.5 are not integers)."""
+    from oracle import gradient
+    ph = synth.physics(0, phi_mean=0.5)
+    box = elder.Box(9, 9, 5, ph)
+    ones = np.ones((4, 8, 8))
+    W = gradient.octant_weights(box, ones)
+    assert W.sum() == pytest.approx(200 * 200 * 50, rel=1e-14)
+    S = (0.0, 600.0, 0.0, 600.0, 0.0, 150.0)
+    assert gradient.octant_weights(box, ones, S).sum() == pytest.approx(600 * 600 * 150, rel=1e-14)
+    # uniform c: J = phi rho(c0) c0 |S|
+    u = np.zeros((5, 9, 9, 2))
+    u[..., 1] = 0.3
+    coef = elder.coefficients(box, [])
+    rho = ph["rho0"] + (ph["rho1"] - ph["rho0"]) * 0.3
+    assert gradient.qoi(box, coef, u) == pytest.approx(0.5 * rho * 0.3 * 200 * 200 * 50, rel=1e-13)
+
+
+def test_tangent_linear_gradient_matches_finite_differences():
+    """dJ/dxi from tangent-linear sensitivities equals central differences of the
+    forward map (h = 1e-6), over three steps of a 9x9x5 box with the 4-mode field."""
+    from oracle import gradient
+    ph = synth.physics(2)
+    box = elder.Box(9, 9, 5, ph)
+    S = (200.0, 400.0, 200.0, 400.0, 0.0, 60.0)
+    xi = np.array([0.3, -0.5, 0.2, 0.6])
+    u0 = synth.initial_state(9, 9, 5, ph)
+    dts = [DT, DT, DT]
+    J, g, _ = gradient.tangent_linear_gradient(box, xi, u0, dts, S)
+    assert J > 0
+    h = 1e-6
+    for m in range(4):
+        e = np.zeros(4)
+        e[m] = h
+        Jp = gradient.qoi(box, elder.coefficients(box, xi + e),
+                          gradient.forward(box, xi + e, u0, dts)[-1], S)
+        Jm = gradient.qoi(box, elder.coefficients(box, xi - e),
+                          gradient.forward(box, xi - e, u0, dts)[-1], S)
+        fd = (Jp - Jm) / (2 * h)
+        assert abs(g[m] - fd) <= 1e-5 * np.abs(g).max(), (m, g[m], fd)
