@@ -174,6 +174,23 @@ edf_status edf_solve(edf_problem* pb, double dt, int32_t n_steps, edf_step_stats
 edf_status edf_moments(edf_problem* pb, int32_t cx, int32_t cy, int32_t cz, double threshold,
                        const double* weights, double* mean, double* var, double* exceed);
 
+/* Discrete adjoint (the gradient of a quantity of interest with respect to the field
+ * parameters xi).  Runs n_steps implicit-Euler steps of length dt from the current
+ * states (as edf_step, keeping a checkpoint at the start of every step; steps that
+ * were split into sub-steps are recomputed from their checkpoint), then the adjoint
+ * equations backwards: per step one BiCGStab solve with the transposed Jacobian,
+ * preconditioned by the multigrid V-cycle of the transposed (frozen-flux) matrices.
+ * The quantity is the salt mass in the box [box[0],box[1]] x [box[2],box[3]] x
+ * [box[4],box[5]] (z = depth) at the final time,
+ *   J = sum_v sum_{e adjacent to v} phi_e |octant(e, v) ∩ box| rho(c_v) c_v,
+ * the mass density phi rho c of eq. e_tran_eq integrated over the box with the
+ * control volumes of the scheme.  Outputs (host): J[S_total], dJ_dxi[S_total][n_xi].
+ * The states are left at the final time.  Needs a field model with parameters.
+ * EDF_ERR_NO_CONVERGENCE if a forward step or an adjoint solve of some sample fails.
+ * Uses opts.lin_rtol as the relative tolerance of the adjoint solves.  Synchronises. */
+edf_status edf_adjoint(edf_problem* pb, const double* box, double dt, int32_t n_steps, double* J,
+                       double* dJ_dxi);
+
 /* Inspection entry points used by the parity tests. */
 
 /* Scaled residual F~(u; u_old) of one sample for dt, written to F [N][2] (same

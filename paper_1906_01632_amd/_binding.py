@@ -73,6 +73,7 @@ _SIGS = {
     "edf_get_jacobian": [_P, C.c_int32, _D, C.c_double, C.c_int32, _D],
     "edf_apply_vcycle": [_P, C.c_int32, C.c_double, _D, _D],
     "edf_apply_jacobian": [_P, C.c_int32, _D, _D],
+    "edf_adjoint": [_P, _D, C.c_double, C.c_int32, _D, _D],
     "edf_profile": [_P, C.c_int32, _D],
     "edf_last_error": [_P],
     "edf_destroy": [_P],
@@ -219,6 +220,16 @@ class Problem:
                                           _dptr(mean), _dptr(var), _dptr(exc)))
         shape = (cz, cy, cx)
         return mean.reshape(shape), var.reshape(shape), exc.reshape(shape)
+
+    def adjoint(self, box, dt: float, n_steps: int):
+        """Salt mass J in `box` (x0, x1, y0, y1, z0, z1) after n_steps steps and dJ/dxi,
+        by the discrete adjoint (edf_adjoint).  Returns (J [S], dJ [S, n_xi])."""
+        b = np.ascontiguousarray(np.asarray(box, dtype=np.float64))
+        J = np.empty(self.S)
+        g = np.empty((self.S, self.n_xi))
+        self._check(self._lib.edf_adjoint(self._h, _dptr(b), float(dt), int(n_steps), _dptr(J),
+                                          _dptr(g)))
+        return J, g
 
     def residual(self, sample: int, u, u_old, dt: float):
         a = np.ascontiguousarray(np.asarray(u, dtype=np.float64).reshape(-1))

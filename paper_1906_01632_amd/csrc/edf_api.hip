@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "adjoint.h"
 #include "edf.h"
 #include "edf_internal.h"
 
@@ -51,6 +52,15 @@ struct Group {
   int n_coarse = 0;
   int n_active = 0;  // samples active in the current Krylov chunk (known at chunk start)
   std::vector<int> h_start, clean;  // per sample: halvings to start the next step with
+  // adjoint buffers (allocated on first use)
+  double* traj = nullptr;      // [S][traj_cap][n]: states at the start of every step
+  size_t traj_cap = 0;
+  double* sub = nullptr;       // [S][sub_cap][n]: the sub-step states of one step
+  size_t sub_cap = 0;
+  double* lam_next = nullptr;  // [S][n]
+  double* tmpA = nullptr;      // [S][108][Np_0] FP64 scratch for transposition
+  int* idx = nullptr;          // [S]
+  double* g4 = nullptr;        // [S][4]
   std::vector<edf_step_stats> stats;
 };
 
@@ -79,6 +89,7 @@ struct edf_problem {
   };
   std::vector<ProfRec> prof_pending;
   double prof_count[2] = {0, 0}, prof_ms[2] = {0, 0}, prof_bytes[2] = {0, 0};
+  double* dxi = nullptr;  // parameters on the device [S_total][max(n_xi, 1)]
   // statistics buffers (allocated on first use)
   double* mom_f = nullptr;
   double* mom_w = nullptr;
@@ -767,6 +778,189 @@ edf_status macro_step(edf_problem* pb, Group& G, double DT) {
   return EDF_OK;
 }
 
+// ---------------------------------------------------------------------------
+// adjoint: matrices of every level transposed, at the current iterate
+// ---------------------------------------------------------------------------
+edf_status assemble_all_transposed(edf_problem* pb, Group& G, const int* mask, const double* dts) {
+  const bool mx = mixed(pb);
+  for (int l = 0; l < G.L; ++l) {
+    Level& L = G.lv[l];
+    if (l > 0) launch_inject(G.lv[l - 1].g, L.g, G.lv[l - 1].u, L.u, G.S, mask, pb->st);
+    const bool coarsest = l == G.L - 1;
+    if (l == 0) {  // exact Jacobian, transposed, for the Krylov products
+      launch_assemble(L.g, L.ph, dts, L.phi, L.K, L.u, G.tmpA, nullptr, G.S, mask, pb->st, false);
+      launch_transpose<double>(L.g, G.tmpA, L.A64, G.S, mask, pb->st);
+    }
+    launch_assemble(L.g, L.ph, dts, L.phi, L.K, L.u, G.tmpA, nullptr, G.S, mask, pb->st, true);
+    if (mx && !coarsest) {
+      launch_transpose<float>(L.g, G.tmpA, L.A32, G.S, mask, pb->st);
+      launch_block_inverse_f32(L.g, L.A32, (float*)L.Dinv, G.S, mask, pb->st);
+    } else {
+      double* m64 = l == 0 ? L.AV64 : L.A64;
+      launch_transpose<double>(L.g, G.tmpA, m64, G.S, mask, pb->st);
+      if (!coarsest) launch_block_inverse_f64(L.g, m64, (double*)L.Dinv, G.S, mask, pb->st);
+    }
+  }
+  const Level& C = G.lv[G.L - 1];
+  launch_coarse_dense(C.g, G.L == 1 ? C.AV64 : C.A64, G.Minv, G.S, mask, pb->st);
+  launch_gauss_jordan(G.n_coarse, G.Minv, G.piv, G.gj_status, G.S, mask, pb->st);
+  EDF_CHECK_LAUNCH();
+  return EDF_OK;
+}
+
+edf_status ensure_adjoint_buffers(edf_problem* pb, Group& G, int n_steps) {
+  const size_t S = G.S, n = G.n;
+  edf_status e;
+  if (G.traj_cap < (size_t)n_steps + 1) {
+    G.traj_cap = n_steps + 1;
+    if ((e = dalloc(pb, &G.traj, S * G.traj_cap * n))) return e;
+  }
+  const size_t kmax = (size_t(1) << pb->opts.dt_max_halvings) + 1;
+  if (G.sub_cap < kmax) {
+    G.sub_cap = kmax;
+    if ((e = dalloc(pb, &G.sub, S * G.sub_cap * n))) return e;
+  }
+  if (!G.lam_next) {
+    if ((e = dalloc(pb, &G.lam_next, S * n))) return e;
+    if ((e = dalloc(pb, &G.tmpA, S * kPlanes * (size_t)G.lv[0].g.off[8]))) return e;
+    if ((e = dalloc(pb, &G.idx, S))) return e;
+    if ((e = dalloc(pb, &G.g4, 4 * S))) return e;
+  }
+  return EDF_OK;
+}
+
+// d = state slot idx[s] of buf ([S][cap][n]) for every sample with idx[s] >= 0
+edf_status gather(edf_problem* pb, Group& G, const double* buf, size_t cap,
+                  const std::vector<int>& idx, double* dst) {
+  edf_status e;
+  if ((e = upload_ints(pb, G.idx, idx))) return e;
+  launch_gather_state(G.n, buf, cap * G.n, G.idx, dst, G.S, pb->st);
+  return EDF_OK;
+}
+
+edf_status scatter(edf_problem* pb, Group& G, const double* src, double* buf, size_t cap,
+                   const std::vector<int>& idx) {
+  edf_status e;
+  if ((e = upload_ints(pb, G.idx, idx))) return e;
+  launch_scatter_state(G.n, src, buf, cap * G.n, G.idx, G.S, pb->st);
+  return EDF_OK;
+}
+
+// forward over n_steps with a checkpoint at the start of every step, then the
+// adjoint sweep backwards; J[s] and dJ[s][4] of the group's samples
+edf_status adjoint_group(edf_problem* pb, Group& G, const QoiBox& box, double dt, int n_steps,
+                         std::vector<double>& Jv, std::vector<double>& grad) {
+  hipStream_t st = pb->st;
+  const int S = G.S;
+  edf_status e;
+  if ((e = ensure_adjoint_buffers(pb, G, n_steps))) return e;
+  const Level& L0 = G.lv[0];
+  // forward with checkpoints; H[n][s] = halvings of step n
+  std::vector<std::vector<int>> H(n_steps, std::vector<int>(S, 0));
+  std::vector<int> idx(S, 0);
+  if ((e = scatter(pb, G, G.u, G.traj, G.traj_cap, idx))) return e;
+  for (int n = 0; n < n_steps; ++n) {
+    if ((e = macro_step(pb, G, dt))) return e;
+    for (int s = 0; s < S; ++s) {
+      if (G.stats[s].status != EDF_SAMPLE_OK)
+        return fail(pb, EDF_ERR_NO_CONVERGENCE,
+                    "forward step " + std::to_string(n) + " failed for sample " +
+                        std::to_string(G.s0 + s) + "; the adjoint needs every step");
+      int h = 0;
+      while ((1 << h) < G.stats[s].substeps) ++h;
+      H[n][s] = h;
+    }
+    std::fill(idx.begin(), idx.end(), n + 1);
+    if ((e = scatter(pb, G, G.u, G.traj, G.traj_cap, idx))) return e;
+  }
+  set_dt(pb, G, dt);
+  FieldParams fp{pb->phys.lx, pb->phys.ly, pb->phys.lz, pb->phys.phi_mean, pb->phys.K_mean,
+                 pb->phys.field_model, pb->phys.n_xi};
+  const double* dxi = pb->dxi + (size_t)G.s0 * std::max(pb->phys.n_xi, 1);
+  Jv.assign(S, 0.0);
+  grad.assign(4 * (size_t)S, 0.0);
+  std::vector<double> hg(4 * S), dts(S), eta(S, pb->opts.lin_rtol);
+  std::vector<int> K(S), act(S), okv, why;
+  bool first = true;
+  for (int n = n_steps - 1; n >= 0; --n) {
+    int kmax = 1;
+    for (int s = 0; s < S; ++s) {
+      K[s] = 1 << H[n][s];
+      kmax = std::max(kmax, K[s]);
+      dts[s] = dt / K[s];
+    }
+    // sub-step states of step n: slot 0 = checkpoint, slot K = next checkpoint, the
+    // others recomputed (the forward kernels are deterministic per sample)
+    std::fill(idx.begin(), idx.end(), n);
+    if ((e = gather(pb, G, G.traj, G.traj_cap, idx, G.u))) return e;
+    std::fill(idx.begin(), idx.end(), 0);
+    if ((e = scatter(pb, G, G.u, G.sub, G.sub_cap, idx))) return e;
+    if ((e = upload_dbls(pb, G.dts, dts))) return e;
+    for (int r = 1; r < kmax; ++r) {
+      for (int s = 0; s < S; ++s) act[s] = K[s] > r;
+      if ((e = upload_ints(pb, G.nmask, act))) return e;
+      launch_masked_copy(G.n, G.u, G.u_old, S, G.nmask, st);
+      if ((e = newton_solve(pb, G, act, okv, why, false))) return e;
+      for (int s = 0; s < S; ++s)
+        if (act[s] && !okv[s]) return fail(pb, EDF_ERR_STATE, "sub-step recomputation failed");
+      for (int s = 0; s < S; ++s) idx[s] = act[s] ? r : -1;
+      if ((e = scatter(pb, G, G.u, G.sub, G.sub_cap, idx))) return e;
+    }
+    std::fill(idx.begin(), idx.end(), n + 1);
+    if ((e = gather(pb, G, G.traj, G.traj_cap, idx, G.u))) return e;
+    for (int s = 0; s < S; ++s) idx[s] = K[s];
+    if ((e = scatter(pb, G, G.u, G.sub, G.sub_cap, idx))) return e;
+    // backward through the sub-steps, one round per sub-step position
+    for (int r = 0; r < kmax; ++r) {
+      for (int s = 0; s < S; ++s) {
+        act[s] = K[s] > r;
+        idx[s] = act[s] ? K[s] - r : -1;
+      }
+      if ((e = gather(pb, G, G.sub, G.sub_cap, idx, G.u))) return e;
+      for (int s = 0; s < S; ++s) idx[s] = act[s] ? K[s] - r - 1 : -1;
+      if ((e = gather(pb, G, G.sub, G.sub_cap, idx, G.u_old))) return e;
+      if ((e = upload_ints(pb, G.nmask, act))) return e;
+      if (first) {  // J and dJ/du~ at the final state
+        const int nb = ceil_div(L0.g.N, kBlock);
+        launch_qoi(L0.g, L0.ph, box, L0.phi, G.u, G.F, G.part, S, nullptr, st);
+        launch_sum4(nb, G.part, G.g4, S, nullptr, st);
+        EDF_CHECK_LAUNCH();
+        EDF_TRY(hipMemcpyAsync(hg.data(), G.g4, 4 * S * sizeof(double), hipMemcpyDeviceToHost, st));
+        EDF_TRY(hipStreamSynchronize(st));
+        for (int s = 0; s < S; ++s) Jv[s] = hg[4 * s];
+      } else {
+        launch_adjoint_rhs(L0.g, L0.ph, L0.phi, G.u, G.lam_next, G.F, S, G.nmask, st);
+      }
+      if ((e = assemble_all_transposed(pb, G, G.nmask, G.dts))) return e;
+      if ((e = upload_dbls(pb, G.eta, eta))) return e;
+      if ((e = bicgstab(pb, G))) return e;
+      EDF_TRY(hipMemcpyAsync(pb->h_ks, G.ks, S * sizeof(KrylovScalars), hipMemcpyDeviceToHost, st));
+      EDF_TRY(hipStreamSynchronize(st));
+      for (int s = 0; s < S; ++s)
+        if (act[s] && pb->h_ks[s].state != 1 && pb->h_ks[s].bb > 0)
+          return fail(pb, EDF_ERR_NO_CONVERGENCE,
+                      "adjoint BiCGStab did not converge for sample " + std::to_string(G.s0 + s));
+      const int nb = launch_param_grad(L0.g, L0.ph, G.dts, fp, dxi, L0.phi, L0.K, G.u, G.u_old,
+                                       G.kx, box, first ? 1 : 0, G.part, S, G.nmask, st);
+      launch_sum4(nb, G.part, G.g4, S, G.nmask, st);
+      launch_masked_copy(G.n, G.kx, G.lam_next, S, G.nmask, st);
+      EDF_CHECK_LAUNCH();
+      EDF_TRY(hipMemcpyAsync(hg.data(), G.g4, 4 * S * sizeof(double), hipMemcpyDeviceToHost, st));
+      EDF_TRY(hipStreamSynchronize(st));
+      for (int s = 0; s < S; ++s)
+        if (act[s])
+          for (int m = 0; m < 4; ++m) grad[4 * s + m] += hg[4 * s + m];
+      first = false;
+    }
+  }
+  // leave the final state as the problem's state
+  std::fill(idx.begin(), idx.end(), n_steps);
+  if ((e = gather(pb, G, G.traj, G.traj_cap, idx, G.u))) return e;
+  EDF_TRY(hipMemcpyAsync(G.u_old, G.u, G.S * G.n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  EDF_TRY(hipStreamSynchronize(st));
+  return EDF_OK;
+}
+
 edf_status check_ready(edf_problem* pb) {
   if (!pb) return EDF_ERR_ARG;
   if (!pb->params_set) return fail(pb, EDF_ERR_STATE, "edf_set_parameters has not been called");
@@ -863,9 +1057,10 @@ edf_status edf_set_parameters(edf_problem* pb, const double* xi) {
     if (!(std::fabs(xi[e]) <= 1.0)) return fail(pb, EDF_ERR_ARG, "|xi| > 1 or not finite");
   FieldParams fp{pb->phys.lx, pb->phys.ly, pb->phys.lz, pb->phys.phi_mean, pb->phys.K_mean,
                  pb->phys.field_model, nxi};
-  double* dxi = nullptr;
   const size_t cnt = (size_t)pb->S_total * std::max(nxi, 1);
-  EDF_TRY(hipMalloc(&dxi, cnt * sizeof(double)));
+  edf_status es;
+  if (!pb->dxi && (es = dalloc(pb, &pb->dxi, cnt))) return es;
+  double* dxi = pb->dxi;
   std::vector<double> hx(cnt, 0.0);
   if (nxi > 0) std::memcpy(hx.data(), xi, (size_t)pb->S_total * nxi * sizeof(double));
   EDF_TRY(hipMemcpyAsync(dxi, hx.data(), cnt * sizeof(double), hipMemcpyHostToDevice, pb->st));
@@ -874,7 +1069,6 @@ edf_status edf_set_parameters(edf_problem* pb, const double* xi) {
       launch_coefficients(L.g, fp, dxi + (size_t)G.s0 * std::max(nxi, 1), G.S, L.phi, L.K, pb->st);
   EDF_CHECK_LAUNCH();
   EDF_TRY(hipStreamSynchronize(pb->st));
-  EDF_TRY(hipFree(dxi));
   // range check of phi and K on the finest grids (host copy per group, chunked per sample)
   for (Group& G : pb->groups) {
     const Level& L = G.lv[0];
@@ -1081,6 +1275,31 @@ edf_status edf_apply_jacobian(edf_problem* pb, int32_t group, const double* x, d
   EDF_CHECK_LAUNCH();
   EDF_TRY(hipMemcpyAsync(y, G.kv, G.S * G.n * sizeof(double), hipMemcpyDeviceToHost, pb->st));
   EDF_TRY(hipStreamSynchronize(pb->st));
+  return EDF_OK;
+}
+
+edf_status edf_adjoint(edf_problem* pb, const double* box, double dt, int32_t n_steps, double* J,
+                       double* dJ_dxi) {
+  edf_status e;
+  if ((e = check_ready(pb))) return e;
+  if (!box || !J || !dJ_dxi || !(dt > 0) || !std::isfinite(dt) || n_steps < 1)
+    return fail(pb, EDF_ERR_ARG, "bad adjoint arguments");
+  if (pb->phys.field_model == EDF_FIELD_CONST || pb->phys.n_xi < 1)
+    return fail(pb, EDF_ERR_ARG, "the constant field has no parameters");
+  QoiBox b;
+  for (int i = 0; i < 6; ++i) {
+    if (!std::isfinite(box[i])) return fail(pb, EDF_ERR_ARG, "box not finite");
+    b.b[i] = box[i];
+  }
+  const int nxi = pb->phys.n_xi;
+  for (Group& G : pb->groups) {
+    std::vector<double> Jv, gr;
+    if ((e = adjoint_group(pb, G, b, dt, n_steps, Jv, gr))) return e;
+    for (int s = 0; s < G.S; ++s) {
+      J[G.s0 + s] = Jv[s];
+      for (int m = 0; m < nxi; ++m) dJ_dxi[(size_t)(G.s0 + s) * nxi + m] = m < 4 ? gr[4 * s + m] : 0.0;
+    }
+  }
   return EDF_OK;
 }
 

@@ -1,0 +1,99 @@
+"""The discrete adjoint of the library against the oracle's tangent-linear gradient
+and against finite differences of the library's own forward map.  GPU."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import elder, gradient
+
+pytestmark = pytest.mark.gpu
+
+DT = synth.MONTH_S
+BOX_UPPER = (200.0, 400.0, 200.0, 400.0, 0.0, 60.0)
+TIGHT = dict(newton_rtol=1e-13, newton_atol=0.0, lin_rtol=1e-12, lin_max_it=800,
+             newton_max_it=40, check_every=8)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _problem(phys, groups, **opts):
+    from paper_1906_01632_amd import Problem
+    o = dict(TIGHT)
+    o.update(opts)
+    return Problem(phys, groups, o)
+
+
+@pytest.mark.parametrize("model,precision", [(2, 0), (3, 0), (2, 1)])
+def test_adjoint_gradient_matches_oracle_tangent_linear(model, precision):
+    nx, ny, nz = 17, 17, 5
+    phys = synth.physics(model)
+    xi = np.random.default_rng(21).uniform(-0.6, 0.6, (2, synth.N_XI[model]))
+    pb = _problem(phys, [(nx, ny, nz, 3, 2)], precision=precision)
+    pb.set_parameters(xi)
+    J, g = pb.adjoint(BOX_UPPER, DT, 3)
+    box = elder.Box(nx, ny, nz, phys)
+    for s in range(2):
+        Jr, gr, states = gradient.tangent_linear_gradient(
+            box, xi[s], synth.initial_state(nx, ny, nz, phys), [DT] * 3, BOX_UPPER)
+        print(f"sample {s}: J {J[s]:.9e} vs {Jr:.9e}; dJ {g[s]} vs {gr}", flush=True)
+        assert abs(J[s] - Jr) <= 1e-9 * abs(Jr)
+        assert np.abs(g[s] - gr).max() <= 1e-6 * np.abs(gr).max()
+        # the problem is left at the final state
+        assert np.abs(pb.get_state(s)[..., 1] - states[-1][..., 1]).max() < 1e-9
+    pb.destroy()
+
+
+def test_adjoint_gradient_matches_finite_differences_of_the_library():
+    """Central differences (h = 1e-6) of the library's own forward map."""
+    nx, ny, nz = 17, 17, 5
+    phys = synth.physics(2)
+    xi0 = np.array([0.2, -0.4, 0.5, 0.1])
+    box = (200.0, 400.0, 200.0, 400.0, 0.0, 60.0)
+    pb = _problem(phys, [(nx, ny, nz, 3, 1)])
+    pb.set_parameters(xi0[None])
+    J, g = pb.adjoint(box, DT, 2)
+    pb.destroy()
+    h = 1e-6
+    pts = [xi0 + h * np.eye(4)[m] for m in range(4)] + [xi0 - h * np.eye(4)[m] for m in range(4)]
+    fd_pb = _problem(phys, [(nx, ny, nz, 3, 8)])
+    fd_pb.set_parameters(np.array(pts))
+    fd_pb.solve(DT, 2)
+    ph = phys
+    ebox = elder.Box(nx, ny, nz, ph)
+    vals = [gradient.qoi(ebox, elder.coefficients(ebox, pts[i]), fd_pb.get_state(i), box)
+            for i in range(8)]
+    fd = np.array([(vals[m] - vals[4 + m]) / (2 * h) for m in range(4)])
+    print("adjoint", g[0], "fd", fd, flush=True)
+    assert np.abs(g[0] - fd).max() <= 1e-5 * np.abs(fd).max()
+    fd_pb.destroy()
+
+
+def test_adjoint_through_split_steps():
+    """A 4-month step that one sample has to take as sub-steps: the adjoint recomputes
+    them from the checkpoint and still matches the oracle replaying the same steps."""
+    nx, ny, nz = 17, 17, 5
+    phys = synth.physics(2)
+    xi = np.array([[0.0, 0.0, 0.0, 0.0], [0.9, 0.9, 0.9, 0.9]])
+    pb = _problem(phys, [(nx, ny, nz, 3, 2)], dt_max_halvings=4)
+    pb.set_parameters(xi)
+    # first step alone to learn the sub-step counts the adjoint run will use
+    probe = _problem(phys, [(nx, ny, nz, 3, 2)], dt_max_halvings=4)
+    probe.set_parameters(xi)
+    sub = [s["substeps"] for s in probe.step(4 * DT)]
+    probe.destroy()
+    assert sub[0] == 1 and sub[1] >= 2
+    J, g = pb.adjoint(BOX_UPPER, 4 * DT, 1)
+    box = elder.Box(nx, ny, nz, phys)
+    for s in range(2):
+        Jr, gr, _ = gradient.tangent_linear_gradient(
+            box, xi[s], synth.initial_state(nx, ny, nz, phys), [4 * DT / sub[s]] * sub[s],
+            BOX_UPPER)
+        print(f"sample {s} substeps {sub[s]}: dJ {g[s]} vs {gr}", flush=True)
+        assert abs(J[s] - Jr) <= 1e-9 * abs(Jr)
+        assert np.abs(g[s] - gr).max() <= 1e-6 * np.abs(gr).max()
+    pb.destroy()
