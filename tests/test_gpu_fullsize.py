@@ -1,0 +1,123 @@
+"""Parity at the benchmark sizes (129x129x33, 257x257x65, the three qMC grids), in the
+launch configuration bench.py times (Eisenstat-Walker forcing, one convergence check
+per BiCGStab iteration).  The oracle cannot run Newton with direct solves at these
+sizes; it checks every output through properties that hold at any size: its own
+residual evaluated at the GPU's converged states, element-wise defect parity, and
+the statistics of the injected fields.  GPU."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import elder, stats
+
+pytestmark = pytest.mark.gpu
+
+DT = synth.MONTH_S
+BENCH_OPTS = dict(lin_rtol=1e-6, lin_max_it=200, newton_max_it=20, check_every=1, forcing=1)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _problem(phys, groups, **opts):
+    from paper_1906_01632_amd import Problem
+    o = dict(BENCH_OPTS)
+    o.update(opts)
+    return Problem(phys, groups, o)
+
+
+def _oracle_scaled_norm(box, coef, u, u_old):
+    F = elder.residual(box, coef, u, u_old, DT) * elder.row_scale(box, DT)
+    return float(np.linalg.norm(F))
+
+
+def test_defect_parity_129_every_vertex():
+    nx, ny, nz = 129, 129, 33
+    phys = synth.physics(2)
+    xi = synth.lattice_points(512, 4, 0)[1:2]
+    pb = _problem(phys, [(nx, ny, nz, 6, 1)])
+    pb.set_parameters(xi)
+    u = synth.random_state(nx, ny, nz, phys, seed=3)
+    uo = synth.random_state(nx, ny, nz, phys, seed=4)
+    got = pb.residual(0, u, uo, DT)
+    box = elder.Box(nx, ny, nz, phys)
+    ref = elder.residual(box, elder.coefficients(box, xi[0]), u, uo, DT) * elder.row_scale(box, DT)
+    assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
+    pb.destroy()
+
+
+def test_qmc_groups_step_solves_the_oracle_system():
+    """Two lattice samples of each resolution of the qMC workload in one problem: every
+    converged state zeroes the oracle's residual to the Newton tolerance, and the pooled
+    moments on the 33x33x9 grid are the oracle statistics of the same fields."""
+    wl = synth.workload("qmc512_mixedres")
+    phys = synth.physics(wl.field_model)
+    groups, xis, off = [], [], 0
+    for g in wl.groups:
+        groups.append((g.nx, g.ny, g.nz, g.levels, 2))
+        xis.append(wl.xi[off:off + 2])
+        off += g.samples
+    xi = np.concatenate(xis)
+    pb = _problem(phys, groups, newton_rtol=wl.newton_rtol)
+    pb.set_parameters(xi)
+    st = pb.step(DT)
+    fields = []
+    for s in range(6):
+        nx, ny, nz = groups[s // 2][:3]
+        box = elder.Box(nx, ny, nz, phys)
+        coef = elder.coefficients(box, xi[s])
+        u0 = synth.initial_state(nx, ny, nz, phys)
+        u = pb.get_state(s)
+        sub = st[s]["substeps"]
+        if sub == 1:
+            r0 = _oracle_scaled_norm(box, coef, u0, u0)
+            r = _oracle_scaled_norm(box, coef, u, u0)
+            print(f"sample {s} {nx}x{ny}x{nz}: oracle |F~| {r:.3e} of {r0:.3e}", flush=True)
+            assert r <= 2 * wl.newton_rtol * r0 + 1e-10
+        assert -0.05 <= u[..., 1].min() and u[..., 1].max() <= 1.05
+        fields.append(stats.inject(u[..., 1], (33, 33, 9)))
+    mean, var, exc = pb.moments((33, 33, 9), threshold=0.5)
+    m, v, e = stats.moments(np.array(fields), threshold=0.5)
+    assert np.abs(mean - m).max() < 1e-14 and np.abs(var - v).max() < 1e-14
+    assert np.abs(exc - e).max() < 1e-14
+    pb.destroy()
+
+
+def test_mixed_257_matches_fp64_and_solves_the_oracle_system():
+    """The mixed-precision workload's shapes: a 257x257x65 sample and a 129x129x33 sample,
+    FP32 V-cycle; the result agrees with the FP64-V-cycle result to 1e-6 relative L2 per
+    field, and the oracle's residual at the mixed result meets the Newton tolerance."""
+    wl = synth.workload("mixed257")
+    phys = synth.physics(wl.field_model)
+    groups = [(257, 257, 65, 7, 1), (129, 129, 33, 6, 1)]
+    xi = wl.xi[:2]
+    out = {}
+    for prec in (1, 0):
+        pb = _problem(phys, groups, newton_rtol=wl.newton_rtol, precision=prec)
+        pb.set_parameters(xi)
+        st = pb.step(DT)
+        assert all(s["status"] == 0 for s in st), st
+        out[prec] = [pb.get_state(s) for s in range(2)]
+        out[("sub", prec)] = [s["substeps"] for s in st]
+        pb.destroy()
+    assert out[("sub", 0)] == out[("sub", 1)]
+    for s in range(2):
+        for f in range(2):
+            a, b = out[1][s][..., f], out[0][s][..., f]
+            rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+            print(f"sample {s} field {f}: mixed vs FP64 rel L2 {rel:.2e}", flush=True)
+            assert rel <= 1e-6
+    if out[("sub", 1)][0] != 1:
+        return  # the step was split; the state does not solve the full-step system
+    nx, ny, nz = 257, 257, 65
+    box = elder.Box(nx, ny, nz, phys)
+    coef = elder.coefficients(box, xi[0])
+    u0 = synth.initial_state(nx, ny, nz, phys)
+    r0 = _oracle_scaled_norm(box, coef, u0, u0)
+    r = _oracle_scaled_norm(box, coef, out[1][0], u0)
+    print(f"257: oracle |F~| at the mixed result {r:.3e} of {r0:.3e}", flush=True)
+    assert r <= 2 * wl.newton_rtol * r0 + 1e-10
