@@ -39,6 +39,23 @@ def roctx_region():
     return (lambda: None), (lambda: None)
 
 
+def measured_traffic(kernel_source):
+    """HBM traffic of the smoother per launch from the committed rocprofv3 counter
+    measurement of the default command, or None when the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_smooth_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(kernel_source, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("kernel_source_sha256") != digest:
+        return None
+    return rec
+
+
 def cpu_baseline(wl, phys, budget_s=20.0):
     """The oracle (plain FP64 NumPy/SciPy, unchanged) on a bounded sample of the
     workload: whole implicit-Euler steps of the samples of its smallest group."""
@@ -75,12 +92,16 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--forcing", type=int, default=1, choices=[0, 1],
                     help="1: Eisenstat-Walker tolerances for the Newton systems")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default fused-bottom levels instead of timing the choices")
     ap.add_argument("--profile-timed-region", action="store_true",
                     help="mark the timed steps for rocprofv3 --selected-regions")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="copy 1 GiB device-to-device at the start of the timed region (a copy "
+                         "of known size that calibrates the HBM byte counters)")
     args = ap.parse_args()
+    # rocprofv3 --selected-regions starts paused: only the timed steps are collected
     region_start, region_stop = roctx_region() if args.profile_timed_region else (None, None)
-    if region_stop:
-        region_stop()  # nothing before the timed steps is collected
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): samples are independent, "
               "so N GPUs would each run their own share; no multi-GPU path is built.",
@@ -106,7 +127,10 @@ def main():
     t = time.perf_counter()
     pb = Problem(phys, groups, opts)
     pb.set_parameters(wl.xi)
-    log(f"set-up {time.perf_counter() - t:.1f} s")
+    if not args.no_autotune:
+        pb.autotune(wl.dt)
+    tuning = [pb.tuning(g)[0] for g in range(len(groups))]
+    log(f"set-up {time.perf_counter() - t:.1f} s; fused V-cycle bottom from levels {tuning}")
     for w in range(args.warmup):
         t = time.perf_counter()
         pb.step(wl.dt)
@@ -117,6 +141,12 @@ def main():
     stats = None
     if region_start:
         region_start()
+    if args.copy_probe:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     t0 = time.perf_counter()
     for k in range(args.steps):
         stats = pb.step(wl.dt)
@@ -146,7 +176,8 @@ def main():
         "data": "synthetic (seeded lattice parameters; no dataset)",
         "config": {"workload": wl.name, "groups": [list(g) for g in groups], "samples": S,
                    "dt_s": wl.dt, "precision": prec, "newton_rtol": wl.newton_rtol,
-                   "lin_rtol": 1e-6, "forcing": "eisenstat-walker" if args.forcing else "fixed"},
+                   "lin_rtol": 1e-6, "forcing": "eisenstat-walker" if args.forcing else "fixed",
+                   "fused_bottom_from_level": tuning},
         "dof_timesteps_per_s": dofs * args.steps / el,
         "solver": {"newton_its_per_step": newton, "bicgstab_its_per_newton": lin,
                    "failed_samples_last_step": failed},
@@ -159,9 +190,13 @@ def main():
                          "bytes_per_vcycle": prof["vcycle_bytes"] / prof["vcycles"]}
     if prof["launches"]:
         gbs = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9
+        tr = measured_traffic(os.path.join(ROOT, "paper_1906_01632_amd", "csrc", "mg_kernels.hip"))
+        traffic = None
+        if tr and tr.get("workload") == wl.name and tr.get("precision") == prec:
+            traffic = tr["hbm_bytes_per_launch"]
         out["roofline"] = {"bound": "hbm", "kernel": "k_smooth (block Gauss-Seidel colour sweep)",
                            "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                           "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
                            "launches": prof["launches"],
                            "avg_launch_us": 1e3 * prof["ms"] / prof["launches"],
                            "bytes_per_launch": prof["bytes"] / prof["launches"]}

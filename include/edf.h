@@ -61,7 +61,7 @@ enum {
 enum {
   EDF_SAMPLE_OK = 0,
   EDF_SAMPLE_NEWTON_FAIL = 1, /* Newton reached its iteration limit                 */
-  EDF_SAMPLE_LINEAR_FAIL = 2, /* BiCGStab reached its limit in the last Newton step */
+  EDF_SAMPLE_LINEAR_FAIL = 2, /* BiCGStab did not reach its tolerance               */
   EDF_SAMPLE_NONFINITE = 3,   /* the residual became NaN or Inf                     */
   EDF_SAMPLE_INADMISSIBLE = 4 /* Newton converged to a state with c outside [0, 1]  */
 };
@@ -155,8 +155,10 @@ edf_status edf_get_state(edf_problem* pb, int32_t sample, double* pc, int32_t is
  * h starts at the value that worked for the sample in its previous step (0 at
  * first; lowered by one after three steps without a retry).  A sample whose Newton
  * iteration fails (iteration limit, no 100-fold residual reduction after 8
- * iterations, a non-finite or 1e4-fold grown residual, or a converged state with c
- * outside [-0.05, 1.05]) restarts the step from its state at the start of the call
+ * iterations, a non-finite or 1e4-fold grown residual, a converged state with c
+ * outside [-0.05, 1.05], or, while h < opts.dt_max_halvings, a Newton system whose
+ * BiCGStab residual ended above twice its tolerance) restarts the step from its state at the
+ * start of the call
  * with h raised by one, up to opts.dt_max_halvings; after that its status is the
  * failure and its state is left unchanged.  stats, if not NULL, is a host array
  * [S_total].  Synchronises. */
@@ -229,6 +231,27 @@ edf_status edf_apply_jacobian(edf_problem* pb, int32_t group, const double* x, d
  * N_l (3 x 108 + 2 x 4 + 12 x 2) values (three stencil sweeps, two block-inverse reads,
  * twelve vector passes) plus the dense coarse inverse.  Synchronises the stream. */
 edf_status edf_profile(edf_problem* pb, int32_t enable, double* out);
+
+/* Autotuning of the V-cycle (an implementation choice, not part of the method): the
+ * coarse levels of every group can run in one launch with one workgroup per sample
+ * (the fused bottom), which saves launches but walks the levels one after the other.
+ * This call assembles the Newton matrices at the current states with time step dt,
+ * times three V-cycles per group for every admissible first fused level and keeps
+ * the fastest.  States are not changed.  Without it (or edf_set_tuning) a group of
+ * >= 64 samples fuses all levels of <= 4096 vertices, a smaller group only the
+ * coarse solve.  EDF_ERR_STATE before edf_set_parameters, EDF_ERR_ARG for dt <= 0. */
+edf_status edf_autotune(edf_problem* pb, double dt);
+
+/* The V-cycle configuration of group `group`: *fuse_from = first level run in the
+ * fused bottom launch; ms (host double[n_levels] or NULL) = the autotuned V-cycle
+ * time per candidate first level in milliseconds (-1 where not measured). */
+edf_status edf_get_tuning(edf_problem* pb, int32_t group, int32_t* fuse_from, double* ms);
+
+/* Fix the first level of the fused bottom of group `group` (e.g. a tuning saved from
+ * an earlier run; a later autotuning step keeps it).  EDF_ERR_ARG unless every level
+ * from fuse_from on has at most 4096 vertices, at most 6 levels are fused, and
+ * fuse_from <= n_levels - 1 (the coarsest level alone is always allowed). */
+edf_status edf_set_tuning(edf_problem* pb, int32_t group, int32_t fuse_from);
 
 const char* edf_last_error(const edf_problem* pb);
 void edf_destroy(edf_problem* pb); /* NULL is allowed */

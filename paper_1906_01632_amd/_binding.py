@@ -74,6 +74,9 @@ _SIGS = {
     "edf_apply_vcycle": [_P, C.c_int32, C.c_double, _D, _D],
     "edf_apply_jacobian": [_P, C.c_int32, _D, _D],
     "edf_adjoint": [_P, _D, C.c_double, C.c_int32, _D, _D],
+    "edf_autotune": [_P, C.c_double],
+    "edf_get_tuning": [_P, C.c_int32, C.POINTER(C.c_int32), _D],
+    "edf_set_tuning": [_P, C.c_int32, C.c_int32],
     "edf_profile": [_P, C.c_int32, _D],
     "edf_last_error": [_P],
     "edf_destroy": [_P],
@@ -270,6 +273,20 @@ class Problem:
         self._check(self._lib.edf_profile(self._h, int(bool(enable)), _dptr(out)))
         return {"launches": int(out[0]), "ms": float(out[1]), "bytes": float(out[2]),
                 "vcycles": int(out[3]), "vcycle_ms": float(out[4]), "vcycle_bytes": float(out[5])}
+
+    def autotune(self, dt: float):
+        self._check(self._lib.edf_autotune(self._h, float(dt)))
+
+    def tuning(self, group: int):
+        """(first fused level, V-cycle ms per candidate level or -1) of a group."""
+        f = C.c_int32()
+        L = self.groups[group][3]
+        ms = np.empty(L)
+        self._check(self._lib.edf_get_tuning(self._h, group, C.byref(f), _dptr(ms)))
+        return int(f.value), ms
+
+    def set_tuning(self, group: int, fuse_from: int):
+        self._check(self._lib.edf_set_tuning(self._h, group, fuse_from))
 
     def destroy(self):
         if getattr(self, "_h", None):

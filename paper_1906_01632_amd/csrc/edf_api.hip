@@ -51,6 +51,8 @@ struct Group {
   int *piv = nullptr, *gj_status = nullptr;
   int n_coarse = 0;
   int n_active = 0;  // samples active in the current Krylov chunk (known at chunk start)
+  int fuse_from = -1;  // levels from here on run in the fused launch (-1: not chosen yet)
+  std::vector<double> tune_ms;  // V-cycle time per candidate fuse_from (autotuning)
   std::vector<int> h_start, clean;  // per sample: halvings to start the next step with
   // adjoint buffers (allocated on first use)
   double* traj = nullptr;      // [S][traj_cap][n]: states at the start of every step
@@ -385,6 +387,17 @@ double vcycle_bytes(const Group& G, size_t tsz) {
 // ---------------------------------------------------------------------------
 // one V-cycle: out = M^{-1} in (FP64 vectors of the scaled unknowns)
 // ---------------------------------------------------------------------------
+// first level of the fused bottom of the V-cycle when not tuned: all levels of at
+// most kFuseMaxN vertices when the group has many samples (their workgroups run side
+// by side), else only the coarse solve (one workgroup per sample walks the levels
+// one after the other, which does not pay for a single sample)
+int first_fusable(const Group& G) {
+  int l0 = G.L - 1;
+  while (l0 > 0 && G.lv[l0 - 1].g.N <= kFuseMaxN && G.L - l0 < kMaxFused) --l0;
+  return l0;
+}
+int default_fuse_from(const Group& G) { return G.S >= 64 ? first_fusable(G) : G.L - 1; }
+
 template <typename T>
 const T* stencil(const Level& L);
 template <>
@@ -418,9 +431,8 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
     b = l == 0 ? b0 : (T*)G.lv[l].b;
     x = l == 0 ? x0 : (T*)G.lv[l].x;
   };
-  // levels from l0 on are small: they run in one fused launch (one workgroup per sample)
-  int l0 = G.L - 1;
-  while (l0 > 0 && G.lv[l0 - 1].g.N <= kFuseMaxN && G.L - l0 < kMaxFused) --l0;
+  // levels from l0 on run in one fused launch (one workgroup per sample)
+  const int l0 = G.fuse_from >= 0 ? G.fuse_from : default_fuse_from(G);
   if (l0 > 0) launch_fill<T>(x0, G.n, S, mask, T(0), st);
   for (int l = 0; l < l0; ++l) {
     Level& L = G.lv[l];
@@ -545,6 +557,51 @@ void set_dt(edf_problem* pb, Group& G, double dt) {
 }
 
 // ---------------------------------------------------------------------------
+// autotuning of the fused V-cycle bottom: with the matrices of the current state,
+// time three V-cycles for every candidate first fused level and keep the fastest
+// ---------------------------------------------------------------------------
+edf_status autotune_group(edf_problem* pb, Group& G) {
+  hipStream_t st = pb->st;
+  std::vector<int> all(G.S, 1);
+  edf_status e;
+  if ((e = upload_ints(pb, G.nmask, all))) return e;
+  if ((e = assemble_all(pb, G, G.nmask, nullptr))) return e;
+  launch_defect(G.lv[0].g, G.lv[0].ph, nullptr, G.lv[0].phi, G.lv[0].K, G.u, G.u, G.kp, G.S,
+                nullptr, st);
+  hipEvent_t a, b;
+  EDF_TRY(hipEventCreate(&a));
+  EDF_TRY(hipEventCreate(&b));
+  const bool was_on = pb->prof_on;
+  pb->prof_on = false;
+  G.n_active = G.S;
+  G.tune_ms.assign(G.L, -1.0);
+  double best = 1e300;
+  int best_l0 = G.L - 1;
+  for (int l0 = first_fusable(G); l0 < G.L; ++l0) {
+    G.fuse_from = l0;
+    precondition(pb, G, G.kp, G.kph, G.nmask);  // warm-up
+    EDF_TRY(hipEventRecord(a, st));
+    for (int r = 0; r < 3; ++r) precondition(pb, G, G.kp, G.kph, G.nmask);
+    EDF_TRY(hipEventRecord(b, st));
+    EDF_TRY(hipEventSynchronize(b));
+    float ms = 0.f;
+    EDF_TRY(hipEventElapsedTime(&ms, a, b));
+    G.tune_ms[l0] = ms / 3.0;
+    if (ms < best) {
+      best = ms;
+      best_l0 = l0;
+    }
+  }
+  pb->prof_on = was_on;
+  G.fuse_from = best_l0;
+  EDF_TRY(hipEventDestroy(a));
+  EDF_TRY(hipEventDestroy(b));
+  EDF_CHECK_LAUNCH();
+  return EDF_OK;
+}
+
+
+// ---------------------------------------------------------------------------
 // Newton with line search (Section 2.3) for the samples in `run`, each with its
 // own step length in G.dts and previous state in G.u_old.  ok[s] = 1 when the
 // sample converged to an admissible state (0 <= c <= 1 up to kRangeTol).
@@ -555,7 +612,8 @@ constexpr int kSlowIts = 8;             // give up after this many iterations ..
 constexpr double kSlowDrop = 1e-2;      // ... without this reduction of ||F~||
 
 edf_status newton_solve(edf_problem* pb, Group& G, const std::vector<int>& run,
-                        std::vector<int>& ok, std::vector<int>& why, bool first_attempt) {
+                        const std::vector<int>& can_retry, std::vector<int>& ok,
+                        std::vector<int>& why, bool first_attempt) {
   hipStream_t st = pb->st;
   const int S = G.S;
   const edf_solver_opts& o = pb->opts;
@@ -625,6 +683,13 @@ edf_status newton_solve(edf_problem* pb, Group& G, const std::vector<int>& run,
       if (nm[s]) {
         G.stats[s].newton_its += 1;
         G.stats[s].lin_its += pb->h_ks[s].it;
+        // BiCGStab ended more than a factor 2 short of its tolerance: the preconditioner
+        // is not up to this time step, and a shorter one is cheaper than inexact Newton
+        const KrylovScalars& k = pb->h_ks[s];
+        if (can_retry[s] && k.state != 1 && !(k.rr <= 4.0 * k.tol2)) {
+          nm[s] = 0;
+          why[s] = EDF_SAMPLE_LINEAR_FAIL;
+        }
       }
     // line search on u - lambda * x  (x solves A x = F~, so the Newton step is -x)
     double l = 1.0;
@@ -716,7 +781,7 @@ edf_status macro_step(edf_problem* pb, Group& G, double DT) {
     G.h_start.assign(S, 0);
     G.clean.assign(S, 0);
   }
-  std::vector<int> h(G.h_start), done(S, 0), running(S, 1), ok, why, restore(S);
+  std::vector<int> h(G.h_start), done(S, 0), running(S, 1), ok, why, restore(S), can_retry(S);
   std::vector<double> dts(S);
   for (int s = 0; s < S; ++s) {
     h[s] = std::min(h[s], pb->opts.dt_max_halvings);
@@ -734,7 +799,8 @@ edf_status macro_step(edf_problem* pb, Group& G, double DT) {
     if ((e = upload_dbls(pb, G.dts, dts))) return e;
     if ((e = upload_ints(pb, G.nmask, running))) return e;
     launch_masked_copy(G.n, G.u, G.u_old, S, G.nmask, st);
-    if ((e = newton_solve(pb, G, running, ok, why, first))) return e;
+    for (int s = 0; s < S; ++s) can_retry[s] = h[s] < pb->opts.dt_max_halvings;
+    if ((e = newton_solve(pb, G, running, can_retry, ok, why, first))) return e;
     first = false;
     bool any_restore = false;
     for (int s = 0; s < S; ++s) {
@@ -900,7 +966,9 @@ edf_status adjoint_group(edf_problem* pb, Group& G, const QoiBox& box, double dt
       for (int s = 0; s < S; ++s) act[s] = K[s] > r;
       if ((e = upload_ints(pb, G.nmask, act))) return e;
       launch_masked_copy(G.n, G.u, G.u_old, S, G.nmask, st);
-      if ((e = newton_solve(pb, G, act, okv, why, false))) return e;
+      // the forward attempt at this sub-step length succeeded, so no Krylov failure
+      // ended it: replaying without that check takes the same path
+      if ((e = newton_solve(pb, G, act, std::vector<int>(S, 0), okv, why, false))) return e;
       for (int s = 0; s < S; ++s)
         if (act[s] && !okv[s]) return fail(pb, EDF_ERR_STATE, "sub-step recomputation failed");
       for (int s = 0; s < S; ++s) idx[s] = act[s] ? r : -1;
@@ -1300,6 +1368,38 @@ edf_status edf_adjoint(edf_problem* pb, const double* box, double dt, int32_t n_
       for (int m = 0; m < nxi; ++m) dJ_dxi[(size_t)(G.s0 + s) * nxi + m] = m < 4 ? gr[4 * s + m] : 0.0;
     }
   }
+  return EDF_OK;
+}
+
+edf_status edf_autotune(edf_problem* pb, double dt) {
+  edf_status e = check_ready(pb);
+  if (e) return e;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(pb, EDF_ERR_ARG, "dt must be positive");
+  for (Group& G : pb->groups) {
+    set_dt(pb, G, dt);
+    if ((e = autotune_group(pb, G))) return fail(pb, e, "autotuning failed");
+  }
+  return EDF_OK;
+}
+
+edf_status edf_get_tuning(edf_problem* pb, int32_t group, int32_t* fuse_from, double* ms) {
+  if (!pb || group < 0 || group >= (int)pb->groups.size() || !fuse_from)
+    return fail(pb, EDF_ERR_ARG, "bad tuning arguments");
+  Group& G = pb->groups[group];
+  *fuse_from = G.fuse_from >= 0 ? G.fuse_from : default_fuse_from(G);
+  if (ms)
+    for (int l = 0; l < G.L; ++l) ms[l] = l < (int)G.tune_ms.size() ? G.tune_ms[l] : -1.0;
+  return EDF_OK;
+}
+
+edf_status edf_set_tuning(edf_problem* pb, int32_t group, int32_t fuse_from) {
+  if (!pb || group < 0 || group >= (int)pb->groups.size())
+    return fail(pb, EDF_ERR_ARG, "bad tuning arguments");
+  Group& G = pb->groups[group];
+  if (fuse_from < first_fusable(G) || fuse_from >= G.L)
+    return fail(pb, EDF_ERR_ARG, "fuse_from must lie between the first level of at most 4096 "
+                                 "vertices (at most 6 fused levels) and the coarsest level");
+  G.fuse_from = fuse_from;
   return EDF_OK;
 }
 

@@ -252,6 +252,59 @@ def test_vcycle_is_a_contraction(precision):
     pb.destroy()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_vcycle_same_for_every_fused_bottom(precision):
+    """The V-cycle gives the same result whichever levels run in the fused bottom launch
+    (same per-vertex arithmetic in the same colour order), and set_tuning rejects levels
+    that do not fit the fused launch."""
+    nx, ny, nz = 33, 33, 9
+    phys = synth.physics(2)
+    pb = _problem(phys, [(nx, ny, nz, 4, 3)], precision=precision)
+    pb.set_parameters(_xi(2, 3, seed=11))
+    b = np.random.default_rng(5).standard_normal((3, nz, ny, nx, 2))
+    b[..., 1][:, -1] = 0.0
+    ys = {}
+    for l0 in (1, 2, 3):  # 17x17x5, 9x9x3 and the 5x5x2 coarse solve alone
+        pb.set_tuning(0, l0)
+        assert pb.tuning(0)[0] == l0
+        ys[l0] = pb.apply_vcycle(0, DT, b)
+    tol = 1e-13 if precision == 0 else 1e-6
+    for l0 in (2, 3):
+        assert _rel(ys[l0], ys[1]) < tol, (l0, _rel(ys[l0], ys[1]))
+    for bad in (0, 4, -1):  # 33x33x9 exceeds the fused launch; 4 is no level
+        with pytest.raises(RuntimeError):
+            pb.set_tuning(0, bad)
+    pb.destroy()
+
+
+def test_autotuned_step_matches_default():
+    """Autotuning times the V-cycle for every fused-bottom choice, keeps the fastest,
+    leaves the states alone, and the step then solves the same system to the same
+    state."""
+    nx, ny, nz = 33, 33, 9
+    phys = synth.physics(2)
+    xi = _xi(2, 2, seed=12)
+    out = {}
+    for tune in (0, 1):
+        pb = _problem(phys, [(nx, ny, nz, 4, 2)])
+        pb.set_parameters(xi)
+        if tune:
+            pb.autotune(DT)
+            assert _rel(pb.get_state(1), synth.initial_state(nx, ny, nz, phys)) < 1e-14
+        st = pb.step(DT)
+        assert all(x["status"] == 0 for x in st)
+        out[tune] = np.stack([pb.get_state(s) for s in range(2)])
+        l0, ms = pb.tuning(0)
+        print(f"autotune {tune}: fused from level {l0}, V-cycle ms {ms}", flush=True)
+        if tune:
+            assert all(ms[l] > 0 for l in (1, 2, 3)) and ms[0] == -1.0
+            assert ms[l0] == min(ms[1:])
+        else:
+            assert l0 == 3 and all(ms == -1.0)  # 2 samples: only the coarse solve fused
+        pb.destroy()
+    assert _rel(out[1], out[0]) < 1e-12
+
+
 def test_mixed_precision_step_matches_fp64_oracle():
     nx, ny, nz = 33, 33, 9
     phys = synth.physics(2)
