@@ -29,7 +29,7 @@ __global__ __launch_bounds__(kBlock) void k_transpose(Geom g, const double* src_
   if (t >= g.off[8] || !colour_decode(g, t, i, j, k)) return;
   const size_t Np = g.off[8];
   const double* src = src_all + (size_t)s * kPlanes * Np;
-  T* dst = dst_all + (size_t)s * kPlanes * Np + tiled(t, 0, kPlanes);
+  T* dst = dst_all + (size_t)s * kPlanes * Np + sidx<T>(t, 0, kPlanes);
   for (int dz = -1; dz <= 1; ++dz)
     for (int dy = -1; dy <= 1; ++dy)
       for (int dx = -1; dx <= 1; ++dx) {
@@ -39,16 +39,16 @@ __global__ __launch_bounds__(kBlock) void k_transpose(Geom g, const double* src_
         if (ii >= 0 && jj >= 0 && kk >= 0 && ii < g.nx && jj < g.ny && kk < g.nz) {
           const int tw = colour_encode(g, ii, jj, kk);
           const int ob = nb_index(-dx, -dy, -dz);
-          const double* w = src + tiled(tw, ob * 4, kPlanes);
-          b00 = w[0];
-          b01 = w[kTile];
-          b10 = w[2 * kTile];
-          b11 = w[3 * kTile];
+          const double* w = src + sidx<double>(tw, 0, kPlanes);
+          b00 = w[soff<double>(ob * 4)];
+          b01 = w[soff<double>(ob * 4 + 1)];
+          b10 = w[soff<double>(ob * 4 + 2)];
+          b11 = w[soff<double>(ob * 4 + 3)];
         }
-        dst[(o * 4 + 0) * kTile] = (T)b00;
-        dst[(o * 4 + 1) * kTile] = (T)b10;
-        dst[(o * 4 + 2) * kTile] = (T)b01;
-        dst[(o * 4 + 3) * kTile] = (T)b11;
+        dst[soff<T>(o * 4 + 0)] = (T)b00;
+        dst[soff<T>(o * 4 + 1)] = (T)b10;
+        dst[soff<T>(o * 4 + 2)] = (T)b01;
+        dst[soff<T>(o * 4 + 3)] = (T)b11;
       }
 }
 

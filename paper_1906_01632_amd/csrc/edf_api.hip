@@ -25,11 +25,11 @@ struct Level {
   double* phi = nullptr;  // [S][cells]
   double* K = nullptr;
   double* u = nullptr;    // state on this level [S][N][2] (level 0: the Newton iterate)
-  double* A64 = nullptr;  // [S][108][N] colour-major (level 0: exact Jacobian)
+  double* A64 = nullptr;  // [S][Np x 108] colour-major, packed (level 0: exact Jacobian)
   double* AV64 = nullptr; // level 0 in FP64 mode: the V-cycle matrix
   float* A32 = nullptr;   // V-cycle matrix in mixed mode
-  void* Dinv = nullptr;   // [S][4][N], V-cycle precision
-  void* x = nullptr;      // V-cycle vectors [S][N][2], V-cycle precision
+  void* Dinv = nullptr;   // [S][Np x 4], V-cycle precision
+  void* x = nullptr;      // V-cycle vectors [S][Np][2] colour-major, V-cycle precision
   void* b = nullptr;
   void* r = nullptr;
 };
@@ -231,21 +231,17 @@ edf_status alloc_group(edf_problem* pb, Group& G) {
       if ((s = dalloc(pb, &L.A32, S * kPlanes * Np))) return s;
     if (l == 0 && (!mx || coarsest))
       if ((s = dalloc(pb, &L.AV64, S * kPlanes * Np))) return s;
+    char* q;
     if (!coarsest) {
-      char* q;
       if ((s = dalloc(pb, &q, S * 4 * Np * tsz))) return s;
       L.Dinv = q;
-      if ((s = dalloc(pb, &q, S * 2 * N * tsz))) return s;
+      if ((s = dalloc(pb, &q, S * 2 * Np * tsz))) return s;
       L.r = q;
     }
-    // V-cycle b and x: level 0 in FP64 mode uses the Krylov vectors directly
-    if (l > 0 || mx) {
-      char* q;
-      if ((s = dalloc(pb, &q, S * 2 * N * tsz))) return s;
-      L.b = q;
-      if ((s = dalloc(pb, &q, S * 2 * N * tsz))) return s;
-      L.x = q;
-    }
+    if ((s = dalloc(pb, &q, S * 2 * Np * tsz))) return s;
+    L.b = q;
+    if ((s = dalloc(pb, &q, S * 2 * Np * tsz))) return s;
+    L.x = q;
     nx = (nx - 1) / 2 + 1;
     ny = (ny - 1) / 2 + 1;
     nz = (nz - 1) / 2 + 1;
@@ -410,16 +406,9 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
   hipStream_t st = pb->st;
   const int S = G.S;
   const int nu1 = pb->opts.nu_pre, nu2 = pb->opts.nu_post;
-  T* b0;
-  T* x0;
-  if constexpr (sizeof(T) == sizeof(double)) {
-    b0 = (T*)in;
-    x0 = (T*)out;
-  } else {
-    b0 = (T*)G.lv[0].b;
-    x0 = (T*)G.lv[0].x;
-    launch_cast_f64_to_f32(in, (float*)b0, G.n, S, mask, st);
-  }
+  T* b0 = (T*)G.lv[0].b;
+  T* x0 = (T*)G.lv[0].x;
+  launch_to_colour<T>(G.lv[0].g, in, b0, S, mask, st);
   // per vertex of the colour: 108 stencil + 4 block-inverse entries, b, x read and written
   auto smooth = [&](const Level& L, int c, const T* b, T* x) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -433,7 +422,7 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
   };
   // levels from l0 on run in one fused launch (one workgroup per sample)
   const int l0 = G.fuse_from >= 0 ? G.fuse_from : default_fuse_from(G);
-  if (l0 > 0) launch_fill<T>(x0, G.n, S, mask, T(0), st);
+  if (l0 > 0) launch_fill<T>(x0, 2 * (size_t)G.lv[0].g.off[8], S, mask, T(0), st);
   for (int l = 0; l < l0; ++l) {
     Level& L = G.lv[l];
     T *b, *x;
@@ -472,7 +461,7 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
     for (int it = 0; it < nu2; ++it)
       for (int c = 7; c >= 0; --c) smooth(L, c, b, x);
   }
-  if constexpr (sizeof(T) != sizeof(double)) launch_cast_f32_to_f64((const float*)x0, out, G.n, S, mask, st);
+  launch_from_colour<T>(G.lv[0].g, x0, out, S, mask, st);
 }
 
 void precondition(edf_problem* pb, Group& G, const double* in, double* out, const int* mask) {

@@ -94,16 +94,16 @@ void launch_prolong(const Geom& gf, const Geom& gc, const T* xc, T* xf, int S, c
                     hipStream_t st);
 template <typename T>
 void launch_fill(T* x, size_t per_sample, int S, const int* mask, T value, hipStream_t st);
-void launch_cast_f64_to_f32(const double* a, float* b, size_t per_sample, int S, const int* mask,
-                            hipStream_t st);
-void launch_cast_f32_to_f64(const float* a, double* b, size_t per_sample, int S, const int* mask,
-                            hipStream_t st);
+// finest-level V-cycle entry and exit: FP64 natural [N][2] <-> T colour-major [Np][2]
+template <typename T>
+void launch_to_colour(const Geom& g, const double* in, T* out, int S, const int* mask,
+                      hipStream_t st);
+template <typename T>
+void launch_from_colour(const Geom& g, const T* in, double* out, int S, const int* mask,
+                        hipStream_t st);
 void launch_coarse_dense(const Geom& g, const double* A, double* M, int S, const int* mask,
                          hipStream_t st);
 void launch_gauss_jordan(int n, double* M, int* piv, int* status, int S, const int* mask,
-                         hipStream_t st);
-template <typename T>
-void launch_coarse_apply(int n, const double* Minv, const T* b, T* x, int S, const int* mask,
                          hipStream_t st);
 
 // The bottom of a V-cycle run by one workgroup per sample: levels 0..n-2 of this

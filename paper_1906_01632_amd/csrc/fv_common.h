@@ -12,9 +12,44 @@ __host__ __device__ constexpr int nb_index(int dx, int dy, int dz) {
 
 __device__ __forceinline__ int clampi(int a, int lo, int hi) { return a < lo ? lo : (a > hi ? hi : a); }
 
-// index of value p (of P per vertex) at colour-major position t in a tiled array
-__host__ __device__ __forceinline__ size_t tiled(int t, int p, int P) {
-  return ((size_t)(t / kTile) * P + p) * kTile + (t % kTile);
+// Layout of per-vertex coefficient arrays (stencils: P = 108, block inverses: P = 4):
+// colour-major positions in tiles of kTile; inside a tile the P values of a position
+// are packed W at a time into 16-byte lane vectors (W = 2 doubles or 4 floats), so
+// one load per lane fetches W coefficients and a wave's load is 1 KiB contiguous.
+template <typename T>
+constexpr int kPack = 16 / (int)sizeof(T);
+
+// index of value p (of P per vertex) at colour-major position t
+template <typename T>
+__host__ __device__ __forceinline__ size_t sidx(int t, int p, int P) {
+  constexpr int W = kPack<T>;
+  return ((size_t)(t / kTile) * (P / W) + p / W) * (kTile * W) + (size_t)(t % kTile) * W + p % W;
+}
+
+// offset of value p from value 0 of the same position
+template <typename T>
+__host__ __device__ __forceinline__ size_t soff(int p) {
+  constexpr int W = kPack<T>;
+  return (size_t)(p / W) * (kTile * W) + p % W;
+}
+
+// the 2x2 block (a00, a01, a10, a11) stored at values p..p+3 (p a multiple of 4), as
+// streaming loads: coefficients are read once per sweep and should not evict vectors
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+template <typename T>
+struct Block2 {
+  T a00, a01, a10, a11;
+};
+__device__ __forceinline__ Block2<double> load_block(const double* base, int p) {
+  const nt_d2 u = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(base + soff<double>(p)));
+  const nt_d2 w =
+      __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(base + soff<double>(p + 2)));
+  return {u.x, u.y, w.x, w.y};
+}
+__device__ __forceinline__ Block2<float> load_block(const float* base, int p) {
+  const nt_f4 u = __builtin_nontemporal_load(reinterpret_cast<const nt_f4*>(base + soff<float>(p)));
+  return {u.x, u.y, u.z, u.w};
 }
 
 // colour-major position t -> vertex (i, j, k); false for padding positions

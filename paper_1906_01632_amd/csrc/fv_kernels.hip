@@ -309,8 +309,8 @@ __device__ __forceinline__ void hex_jacobian(const Geom& g, int i, int j, int k,
 template <int EQ, bool FROZEN>
 __device__ __forceinline__ void assemble_row(const Geom& g, const Phys& ph, const double* phi,
                                              const double* K, const double* P, const double* C,
-                                             int i, int j, int k, size_t base, double* A64,
-                                             float* A32) {
+                                             int i, int j, int k, size_t s0, int t,
+                                             double* A64, float* A32) {
   double Ap[27], Ac[27];
 #pragma unroll
   for (int o = 0; o < 27; ++o) {
@@ -343,14 +343,16 @@ __device__ __forceinline__ void assemble_row(const Geom& g, const Phys& ph, cons
       ap = (o == kDiag && EQ == 0) ? 1.0 : 0.0;
       ac = (o == kDiag && EQ == 1) ? 1.0 : 0.0;
     }
-    const size_t q = base + (size_t)(o * 4 + EQ * 2) * kTile;
+    const int pl = o * 4 + EQ * 2;  // (row EQ, column p) and (row EQ, column c)
     if (A64) {
-      A64[q] = ap;
-      A64[q + kTile] = ac;
+      double* a = A64 + s0 + sidx<double>(t, 0, kPlanes);
+      a[soff<double>(pl)] = ap;
+      a[soff<double>(pl + 1)] = ac;
     }
     if (A32) {
-      A32[q] = (float)ap;
-      A32[q + kTile] = (float)ac;
+      float* a = A32 + s0 + sidx<float>(t, 0, kPlanes);
+      a[soff<float>(pl)] = (float)ap;
+      a[soff<float>(pl + 1)] = (float)ac;
     }
   }
 }
@@ -378,11 +380,11 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Geom g, Phys ph0, const dou
   const double2* u = reinterpret_cast<const double2*>(u_all) + (size_t)s * g.N;
   double P[27], C[27];
   load_neighbourhood(g, u, i, j, k, P, C);
-  const size_t base = (size_t)s * kPlanes * g.off[8] + tiled(t, 0, kPlanes);
+  const size_t s0 = (size_t)s * kPlanes * g.off[8];
   if (blockIdx.z == 0)
-    assemble_row<0, FROZEN>(g, ph, phi, K, P, C, i, j, k, base, A64, A32);
+    assemble_row<0, FROZEN>(g, ph, phi, K, P, C, i, j, k, s0, t, A64, A32);
   else
-    assemble_row<1, FROZEN>(g, ph, phi, K, P, C, i, j, k, base, A64, A32);
+    assemble_row<1, FROZEN>(g, ph, phi, K, P, C, i, j, k, s0, t, A64, A32);
 }
 
 void launch_assemble(const Geom& g, const Phys& ph, const double* dts, const double* phi,
@@ -398,7 +400,7 @@ void launch_assemble(const Geom& g, const Phys& ph, const double* dts, const dou
 }
 
 // ---------------------------------------------------------------------------
-// inverses of the 2x2 diagonal blocks, Dinv[s][4][N] (colour-major)
+// inverses of the 2x2 diagonal blocks, Dinv[s][Np x 4] (colour-major, packed)
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_block_inverse(Geom g, const T* A, T* Dinv,
@@ -409,15 +411,16 @@ __global__ __launch_bounds__(kBlock) void k_block_inverse(Geom g, const T* A, T*
   int i, j, k;
   if (t >= g.off[8] || !colour_decode(g, t, i, j, k)) return;
   const size_t Np = g.off[8];
-  const T* a = A + (size_t)s * kPlanes * Np + tiled(t, kDiag * 4, kPlanes);
-  const double a00 = a[0], a01 = a[kTile], a10 = a[2 * kTile], a11 = a[3 * kTile];
+  const T* a = A + (size_t)s * kPlanes * Np + sidx<T>(t, 0, kPlanes);
+  const double a00 = a[soff<T>(kDiag * 4)], a01 = a[soff<T>(kDiag * 4 + 1)],
+               a10 = a[soff<T>(kDiag * 4 + 2)], a11 = a[soff<T>(kDiag * 4 + 3)];
   const double det = a00 * a11 - a01 * a10;
   const double id = det != 0.0 ? 1.0 / det : 0.0;
-  T* d = Dinv + (size_t)s * 4 * Np + tiled(t, 0, 4);
-  d[0] = (T)(a11 * id);
-  d[kTile] = (T)(-a01 * id);
-  d[2 * kTile] = (T)(-a10 * id);
-  d[3 * kTile] = (T)(a00 * id);
+  T* d = Dinv + (size_t)s * 4 * Np + sidx<T>(t, 0, 4);
+  d[soff<T>(0)] = (T)(a11 * id);
+  d[soff<T>(1)] = (T)(-a01 * id);
+  d[soff<T>(2)] = (T)(-a10 * id);
+  d[soff<T>(3)] = (T)(a00 * id);
 }
 
 void launch_block_inverse_f64(const Geom& g, const double* A, double* Dinv, int S,
@@ -459,7 +462,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil_to_natural(Geom g, const dou
   if (v >= g.N) return;
   const int i = v % g.nx, j = (v / g.nx) % g.ny, k = v / (g.nx * g.ny);
   const int t = colour_encode(g, i, j, k);
-  for (int p = 0; p < kPlanes; ++p) out[(size_t)p * g.N + v] = A[tiled(t, p, kPlanes)];
+  for (int p = 0; p < kPlanes; ++p) out[(size_t)p * g.N + v] = A[sidx<double>(t, p, kPlanes)];
 }
 
 void launch_stencil_to_natural(const Geom& g, const double* A, double* out, hipStream_t st) {

@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Geom g, const double* A_all, co
   double acc[2] = {0.0, 0.0};
   int i, j, k;
   if (t < g.off[8] && colour_decode(g, t, i, j, k)) {
-    const double* A = A_all + (size_t)s * kPlanes * Np + tiled(t, 0, kPlanes);
+    const double* A = A_all + (size_t)s * kPlanes * Np + sidx<double>(t, 0, kPlanes);
     const double2* x = reinterpret_cast<const double2*>(x_all) + (size_t)s * N;
     double r0 = 0.0, r1 = 0.0;
 #pragma unroll
@@ -69,10 +69,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Geom g, const double* A_all, co
           const int ii = clampi(i + dx, 0, g.nx - 1);
           const int o = nb_index(dx, dy, dz);
           const double2 xv = x[ii + (size_t)g.nx * (jj + (size_t)g.ny * kk)];
-          r0 += __builtin_nontemporal_load(A + (o * 4 + 0) * kTile) * xv.x +
-                __builtin_nontemporal_load(A + (o * 4 + 1) * kTile) * xv.y;
-          r1 += __builtin_nontemporal_load(A + (o * 4 + 2) * kTile) * xv.x +
-                __builtin_nontemporal_load(A + (o * 4 + 3) * kTile) * xv.y;
+          const Block2<double> a = load_block(A, o * 4);
+          r0 += a.a00 * xv.x + a.a01 * xv.y;
+          r1 += a.a10 * xv.x + a.a11 * xv.y;
         }
       }
     }

@@ -26,21 +26,13 @@ struct V2<float> {
   using type = float2;
 };
 
-// Stencil entries are read once per sweep and never reused from cache: load them
-// as streaming (non-temporal) data so that the vectors stay cached.
-template <typename T>
-__device__ __forceinline__ T stream_load(const T* p) {
-#ifdef EDF_CACHED_STENCIL
-  return *p;
-#else
-  return __builtin_nontemporal_load(p);
-#endif
-}
-
 // ---------------------------------------------------------------------------
-// Per-vertex operations.  Pointers are those of one sample.  They serve both the
-// one-launch-per-sweep kernels (large grids) and the fused kernel that runs the
-// bottom of the V-cycle in one workgroup per sample (small grids).
+// Per-vertex operations.  Pointers are those of one sample; the V-cycle vectors
+// (b, x, r: [Np][2] of T on every level) are in the colour-major order of the
+// stencil rows, so a wave reads and writes its own vertices contiguously and the
+// neighbours of a run of one colour are runs of the neighbouring colours.  The
+// helpers serve both the one-launch-per-sweep kernels (large grids) and the fused
+// kernel that runs the bottom of the V-cycle in one workgroup per sample.
 // ---------------------------------------------------------------------------
 
 // block Gauss-Seidel update of vertex q of colour col: x_v += D_v^{-1} (b - A x)_v
@@ -51,11 +43,9 @@ __device__ __forceinline__ void smooth_vertex(const Geom& g, int col, int q, con
   int i, j, k;
   colour_decode_in(g, col, q, i, j, k);
   const int t = g.off[col] + q;
-  const T* A = A_s + tiled(t, 0, kPlanes);
-  const T2* b = reinterpret_cast<const T2*>(b_s);
+  const T* A = A_s + sidx<T>(t, 0, kPlanes);
   T2* x = reinterpret_cast<T2*>(x_s);
-  const size_t v = i + (size_t)g.nx * (j + (size_t)g.ny * k);
-  T2 bv = b[v];
+  const T2 bv = reinterpret_cast<const T2*>(b_s)[t];
   T r0 = bv.x, r1 = bv.y;
 #pragma unroll
   for (int dz = -1; dz <= 1; ++dz) {
@@ -66,20 +56,18 @@ __device__ __forceinline__ void smooth_vertex(const Geom& g, int col, int q, con
 #pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
         const int ii = clampi(i + dx, 0, g.nx - 1);
-        const int o = nb_index(dx, dy, dz);
-        const T2 xv = x[ii + (size_t)g.nx * (jj + (size_t)g.ny * kk)];
-        r0 -= stream_load(A + (o * 4 + 0) * kTile) * xv.x +
-              stream_load(A + (o * 4 + 1) * kTile) * xv.y;
-        r1 -= stream_load(A + (o * 4 + 2) * kTile) * xv.x +
-              stream_load(A + (o * 4 + 3) * kTile) * xv.y;
+        const T2 xv = x[colour_encode(g, ii, jj, kk)];
+        const Block2<T> a = load_block(A, nb_index(dx, dy, dz) * 4);
+        r0 -= a.a00 * xv.x + a.a01 * xv.y;
+        r1 -= a.a10 * xv.x + a.a11 * xv.y;
       }
     }
   }
-  const T* d = D_s + tiled(t, 0, 4);
-  T2 xv = x[v];
-  xv.x += stream_load(d) * r0 + stream_load(d + kTile) * r1;
-  xv.y += stream_load(d + 2 * kTile) * r0 + stream_load(d + 3 * kTile) * r1;
-  x[v] = xv;
+  const Block2<T> d = load_block(D_s + sidx<T>(t, 0, 4), 0);
+  T2 xv = x[t];
+  xv.x += d.a00 * r0 + d.a01 * r1;
+  xv.y += d.a10 * r0 + d.a11 * r1;
+  x[t] = xv;
 }
 
 // residual r = b - A x at colour-major position t, zero in Dirichlet rows (their
@@ -90,7 +78,7 @@ __device__ __forceinline__ void residual_vertex(const Geom& g, int t, const T* A
   using T2 = typename V2<T>::type;
   int i, j, k;
   if (!colour_decode(g, t, i, j, k)) return;
-  const T* A = A_s + tiled(t, 0, kPlanes);
+  const T* A = A_s + sidx<T>(t, 0, kPlanes);
   const T2* x = reinterpret_cast<const T2*>(x_s);
   T a0 = 0, a1 = 0;  // (A x)_v; b is read after the sweep over the neighbours
 #pragma unroll 1  // one z-plane of neighbours at a time keeps the register count low
@@ -102,32 +90,30 @@ __device__ __forceinline__ void residual_vertex(const Geom& g, int t, const T* A
 #pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
         const int ii = clampi(i + dx, 0, g.nx - 1);
-        const int o = nb_index(dx, dy, dz);
-        const T2 xv = x[ii + (size_t)g.nx * (jj + (size_t)g.ny * kk)];
-        a0 += stream_load(A + (o * 4 + 0) * kTile) * xv.x +
-              stream_load(A + (o * 4 + 1) * kTile) * xv.y;
-        a1 += stream_load(A + (o * 4 + 2) * kTile) * xv.x +
-              stream_load(A + (o * 4 + 3) * kTile) * xv.y;
+        const T2 xv = x[colour_encode(g, ii, jj, kk)];
+        const Block2<T> a = load_block(A, nb_index(dx, dy, dz) * 4);
+        a0 += a.a00 * xv.x + a.a01 * xv.y;
+        a1 += a.a10 * xv.x + a.a11 * xv.y;
       }
     }
   }
-  const size_t v = i + (size_t)g.nx * (j + (size_t)g.ny * k);
-  const T2 bv = reinterpret_cast<const T2*>(b_s)[v];
+  const T2 bv = reinterpret_cast<const T2*>(b_s)[t];
   double cD;
   T2 out;
   out.x = is_pin(g, i, j, k) ? T(0) : bv.x - a0;
   out.y = is_cdir(g, i, j, k, cD) ? T(0) : bv.y - a1;
-  reinterpret_cast<T2*>(r_s)[v] = out;
+  reinterpret_cast<T2*>(r_s)[t] = out;
 }
 
-// restriction b_c = (1/8) P^T r_f of the scaled residual at coarse vertex v (the 1/8
-// converts the fine row scaling to the coarse one: rows are scaled by 1/(hx hy hz));
-// also clears x_c
+// restriction b_c = (1/8) P^T r_f of the scaled residual at coarse position t (the
+// 1/8 converts the fine row scaling to the coarse one: rows are scaled by
+// 1/(hx hy hz)); also clears x_c
 template <typename T>
-__device__ __forceinline__ void restrict_vertex(const Geom& gf, const Geom& gc, int v,
+__device__ __forceinline__ void restrict_vertex(const Geom& gf, const Geom& gc, int t,
                                                 const T* rf_s, T* bc_s, T* xc_s) {
   using T2 = typename V2<T>::type;
-  const int I = v % gc.nx, J = (v / gc.nx) % gc.ny, K = v / (gc.nx * gc.ny);
+  int I, J, K;
+  if (!colour_decode(gc, t, I, J, K)) return;
   const T2* rf = reinterpret_cast<const T2*>(rf_s);
   T a0 = 0, a1 = 0;
 #pragma unroll
@@ -143,7 +129,7 @@ __device__ __forceinline__ void restrict_vertex(const Geom& gf, const Geom& gc, 
         const int i = 2 * I + dx;
         if (i < 0 || i >= gf.nx) continue;
         const T w = (dx ? T(0.5) : T(1)) * (dy ? T(0.5) : T(1)) * (dz ? T(0.5) : T(1));
-        const T2 r = rf[i + (size_t)gf.nx * (j + (size_t)gf.ny * k)];
+        const T2 r = rf[colour_encode(gf, i, j, k)];
         a0 += w * r.x;
         a1 += w * r.y;
       }
@@ -153,20 +139,21 @@ __device__ __forceinline__ void restrict_vertex(const Geom& gf, const Geom& gc, 
   T2 out;
   out.x = is_pin(gc, I, J, K) ? T(0) : T(0.125) * a0;
   out.y = is_cdir(gc, I, J, K, cD) ? T(0) : T(0.125) * a1;
-  reinterpret_cast<T2*>(bc_s)[v] = out;
+  reinterpret_cast<T2*>(bc_s)[t] = out;
   T2 z;
   z.x = 0;
   z.y = 0;
-  reinterpret_cast<T2*>(xc_s)[v] = z;
+  reinterpret_cast<T2*>(xc_s)[t] = z;
 }
 
-// prolongation and correction x_f += P x_c (trilinear) at fine vertex v, none in
+// prolongation and correction x_f += P x_c (trilinear) at fine position t, none in
 // Dirichlet rows
 template <typename T>
-__device__ __forceinline__ void prolong_vertex(const Geom& gf, const Geom& gc, int v,
+__device__ __forceinline__ void prolong_vertex(const Geom& gf, const Geom& gc, int t,
                                                const T* xc_s, T* xf_s) {
   using T2 = typename V2<T>::type;
-  const int i = v % gf.nx, j = (v / gf.nx) % gf.ny, k = v / (gf.nx * gf.ny);
+  int i, j, k;
+  if (!colour_decode(gf, t, i, j, k)) return;
   const T2* xc = reinterpret_cast<const T2*>(xc_s);
   const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1, k0 = k >> 1,
             k1 = (k + 1) >> 1;
@@ -177,17 +164,17 @@ __device__ __forceinline__ void prolong_vertex(const Geom& gf, const Geom& gc, i
     const int I = (c & 1) ? i1 : i0, J = (c & 2) ? j1 : j0, K = (c & 4) ? k1 : k0;
     // the second parent of an even index coincides with the first: count it once
     if (((c & 1) && !(i & 1)) || ((c & 2) && !(j & 1)) || ((c & 4) && !(k & 1))) continue;
-    const T2 e = xc[I + (size_t)gc.nx * (J + (size_t)gc.ny * K)];
+    const T2 e = xc[colour_encode(gc, I, J, K)];
     const T w = wi * wj * wk;
     a0 += w * e.x;
     a1 += w * e.y;
   }
   T2* xf = reinterpret_cast<T2*>(xf_s);
-  T2 x = xf[v];
+  T2 x = xf[t];
   double cD;
   if (!is_pin(gf, i, j, k)) x.x += a0;
   if (!is_cdir(gf, i, j, k, cD)) x.y += a1;
-  xf[v] = x;
+  xf[t] = x;
 }
 
 // ---------------------------------------------------------------------------
@@ -200,9 +187,9 @@ __global__ __launch_bounds__(kBlock) void k_smooth(Geom g, int col, const T* A_a
   if (mask && !mask[s]) return;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= g.cnt[col]) return;
-  const size_t N = g.N, Np = g.off[8];
+  const size_t Np = g.off[8];
   smooth_vertex<T>(g, col, q, A_all + (size_t)s * kPlanes * Np, Dinv_all + (size_t)s * 4 * Np,
-                   b_all + (size_t)s * 2 * N, x_all + (size_t)s * 2 * N);
+                   b_all + (size_t)s * 2 * Np, x_all + (size_t)s * 2 * Np);
 }
 
 template <typename T>
@@ -225,9 +212,9 @@ __global__ __launch_bounds__(kBlock) void k_residual(Geom g, const T* A_all, con
   if (mask && !mask[s]) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= g.off[8]) return;
-  const size_t N = g.N, Np = g.off[8];
-  residual_vertex<T>(g, t, A_all + (size_t)s * kPlanes * Np, b_all + (size_t)s * 2 * N,
-                     x_all + (size_t)s * 2 * N, r_all + (size_t)s * 2 * N);
+  const size_t Np = g.off[8];
+  residual_vertex<T>(g, t, A_all + (size_t)s * kPlanes * Np, b_all + (size_t)s * 2 * Np,
+                     x_all + (size_t)s * 2 * Np, r_all + (size_t)s * 2 * Np);
 }
 
 template <typename T>
@@ -242,16 +229,16 @@ __global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, const T* 
                                                      T* xc_all, const int* mask) {
   const int s = blockIdx.y;
   if (mask && !mask[s]) return;
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= gc.N) return;
-  restrict_vertex<T>(gf, gc, v, rf_all + (size_t)s * 2 * gf.N, bc_all + (size_t)s * 2 * gc.N,
-                     xc_all + (size_t)s * 2 * gc.N);
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= gc.off[8]) return;
+  restrict_vertex<T>(gf, gc, t, rf_all + (size_t)s * 2 * gf.off[8],
+                     bc_all + (size_t)s * 2 * gc.off[8], xc_all + (size_t)s * 2 * gc.off[8]);
 }
 
 template <typename T>
 void launch_restrict(const Geom& gf, const Geom& gc, const T* rf, T* bc, T* xc, int S,
                      const int* mask, hipStream_t st) {
-  dim3 grid(ceil_div(gc.N, kBlock), S);
+  dim3 grid(ceil_div(gc.off[8], kBlock), S);
   hipLaunchKernelGGL(k_restrict<T>, grid, dim3(kBlock), 0, st, gf, gc, rf, bc, xc, mask);
 }
 
@@ -260,15 +247,16 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Geom gf, Geom gc, const T* x
                                                     const int* mask) {
   const int s = blockIdx.y;
   if (mask && !mask[s]) return;
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= gf.N) return;
-  prolong_vertex<T>(gf, gc, v, xc_all + (size_t)s * 2 * gc.N, xf_all + (size_t)s * 2 * gf.N);
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= gf.off[8]) return;
+  prolong_vertex<T>(gf, gc, t, xc_all + (size_t)s * 2 * gc.off[8],
+                    xf_all + (size_t)s * 2 * gf.off[8]);
 }
 
 template <typename T>
 void launch_prolong(const Geom& gf, const Geom& gc, const T* xc, T* xf, int S, const int* mask,
                     hipStream_t st) {
-  dim3 grid(ceil_div(gf.N, kBlock), S);
+  dim3 grid(ceil_div(gf.off[8], kBlock), S);
   hipLaunchKernelGGL(k_prolong<T>, grid, dim3(kBlock), 0, st, gf, gc, xc, xf, mask);
 }
 
@@ -292,26 +280,50 @@ void launch_fill(T* x, size_t per_sample, int S, const int* mask, T value, hipSt
   hipLaunchKernelGGL(k_fill<T>, grid, dim3(kBlock), 0, st, x, per_sample, value, mask);
 }
 
-template <typename A, typename B>
-__global__ __launch_bounds__(kBlock) void k_cast(const A* a, B* b, size_t n, const int* mask) {
+// V-cycle entry and exit on the finest level: Krylov vectors (FP64, natural vertex
+// order [N][2]) to and from the V-cycle vectors (T, colour-major [Np][2])
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_to_colour(Geom g, const double* in_all, T* out_all,
+                                                      const int* mask) {
   const int s = blockIdx.y;
   if (mask && !mask[s]) return;
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
-       e += (size_t)gridDim.x * blockDim.x)
-    b[(size_t)s * n + e] = (B)a[(size_t)s * n + e];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int i, j, k;
+  if (t >= g.off[8] || !colour_decode(g, t, i, j, k)) return;
+  const size_t v = i + (size_t)g.nx * (j + (size_t)g.ny * k);
+  const double2 a = reinterpret_cast<const double2*>(in_all)[(size_t)s * g.N + v];
+  typename V2<T>::type b;
+  b.x = (T)a.x;
+  b.y = (T)a.y;
+  reinterpret_cast<typename V2<T>::type*>(out_all)[(size_t)s * g.off[8] + t] = b;
 }
 
-void launch_cast_f64_to_f32(const double* a, float* b, size_t per_sample, int S, const int* mask,
-                            hipStream_t st) {
-  const int nb = (int)std::min<size_t>((per_sample + kBlock - 1) / kBlock, 4096);
-  hipLaunchKernelGGL((k_cast<double, float>), dim3(nb, S), dim3(kBlock), 0, st, a, b, per_sample,
-                     mask);
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_from_colour(Geom g, const T* in_all, double* out_all,
+                                                        const int* mask) {
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= g.N) return;
+  const int i = v % g.nx, j = (v / g.nx) % g.ny, k = v / (g.nx * g.ny);
+  const typename V2<T>::type a =
+      reinterpret_cast<const typename V2<T>::type*>(in_all)[(size_t)s * g.off[8] +
+                                                           colour_encode(g, i, j, k)];
+  reinterpret_cast<double2*>(out_all)[(size_t)s * g.N + v] = make_double2((double)a.x, (double)a.y);
 }
-void launch_cast_f32_to_f64(const float* a, double* b, size_t per_sample, int S, const int* mask,
-                            hipStream_t st) {
-  const int nb = (int)std::min<size_t>((per_sample + kBlock - 1) / kBlock, 4096);
-  hipLaunchKernelGGL((k_cast<float, double>), dim3(nb, S), dim3(kBlock), 0, st, a, b, per_sample,
-                     mask);
+
+template <typename T>
+void launch_to_colour(const Geom& g, const double* in, T* out, int S, const int* mask,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_to_colour<T>, dim3(ceil_div(g.off[8], kBlock), S), dim3(kBlock), 0, st, g,
+                     in, out, mask);
+}
+
+template <typename T>
+void launch_from_colour(const Geom& g, const T* in, double* out, int S, const int* mask,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_from_colour<T>, dim3(ceil_div(g.N, kBlock), S), dim3(kBlock), 0, st, g,
+                     in, out, mask);
 }
 
 // ---------------------------------------------------------------------------
@@ -326,7 +338,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_dense(Geom g, const double* A
   int i, j, k;
   if (t >= g.off[8] || !colour_decode(g, t, i, j, k)) return;
   const size_t N = g.N, n = 2 * N;
-  const double* A = A_all + (size_t)s * kPlanes * g.off[8] + tiled(t, 0, kPlanes);
+  const double* A = A_all + (size_t)s * kPlanes * g.off[8] + sidx<double>(t, 0, kPlanes);
   double* M = M_all + (size_t)s * n * n;
   const size_t v = i + (size_t)g.nx * (j + (size_t)g.ny * k);
   for (int dz = -1; dz <= 1; ++dz)
@@ -338,7 +350,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_dense(Geom g, const double* A
         const int o = nb_index(dx, dy, dz);
         for (int e = 0; e < 2; ++e)
           for (int var = 0; var < 2; ++var)
-            M[(2 * v + e) * n + 2 * w + var] = A[(o * 4 + e * 2 + var) * kTile];
+            M[(2 * v + e) * n + 2 * w + var] = A[soff<double>(o * 4 + e * 2 + var)];
       }
 }
 
@@ -444,31 +456,6 @@ void launch_gauss_jordan(int n, double* M, int* piv, int* status, int S, const i
   hipLaunchKernelGGL(k_gauss_jordan, dim3(S), dim3(kGJThreads), 0, st, n, M, piv, status, mask);
 }
 
-// x = M^{-1} b: one wave per row, lanes stride the columns
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_coarse_apply(int n, const double* Minv_all, const T* b_all,
-                                                         T* x_all, const int* mask) {
-  const int s = blockIdx.y;
-  if (mask && !mask[s]) return;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int row = blockIdx.x * (kBlock / 64) + wave;
-  if (row >= n) return;
-  const double* Mr = Minv_all + (size_t)s * n * n + (size_t)row * n;
-  const T* b = b_all + (size_t)s * n;
-  double acc = 0.0;
-  for (int j = lane; j < n; j += 64) acc += Mr[j] * (double)b[j];
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-  if (lane == 0) x_all[(size_t)s * n + row] = (T)acc;
-}
-
-template <typename T>
-void launch_coarse_apply(int n, const double* Minv, const T* b, T* x, int S, const int* mask,
-                         hipStream_t st) {
-  dim3 grid(ceil_div(n, kBlock / 64), S);
-  hipLaunchKernelGGL(k_coarse_apply<T>, grid, dim3(kBlock), 0, st, n, Minv, b, x, mask);
-}
-
 // ---------------------------------------------------------------------------
 // bottom of the V-cycle in one launch: one workgroup per sample runs the smoothed
 // levels l0..n-2 of F and the dense coarse solve on level n-1, with workgroup
@@ -483,12 +470,12 @@ __global__ __launch_bounds__(kFusedThreads) void k_vcycle_bottom(FusedLevels<T> 
   const int tid = threadIdx.x, nt = blockDim.x;
   auto A = [&](int l) { return F.A[l] + (size_t)s * kPlanes * F.g[l].off[8]; };
   auto D = [&](int l) { return F.D[l] + (size_t)s * 4 * F.g[l].off[8]; };
-  auto X = [&](int l) { return F.x[l] + (size_t)s * 2 * F.g[l].N; };
-  auto B = [&](int l) { return F.b[l] + (size_t)s * 2 * F.g[l].N; };
-  auto Rv = [&](int l) { return F.r[l] + (size_t)s * 2 * F.g[l].N; };
+  auto X = [&](int l) { return F.x[l] + (size_t)s * 2 * F.g[l].off[8]; };
+  auto B = [&](int l) { return F.b[l] + (size_t)s * 2 * F.g[l].off[8]; };
+  auto Rv = [&](int l) { return F.r[l] + (size_t)s * 2 * F.g[l].off[8]; };
   const int last = F.n - 1;
   // x = 0 on the first fused level (the finer levels' restriction clears the others)
-  for (int e = tid; e < 2 * F.g[0].N; e += nt) X(0)[e] = T(0);
+  for (int e = tid; e < 2 * F.g[0].off[8]; e += nt) X(0)[e] = T(0);
   __syncthreads();
   for (int l = 0; l < last; ++l) {
     const Geom& g = F.g[l];
@@ -499,27 +486,37 @@ __global__ __launch_bounds__(kFusedThreads) void k_vcycle_bottom(FusedLevels<T> 
       }
     for (int t = tid; t < g.off[8]; t += nt) residual_vertex<T>(g, t, A(l), B(l), X(l), Rv(l));
     __syncthreads();
-    for (int v = tid; v < F.g[l + 1].N; v += nt)
-      restrict_vertex<T>(g, F.g[l + 1], v, Rv(l), B(l + 1), X(l + 1));
+    for (int t = tid; t < F.g[l + 1].off[8]; t += nt)
+      restrict_vertex<T>(g, F.g[l + 1], t, Rv(l), B(l + 1), X(l + 1));
     __syncthreads();
   }
-  {  // coarsest level: x = M^{-1} b, one wave per row
+  {  // coarsest level: x = M^{-1} b, one wave per row; M is in the natural unknown
+     // order 2v + var, so b is gathered into that order first
+    __shared__ double bn[kMaxCoarse];
+    const Geom& gc = F.g[last];
     const int n = F.nc, lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
     const double* Minv = F.Minv + (size_t)s * n * n;
     const T* b = B(last);
     T* x = X(last);
+    auto pos = [&](int e) {  // natural unknown e -> colour-major unknown
+      const int v = e >> 1;
+      const int i = v % gc.nx, j = (v / gc.nx) % gc.ny, k = v / (gc.nx * gc.ny);
+      return 2 * colour_encode(gc, i, j, k) + (e & 1);
+    };
+    for (int e = tid; e < n; e += nt) bn[e] = (double)b[pos(e)];
+    __syncthreads();
     for (int row = wave; row < n; row += nw) {
       double acc = 0.0;
-      for (int j = lane; j < n; j += 64) acc += Minv[(size_t)row * n + j] * (double)b[j];
+      for (int j = lane; j < n; j += 64) acc += Minv[(size_t)row * n + j] * bn[j];
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-      if (lane == 0) x[row] = (T)acc;
+      if (lane == 0) x[pos(row)] = (T)acc;
     }
     __syncthreads();
   }
   for (int l = last - 1; l >= 0; --l) {
     const Geom& g = F.g[l];
-    for (int v = tid; v < g.N; v += nt) prolong_vertex<T>(g, F.g[l + 1], v, X(l + 1), X(l));
+    for (int t = tid; t < g.off[8]; t += nt) prolong_vertex<T>(g, F.g[l + 1], t, X(l + 1), X(l));
     __syncthreads();
     for (int it = 0; it < F.nu2; ++it)
       for (int c = 7; c >= 0; --c) {
@@ -545,8 +542,10 @@ void launch_vcycle_bottom(const FusedLevels<T>& F, int S, const int* mask, hipSt
   template void launch_prolong<T>(const Geom&, const Geom&, const T*, T*, int, const int*,       \
                                   hipStream_t);                                                  \
   template void launch_fill<T>(T*, size_t, int, const int*, T, hipStream_t);                     \
-  template void launch_coarse_apply<T>(int, const double*, const T*, T*, int, const int*,        \
-                                       hipStream_t);                                             \
+  template void launch_to_colour<T>(const Geom&, const double*, T*, int, const int*,             \
+                                    hipStream_t);                                                \
+  template void launch_from_colour<T>(const Geom&, const T*, double*, int, const int*,           \
+                                      hipStream_t);                                              \
   template void launch_vcycle_bottom<T>(const FusedLevels<T>&, int, const int*, hipStream_t);
 EDF_INST(double)
 EDF_INST(float)
