@@ -84,7 +84,7 @@ def cpu_baseline(wl, phys, budget_s=20.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="qmc512_mixedres")
     ap.add_argument("--precision", choices=["f64", "mixed"], default=None)
@@ -120,7 +120,7 @@ def main():
     prec = args.precision or wl.precision
     phys = synth.physics(wl.field_model)
     groups = [(g.nx, g.ny, g.nz, g.levels, g.samples) for g in wl.groups]
-    opts = dict(newton_rtol=wl.newton_rtol, lin_rtol=1e-6, lin_max_it=200, newton_max_it=20,
+    opts = dict(newton_rtol=wl.newton_rtol, lin_rtol=1e-6, lin_max_it=100, newton_max_it=20,
                 precision=PREC_MIXED if prec == "mixed" else PREC_F64, check_every=1,
                 forcing=args.forcing)
     log(f"workload {wl.name}: groups {groups}, precision {prec}")
@@ -176,7 +176,8 @@ def main():
         "data": "synthetic (seeded lattice parameters; no dataset)",
         "config": {"workload": wl.name, "groups": [list(g) for g in groups], "samples": S,
                    "dt_s": wl.dt, "precision": prec, "newton_rtol": wl.newton_rtol,
-                   "lin_rtol": 1e-6, "forcing": "eisenstat-walker" if args.forcing else "fixed",
+                   "lin_rtol": 1e-6, "lin_max_it": 100,
+                   "forcing": "eisenstat-walker" if args.forcing else "fixed",
                    "fused_bottom_from_level": tuning},
         "dof_timesteps_per_s": dofs * args.steps / el,
         "solver": {"newton_its_per_step": newton, "bicgstab_its_per_newton": lin,

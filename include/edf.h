@@ -153,7 +153,8 @@ edf_status edf_get_state(edf_problem* pb, int32_t sample, double* pc, int32_t is
 /* Exactly one implicit-Euler step of length dt [s] for every sample (Section 2.3),
  * taken as 2^h equal implicit-Euler sub-steps of dt / 2^h (stats.substeps = 2^h).
  * h starts at the value that worked for the sample in its previous step (0 at
- * first; lowered by one after three steps without a retry).  A sample whose Newton
+ * first; lowered by one after w steps without a retry, where w = 3 and doubles, up
+ * to 64, whenever such a lowered start fails).  A sample whose Newton
  * iteration fails (iteration limit, no 100-fold residual reduction after 8
  * iterations, a non-finite or 1e4-fold grown residual, a converged state with c
  * outside [-0.05, 1.05], or, while h < opts.dt_max_halvings, a Newton system whose

@@ -53,7 +53,9 @@ struct Group {
   int n_active = 0;  // samples active in the current Krylov chunk (known at chunk start)
   int fuse_from = -1;  // levels from here on run in the fused launch (-1: not chosen yet)
   std::vector<double> tune_ms;  // V-cycle time per candidate fuse_from (autotuning)
-  std::vector<int> h_start, clean;  // per sample: halvings to start the next step with
+  // per sample: halvings to start the next step with, steps since the last retry,
+  // steps to wait before trying one halving less, whether this step is such a try
+  std::vector<int> h_start, clean, wait, probing;
   // adjoint buffers (allocated on first use)
   double* traj = nullptr;      // [S][traj_cap][n]: states at the start of every step
   size_t traj_cap = 0;
@@ -368,14 +370,16 @@ edf_status prof_flush(edf_problem* pb) {
   return EDF_OK;
 }
 
-// algorithmic bytes of one V-cycle per sample: on every smoothed level, 3 stencil
-// sweeps (pre-smoothing, residual, post-smoothing), 2 block-inverse reads and 12
-// vector passes (b and x in and out per sweep, residual out and in, correction), plus
-// the coarse right-hand side and solution and the dense coarse inverse
-double vcycle_bytes(const Group& G, size_t tsz) {
+// algorithmic bytes of one V-cycle per sample: on every smoothed level, nu1 + nu2 + 1
+// stencil sweeps (smoothing sweeps and the residual), nu1 + nu2 block-inverse reads
+// and 3 (nu1 + nu2) + 6 vector passes (b, x in and x out per smoothing sweep; b, x
+// in and r out for the residual; r into the restriction; x in and out for the
+// correction), plus the coarse right-hand side and solution and the dense inverse
+double vcycle_bytes(const Group& G, size_t tsz, int nu1, int nu2) {
+  const double sw = nu1 + nu2;
   double b = 0;
   for (int l = 0; l + 1 < G.L; ++l)
-    b += (double)G.lv[l].g.N * (3.0 * kPlanes + 2.0 * 4 + 12.0 * 2) * tsz;
+    b += (double)G.lv[l].g.N * ((sw + 1.0) * kPlanes + sw * 4 + (3.0 * sw + 6.0) * 2) * tsz;
   const double nc = G.n_coarse;
   return b + nc * nc * 8.0 + 2.0 * nc * tsz;
 }
@@ -467,7 +471,8 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
 void precondition(edf_problem* pb, Group& G, const double* in, double* out, const int* mask) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const size_t tsz = mixed(pb) ? sizeof(float) : sizeof(double);
-  if (prof_pair(pb, e0, e1, vcycle_bytes(G, tsz) * G.n_active, 1)) (void)hipEventRecord(e0, pb->st);
+  const double bytes = vcycle_bytes(G, tsz, pb->opts.nu_pre, pb->opts.nu_post) * G.n_active;
+  if (prof_pair(pb, e0, e1, bytes, 1)) (void)hipEventRecord(e0, pb->st);
   if (mixed(pb))
     vcycle<float>(pb, G, in, out, mask);
   else
@@ -760,6 +765,8 @@ edf_status newton_solve(edf_problem* pb, Group& G, const std::vector<int>& run,
 // sub-steps of DT / 2^h (h <= dt_max_halvings); samples advance in lockstep, one
 // sub-step each per round, and finished samples are masked out.
 // ---------------------------------------------------------------------------
+constexpr int kFirstWait = 3, kMaxWait = 64;
+
 edf_status macro_step(edf_problem* pb, Group& G, double DT) {
   hipStream_t st = pb->st;
   const int S = G.S;
@@ -769,6 +776,8 @@ edf_status macro_step(edf_problem* pb, Group& G, double DT) {
   if ((int)G.h_start.size() != S) {
     G.h_start.assign(S, 0);
     G.clean.assign(S, 0);
+    G.wait.assign(S, kFirstWait);
+    G.probing.assign(S, 0);
   }
   std::vector<int> h(G.h_start), done(S, 0), running(S, 1), ok, why, restore(S), can_retry(S);
   std::vector<double> dts(S);
@@ -815,16 +824,22 @@ edf_status macro_step(edf_problem* pb, Group& G, double DT) {
       launch_masked_copy(G.n, G.u0, G.u, S, G.lsmask, st);
     }
   }
-  // the next step starts with the sub-step count that worked; after three steps
-  // without a retry it tries one halving less
+  // the next step starts with the sub-step count that worked; after `wait` steps
+  // without a retry it tries one halving less, and every such try that fails
+  // doubles `wait` (3 at first, at most kMaxWait)
   for (int s = 0; s < S; ++s) {
     if (G.stats[s].status != EDF_SAMPLE_OK) continue;
     if (h[s] == G.h_start[s]) {
-      if (++G.clean[s] >= 3 && h[s] > 0) {
+      if (G.probing[s]) G.wait[s] = kFirstWait;
+      G.probing[s] = 0;
+      if (++G.clean[s] >= G.wait[s] && h[s] > 0) {
         G.h_start[s] = h[s] - 1;
         G.clean[s] = 0;
+        G.probing[s] = 1;
       }
     } else {
+      if (G.probing[s]) G.wait[s] = std::min(2 * G.wait[s], kMaxWait);
+      G.probing[s] = 0;
       G.h_start[s] = h[s];
       G.clean[s] = 0;
     }

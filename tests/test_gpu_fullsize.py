@@ -13,7 +13,7 @@ from oracle import elder, stats
 pytestmark = pytest.mark.gpu
 
 DT = synth.MONTH_S
-BENCH_OPTS = dict(lin_rtol=1e-6, lin_max_it=200, newton_max_it=20, check_every=1, forcing=1)
+BENCH_OPTS = dict(lin_rtol=1e-6, lin_max_it=100, newton_max_it=20, check_every=1, forcing=1)
 
 
 @pytest.fixture(scope="module", autouse=True)
