@@ -92,6 +92,10 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--forcing", type=int, default=1, choices=[0, 1],
                     help="1: Eisenstat-Walker tolerances for the Newton systems")
+    ap.add_argument("--concurrent-groups", action="store_true",
+                    help="advance the grid groups at the same time (one host thread and stream "
+                         "each); more throughput, but overlapping kernels lengthen the per-launch "
+                         "durations the roofline is computed from")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default fused-bottom levels instead of timing the choices")
     ap.add_argument("--profile-timed-region", action="store_true",
@@ -122,7 +126,7 @@ def main():
     groups = [(g.nx, g.ny, g.nz, g.levels, g.samples) for g in wl.groups]
     opts = dict(newton_rtol=wl.newton_rtol, lin_rtol=1e-6, lin_max_it=100, newton_max_it=20,
                 precision=PREC_MIXED if prec == "mixed" else PREC_F64, check_every=1,
-                forcing=args.forcing)
+                forcing=args.forcing, concurrent_groups=int(args.concurrent_groups))
     log(f"workload {wl.name}: groups {groups}, precision {prec}")
     t = time.perf_counter()
     pb = Problem(phys, groups, opts)
@@ -178,7 +182,8 @@ def main():
                    "dt_s": wl.dt, "precision": prec, "newton_rtol": wl.newton_rtol,
                    "lin_rtol": 1e-6, "lin_max_it": 100,
                    "forcing": "eisenstat-walker" if args.forcing else "fixed",
-                   "fused_bottom_from_level": tuning},
+                   "fused_bottom_from_level": tuning,
+                   "concurrent_groups": bool(args.concurrent_groups)},
         "dof_timesteps_per_s": dofs * args.steps / el,
         "solver": {"newton_its_per_step": newton, "bicgstab_its_per_newton": lin,
                    "failed_samples_last_step": failed},

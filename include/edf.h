@@ -116,7 +116,12 @@ typedef struct {
   int32_t forcing;         /* 0: every Newton system solved to lin_rtol; 1: to the  */
                            /* Eisenstat-Walker forcing term (choice 2, gamma 0.9,   */
                            /* at most 0.1, at least lin_rtol)                       */
-  int32_t reserved[3];     /* must be zero                                         */
+  int32_t concurrent_groups; /* 1: edf_step advances the groups at the same time,  */
+                           /* one host thread and stream each (more throughput;     */
+                           /* kernels of different groups then share the GPU, which */
+                           /* lengthens each one's measured duration); 0: one after */
+                           /* the other                                             */
+  int32_t reserved[2];     /* must be zero                                         */
 } edf_solver_opts;
 
 typedef struct {

@@ -10,7 +10,7 @@ SOURCES = ["fv_kernels.hip", "mg_kernels.hip", "krylov_kernels.hip", "adjoint_ke
 LIB = os.path.join(HERE, "libedf.so")
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread",
     # packed FP32 instructions are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",

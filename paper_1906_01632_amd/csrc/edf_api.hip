@@ -7,7 +7,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "adjoint.h"
@@ -34,8 +36,24 @@ struct Level {
   void* r = nullptr;
 };
 
+// one timed launch (edf_profile)
+struct ProfRec {
+  int pair, kind;  // kind 0: one smoother launch, 1: one whole V-cycle
+  double bytes;    // algorithmic bytes
+};
+
 struct Group {
   edf_group_desc d{};
+  // groups step concurrently, each from its own host thread on its own stream
+  hipStream_t st = nullptr;
+  int* h_int = nullptr;  // pinned host staging [S]
+  double* h_dbl = nullptr;
+  KrylovScalars* h_ks = nullptr;
+  // smoother and V-cycle timing: event pairs around every timed launch
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_ev;
+  std::vector<ProfRec> prof_pending;
+  double prof_count[2] = {0, 0}, prof_ms[2] = {0, 0}, prof_bytes[2] = {0, 0};
   int S = 0, s0 = 0, L = 0;
   std::vector<Level> lv;
   size_t N = 0, n = 0;  // finest vertices, unknowns
@@ -78,21 +96,9 @@ struct edf_problem {
   int S_total = 0;
   bool params_set = false;
   std::string err;
+  std::mutex mu;  // guards err and allocs (groups run on several host threads)
+  int device = 0;  // the device current at creation; every group thread uses it
   std::vector<void*> allocs;
-  // pinned host staging
-  int* h_int = nullptr;
-  double* h_dbl = nullptr;
-  KrylovScalars* h_ks = nullptr;
-  int h_cap = 0;
-  // smoother timing (edf_profile): event pairs around every smoother launch
-  bool prof_on = false;
-  std::vector<hipEvent_t> prof_ev;
-  struct ProfRec {
-    int pair, kind;  // kind 0: one smoother launch, 1: one whole V-cycle
-    double bytes;    // algorithmic bytes
-  };
-  std::vector<ProfRec> prof_pending;
-  double prof_count[2] = {0, 0}, prof_ms[2] = {0, 0}, prof_bytes[2] = {0, 0};
   double* dxi = nullptr;  // parameters on the device [S_total][max(n_xi, 1)]
   // statistics buffers (allocated on first use)
   double* mom_f = nullptr;
@@ -103,26 +109,32 @@ struct edf_problem {
 
 namespace {
 
-#define EDF_TRY(expr)                                              \
-  do {                                                             \
-    hipError_t e_ = (expr);                                        \
-    if (e_ != hipSuccess) {                                        \
-      pb->err = std::string(#expr ": ") + hipGetErrorString(e_);   \
-      return EDF_ERR_HIP;                                          \
-    }                                                              \
+void set_err(edf_problem* pb, const std::string& msg) {
+  if (!pb) return;
+  std::lock_guard<std::mutex> lock(pb->mu);
+  pb->err = msg;
+}
+
+#define EDF_TRY(expr)                                                   \
+  do {                                                                  \
+    hipError_t e_ = (expr);                                             \
+    if (e_ != hipSuccess) {                                             \
+      set_err(pb, std::string(#expr ": ") + hipGetErrorString(e_));     \
+      return EDF_ERR_HIP;                                               \
+    }                                                                   \
   } while (0)
 
-#define EDF_CHECK_LAUNCH()                                               \
-  do {                                                                   \
-    hipError_t e_ = hipGetLastError();                                   \
-    if (e_ != hipSuccess) {                                              \
-      pb->err = std::string("kernel launch: ") + hipGetErrorString(e_);  \
-      return EDF_ERR_HIP;                                                \
-    }                                                                    \
+#define EDF_CHECK_LAUNCH()                                                   \
+  do {                                                                       \
+    hipError_t e_ = hipGetLastError();                                       \
+    if (e_ != hipSuccess) {                                                  \
+      set_err(pb, std::string("kernel launch: ") + hipGetErrorString(e_));   \
+      return EDF_ERR_HIP;                                                    \
+    }                                                                        \
   } while (0)
 
 edf_status fail(edf_problem* pb, edf_status code, const std::string& msg) {
-  if (pb) pb->err = msg;
+  set_err(pb, msg);
   return code;
 }
 
@@ -136,7 +148,10 @@ edf_status dalloc(edf_problem* pb, T** p, size_t count) {
     return fail(pb, EDF_ERR_OOM, "device allocation of " + std::to_string(count * sizeof(T)) +
                                      " bytes failed");
   }
-  pb->allocs.push_back(q);
+  {
+    std::lock_guard<std::mutex> lock(pb->mu);
+    pb->allocs.push_back(q);
+  }
   *p = static_cast<T*>(q);
   return EDF_OK;
 }
@@ -191,21 +206,6 @@ Phys make_phys(const edf_physics& P, const Geom& g, double dt) {
 constexpr double kUpdateFloor = 1e-14;
 
 bool mixed(const edf_problem* pb) { return pb->opts.precision == EDF_PREC_MIXED; }
-
-edf_status ensure_pinned(edf_problem* pb, int count) {
-  if (count <= pb->h_cap) return EDF_OK;
-  if (pb->h_int) (void)hipHostFree(pb->h_int);
-  if (pb->h_dbl) (void)hipHostFree(pb->h_dbl);
-  if (pb->h_ks) (void)hipHostFree(pb->h_ks);
-  pb->h_int = nullptr;
-  pb->h_dbl = nullptr;
-  pb->h_ks = nullptr;
-  EDF_TRY(hipHostMalloc((void**)&pb->h_int, sizeof(int) * count));
-  EDF_TRY(hipHostMalloc((void**)&pb->h_dbl, sizeof(double) * count));
-  EDF_TRY(hipHostMalloc((void**)&pb->h_ks, sizeof(KrylovScalars) * count));
-  pb->h_cap = count;
-  return EDF_OK;
-}
 
 // ---------------------------------------------------------------------------
 // allocation of one group
@@ -292,11 +292,11 @@ edf_status upload_initial(edf_problem* pb, Group& G) {
       }
   for (int s = 0; s < G.S; ++s) {
     EDF_TRY(hipMemcpyAsync(G.u + s * G.n, u.data(), G.n * sizeof(double), hipMemcpyHostToDevice,
-                           pb->st));
+                           G.st));
     EDF_TRY(hipMemcpyAsync(G.u_old + s * G.n, u.data(), G.n * sizeof(double),
-                           hipMemcpyHostToDevice, pb->st));
+                           hipMemcpyHostToDevice, G.st));
   }
-  EDF_TRY(hipStreamSynchronize(pb->st));
+  EDF_TRY(hipStreamSynchronize(G.st));
   return EDF_OK;
 }
 
@@ -317,25 +317,25 @@ edf_status assemble_all(edf_problem* pb, Group& G, const int* mask, const double
   const bool mx = mixed(pb);
   for (int l = 0; l < G.L; ++l) {
     Level& L = G.lv[l];
-    if (l > 0) launch_inject(G.lv[l - 1].g, L.g, G.lv[l - 1].u, L.u, G.S, mask, pb->st);
+    if (l > 0) launch_inject(G.lv[l - 1].g, L.g, G.lv[l - 1].u, L.u, G.S, mask, G.st);
     const bool coarsest = l == G.L - 1;
     if (l == 0)  // exact Jacobian for the Krylov products
-      launch_assemble(L.g, L.ph, dts, L.phi, L.K, L.u, L.A64, nullptr, G.S, mask, pb->st, false);
+      launch_assemble(L.g, L.ph, dts, L.phi, L.K, L.u, L.A64, nullptr, G.S, mask, G.st, false);
     // preconditioner matrix (frozen Darcy flux in the salt rows): FP32 on the smoothed
     // levels in mixed mode, FP64 otherwise and always on the coarsest level
     double* m64 = (mx && !coarsest) ? nullptr : (l == 0 ? L.AV64 : L.A64);
     float* m32 = (mx && !coarsest) ? L.A32 : nullptr;
-    launch_assemble(L.g, L.ph, dts, L.phi, L.K, L.u, m64, m32, G.S, mask, pb->st, true);
+    launch_assemble(L.g, L.ph, dts, L.phi, L.K, L.u, m64, m32, G.S, mask, G.st, true);
     if (!coarsest) {
       if (mx)
-        launch_block_inverse_f32(L.g, L.A32, (float*)L.Dinv, G.S, mask, pb->st);
+        launch_block_inverse_f32(L.g, L.A32, (float*)L.Dinv, G.S, mask, G.st);
       else
-        launch_block_inverse_f64(L.g, m64, (double*)L.Dinv, G.S, mask, pb->st);
+        launch_block_inverse_f64(L.g, m64, (double*)L.Dinv, G.S, mask, G.st);
     }
   }
   const Level& C = G.lv[G.L - 1];
-  launch_coarse_dense(C.g, G.L == 1 ? C.AV64 : C.A64, G.Minv, G.S, mask, pb->st);
-  launch_gauss_jordan(G.n_coarse, G.Minv, G.piv, G.gj_status, G.S, mask, pb->st);
+  launch_coarse_dense(C.g, G.L == 1 ? C.AV64 : C.A64, G.Minv, G.S, mask, G.st);
+  launch_gauss_jordan(G.n_coarse, G.Minv, G.piv, G.gj_status, G.S, mask, G.st);
   EDF_CHECK_LAUNCH();
   return EDF_OK;
 }
@@ -343,30 +343,30 @@ edf_status assemble_all(edf_problem* pb, Group& G, const int* mask, const double
 // ---------------------------------------------------------------------------
 // smoother timing
 // ---------------------------------------------------------------------------
-bool prof_pair(edf_problem* pb, hipEvent_t& a, hipEvent_t& b, double bytes, int kind) {
-  if (!pb->prof_on) return false;
-  const size_t k = pb->prof_pending.size();
-  while (pb->prof_ev.size() < 2 * (k + 1)) {
+bool prof_pair(Group& G, hipEvent_t& a, hipEvent_t& b, double bytes, int kind) {
+  if (!G.prof_on) return false;
+  const size_t k = G.prof_pending.size();
+  while (G.prof_ev.size() < 2 * (k + 1)) {
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return false;
-    pb->prof_ev.push_back(e);
+    G.prof_ev.push_back(e);
   }
-  a = pb->prof_ev[2 * k];
-  b = pb->prof_ev[2 * k + 1];
-  pb->prof_pending.push_back({(int)k, kind, bytes});
+  a = G.prof_ev[2 * k];
+  b = G.prof_ev[2 * k + 1];
+  G.prof_pending.push_back({(int)k, kind, bytes});
   return true;
 }
 
-edf_status prof_flush(edf_problem* pb) {
-  for (auto& r : pb->prof_pending) {
+edf_status prof_flush(edf_problem* pb, Group& G) {
+  for (auto& r : G.prof_pending) {
     float ms = 0.f;
-    EDF_TRY(hipEventSynchronize(pb->prof_ev[2 * r.pair + 1]));
-    EDF_TRY(hipEventElapsedTime(&ms, pb->prof_ev[2 * r.pair], pb->prof_ev[2 * r.pair + 1]));
-    pb->prof_count[r.kind] += 1;
-    pb->prof_ms[r.kind] += ms;
-    pb->prof_bytes[r.kind] += r.bytes;
+    EDF_TRY(hipEventSynchronize(G.prof_ev[2 * r.pair + 1]));
+    EDF_TRY(hipEventElapsedTime(&ms, G.prof_ev[2 * r.pair], G.prof_ev[2 * r.pair + 1]));
+    G.prof_count[r.kind] += 1;
+    G.prof_ms[r.kind] += ms;
+    G.prof_bytes[r.kind] += r.bytes;
   }
-  pb->prof_pending.clear();
+  G.prof_pending.clear();
   return EDF_OK;
 }
 
@@ -407,7 +407,7 @@ const float* stencil<float>(const Level& L) { return L.A32; }
 
 template <typename T>
 void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int* mask) {
-  hipStream_t st = pb->st;
+  hipStream_t st = G.st;
   const int S = G.S;
   const int nu1 = pb->opts.nu_pre, nu2 = pb->opts.nu_post;
   T* b0 = (T*)G.lv[0].b;
@@ -417,7 +417,7 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
   auto smooth = [&](const Level& L, int c, const T* b, T* x) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const double bytes = (double)L.g.cnt[c] * G.n_active * 118.0 * sizeof(T);
-    prof_pair(pb, e0, e1, bytes, 0);
+    prof_pair(G, e0, e1, bytes, 0);
     launch_smooth<T>(L.g, c, stencil<T>(L), (const T*)L.Dinv, b, x, S, mask, st, e0, e1);
   };
   auto bx = [&](int l, T*& b, T*& x) {
@@ -472,19 +472,19 @@ void precondition(edf_problem* pb, Group& G, const double* in, double* out, cons
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const size_t tsz = mixed(pb) ? sizeof(float) : sizeof(double);
   const double bytes = vcycle_bytes(G, tsz, pb->opts.nu_pre, pb->opts.nu_post) * G.n_active;
-  if (prof_pair(pb, e0, e1, bytes, 1)) (void)hipEventRecord(e0, pb->st);
+  if (prof_pair(G, e0, e1, bytes, 1)) (void)hipEventRecord(e0, G.st);
   if (mixed(pb))
     vcycle<float>(pb, G, in, out, mask);
   else
     vcycle<double>(pb, G, in, out, mask);
-  if (e1) (void)hipEventRecord(e1, pb->st);
+  if (e1) (void)hipEventRecord(e1, G.st);
 }
 
 // ---------------------------------------------------------------------------
 // BiCGStab on A x = F~ for the samples in G.nmask; x in G.kx
 // ---------------------------------------------------------------------------
 edf_status bicgstab(edf_problem* pb, Group& G) {
-  hipStream_t st = pb->st;
+  hipStream_t st = G.st;
   const int S = G.S;
   const size_t n = G.n;
   const Geom& g0 = G.lv[0].g;
@@ -493,11 +493,11 @@ edf_status bicgstab(edf_problem* pb, Group& G) {
                    G.nmask, st);
   auto count_active = [&]() -> edf_status {
     EDF_CHECK_LAUNCH();
-    EDF_TRY(hipMemcpyAsync(pb->h_int, G.active, S * sizeof(int), hipMemcpyDeviceToHost, st));
+    EDF_TRY(hipMemcpyAsync(G.h_int, G.active, S * sizeof(int), hipMemcpyDeviceToHost, st));
     EDF_TRY(hipStreamSynchronize(st));
     G.n_active = 0;
-    for (int s = 0; s < S; ++s) G.n_active += pb->h_int[s] != 0;
-    return prof_flush(pb);
+    for (int s = 0; s < S; ++s) G.n_active += G.h_int[s] != 0;
+    return prof_flush(pb, G);
   };
   edf_status e;
   if ((e = count_active())) return e;
@@ -520,29 +520,29 @@ edf_status bicgstab(edf_problem* pb, Group& G) {
 
 edf_status read_norms(edf_problem* pb, Group& G, const double* F, const int* mask,
                       std::vector<double>& out) {
-  launch_sq_norm(G.n, F, G.part, G.norms, G.S, mask, pb->st);
+  launch_sq_norm(G.n, F, G.part, G.norms, G.S, mask, G.st);
   EDF_CHECK_LAUNCH();
-  EDF_TRY(hipMemcpyAsync(pb->h_dbl, G.norms, G.S * sizeof(double), hipMemcpyDeviceToHost, pb->st));
-  EDF_TRY(hipStreamSynchronize(pb->st));
+  EDF_TRY(hipMemcpyAsync(G.h_dbl, G.norms, G.S * sizeof(double), hipMemcpyDeviceToHost, G.st));
+  EDF_TRY(hipStreamSynchronize(G.st));
   out.resize(G.S);
-  for (int s = 0; s < G.S; ++s) out[s] = std::sqrt(pb->h_dbl[s]);
+  for (int s = 0; s < G.S; ++s) out[s] = std::sqrt(G.h_dbl[s]);
   return EDF_OK;
 }
 
-edf_status upload_ints(edf_problem* pb, int* dst, const std::vector<int>& v) {
-  EDF_TRY(hipStreamSynchronize(pb->st));  // the staging buffer may still feed a copy
-  std::copy(v.begin(), v.end(), pb->h_int);
-  EDF_TRY(hipMemcpyAsync(dst, pb->h_int, v.size() * sizeof(int), hipMemcpyHostToDevice, pb->st));
-  EDF_TRY(hipStreamSynchronize(pb->st));
+edf_status upload_ints(edf_problem* pb, Group& G, int* dst, const std::vector<int>& v) {
+  EDF_TRY(hipStreamSynchronize(G.st));  // the staging buffer may still feed a copy
+  std::copy(v.begin(), v.end(), G.h_int);
+  EDF_TRY(hipMemcpyAsync(dst, G.h_int, v.size() * sizeof(int), hipMemcpyHostToDevice, G.st));
+  EDF_TRY(hipStreamSynchronize(G.st));
   return EDF_OK;
 }
 
-edf_status upload_dbls(edf_problem* pb, double* dst, const std::vector<double>& v) {
-  EDF_TRY(hipStreamSynchronize(pb->st));
-  std::copy(v.begin(), v.end(), pb->h_dbl);
-  EDF_TRY(hipMemcpyAsync(dst, pb->h_dbl, v.size() * sizeof(double), hipMemcpyHostToDevice,
-                         pb->st));
-  EDF_TRY(hipStreamSynchronize(pb->st));
+edf_status upload_dbls(edf_problem* pb, Group& G, double* dst, const std::vector<double>& v) {
+  EDF_TRY(hipStreamSynchronize(G.st));
+  std::copy(v.begin(), v.end(), G.h_dbl);
+  EDF_TRY(hipMemcpyAsync(dst, G.h_dbl, v.size() * sizeof(double), hipMemcpyHostToDevice,
+                         G.st));
+  EDF_TRY(hipStreamSynchronize(G.st));
   return EDF_OK;
 }
 
@@ -555,18 +555,18 @@ void set_dt(edf_problem* pb, Group& G, double dt) {
 // time three V-cycles for every candidate first fused level and keep the fastest
 // ---------------------------------------------------------------------------
 edf_status autotune_group(edf_problem* pb, Group& G) {
-  hipStream_t st = pb->st;
+  hipStream_t st = G.st;
   std::vector<int> all(G.S, 1);
   edf_status e;
-  if ((e = upload_ints(pb, G.nmask, all))) return e;
+  if ((e = upload_ints(pb, G, G.nmask, all))) return e;
   if ((e = assemble_all(pb, G, G.nmask, nullptr))) return e;
   launch_defect(G.lv[0].g, G.lv[0].ph, nullptr, G.lv[0].phi, G.lv[0].K, G.u, G.u, G.kp, G.S,
                 nullptr, st);
   hipEvent_t a, b;
   EDF_TRY(hipEventCreate(&a));
   EDF_TRY(hipEventCreate(&b));
-  const bool was_on = pb->prof_on;
-  pb->prof_on = false;
+  const bool was_on = G.prof_on;
+  G.prof_on = false;
   G.n_active = G.S;
   G.tune_ms.assign(G.L, -1.0);
   double best = 1e300;
@@ -586,7 +586,7 @@ edf_status autotune_group(edf_problem* pb, Group& G) {
       best_l0 = l0;
     }
   }
-  pb->prof_on = was_on;
+  G.prof_on = was_on;
   G.fuse_from = best_l0;
   EDF_TRY(hipEventDestroy(a));
   EDF_TRY(hipEventDestroy(b));
@@ -608,13 +608,13 @@ constexpr double kSlowDrop = 1e-2;      // ... without this reduction of ||F~||
 edf_status newton_solve(edf_problem* pb, Group& G, const std::vector<int>& run,
                         const std::vector<int>& can_retry, std::vector<int>& ok,
                         std::vector<int>& why, bool first_attempt) {
-  hipStream_t st = pb->st;
+  hipStream_t st = G.st;
   const int S = G.S;
   const edf_solver_opts& o = pb->opts;
   const Level& L0 = G.lv[0];
   const double pu = p_unit(pb->phys);
   edf_status e;
-  if ((e = upload_ints(pb, G.nmask, run))) return e;
+  if ((e = upload_ints(pb, G, G.nmask, run))) return e;
   launch_defect(L0.g, L0.ph, G.dts, L0.phi, L0.K, G.u, G.u_old, G.F, S, G.nmask, st);
   std::vector<double> r, r0, rt;
   if ((e = read_norms(pb, G, G.F, G.nmask, r))) return e;
@@ -665,21 +665,21 @@ edf_status newton_solve(edf_problem* pb, Group& G, const std::vector<int>& run,
       eta[s] = std::max(std::min(et, 0.1), o.lin_rtol);
     }
     for (int s = 0; s < S; ++s) r_prev[s] = r[s];
-    if ((e = upload_dbls(pb, G.eta, eta))) return e;
-    if ((e = upload_ints(pb, G.nmask, nm))) return e;
+    if ((e = upload_dbls(pb, G, G.eta, eta))) return e;
+    if ((e = upload_ints(pb, G, G.nmask, nm))) return e;
     if ((e = assemble_all(pb, G, G.nmask, G.dts))) return e;
     if ((e = bicgstab(pb, G))) return e;
     // BiCGStab statistics and the size of the Newton update
-    EDF_TRY(hipMemcpyAsync(pb->h_ks, G.ks, S * sizeof(KrylovScalars), hipMemcpyDeviceToHost, st));
+    EDF_TRY(hipMemcpyAsync(G.h_ks, G.ks, S * sizeof(KrylovScalars), hipMemcpyDeviceToHost, st));
     std::vector<double> dnorm;
     if ((e = read_norms(pb, G, G.kx, G.nmask, dnorm))) return e;
     for (int s = 0; s < S; ++s)
       if (nm[s]) {
         G.stats[s].newton_its += 1;
-        G.stats[s].lin_its += pb->h_ks[s].it;
+        G.stats[s].lin_its += G.h_ks[s].it;
         // BiCGStab ended more than a factor 2 short of its tolerance: the preconditioner
         // is not up to this time step, and a shorter one is cheaper than inexact Newton
-        const KrylovScalars& k = pb->h_ks[s];
+        const KrylovScalars& k = G.h_ks[s];
         if (can_retry[s] && k.state != 1 && !(k.rr <= 4.0 * k.tol2)) {
           nm[s] = 0;
           why[s] = EDF_SAMPLE_LINEAR_FAIL;
@@ -696,8 +696,8 @@ edf_status newton_solve(edf_problem* pb, Group& G, const std::vector<int>& run,
       bool any_ls = false;
       for (int s = 0; s < S; ++s) any_ls |= ls[s] != 0;
       if (!any_ls) break;
-      if ((e = upload_ints(pb, G.lsmask, ls))) return e;
-      if ((e = upload_dbls(pb, G.lam, lam))) return e;
+      if ((e = upload_ints(pb, G, G.lsmask, ls))) return e;
+      if ((e = upload_dbls(pb, G, G.lam, lam))) return e;
       launch_axpy_state(G.N, G.u, G.kx, G.lam, pu, G.ut, S, G.lsmask, st);
       launch_defect(L0.g, L0.ph, G.dts, L0.phi, L0.K, G.ut, G.u_old, G.Ft, S, G.lsmask, st);
       std::vector<double> rr;
@@ -726,7 +726,7 @@ edf_status newton_solve(edf_problem* pb, Group& G, const std::vector<int>& run,
       }
       acc[s] = 1;
     }
-    if ((e = upload_ints(pb, G.lsmask, acc))) return e;
+    if ((e = upload_ints(pb, G, G.lsmask, acc))) return e;
     launch_masked_copy(G.n, G.ut, G.u, S, G.lsmask, st);
     launch_masked_copy(G.n, G.Ft, G.F, S, G.lsmask, st);
     for (int s = 0; s < S; ++s)
@@ -743,7 +743,7 @@ edf_status newton_solve(edf_problem* pb, Group& G, const std::vector<int>& run,
   bool any_ok = false;
   for (int s = 0; s < S; ++s) any_ok |= ok[s] != 0;
   if (any_ok) {
-    if ((e = upload_ints(pb, G.lsmask, ok))) return e;
+    if ((e = upload_ints(pb, G, G.lsmask, ok))) return e;
     launch_c_range(L0.g, G.u, G.part, G.crange, S, G.lsmask, st);
     EDF_CHECK_LAUNCH();
     std::vector<double> cr(2 * S);
@@ -768,7 +768,7 @@ edf_status newton_solve(edf_problem* pb, Group& G, const std::vector<int>& run,
 constexpr int kFirstWait = 3, kMaxWait = 64;
 
 edf_status macro_step(edf_problem* pb, Group& G, double DT) {
-  hipStream_t st = pb->st;
+  hipStream_t st = G.st;
   const int S = G.S;
   set_dt(pb, G, DT);
   edf_status e;
@@ -794,8 +794,8 @@ edf_status macro_step(edf_problem* pb, Group& G, double DT) {
       dts[s] = DT / double(1 << h[s]);
     }
     if (!any) break;
-    if ((e = upload_dbls(pb, G.dts, dts))) return e;
-    if ((e = upload_ints(pb, G.nmask, running))) return e;
+    if ((e = upload_dbls(pb, G, G.dts, dts))) return e;
+    if ((e = upload_ints(pb, G, G.nmask, running))) return e;
     launch_masked_copy(G.n, G.u, G.u_old, S, G.nmask, st);
     for (int s = 0; s < S; ++s) can_retry[s] = h[s] < pb->opts.dt_max_halvings;
     if ((e = newton_solve(pb, G, running, can_retry, ok, why, first))) return e;
@@ -820,7 +820,7 @@ edf_status macro_step(edf_problem* pb, Group& G, double DT) {
       }
     }
     if (any_restore) {
-      if ((e = upload_ints(pb, G.lsmask, restore))) return e;
+      if ((e = upload_ints(pb, G, G.lsmask, restore))) return e;
       launch_masked_copy(G.n, G.u0, G.u, S, G.lsmask, st);
     }
   }
@@ -855,25 +855,25 @@ edf_status assemble_all_transposed(edf_problem* pb, Group& G, const int* mask, c
   const bool mx = mixed(pb);
   for (int l = 0; l < G.L; ++l) {
     Level& L = G.lv[l];
-    if (l > 0) launch_inject(G.lv[l - 1].g, L.g, G.lv[l - 1].u, L.u, G.S, mask, pb->st);
+    if (l > 0) launch_inject(G.lv[l - 1].g, L.g, G.lv[l - 1].u, L.u, G.S, mask, G.st);
     const bool coarsest = l == G.L - 1;
     if (l == 0) {  // exact Jacobian, transposed, for the Krylov products
-      launch_assemble(L.g, L.ph, dts, L.phi, L.K, L.u, G.tmpA, nullptr, G.S, mask, pb->st, false);
-      launch_transpose<double>(L.g, G.tmpA, L.A64, G.S, mask, pb->st);
+      launch_assemble(L.g, L.ph, dts, L.phi, L.K, L.u, G.tmpA, nullptr, G.S, mask, G.st, false);
+      launch_transpose<double>(L.g, G.tmpA, L.A64, G.S, mask, G.st);
     }
-    launch_assemble(L.g, L.ph, dts, L.phi, L.K, L.u, G.tmpA, nullptr, G.S, mask, pb->st, true);
+    launch_assemble(L.g, L.ph, dts, L.phi, L.K, L.u, G.tmpA, nullptr, G.S, mask, G.st, true);
     if (mx && !coarsest) {
-      launch_transpose<float>(L.g, G.tmpA, L.A32, G.S, mask, pb->st);
-      launch_block_inverse_f32(L.g, L.A32, (float*)L.Dinv, G.S, mask, pb->st);
+      launch_transpose<float>(L.g, G.tmpA, L.A32, G.S, mask, G.st);
+      launch_block_inverse_f32(L.g, L.A32, (float*)L.Dinv, G.S, mask, G.st);
     } else {
       double* m64 = l == 0 ? L.AV64 : L.A64;
-      launch_transpose<double>(L.g, G.tmpA, m64, G.S, mask, pb->st);
-      if (!coarsest) launch_block_inverse_f64(L.g, m64, (double*)L.Dinv, G.S, mask, pb->st);
+      launch_transpose<double>(L.g, G.tmpA, m64, G.S, mask, G.st);
+      if (!coarsest) launch_block_inverse_f64(L.g, m64, (double*)L.Dinv, G.S, mask, G.st);
     }
   }
   const Level& C = G.lv[G.L - 1];
-  launch_coarse_dense(C.g, G.L == 1 ? C.AV64 : C.A64, G.Minv, G.S, mask, pb->st);
-  launch_gauss_jordan(G.n_coarse, G.Minv, G.piv, G.gj_status, G.S, mask, pb->st);
+  launch_coarse_dense(C.g, G.L == 1 ? C.AV64 : C.A64, G.Minv, G.S, mask, G.st);
+  launch_gauss_jordan(G.n_coarse, G.Minv, G.piv, G.gj_status, G.S, mask, G.st);
   EDF_CHECK_LAUNCH();
   return EDF_OK;
 }
@@ -903,16 +903,16 @@ edf_status ensure_adjoint_buffers(edf_problem* pb, Group& G, int n_steps) {
 edf_status gather(edf_problem* pb, Group& G, const double* buf, size_t cap,
                   const std::vector<int>& idx, double* dst) {
   edf_status e;
-  if ((e = upload_ints(pb, G.idx, idx))) return e;
-  launch_gather_state(G.n, buf, cap * G.n, G.idx, dst, G.S, pb->st);
+  if ((e = upload_ints(pb, G, G.idx, idx))) return e;
+  launch_gather_state(G.n, buf, cap * G.n, G.idx, dst, G.S, G.st);
   return EDF_OK;
 }
 
 edf_status scatter(edf_problem* pb, Group& G, const double* src, double* buf, size_t cap,
                    const std::vector<int>& idx) {
   edf_status e;
-  if ((e = upload_ints(pb, G.idx, idx))) return e;
-  launch_scatter_state(G.n, src, buf, cap * G.n, G.idx, G.S, pb->st);
+  if ((e = upload_ints(pb, G, G.idx, idx))) return e;
+  launch_scatter_state(G.n, src, buf, cap * G.n, G.idx, G.S, G.st);
   return EDF_OK;
 }
 
@@ -920,7 +920,7 @@ edf_status scatter(edf_problem* pb, Group& G, const double* src, double* buf, si
 // adjoint sweep backwards; J[s] and dJ[s][4] of the group's samples
 edf_status adjoint_group(edf_problem* pb, Group& G, const QoiBox& box, double dt, int n_steps,
                          std::vector<double>& Jv, std::vector<double>& grad) {
-  hipStream_t st = pb->st;
+  hipStream_t st = G.st;
   const int S = G.S;
   edf_status e;
   if ((e = ensure_adjoint_buffers(pb, G, n_steps))) return e;
@@ -965,10 +965,10 @@ edf_status adjoint_group(edf_problem* pb, Group& G, const QoiBox& box, double dt
     if ((e = gather(pb, G, G.traj, G.traj_cap, idx, G.u))) return e;
     std::fill(idx.begin(), idx.end(), 0);
     if ((e = scatter(pb, G, G.u, G.sub, G.sub_cap, idx))) return e;
-    if ((e = upload_dbls(pb, G.dts, dts))) return e;
+    if ((e = upload_dbls(pb, G, G.dts, dts))) return e;
     for (int r = 1; r < kmax; ++r) {
       for (int s = 0; s < S; ++s) act[s] = K[s] > r;
-      if ((e = upload_ints(pb, G.nmask, act))) return e;
+      if ((e = upload_ints(pb, G, G.nmask, act))) return e;
       launch_masked_copy(G.n, G.u, G.u_old, S, G.nmask, st);
       // the forward attempt at this sub-step length succeeded, so no Krylov failure
       // ended it: replaying without that check takes the same path
@@ -991,7 +991,7 @@ edf_status adjoint_group(edf_problem* pb, Group& G, const QoiBox& box, double dt
       if ((e = gather(pb, G, G.sub, G.sub_cap, idx, G.u))) return e;
       for (int s = 0; s < S; ++s) idx[s] = act[s] ? K[s] - r - 1 : -1;
       if ((e = gather(pb, G, G.sub, G.sub_cap, idx, G.u_old))) return e;
-      if ((e = upload_ints(pb, G.nmask, act))) return e;
+      if ((e = upload_ints(pb, G, G.nmask, act))) return e;
       if (first) {  // J and dJ/du~ at the final state
         const int nb = ceil_div(L0.g.N, kBlock);
         launch_qoi(L0.g, L0.ph, box, L0.phi, G.u, G.F, G.part, S, nullptr, st);
@@ -1004,12 +1004,12 @@ edf_status adjoint_group(edf_problem* pb, Group& G, const QoiBox& box, double dt
         launch_adjoint_rhs(L0.g, L0.ph, L0.phi, G.u, G.lam_next, G.F, S, G.nmask, st);
       }
       if ((e = assemble_all_transposed(pb, G, G.nmask, G.dts))) return e;
-      if ((e = upload_dbls(pb, G.eta, eta))) return e;
+      if ((e = upload_dbls(pb, G, G.eta, eta))) return e;
       if ((e = bicgstab(pb, G))) return e;
-      EDF_TRY(hipMemcpyAsync(pb->h_ks, G.ks, S * sizeof(KrylovScalars), hipMemcpyDeviceToHost, st));
+      EDF_TRY(hipMemcpyAsync(G.h_ks, G.ks, S * sizeof(KrylovScalars), hipMemcpyDeviceToHost, st));
       EDF_TRY(hipStreamSynchronize(st));
       for (int s = 0; s < S; ++s)
-        if (act[s] && pb->h_ks[s].state != 1 && pb->h_ks[s].bb > 0)
+        if (act[s] && G.h_ks[s].state != 1 && G.h_ks[s].bb > 0)
           return fail(pb, EDF_ERR_NO_CONVERGENCE,
                       "adjoint BiCGStab did not converge for sample " + std::to_string(G.s0 + s));
       const int nb = launch_param_grad(L0.g, L0.ph, G.dts, fp, dxi, L0.phi, L0.K, G.u, G.u_old,
@@ -1057,6 +1057,10 @@ edf_status edf_create_problem(const edf_physics* phys, const edf_group_desc* gro
   pb->phys = *phys;
   pb->opts = *opts;
   pb->st = (hipStream_t)hip_stream;
+  if (hipGetDevice(&pb->device) != hipSuccess) {
+    delete pb;
+    return EDF_ERR_HIP;
+  }
   const edf_physics& P = *phys;
   auto bad = [&](const std::string& m) {
     std::fprintf(stderr, "edf_create_problem: %s\n", m.c_str());
@@ -1074,8 +1078,10 @@ edf_status edf_create_problem(const edf_physics* phys, const edf_group_desc* gro
   if (opts->newton_max_it < 1 || opts->lin_max_it < 1 || opts->nu_pre < 1 || opts->nu_post < 0 ||
       opts->ls_max_halvings < 0 || !(opts->lin_rtol > 0) || !(opts->newton_rtol >= 0))
     return bad("invalid solver options");
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < 2; ++i)
     if (opts->reserved[i] != 0) return bad("reserved options must be zero");
+  if (opts->concurrent_groups != 0 && opts->concurrent_groups != 1)
+    return bad("concurrent_groups must be 0 or 1");
   if (opts->forcing != 0 && opts->forcing != 1) return bad("forcing must be 0 or 1");
   if (opts->dt_max_halvings < 0 || opts->dt_max_halvings > 12)
     return bad("dt_max_halvings must be in [0, 12]");
@@ -1106,17 +1112,18 @@ edf_status edf_create_problem(const edf_physics* phys, const edf_group_desc* gro
       return s;
     }
   }
-  int maxS = 0;
-  for (Group& G : pb->groups) maxS = std::max(maxS, G.S);
-  if (ensure_pinned(pb, std::max(maxS, pb->S_total)) != EDF_OK) {
-    edf_destroy(pb);
-    return EDF_ERR_HIP;
-  }
-  for (Group& G : pb->groups)
-    if (upload_initial(pb, G) != EDF_OK) {
+  for (Group& G : pb->groups) {
+    const bool ok =
+        hipStreamCreateWithFlags(&G.st, hipStreamNonBlocking) == hipSuccess &&
+        hipHostMalloc((void**)&G.h_int, sizeof(int) * G.S) == hipSuccess &&
+        hipHostMalloc((void**)&G.h_dbl, sizeof(double) * G.S) == hipSuccess &&
+        hipHostMalloc((void**)&G.h_ks, sizeof(KrylovScalars) * G.S) == hipSuccess;
+    if (!ok || upload_initial(pb, G) != EDF_OK) {
+      (void)hipGetLastError();
       edf_destroy(pb);
       return EDF_ERR_HIP;
     }
+  }
   *out = pb;
   return EDF_OK;
 }
@@ -1188,14 +1195,37 @@ edf_status edf_step(edf_problem* pb, double dt, edf_step_stats* stats) {
   edf_status e;
   if ((e = check_ready(pb))) return e;
   if (!(dt > 0) || !std::isfinite(dt)) return fail(pb, EDF_ERR_ARG, "dt must be positive");
+  EDF_TRY(hipStreamSynchronize(pb->st));  // work the caller queued before this step
+  // the groups are independent and each steps on its own stream; with
+  // concurrent_groups each also runs from its own host thread, so that one group's
+  // host round trips and small launches overlap another's sweeps
+  const size_t ng = pb->groups.size();
+  std::vector<edf_status> rc(ng, EDF_OK);
+  auto run = [&](size_t gi) {
+    if (hipSetDevice(pb->device) != hipSuccess) {
+      rc[gi] = fail(pb, EDF_ERR_HIP, "hipSetDevice failed in a group thread");
+      return;
+    }
+    rc[gi] = macro_step(pb, pb->groups[gi], dt);
+    if (hipStreamSynchronize(pb->groups[gi].st) != hipSuccess && rc[gi] == EDF_OK)
+      rc[gi] = fail(pb, EDF_ERR_HIP, "group stream synchronisation failed");
+  };
+  if (ng == 1 || !pb->opts.concurrent_groups) {
+    for (size_t gi = 0; gi < ng; ++gi) run(gi);
+  } else {
+    std::vector<std::thread> th;
+    th.reserve(ng);
+    for (size_t gi = 0; gi < ng; ++gi) th.emplace_back(run, gi);
+    for (std::thread& t : th) t.join();
+  }
+  for (size_t gi = 0; gi < ng; ++gi)
+    if (rc[gi] != EDF_OK) return rc[gi];
   bool all_failed = true;
-  for (Group& G : pb->groups) {
-    if ((e = macro_step(pb, G, dt))) return e;
+  for (Group& G : pb->groups)
     for (int s = 0; s < G.S; ++s) {
       if (stats) stats[G.s0 + s] = G.stats[s];
       all_failed &= G.stats[s].status != EDF_SAMPLE_OK;
     }
-  }
   if (all_failed) return fail(pb, EDF_ERR_NO_CONVERGENCE, "every sample failed in this step");
   return EDF_OK;
 }
@@ -1323,17 +1353,18 @@ edf_status edf_apply_vcycle(edf_problem* pb, int32_t group, double dt, const dou
   if (group < 0 || group >= (int)pb->groups.size() || !x || !y || !(dt > 0))
     return fail(pb, EDF_ERR_ARG, "bad vcycle arguments");
   Group& G = pb->groups[group];
+  EDF_TRY(hipStreamSynchronize(pb->st));
   set_dt(pb, G, dt);
   std::vector<int> all(G.S, 1);
-  if ((e = upload_ints(pb, G.nmask, all))) return e;
+  if ((e = upload_ints(pb, G, G.nmask, all))) return e;
   if ((e = assemble_all(pb, G, G.nmask, nullptr))) return e;
-  EDF_TRY(hipMemcpyAsync(G.kp, x, G.S * G.n * sizeof(double), hipMemcpyHostToDevice, pb->st));
+  EDF_TRY(hipMemcpyAsync(G.kp, x, G.S * G.n * sizeof(double), hipMemcpyHostToDevice, G.st));
   G.n_active = G.S;
   precondition(pb, G, G.kp, G.kph, G.nmask);
   EDF_CHECK_LAUNCH();
-  EDF_TRY(hipMemcpyAsync(y, G.kph, G.S * G.n * sizeof(double), hipMemcpyDeviceToHost, pb->st));
-  EDF_TRY(hipStreamSynchronize(pb->st));
-  return prof_flush(pb);
+  EDF_TRY(hipMemcpyAsync(y, G.kph, G.S * G.n * sizeof(double), hipMemcpyDeviceToHost, G.st));
+  EDF_TRY(hipStreamSynchronize(G.st));
+  return prof_flush(pb, G);
 }
 
 edf_status edf_apply_jacobian(edf_problem* pb, int32_t group, const double* x, double* y) {
@@ -1364,6 +1395,7 @@ edf_status edf_adjoint(edf_problem* pb, const double* box, double dt, int32_t n_
     b.b[i] = box[i];
   }
   const int nxi = pb->phys.n_xi;
+  EDF_TRY(hipStreamSynchronize(pb->st));
   for (Group& G : pb->groups) {
     std::vector<double> Jv, gr;
     if ((e = adjoint_group(pb, G, b, dt, n_steps, Jv, gr))) return e;
@@ -1379,6 +1411,7 @@ edf_status edf_autotune(edf_problem* pb, double dt) {
   edf_status e = check_ready(pb);
   if (e) return e;
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(pb, EDF_ERR_ARG, "dt must be positive");
+  EDF_TRY(hipStreamSynchronize(pb->st));
   for (Group& G : pb->groups) {
     set_dt(pb, G, dt);
     if ((e = autotune_group(pb, G))) return fail(pb, e, "autotuning failed");
@@ -1410,16 +1443,20 @@ edf_status edf_set_tuning(edf_problem* pb, int32_t group, int32_t fuse_from) {
 edf_status edf_profile(edf_problem* pb, int32_t enable, double* out) {
   if (!pb) return EDF_ERR_ARG;
   edf_status e;
-  if ((e = prof_flush(pb))) return e;
   if (out)
-    for (int k = 0; k < 2; ++k) {
-      out[3 * k + 0] = pb->prof_count[k];
-      out[3 * k + 1] = pb->prof_ms[k];
-      out[3 * k + 2] = pb->prof_bytes[k];
-    }
-  if (enable)
-    for (int k = 0; k < 2; ++k) pb->prof_count[k] = pb->prof_ms[k] = pb->prof_bytes[k] = 0;
-  pb->prof_on = enable != 0;
+    for (int q = 0; q < 6; ++q) out[q] = 0.0;
+  for (Group& G : pb->groups) {
+    if ((e = prof_flush(pb, G))) return e;
+    if (out)
+      for (int k = 0; k < 2; ++k) {
+        out[3 * k + 0] += G.prof_count[k];
+        out[3 * k + 1] += G.prof_ms[k];
+        out[3 * k + 2] += G.prof_bytes[k];
+      }
+    if (enable)
+      for (int k = 0; k < 2; ++k) G.prof_count[k] = G.prof_ms[k] = G.prof_bytes[k] = 0;
+    G.prof_on = enable != 0;
+  }
   return EDF_OK;
 }
 
@@ -1428,12 +1465,18 @@ const char* edf_last_error(const edf_problem* pb) { return pb ? pb->err.c_str() 
 void edf_destroy(edf_problem* pb) {
   if (!pb) return;
   if (pb->st) (void)hipStreamSynchronize(pb->st);
+  for (Group& G : pb->groups) {
+    if (G.st) {
+      (void)hipStreamSynchronize(G.st);
+      (void)hipStreamDestroy(G.st);
+    }
+    for (hipEvent_t e : G.prof_ev) (void)hipEventDestroy(e);
+    if (G.h_int) (void)hipHostFree(G.h_int);
+    if (G.h_dbl) (void)hipHostFree(G.h_dbl);
+    if (G.h_ks) (void)hipHostFree(G.h_ks);
+  }
   for (void* p : pb->allocs) (void)hipFree(p);
-  for (hipEvent_t e : pb->prof_ev) (void)hipEventDestroy(e);
   if (pb->mom_f) (void)hipFree(pb->mom_f);
-  if (pb->h_int) (void)hipHostFree(pb->h_int);
-  if (pb->h_dbl) (void)hipHostFree(pb->h_dbl);
-  if (pb->h_ks) (void)hipHostFree(pb->h_ks);
   delete pb;
 }
 

@@ -305,6 +305,28 @@ def test_autotuned_step_matches_default():
     assert _rel(out[1], out[0]) < 1e-12
 
 
+def test_concurrent_groups_give_the_serial_result():
+    """Groups advanced at the same time (one host thread and stream each) reach bitwise
+    the states and statistics of groups advanced one after the other."""
+    phys = synth.physics(2)
+    groups = [(9, 9, 3, 2, 3), (17, 17, 5, 3, 2), (33, 33, 9, 4, 2)]
+    xi = _xi(2, 7, seed=21)
+    xi[3] = 0.9  # a high-permeability sample that needs sub-steps at 4 months
+    out = {}
+    for conc in (0, 1):
+        pb = _problem(phys, groups, concurrent_groups=conc, dt_max_halvings=4)
+        pb.set_parameters(xi)
+        sts = [pb.step(4 * DT) for _ in range(2)]
+        out[conc] = ([pb.get_state(s) for s in range(7)],
+                     [[(x["status"], x["newton_its"], x["lin_its"], x["substeps"]) for x in st]
+                      for st in sts])
+        pb.destroy()
+    print("sub-steps", [x[3] for x in out[1][1][1]], flush=True)
+    assert out[1][1] == out[0][1]
+    for s in range(7):
+        assert np.array_equal(out[1][0][s], out[0][0][s]), s
+
+
 def test_mixed_precision_step_matches_fp64_oracle():
     nx, ny, nz = 33, 33, 9
     phys = synth.physics(2)
