@@ -26,32 +26,44 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def roctx_region():
-    """(start, stop) of the region that `rocprofv3 --selected-regions` collects, so that
-    the profiler sees exactly the timed steps; no-ops if the marker library is absent."""
+def roctx_range():
+    """(push, pop) of a named roctx range, recorded by `rocprofv3 --marker-trace` in the
+    clock of its kernel trace; no-ops if the marker library is absent."""
     import ctypes
     for name in ("librocprofiler-sdk-roctx.so.1", "librocprofiler-sdk-roctx.so"):
         try:
             lib = ctypes.CDLL(name)
-            return (lambda: lib.roctxProfilerResume(0)), (lambda: lib.roctxProfilerPause(0))
-        except OSError:
+            lib.roctxRangePushA.argtypes = [ctypes.c_char_p]
+            return (lambda: lib.roctxRangePushA(b"timed steps")), (lambda: lib.roctxRangePop())
+        except (OSError, AttributeError):
             continue
     return (lambda: None), (lambda: None)
 
 
-def measured_traffic(kernel_source):
-    """HBM traffic of the smoother per launch from the committed rocprofv3 counter
-    measurement of the default command, or None when the kernel source changed since."""
+KERNEL_SOURCES = ("mg_kernels.hip", "fv_common.h", "edf_api.hip")  # smoother, layout, launches
+
+
+def kernel_digest():
     import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1906_01632_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """Ratio of measured HBM bytes to algorithmic bytes per smoother launch, from the
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE measurement, or None when the kernel
+    sources changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "k_smooth_traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f)
-        with open(kernel_source, "rb") as f:
-            digest = hashlib.sha256(f.read()).hexdigest()
+        digest = kernel_digest()
     except OSError:
         return None
-    if rec.get("kernel_source_sha256") != digest:
+    if rec.get("kernel_sources_sha256") != digest:
         return None
     return rec
 
@@ -98,14 +110,13 @@ def main():
                          "durations the roofline is computed from")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default fused-bottom levels instead of timing the choices")
-    ap.add_argument("--profile-timed-region", action="store_true",
-                    help="mark the timed steps for rocprofv3 --selected-regions")
+    ap.add_argument("--mark-timed-region", action="store_true",
+                    help="mark the timed steps with a roctx range (rocprofv3 --marker-trace)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="copy 1 GiB device-to-device at the start of the timed region (a copy "
                          "of known size that calibrates the HBM byte counters)")
     args = ap.parse_args()
-    # rocprofv3 --selected-regions starts paused: only the timed steps are collected
-    region_start, region_stop = roctx_region() if args.profile_timed_region else (None, None)
+    region_start, region_stop = roctx_range() if args.mark_timed_region else (None, None)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): samples are independent, "
               "so N GPUs would each run their own share; no multi-GPU path is built.",
@@ -143,14 +154,14 @@ def main():
     if not args.no_profile:
         pb.profile(True)
     stats = None
-    if region_start:
-        region_start()
     if args.copy_probe:
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    if region_start:
+        region_start()
     t0 = time.perf_counter()
     for k in range(args.steps):
         stats = pb.step(wl.dt)
@@ -196,16 +207,22 @@ def main():
                          "bytes_per_vcycle": prof["vcycle_bytes"] / prof["vcycles"]}
     if prof["launches"]:
         gbs = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9
-        tr = measured_traffic(os.path.join(ROOT, "paper_1906_01632_amd", "csrc", "mg_kernels.hip"))
-        traffic = None
+        tr = measured_traffic()
+        traffic = ratio = None
         if tr and tr.get("workload") == wl.name and tr.get("precision") == prec:
-            traffic = tr["hbm_bytes_per_launch"]
+            # HBM bytes per launch of this run's launch mix: the measured ratio of HBM to
+            # algorithmic bytes times this run's algorithmic bytes per launch
+            ratio = tr["ratio"]
+            traffic = ratio * prof["all_bytes"] / prof["all_launches"]
         out["roofline"] = {"bound": "hbm", "kernel": "k_smooth (block Gauss-Seidel colour sweep)",
                            "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
-                           "launches": prof["launches"],
+                           "traffic_over_algorithmic": ratio,
+                           "launches": prof["all_launches"],
+                           "launches_timed": prof["launches"],
                            "avg_launch_us": 1e3 * prof["ms"] / prof["launches"],
-                           "bytes_per_launch": prof["bytes"] / prof["launches"]}
+                           "bytes_per_launch": prof["bytes"] / prof["launches"],
+                           "bytes_per_launch_all": prof["all_bytes"] / prof["all_launches"]}
     if not args.no_cpu_baseline:
         log("oracle timing on the host ...")
         out["cpu_baseline"] = cpu_baseline(wl, phys)

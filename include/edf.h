@@ -225,17 +225,20 @@ edf_status edf_apply_vcycle(edf_problem* pb, int32_t group, double dt, const dou
  * (edf_apply_vcycle or a Newton iteration); x, y host [S_group][N][2]. */
 edf_status edf_apply_jacobian(edf_problem* pb, int32_t group, const double* x, double* y);
 
-/* Timing of the multigrid preconditioner with HIP events on the problem's stream.
- * edf_profile(pb, 1, out) starts: every later smoother launch (the dominant kernel,
- * block Gauss-Seidel over one colour) and every whole V-cycle is bracketed by events;
- * edf_profile(pb, 0, out) stops.  Both fill out (if not NULL, host double[6]) with
- * totals since the last start: out[0..2] = smoother launches, summed kernel time [ms],
- * algorithmic bytes; out[3..5] = V-cycles, summed time [ms], algorithmic bytes.
+/* Timing of the multigrid preconditioner with HIP events on the groups' streams.
+ * edf_profile(pb, 1, out) starts: every 13th smoother launch (the dominant kernel,
+ * block Gauss-Seidel over one colour; the stride runs through colours, levels and
+ * sweeps alike) and every whole V-cycle is bracketed by events; edf_profile(pb, 0,
+ * out) stops.  Both fill out (if not NULL, host double[8]) with totals since the last
+ * start: out[0..2] = timed smoother launches, their summed kernel time [ms] and
+ * algorithmic bytes; out[3..5] = V-cycles, summed time [ms], algorithmic bytes;
+ * out[6..7] = all smoother launches and their algorithmic bytes.
  * Smoother bytes per vertex of the swept colour and per active sample: 108 stencil +
  * 4 block-inverse entries + 2 right-hand side + 4 own-unknown reads and writes, times
  * the V-cycle precision.  V-cycle bytes per active sample: on every smoothed level
- * N_l (3 x 108 + 2 x 4 + 12 x 2) values (three stencil sweeps, two block-inverse reads,
- * twelve vector passes) plus the dense coarse inverse.  Synchronises the stream. */
+ * N_l ((s + 1) 108 + 4 s + 2 (3 s + 6)) values with s = nu_pre + nu_post (s sweeps and
+ * the residual, s block-inverse reads, the vector passes) plus the dense coarse
+ * inverse.  Synchronises the streams. */
 edf_status edf_profile(edf_problem* pb, int32_t enable, double* out);
 
 /* Autotuning of the V-cycle (an implementation choice, not part of the method): the

@@ -54,6 +54,8 @@ struct Group {
   std::vector<hipEvent_t> prof_ev;
   std::vector<ProfRec> prof_pending;
   double prof_count[2] = {0, 0}, prof_ms[2] = {0, 0}, prof_bytes[2] = {0, 0};
+  double prof_all_count = 0, prof_all_bytes = 0;  // every smoother launch, timed or not
+  long long prof_tick = 0;
   int S = 0, s0 = 0, L = 0;
   std::vector<Level> lv;
   size_t N = 0, n = 0;  // finest vertices, unknowns
@@ -343,8 +345,18 @@ edf_status assemble_all(edf_problem* pb, Group& G, const int* mask, const double
 // ---------------------------------------------------------------------------
 // smoother timing
 // ---------------------------------------------------------------------------
+// every kProfStride-th smoother launch is timed (events around every launch would
+// themselves cost about a tenth of the run time); 13 is coprime with the 8 colours
+// and 16 launches of a pre- and post-smoothing pair
+constexpr int kProfStride = 13;
+
 bool prof_pair(Group& G, hipEvent_t& a, hipEvent_t& b, double bytes, int kind) {
   if (!G.prof_on) return false;
+  if (kind == 0) {
+    G.prof_all_count += 1;
+    G.prof_all_bytes += bytes;
+    if (G.prof_tick++ % kProfStride != 0) return false;
+  }
   const size_t k = G.prof_pending.size();
   while (G.prof_ev.size() < 2 * (k + 1)) {
     hipEvent_t e;
@@ -1444,17 +1456,23 @@ edf_status edf_profile(edf_problem* pb, int32_t enable, double* out) {
   if (!pb) return EDF_ERR_ARG;
   edf_status e;
   if (out)
-    for (int q = 0; q < 6; ++q) out[q] = 0.0;
+    for (int q = 0; q < 8; ++q) out[q] = 0.0;
   for (Group& G : pb->groups) {
     if ((e = prof_flush(pb, G))) return e;
-    if (out)
+    if (out) {
       for (int k = 0; k < 2; ++k) {
         out[3 * k + 0] += G.prof_count[k];
         out[3 * k + 1] += G.prof_ms[k];
         out[3 * k + 2] += G.prof_bytes[k];
       }
-    if (enable)
+      out[6] += G.prof_all_count;
+      out[7] += G.prof_all_bytes;
+    }
+    if (enable) {
       for (int k = 0; k < 2; ++k) G.prof_count[k] = G.prof_ms[k] = G.prof_bytes[k] = 0;
+      G.prof_all_count = G.prof_all_bytes = 0;
+      G.prof_tick = 0;
+    }
     G.prof_on = enable != 0;
   }
   return EDF_OK;

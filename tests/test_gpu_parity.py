@@ -327,6 +327,27 @@ def test_concurrent_groups_give_the_serial_result():
         assert np.array_equal(out[1][0][s], out[0][0][s]), s
 
 
+def test_profile_counts_launches_and_algorithmic_bytes():
+    """edf_profile: every smoother launch is counted with its algorithmic bytes (118
+    values per vertex of the swept colour and active sample), every 13th is timed, and
+    every V-cycle is timed."""
+    nx, ny, nz, L, S = 33, 33, 9, 4, 2
+    phys = synth.physics(2)
+    pb = _problem(phys, [(nx, ny, nz, L, S)])
+    pb.set_parameters(_xi(2, S))
+    pb.set_tuning(0, L - 1)  # levels 0..2 smoothed by separate launches
+    b = np.random.default_rng(1).standard_normal((S, nz, ny, nx, 2))
+    pb.profile(True)
+    pb.apply_vcycle(0, DT, b)
+    pr = pb.profile(False)
+    sizes = [(33 * 33 * 9), (17 * 17 * 5), (9 * 9 * 3)]
+    assert pr["all_launches"] == 3 * 16
+    assert pr["launches"] == len(range(0, 48, 13))
+    assert pr["all_bytes"] == sum(2 * n * S * 118 * 8 for n in sizes)
+    assert pr["vcycles"] == 1 and pr["vcycle_ms"] > 0 and pr["ms"] > 0
+    pb.destroy()
+
+
 def test_mixed_precision_step_matches_fp64_oracle():
     nx, ny, nz = 33, 33, 9
     phys = synth.physics(2)
