@@ -68,6 +68,40 @@ def measured_traffic():
     return rec
 
 
+# quantity of interest of the gradient workload: salt mass in the bottom 50 m under
+# the centre of the box, [200, 400] x [200, 400] x [100, 150] m (z = depth)
+QOI_BOX = (200.0, 400.0, 200.0, 400.0, 100.0, 150.0)
+
+
+def run_adjoint(args, wl, pb, prec):
+    """One timed edf_adjoint call over args.steps steps: sample-timesteps/s of the
+    gradient (forward steps with checkpoints plus the backward sweep)."""
+    import numpy as np
+    import torch
+    pb.profile(True)
+    t0 = time.perf_counter()
+    J, g = pb.adjoint(QOI_BOX, wl.dt, args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = pb.profile(False)
+    out = {"metric": "dJ/dxi sample-timesteps/s (forward with checkpoints + discrete adjoint)",
+           "value": wl.n_samples * args.steps / el, "unit": "sample-timesteps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if prec == "f64" else "f64+f32",
+           "data": "synthetic (seeded lattice parameters; no dataset)",
+           "config": {"workload": wl.name, "groups": [[q.nx, q.ny, q.nz, q.levels, q.samples]
+                                                      for q in wl.groups],
+                      "qoi_box": QOI_BOX, "dt_s": wl.dt, "precision": prec},
+           "J_mean": float(np.mean(J)), "dJ_dxi_mean": np.mean(g, axis=0).tolist()}
+    if prof["vcycles"]:
+        vg = prof["vcycle_bytes"] / (prof["vcycle_ms"] * 1e-3) / 1e9
+        out["vcycle"] = {"achieved": vg, "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                         "frac": vg / HBM_PEAK_GBS, "count": prof["vcycles"]}
+    pb.destroy()
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(wl, phys, budget_s=20.0):
     """The oracle (plain FP64 NumPy/SciPy, unchanged) on a bounded sample of the
     workload: whole implicit-Euler steps of the samples of its smallest group."""
@@ -108,6 +142,10 @@ def main():
                     help="advance the grid groups at the same time (one host thread and stream "
                          "each); more throughput, but overlapping kernels lengthen the per-launch "
                          "durations the roofline is computed from")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="time the gradient instead of plain steps: edf_adjoint over --steps steps "
+                         "(forward with checkpoints, then the backward sweep) of the salt mass in "
+                         "the lower-central box")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default fused-bottom levels instead of timing the choices")
     ap.add_argument("--mark-timed-region", action="store_true",
@@ -135,7 +173,9 @@ def main():
     prec = args.precision or wl.precision
     phys = synth.physics(wl.field_model)
     groups = [(g.nx, g.ny, g.nz, g.levels, g.samples) for g in wl.groups]
-    opts = dict(newton_rtol=wl.newton_rtol, lin_rtol=1e-6, lin_max_it=100, newton_max_it=20,
+    # the adjoint solves (transposed Jacobian, no Newton retry) get more Krylov iterations
+    opts = dict(newton_rtol=wl.newton_rtol, lin_rtol=1e-6, lin_max_it=400 if args.adjoint else 100,
+                newton_max_it=20,
                 precision=PREC_MIXED if prec == "mixed" else PREC_F64, check_every=1,
                 forcing=args.forcing, concurrent_groups=int(args.concurrent_groups))
     log(f"workload {wl.name}: groups {groups}, precision {prec}")
@@ -151,6 +191,8 @@ def main():
         pb.step(wl.dt)
         log(f"warmup step {w + 1}: {time.perf_counter() - t:.2f} s")
     torch.cuda.synchronize()
+    if args.adjoint:
+        return run_adjoint(args, wl, pb, prec)
     if not args.no_profile:
         pb.profile(True)
     stats = None

@@ -8,3 +8,8 @@ creating a Problem does, and fails loudly if libedf.so has not been built.
 from ._binding import (EDFError, EXPORTS, PREC_F64, PREC_MIXED, SAMPLE_LINEAR_FAIL,  # noqa: F401
                        SAMPLE_NEWTON_FAIL, SAMPLE_NONFINITE, SAMPLE_OK, Problem, create_problem,
                        default_options, load_library)
+
+try:  # the autograd wrapper needs torch; the C-ABI binding does not
+    from .autograd import ElderQoI, salt_mass  # noqa: F401
+except ImportError:  # pragma: no cover
+    pass

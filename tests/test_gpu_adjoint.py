@@ -97,3 +97,30 @@ def test_adjoint_through_split_steps():
         assert abs(J[s] - Jr) <= 1e-9 * abs(Jr)
         assert np.abs(g[s] - gr).max() <= 1e-6 * np.abs(gr).max()
     pb.destroy()
+
+
+def test_autograd_wrapper_gives_the_adjoint_gradient():
+    """ElderQoI (torch.autograd): J and xi.grad equal the library's edf_adjoint output,
+    the backward pass applies the incoming gradient per sample, and the problem's
+    states are the starting states again after the call."""
+    import torch
+    from paper_1906_01632_amd import salt_mass
+    nx, ny, nz = 17, 17, 5
+    phys = synth.physics(2)
+    xi0 = np.random.default_rng(4).uniform(-0.5, 0.5, (2, 4))
+    pb = _problem(phys, [(nx, ny, nz, 3, 2)])
+    pb.set_parameters(xi0)
+    u0 = [pb.get_state(s) for s in range(2)]
+    xi = torch.tensor(xi0, dtype=torch.float64, requires_grad=True)
+    J = salt_mass(xi, pb, BOX_UPPER, DT, 2)
+    w = torch.tensor([1.0, -2.5], dtype=torch.float64)
+    (w * J).sum().backward()
+    for s in range(2):
+        assert np.array_equal(pb.get_state(s), u0[s])
+    ref = _problem(phys, [(nx, ny, nz, 3, 2)])
+    ref.set_parameters(xi0)
+    Jr, gr = ref.adjoint(BOX_UPPER, DT, 2)
+    ref.destroy()
+    pb.destroy()
+    np.testing.assert_array_equal(J.detach().numpy(), Jr)
+    np.testing.assert_array_equal(xi.grad.numpy(), w.numpy()[:, None] * gr)
