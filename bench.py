@@ -88,7 +88,7 @@ def run_adjoint(args, wl, pb, prec):
            "value": wl.n_samples * args.steps / el, "unit": "sample-timesteps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64" if prec == "f64" else "f64+f32",
+           "dtype": {"f64": "f64", "mixed": "f64+f32", "mixed16": "f64+f32+f16"}[prec],
            "data": "synthetic (seeded lattice parameters; no dataset)",
            "config": {"workload": wl.name, "groups": [[q.nx, q.ny, q.nz, q.levels, q.samples]
                                                       for q in wl.groups],
@@ -133,7 +133,8 @@ def main():
     ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="qmc512_mixedres")
-    ap.add_argument("--precision", choices=["f64", "mixed"], default=None)
+    ap.add_argument("--precision", choices=["f64", "mixed", "mixed16"], default=None,
+                    help="V-cycle precision: FP64, FP32, or FP32 with the finest matrix in FP16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--forcing", type=int, default=1, choices=[0, 1],
@@ -165,7 +166,7 @@ def main():
     import torch
 
     import synth
-    from paper_1906_01632_amd import PREC_F64, PREC_MIXED, Problem
+    from paper_1906_01632_amd import PREC_F64, PREC_MIXED, PREC_MIXED_F16, Problem
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -176,7 +177,8 @@ def main():
     # the adjoint solves (transposed Jacobian, no Newton retry) get more Krylov iterations
     opts = dict(newton_rtol=wl.newton_rtol, lin_rtol=1e-6, lin_max_it=400 if args.adjoint else 100,
                 newton_max_it=20,
-                precision=PREC_MIXED if prec == "mixed" else PREC_F64, check_every=1,
+                precision={"f64": PREC_F64, "mixed": PREC_MIXED, "mixed16": PREC_MIXED_F16}[prec],
+                check_every=1,
                 forcing=args.forcing, concurrent_groups=int(args.concurrent_groups))
     log(f"workload {wl.name}: groups {groups}, precision {prec}")
     t = time.perf_counter()
@@ -229,7 +231,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == "f64" else "f64+f32",
+        "dtype": {"f64": "f64", "mixed": "f64+f32", "mixed16": "f64+f32+f16"}[prec],
         "data": "synthetic (seeded lattice parameters; no dataset)",
         "config": {"workload": wl.name, "groups": [list(g) for g in groups], "samples": S,
                    "dt_s": wl.dt, "precision": prec, "newton_rtol": wl.newton_rtol,

@@ -78,8 +78,11 @@ enum {
  * normalised so that KC(phi_mean) = K_mean). */
 enum { EDF_FIELD_CONST = 0, EDF_FIELD_COS1 = 1, EDF_FIELD_MODES4 = 2, EDF_FIELD_PAPER3 = 3 };
 
-enum { EDF_PREC_F64 = 0,   /* V-cycle in FP64                                       */
-       EDF_PREC_MIXED = 1  /* V-cycle in FP32 inside FP64 Newton/BiCGStab           */ };
+enum { EDF_PREC_F64 = 0,       /* V-cycle in FP64                                   */
+       EDF_PREC_MIXED = 1,     /* V-cycle in FP32 inside FP64 Newton/BiCGStab       */
+       EDF_PREC_MIXED_F16 = 2  /* as EDF_PREC_MIXED, with the finest level's matrix */
+                               /* stored in FP16, scaled by its diagonal-block      */
+                               /* inverse (unit diagonal blocks, O(1) entries)      */ };
 
 /* One resolution group: n_samples realisations on an nx*ny*nz vertex grid with an
  * n_levels-grid multigrid hierarchy (each coarser grid keeps every other vertex, so

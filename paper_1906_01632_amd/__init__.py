@@ -5,7 +5,8 @@ The binding only marshals arguments; every step of the time integration runs in
 the HIP kernels of the library.  Importing the package does not need a GPU;
 creating a Problem does, and fails loudly if libedf.so has not been built.
 """
-from ._binding import (EDFError, EXPORTS, PREC_F64, PREC_MIXED, SAMPLE_LINEAR_FAIL,  # noqa: F401
+from ._binding import (EDFError, EXPORTS, PREC_F64, PREC_MIXED, PREC_MIXED_F16,  # noqa: F401
+                       SAMPLE_LINEAR_FAIL,
                        SAMPLE_NEWTON_FAIL, SAMPLE_NONFINITE, SAMPLE_OK, Problem, create_problem,
                        default_options, load_library)
 

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libedf.so")
 EDF_OK = 0
 STATUS_NAMES = {1: "EDF_ERR_ARG", 2: "EDF_ERR_OOM", 3: "EDF_ERR_HIP", 4: "EDF_ERR_STATE",
                 5: "EDF_ERR_NO_CONVERGENCE", 6: "EDF_ERR_NONFINITE"}
-PREC_F64, PREC_MIXED = 0, 1
+PREC_F64, PREC_MIXED, PREC_MIXED_F16 = 0, 1, 2
 SAMPLE_OK, SAMPLE_NEWTON_FAIL, SAMPLE_LINEAR_FAIL, SAMPLE_NONFINITE = 0, 1, 2, 3
 SAMPLE_INADMISSIBLE = 4
 N_XI = {0: 0, 1: 1, 2: 4, 3: 3}

@@ -10,6 +10,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "adjoint.h"
@@ -30,6 +31,8 @@ struct Level {
   double* A64 = nullptr;  // [S][Np x 108] colour-major, packed (level 0: exact Jacobian)
   double* AV64 = nullptr; // level 0 in FP64 mode: the V-cycle matrix
   float* A32 = nullptr;   // V-cycle matrix in mixed mode
+  _Float16* A16 = nullptr;  // finest level with EDF_PREC_MIXED_F16: D^{-1} A in FP16 (Dinv
+                            // then holds the diagonal blocks D themselves, FP32)
   void* Dinv = nullptr;   // [S][Np x 4], V-cycle precision
   void* x = nullptr;      // V-cycle vectors [S][Np][2] colour-major, V-cycle precision
   void* b = nullptr;
@@ -72,6 +75,7 @@ struct Group {
   int n_coarse = 0;
   int n_active = 0;  // samples active in the current Krylov chunk (known at chunk start)
   int fuse_from = -1;  // levels from here on run in the fused launch (-1: not chosen yet)
+  int min_fuse = 0;    // 1 when the finest level has an FP16 matrix (separate launches)
   std::vector<double> tune_ms;  // V-cycle time per candidate fuse_from (autotuning)
   // per sample: halvings to start the next step with, steps since the last retry,
   // steps to wait before trying one halving less, whether this step is such a try
@@ -207,7 +211,12 @@ Phys make_phys(const edf_physics& P, const Geom& g, double dt) {
 // the unknowns are O(1) in scaled units, so further iterations only move rounding.
 constexpr double kUpdateFloor = 1e-14;
 
-bool mixed(const edf_problem* pb) { return pb->opts.precision == EDF_PREC_MIXED; }
+// the V-cycle runs in FP32 (EDF_PREC_MIXED, EDF_PREC_MIXED_F16)
+bool mixed(const edf_problem* pb) { return pb->opts.precision != EDF_PREC_F64; }
+// the finest level's V-cycle matrix is stored in FP16 (it must be a smoothed level)
+bool f16_finest(const edf_problem* pb, const Group& G) {
+  return pb->opts.precision == EDF_PREC_MIXED_F16 && G.L >= 2;
+}
 
 // ---------------------------------------------------------------------------
 // allocation of one group
@@ -218,6 +227,7 @@ edf_status alloc_group(edf_problem* pb, Group& G) {
   const bool mx = mixed(pb);
   const size_t tsz = mx ? sizeof(float) : sizeof(double);
   G.lv.resize(G.L);
+  G.min_fuse = f16_finest(pb, G) ? 1 : 0;
   int nx = G.d.nx, ny = G.d.ny, nz = G.d.nz;
   for (int l = 0; l < G.L; ++l) {
     Level& L = G.lv[l];
@@ -233,6 +243,8 @@ edf_status alloc_group(edf_problem* pb, Group& G) {
       if ((s = dalloc(pb, &L.A64, S * kPlanes * Np))) return s;
     if (mx && !coarsest)
       if ((s = dalloc(pb, &L.A32, S * kPlanes * Np))) return s;
+    if (l == 0 && f16_finest(pb, G))
+      if ((s = dalloc(pb, &L.A16, S * kPlanes * Np))) return s;
     if (l == 0 && (!mx || coarsest))
       if ((s = dalloc(pb, &L.AV64, S * kPlanes * Np))) return s;
     char* q;
@@ -329,7 +341,9 @@ edf_status assemble_all(edf_problem* pb, Group& G, const int* mask, const double
     float* m32 = (mx && !coarsest) ? L.A32 : nullptr;
     launch_assemble(L.g, L.ph, dts, L.phi, L.K, L.u, m64, m32, G.S, mask, G.st, true);
     if (!coarsest) {
-      if (mx)
+      if (l == 0 && f16_finest(pb, G))
+        launch_scale_f16(L.g, L.A32, L.A16, (float*)L.Dinv, G.S, mask, G.st);
+      else if (mx)
         launch_block_inverse_f32(L.g, L.A32, (float*)L.Dinv, G.S, mask, G.st);
       else
         launch_block_inverse_f64(L.g, m64, (double*)L.Dinv, G.S, mask, G.st);
@@ -390,8 +404,17 @@ edf_status prof_flush(edf_problem* pb, Group& G) {
 double vcycle_bytes(const Group& G, size_t tsz, int nu1, int nu2) {
   const double sw = nu1 + nu2;
   double b = 0;
-  for (int l = 0; l + 1 < G.L; ++l)
+  for (int l = 0; l + 1 < G.L; ++l) {
+    if (l == 0 && G.lv[0].A16) {
+      // FP16 finest level: per sweep 26 FP16 blocks, D^{-1} b, x in and out; the
+      // residual reads the blocks, D (FP32), D^{-1} b and x and writes r; r into the
+      // restriction, x in and out for the correction (FP32 vectors)
+      b += (double)G.lv[0].g.N * (sw * (26 * 4 * 2 + 6 * 4) + (26 * 4 * 2 + 4 * 4 + 6 * 4) +
+                                  2 * 4 + 4 * 4);
+      continue;
+    }
     b += (double)G.lv[l].g.N * ((sw + 1.0) * kPlanes + sw * 4 + (3.0 * sw + 6.0) * 2) * tsz;
+  }
   const double nc = G.n_coarse;
   return b + nc * nc * 8.0 + 2.0 * nc * tsz;
 }
@@ -405,7 +428,7 @@ double vcycle_bytes(const Group& G, size_t tsz, int nu1, int nu2) {
 // one after the other, which does not pay for a single sample)
 int first_fusable(const Group& G) {
   int l0 = G.L - 1;
-  while (l0 > 0 && G.lv[l0 - 1].g.N <= kFuseMaxN && G.L - l0 < kMaxFused) --l0;
+  while (l0 > G.min_fuse && G.lv[l0 - 1].g.N <= kFuseMaxN && G.L - l0 < kMaxFused) --l0;
   return l0;
 }
 int default_fuse_from(const Group& G) { return G.S >= 64 ? first_fusable(G) : G.L - 1; }
@@ -424,13 +447,40 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
   const int nu1 = pb->opts.nu_pre, nu2 = pb->opts.nu_post;
   T* b0 = (T*)G.lv[0].b;
   T* x0 = (T*)G.lv[0].x;
-  launch_to_colour<T>(G.lv[0].g, in, b0, S, mask, st);
-  // per vertex of the colour: 108 stencil + 4 block-inverse entries, b, x read and written
-  auto smooth = [&](const Level& L, int c, const T* b, T* x) {
+  // finest level with an FP16 matrix: b0 holds D^{-1} b (only for T = float)
+  const bool h0 = std::is_same<T, float>::value && G.L >= 2 && G.lv[0].A16;
+  if constexpr (std::is_same<T, float>::value) {
+    if (h0)
+      launch_to_colour_scaled(G.lv[0].g, in, (const float*)G.lv[0].Dinv, (float*)b0, S, mask, st);
+    else
+      launch_to_colour<T>(G.lv[0].g, in, b0, S, mask, st);
+  } else {
+    launch_to_colour<T>(G.lv[0].g, in, b0, S, mask, st);
+  }
+  // algorithmic bytes per vertex of the swept colour: 108 stencil + 4 block-inverse
+  // entries, b, own x read and written; FP16 finest level: the 26 off-diagonal blocks in
+  // FP16, D^{-1} b and x in FP32
+  auto smooth = [&](int l, const Level& L, int c, const T* b, T* x) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    const double bytes = (double)L.g.cnt[c] * G.n_active * 118.0 * sizeof(T);
-    prof_pair(G, e0, e1, bytes, 0);
+    const double per_vertex = (l == 0 && h0) ? 26.0 * 4 * 2 + 6.0 * 4 : 118.0 * sizeof(T);
+    prof_pair(G, e0, e1, (double)L.g.cnt[c] * G.n_active * per_vertex, 0);
+    if constexpr (std::is_same<T, float>::value) {
+      if (l == 0 && h0) {
+        launch_smooth_f16(L.g, c, L.A16, (const float*)b, (float*)x, S, mask, st, e0, e1);
+        return;
+      }
+    }
     launch_smooth<T>(L.g, c, stencil<T>(L), (const T*)L.Dinv, b, x, S, mask, st, e0, e1);
+  };
+  auto residual = [&](int l, const Level& L, const T* b, const T* x) {
+    if constexpr (std::is_same<T, float>::value) {
+      if (l == 0 && h0) {
+        launch_residual_f16(L.g, L.A16, (const float*)L.Dinv, (const float*)b, (const float*)x,
+                            (float*)L.r, S, mask, st);
+        return;
+      }
+    }
+    launch_residual<T>(L.g, stencil<T>(L), b, x, (T*)L.r, S, mask, st);
   };
   auto bx = [&](int l, T*& b, T*& x) {
     b = l == 0 ? b0 : (T*)G.lv[l].b;
@@ -444,8 +494,8 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
     T *b, *x;
     bx(l, b, x);
     for (int it = 0; it < nu1; ++it)
-      for (int c = 0; c < 8; ++c) smooth(L, c, b, x);
-    launch_residual<T>(L.g, stencil<T>(L), b, x, (T*)L.r, S, mask, st);
+      for (int c = 0; c < 8; ++c) smooth(l, L, c, b, x);
+    residual(l, L, b, x);
     T *bc, *xc;
     bx(l + 1, bc, xc);
     launch_restrict<T>(L.g, G.lv[l + 1].g, (const T*)L.r, bc, xc, S, mask, st);
@@ -475,7 +525,7 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
     bx(l + 1, bc, xc);
     launch_prolong<T>(L.g, G.lv[l + 1].g, xc, x, S, mask, st);
     for (int it = 0; it < nu2; ++it)
-      for (int c = 7; c >= 0; --c) smooth(L, c, b, x);
+      for (int c = 7; c >= 0; --c) smooth(l, L, c, b, x);
   }
   launch_from_colour<T>(G.lv[0].g, x0, out, S, mask, st);
 }
@@ -876,7 +926,10 @@ edf_status assemble_all_transposed(edf_problem* pb, Group& G, const int* mask, c
     launch_assemble(L.g, L.ph, dts, L.phi, L.K, L.u, G.tmpA, nullptr, G.S, mask, G.st, true);
     if (mx && !coarsest) {
       launch_transpose<float>(L.g, G.tmpA, L.A32, G.S, mask, G.st);
-      launch_block_inverse_f32(L.g, L.A32, (float*)L.Dinv, G.S, mask, G.st);
+      if (l == 0 && f16_finest(pb, G))
+        launch_scale_f16(L.g, L.A32, L.A16, (float*)L.Dinv, G.S, mask, G.st);
+      else
+        launch_block_inverse_f32(L.g, L.A32, (float*)L.Dinv, G.S, mask, G.st);
     } else {
       double* m64 = l == 0 ? L.AV64 : L.A64;
       launch_transpose<double>(L.g, G.tmpA, m64, G.S, mask, G.st);
@@ -1085,7 +1138,8 @@ edf_status edf_create_problem(const edf_physics* phys, const edf_group_desc* gro
   const int nxi_needed[4] = {0, 1, 4, 3};
   if (P.field_model < 0 || P.field_model > 3 || P.n_xi < nxi_needed[P.field_model] || P.n_xi > 16)
     return bad("invalid field model or n_xi");
-  if (opts->precision != EDF_PREC_F64 && opts->precision != EDF_PREC_MIXED)
+  if (opts->precision != EDF_PREC_F64 && opts->precision != EDF_PREC_MIXED &&
+      opts->precision != EDF_PREC_MIXED_F16)
     return bad("invalid precision");
   if (opts->newton_max_it < 1 || opts->lin_max_it < 1 || opts->nu_pre < 1 || opts->nu_post < 0 ||
       opts->ls_max_halvings < 0 || !(opts->lin_rtol > 0) || !(opts->newton_rtol >= 0))

@@ -94,6 +94,19 @@ void launch_prolong(const Geom& gf, const Geom& gc, const T* xc, T* xf, int S, c
                     hipStream_t st);
 template <typename T>
 void launch_fill(T* x, size_t per_sample, int S, const int* mask, T value, hipStream_t st);
+// FP16 finest level (EDF_PREC_MIXED_F16): from the FP32 matrix A32, the block-scaled
+// A16 = D^{-1} A (FP16, unit diagonal blocks) and the diagonal blocks D32 (FP32)
+void launch_scale_f16(const Geom& g, const float* A32, _Float16* A16, float* D32, int S,
+                      const int* mask, hipStream_t st);
+// block Gauss-Seidel with A16: x_v = bh_v - sum_{o != diag} A16_vo x_{v+o}, bh = D^{-1} b
+void launch_smooth_f16(const Geom& g, int colour, const _Float16* A16, const float* bh, float* x,
+                       int S, const int* mask, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
+// r = b - A x = D (bh - A16 x), zero in Dirichlet rows
+void launch_residual_f16(const Geom& g, const _Float16* A16, const float* D32, const float* bh,
+                         const float* x, float* r, int S, const int* mask, hipStream_t st);
+// entry: bh = D^{-1} b, FP64 natural [N][2] -> FP32 colour-major [Np][2]
+void launch_to_colour_scaled(const Geom& g, const double* in, const float* D32, float* out, int S,
+                             const int* mask, hipStream_t st);
 // finest-level V-cycle entry and exit: FP64 natural [N][2] <-> T colour-major [Np][2]
 template <typename T>
 void launch_to_colour(const Geom& g, const double* in, T* out, int S, const int* mask,

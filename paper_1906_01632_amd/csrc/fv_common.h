@@ -17,7 +17,7 @@ __device__ __forceinline__ int clampi(int a, int lo, int hi) { return a < lo ? l
 // are packed W at a time into 16-byte lane vectors (W = 2 doubles or 4 floats), so
 // one load per lane fetches W coefficients and a wave's load is 1 KiB contiguous.
 template <typename T>
-constexpr int kPack = 16 / (int)sizeof(T);
+constexpr int kPack = sizeof(T) == 2 ? 4 : 16 / (int)sizeof(T);  // FP16: one 2x2 block
 
 // index of value p (of P per vertex) at colour-major position t
 template <typename T>
@@ -33,23 +33,39 @@ __host__ __device__ __forceinline__ size_t soff(int p) {
   return (size_t)(p / W) * (kTile * W) + p % W;
 }
 
-// the 2x2 block (a00, a01, a10, a11) stored at values p..p+3 (p a multiple of 4), as
-// streaming loads: coefficients are read once per sweep and should not evict vectors
+// the 2x2 block (a00, a01, a10, a11) stored at values p..p+3 (p a multiple of 4).  NT:
+// streaming (non-temporal) loads for coefficients read once per sweep, which should not
+// evict the vectors; plain loads for the small coarse levels, which may stay cached from
+// one sweep to the next.  FP16 blocks are returned in FP32.
 typedef double nt_d2 __attribute__((ext_vector_type(2)));
 typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef _Float16 nt_h4 __attribute__((ext_vector_type(4)));
 template <typename T>
 struct Block2 {
   T a00, a01, a10, a11;
 };
+template <bool NT, typename V>
+__device__ __forceinline__ V load_vec(const V* p) {
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+template <bool NT = true>
 __device__ __forceinline__ Block2<double> load_block(const double* base, int p) {
-  const nt_d2 u = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(base + soff<double>(p)));
-  const nt_d2 w =
-      __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(base + soff<double>(p + 2)));
+  const nt_d2 u = load_vec<NT>(reinterpret_cast<const nt_d2*>(base + soff<double>(p)));
+  const nt_d2 w = load_vec<NT>(reinterpret_cast<const nt_d2*>(base + soff<double>(p + 2)));
   return {u.x, u.y, w.x, w.y};
 }
+template <bool NT = true>
 __device__ __forceinline__ Block2<float> load_block(const float* base, int p) {
-  const nt_f4 u = __builtin_nontemporal_load(reinterpret_cast<const nt_f4*>(base + soff<float>(p)));
+  const nt_f4 u = load_vec<NT>(reinterpret_cast<const nt_f4*>(base + soff<float>(p)));
   return {u.x, u.y, u.z, u.w};
+}
+template <bool NT = true>
+__device__ __forceinline__ Block2<float> load_block(const _Float16* base, int p) {
+  const nt_h4 u = load_vec<NT>(reinterpret_cast<const nt_h4*>(base + soff<_Float16>(p)));
+  return {(float)u.x, (float)u.y, (float)u.z, (float)u.w};
 }
 
 // colour-major position t -> vertex (i, j, k); false for padding positions

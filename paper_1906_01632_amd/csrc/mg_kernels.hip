@@ -36,7 +36,7 @@ struct V2<float> {
 // ---------------------------------------------------------------------------
 
 // block Gauss-Seidel update of vertex q of colour col: x_v += D_v^{-1} (b - A x)_v
-template <typename T>
+template <typename T, bool NT>
 __device__ __forceinline__ void smooth_vertex(const Geom& g, int col, int q, const T* A_s,
                                               const T* D_s, const T* b_s, T* x_s) {
   using T2 = typename V2<T>::type;
@@ -57,13 +57,13 @@ __device__ __forceinline__ void smooth_vertex(const Geom& g, int col, int q, con
       for (int dx = -1; dx <= 1; ++dx) {
         const int ii = clampi(i + dx, 0, g.nx - 1);
         const T2 xv = x[colour_encode(g, ii, jj, kk)];
-        const Block2<T> a = load_block(A, nb_index(dx, dy, dz) * 4);
+        const Block2<T> a = load_block<NT>(A, nb_index(dx, dy, dz) * 4);
         r0 -= a.a00 * xv.x + a.a01 * xv.y;
         r1 -= a.a10 * xv.x + a.a11 * xv.y;
       }
     }
   }
-  const Block2<T> d = load_block(D_s + sidx<T>(t, 0, 4), 0);
+  const Block2<T> d = load_block<NT>(D_s + sidx<T>(t, 0, 4), 0);
   T2 xv = x[t];
   xv.x += d.a00 * r0 + d.a01 * r1;
   xv.y += d.a10 * r0 + d.a11 * r1;
@@ -72,7 +72,7 @@ __device__ __forceinline__ void smooth_vertex(const Geom& g, int col, int q, con
 
 // residual r = b - A x at colour-major position t, zero in Dirichlet rows (their
 // equations are solved exactly by the smoother and carry no coarse-grid correction)
-template <typename T>
+template <typename T, bool NT>
 __device__ __forceinline__ void residual_vertex(const Geom& g, int t, const T* A_s,
                                                 const T* b_s, const T* x_s, T* r_s) {
   using T2 = typename V2<T>::type;
@@ -91,7 +91,7 @@ __device__ __forceinline__ void residual_vertex(const Geom& g, int t, const T* A
       for (int dx = -1; dx <= 1; ++dx) {
         const int ii = clampi(i + dx, 0, g.nx - 1);
         const T2 xv = x[colour_encode(g, ii, jj, kk)];
-        const Block2<T> a = load_block(A, nb_index(dx, dy, dz) * 4);
+        const Block2<T> a = load_block<NT>(A, nb_index(dx, dy, dz) * 4);
         a0 += a.a00 * xv.x + a.a01 * xv.y;
         a1 += a.a10 * xv.x + a.a11 * xv.y;
       }
@@ -180,7 +180,17 @@ __device__ __forceinline__ void prolong_vertex(const Geom& gf, const Geom& gc, i
 // ---------------------------------------------------------------------------
 // one launch per colour sweep / transfer (large grids)
 // ---------------------------------------------------------------------------
+// Matrices of at most this many bytes (all samples of a level) are read with plain
+// loads: the small levels' matrices can stay in the last-level cache across sweeps
+// and V-cycles, where the large levels' are streamed.
+constexpr double kCachedMatrixBytes = 64.0 * 1024 * 1024;
+
 template <typename T>
+bool stream_matrix(const Geom& g, int S) {
+  return (double)S * kPlanes * g.off[8] * sizeof(T) > kCachedMatrixBytes;
+}
+
+template <typename T, bool NT>
 __global__ __launch_bounds__(kBlock) void k_smooth(Geom g, int col, const T* A_all, const T* Dinv_all,
                                                    const T* b_all, T* x_all, const int* mask) {
   const int s = blockIdx.y;
@@ -188,8 +198,8 @@ __global__ __launch_bounds__(kBlock) void k_smooth(Geom g, int col, const T* A_a
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= g.cnt[col]) return;
   const size_t Np = g.off[8];
-  smooth_vertex<T>(g, col, q, A_all + (size_t)s * kPlanes * Np, Dinv_all + (size_t)s * 4 * Np,
-                   b_all + (size_t)s * 2 * Np, x_all + (size_t)s * 2 * Np);
+  smooth_vertex<T, NT>(g, col, q, A_all + (size_t)s * kPlanes * Np, Dinv_all + (size_t)s * 4 * Np,
+                       b_all + (size_t)s * 2 * Np, x_all + (size_t)s * 2 * Np);
 }
 
 template <typename T>
@@ -198,14 +208,15 @@ void launch_smooth(const Geom& g, int colour, const T* A, const T* Dinv, const T
   const int n = g.cnt[colour];
   if (n <= 0) return;
   dim3 grid(ceil_div(n, kBlock), S);
+  auto kern = stream_matrix<T>(g, S) ? k_smooth<T, true> : k_smooth<T, false>;
   if (ev0)  // timed launch: events recorded around this kernel only
-    hipExtLaunchKernelGGL(k_smooth<T>, grid, dim3(kBlock), 0, st, ev0, ev1, 0, g, colour, A, Dinv,
-                          b, x, mask);
+    hipExtLaunchKernelGGL(kern, grid, dim3(kBlock), 0, st, ev0, ev1, 0, g, colour, A, Dinv, b, x,
+                          mask);
   else
-    hipLaunchKernelGGL(k_smooth<T>, grid, dim3(kBlock), 0, st, g, colour, A, Dinv, b, x, mask);
+    hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, st, g, colour, A, Dinv, b, x, mask);
 }
 
-template <typename T>
+template <typename T, bool NT>
 __global__ __launch_bounds__(kBlock) void k_residual(Geom g, const T* A_all, const T* b_all,
                                                      const T* x_all, T* r_all, const int* mask) {
   const int s = blockIdx.y;
@@ -213,15 +224,16 @@ __global__ __launch_bounds__(kBlock) void k_residual(Geom g, const T* A_all, con
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= g.off[8]) return;
   const size_t Np = g.off[8];
-  residual_vertex<T>(g, t, A_all + (size_t)s * kPlanes * Np, b_all + (size_t)s * 2 * Np,
-                     x_all + (size_t)s * 2 * Np, r_all + (size_t)s * 2 * Np);
+  residual_vertex<T, NT>(g, t, A_all + (size_t)s * kPlanes * Np, b_all + (size_t)s * 2 * Np,
+                         x_all + (size_t)s * 2 * Np, r_all + (size_t)s * 2 * Np);
 }
 
 template <typename T>
 void launch_residual(const Geom& g, const T* A, const T* b, const T* x, T* r, int S,
                      const int* mask, hipStream_t st) {
   dim3 grid(ceil_div(g.off[8], kBlock), S);
-  hipLaunchKernelGGL(k_residual<T>, grid, dim3(kBlock), 0, st, g, A, b, x, r, mask);
+  auto kern = stream_matrix<T>(g, S) ? k_residual<T, true> : k_residual<T, false>;
+  hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, st, g, A, b, x, r, mask);
 }
 
 template <typename T>
@@ -258,6 +270,188 @@ void launch_prolong(const Geom& gf, const Geom& gc, const T* xc, T* xf, int S, c
                     hipStream_t st) {
   dim3 grid(ceil_div(gf.off[8], kBlock), S);
   hipLaunchKernelGGL(k_prolong<T>, grid, dim3(kBlock), 0, st, gf, gc, xc, xf, mask);
+}
+
+// ---------------------------------------------------------------------------
+// finest level with an FP16 matrix (EDF_PREC_MIXED_F16).  The FP32 matrix is scaled
+// by its diagonal-block inverses, A16_vo = D_v^{-1} A_vo, so the stored entries are
+// O(1) whatever the physical units and the diagonal blocks are exactly the identity
+// (not read back).  The smoother then needs no block inverse: with bh = D^{-1} b
+// (formed once at V-cycle entry), x_v = bh_v - sum_{o != diag} A16_vo x_{v+o}; the
+// residual is unscaled with the FP32 diagonal blocks D.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_scale_f16(Geom g, const float* A32_all,
+                                                      _Float16* A16_all, float* D_all,
+                                                      const int* mask) {
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int i, j, k;
+  if (t >= g.off[8] || !colour_decode(g, t, i, j, k)) return;
+  const size_t Np = g.off[8];
+  const float* a = A32_all + (size_t)s * kPlanes * Np + sidx<float>(t, 0, kPlanes);
+  _Float16* h = A16_all + (size_t)s * kPlanes * Np + sidx<_Float16>(t, 0, kPlanes);
+  const double d00 = a[soff<float>(kDiag * 4)], d01 = a[soff<float>(kDiag * 4 + 1)],
+               d10 = a[soff<float>(kDiag * 4 + 2)], d11 = a[soff<float>(kDiag * 4 + 3)];
+  const double det = d00 * d11 - d01 * d10;
+  const double id = det != 0.0 ? 1.0 / det : 0.0;
+  const double i00 = d11 * id, i01 = -d01 * id, i10 = -d10 * id, i11 = d00 * id;
+  for (int o = 0; o < 27; ++o) {
+    const double b00 = a[soff<float>(o * 4)], b01 = a[soff<float>(o * 4 + 1)],
+                 b10 = a[soff<float>(o * 4 + 2)], b11 = a[soff<float>(o * 4 + 3)];
+    double s00 = i00 * b00 + i01 * b10, s01 = i00 * b01 + i01 * b11;
+    double s10 = i10 * b00 + i11 * b10, s11 = i10 * b01 + i11 * b11;
+    if (o == kDiag) {
+      s00 = 1.0;
+      s01 = 0.0;
+      s10 = 0.0;
+      s11 = 1.0;
+    }
+    h[soff<_Float16>(o * 4)] = (_Float16)s00;
+    h[soff<_Float16>(o * 4 + 1)] = (_Float16)s01;
+    h[soff<_Float16>(o * 4 + 2)] = (_Float16)s10;
+    h[soff<_Float16>(o * 4 + 3)] = (_Float16)s11;
+  }
+  float* d = D_all + (size_t)s * 4 * Np + sidx<float>(t, 0, 4);
+  d[soff<float>(0)] = (float)d00;
+  d[soff<float>(1)] = (float)d01;
+  d[soff<float>(2)] = (float)d10;
+  d[soff<float>(3)] = (float)d11;
+}
+
+void launch_scale_f16(const Geom& g, const float* A32, _Float16* A16, float* D32, int S,
+                      const int* mask, hipStream_t st) {
+  dim3 grid(ceil_div(g.off[8], kBlock), S);
+  hipLaunchKernelGGL(k_scale_f16, grid, dim3(kBlock), 0, st, g, A32, A16, D32, mask);
+}
+
+template <bool NT>
+__global__ __launch_bounds__(kBlock) void k_smooth_f16(Geom g, int col, const _Float16* A_all,
+                                                       const float* bh_all, float* x_all,
+                                                       const int* mask) {
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= g.cnt[col]) return;
+  const size_t Np = g.off[8];
+  int i, j, k;
+  colour_decode_in(g, col, q, i, j, k);
+  const int t = g.off[col] + q;
+  const _Float16* A = A_all + (size_t)s * kPlanes * Np + sidx<_Float16>(t, 0, kPlanes);
+  float2* x = reinterpret_cast<float2*>(x_all + (size_t)s * 2 * Np);
+  const float2 bv = reinterpret_cast<const float2*>(bh_all + (size_t)s * 2 * Np)[t];
+  float r0 = bv.x, r1 = bv.y;
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int kk = clampi(k + dz, 0, g.nz - 1);
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int jj = clampi(j + dy, 0, g.ny - 1);
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int o = nb_index(dx, dy, dz);
+        if (o == kDiag) continue;  // the unit diagonal block
+        const int ii = clampi(i + dx, 0, g.nx - 1);
+        const float2 xv = x[colour_encode(g, ii, jj, kk)];
+        const Block2<float> a = load_block<NT>(A, o * 4);
+        r0 -= a.a00 * xv.x + a.a01 * xv.y;
+        r1 -= a.a10 * xv.x + a.a11 * xv.y;
+      }
+    }
+  }
+  x[t] = make_float2(r0, r1);
+}
+
+void launch_smooth_f16(const Geom& g, int colour, const _Float16* A16, const float* bh, float* x,
+                       int S, const int* mask, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  const int n = g.cnt[colour];
+  if (n <= 0) return;
+  dim3 grid(ceil_div(n, kBlock), S);
+  const bool stream = (double)S * kPlanes * g.off[8] * sizeof(_Float16) > kCachedMatrixBytes;
+  auto kern = stream ? k_smooth_f16<true> : k_smooth_f16<false>;
+  if (ev0)
+    hipExtLaunchKernelGGL(kern, grid, dim3(kBlock), 0, st, ev0, ev1, 0, g, colour, A16, bh, x,
+                          mask);
+  else
+    hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, st, g, colour, A16, bh, x, mask);
+}
+
+template <bool NT>
+__global__ __launch_bounds__(kBlock) void k_residual_f16(Geom g, const _Float16* A_all,
+                                                         const float* D_all, const float* bh_all,
+                                                         const float* x_all, float* r_all,
+                                                         const int* mask) {
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int i, j, k;
+  if (t >= g.off[8] || !colour_decode(g, t, i, j, k)) return;
+  const size_t Np = g.off[8];
+  const _Float16* A = A_all + (size_t)s * kPlanes * Np + sidx<_Float16>(t, 0, kPlanes);
+  const float2* x = reinterpret_cast<const float2*>(x_all + (size_t)s * 2 * Np);
+  float a0 = 0.f, a1 = 0.f;  // (A16 x)_v
+#pragma unroll 1
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int kk = clampi(k + dz, 0, g.nz - 1);
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int jj = clampi(j + dy, 0, g.ny - 1);
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int ii = clampi(i + dx, 0, g.nx - 1);
+        const float2 xv = x[colour_encode(g, ii, jj, kk)];
+        if (dx == 0 && dy == 0 && dz == 0) {
+          a0 += xv.x;
+          a1 += xv.y;
+        } else {
+          const Block2<float> a = load_block<NT>(A, nb_index(dx, dy, dz) * 4);
+          a0 += a.a00 * xv.x + a.a01 * xv.y;
+          a1 += a.a10 * xv.x + a.a11 * xv.y;
+        }
+      }
+    }
+  }
+  const float2 bv = reinterpret_cast<const float2*>(bh_all + (size_t)s * 2 * Np)[t];
+  const Block2<float> d = load_block<NT>(D_all + (size_t)s * 4 * Np + sidx<float>(t, 0, 4), 0);
+  const float u0 = bv.x - a0, u1 = bv.y - a1;
+  double cD;
+  float2 out;
+  out.x = is_pin(g, i, j, k) ? 0.f : d.a00 * u0 + d.a01 * u1;
+  out.y = is_cdir(g, i, j, k, cD) ? 0.f : d.a10 * u0 + d.a11 * u1;
+  reinterpret_cast<float2*>(r_all + (size_t)s * 2 * Np)[t] = out;
+}
+
+void launch_residual_f16(const Geom& g, const _Float16* A16, const float* D32, const float* bh,
+                         const float* x, float* r, int S, const int* mask, hipStream_t st) {
+  dim3 grid(ceil_div(g.off[8], kBlock), S);
+  const bool stream = (double)S * kPlanes * g.off[8] * sizeof(_Float16) > kCachedMatrixBytes;
+  auto kern = stream ? k_residual_f16<true> : k_residual_f16<false>;
+  hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, st, g, A16, D32, bh, x, r, mask);
+}
+
+__global__ __launch_bounds__(kBlock) void k_to_colour_scaled(Geom g, const double* in_all,
+                                                             const float* D_all, float* out_all,
+                                                             const int* mask) {
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int i, j, k;
+  if (t >= g.off[8] || !colour_decode(g, t, i, j, k)) return;
+  const size_t v = i + (size_t)g.nx * (j + (size_t)g.ny * k);
+  const double2 b = reinterpret_cast<const double2*>(in_all)[(size_t)s * g.N + v];
+  const float* d = D_all + (size_t)s * 4 * g.off[8] + sidx<float>(t, 0, 4);
+  const double d00 = d[soff<float>(0)], d01 = d[soff<float>(1)], d10 = d[soff<float>(2)],
+               d11 = d[soff<float>(3)];
+  const double det = d00 * d11 - d01 * d10;
+  const double id = det != 0.0 ? 1.0 / det : 0.0;
+  reinterpret_cast<float2*>(out_all)[(size_t)s * g.off[8] + t] =
+      make_float2((float)((d11 * b.x - d01 * b.y) * id), (float)((d00 * b.y - d10 * b.x) * id));
+}
+
+void launch_to_colour_scaled(const Geom& g, const double* in, const float* D32, float* out, int S,
+                             const int* mask, hipStream_t st) {
+  hipLaunchKernelGGL(k_to_colour_scaled, dim3(ceil_div(g.off[8], kBlock), S), dim3(kBlock), 0, st,
+                     g, in, D32, out, mask);
 }
 
 // ---------------------------------------------------------------------------
@@ -481,10 +675,12 @@ __global__ __launch_bounds__(kFusedThreads) void k_vcycle_bottom(FusedLevels<T> 
     const Geom& g = F.g[l];
     for (int it = 0; it < F.nu1; ++it)
       for (int c = 0; c < 8; ++c) {
-        for (int q = tid; q < g.cnt[c]; q += nt) smooth_vertex<T>(g, c, q, A(l), D(l), B(l), X(l));
+        for (int q = tid; q < g.cnt[c]; q += nt)
+          smooth_vertex<T, false>(g, c, q, A(l), D(l), B(l), X(l));
         __syncthreads();
       }
-    for (int t = tid; t < g.off[8]; t += nt) residual_vertex<T>(g, t, A(l), B(l), X(l), Rv(l));
+    for (int t = tid; t < g.off[8]; t += nt)
+      residual_vertex<T, false>(g, t, A(l), B(l), X(l), Rv(l));
     __syncthreads();
     for (int t = tid; t < F.g[l + 1].off[8]; t += nt)
       restrict_vertex<T>(g, F.g[l + 1], t, Rv(l), B(l + 1), X(l + 1));
@@ -520,7 +716,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_vcycle_bottom(FusedLevels<T> 
     __syncthreads();
     for (int it = 0; it < F.nu2; ++it)
       for (int c = 7; c >= 0; --c) {
-        for (int q = tid; q < g.cnt[c]; q += nt) smooth_vertex<T>(g, c, q, A(l), D(l), B(l), X(l));
+        for (int q = tid; q < g.cnt[c]; q += nt)
+          smooth_vertex<T, false>(g, c, q, A(l), D(l), B(l), X(l));
         __syncthreads();
       }
   }

@@ -28,7 +28,7 @@ def _problem(phys, groups, **opts):
     return Problem(phys, groups, o)
 
 
-@pytest.mark.parametrize("model,precision", [(2, 0), (3, 0), (2, 1)])
+@pytest.mark.parametrize("model,precision", [(2, 0), (3, 0), (2, 1), (2, 2)])
 def test_adjoint_gradient_matches_oracle_tangent_linear(model, precision):
     nx, ny, nz = 17, 17, 5
     phys = synth.physics(model)

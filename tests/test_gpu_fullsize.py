@@ -89,14 +89,15 @@ def test_qmc_groups_step_solves_the_oracle_system():
 
 def test_mixed_257_matches_fp64_and_solves_the_oracle_system():
     """The mixed-precision workload's shapes: a 257x257x65 sample and a 129x129x33 sample,
-    FP32 V-cycle; the result agrees with the FP64-V-cycle result to 1e-6 relative L2 per
-    field, and the oracle's residual at the mixed result meets the Newton tolerance."""
+    FP32 V-cycle (and FP32 with the finest matrix stored in FP16); each result agrees
+    with the FP64-V-cycle result to 1e-6 relative L2 per field, and the oracle's
+    residual at the mixed result meets the Newton tolerance."""
     wl = synth.workload("mixed257")
     phys = synth.physics(wl.field_model)
     groups = [(257, 257, 65, 7, 1), (129, 129, 33, 6, 1)]
     xi = wl.xi[:2]
     out = {}
-    for prec in (1, 0):
+    for prec in (2, 1, 0):
         pb = _problem(phys, groups, newton_rtol=wl.newton_rtol, precision=prec)
         pb.set_parameters(xi)
         st = pb.step(DT)
@@ -104,13 +105,15 @@ def test_mixed_257_matches_fp64_and_solves_the_oracle_system():
         out[prec] = [pb.get_state(s) for s in range(2)]
         out[("sub", prec)] = [s["substeps"] for s in st]
         pb.destroy()
-    assert out[("sub", 0)] == out[("sub", 1)]
-    for s in range(2):
-        for f in range(2):
-            a, b = out[1][s][..., f], out[0][s][..., f]
-            rel = np.linalg.norm(a - b) / np.linalg.norm(b)
-            print(f"sample {s} field {f}: mixed vs FP64 rel L2 {rel:.2e}", flush=True)
-            assert rel <= 1e-6
+    for prec in (1, 2):  # FP32 V-cycle; FP32 with the finest matrix in FP16
+        assert out[("sub", 0)] == out[("sub", prec)]
+        for s in range(2):
+            for f in range(2):
+                a, b = out[prec][s][..., f], out[0][s][..., f]
+                rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+                print(f"precision {prec} sample {s} field {f}: vs FP64 rel L2 {rel:.2e}",
+                      flush=True)
+                assert rel <= 1e-6
     if out[("sub", 1)][0] != 1:
         return  # the step was split; the state does not solve the full-step system
     nx, ny, nz = 257, 257, 65

@@ -234,7 +234,7 @@ def test_mixed_resolution_groups_and_moments():
     pb.destroy()
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_vcycle_is_a_contraction(precision):
     """One V-cycle reduces the residual of the Newton matrix by a solid factor."""
     nx, ny, nz = 33, 33, 9
@@ -252,7 +252,7 @@ def test_vcycle_is_a_contraction(precision):
     pb.destroy()
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_vcycle_same_for_every_fused_bottom(precision):
     """The V-cycle gives the same result whichever levels run in the fused bottom launch
     (same per-vertex arithmetic in the same colour order), and set_tuning rejects levels
@@ -348,11 +348,12 @@ def test_profile_counts_launches_and_algorithmic_bytes():
     pb.destroy()
 
 
-def test_mixed_precision_step_matches_fp64_oracle():
+@pytest.mark.parametrize("precision", [1, 2])
+def test_mixed_precision_step_matches_fp64_oracle(precision):
     nx, ny, nz = 33, 33, 9
     phys = synth.physics(2)
     xi = _xi(2, 1, seed=6)
-    pb = _problem(phys, [(nx, ny, nz, 4, 1)], precision=1)
+    pb = _problem(phys, [(nx, ny, nz, 4, 1)], precision=precision)
     pb.set_parameters(xi)
     pb.step(DT)
     box = elder.Box(nx, ny, nz, phys)
