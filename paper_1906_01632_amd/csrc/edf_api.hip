@@ -76,6 +76,8 @@ struct Group {
   int n_active = 0;  // samples active in the current Krylov chunk (known at chunk start)
   int fuse_from = -1;  // levels from here on run in the fused launch (-1: not chosen yet)
   int min_fuse = 0;    // 1 when the finest level has an FP16 matrix (separate launches)
+  void* fdesc = nullptr;  // device copy of the fused-bottom description (FusedLevels<T>)
+  int fdesc_l0 = -1;      // the first fused level it describes (-1: not written yet)
   std::vector<double> tune_ms;  // V-cycle time per candidate fuse_from (autotuning)
   // per sample: halvings to start the next step with, steps since the last retry,
   // steps to wait before trying one halving less, whether this step is such a try
@@ -283,6 +285,11 @@ edf_status alloc_group(edf_problem* pb, Group& G) {
   if ((s = dalloc(pb, &G.eta, (size_t)S))) return s;
   if ((s = dalloc(pb, &G.crange, 2 * (size_t)S))) return s;
   if ((s = dalloc(pb, &G.u0, S * n))) return s;
+  {
+    char* q;
+    if ((s = dalloc(pb, &q, sizeof(FusedLevels<double>)))) return s;
+    G.fdesc = q;
+  }
   G.n_coarse = 2 * G.lv[G.L - 1].g.N;
   const size_t nc = G.n_coarse;
   if ((s = dalloc(pb, &G.Minv, S * nc * nc))) return s;
@@ -516,7 +523,12 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
       F.r[k] = coarsest ? nullptr : (T*)L.r;
       bx(l0 + k, F.b[k], F.x[k]);
     }
-    launch_vcycle_bottom<T>(F, S, mask, st);
+    if (G.fdesc_l0 != l0) {  // the description changes only with the first fused level
+      (void)hipMemcpyAsync(G.fdesc, &F, sizeof(F), hipMemcpyHostToDevice, st);
+      (void)hipStreamSynchronize(st);
+      G.fdesc_l0 = l0;
+    }
+    launch_vcycle_bottom<T>((const FusedLevels<T>*)G.fdesc, S, mask, st);
   }
   for (int l = l0 - 1; l >= 0; --l) {
     Level& L = G.lv[l];

@@ -121,7 +121,9 @@ void launch_gauss_jordan(int n, double* M, int* piv, int* status, int S, const i
 
 // The bottom of a V-cycle run by one workgroup per sample: levels 0..n-2 of this
 // struct are smoothed, level n-1 is solved with the dense inverse.  Array pointers
-// are the all-sample bases of the respective level.
+// are the all-sample bases of the respective level.  The kernel reads the struct from
+// device memory (indexing a by-value kernel argument with the runtime level number
+// would copy it to per-lane scratch).
 constexpr int kMaxFused = 6;
 constexpr int kFuseMaxN = 4096;  // levels with at most this many vertices are fused
 template <typename T>
@@ -136,7 +138,7 @@ struct FusedLevels {
   const double* Minv;
 };
 template <typename T>
-void launch_vcycle_bottom(const FusedLevels<T>& F, int S, const int* mask, hipStream_t st);
+void launch_vcycle_bottom(const FusedLevels<T>* F_dev, int S, const int* mask, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Krylov / Newton kernels (krylov_kernels.hip), FP64 vectors of n = 2N per sample

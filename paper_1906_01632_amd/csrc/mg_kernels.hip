@@ -70,12 +70,24 @@ __device__ __forceinline__ void smooth_vertex(const Geom& g, int col, int q, con
   x[t] = xv;
 }
 
-// residual r = b - A x at colour-major position t, zero in Dirichlet rows (their
-// equations are solved exactly by the smoother and carry no coarse-grid correction)
+// residual r = b - A x at colour-major position t after the pre-smoothing sweeps, zero
+// in Dirichlet rows (their equations are solved exactly by the smoother and carry no
+// coarse-grid correction) and in the rows of the last colour swept (colour 7: block
+// Gauss-Seidel has just solved them with all their neighbours final, so their residual
+// is zero up to rounding)
 template <typename T, bool NT>
 __device__ __forceinline__ void residual_vertex(const Geom& g, int t, const T* A_s,
                                                 const T* b_s, const T* x_s, T* r_s) {
   using T2 = typename V2<T>::type;
+  if (t >= g.off[7]) {
+    if (t - g.off[7] < g.cnt[7]) {
+      T2 z;
+      z.x = 0;
+      z.y = 0;
+      reinterpret_cast<T2*>(r_s)[t] = z;
+    }
+    return;
+  }
   int i, j, k;
   if (!colour_decode(g, t, i, j, k)) return;
   const T* A = A_s + sidx<T>(t, 0, kPlanes);
@@ -183,7 +195,7 @@ __device__ __forceinline__ void prolong_vertex(const Geom& gf, const Geom& gc, i
 // Matrices of at most this many bytes (all samples of a level) are read with plain
 // loads: the small levels' matrices can stay in the last-level cache across sweeps
 // and V-cycles, where the large levels' are streamed.
-constexpr double kCachedMatrixBytes = 64.0 * 1024 * 1024;
+constexpr double kCachedMatrixBytes = 128.0 * 1024 * 1024;
 
 template <typename T>
 bool stream_matrix(const Geom& g, int S) {
@@ -384,9 +396,14 @@ __global__ __launch_bounds__(kBlock) void k_residual_f16(Geom g, const _Float16*
   const int s = blockIdx.y;
   if (mask && !mask[s]) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int i, j, k;
-  if (t >= g.off[8] || !colour_decode(g, t, i, j, k)) return;
   const size_t Np = g.off[8];
+  if (t >= g.off[7]) {  // the last colour swept: zero residual (see residual_vertex)
+    if (t < g.off[8] && t - g.off[7] < g.cnt[7])
+      reinterpret_cast<float2*>(r_all + (size_t)s * 2 * Np)[t] = make_float2(0.f, 0.f);
+    return;
+  }
+  int i, j, k;
+  if (!colour_decode(g, t, i, j, k)) return;
   const _Float16* A = A_all + (size_t)s * kPlanes * Np + sidx<_Float16>(t, 0, kPlanes);
   const float2* x = reinterpret_cast<const float2*>(x_all + (size_t)s * 2 * Np);
   float a0 = 0.f, a1 = 0.f;  // (A16 x)_v
@@ -658,7 +675,9 @@ void launch_gauss_jordan(int n, double* M, int* piv, int* status, int S, const i
 constexpr int kFusedThreads = 1024;
 
 template <typename T>
-__global__ __launch_bounds__(kFusedThreads) void k_vcycle_bottom(FusedLevels<T> F, const int* mask) {
+__global__ __launch_bounds__(kFusedThreads) void k_vcycle_bottom(const FusedLevels<T>* __restrict__ Fp,
+                                                                 const int* mask) {
+  const FusedLevels<T>& F = *Fp;
   const int s = blockIdx.x;
   if (mask && !mask[s]) return;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -724,7 +743,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_vcycle_bottom(FusedLevels<T> 
 }
 
 template <typename T>
-void launch_vcycle_bottom(const FusedLevels<T>& F, int S, const int* mask, hipStream_t st) {
+void launch_vcycle_bottom(const FusedLevels<T>* F, int S, const int* mask, hipStream_t st) {
   hipLaunchKernelGGL(k_vcycle_bottom<T>, dim3(S), dim3(kFusedThreads), 0, st, F, mask);
 }
 
@@ -743,7 +762,7 @@ void launch_vcycle_bottom(const FusedLevels<T>& F, int S, const int* mask, hipSt
                                     hipStream_t);                                                \
   template void launch_from_colour<T>(const Geom&, const T*, double*, int, const int*,           \
                                       hipStream_t);                                              \
-  template void launch_vcycle_bottom<T>(const FusedLevels<T>&, int, const int*, hipStream_t);
+  template void launch_vcycle_bottom<T>(const FusedLevels<T>*, int, const int*, hipStream_t);
 EDF_INST(double)
 EDF_INST(float)
 template void launch_fill<int>(int*, size_t, int, const int*, int, hipStream_t);
