@@ -401,3 +401,87 @@ def test_tangent_linear_gradient_matches_finite_differences():
                           gradient.forward(box, xi - e, u0, dts)[-1], S)
         fd = (Jp - Jm) / (2 * h)
         assert abs(g[m] - fd) <= 1e-5 * np.abs(g).max(), (m, g[m], fd)
+
+
+# ---------------------------------------------------- manufactured solution -----
+
+def _mms_fields(ph, x, y, z, P=1.0e4):
+    """A smooth manufactured state: p = rho0 g z + P cos cos cos, c = 0.5 + 0.3 sin sin
+    cos (values in [0.2, 0.8]), with their exact gradients."""
+    lx, ly, lz = ph["lx"], ph["ly"], ph["lz"]
+    sx, cx = np.sin(np.pi * x / lx), np.cos(np.pi * x / lx)
+    sy, cy = np.sin(np.pi * y / ly), np.cos(np.pi * y / ly)
+    sz, cz = np.sin(np.pi * z / lz), np.cos(np.pi * z / lz)
+    p = ph["rho0"] * ph["g"] * z + P * cx * cy * cz
+    dp = (-P * np.pi / lx * sx * cy * cz, -P * np.pi / ly * cx * sy * cz,
+          ph["rho0"] * ph["g"] - P * np.pi / lz * cx * cy * sz)
+    c = 0.5 + 0.3 * sx * sy * cz
+    dc = (0.3 * np.pi / lx * cx * sy * cz, 0.3 * np.pi / ly * sx * cy * cz,
+          -0.3 * np.pi / lz * sx * sy * sz)
+    return p, dp, c, dc
+
+
+def _mms_exact_fluxes(ph, x, y, z):
+    """The continuous liquid and salt flux vectors of Section 2.1 (eqs. e_cont_eq,
+    e_tran_eq, e_Darcy_vel) at points, for constant phi and K."""
+    _, dp, c, dc = _mms_fields(ph, x, y, z)
+    rho = ph["rho0"] + (ph["rho1"] - ph["rho0"]) * c
+    kmu = ph["K_mean"] / ph["mu"]
+    q = (-kmu * dp[0], -kmu * dp[1], -kmu * (dp[2] - rho * ph["g"]))
+    Fl = [rho * qd for qd in q]
+    Fs = [rho * c * qd - rho * ph["phi_mean"] * ph["Dm"] * dcd for qd, dcd in zip(q, dc)]
+    return Fl, Fs
+
+
+def _mms_truncation(ph, n):
+    """Finite-volume flux sums of the manufactured state minus the exact outward fluxes
+    through the dual cells of the interior vertices (4x4 Gauss-Legendre per face),
+    divided by the cell volume: the consistency error density of both rows."""
+    nz = (n - 1) // 4 + 1
+    box = elder.Box(n, n, nz, ph)
+    coef = elder.coefficients(box, np.zeros(0))
+    p, _, c, _ = _mms_fields(ph, box.x, box.y, box.z)
+    u = np.stack([p, c], axis=-1)
+    Fl, Fs = elder.fv_rows(box, coef, u, u, 1.0)  # u_old = u: no storage term
+    sl = (slice(1, -1),) * 3
+    ctr = [box.x[sl], box.y[sl], box.z[sl]]
+    gx, gw = np.polynomial.legendre.leggauss(4)
+    el, es = np.zeros_like(ctr[0]), np.zeros_like(ctr[0])
+    for d in range(3):
+        o = [e for e in range(3) if e != d]
+        for sgn in (1.0, -1.0):
+            for a, wa in zip(gx, gw):
+                for b, wb in zip(gx, gw):
+                    pt = list(ctr)
+                    pt[d] = pt[d] + sgn * box.h[d] / 2
+                    pt[o[0]] = pt[o[0]] + a * box.h[o[0]] / 2
+                    pt[o[1]] = pt[o[1]] + b * box.h[o[1]] / 2
+                    fl, fs = _mms_exact_fluxes(ph, *pt)
+                    w = sgn * wa * wb * box.h[o[0]] * box.h[o[1]] / 4
+                    el += w * fl[d]
+                    es += w * fs[d]
+    V = np.prod(box.h)
+    return (Fl[sl] - el) / V, (Fs[sl] - es) / V
+
+
+def test_manufactured_solution_consistency_orders():
+    """Consistency of the discrete fluxes with the PDE under refinement (h = 37.5,
+    18.75, 9.375 m): the liquid row (central, trilinear gradients at the face points)
+    is second order, the salt row first order (full upwinding of the advected salt),
+    and its diffusion part alone second order.  A dropped or mis-scaled flux term
+    leaves an O(1) error and an order near zero."""
+    ph = synth.physics(0)
+    diff_only = dict(ph, K_mean=1e-30)
+    el, es, ed = [], [], []
+    for n in (17, 33, 65):
+        tl, ts = _mms_truncation(ph, n)
+        _, td = _mms_truncation(diff_only, n)
+        el.append(np.abs(tl).max())
+        es.append(np.sqrt(np.mean(ts ** 2)))
+        ed.append(np.sqrt(np.mean(td ** 2)))
+    order = lambda e: math.log2(e[-2] / e[-1])
+    print("liquid", el, order(el), "salt", es, order(es), "salt diffusion", ed, order(ed))
+    assert order(el) > 1.8
+    assert order(es) > 0.9
+    assert order(ed) > 1.8
+    assert el[-1] < 0.05 * 7e-6 and es[-1] < 0.05 * 8e-6  # small against the flux divergence
