@@ -10,5 +10,7 @@ Modules:
   stats   - weighted mean, variance and exceedance probability (Section 3, eqs. pdestat,
             numer_var; Section 3.2 exceedance estimate)
   gradient - salt mass in a subregion and its tangent-linear gradient in xi
+  gpc     - Legendre polynomial chaos surrogate: projection, moments, exceedance
+            (Section 3.1 and the appendix)
 """
-from . import elder, gradient, newton, stats  # noqa: F401
+from . import elder, gpc, gradient, newton, stats  # noqa: F401

@@ -485,3 +485,92 @@ def test_manufactured_solution_consistency_orders():
     assert order(es) > 0.9
     assert order(ed) > 1.8
     assert el[-1] < 0.05 * 7e-6 and es[-1] < 0.05 * 8e-6  # small against the flux divergence
+
+
+# ---------------------------------------------------------- polynomial chaos -----
+
+def test_legendre_matches_the_printed_polynomials():
+    """psi_0..psi_5 of the recursion equal the appendix's list (psi_3 as the recursion
+    gives it; the printed psi_3 is not a Legendre polynomial: it fails orthogonality)."""
+    from oracle import gpc
+    g = _load("legendre.json")
+    x = np.linspace(-1.0, 1.0, 41)
+    for n, c in g["psi"].items():
+        ref = np.polynomial.polynomial.polyval(x, c)
+        assert np.abs(gpc.legendre(int(n), x) - ref).max() < 1e-14
+    printed = np.polynomial.polynomial.polyval(x, g["psi3_as_printed"])
+    xq, wq = np.polynomial.legendre.leggauss(8)
+    pr = np.polynomial.polynomial.polyval(xq, g["psi3_as_printed"])
+    assert abs(np.sum(wq * pr * gpc.legendre(1, xq))) > 0.1   # printed form is not orthogonal
+    assert np.abs(printed - gpc.legendre(3, x)).max() > 0.1
+
+
+def test_legendre_orthogonality_and_norms():
+    """<psi_m, psi_n> = delta_mn / (2n + 1) under the uniform density, with a
+    Gauss-Legendre rule exact for degree <= 11."""
+    from oracle import gpc
+    nodes, w = gpc.tensor_gauss_legendre(1, 6)
+    x = nodes[:, 0]
+    assert abs(w.sum() - 1.0) < 1e-15
+    for m in range(6):
+        for n in range(6):
+            got = np.sum(w * gpc.legendre(m, x) * gpc.legendre(n, x))
+            assert abs(got - (1.0 / (2 * n + 1) if m == n else 0.0)) < 1e-14
+
+
+def test_multi_index_sets():
+    from oracle import gpc
+    assert len(gpc.multi_indices(3, 4)) == math.comb(7, 4) == 35
+    assert len(gpc.multi_indices(4, 4)) == math.comb(8, 4)
+    assert len(gpc.multi_indices(3, 2, truncation=1)) == 27
+    assert gpc.multi_indices(2, 2) == [(0, 0), (1, 0), (0, 1), (2, 0), (1, 1), (0, 2)]
+    J = gpc.multi_indices(3, 3, truncation=1)
+    assert len(set(J)) == len(J) and max(max(b) for b in J) == 3
+    assert [sum(b) for b in J] == sorted(sum(b) for b in J)
+
+
+def test_projection_recovers_a_polynomial_field():
+    """Fields that are gPC polynomials of degree <= p are projected back to their own
+    coefficients by a tensor Gauss-Legendre rule with p + 1 points per direction."""
+    from oracle import gpc
+    rng = np.random.default_rng(7)
+    for M, p, trunc in ((3, 4, 0), (2, 3, 1), (1, 5, 0)):
+        J = gpc.multi_indices(M, p, trunc)
+        true = rng.standard_normal((len(J), 5, 4))
+        nodes, w = gpc.tensor_gauss_legendre(M, p + 1)
+        fields = gpc.surrogate(true, J, nodes)
+        got = gpc.project(fields, nodes, w, J)
+        assert np.abs(got - true).max() < 1e-12
+
+
+def test_gpc_moments_closed_form():
+    """f = a + b th1 + c th1 th2 + d psi_2(th3): mean a, variance b^2/3 + c^2/9 + d^2/5,
+    from the coefficients (eqs. PCEcoef2, var) and equal to the quadrature moments."""
+    from oracle import gpc
+    a, b, c, d = 0.4, -0.3, 0.7, 0.2
+    J = gpc.multi_indices(3, 2)
+    nodes, w = gpc.tensor_gauss_legendre(3, 3)
+    t = nodes
+    f = a + b * t[:, 0] + c * t[:, 0] * t[:, 1] + d * gpc.legendre(2, t[:, 2])
+    coef = gpc.project(f[:, None], nodes, w, J)
+    mean, var = gpc.moments(coef, J)
+    assert abs(mean[0] - a) < 1e-15
+    assert abs(var[0] - (b * b / 3 + c * c / 9 + d * d / 5)) < 1e-15
+    m2, v2, _ = stats.moments(f[:, None], w)
+    assert abs(m2[0] - a) < 1e-15 and abs(v2[0] - var[0]) < 1e-15
+
+
+def test_surrogate_exceedance():
+    """For c = th1, P(c > t) = (1 - t)/2: the sampled estimate (Section 3.2) lies within
+    four standard errors, and equals a direct count."""
+    from oracle import gpc
+    J = gpc.multi_indices(2, 1)
+    coef = np.zeros((len(J), 3))
+    coef[1] = 1.0                                   # beta = (1, 0): psi_1(th1) = th1
+    pts = np.random.default_rng(3).uniform(-1, 1, (200000, 2))
+    t = np.array([-0.5, 0.1, 0.8])
+    got = np.array([gpc.exceedance(coef[:, q:q + 1], J, pts, t[q])[0] for q in range(3)])
+    ref = (1.0 - t) / 2.0
+    se = np.sqrt(ref * (1 - ref) / len(pts))
+    assert np.all(np.abs(got - ref) < 4 * se)
+    assert np.array_equal(got, np.array([np.mean(pts[:, 0] > tq) for tq in t]))
