@@ -185,6 +185,35 @@ edf_status edf_solve(edf_problem* pb, double dt, int32_t n_steps, edf_step_stats
 edf_status edf_moments(edf_problem* pb, int32_t cx, int32_t cy, int32_t cz, double threshold,
                        const double* weights, double* mean, double* var, double* exceed);
 
+/* Polynomial chaos surrogate of c from the samples of group `group` (Section 3.1,
+ * eqs. PCEdecom2, PCEcoef, PCEcoef2, var; appendix).  The samples are the quadrature
+ * nodes: theta_i = xi_i (the parameters of edf_set_parameters, M = n_xi in [1, 4]), with
+ * probability weights `weights` (host [S_group], e.g. tensor Gauss-Legendre weights
+ * times 2^-M).  Basis Psi_beta(theta) = prod_j psi_{beta_j}(theta_j), psi_n the Legendre
+ * polynomials of the appendix's recursion; multi-indices with total degree <= degree
+ * (truncation 0) or every degree <= degree (truncation 1), degree <= 8, at most 128 of
+ * them, ordered by total degree and then decreasingly lexicographic (M = 2: (0,0), (1,0),
+ * (0,1), (2,0), (1,1), (0,2), ...).  The c field of every sample is injected to the
+ * common vertex set (cx, cy, cz), which must be nested in the group's grid, and
+ *   c_beta(x) = sum_i w_i Psi_beta(theta_i) c(x, theta_i) / Q_beta,
+ *   Q_beta = prod_j 1/(2 beta_j + 1);  mean = c_0;  var = sum_{beta != 0} Q_beta c_beta^2.
+ * Outputs: *n_coef; coef (host [n_coef][cz][cy][cx] or NULL); mean, var (host
+ * [cz][cy][cx]); kernel_ms (or NULL): duration of the projection kernel.  The
+ * coefficients stay in the problem for edf_gpc_exceed.  Synchronises. */
+edf_status edf_gpc_project(edf_problem* pb, int32_t group, int32_t cx, int32_t cy, int32_t cz,
+                           int32_t degree, int32_t truncation, const double* weights,
+                           int32_t* n_coef, double* coef, double* mean, double* var,
+                           double* kernel_ms);
+
+/* Exceedance probability of the last edf_gpc_project surrogate (eq. PCEpoint and the
+ * count under it, Section 3.2): at every common-grid vertex,
+ *   P(c > threshold) ~ #{s : sum_beta c_beta Psi_beta(theta_s) > threshold} / n_points
+ * over the points theta (host [n_points][M] in [-1,1]^M; the caller draws them).  The
+ * surrogate is evaluated in FP64.  prob: host [cz][cy][cx]; kernel_ms (or NULL): the
+ * duration of the evaluation kernel.  EDF_ERR_STATE without a projection.  Synchronises. */
+edf_status edf_gpc_exceed(edf_problem* pb, int32_t n_points, const double* theta, double threshold,
+                          double* prob, double* kernel_ms);
+
 /* Discrete adjoint (the gradient of a quantity of interest with respect to the field
  * parameters xi).  Runs n_steps implicit-Euler steps of length dt from the current
  * states (as edf_step, keeping a checkpoint at the start of every step; steps that

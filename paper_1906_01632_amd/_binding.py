@@ -75,6 +75,9 @@ _SIGS = {
     "edf_apply_vcycle": [_P, C.c_int32, C.c_double, _D, _D],
     "edf_apply_jacobian": [_P, C.c_int32, _D, _D],
     "edf_adjoint": [_P, _D, C.c_double, C.c_int32, _D, _D],
+    "edf_gpc_project": [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _D,
+                        C.POINTER(C.c_int32), _D, _D, _D, _D],
+    "edf_gpc_exceed": [_P, C.c_int32, _D, C.c_double, _D, _D],
     "edf_autotune": [_P, C.c_double],
     "edf_get_tuning": [_P, C.c_int32, C.POINTER(C.c_int32), _D],
     "edf_set_tuning": [_P, C.c_int32, C.c_int32],
@@ -224,6 +227,41 @@ class Problem:
                                           _dptr(mean), _dptr(var), _dptr(exc)))
         shape = (cz, cy, cx)
         return mean.reshape(shape), var.reshape(shape), exc.reshape(shape)
+
+    def gpc_project(self, group: int, common, degree: int, weights, truncation: int = 0,
+                    coefficients: bool = True):
+        """Polynomial chaos surrogate of the group's samples (edf_gpc_project): returns a
+        dict with n_coef, coef [n_coef, cz, cy, cx] (if asked), mean, var [cz, cy, cx] and
+        kernel_ms (the projection kernel's duration)."""
+        cx, cy, cz = common
+        n = cx * cy * cz
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
+        assert w.size == self.groups[group][4]
+        nc = C.c_int32()
+        ms = C.c_double()
+        coef = np.empty(128 * n) if coefficients else None
+        mean, var = np.empty(n), np.empty(n)
+        self._check(self._lib.edf_gpc_project(
+            self._h, group, cx, cy, cz, int(degree), int(truncation), _dptr(w), C.byref(nc),
+            _dptr(coef) if coef is not None else None, _dptr(mean), _dptr(var),
+            C.cast(C.pointer(ms), _D)))
+        shape = (cz, cy, cx)
+        out = {"n_coef": nc.value, "mean": mean.reshape(shape), "var": var.reshape(shape),
+               "kernel_ms": ms.value}
+        if coef is not None:
+            out["coef"] = coef[:nc.value * n].reshape((nc.value,) + shape)
+        return out
+
+    def gpc_exceed(self, theta, threshold: float, common):
+        """P(c > threshold) of the last surrogate sampled at points theta [N_s, M]
+        (edf_gpc_exceed); returns (prob [cz, cy, cx], kernel_ms)."""
+        t = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
+        cx, cy, cz = common
+        prob = np.empty(cx * cy * cz)
+        ms = C.c_double()
+        self._check(self._lib.edf_gpc_exceed(self._h, t.shape[0], _dptr(t), float(threshold),
+                                             _dptr(prob), C.cast(C.pointer(ms), _D)))
+        return prob.reshape(cz, cy, cx), ms.value
 
     def adjoint(self, box, dt: float, n_steps: int):
         """Salt mass J in `box` (x0, x1, y0, y1, z0, z1) after n_steps steps and dJ/dxi,

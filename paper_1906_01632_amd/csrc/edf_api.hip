@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -14,6 +15,7 @@
 #include <vector>
 
 #include "adjoint.h"
+#include "gpc.h"
 #include "edf.h"
 #include "edf_internal.h"
 
@@ -108,6 +110,14 @@ struct edf_problem {
   int device = 0;  // the device current at creation; every group thread uses it
   std::vector<void*> allocs;
   double* dxi = nullptr;  // parameters on the device [S_total][max(n_xi, 1)]
+  // polynomial chaos surrogate of the last edf_gpc_project (device, grow-only)
+  int gpc_nc = 0, gpc_M = 0, gpc_deg = 0, gpc_trunc = 0, gpc_Nc = 0;
+  double* gpc_buf = nullptr;  // C [nc][Nc], Q [nc], W [nc][S], w [S], F [S][Nc], mean/var
+  size_t gpc_cap = 0;
+  int* gpc_ibuf = nullptr;    // idx [nc][M], then exceedance counts
+  size_t gpc_icap = 0;
+  double* gpc_pts = nullptr;  // exceedance points [Ns][M], then probabilities [Nc]
+  size_t gpc_pcap = 0;
   // statistics buffers (allocated on first use)
   double* mom_f = nullptr;
   double* mom_w = nullptr;
@@ -1110,6 +1120,42 @@ edf_status adjoint_group(edf_problem* pb, Group& G, const QoiBox& box, double dt
   return EDF_OK;
 }
 
+// ---------------------------------------------------------------------------
+// polynomial chaos: the multi-index set J_{M,p} (total degree <= p, or every degree
+// <= p), ordered by total degree and then decreasingly lexicographic
+// ---------------------------------------------------------------------------
+void gpc_indices(int M, int p, int truncation, std::vector<int>& out) {
+  out.clear();
+  std::vector<int> b(M);
+  // all tuples of total t with components <= p, first component largest first
+  std::function<void(int, int)> rec = [&](int j, int rem) {
+    if (j == M - 1) {
+      if (rem <= p) {
+        b[j] = rem;
+        out.insert(out.end(), b.begin(), b.end());
+      }
+      return;
+    }
+    for (int v = std::min(p, rem); v >= 0; --v) {
+      b[j] = v;
+      rec(j + 1, rem - v);
+    }
+  };
+  const int tmax = truncation == 0 ? p : M * p;
+  for (int t = 0; t <= tmax; ++t) rec(0, t);
+}
+
+template <typename T>
+edf_status grow(edf_problem* pb, T** buf, size_t* cap, size_t need) {
+  if (need <= *cap) return EDF_OK;
+  if (*buf) (void)hipFree(*buf);
+  *buf = nullptr;
+  *cap = 0;
+  EDF_TRY(hipMalloc((void**)buf, need * sizeof(T)));
+  *cap = need;
+  return EDF_OK;
+}
+
 edf_status check_ready(edf_problem* pb) {
   if (!pb) return EDF_ERR_ARG;
   if (!pb->params_set) return fail(pb, EDF_ERR_STATE, "edf_set_parameters has not been called");
@@ -1315,6 +1361,130 @@ edf_status edf_solve(edf_problem* pb, double dt, int32_t n_steps, edf_step_stats
   for (int n = 0; n < n_steps; ++n)
     if ((e = edf_step(pb, dt, n + 1 == n_steps ? stats : nullptr))) return e;
   EDF_TRY(hipStreamSynchronize(pb->st));
+  return EDF_OK;
+}
+
+edf_status edf_gpc_project(edf_problem* pb, int32_t group, int32_t cx, int32_t cy, int32_t cz,
+                           int32_t degree, int32_t truncation, const double* weights,
+                           int32_t* n_coef, double* coef, double* mean, double* var,
+                           double* kernel_ms) {
+  edf_status e;
+  if ((e = check_ready(pb))) return e;
+  if (group < 0 || group >= (int)pb->groups.size() || !weights || !n_coef || !mean || !var)
+    return fail(pb, EDF_ERR_ARG, "bad gpc arguments");
+  Group& G = pb->groups[group];
+  const int M = pb->phys.n_xi, S = G.S;
+  if (M < 1 || M > kGpcMaxM) return fail(pb, EDF_ERR_ARG, "the expansion needs 1..4 parameters");
+  if (degree < 0 || degree > kGpcMaxDeg || (truncation != 0 && truncation != 1))
+    return fail(pb, EDF_ERR_ARG, "degree must be in [0, 8] and truncation 0 or 1");
+  const Geom& g = G.lv[0].g;
+  if (cx < 2 || cy < 2 || cz < 2 || (g.nx - 1) % (cx - 1) || (g.ny - 1) % (cy - 1) ||
+      (g.nz - 1) % (cz - 1))
+    return fail(pb, EDF_ERR_ARG, "common grid not nested in the group's grid");
+  for (int i = 0; i < S; ++i)
+    if (!std::isfinite(weights[i])) return fail(pb, EDF_ERR_ARG, "weights not finite");
+  std::vector<int> idx;
+  gpc_indices(M, degree, truncation, idx);
+  const int nc = (int)idx.size() / M;
+  if (nc > kGpcMaxCoef) return fail(pb, EDF_ERR_ARG, "more than 128 expansion terms");
+  std::vector<double> Q(nc);
+  for (int q = 0; q < nc; ++q) {
+    double a = 1.0;
+    for (int j = 0; j < M; ++j) a /= 2.0 * idx[q * M + j] + 1.0;
+    Q[q] = a;
+  }
+  const size_t Nc = (size_t)cx * cy * cz;
+  hipStream_t st = pb->st;
+  EDF_TRY(hipStreamSynchronize(st));
+  if ((e = grow(pb, &pb->gpc_buf, &pb->gpc_cap, nc * Nc + nc + (size_t)nc * S + S + S * Nc + 2 * Nc)))
+    return e;
+  if ((e = grow(pb, &pb->gpc_ibuf, &pb->gpc_icap, (size_t)nc * M))) return e;
+  double* C = pb->gpc_buf;
+  double* dQ = C + nc * Nc;
+  double* W = dQ + nc;
+  double* dw = W + (size_t)nc * S;
+  double* F = dw + S;
+  double* mv = F + S * Nc;
+  EDF_TRY(hipMemcpyAsync(pb->gpc_ibuf, idx.data(), idx.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  EDF_TRY(hipMemcpyAsync(dQ, Q.data(), nc * sizeof(double), hipMemcpyHostToDevice, st));
+  EDF_TRY(hipMemcpyAsync(dw, weights, S * sizeof(double), hipMemcpyHostToDevice, st));
+  launch_gather_common(g, cx, cy, cz, G.u, F, S, st);
+  const int ldt = std::max(pb->phys.n_xi, 1);
+  launch_gpc_weights(S, M, nc, pb->dxi + (size_t)G.s0 * ldt, ldt, dw, pb->gpc_ibuf, dQ, W, st);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (kernel_ms) {
+    EDF_TRY(hipEventCreate(&e0));
+    EDF_TRY(hipEventCreate(&e1));
+  }
+  launch_gpc_project(S, (int)Nc, nc, W, F, C, st, e0, e1);
+  launch_gpc_moments((int)Nc, nc, C, dQ, mv, mv + Nc, st);
+  EDF_CHECK_LAUNCH();
+  if (coef) EDF_TRY(hipMemcpyAsync(coef, C, nc * Nc * sizeof(double), hipMemcpyDeviceToHost, st));
+  EDF_TRY(hipMemcpyAsync(mean, mv, Nc * sizeof(double), hipMemcpyDeviceToHost, st));
+  EDF_TRY(hipMemcpyAsync(var, mv + Nc, Nc * sizeof(double), hipMemcpyDeviceToHost, st));
+  EDF_TRY(hipStreamSynchronize(st));
+  if (kernel_ms) {
+    float ms = 0.f;
+    EDF_TRY(hipEventElapsedTime(&ms, e0, e1));
+    *kernel_ms = ms;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  *n_coef = nc;
+  pb->gpc_nc = nc;
+  pb->gpc_M = M;
+  pb->gpc_deg = degree;
+  pb->gpc_trunc = truncation;
+  pb->gpc_Nc = (int)Nc;
+  return EDF_OK;
+}
+
+edf_status edf_gpc_exceed(edf_problem* pb, int32_t n_points, const double* theta, double threshold,
+                          double* prob, double* kernel_ms) {
+  if (!pb || !theta || !prob || n_points < 1 || !std::isfinite(threshold))
+    return fail(pb, EDF_ERR_ARG, "bad gpc exceedance arguments");
+  if (pb->gpc_nc == 0) return fail(pb, EDF_ERR_STATE, "edf_gpc_project has not been called");
+  const int M = pb->gpc_M, nc = pb->gpc_nc, Nc = pb->gpc_Nc;
+  for (size_t e = 0; e < (size_t)n_points * M; ++e)
+    if (!(std::fabs(theta[e]) <= 1.0)) return fail(pb, EDF_ERR_ARG, "points outside [-1,1]^M");
+  // point chunks per block: at least 2048 points, at most 2^26 partial counts in all
+  int chunk = 2048;
+  while ((size_t)ceil_div(n_points, chunk) * Nc > (1u << 26)) chunk *= 2;
+  const int n_chunks = ceil_div(n_points, chunk);
+  hipStream_t st = pb->st;
+  edf_status e;
+  EDF_TRY(hipStreamSynchronize(st));
+  if ((e = grow(pb, &pb->gpc_pts, &pb->gpc_pcap, (size_t)n_points * M + Nc))) return e;
+  if ((e = grow(pb, &pb->gpc_ibuf, &pb->gpc_icap, (size_t)nc * M + (size_t)n_chunks * Nc)))
+    return e;
+  double* pts = pb->gpc_pts;
+  double* dprob = pts + (size_t)n_points * M;
+  int* idx = pb->gpc_ibuf;
+  int* partial = idx + (size_t)nc * M;
+  // the index table of the projection is written again: the buffer may have moved
+  std::vector<int> table;
+  gpc_indices(M, pb->gpc_deg, pb->gpc_trunc, table);
+  EDF_TRY(hipMemcpyAsync(idx, table.data(), table.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  EDF_TRY(hipMemcpyAsync(pts, theta, (size_t)n_points * M * sizeof(double), hipMemcpyHostToDevice,
+                         st));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (kernel_ms) {
+    EDF_TRY(hipEventCreate(&e0));
+    EDF_TRY(hipEventCreate(&e1));
+  }
+  launch_gpc_exceed(Nc, nc, M, pb->gpc_deg, pb->gpc_buf, idx, pts, n_points, chunk, n_chunks,
+                    threshold, partial, st, e0, e1);
+  launch_gpc_count(Nc, n_chunks, n_points, partial, dprob, st);
+  EDF_CHECK_LAUNCH();
+  EDF_TRY(hipMemcpyAsync(prob, dprob, Nc * sizeof(double), hipMemcpyDeviceToHost, st));
+  EDF_TRY(hipStreamSynchronize(st));
+  if (kernel_ms) {
+    float ms = 0.f;
+    EDF_TRY(hipEventElapsedTime(&ms, e0, e1));
+    *kernel_ms = ms;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
   return EDF_OK;
 }
 
@@ -1561,6 +1731,9 @@ void edf_destroy(edf_problem* pb) {
   }
   for (void* p : pb->allocs) (void)hipFree(p);
   if (pb->mom_f) (void)hipFree(pb->mom_f);
+  if (pb->gpc_buf) (void)hipFree(pb->gpc_buf);
+  if (pb->gpc_ibuf) (void)hipFree(pb->gpc_ibuf);
+  if (pb->gpc_pts) (void)hipFree(pb->gpc_pts);
   delete pb;
 }
 

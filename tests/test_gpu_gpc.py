@@ -1,0 +1,109 @@
+"""Polynomial chaos surrogate of the library (edf_gpc_project, edf_gpc_exceed) against
+the oracle's projection, moments and sampled exceedance.  GPU."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import gpc, stats
+
+pytestmark = pytest.mark.gpu
+
+DT = synth.MONTH_S
+TIGHT = dict(newton_rtol=1e-13, newton_atol=0.0, lin_rtol=1e-12, lin_max_it=600,
+             newton_max_it=40, check_every=8)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _problem(phys, groups, **opts):
+    from paper_1906_01632_amd import Problem
+    o = dict(TIGHT)
+    o.update(opts)
+    return Problem(phys, groups, o)
+
+
+def test_projection_recovers_polynomial_states():
+    """States that are gPC polynomials of the node parameters (degree 2 in 3 parameters,
+    27 tensor Gauss-Legendre nodes) are projected back to their coefficients, and the
+    moments are those of the coefficients; a ragged common grid (9x5x3 of 17x9x5)."""
+    phys = synth.physics(3)
+    nx, ny, nz = 17, 9, 5
+    nodes, w = gpc.tensor_gauss_legendre(3, 3)
+    J = gpc.multi_indices(3, 2)
+    pb = _problem(phys, [(nx, ny, nz, 2, len(nodes))])
+    pb.set_parameters(nodes)
+    true = np.random.default_rng(1).standard_normal((len(J), nz, ny, nx)) * 0.1
+    c = gpc.surrogate(true, J, nodes)                     # [27, nz, ny, nx]
+    base = synth.initial_state(nx, ny, nz, phys)
+    for i in range(len(nodes)):
+        u = base.copy()
+        u[..., 1] = c[i]
+        pb.set_state(i, u)
+    out = pb.gpc_project(0, (9, 5, 3), 2, w)
+    assert out["n_coef"] == len(J) == 10
+    sub = true[:, ::2, ::2, ::2]
+    assert np.abs(out["coef"] - sub).max() < 1e-13
+    m, v = gpc.moments(sub, J)
+    assert np.abs(out["mean"] - m).max() < 1e-14
+    assert np.abs(out["var"] - v).max() < 1e-14
+    pb.destroy()
+
+
+@pytest.mark.parametrize("degree,truncation", [(1, 0), (2, 0), (1, 1)])
+def test_projection_and_exceedance_of_solved_samples(degree, truncation):
+    """Eight samples at the 2-point tensor Gauss-Legendre nodes solved for two steps:
+    the library's coefficients, moments and sampled exceedance equal the oracle's on the
+    same states (a decision may differ only where the surrogate is within 1e-12 of the
+    threshold)."""
+    phys = synth.physics(3)
+    nx, ny, nz = 17, 17, 5
+    nodes, w = gpc.tensor_gauss_legendre(3, 2)
+    pb = _problem(phys, [(nx, ny, nz, 3, len(nodes))])
+    pb.set_parameters(nodes)
+    for _ in range(2):
+        pb.step(DT)
+    common = (9, 9, 3)
+    out = pb.gpc_project(0, common, degree, w, truncation=truncation)
+    J = gpc.multi_indices(3, degree, truncation)
+    fields = np.array([stats.inject(pb.get_state(i)[..., 1], common) for i in range(len(nodes))])
+    ref = gpc.project(fields, nodes, w, J)
+    assert out["n_coef"] == len(J)
+    scale = np.abs(ref).max()
+    assert np.abs(out["coef"] - ref).max() <= 1e-13 * scale
+    m, v = gpc.moments(ref, J)
+    assert np.abs(out["mean"] - m).max() < 1e-14
+    assert np.abs(out["var"] - v).max() <= 1e-13 * max(np.abs(v).max(), 1e-300)
+    qm, _, _ = stats.moments(fields, w)                  # c_0 is the quadrature mean
+    assert np.abs(out["mean"] - qm).max() < 1e-14
+    pts = np.random.default_rng(5).uniform(-1, 1, (20000, 3))
+    for thr in (0.05, 0.5):
+        prob, _ = pb.gpc_exceed(pts, thr, common)
+        vals = gpc.surrogate(out["coef"], J, pts)        # [N_s, cz, cy, cx]
+        want = np.mean(vals > thr, axis=0)
+        near = np.sum(np.abs(vals - thr) < 1e-12, axis=0) / len(pts)
+        assert np.all(np.abs(prob - want) <= near + 1e-15), thr
+        assert np.all((prob >= 0) & (prob <= 1))
+    pb.destroy()
+
+
+def test_gpc_invalid_calls_are_rejected():
+    from paper_1906_01632_amd import EDFError
+    phys = synth.physics(3)
+    nodes, w = gpc.tensor_gauss_legendre(3, 2)
+    pb = _problem(phys, [(9, 9, 3, 2, len(nodes))])
+    pb.set_parameters(nodes)
+    with pytest.raises(EDFError):
+        pb.gpc_exceed(np.zeros((4, 3)), 0.5, (9, 9, 3))      # no projection yet
+    with pytest.raises(EDFError):
+        pb.gpc_project(0, (9, 9, 3), 9, w)                   # degree above 8
+    with pytest.raises(EDFError):
+        pb.gpc_project(0, (4, 9, 3), 1, w)                   # not nested
+    pb.gpc_project(0, (9, 9, 3), 1, w)
+    with pytest.raises(EDFError):
+        pb.gpc_exceed(np.full((4, 3), 1.5), 0.5, (9, 9, 3))  # points outside [-1, 1]^3
+    pb.destroy()
