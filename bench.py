@@ -102,6 +102,55 @@ def run_adjoint(args, wl, pb, prec):
     print(json.dumps(out), flush=True)
 
 
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector (and matrix) peak
+
+
+def run_gpc(args, wl, pb, prec, degree=4, n_points=10**6, threshold=0.5):
+    """The quadrature nodes' samples stepped wl.steps times (untimed), then the surrogate:
+    projection of the full-grid c fields (HBM bound) and the exceedance probability
+    from n_points surrogate samples per vertex (FP64 ALU bound), both timed by events
+    around their kernels."""
+    import numpy as np
+    for k in range(wl.steps):
+        t = time.perf_counter()
+        pb.step(wl.dt)
+        log(f"node samples, step {k + 1}: {time.perf_counter() - t:.2f} s")
+    g = wl.groups[0]
+    common = (g.nx, g.ny, g.nz)
+    Nc, S = g.n_vertices, g.samples
+    pts = np.random.default_rng(11).uniform(-1.0, 1.0, (n_points, wl.xi.shape[1]))
+    proj_ms, ex_ms = [], []
+    for r in range(1 + args.steps):  # the first of each is a warm-up
+        out = pb.gpc_project(0, common, degree, wl.weights, coefficients=False)
+        prob, ms = pb.gpc_exceed(pts, threshold, common)
+        if r:
+            proj_ms.append(out["kernel_ms"])
+            ex_ms.append(ms)
+    nc = out["n_coef"]
+    pm, em = float(np.mean(proj_ms)), float(np.mean(ex_ms))
+    proj_bytes = 8.0 * Nc * (S + nc)        # every sample field read, every coefficient written
+    flops = 2.0 * nc * Nc * n_points        # one FMA per term, vertex and point
+    gbs, tfs = proj_bytes / (pm * 1e-3) / 1e9, flops / (em * 1e-3) / 1e12
+    res = {"metric": "gPC surrogate: vertex-samples/s of the exceedance estimate",
+           "value": Nc * n_points / (em * 1e-3), "unit": "vertex-samples/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": 1, "ms_per_step": pm + em, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (Gauss-Legendre nodes, seeded surrogate points; no dataset)",
+           "config": {"workload": wl.name, "grid": list(common), "nodes": S, "degree": degree,
+                      "n_coef": nc, "points": n_points, "threshold": threshold},
+           "mean_range": [float(out["mean"].min()), float(out["mean"].max())],
+           "max_var": float(out["var"].max()), "max_prob": float(prob.max()),
+           "roofline": {"bound": "alu", "kernel": "k_gpc_exceed (surrogate evaluation)",
+                        "achieved": tfs, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": tfs / FP64_PEAK_TFLOPS, "traffic": None, "avg_launch_us": 1e3 * em,
+                        "flops_per_launch": flops},
+           "projection": {"bound": "hbm", "kernel": "k_gpc_project", "achieved": gbs,
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                          "avg_launch_us": 1e3 * pm, "bytes_per_launch": proj_bytes}}
+    pb.destroy()
+    print(json.dumps(res), flush=True)
+
+
 def cpu_baseline(wl, phys, budget_s=20.0):
     """The oracle (plain FP64 NumPy/SciPy, unchanged) on a bounded sample of the
     workload: whole implicit-Euler steps of the samples of its smallest group."""
@@ -147,6 +196,10 @@ def main():
                     help="time the gradient instead of plain steps: edf_adjoint over --steps steps "
                          "(forward with checkpoints, then the backward sweep) of the salt mass in "
                          "the lower-central box")
+    ap.add_argument("--gpc", action="store_true",
+                    help="time the polynomial chaos surrogate instead of plain steps: solve the "
+                         "quadrature nodes' samples (untimed), then project them (degree 4) and "
+                         "sample the surrogate's exceedance at 10^6 points (workload gpc125)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default fused-bottom levels instead of timing the choices")
     ap.add_argument("--mark-timed-region", action="store_true",
@@ -195,6 +248,8 @@ def main():
     torch.cuda.synchronize()
     if args.adjoint:
         return run_adjoint(args, wl, pb, prec)
+    if args.gpc:
+        return run_gpc(args, wl, pb, prec)
     if not args.no_profile:
         pb.profile(True)
     stats = None

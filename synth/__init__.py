@@ -71,6 +71,7 @@ class Workload:
     precision: str = "f64"          # "f64" or "mixed" (FP32 V-cycle)
     newton_rtol: float = 1e-10
     xi: np.ndarray = field(default=None, repr=False)  # [S_total, n_xi]
+    weights: np.ndarray = field(default=None, repr=False)  # quadrature weights (gPC)
 
     @property
     def n_samples(self) -> int:
@@ -151,10 +152,16 @@ def workload(name: str, seed: int = 0) -> Workload:
         i = np.arange(512)
         return Workload(name, [Group(65, 65, 17, 64, 5)], FIELD_LATTICE4, 50,
                         newton_rtol=1e-10, xi=pts[i % 8 == 0])
+    if name == "gpc125":               # the paper's 3-parameter box field at 125 nodes
+        x, w = np.polynomial.legendre.leggauss(5)
+        nodes = np.array([(a, b, c) for a in x for b in x for c in x])
+        weights = np.array([wa * wb * wc for wa in w for wb in w for wc in w]) / 8.0
+        return Workload(name, [Group(65, 65, 17, 125, 5)], FIELD_PAPER3, 3,
+                        newton_rtol=1e-8, xi=nodes, weights=weights)
     raise KeyError(name)
 
 
-WORKLOADS = ("elder33_f64", "elder129_f64", "qmc512_mixedres", "mixed257", "adjoint65")
+WORKLOADS = ("elder33_f64", "elder129_f64", "qmc512_mixedres", "mixed257", "adjoint65", "gpc125")
 
 
 # --------------------------------------------------------------------------
