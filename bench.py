@@ -240,6 +240,8 @@ def main():
     if not args.no_autotune:
         pb.autotune(wl.dt)
     tuning = [pb.tuning(g)[0] for g in range(len(groups))]
+    for gi in range(len(groups)):
+        log(f"group {gi}: V-cycle ms per first fused level {np.round(pb.tuning(gi)[1], 3).tolist()}")
     log(f"set-up {time.perf_counter() - t:.1f} s; fused V-cycle bottom from levels {tuning}")
     for w in range(args.warmup):
         t = time.perf_counter()

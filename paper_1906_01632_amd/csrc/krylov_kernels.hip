@@ -50,11 +50,15 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Geom g, const double* A_all, co
                                                  const int* mask) {
   const int s = blockIdx.y;
   if (mask && !mask[s]) return;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  // one thread per vertex in natural order: the Krylov vectors x, y, d are read and
+  // written contiguously; the stencil rows of a wave's 64 vertices are two runs of 32
+  // positions of two colours
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
   const size_t N = g.N, Np = g.off[8];
   double acc[2] = {0.0, 0.0};
-  int i, j, k;
-  if (t < g.off[8] && colour_decode(g, t, i, j, k)) {
+  if (v < g.N) {
+    const int i = v % g.nx, j = (v / g.nx) % g.ny, k = v / (g.nx * g.ny);
+    const int t = colour_encode(g, i, j, k);
     const double* A = A_all + (size_t)s * kPlanes * Np + sidx<double>(t, 0, kPlanes);
     const double2* x = reinterpret_cast<const double2*>(x_all) + (size_t)s * N;
     double r0 = 0.0, r1 = 0.0;
@@ -75,7 +79,6 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Geom g, const double* A_all, co
         }
       }
     }
-    const size_t v = i + (size_t)g.nx * (j + (size_t)g.ny * k);
     reinterpret_cast<double2*>(y_all)[(size_t)s * N + v] = make_double2(r0, r1);
     if (MODE != kDotNone) {
       const double2 d = reinterpret_cast<const double2*>(d_all)[(size_t)s * N + v];
@@ -93,7 +96,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Geom g, const double* A_all, co
 
 void launch_spmv(const Geom& g, const double* A, const double* x, double* y, int S,
                  const int* mask, hipStream_t st) {
-  dim3 grid(ceil_div(g.off[8], kBlock), S);
+  dim3 grid(ceil_div(g.N, kBlock), S);
   hipLaunchKernelGGL(k_spmv<kDotNone>, grid, dim3(kBlock), 0, st, g, A, x, y, (const double*)nullptr,
                      (double*)nullptr, mask);
 }
@@ -236,7 +239,7 @@ void launch_bicg_p(size_t n, const double* r, const double* v, double* p, const 
 void launch_bicg_alpha(const Geom& g, const double* A, const double* ph, double* v,
                        const double* rh, double* part, KrylovScalars* ks, int S, const int* mask,
                        hipStream_t st) {
-  const int nb = ceil_div(g.off[8], kBlock);
+  const int nb = ceil_div(g.N, kBlock);
   hipLaunchKernelGGL(k_spmv<kDotOne>, dim3(nb, S), dim3(kBlock), 0, st, g, A, ph, v, rh, part,
                      mask);
   finalize(kAlpha, nb, part, ks, const_cast<int*>(mask), nullptr, S, st);  // mask is `active`
@@ -269,7 +272,7 @@ void launch_bicg_s(size_t n, const double* r, const double* v, double* s, double
 void launch_bicg_omega(const Geom& g, const double* A, const double* sh, const double* s,
                        double* t, double* part, KrylovScalars* ks, int S, const int* mask,
                        hipStream_t st) {
-  const int nb = ceil_div(g.off[8], kBlock);
+  const int nb = ceil_div(g.N, kBlock);
   hipLaunchKernelGGL(k_spmv<kDotTS>, dim3(nb, S), dim3(kBlock), 0, st, g, A, sh, t, s, part, mask);
   finalize(kOmega, nb, part, ks, const_cast<int*>(mask), nullptr, S, st);
 }
