@@ -18,8 +18,6 @@ void launch_gpc_project(int S, int Nc, int nc, const double* W, const double* F,
 // mean = C[0], var = sum_{q >= 1} Q_q C[q]^2
 void launch_gpc_moments(int Nc, int nc, const double* C, const double* Q, double* mean,
                         double* var, hipStream_t st);
-// nc padded to the next instantiated register-array length, -1 if too many
-int gpc_exceed_padded(int nc);
 // partial[y][v] = #{s in chunk y : sum_q C[q][v] Psi_q(theta_s) > thr}; theta [Ns][M]
 void launch_gpc_exceed(int Nc, int nc, int M, int pmax, const double* C, const int* idx,
                        const double* theta, int Ns, int chunk, int n_chunks, double thr,

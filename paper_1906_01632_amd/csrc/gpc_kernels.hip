@@ -4,11 +4,10 @@
 // coefficients (eqs. PCEcoef2, var), and the exceedance probability of the surrogate
 // sampled at many parameter points (eq. PCEpoint and Section 3.2).
 //
-// All of it is FP64 on the vector units.  The projection is a [n_coef x S] x [S x N]
-// product that reads every sample field once (HBM bound); the exceedance is an
-// [N x n_coef] x [n_coef x N_s] product fused with the threshold count (ALU bound).
-// FP64 matrix cores have the same peak rate as FP64 vector FMAs on this chip, so the
-// contractions use plain FMAs with the point-side basis values broadcast from LDS.
+// All of it is FP64.  The projection is a [n_coef x S] x [S x N] product that reads
+// every sample field once (HBM bound, vector FMAs); the exceedance is an
+// [N x n_coef] x [n_coef x N_s] product fused with the threshold count (compute
+// bound), run on the FP64 matrix cores.
 #include <hip/hip_ext.h>
 
 #include "gpc.h"
@@ -46,23 +45,47 @@ void launch_gpc_weights(int S, int M, int nc, const double* theta, int ldt, cons
 }
 
 // C[q][v] = sum_i W[q][i] F[i][v]: one vertex per thread, kProjChunk coefficients per
-// thread in registers (blockIdx.y selects the chunk), the samples' values read once
+// thread in registers (blockIdx.y selects the chunk); the samples are taken in tiles of
+// kProjTile whose weights are staged in LDS (read back as broadcasts), and the tile's
+// field values are loaded eight at a time so that enough loads are in flight
 constexpr int kProjChunk = 32;
+constexpr int kProjTile = 64;
 
 __global__ __launch_bounds__(kBlock) void k_gpc_project(int S, int Nc, int nc, const double* W,
                                                         const double* F, double* C) {
+  __shared__ double w[kProjTile][kProjChunk];
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   const int q0 = blockIdx.y * kProjChunk;
-  if (v >= Nc) return;
   double acc[kProjChunk];
 #pragma unroll
   for (int q = 0; q < kProjChunk; ++q) acc[q] = 0.0;
-  for (int i = 0; i < S; ++i) {
-    const double f = F[(size_t)i * Nc + v];
+  for (int i0 = 0; i0 < S; i0 += kProjTile) {
+    const int ni = min(kProjTile, S - i0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < kProjTile * kProjChunk; e += blockDim.x) {
+      const int i = e / kProjChunk, q = e % kProjChunk;
+      w[i][q] = (i < ni && q0 + q < nc) ? W[(size_t)(q0 + q) * S + i0 + i] : 0.0;
+    }
+    __syncthreads();
+    if (v < Nc) {
+      int i = 0;
+      for (; i + 8 <= ni; i += 8) {
+        double f[8];
 #pragma unroll
-    for (int q = 0; q < kProjChunk; ++q)
-      if (q0 + q < nc) acc[q] += W[(size_t)(q0 + q) * S + i] * f;
+        for (int u = 0; u < 8; ++u) f[u] = F[(size_t)(i0 + i + u) * Nc + v];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int q = 0; q < kProjChunk; ++q) acc[q] += w[i + u][q] * f[u];
+      }
+      for (; i < ni; ++i) {
+        const double f = F[(size_t)(i0 + i) * Nc + v];
+#pragma unroll
+        for (int q = 0; q < kProjChunk; ++q) acc[q] += w[i][q] * f;
+      }
+    }
   }
+  if (v >= Nc) return;
 #pragma unroll
   for (int q = 0; q < kProjChunk; ++q)
     if (q0 + q < nc) C[(size_t)(q0 + q) * Nc + v] = acc[q];
@@ -99,113 +122,119 @@ void launch_gpc_moments(int Nc, int nc, const double* C, const double* Q, double
                      mean, var);
 }
 
-// Exceedance counts: a block holds kBlock vertices' coefficients in registers (NC
-// padded to a multiple of 8 with zeros) and walks its chunk of points in tiles of
-// kTilePts: the tile's basis values Psi_q(theta_s) are formed in LDS (1D Legendre
-// values first, then the products), then every thread evaluates the surrogate at the
-// tile's points with FMAs on broadcast LDS reads and counts values above the threshold.
+// Exceedance counts on the matrix cores.  The surrogate values of 16 vertices at 16
+// points are one 16x16 tile of the product [vertices x q] x [q x points], built by
+// v_mfma_f64_16x16x4f64 over q in steps of 4 (FP64 throughout).  Lane l supplies
+// A[l % 16][l / 16] (a vertex's coefficient) and B[l / 16][l % 16] (a point's basis
+// value) and receives D[l / 16 + 4 v][l % 16], v = 0..3.  A wave keeps the coefficients
+// of its 16 vertices in registers (one value per lane and step of 4 terms), a block of
+// four waves walks its chunk of points in tiles of kTilePts: the tile's basis values are
+// formed in LDS ([q][point], point fastest), every wave runs four independent 16-point
+// accumulations, compares the values with the threshold and counts per lane; the
+// counts of the 16 lanes that share a vertex are summed by shuffles at the end.
 constexpr int kTilePts = 64;
+constexpr int kMaxKb = kGpcMaxCoef / 4;
+typedef double v4d __attribute__((ext_vector_type(4)));
 
-template <int NC>
 __global__ __launch_bounds__(kBlock) void k_gpc_exceed(int Nc, int nc, int M, int pmax,
                                                        const double* C, const int* idx,
                                                        const double* theta, int Ns, int chunk,
                                                        double thr, int* partial) {
-  __shared__ double basis[kTilePts][NC];
-  __shared__ double leg[kTilePts][kGpcMaxM][kGpcMaxDeg + 1];
-  __shared__ int sidx[NC * kGpcMaxM];
-  const int tid = threadIdx.x;
-  const int v = blockIdx.x * blockDim.x + tid;
-  for (int e = tid; e < NC * M; e += blockDim.x) sidx[e] = e < nc * M ? idx[e] : 0;
-  double c[NC];
+  // dynamic LDS: basis [ncp][kTilePts], Legendre values [kTilePts][M][pmax + 1], indices
+  extern __shared__ double smem[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int kb_n = (nc + 3) / 4;  // steps of 4 terms
+  const int ncp = 4 * kb_n;
+  const int P1 = pmax + 1;
+  double* basis = smem;
+  double* leg = basis + (size_t)ncp * kTilePts;
+  int* sidx = reinterpret_cast<int*>(leg + (size_t)kTilePts * M * P1);
+  for (int e = tid; e < ncp * M; e += blockDim.x) sidx[e] = e < nc * M ? idx[e] : 0;
+  // this lane's A operand for every step: coefficient (l / 16 + 4 kb) of vertex l % 16
+  const int vrow = blockIdx.x * 64 + wave * 16 + (lane & 15);
+  double a[kMaxKb];
 #pragma unroll
-  for (int q = 0; q < NC; ++q) c[q] = (v < Nc && q < nc) ? C[(size_t)q * Nc + v] : 0.0;
+  for (int kb = 0; kb < kMaxKb; ++kb) {
+    const int q = 4 * kb + (lane >> 4);
+    a[kb] = (kb < kb_n && q < nc && vrow < Nc) ? C[(size_t)q * Nc + vrow] : 0.0;
+  }
   const int s_begin = blockIdx.y * chunk;
   const int s_end = min(Ns, s_begin + chunk);
-  int count = 0;
+  int cnt[4] = {0, 0, 0, 0};
   for (int s0 = s_begin; s0 < s_end; s0 += kTilePts) {
     const int nt = min(kTilePts, s_end - s0);
     __syncthreads();  // the previous tile's basis values are no longer read
     for (int e = tid; e < nt * M; e += blockDim.x) {
-      const int s = e / M, j = e % M;
-      const double x = theta[(size_t)(s0 + s) * M + j];
-      double a = 1.0, b = x;
-      leg[s][j][0] = 1.0;
-      if (pmax >= 1) leg[s][j][1] = x;
+      const int sp = e / M, j = e % M;
+      const double x = theta[(size_t)(s0 + sp) * M + j];
+      double* L = leg + (size_t)(sp * M + j) * P1;
+      double u = 1.0, w = x;
+      L[0] = 1.0;
+      if (pmax >= 1) L[1] = x;
       for (int k = 1; k < pmax; ++k) {
-        const double cc = ((2 * k + 1) * x * b - k * a) / (k + 1);
-        a = b;
-        b = cc;
-        leg[s][j][k + 1] = cc;
+        const double z = ((2 * k + 1) * x * w - k * u) / (k + 1);
+        u = w;
+        w = z;
+        L[k + 1] = z;
       }
     }
     __syncthreads();
-    for (int e = tid; e < nt * NC; e += blockDim.x) {
-      const int s = e / NC, q = e % NC;
+    for (int e = tid; e < ncp * kTilePts; e += blockDim.x) {
+      const int q = e / kTilePts, sp = e % kTilePts;
       double psi = 0.0;
-      if (q < nc) {
+      if (q < nc && sp < nt) {
         psi = 1.0;
-        for (int j = 0; j < M; ++j) psi *= leg[s][j][sidx[q * M + j]];
+        for (int j = 0; j < M; ++j) psi *= leg[(size_t)(sp * M + j) * P1 + sidx[q * M + j]];
       }
-      basis[s][q] = psi;
+      basis[q * kTilePts + sp] = psi;
     }
     __syncthreads();
-    int s = 0;
-    for (; s + 4 <= nt; s += 4) {  // four independent chains per thread
-      double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+    v4d d[4];
 #pragma unroll
-      for (int q = 0; q < NC; ++q) {
-        v0 = fma(c[q], basis[s][q], v0);
-        v1 = fma(c[q], basis[s + 1][q], v1);
-        v2 = fma(c[q], basis[s + 2][q], v2);
-        v3 = fma(c[q], basis[s + 3][q], v3);
+    for (int t = 0; t < 4; ++t) d[t] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kb = 0; kb < kMaxKb; ++kb) {
+      if (kb < kb_n) {
+        const int q = 4 * kb + (lane >> 4);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          d[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+              a[kb], basis[q * kTilePts + 16 * t + (lane & 15)], d[t], 0, 0, 0);
       }
-      count += (v0 > thr) + (v1 > thr) + (v2 > thr) + (v3 > thr);
     }
-    for (; s < nt; ++s) {
-      double val = 0.0;
 #pragma unroll
-      for (int q = 0; q < NC; ++q) val = fma(c[q], basis[s][q], val);
-      count += val > thr ? 1 : 0;
+    for (int t = 0; t < 4; ++t) {
+      const bool point = 16 * t + (lane & 15) < nt;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) cnt[v] += (point && d[t][v] > thr) ? 1 : 0;
     }
   }
-  if (v < Nc) partial[(size_t)blockIdx.y * Nc + v] = count;
-}
-
-template <int NC>
-static void exceed_nc(dim3 grid, int Nc, int nc, int M, int pmax, const double* C, const int* idx,
-                      const double* theta, int Ns, int chunk, double thr, int* partial,
-                      hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-  if (ev0)
-    hipExtLaunchKernelGGL(k_gpc_exceed<NC>, grid, dim3(kBlock), 0, st, ev0, ev1, 0, Nc, nc, M,
-                          pmax, C, idx, theta, Ns, chunk, thr, partial);
-  else
-    hipLaunchKernelGGL(k_gpc_exceed<NC>, grid, dim3(kBlock), 0, st, Nc, nc, M, pmax, C, idx,
-                       theta, Ns, chunk, thr, partial);
-}
-
-int gpc_exceed_padded(int nc) {
-  const int steps[] = {8, 16, 24, 32, 40, 48, 56, 64, 80, 96, 112, 128};
-  for (int p : steps)
-    if (nc <= p) return p;
-  return -1;
+  // lanes with the same l / 16 hold the same four vertices: sum over l % 16
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) cnt[v] += __shfl_xor(cnt[v], off, 16);
+  if ((lane & 15) == 0)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = blockIdx.x * 64 + wave * 16 + (lane >> 4) + 4 * v;
+      if (row < Nc) partial[(size_t)blockIdx.y * Nc + row] = cnt[v];
+    }
 }
 
 void launch_gpc_exceed(int Nc, int nc, int M, int pmax, const double* C, const int* idx,
                        const double* theta, int Ns, int chunk, int n_chunks, double thr,
                        int* partial, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-  const dim3 grid(ceil_div(Nc, kBlock), n_chunks);
-  switch (gpc_exceed_padded(nc)) {
-#define EDF_NC(P)                                                                                \
-  case P:                                                                                        \
-    exceed_nc<P>(grid, Nc, nc, M, pmax, C, idx, theta, Ns, chunk, thr, partial, st, ev0, ev1);   \
-    break;
-    EDF_NC(8) EDF_NC(16) EDF_NC(24) EDF_NC(32) EDF_NC(40) EDF_NC(48) EDF_NC(56) EDF_NC(64)
-    EDF_NC(80) EDF_NC(96) EDF_NC(112) EDF_NC(128)
-#undef EDF_NC
-    default:
-      break;
-  }
+  const dim3 grid(ceil_div(Nc, 64), n_chunks);
+  const int ncp = 4 * ((nc + 3) / 4);
+  const size_t lds = sizeof(double) * ((size_t)ncp * kTilePts + (size_t)kTilePts * M * (pmax + 1)) +
+                     sizeof(int) * (size_t)ncp * M;
+  if (ev0)
+    hipExtLaunchKernelGGL(k_gpc_exceed, grid, dim3(kBlock), lds, st, ev0, ev1, 0, Nc, nc, M, pmax,
+                          C, idx, theta, Ns, chunk, thr, partial);
+  else
+    hipLaunchKernelGGL(k_gpc_exceed, grid, dim3(kBlock), lds, st, Nc, nc, M, pmax, C, idx, theta,
+                       Ns, chunk, thr, partial);
 }
 
 // prob[v] = sum over chunks of the counts / N_s (integer sums: exact, order-free)
