@@ -129,13 +129,14 @@ void launch_gpc_moments(int Nc, int nc, const double* C, const double* Q, double
 // value) and receives D[l / 16 + 4 v][l % 16], v = 0..3.  A wave keeps the coefficients
 // of its 16 vertices in registers (one value per lane and step of 4 terms), a block of
 // four waves walks its chunk of points in tiles of kTilePts: the tile's basis values are
-// formed in LDS ([q][point], point fastest), every wave runs four independent 16-point
-// accumulations, compares the values with the threshold and counts per lane; the
+// formed in LDS ([q][point], point fastest), every wave runs kTilePts / 16 independent
+// 16-point accumulations, compares the values with the threshold and counts per lane; the
 // counts of the 16 lanes that share a vertex are summed by shuffles at the end.
 constexpr int kTilePts = 64;
 constexpr int kMaxKb = kGpcMaxCoef / 4;
 typedef double v4d __attribute__((ext_vector_type(4)));
 
+template <int KB>  // at most KB steps of 4 terms (register array length)
 __global__ __launch_bounds__(kBlock) void k_gpc_exceed(int Nc, int nc, int M, int pmax,
                                                        const double* C, const int* idx,
                                                        const double* theta, int Ns, int chunk,
@@ -152,9 +153,9 @@ __global__ __launch_bounds__(kBlock) void k_gpc_exceed(int Nc, int nc, int M, in
   for (int e = tid; e < ncp * M; e += blockDim.x) sidx[e] = e < nc * M ? idx[e] : 0;
   // this lane's A operand for every step: coefficient (l / 16 + 4 kb) of vertex l % 16
   const int vrow = blockIdx.x * 64 + wave * 16 + (lane & 15);
-  double a[kMaxKb];
+  double a[KB];
 #pragma unroll
-  for (int kb = 0; kb < kMaxKb; ++kb) {
+  for (int kb = 0; kb < KB; ++kb) {
     const int q = 4 * kb + (lane >> 4);
     a[kb] = (kb < kb_n && q < nc && vrow < Nc) ? C[(size_t)q * Nc + vrow] : 0.0;
   }
@@ -189,21 +190,22 @@ __global__ __launch_bounds__(kBlock) void k_gpc_exceed(int Nc, int nc, int M, in
       basis[q * kTilePts + sp] = psi;
     }
     __syncthreads();
-    v4d d[4];
+    constexpr int kCols = kTilePts / 16;  // independent 16-point accumulations
+    v4d d[kCols];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) d[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < kCols; ++t) d[t] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int kb = 0; kb < kMaxKb; ++kb) {
+    for (int kb = 0; kb < KB; ++kb) {
       if (kb < kb_n) {
         const int q = 4 * kb + (lane >> 4);
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
+        for (int t = 0; t < kCols; ++t)
           d[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(
               a[kb], basis[q * kTilePts + 16 * t + (lane & 15)], d[t], 0, 0, 0);
       }
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < kCols; ++t) {
       const bool point = 16 * t + (lane & 15) < nt;
 #pragma unroll
       for (int v = 0; v < 4; ++v) cnt[v] += (point && d[t][v] > thr) ? 1 : 0;
@@ -229,12 +231,20 @@ void launch_gpc_exceed(int Nc, int nc, int M, int pmax, const double* C, const i
   const int ncp = 4 * ((nc + 3) / 4);
   const size_t lds = sizeof(double) * ((size_t)ncp * kTilePts + (size_t)kTilePts * M * (pmax + 1)) +
                      sizeof(int) * (size_t)ncp * M;
+  const int kb_n = ncp / 4;
+  auto kern = kb_n <= 2    ? k_gpc_exceed<2>
+              : kb_n <= 4  ? k_gpc_exceed<4>
+              : kb_n <= 8  ? k_gpc_exceed<8>
+              : kb_n <= 12 ? k_gpc_exceed<12>
+              : kb_n <= 16 ? k_gpc_exceed<16>
+              : kb_n <= 24 ? k_gpc_exceed<24>
+                           : k_gpc_exceed<kMaxKb>;
   if (ev0)
-    hipExtLaunchKernelGGL(k_gpc_exceed, grid, dim3(kBlock), lds, st, ev0, ev1, 0, Nc, nc, M, pmax,
-                          C, idx, theta, Ns, chunk, thr, partial);
+    hipExtLaunchKernelGGL(kern, grid, dim3(kBlock), lds, st, ev0, ev1, 0, Nc, nc, M, pmax, C, idx,
+                          theta, Ns, chunk, thr, partial);
   else
-    hipLaunchKernelGGL(k_gpc_exceed, grid, dim3(kBlock), lds, st, Nc, nc, M, pmax, C, idx, theta,
-                       Ns, chunk, thr, partial);
+    hipLaunchKernelGGL(kern, grid, dim3(kBlock), lds, st, Nc, nc, M, pmax, C, idx, theta, Ns, chunk,
+                       thr, partial);
 }
 
 // prob[v] = sum over chunks of the counts / N_s (integer sums: exact, order-free)
