@@ -108,7 +108,7 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector (and matrix) peak
 def run_gpc(args, wl, pb, prec, degree=4, n_points=10**6, threshold=0.5):
     """The quadrature nodes' samples stepped wl.steps times (untimed), then the surrogate:
     projection of the full-grid c fields (HBM bound) and the exceedance probability
-    from n_points surrogate samples per vertex (FP64 ALU bound), both timed by events
+    from n_points surrogate samples per vertex (FP64 matrix cores), both timed by events
     around their kernels."""
     import numpy as np
     for k in range(wl.steps):
@@ -140,7 +140,7 @@ def run_gpc(args, wl, pb, prec, degree=4, n_points=10**6, threshold=0.5):
                       "n_coef": nc, "points": n_points, "threshold": threshold},
            "mean_range": [float(out["mean"].min()), float(out["mean"].max())],
            "max_var": float(out["var"].max()), "max_prob": float(prob.max()),
-           "roofline": {"bound": "alu", "kernel": "k_gpc_exceed (surrogate evaluation)",
+           "roofline": {"bound": "mfma", "kernel": "k_gpc_exceed (surrogate evaluation)",
                         "achieved": tfs, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "frac": tfs / FP64_PEAK_TFLOPS, "traffic": None, "avg_launch_us": 1e3 * em,
                         "flops_per_launch": flops},
@@ -266,7 +266,8 @@ def main():
     t0 = time.perf_counter()
     for k in range(args.steps):
         stats = pb.step(wl.dt)
-        log(f"step {k + 1}: {time.perf_counter() - t0:.2f} s elapsed")
+        if k < 10 or (k + 1) % 50 == 0 or k + 1 == args.steps:
+            log(f"step {k + 1}: {time.perf_counter() - t0:.2f} s elapsed")
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     if region_stop:
@@ -289,7 +290,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"f64": "f64", "mixed": "f64+f32", "mixed16": "f64+f32+f16"}[prec],
-        "data": "synthetic (seeded lattice parameters; no dataset)",
+        "data": ("synthetic (Halton points and Gauss-Legendre nodes; no dataset)"
+                 if wl.name in synth.E1_GRIDS else "synthetic (seeded lattice parameters; no dataset)"),
         "config": {"workload": wl.name, "groups": [list(g) for g in groups], "samples": S,
                    "dt_s": wl.dt, "precision": prec, "newton_rtol": wl.newton_rtol,
                    "lin_rtol": 1e-6, "lin_max_it": 100,
@@ -324,6 +326,14 @@ def main():
                            "avg_launch_us": 1e3 * prof["ms"] / prof["launches"],
                            "bytes_per_launch": prof["bytes"] / prof["launches"],
                            "bytes_per_launch_all": prof["all_bytes"] / prof["all_launches"]}
+    if wl.name in synth.E1_GRIDS:
+        # the box experiment's comparison after the last timed step: 200 Halton qMC samples
+        # (group 0) against the degree-4 surrogate from the 125 quadrature nodes (group 1)
+        from paper_1906_01632_amd.uq import qmc_vs_gpc
+        g0 = wl.groups[0]
+        res = qmc_vs_gpc(pb, 0, 1, wl.weights, (g0.nx, g0.ny, g0.nz), degree=4)
+        out["e1_compare"] = dict(res["compare"], years=(args.warmup + args.steps) * wl.dt / synth.YEAR_S)
+        log(f"qMC vs gPC: {out['e1_compare']}")
     if not args.no_cpu_baseline:
         log("oracle timing on the host ...")
         out["cpu_baseline"] = cpu_baseline(wl, phys)

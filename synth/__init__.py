@@ -116,6 +116,48 @@ def lattice_points(n: int, s: int, seed: int = 0) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------
+# Halton points (quasi-Monte Carlo on [0,1)^s): coordinate d of point i is the
+# radical inverse of i in the d-th prime base
+# --------------------------------------------------------------------------
+
+PRIMES = (2, 3, 5, 7, 11, 13, 17, 19)
+
+
+def radical_inverse(i: int, base: int) -> float:
+    """The base-`base` digits of i written in reverse order after the radix point."""
+    x, f = 0.0, 1.0 / base
+    while i > 0:
+        i, d = divmod(i, base)
+        x += d * f
+        f /= base
+    return x
+
+
+def halton_points(n: int, s: int, skip: int = 1) -> np.ndarray:
+    """xi_i = 2 (phi_2(i), phi_3(i), phi_5(i), ...) - 1 for i = skip .. skip + n - 1 (the
+    first index, 0, maps to the corner and is skipped by default)."""
+    return np.array([[2.0 * radical_inverse(i, PRIMES[d]) - 1.0 for d in range(s)]
+                     for i in range(skip, skip + n)])
+
+
+def gauss_legendre_tensor(n: int, m: int):
+    """Full tensor n^m Gauss-Legendre nodes on [-1, 1]^m (first coordinate slowest) and
+    weights of the uniform probability measure (summing to 1)."""
+    x, w = np.polynomial.legendre.leggauss(n)
+    grids = np.meshgrid(*([x] * m), indexing="ij")
+    wg = np.meshgrid(*([w] * m), indexing="ij")
+    nodes = np.stack([g.ravel() for g in grids], axis=1)
+    weights = np.prod(np.stack([g.ravel() for g in wg], axis=1), axis=1) / 2.0 ** m
+    return nodes, weights
+
+
+YEAR_S = 365.0 * 86400.0
+# the box experiment on two grids; on the paper's 129x129x33 mesh its 325 samples would
+# need ~390 GB in FP64, more than one GPU holds
+E1_GRIDS = {"e1box33": (33, 33, 9, 4), "e1box65": (65, 65, 17, 5)}
+
+
+# --------------------------------------------------------------------------
 # Workloads
 # --------------------------------------------------------------------------
 
@@ -153,15 +195,23 @@ def workload(name: str, seed: int = 0) -> Workload:
         return Workload(name, [Group(65, 65, 17, 64, 5)], FIELD_LATTICE4, 50,
                         newton_rtol=1e-10, xi=pts[i % 8 == 0])
     if name == "gpc125":               # the paper's 3-parameter box field at 125 nodes
-        x, w = np.polynomial.legendre.leggauss(5)
-        nodes = np.array([(a, b, c) for a in x for b in x for c in x])
-        weights = np.array([wa * wb * wc for wa in w for wb in w for wc in w]) / 8.0
+        nodes, weights = gauss_legendre_tensor(5, 3)
         return Workload(name, [Group(65, 65, 17, 125, 5)], FIELD_PAPER3, 3,
                         newton_rtol=1e-8, xi=nodes, weights=weights)
+    if name in E1_GRIDS:               # the paper's box experiment with 3 parameters:
+        # 200 Halton qMC samples (group 0) beside the 125 tensor Gauss-Legendre nodes of the
+        # degree-4 surrogate (group 1) on one grid, 1500 steps of 0.005 years
+        nx, ny, nz, levels = E1_GRIDS[name]
+        nodes, weights = gauss_legendre_tensor(5, 3)
+        xi = np.concatenate([halton_points(200, 3), nodes])
+        return Workload(name, [Group(nx, ny, nz, 200, levels), Group(nx, ny, nz, 125, levels)],
+                        FIELD_PAPER3, 1500, dt=0.005 * YEAR_S, newton_rtol=1e-8, xi=xi,
+                        weights=weights)
     raise KeyError(name)
 
 
-WORKLOADS = ("elder33_f64", "elder129_f64", "qmc512_mixedres", "mixed257", "adjoint65", "gpc125")
+WORKLOADS = ("elder33_f64", "elder129_f64", "qmc512_mixedres", "mixed257", "adjoint65", "gpc125",
+             "e1box33", "e1box65")
 
 
 # --------------------------------------------------------------------------

@@ -107,3 +107,42 @@ def test_gpc_invalid_calls_are_rejected():
     with pytest.raises(EDFError):
         pb.gpc_exceed(np.full((4, 3), 1.5), 0.5, (9, 9, 3))  # points outside [-1, 1]^3
     pb.destroy()
+
+
+def test_qmc_against_gpc_statistics():
+    """The box experiment's comparison (Section 5) on a small grid: 16 Halton samples and
+    the 27 tensor Gauss-Legendre nodes of a degree-2 surrogate, two steps of 0.005 years.
+    The qMC statistics equal the oracle's equally weighted moments of the same states,
+    the surrogate's mean and variance the oracle's projection of the node states, and the
+    sampled exceedance the oracle surrogate's counts (up to 1e-12 ties)."""
+    from paper_1906_01632_amd.uq import qmc_vs_gpc
+    phys = synth.physics(3)
+    nx, ny, nz = 17, 17, 5
+    nodes, w = gpc.tensor_gauss_legendre(3, 3)
+    halton = synth.halton_points(16, 3)
+    pb = _problem(phys, [(nx, ny, nz, 2, 16), (nx, ny, nz, 2, len(nodes))])
+    pb.set_parameters(np.concatenate([halton, nodes]))
+    for _ in range(2):
+        pb.step(0.005 * synth.YEAR_S)
+    common = (nx, ny, nz)
+    res = qmc_vs_gpc(pb, 0, 1, w, common, degree=2, n_points=20000, seed=3)
+    fq = np.array([pb.get_state(i)[..., 1] for i in range(16)])
+    fg = np.array([pb.get_state(16 + i)[..., 1] for i in range(len(nodes))])
+    qm, qv, qe = stats.moments(fq)
+    assert np.abs(res["qmc_mean"] - qm).max() < 1e-14
+    assert np.abs(res["qmc_var"] - qv).max() <= 1e-13 * max(qv.max(), 1e-300)
+    assert np.abs(res["qmc_exceed"] - qe).max() < 1e-15
+    J = gpc.multi_indices(3, 2)
+    coef = gpc.project(fg, nodes, w, J)
+    gm, gv = gpc.moments(coef, J)
+    assert np.abs(res["gpc_mean"] - gm).max() < 1e-14
+    assert np.abs(res["gpc_var"] - gv).max() <= 1e-13 * max(gv.max(), 1e-300)
+    pts = np.random.default_rng(3).uniform(-1.0, 1.0, (20000, 3))
+    vals = gpc.surrogate(coef, J, pts)
+    want = np.mean(vals > 0.5, axis=0)
+    near = np.sum(np.abs(vals - 0.5) < 1e-12, axis=0) / len(pts)
+    assert np.all(np.abs(res["gpc_exceed"] - want) <= near + 1e-15)
+    c = res["compare"]
+    assert c["mean_max_abs"] == np.abs(res["qmc_mean"] - res["gpc_mean"]).max()
+    assert c["n_coef"] == len(J) and 0 <= c["mean_level_side_differs"] <= 1
+    pb.destroy()
