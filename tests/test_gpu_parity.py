@@ -66,6 +66,30 @@ def test_defect_matches_oracle(shape, levels, model):
     pb.destroy()
 
 
+@pytest.mark.parametrize("model", [0, 2, 3])
+def test_stratified_hydrostatic_defect(model):
+    """A non-uniform stratification c(z) with its discrete hydrostatic pressure (trapezoid
+    rule down each column): the library's liquid rows vanish (no Darcy flux through any
+    face, whatever K), and its whole defect equals the oracle's."""
+    nx, ny, nz = 17, 13, 5
+    phys = synth.physics(model)
+    xi = _xi(model, 1)
+    pb = _problem(phys, [(nx, ny, nz, 3, 1)])
+    pb.set_parameters(xi)
+    box = elder.Box(nx, ny, nz, phys)
+    cz = np.array([0.0, 0.45, 0.2, 0.8, 0.6])
+    rho = phys["rho0"] + (phys["rho1"] - phys["rho0"]) * cz
+    p = np.concatenate([[0.0], np.cumsum(phys["g"] * box.h[2] * 0.5 * (rho[1:] + rho[:-1]))])
+    u = np.zeros((nz, ny, nx, 2))
+    u[..., 0] = p[:, None, None]
+    u[..., 1] = cz[:, None, None]
+    got = pb.residual(0, u, u, DT)
+    ref = elder.residual(box, elder.coefficients(box, xi[0]), u, u, DT) * elder.row_scale(box, DT)
+    assert np.abs(got[..., 0]).max() < 1e-12
+    assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
+    pb.destroy()
+
+
 def _oracle_stencil(box, coef, u):
     """Oracle Jacobian scaled like the library's, as [27][2][2][nz][ny][nx]."""
     J = elder.jacobian(box, coef, u, DT)

@@ -123,6 +123,47 @@ def test_hydrostatic_state_is_a_fixed_point(model):
     assert np.abs(u1[..., 0] - u[..., 0]).max() < 1e-9 * ph["rho0"] * ph["g"] * ph["lz"]
 
 
+def _stratified_hydrostatic(box, ph, cz):
+    """c = c(z) laterally uniform, p from the trapezoid rule of dp/dz = rho(c) g down each
+    column (p = 0 at the top)."""
+    rho = ph["rho0"] + (ph["rho1"] - ph["rho0"]) * np.asarray(cz)
+    p = np.concatenate([[0.0], np.cumsum(ph["g"] * box.h[2] * 0.5 * (rho[1:] + rho[:-1]))])
+    u = np.zeros((box.nz, box.ny, box.nx, 2))
+    u[..., 0] = p[:, None, None]
+    u[..., 1] = np.asarray(cz)[:, None, None]
+    return u
+
+
+@pytest.mark.parametrize("model", [0, 2, 3])
+def test_stratified_hydrostatic_state_has_no_darcy_flux(model):
+    """Consistent velocity (Section 4, the flux that keeps hydrostatic states free of
+    spurious flow): with a non-uniform, non-monotone stratification c(z) and the discrete
+    hydrostatic pressure, every face's Darcy flux vanishes for any per-hex K, so the
+    liquid rows are zero and the salt rows are pure vertical diffusion (the same rows as
+    with the permeability switched off)."""
+    ph = synth.physics(model)
+    box = elder.Box(9, 7, 6, ph)
+    coef = elder.coefficients(box, [0.7, -0.4, 0.9, -1.0][:synth.N_XI[model]])
+    u = _stratified_hydrostatic(box, ph, [0.0, 0.3, 0.35, 0.9, 0.1, 0.6])
+    qscale = coef[1].max() / ph["mu"] * ph["rho1"] * ph["g"] * box.h[0] * box.h[1]
+    for face in elder.SCVFS:
+        Q = elder._face_quantities(box, coef, u[..., 0], u[..., 1], face)[3]
+        assert np.abs(Q).max() < 1e-13 * qscale
+    Fl, Fs = elder.fv_rows(box, coef, u, u, DT)
+    Fl0, Fs0 = elder.fv_rows(box, (coef[0], coef[1] * 0.0), u, u, DT)
+    s = elder.row_scale(box, DT)[..., 0]
+    assert np.abs(Fl * s).max() < 1e-12
+    assert np.abs(Fl0 * s).max() == 0.0
+    assert np.abs((Fs - Fs0) * s).max() < 1e-12 * np.abs(Fs0 * s).max()
+    assert np.abs(Fs0 * s).max() > 1e-6  # diffusion across the stratification is there
+    # a lateral density contrast is not in equilibrium: flux appears
+    u2 = u.copy()
+    u2[:, :, : box.nx // 2, 1] += 0.2
+    Q2 = max(np.abs(elder._face_quantities(box, coef, u2[..., 0], u2[..., 1], f)[3]).max()
+             for f in elder.SCVFS)
+    assert Q2 > 1e-3 * qscale
+
+
 @pytest.mark.parametrize("c0", [0.0, 0.37, 1.0])
 def test_uniform_salt_is_consistent(c0):
     """c = c0 everywhere, p = rho(c0) g z: both FV rows vanish at every vertex, i.e.
