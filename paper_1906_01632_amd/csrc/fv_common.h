@@ -103,6 +103,55 @@ __device__ __forceinline__ int colour_encode(const Geom& g, int i, int j, int k)
   return g.off[col] + (i >> 1) + g.mx[col] * ((j >> 1) + g.my[col] * (k >> 1));
 }
 
+// Neighbour values for the vertices of one colour.  Colour c = px + 2 py + 4 pz holds
+// the vertices with those coordinate parities; its row length g.mx[c] depends on px only
+// and its rows per plane g.my[c] on py only.  The colour of neighbour (dx, dy, dz) is the
+// same for every vertex of a colour, so once the colour is known for the whole wave the
+// neighbour colour's start, size, row length and plane size are scalars, and the
+// neighbour's place in its colour is one of four per-vertex bases (one per parity flip in
+// x and y) plus a scalar.  A neighbour outside the grid carries a zero stencil block; its
+// place is clamped into the neighbour colour's range (never empty: every dimension has at
+// least 2 vertices), so it reads some valid value of that colour.
+struct NbrMap {
+  int px, py, pz;
+  int base[4];  // a + mx(px ^ fx) (b + my(py ^ fy) c) for the flips fx + 2 fy
+};
+
+__device__ __forceinline__ NbrMap nbr_map(const Geom& g, int col, int i, int j, int k) {
+  NbrMap m;
+  m.px = col & 1;
+  m.py = (col >> 1) & 1;
+  m.pz = col >> 2;
+  const int a = i >> 1, b = j >> 1, c = k >> 1;
+#pragma unroll
+  for (int f = 0; f < 4; ++f)
+    m.base[f] = a + g.mx[m.px ^ (f & 1)] * (b + g.my[2 * (m.py ^ (f >> 1))] * c);
+  return m;
+}
+
+// place of neighbour (dx, dy, dz) in its colour cn (a scalar for the wave): inside the
+// grid, colour_encode(i + dx, j + dy, k + dz) = g.off[cn] + place.  A place below 0 wraps
+// to a large unsigned value and is clamped like one beyond the colour's end.
+__device__ __forceinline__ unsigned nbr_place(const Geom& g, const NbrMap& m, int dx, int dy,
+                                              int dz, int& cn) {
+  const int qx = m.px ^ (dx & 1), qy = m.py ^ (dy & 1), qz = m.pz ^ (dz & 1);
+  cn = qx + 2 * qy + 4 * qz;
+  const int shift =
+      ((m.px + dx) >> 1) + g.mx[qx] * (((m.py + dy) >> 1) + g.my[2 * qy] * ((m.pz + dz) >> 1));
+  return min((unsigned)(m.base[(dx & 1) + 2 * (dy & 1)] + shift), (unsigned)(g.cnt[cn] - 1));
+}
+
+// the value of neighbour (dx, dy, dz) in a colour-major vector of V: the colour's start
+// offsets the (scalar) base pointer, the place is a 32-bit unsigned byte offset
+template <typename V>
+__device__ __forceinline__ V load_nbr(const V* x, const Geom& g, const NbrMap& m, int dx, int dy,
+                                      int dz) {
+  int cn;
+  const unsigned u = nbr_place(g, m, dx, dy, dz, cn);
+  return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(x + g.off[cn]) +
+                                     u * (unsigned)sizeof(V));
+}
+
 // salt Dirichlet vertex (closed top patch: c = 1; bottom: c = 0)
 __device__ __forceinline__ bool is_cdir(const Geom& g, int i, int j, int k, double& value) {
   if (k == g.nz - 1) { value = 0.0; return true; }

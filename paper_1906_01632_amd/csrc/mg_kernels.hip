@@ -46,17 +46,15 @@ __device__ __forceinline__ void smooth_vertex(const Geom& g, int col, int q, con
   const T* A = A_s + sidx<T>(t, 0, kPlanes);
   T2* x = reinterpret_cast<T2*>(x_s);
   const T2 bv = reinterpret_cast<const T2*>(b_s)[t];
+  const NbrMap nm = nbr_map(g, col, i, j, k);
   T r0 = bv.x, r1 = bv.y;
 #pragma unroll
   for (int dz = -1; dz <= 1; ++dz) {
-    const int kk = clampi(k + dz, 0, g.nz - 1);
 #pragma unroll
     for (int dy = -1; dy <= 1; ++dy) {
-      const int jj = clampi(j + dy, 0, g.ny - 1);
 #pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
-        const int ii = clampi(i + dx, 0, g.nx - 1);
-        const T2 xv = x[colour_encode(g, ii, jj, kk)];
+        const T2 xv = load_nbr(x, g, nm, dx, dy, dz);
         const Block2<T> a = load_block<NT>(A, nb_index(dx, dy, dz) * 4);
         r0 -= a.a00 * xv.x + a.a01 * xv.y;
         r1 -= a.a10 * xv.x + a.a11 * xv.y;
@@ -90,19 +88,20 @@ __device__ __forceinline__ void residual_vertex(const Geom& g, int t, const T* A
   }
   int i, j, k;
   if (!colour_decode(g, t, i, j, k)) return;
+  // a wave's 64 positions lie in one colour (colours start at multiples of 64)
+  const int col = __builtin_amdgcn_readfirstlane((t >= g.off[1]) + (t >= g.off[2]) + (t >= g.off[3]) +
+                                                 (t >= g.off[4]) + (t >= g.off[5]) + (t >= g.off[6]));
+  const NbrMap nm = nbr_map(g, col, i, j, k);
   const T* A = A_s + sidx<T>(t, 0, kPlanes);
   const T2* x = reinterpret_cast<const T2*>(x_s);
   T a0 = 0, a1 = 0;  // (A x)_v; b is read after the sweep over the neighbours
 #pragma unroll 1  // one z-plane of neighbours at a time keeps the register count low
   for (int dz = -1; dz <= 1; ++dz) {
-    const int kk = clampi(k + dz, 0, g.nz - 1);
 #pragma unroll
     for (int dy = -1; dy <= 1; ++dy) {
-      const int jj = clampi(j + dy, 0, g.ny - 1);
 #pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
-        const int ii = clampi(i + dx, 0, g.nx - 1);
-        const T2 xv = x[colour_encode(g, ii, jj, kk)];
+        const T2 xv = load_nbr(x, g, nm, dx, dy, dz);
         const Block2<T> a = load_block<NT>(A, nb_index(dx, dy, dz) * 4);
         a0 += a.a00 * xv.x + a.a01 * xv.y;
         a1 += a.a10 * xv.x + a.a11 * xv.y;
@@ -352,19 +351,17 @@ __global__ __launch_bounds__(kBlock) void k_smooth_f16(Geom g, int col, const _F
   const _Float16* A = A_all + (size_t)s * kPlanes * Np + sidx<_Float16>(t, 0, kPlanes);
   float2* x = reinterpret_cast<float2*>(x_all + (size_t)s * 2 * Np);
   const float2 bv = reinterpret_cast<const float2*>(bh_all + (size_t)s * 2 * Np)[t];
+  const NbrMap nm = nbr_map(g, col, i, j, k);
   float r0 = bv.x, r1 = bv.y;
 #pragma unroll
   for (int dz = -1; dz <= 1; ++dz) {
-    const int kk = clampi(k + dz, 0, g.nz - 1);
 #pragma unroll
     for (int dy = -1; dy <= 1; ++dy) {
-      const int jj = clampi(j + dy, 0, g.ny - 1);
 #pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
         const int o = nb_index(dx, dy, dz);
         if (o == kDiag) continue;  // the unit diagonal block
-        const int ii = clampi(i + dx, 0, g.nx - 1);
-        const float2 xv = x[colour_encode(g, ii, jj, kk)];
+        const float2 xv = load_nbr(x, g, nm, dx, dy, dz);
         const Block2<float> a = load_block<NT>(A, o * 4);
         r0 -= a.a00 * xv.x + a.a01 * xv.y;
         r1 -= a.a10 * xv.x + a.a11 * xv.y;
@@ -404,19 +401,19 @@ __global__ __launch_bounds__(kBlock) void k_residual_f16(Geom g, const _Float16*
   }
   int i, j, k;
   if (!colour_decode(g, t, i, j, k)) return;
+  const int col = __builtin_amdgcn_readfirstlane((t >= g.off[1]) + (t >= g.off[2]) + (t >= g.off[3]) +
+                                                 (t >= g.off[4]) + (t >= g.off[5]) + (t >= g.off[6]));
+  const NbrMap nm = nbr_map(g, col, i, j, k);
   const _Float16* A = A_all + (size_t)s * kPlanes * Np + sidx<_Float16>(t, 0, kPlanes);
   const float2* x = reinterpret_cast<const float2*>(x_all + (size_t)s * 2 * Np);
   float a0 = 0.f, a1 = 0.f;  // (A16 x)_v
 #pragma unroll 1
   for (int dz = -1; dz <= 1; ++dz) {
-    const int kk = clampi(k + dz, 0, g.nz - 1);
 #pragma unroll
     for (int dy = -1; dy <= 1; ++dy) {
-      const int jj = clampi(j + dy, 0, g.ny - 1);
 #pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
-        const int ii = clampi(i + dx, 0, g.nx - 1);
-        const float2 xv = x[colour_encode(g, ii, jj, kk)];
+        const float2 xv = load_nbr(x, g, nm, dx, dy, dz);
         if (dx == 0 && dy == 0 && dz == 0) {
           a0 += xv.x;
           a1 += xv.y;
