@@ -103,6 +103,38 @@ __device__ __forceinline__ int colour_encode(const Geom& g, int i, int j, int k)
   return g.off[col] + (i >> 1) + g.mx[col] * ((j >> 1) + g.my[col] * (k >> 1));
 }
 
+// colour of position t for a wave of 64 consecutive positions that starts at a multiple
+// of 64: colours start at multiples of 64, so the wave lies in one colour, which is
+// returned as a scalar
+__device__ __forceinline__ int wave_colour(const Geom& g, int t) {
+  int col = 0;
+#pragma unroll
+  for (int c = 1; c < 8; ++c) col += (t >= g.off[c]) ? 1 : 0;
+  return __builtin_amdgcn_readfirstlane(col);
+}
+
+// colour_decode for such a wave, also giving the (scalar) colour
+__device__ __forceinline__ bool colour_decode_wave(const Geom& g, int t, int& col, int& i, int& j,
+                                                   int& k) {
+  col = wave_colour(g, t);
+  const int s = t - g.off[col];
+  if (s >= g.cnt[col]) return false;
+  colour_decode_in(g, col, s, i, j, k);
+  return true;
+}
+
+// colour_encode where the colour differs between the lanes of a wave: the colour's
+// start, row length and plane size are picked by selects among scalars instead of
+// per-lane reads of the grid description
+__device__ __forceinline__ int colour_encode_sel(const Geom& g, int i, int j, int k) {
+  const bool bx = i & 1, by = j & 1, bz = k & 1;
+  const int o0 = bx ? g.off[1] : g.off[0], o1 = bx ? g.off[3] : g.off[2];
+  const int o2 = bx ? g.off[5] : g.off[4], o3 = bx ? g.off[7] : g.off[6];
+  const int o = bz ? (by ? o3 : o2) : (by ? o1 : o0);
+  const int mx = bx ? g.mx[1] : g.mx[0], my = by ? g.my[2] : g.my[0];
+  return o + (i >> 1) + mx * ((j >> 1) + my * (k >> 1));
+}
+
 // Neighbour values for the vertices of one colour.  Colour c = px + 2 py + 4 pz holds
 // the vertices with those coordinate parities; its row length g.mx[c] depends on px only
 // and its rows per plane g.my[c] on py only.  The colour of neighbour (dx, dy, dz) is the

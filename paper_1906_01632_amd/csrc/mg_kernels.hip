@@ -86,11 +86,8 @@ __device__ __forceinline__ void residual_vertex(const Geom& g, int t, const T* A
     }
     return;
   }
-  int i, j, k;
-  if (!colour_decode(g, t, i, j, k)) return;
-  // a wave's 64 positions lie in one colour (colours start at multiples of 64)
-  const int col = __builtin_amdgcn_readfirstlane((t >= g.off[1]) + (t >= g.off[2]) + (t >= g.off[3]) +
-                                                 (t >= g.off[4]) + (t >= g.off[5]) + (t >= g.off[6]));
+  int col, i, j, k;
+  if (!colour_decode_wave(g, t, col, i, j, k)) return;
   const NbrMap nm = nbr_map(g, col, i, j, k);
   const T* A = A_s + sidx<T>(t, 0, kPlanes);
   const T2* x = reinterpret_cast<const T2*>(x_s);
@@ -123,8 +120,8 @@ template <typename T>
 __device__ __forceinline__ void restrict_vertex(const Geom& gf, const Geom& gc, int t,
                                                 const T* rf_s, T* bc_s, T* xc_s) {
   using T2 = typename V2<T>::type;
-  int I, J, K;
-  if (!colour_decode(gc, t, I, J, K)) return;
+  int cc, I, J, K;
+  if (!colour_decode_wave(gc, t, cc, I, J, K)) return;
   const T2* rf = reinterpret_cast<const T2*>(rf_s);
   T a0 = 0, a1 = 0;
 #pragma unroll
@@ -163,8 +160,8 @@ template <typename T>
 __device__ __forceinline__ void prolong_vertex(const Geom& gf, const Geom& gc, int t,
                                                const T* xc_s, T* xf_s) {
   using T2 = typename V2<T>::type;
-  int i, j, k;
-  if (!colour_decode(gf, t, i, j, k)) return;
+  int cf, i, j, k;
+  if (!colour_decode_wave(gf, t, cf, i, j, k)) return;
   const T2* xc = reinterpret_cast<const T2*>(xc_s);
   const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1, k0 = k >> 1,
             k1 = (k + 1) >> 1;
@@ -175,7 +172,7 @@ __device__ __forceinline__ void prolong_vertex(const Geom& gf, const Geom& gc, i
     const int I = (c & 1) ? i1 : i0, J = (c & 2) ? j1 : j0, K = (c & 4) ? k1 : k0;
     // the second parent of an even index coincides with the first: count it once
     if (((c & 1) && !(i & 1)) || ((c & 2) && !(j & 1)) || ((c & 4) && !(k & 1))) continue;
-    const T2 e = xc[colour_encode(gc, I, J, K)];
+    const T2 e = xc[colour_encode_sel(gc, I, J, K)];
     const T w = wi * wj * wk;
     a0 += w * e.x;
     a1 += w * e.y;
@@ -297,8 +294,8 @@ __global__ __launch_bounds__(kBlock) void k_scale_f16(Geom g, const float* A32_a
   const int s = blockIdx.y;
   if (mask && !mask[s]) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int i, j, k;
-  if (t >= g.off[8] || !colour_decode(g, t, i, j, k)) return;
+  int col, i, j, k;
+  if (t >= g.off[8] || !colour_decode_wave(g, t, col, i, j, k)) return;
   const size_t Np = g.off[8];
   const float* a = A32_all + (size_t)s * kPlanes * Np + sidx<float>(t, 0, kPlanes);
   _Float16* h = A16_all + (size_t)s * kPlanes * Np + sidx<_Float16>(t, 0, kPlanes);
@@ -399,10 +396,8 @@ __global__ __launch_bounds__(kBlock) void k_residual_f16(Geom g, const _Float16*
       reinterpret_cast<float2*>(r_all + (size_t)s * 2 * Np)[t] = make_float2(0.f, 0.f);
     return;
   }
-  int i, j, k;
-  if (!colour_decode(g, t, i, j, k)) return;
-  const int col = __builtin_amdgcn_readfirstlane((t >= g.off[1]) + (t >= g.off[2]) + (t >= g.off[3]) +
-                                                 (t >= g.off[4]) + (t >= g.off[5]) + (t >= g.off[6]));
+  int col, i, j, k;
+  if (!colour_decode_wave(g, t, col, i, j, k)) return;
   const NbrMap nm = nbr_map(g, col, i, j, k);
   const _Float16* A = A_all + (size_t)s * kPlanes * Np + sidx<_Float16>(t, 0, kPlanes);
   const float2* x = reinterpret_cast<const float2*>(x_all + (size_t)s * 2 * Np);
@@ -449,8 +444,8 @@ __global__ __launch_bounds__(kBlock) void k_to_colour_scaled(Geom g, const doubl
   const int s = blockIdx.y;
   if (mask && !mask[s]) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int i, j, k;
-  if (t >= g.off[8] || !colour_decode(g, t, i, j, k)) return;
+  int col, i, j, k;
+  if (t >= g.off[8] || !colour_decode_wave(g, t, col, i, j, k)) return;
   const size_t v = i + (size_t)g.nx * (j + (size_t)g.ny * k);
   const double2 b = reinterpret_cast<const double2*>(in_all)[(size_t)s * g.N + v];
   const float* d = D_all + (size_t)s * 4 * g.off[8] + sidx<float>(t, 0, 4);
@@ -496,8 +491,8 @@ __global__ __launch_bounds__(kBlock) void k_to_colour(Geom g, const double* in_a
   const int s = blockIdx.y;
   if (mask && !mask[s]) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int i, j, k;
-  if (t >= g.off[8] || !colour_decode(g, t, i, j, k)) return;
+  int col, i, j, k;
+  if (t >= g.off[8] || !colour_decode_wave(g, t, col, i, j, k)) return;
   const size_t v = i + (size_t)g.nx * (j + (size_t)g.ny * k);
   const double2 a = reinterpret_cast<const double2*>(in_all)[(size_t)s * g.N + v];
   typename V2<T>::type b;
@@ -516,7 +511,7 @@ __global__ __launch_bounds__(kBlock) void k_from_colour(Geom g, const T* in_all,
   const int i = v % g.nx, j = (v / g.nx) % g.ny, k = v / (g.nx * g.ny);
   const typename V2<T>::type a =
       reinterpret_cast<const typename V2<T>::type*>(in_all)[(size_t)s * g.off[8] +
-                                                           colour_encode(g, i, j, k)];
+                                                           colour_encode_sel(g, i, j, k)];
   reinterpret_cast<double2*>(out_all)[(size_t)s * g.N + v] = make_double2((double)a.x, (double)a.y);
 }
 
@@ -543,8 +538,8 @@ __global__ __launch_bounds__(kBlock) void k_coarse_dense(Geom g, const double* A
   const int s = blockIdx.y;
   if (mask && !mask[s]) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int i, j, k;
-  if (t >= g.off[8] || !colour_decode(g, t, i, j, k)) return;
+  int col, i, j, k;
+  if (t >= g.off[8] || !colour_decode_wave(g, t, col, i, j, k)) return;
   const size_t N = g.N, n = 2 * N;
   const double* A = A_all + (size_t)s * kPlanes * g.off[8] + sidx<double>(t, 0, kPlanes);
   double* M = M_all + (size_t)s * n * n;
@@ -713,7 +708,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_vcycle_bottom(const FusedLeve
     auto pos = [&](int e) {  // natural unknown e -> colour-major unknown
       const int v = e >> 1;
       const int i = v % gc.nx, j = (v / gc.nx) % gc.ny, k = v / (gc.nx * gc.ny);
-      return 2 * colour_encode(gc, i, j, k) + (e & 1);
+      return 2 * colour_encode_sel(gc, i, j, k) + (e & 1);
     };
     for (int e = tid; e < n; e += nt) bn[e] = (double)b[pos(e)];
     __syncthreads();
