@@ -202,6 +202,9 @@ def main():
                          "sample the surrogate's exceedance at 10^6 points (workload gpc125)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default fused-bottom levels instead of timing the choices")
+    ap.add_argument("--fuse-from", default=None,
+                    help="first fused V-cycle level per group, comma separated (instead of "
+                         "autotuning; e.g. to repeat a run's launch configuration under a profiler)")
     ap.add_argument("--mark-timed-region", action="store_true",
                     help="mark the timed steps with a roctx range (rocprofv3 --marker-trace)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -237,7 +240,12 @@ def main():
     t = time.perf_counter()
     pb = Problem(phys, groups, opts)
     pb.set_parameters(wl.xi)
-    if not args.no_autotune:
+    if args.fuse_from:
+        levels = [int(v) for v in args.fuse_from.split(",")]
+        assert len(levels) == len(groups), "--fuse-from needs one level per group"
+        for gi, lv in enumerate(levels):
+            pb.set_tuning(gi, lv)
+    elif not args.no_autotune:
         pb.autotune(wl.dt)
     tuning = [pb.tuning(g)[0] for g in range(len(groups))]
     for gi in range(len(groups)):

@@ -58,21 +58,22 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Geom g, const double* A_all, co
   double acc[2] = {0.0, 0.0};
   if (v < g.N) {
     const int i = v % g.nx, j = (v / g.nx) % g.ny, k = v / (g.nx * g.ny);
-    const int t = colour_encode(g, i, j, k);
+    const int t = colour_encode_sel(g, i, j, k);
     const double* A = A_all + (size_t)s * kPlanes * Np + sidx<double>(t, 0, kPlanes);
-    const double2* x = reinterpret_cast<const double2*>(x_all) + (size_t)s * N;
+    const char* x = reinterpret_cast<const char*>(reinterpret_cast<const double2*>(x_all) + (size_t)s * N);
+    const int plane = g.nx * g.ny;
     double r0 = 0.0, r1 = 0.0;
 #pragma unroll
     for (int dz = -1; dz <= 1; ++dz) {
-      const int kk = clampi(k + dz, 0, g.nz - 1);
 #pragma unroll
       for (int dy = -1; dy <= 1; ++dy) {
-        const int jj = clampi(j + dy, 0, g.ny - 1);
 #pragma unroll
         for (int dx = -1; dx <= 1; ++dx) {
-          const int ii = clampi(i + dx, 0, g.nx - 1);
           const int o = nb_index(dx, dy, dz);
-          const double2 xv = x[ii + (size_t)g.nx * (jj + (size_t)g.ny * kk)];
+          // a neighbour outside the grid has a zero block: any vertex of the sample will do,
+          // so the index is clamped (below 0 wraps to a large unsigned value)
+          const unsigned w = min((unsigned)(v + dx + g.nx * dy + plane * dz), (unsigned)(g.N - 1));
+          const double2 xv = *reinterpret_cast<const double2*>(x + w * (unsigned)sizeof(double2));
           const Block2<double> a = load_block(A, o * 4);
           r0 += a.a00 * xv.x + a.a01 * xv.y;
           r1 += a.a10 * xv.x + a.a11 * xv.y;
