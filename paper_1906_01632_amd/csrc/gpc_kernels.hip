@@ -127,12 +127,16 @@ void launch_gpc_moments(int Nc, int nc, const double* C, const double* Q, double
 // v_mfma_f64_16x16x4f64 over q in steps of 4 (FP64 throughout).  Lane l supplies
 // A[l % 16][l / 16] (a vertex's coefficient) and B[l / 16][l % 16] (a point's basis
 // value) and receives D[l / 16 + 4 v][l % 16], v = 0..3.  A wave keeps the coefficients
-// of its 16 vertices in registers (one value per lane and step of 4 terms), a block of
-// four waves walks its chunk of points in tiles of kTilePts: the tile's basis values are
-// formed in LDS ([q][point], point fastest), every wave runs kTilePts / 16 independent
-// 16-point accumulations, compares the values with the threshold and counts per lane; the
-// counts of the 16 lanes that share a vertex are summed by shuffles at the end.
+// of its kRowBlocks x 16 vertices in registers (one value per lane, row block and step of
+// 4 terms), a block of four waves walks its chunk of points in tiles of kTilePts: the
+// tile's basis values are formed in LDS ([q][point], point fastest), every wave runs
+// kTilePts / 16 x kRowBlocks independent 16 x 16 accumulations (each basis value read
+// from LDS feeds kRowBlocks products), compares the values with the threshold and counts
+// per lane; the counts of the 16 lanes that share a vertex are summed by shuffles at the
+// end.
 constexpr int kTilePts = 64;
+constexpr int kRowBlocks = 2;
+constexpr int kExceedRows = 4 * 16 * kRowBlocks;  // vertices per workgroup
 constexpr int kMaxKb = kGpcMaxCoef / 4;
 typedef double v4d __attribute__((ext_vector_type(4)));
 
@@ -151,17 +155,22 @@ __global__ __launch_bounds__(kBlock) void k_gpc_exceed(int Nc, int nc, int M, in
   double* leg = basis + (size_t)ncp * kTilePts;
   int* sidx = reinterpret_cast<int*>(leg + (size_t)kTilePts * M * P1);
   for (int e = tid; e < ncp * M; e += blockDim.x) sidx[e] = e < nc * M ? idx[e] : 0;
-  // this lane's A operand for every step: coefficient (l / 16 + 4 kb) of vertex l % 16
-  const int vrow = blockIdx.x * 64 + wave * 16 + (lane & 15);
-  double a[KB];
+  // this lane's A operand for every row block and step: coefficient (l / 16 + 4 kb) of
+  // vertex l % 16 of the row block
+  const int row0 = blockIdx.x * kExceedRows + wave * 16 * kRowBlocks;
+  double a[kRowBlocks][KB];
 #pragma unroll
-  for (int kb = 0; kb < KB; ++kb) {
-    const int q = 4 * kb + (lane >> 4);
-    a[kb] = (kb < kb_n && q < nc && vrow < Nc) ? C[(size_t)q * Nc + vrow] : 0.0;
+  for (int r = 0; r < kRowBlocks; ++r) {
+    const int vrow = row0 + 16 * r + (lane & 15);
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      const int q = 4 * kb + (lane >> 4);
+      a[r][kb] = (kb < kb_n && q < nc && vrow < Nc) ? C[(size_t)q * Nc + vrow] : 0.0;
+    }
   }
   const int s_begin = blockIdx.y * chunk;
   const int s_end = min(Ns, s_begin + chunk);
-  int cnt[4] = {0, 0, 0, 0};
+  int cnt[kRowBlocks][4] = {};
   for (int s0 = s_begin; s0 < s_end; s0 += kTilePts) {
     const int nt = min(kTilePts, s_end - s0);
     __syncthreads();  // the previous tile's basis values are no longer read
@@ -191,43 +200,54 @@ __global__ __launch_bounds__(kBlock) void k_gpc_exceed(int Nc, int nc, int M, in
     }
     __syncthreads();
     constexpr int kCols = kTilePts / 16;  // independent 16-point accumulations
-    v4d d[kCols];
+    v4d d[kRowBlocks][kCols];
 #pragma unroll
-    for (int t = 0; t < kCols; ++t) d[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int r = 0; r < kRowBlocks; ++r)
+#pragma unroll
+      for (int t = 0; t < kCols; ++t) d[r][t] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
       if (kb < kb_n) {
         const int q = 4 * kb + (lane >> 4);
 #pragma unroll
-        for (int t = 0; t < kCols; ++t)
-          d[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-              a[kb], basis[q * kTilePts + 16 * t + (lane & 15)], d[t], 0, 0, 0);
+        for (int t = 0; t < kCols; ++t) {
+          const double b = basis[q * kTilePts + 16 * t + (lane & 15)];
+#pragma unroll
+          for (int r = 0; r < kRowBlocks; ++r)
+            d[r][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r][kb], b, d[r][t], 0, 0, 0);
+        }
       }
     }
 #pragma unroll
     for (int t = 0; t < kCols; ++t) {
       const bool point = 16 * t + (lane & 15) < nt;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) cnt[v] += (point && d[t][v] > thr) ? 1 : 0;
+      for (int r = 0; r < kRowBlocks; ++r)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) cnt[r][v] += (point && d[r][t][v] > thr) ? 1 : 0;
     }
   }
   // lanes with the same l / 16 hold the same four vertices: sum over l % 16
 #pragma unroll
-  for (int v = 0; v < 4; ++v)
+  for (int r = 0; r < kRowBlocks; ++r)
 #pragma unroll
-    for (int off = 8; off > 0; off >>= 1) cnt[v] += __shfl_xor(cnt[v], off, 16);
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int off = 8; off > 0; off >>= 1) cnt[r][v] += __shfl_xor(cnt[r][v], off, 16);
   if ((lane & 15) == 0)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = blockIdx.x * 64 + wave * 16 + (lane >> 4) + 4 * v;
-      if (row < Nc) partial[(size_t)blockIdx.y * Nc + row] = cnt[v];
-    }
+    for (int r = 0; r < kRowBlocks; ++r)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = row0 + 16 * r + (lane >> 4) + 4 * v;
+        if (row < Nc) partial[(size_t)blockIdx.y * Nc + row] = cnt[r][v];
+      }
 }
 
 void launch_gpc_exceed(int Nc, int nc, int M, int pmax, const double* C, const int* idx,
                        const double* theta, int Ns, int chunk, int n_chunks, double thr,
                        int* partial, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-  const dim3 grid(ceil_div(Nc, 64), n_chunks);
+  const dim3 grid(ceil_div(Nc, kExceedRows), n_chunks);
   const int ncp = 4 * ((nc + 3) / 4);
   const size_t lds = sizeof(double) * ((size_t)ncp * kTilePts + (size_t)kTilePts * M * (pmax + 1)) +
                      sizeof(int) * (size_t)ncp * M;
