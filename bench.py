@@ -342,6 +342,31 @@ def main():
         res = qmc_vs_gpc(pb, 0, 1, wl.weights, (g0.nx, g0.ny, g0.nz), degree=4)
         out["e1_compare"] = dict(res["compare"], years=(args.warmup + args.steps) * wl.dt / synth.YEAR_S)
         log(f"qMC vs gPC: {out['e1_compare']}")
+    if wl.mlmc_levels:
+        # multilevel estimates after the last timed step on the coarsest grid: level 0
+        # alone, levels 0-1, all levels (the differences are the level corrections)
+        from paper_1906_01632_amd.uq import mlmc_weights
+        g0 = wl.groups[0]
+        common = (g0.nx, g0.ny, g0.nz)
+        n = wl.mlmc_levels
+        est = []
+        for L in range(1, len(n) + 1):
+            w = np.zeros(S)
+            part = mlmc_weights(n[:L])
+            w[:part.size] = part
+            if L < len(n):  # the partners of level L stay out
+                w[sum(n[:L]) + sum(n[1:L]):] = 0.0
+            est.append(pb.moments(common, weights=w))
+        ref = np.linalg.norm(est[0][0])
+        out["mlmc"] = {"levels": list(n), "grids": [[g.nx, g.ny, g.nz] for g in wl.groups],
+                       "correction_rel_l2": [float(np.linalg.norm(est[L][0] - est[L - 1][0]) / ref)
+                                             for L in range(1, len(n))],
+                       "mean_range": [float(est[-1][0].min()), float(est[-1][0].max())],
+                       "max_var": float(est[-1][1].max()),
+                       "sample_dof_share": [g.samples * g.n_vertices / sum(q.samples * q.n_vertices
+                                                                             for q in wl.groups)
+                                            for g in wl.groups]}
+        log(f"multilevel: {out['mlmc']}")
     if not args.no_cpu_baseline:
         log("oracle timing on the host ...")
         out["cpu_baseline"] = cpu_baseline(wl, phys)

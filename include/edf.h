@@ -179,8 +179,11 @@ edf_status edf_solve(edf_problem* pb, double dt, int32_t n_steps, edf_step_stats
 /* Weighted statistics of c over the samples (eqs. pdestat, numer_var; Section 3.2):
  * mean = sum w_i c_i, var = sum w_i (c_i - mean)^2, exceed = sum w_i [c_i > threshold].
  * Every group is injected to the common vertex set (cx, cy, cz), which must be nested
- * in every group's grid.  weights: host [S_total] or NULL for 1/S_total.  Samples whose
- * last step failed are left out and the weights of the others renormalised.
+ * in every group's grid.  weights: host [S_total] or NULL for 1/S_total; they are divided
+ * by their sum, which must be positive, and may be signed (a multilevel estimator gives
+ * the coarse partners of a level negative weights: var is then sum w c^2 - mean^2 and
+ * may dip below zero).  Samples whose last step failed are left out and the weights of
+ * the others renormalised.
  * mean, var, exceed: host arrays [cx*cy*cz].  Synchronises. */
 edf_status edf_moments(edf_problem* pb, int32_t cx, int32_t cy, int32_t cz, double threshold,
                        const double* weights, double* mean, double* var, double* exceed);

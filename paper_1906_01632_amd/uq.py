@@ -1,4 +1,5 @@
-"""Quasi-Monte Carlo against polynomial chaos statistics of one problem.
+"""Quasi-Monte Carlo against polynomial chaos statistics of one problem, and multilevel
+Monte Carlo statistics on nested grids.
 
 The box experiment with three random variables (Section 5, eq. poro-paral3RVS) runs
 the same porosity model twice: as 200 Halton qMC samples, whose mean, variance and
@@ -57,3 +58,33 @@ def qmc_vs_gpc(pb, qmc_group: int, gpc_group: int, gl_weights, common, degree: i
     }
     return {"qmc_mean": qm, "qmc_var": qv, "qmc_exceed": qe, "gpc_mean": gm, "gpc_var": gv,
             "gpc_exceed": ge, "compare": cmp}
+
+
+def mlmc_weights(n_per_level) -> np.ndarray:
+    """Sample weights of the multilevel estimator on nested grids (level 0 coarsest).
+
+    Layout of the problem: group l holds the n_l samples of level l followed by the
+    coarse partners (the same parameters) of the n_{l+1} samples of level l + 1.  The
+    estimator E[c_L] = E[c_0] + sum_l E[c_l - c_{l-1}] with sample means per level gives
+    weight +1/n_l to the level-l samples and -1/n_{l+1} to the partners; the weights sum
+    to 1.  Applied to c and c^2 alike, the weighted mean and the weighted spread
+    sum w (c - mean)^2 = sum w c^2 - mean^2 are the multilevel estimates of the mean and
+    the variance (the latter may come out slightly negative where the variance is small);
+    the weighted indicator sum is the multilevel estimate of the exceedance probability."""
+    n = [int(k) for k in n_per_level]
+    w = []
+    for l, k in enumerate(n):
+        w += [1.0 / k] * k
+        if l + 1 < len(n):
+            w += [-1.0 / n[l + 1]] * n[l + 1]
+    return np.array(w)
+
+
+def mlmc_moments(pb, n_per_level, common, threshold: float = 0.5):
+    """Multilevel mean, variance and exceedance probability [cz, cy, cx] on the common
+    grid (edf_moments with the weights of mlmc_weights).  Every sample must have taken its
+    last step: a failed one would break its level pair."""
+    w = mlmc_weights(n_per_level)
+    if w.size != pb.S:
+        raise ValueError(f"{w.size} weights for {pb.S} samples")
+    return pb.moments(common, threshold=threshold, weights=w)

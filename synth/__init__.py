@@ -72,6 +72,7 @@ class Workload:
     newton_rtol: float = 1e-10
     xi: np.ndarray = field(default=None, repr=False)  # [S_total, n_xi]
     weights: np.ndarray = field(default=None, repr=False)  # quadrature weights (gPC)
+    mlmc_levels: tuple = None       # samples per level of a multilevel workload
 
     @property
     def n_samples(self) -> int:
@@ -198,6 +199,15 @@ def workload(name: str, seed: int = 0) -> Workload:
         nodes, weights = gauss_legendre_tensor(5, 3)
         return Workload(name, [Group(65, 65, 17, 125, 5)], FIELD_PAPER3, 3,
                         newton_rtol=1e-8, xi=nodes, weights=weights)
+    if name == "mlmc3":                # multilevel MC on the nested 33^3/65^3/129^3 grids:
+        # group l holds the n_l samples of level l, then the coarse partners (same xi) of
+        # the n_{l+1} samples of level l + 1; every level draws its own shifted lattice
+        n = (256, 64, 16)
+        pts = [lattice_points(k, 4, seed + 1 + l) for l, k in enumerate(n)]
+        xi = np.concatenate([pts[0], pts[1], pts[1], pts[2], pts[2]])
+        return Workload(name, [Group(33, 33, 9, n[0] + n[1], 4), Group(65, 65, 17, n[1] + n[2], 5),
+                               Group(129, 129, 33, n[2], 6)], FIELD_LATTICE4, 100,
+                        newton_rtol=1e-8, xi=xi, mlmc_levels=n)
     if name in E1_GRIDS:               # the paper's box experiment with 3 parameters:
         # 200 Halton qMC samples (group 0) beside the 125 tensor Gauss-Legendre nodes of the
         # degree-4 surrogate (group 1) on one grid, 1500 steps of 0.005 years
@@ -211,7 +221,7 @@ def workload(name: str, seed: int = 0) -> Workload:
 
 
 WORKLOADS = ("elder33_f64", "elder129_f64", "qmc512_mixedres", "mixed257", "adjoint65", "gpc125",
-             "e1box33", "e1box65")
+             "e1box33", "e1box65", "mlmc3")
 
 
 # --------------------------------------------------------------------------

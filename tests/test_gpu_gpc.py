@@ -146,3 +146,38 @@ def test_qmc_against_gpc_statistics():
     assert c["mean_max_abs"] == np.abs(res["qmc_mean"] - res["gpc_mean"]).max()
     assert c["n_coef"] == len(J) and 0 <= c["mean_level_side_differs"] <= 1
     pb.destroy()
+
+
+def test_multilevel_moments_of_nested_groups():
+    """Multilevel estimates (signed weights through edf_moments) on a 9x9x3 / 17x17x5 /
+    33x33x9 hierarchy after two steps: equal to the level sums of differences of the
+    library's own states on the common 9x9x3 grid, written out here from the estimator's
+    definition (mean, mean of squares minus the squared mean, indicator)."""
+    from paper_1906_01632_amd.uq import mlmc_moments
+    phys = synth.physics(2)
+    n = (6, 3, 2)
+    xi = [synth.lattice_points(k, 4, 10 + l) for l, k in enumerate(n)]
+    groups = [(9, 9, 3, 2, n[0] + n[1]), (17, 17, 5, 3, n[1] + n[2]), (33, 33, 9, 4, n[2])]
+    pb = _problem(phys, groups)
+    pb.set_parameters(np.concatenate([xi[0], xi[1], xi[1], xi[2], xi[2]]))
+    for _ in range(2):
+        st = pb.step(DT)
+        assert all(s["status"] == 0 for s in st)
+    common = (9, 9, 3)
+    m, v, e = mlmc_moments(pb, n, common, threshold=0.5)
+    c = [stats.inject(pb.get_state(i)[..., 1], common) for i in range(pb.S)]
+    lvl0 = np.array(c[:n[0]])
+    partners1, fine1 = np.array(c[n[0]:n[0] + n[1]]), np.array(c[n[0] + n[1]:n[0] + 2 * n[1]])
+    partners2 = np.array(c[n[0] + 2 * n[1]:n[0] + 2 * n[1] + n[2]])
+    fine2 = np.array(c[n[0] + 2 * n[1] + n[2]:])
+    m1 = lvl0.mean(0) + (fine1 - partners1).mean(0) + (fine2 - partners2).mean(0)
+    m2 = (lvl0 ** 2).mean(0) + (fine1 ** 2 - partners1 ** 2).mean(0) + (fine2 ** 2 - partners2 ** 2).mean(0)
+    ind = lambda a: (a > 0.5).astype(float)
+    ex = ind(lvl0).mean(0) + (ind(fine1) - ind(partners1)).mean(0) + (ind(fine2) - ind(partners2)).mean(0)
+    assert np.abs(m - m1).max() < 1e-14
+    assert np.abs(v - (m2 - m1 ** 2)).max() < 1e-13
+    assert np.abs(e - ex).max() < 1e-14
+    # the partner states are the same parameters on the coarser grid: close to, not equal
+    # to, the fine ones
+    assert 0 < np.abs(fine1 - partners1).max() < 0.5
+    pb.destroy()
