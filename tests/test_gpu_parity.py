@@ -424,7 +424,15 @@ def test_invalid_arguments_are_rejected():
         pb.step(-1.0)
     with pytest.raises(EDFError):
         pb.moments((4, 9, 3))                     # not nested
+    with pytest.raises(EDFError):
+        pb.moments((9, 9, 3), weights=[-0.5])     # weights summing to a non-positive value
     pb.destroy()
+    with pytest.raises(EDFError):
+        _problem(phys, [(9, 9, 3, 2, 0)])         # no samples
+    with pytest.raises(EDFError):
+        _problem(phys, [(9, 9, 3, 0, 1)])         # no levels
+    with pytest.raises(EDFError):
+        _problem(phys, [(1, 9, 3, 1, 1)])         # a dimension of one vertex
 
 
 def test_failed_step_is_redone_as_equal_substeps():
