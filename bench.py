@@ -129,7 +129,8 @@ def run_gpc(args, wl, pb, prec, degree=4, n_points=10**6, threshold=0.5):
     nc = out["n_coef"]
     pm, em = float(np.mean(proj_ms)), float(np.mean(ex_ms))
     proj_bytes = 8.0 * Nc * (S + nc)        # every sample field read, every coefficient written
-    flops = 2.0 * nc * Nc * n_points        # one FMA per term, vertex and point
+    flops = 2.0 * nc * Nc * n_points        # one FMA per term, vertex and point (the basis
+                                            # tables' time is counted, their flops are not)
     gbs, tfs = proj_bytes / (pm * 1e-3) / 1e9, flops / (em * 1e-3) / 1e12
     res = {"metric": "gPC surrogate: vertex-samples/s of the exceedance estimate",
            "value": Nc * n_points / (em * 1e-3), "unit": "vertex-samples/s", "n_gpus": 1,

@@ -213,7 +213,9 @@ edf_status edf_gpc_project(edf_problem* pb, int32_t group, int32_t cx, int32_t c
  *   P(c > threshold) ~ #{s : sum_beta c_beta Psi_beta(theta_s) > threshold} / n_points
  * over the points theta (host [n_points][M] in [-1,1]^M; the caller draws them).  The
  * surrogate is evaluated in FP64.  prob: host [cz][cy][cx]; kernel_ms (or NULL): the
- * duration of the evaluation kernel.  EDF_ERR_STATE without a projection.  Synchronises. */
+ * duration of the evaluation on the device (the basis tables of the points, built about
+ * 2^20 points at a time, and the surrogate products and counts), from events around it.
+ * EDF_ERR_STATE without a projection.  Synchronises. */
 edf_status edf_gpc_exceed(edf_problem* pb, int32_t n_points, const double* theta, double threshold,
                           double* prob, double* kernel_ms);
 

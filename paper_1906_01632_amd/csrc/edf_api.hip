@@ -1447,18 +1447,24 @@ edf_status edf_gpc_exceed(edf_problem* pb, int32_t n_points, const double* theta
   const int M = pb->gpc_M, nc = pb->gpc_nc, Nc = pb->gpc_Nc;
   for (size_t e = 0; e < (size_t)n_points * M; ++e)
     if (!(std::fabs(theta[e]) <= 1.0)) return fail(pb, EDF_ERR_ARG, "points outside [-1,1]^M");
-  // point chunks per block: at least 2048 points, at most 2^26 partial counts in all
+  // point chunks per block: at least 2048 points, at most 2^26 partial counts in all;
+  // the basis table is built for batches of whole chunks, about 2^20 points at a time
   int chunk = 2048;
   while ((size_t)ceil_div(n_points, chunk) * Nc > (1u << 26)) chunk *= 2;
   const int n_chunks = ceil_div(n_points, chunk);
+  const int batch_chunks = std::max(1, (1 << 20) / chunk);
+  const int batch = std::min(n_chunks, batch_chunks) * chunk;  // a multiple of 64
+  const int ncp = 4 * ((nc + 3) / 4);
   hipStream_t st = pb->st;
   edf_status e;
   EDF_TRY(hipStreamSynchronize(st));
-  if ((e = grow(pb, &pb->gpc_pts, &pb->gpc_pcap, (size_t)n_points * M + Nc))) return e;
+  const size_t basis_off = ((size_t)n_points * M + Nc + 31) / 32 * 32;  // 256-byte aligned
+  if ((e = grow(pb, &pb->gpc_pts, &pb->gpc_pcap, basis_off + (size_t)ncp * batch))) return e;
   if ((e = grow(pb, &pb->gpc_ibuf, &pb->gpc_icap, (size_t)nc * M + (size_t)n_chunks * Nc)))
     return e;
   double* pts = pb->gpc_pts;
   double* dprob = pts + (size_t)n_points * M;
+  double* basis = pts + basis_off;
   int* idx = pb->gpc_ibuf;
   int* partial = idx + (size_t)nc * M;
   // the index table of the projection is written again: the buffer may have moved
@@ -1471,9 +1477,18 @@ edf_status edf_gpc_exceed(edf_problem* pb, int32_t n_points, const double* theta
   if (kernel_ms) {
     EDF_TRY(hipEventCreate(&e0));
     EDF_TRY(hipEventCreate(&e1));
+    EDF_TRY(hipEventRecord(e0, st));
   }
-  launch_gpc_exceed(Nc, nc, M, pb->gpc_deg, pb->gpc_buf, idx, pts, n_points, chunk, n_chunks,
-                    threshold, partial, st, e0, e1);
+  // the surrogate's evaluation (basis tables and products) is timed as a whole
+  for (int c0 = 0; c0 < n_chunks; c0 += batch_chunks) {
+    const int nch = std::min(batch_chunks, n_chunks - c0);
+    const int s0 = c0 * chunk;
+    const int n = std::min(batch, n_points - s0);
+    launch_gpc_basis(n, batch, nc, ncp, M, idx, pts + (size_t)s0 * M, basis, st);
+    launch_gpc_exceed(Nc, nc, pb->gpc_buf, basis, batch, n, chunk, c0, nch, threshold, partial,
+                      st, nullptr, nullptr);
+  }
+  if (kernel_ms) EDF_TRY(hipEventRecord(e1, st));
   launch_gpc_count(Nc, n_chunks, n_points, partial, dprob, st);
   EDF_CHECK_LAUNCH();
   EDF_TRY(hipMemcpyAsync(prob, dprob, Nc * sizeof(double), hipMemcpyDeviceToHost, st));

@@ -122,6 +122,29 @@ void launch_gpc_moments(int Nc, int nc, const double* C, const double* Q, double
                      mean, var);
 }
 
+// Basis table of a batch of surrogate points: B[q][s] = Psi_q(theta_s) for q < nc,
+// zero for the padding terms q < ncp and the padding points s < ldb (one thread per
+// point and term; the recursion is the one of k_gpc_weights)
+__global__ __launch_bounds__(kBlock) void k_gpc_basis(int n, int ldb, int nc, int M,
+                                                      const int* idx, const double* theta,
+                                                      double* B) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  if (s >= ldb) return;
+  double psi = 0.0;
+  if (q < nc && s < n) {
+    psi = 1.0;
+    for (int j = 0; j < M; ++j) psi *= legendre(idx[q * M + j], theta[(size_t)s * M + j]);
+  }
+  B[(size_t)q * ldb + s] = psi;
+}
+
+void launch_gpc_basis(int n, int ldb, int nc, int ncp, int M, const int* idx, const double* theta,
+                      double* B, hipStream_t st) {
+  hipLaunchKernelGGL(k_gpc_basis, dim3(ceil_div(ldb, kBlock), ncp), dim3(kBlock), 0, st, n, ldb,
+                     nc, M, idx, theta, B);
+}
+
 // Exceedance counts on the matrix cores.  The surrogate values of 16 vertices at 16
 // points are one 16x16 tile of the product [vertices x q] x [q x points], built by
 // v_mfma_f64_16x16x4f64 over q in steps of 4 (FP64 throughout).  Lane l supplies
@@ -129,11 +152,11 @@ void launch_gpc_moments(int Nc, int nc, const double* C, const double* Q, double
 // value) and receives D[l / 16 + 4 v][l % 16], v = 0..3.  A wave keeps the coefficients
 // of its kRowBlocks x 16 vertices in registers (one value per lane, row block and step of
 // 4 terms), a block of four waves walks its chunk of points in tiles of kTilePts: the
-// tile's basis values are formed in LDS ([q][point], point fastest), every wave runs
-// kTilePts / 16 x kRowBlocks independent 16 x 16 accumulations (each basis value read
-// from LDS feeds kRowBlocks products), compares the values with the threshold and counts
-// per lane; the counts of the 16 lanes that share a vertex are summed by shuffles at the
-// end.
+// tile's columns of the basis table are copied to LDS ([q][point], point fastest), every
+// wave runs kTilePts / 16 x kRowBlocks independent 16 x 16 accumulations (each basis
+// value read from LDS feeds kRowBlocks products), compares the values with the threshold
+// and counts per lane; the counts of the 16 lanes that share a vertex are summed by
+// shuffles at the end.
 constexpr int kTilePts = 64;
 constexpr int kRowBlocks = 2;
 constexpr int kExceedRows = 4 * 16 * kRowBlocks;  // vertices per workgroup
@@ -141,20 +164,13 @@ constexpr int kMaxKb = kGpcMaxCoef / 4;
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 template <int KB>  // at most KB steps of 4 terms (register array length)
-__global__ __launch_bounds__(kBlock) void k_gpc_exceed(int Nc, int nc, int M, int pmax,
-                                                       const double* C, const int* idx,
-                                                       const double* theta, int Ns, int chunk,
-                                                       double thr, int* partial) {
-  // dynamic LDS: basis [ncp][kTilePts], Legendre values [kTilePts][M][pmax + 1], indices
-  extern __shared__ double smem[];
+__global__ __launch_bounds__(kBlock) void k_gpc_exceed(int Nc, int nc, const double* C,
+                                                       const double* B, int ldb, int n, int chunk,
+                                                       int chunk0, double thr, int* partial) {
+  extern __shared__ double basis[];  // [ncp][kTilePts]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int kb_n = (nc + 3) / 4;  // steps of 4 terms
   const int ncp = 4 * kb_n;
-  const int P1 = pmax + 1;
-  double* basis = smem;
-  double* leg = basis + (size_t)ncp * kTilePts;
-  int* sidx = reinterpret_cast<int*>(leg + (size_t)kTilePts * M * P1);
-  for (int e = tid; e < ncp * M; e += blockDim.x) sidx[e] = e < nc * M ? idx[e] : 0;
   // this lane's A operand for every row block and step: coefficient (l / 16 + 4 kb) of
   // vertex l % 16 of the row block
   const int row0 = blockIdx.x * kExceedRows + wave * 16 * kRowBlocks;
@@ -169,34 +185,16 @@ __global__ __launch_bounds__(kBlock) void k_gpc_exceed(int Nc, int nc, int M, in
     }
   }
   const int s_begin = blockIdx.y * chunk;
-  const int s_end = min(Ns, s_begin + chunk);
+  const int s_end = min(n, s_begin + chunk);
   int cnt[kRowBlocks][4] = {};
   for (int s0 = s_begin; s0 < s_end; s0 += kTilePts) {
     const int nt = min(kTilePts, s_end - s0);
     __syncthreads();  // the previous tile's basis values are no longer read
-    for (int e = tid; e < nt * M; e += blockDim.x) {
-      const int sp = e / M, j = e % M;
-      const double x = theta[(size_t)(s0 + sp) * M + j];
-      double* L = leg + (size_t)(sp * M + j) * P1;
-      double u = 1.0, w = x;
-      L[0] = 1.0;
-      if (pmax >= 1) L[1] = x;
-      for (int k = 1; k < pmax; ++k) {
-        const double z = ((2 * k + 1) * x * w - k * u) / (k + 1);
-        u = w;
-        w = z;
-        L[k + 1] = z;
-      }
-    }
-    __syncthreads();
-    for (int e = tid; e < ncp * kTilePts; e += blockDim.x) {
-      const int q = e / kTilePts, sp = e % kTilePts;
-      double psi = 0.0;
-      if (q < nc && sp < nt) {
-        psi = 1.0;
-        for (int j = 0; j < M; ++j) psi *= leg[(size_t)(sp * M + j) * P1 + sidx[q * M + j]];
-      }
-      basis[q * kTilePts + sp] = psi;
+    // s0 is a multiple of kTilePts and s0 + kTilePts <= ldb: 16-byte copies in bounds
+    for (int e = tid; e < ncp * (kTilePts / 2); e += blockDim.x) {
+      const int q = e / (kTilePts / 2), sp = 2 * (e % (kTilePts / 2));
+      *reinterpret_cast<double2*>(basis + q * kTilePts + sp) =
+          *reinterpret_cast<const double2*>(B + (size_t)q * ldb + s0 + sp);
     }
     __syncthreads();
     constexpr int kCols = kTilePts / 16;  // independent 16-point accumulations
@@ -240,17 +238,16 @@ __global__ __launch_bounds__(kBlock) void k_gpc_exceed(int Nc, int nc, int M, in
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = row0 + 16 * r + (lane >> 4) + 4 * v;
-        if (row < Nc) partial[(size_t)blockIdx.y * Nc + row] = cnt[r][v];
+        if (row < Nc) partial[(size_t)(chunk0 + blockIdx.y) * Nc + row] = cnt[r][v];
       }
 }
 
-void launch_gpc_exceed(int Nc, int nc, int M, int pmax, const double* C, const int* idx,
-                       const double* theta, int Ns, int chunk, int n_chunks, double thr,
-                       int* partial, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+void launch_gpc_exceed(int Nc, int nc, const double* C, const double* B, int ldb, int n, int chunk,
+                       int chunk0, int n_chunks, double thr, int* partial, hipStream_t st,
+                       hipEvent_t ev0, hipEvent_t ev1) {
   const dim3 grid(ceil_div(Nc, kExceedRows), n_chunks);
   const int ncp = 4 * ((nc + 3) / 4);
-  const size_t lds = sizeof(double) * ((size_t)ncp * kTilePts + (size_t)kTilePts * M * (pmax + 1)) +
-                     sizeof(int) * (size_t)ncp * M;
+  const size_t lds = sizeof(double) * (size_t)ncp * kTilePts;
   const int kb_n = ncp / 4;
   auto kern = kb_n <= 2    ? k_gpc_exceed<2>
               : kb_n <= 4  ? k_gpc_exceed<4>
@@ -260,11 +257,11 @@ void launch_gpc_exceed(int Nc, int nc, int M, int pmax, const double* C, const i
               : kb_n <= 24 ? k_gpc_exceed<24>
                            : k_gpc_exceed<kMaxKb>;
   if (ev0)
-    hipExtLaunchKernelGGL(kern, grid, dim3(kBlock), lds, st, ev0, ev1, 0, Nc, nc, M, pmax, C, idx,
-                          theta, Ns, chunk, thr, partial);
+    hipExtLaunchKernelGGL(kern, grid, dim3(kBlock), lds, st, ev0, ev1, 0, Nc, nc, C, B, ldb, n,
+                          chunk, chunk0, thr, partial);
   else
-    hipLaunchKernelGGL(kern, grid, dim3(kBlock), lds, st, Nc, nc, M, pmax, C, idx, theta, Ns, chunk,
-                       thr, partial);
+    hipLaunchKernelGGL(kern, grid, dim3(kBlock), lds, st, Nc, nc, C, B, ldb, n, chunk, chunk0, thr,
+                       partial);
 }
 
 // prob[v] = sum over chunks of the counts / N_s (integer sums: exact, order-free)
