@@ -152,8 +152,8 @@ void launch_gpc_basis(int n, int ldb, int nc, int ncp, int M, const int* idx, co
 // value) and receives D[l / 16 + 4 v][l % 16], v = 0..3.  A wave keeps the coefficients
 // of its kRowBlocks x 16 vertices in registers (one value per lane, row block and step of
 // 4 terms), a block of four waves walks its chunk of points in tiles of kTilePts: the
-// tile's columns of the basis table are copied to LDS ([q][point], point fastest), every
-// wave runs kTilePts / 16 x kRowBlocks independent 16 x 16 accumulations (each basis
+// tile's columns of the basis table are copied to LDS ([q][point], point fastest; the
+// next tile's are fetched into registers during the products), every wave runs kTilePts / 16 x kRowBlocks independent 16 x 16 accumulations (each basis
 // value read from LDS feeds kRowBlocks products), compares the values with the threshold
 // and counts per lane; the counts of the 16 lanes that share a vertex are summed by
 // shuffles at the end.
@@ -162,6 +162,20 @@ constexpr int kRowBlocks = 2;
 constexpr int kExceedRows = 4 * 16 * kRowBlocks;  // vertices per workgroup
 constexpr int kMaxKb = kGpcMaxCoef / 4;
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+// this thread's share of the columns [s0, s0 + kTilePts) of the basis table, 16 bytes
+// per load (element e = q * kTilePts / 2 + pair)
+template <int P>
+__device__ __forceinline__ void load_basis_tile(v2d (&nxt)[P], const double* B, int ldb, int s0,
+                                                int ncp, int tid) {
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int e = tid + p * kBlock;
+    const int q = min(e / (kTilePts / 2), ncp - 1), sp = 2 * (e % (kTilePts / 2));
+    nxt[p] = *reinterpret_cast<const v2d*>(B + (size_t)q * ldb + s0 + sp);
+  }
+}
 
 template <int KB>  // at most KB steps of 4 terms (register array length)
 __global__ __launch_bounds__(kBlock) void k_gpc_exceed(int Nc, int nc, const double* C,
@@ -187,16 +201,37 @@ __global__ __launch_bounds__(kBlock) void k_gpc_exceed(int Nc, int nc, const dou
   const int s_begin = blockIdx.y * chunk;
   const int s_end = min(n, s_begin + chunk);
   int cnt[kRowBlocks][4] = {};
+  // up to 48 terms (KB <= 12) the next tile's columns of the basis table are loaded into
+  // registers while the current tile's products run, and stored to LDS after them; with
+  // more terms those registers would halve the waves per SIMD, and the tile is copied
+  // between two barriers.  A tile starts at a multiple of kTilePts below n <= ldb, so its
+  // 16-byte loads stay in the table.
+  constexpr bool kPrefetch = KB <= 12;
+  constexpr int kPref = kPrefetch ? (KB * 4 * (kTilePts / 2) + kBlock - 1) / kBlock : 1;
+  v2d nxt[kPref];
+  if (kPrefetch && s_begin < s_end) load_basis_tile<kPref>(nxt, B, ldb, s_begin, ncp, tid);
   for (int s0 = s_begin; s0 < s_end; s0 += kTilePts) {
     const int nt = min(kTilePts, s_end - s0);
     __syncthreads();  // the previous tile's basis values are no longer read
-    // s0 is a multiple of kTilePts and s0 + kTilePts <= ldb: 16-byte copies in bounds
-    for (int e = tid; e < ncp * (kTilePts / 2); e += blockDim.x) {
-      const int q = e / (kTilePts / 2), sp = 2 * (e % (kTilePts / 2));
-      *reinterpret_cast<double2*>(basis + q * kTilePts + sp) =
-          *reinterpret_cast<const double2*>(B + (size_t)q * ldb + s0 + sp);
+    if constexpr (kPrefetch) {
+#pragma unroll
+      for (int p = 0; p < kPref; ++p) {
+        const int e = tid + p * kBlock;
+        if (e < ncp * (kTilePts / 2)) {
+          const int q = e / (kTilePts / 2), sp = 2 * (e % (kTilePts / 2));
+          *reinterpret_cast<v2d*>(basis + q * kTilePts + sp) = nxt[p];
+        }
+      }
+    } else {
+      for (int e = tid; e < ncp * (kTilePts / 2); e += blockDim.x) {
+        const int q = e / (kTilePts / 2), sp = 2 * (e % (kTilePts / 2));
+        *reinterpret_cast<v2d*>(basis + q * kTilePts + sp) =
+            *reinterpret_cast<const v2d*>(B + (size_t)q * ldb + s0 + sp);
+      }
     }
     __syncthreads();
+    if (kPrefetch && s0 + kTilePts < s_end)
+      load_basis_tile<kPref>(nxt, B, ldb, s0 + kTilePts, ncp, tid);
     constexpr int kCols = kTilePts / 16;  // independent 16-point accumulations
     v4d d[kRowBlocks][kCols];
 #pragma unroll
