@@ -282,8 +282,8 @@ edf_status edf_profile(edf_problem* pb, int32_t enable, double* out);
  * coarse levels of every group can run in one launch with one workgroup per sample
  * (the fused bottom), which saves launches but walks the levels one after the other.
  * This call assembles the Newton matrices at the current states with time step dt,
- * times three V-cycles per group for every admissible first fused level and keeps
- * the fastest.  States are not changed.  Without it (or edf_set_tuning) a group of
+ * times three V-cycles per group for every admissible first fused level, twice over,
+ * and keeps the fastest (the better of its two timings counts for each).  States are not changed.  Without it (or edf_set_tuning) a group of
  * >= 64 samples fuses all levels of <= 4096 vertices, a smaller group only the
  * coarse solve.  EDF_ERR_STATE before edf_set_parameters, EDF_ERR_ARG for dt <= 0. */
 edf_status edf_autotune(edf_problem* pb, double dt);
