@@ -524,6 +524,8 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
     F.nu1 = nu1;
     F.nu2 = nu2;
     F.Minv = G.Minv;
+    // the levels' x, b and r (three vectors of 2 Np_k) in LDS when they all fit
+    size_t lds_elems = 0;
     for (int k = 0; k < F.n; ++k) {
       const Level& L = G.lv[l0 + k];
       F.g[k] = L.g;
@@ -532,13 +534,19 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
       F.D[k] = coarsest ? nullptr : (const T*)L.Dinv;
       F.r[k] = coarsest ? nullptr : (T*)L.r;
       bx(l0 + k, F.b[k], F.x[k]);
+      F.lds_off[k] = (int)lds_elems;
+      lds_elems += 6 * (size_t)L.g.off[8];
     }
+    const size_t lds_bytes = lds_elems * sizeof(T);
+    const bool in_lds = lds_bytes <= vcycle_bottom_lds_limit<T>();
+    if (!in_lds)
+      for (int k = 0; k < F.n; ++k) F.lds_off[k] = -1;
     if (G.fdesc_l0 != l0) {  // the description changes only with the first fused level
       (void)hipMemcpyAsync(G.fdesc, &F, sizeof(F), hipMemcpyHostToDevice, st);
       (void)hipStreamSynchronize(st);
       G.fdesc_l0 = l0;
     }
-    launch_vcycle_bottom<T>((const FusedLevels<T>*)G.fdesc, S, mask, st);
+    launch_vcycle_bottom<T>((const FusedLevels<T>*)G.fdesc, in_lds ? lds_bytes : 0, S, mask, st);
   }
   for (int l = l0 - 1; l >= 0; --l) {
     Level& L = G.lv[l];

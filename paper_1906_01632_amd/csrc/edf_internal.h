@@ -129,6 +129,10 @@ constexpr int kFuseMaxN = 4096;  // levels with at most this many vertices are f
 template <typename T>
 struct FusedLevels {
   int n, nc, nu1, nu2;
+  // lds_off[k] >= 0: level k's x, b and r are kept in LDS at element lds_off[k] (x, then
+  // b at + 2 Np, r at + 4 Np) instead of in x/b/r; only the first level's b is read from
+  // and its x written back to device memory.  All levels or none are in LDS.
+  int lds_off[kMaxFused];
   Geom g[kMaxFused];
   const T* A[kMaxFused];
   const T* D[kMaxFused];
@@ -137,8 +141,14 @@ struct FusedLevels {
   T* r[kMaxFused];
   const double* Minv;
 };
+// lds_bytes: dynamic LDS of the launch (0 when the levels stay in device memory)
 template <typename T>
-void launch_vcycle_bottom(const FusedLevels<T>* F_dev, int S, const int* mask, hipStream_t st);
+void launch_vcycle_bottom(const FusedLevels<T>* F_dev, size_t lds_bytes, int S, const int* mask,
+                          hipStream_t st);
+// LDS a workgroup of the fused bottom may take for the levels' vectors (0 when the device
+// does not allow more than the static part)
+template <typename T>
+size_t vcycle_bottom_lds_limit();
 
 // ---------------------------------------------------------------------------
 // Krylov / Newton kernels (krylov_kernels.hip), FP64 vectors of n = 2N per sample

@@ -669,18 +669,32 @@ constexpr int kFusedThreads = 1024;
 template <typename T>
 __global__ __launch_bounds__(kFusedThreads) void k_vcycle_bottom(const FusedLevels<T>* __restrict__ Fp,
                                                                  const int* mask) {
+  // the levels' x, b and r in LDS when F.lds_off says so (the dynamic LDS of the launch)
+  extern __shared__ double lds_vec[];
   const FusedLevels<T>& F = *Fp;
   const int s = blockIdx.x;
   if (mask && !mask[s]) return;
   const int tid = threadIdx.x, nt = blockDim.x;
+  const bool in_lds = F.lds_off[0] >= 0;
+  T* lds = reinterpret_cast<T*>(lds_vec);
   auto A = [&](int l) { return F.A[l] + (size_t)s * kPlanes * F.g[l].off[8]; };
   auto D = [&](int l) { return F.D[l] + (size_t)s * 4 * F.g[l].off[8]; };
-  auto X = [&](int l) { return F.x[l] + (size_t)s * 2 * F.g[l].off[8]; };
-  auto B = [&](int l) { return F.b[l] + (size_t)s * 2 * F.g[l].off[8]; };
-  auto Rv = [&](int l) { return F.r[l] + (size_t)s * 2 * F.g[l].off[8]; };
+  auto X = [&](int l) {
+    return in_lds ? lds + F.lds_off[l] : F.x[l] + (size_t)s * 2 * F.g[l].off[8];
+  };
+  auto B = [&](int l) {
+    return in_lds ? lds + F.lds_off[l] + 2 * F.g[l].off[8] : F.b[l] + (size_t)s * 2 * F.g[l].off[8];
+  };
+  auto Rv = [&](int l) {
+    return in_lds ? lds + F.lds_off[l] + 4 * F.g[l].off[8] : F.r[l] + (size_t)s * 2 * F.g[l].off[8];
+  };
   const int last = F.n - 1;
-  // x = 0 on the first fused level (the finer levels' restriction clears the others)
-  for (int e = tid; e < 2 * F.g[0].off[8]; e += nt) X(0)[e] = T(0);
+  // x = 0 on the first fused level (the finer levels' restriction clears the others);
+  // in LDS the first level's right-hand side is brought in from device memory
+  for (int e = tid; e < 2 * F.g[0].off[8]; e += nt) {
+    X(0)[e] = T(0);
+    if (in_lds) B(0)[e] = F.b[0][(size_t)s * 2 * F.g[0].off[8] + e];
+  }
   __syncthreads();
   for (int l = 0; l < last; ++l) {
     const Geom& g = F.g[l];
@@ -732,11 +746,36 @@ __global__ __launch_bounds__(kFusedThreads) void k_vcycle_bottom(const FusedLeve
         __syncthreads();
       }
   }
+  if (in_lds)  // the first level's correction goes back for the finer level's prolongation
+    for (int e = tid; e < 2 * F.g[0].off[8]; e += nt)
+      F.x[0][(size_t)s * 2 * F.g[0].off[8] + e] = X(0)[e];
+}
+
+// dynamic LDS the kernel may take: the device's per-workgroup limit less the static
+// part (the coarse right-hand side) and a margin; 0 if the device does not grant it
+constexpr size_t kBottomStaticLds = kMaxCoarse * sizeof(double);
+
+template <typename T>
+size_t vcycle_bottom_lds_limit() {
+  static size_t limit = [] {
+    int dev = 0, per_block = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+            hipSuccess ||
+        (size_t)per_block <= kBottomStaticLds + 1024)
+      return (size_t)0;
+    const size_t want = (size_t)per_block - kBottomStaticLds - 1024;
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vcycle_bottom<T>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)want);
+    return e == hipSuccess ? want : (size_t)0;
+  }();
+  return limit;
 }
 
 template <typename T>
-void launch_vcycle_bottom(const FusedLevels<T>* F, int S, const int* mask, hipStream_t st) {
-  hipLaunchKernelGGL(k_vcycle_bottom<T>, dim3(S), dim3(kFusedThreads), 0, st, F, mask);
+void launch_vcycle_bottom(const FusedLevels<T>* F, size_t lds_bytes, int S, const int* mask,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_vcycle_bottom<T>, dim3(S), dim3(kFusedThreads), lds_bytes, st, F, mask);
 }
 
 // explicit instantiations
@@ -754,7 +793,9 @@ void launch_vcycle_bottom(const FusedLevels<T>* F, int S, const int* mask, hipSt
                                     hipStream_t);                                                \
   template void launch_from_colour<T>(const Geom&, const T*, double*, int, const int*,           \
                                       hipStream_t);                                              \
-  template void launch_vcycle_bottom<T>(const FusedLevels<T>*, int, const int*, hipStream_t);
+  template void launch_vcycle_bottom<T>(const FusedLevels<T>*, size_t, int, const int*,         \
+                                        hipStream_t);                                            \
+  template size_t vcycle_bottom_lds_limit<T>();
 EDF_INST(double)
 EDF_INST(float)
 template void launch_fill<int>(int*, size_t, int, const int*, int, hipStream_t);
