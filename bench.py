@@ -41,16 +41,22 @@ def roctx_range():
 
 
 # the smoother kernel, its device helpers and the structures it takes: the measured HBM
-# traffic per launch is reported only while these are unchanged
+# traffic per launch is reported only while their code is unchanged
 KERNEL_SOURCES = ("mg_kernels.hip", "fv_common.h", "edf_internal.h")
 
 
 def kernel_digest():
+    """sha256 of the code of KERNEL_SOURCES: comments and blank space are left out, so
+    that a change of wording does not void a measurement while any change of code does."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1906_01632_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_1906_01632_amd", "csrc", name)) as f:
+            src = f.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)   # block comments
+        src = re.sub(r"//[^\n]*", " ", src)                # line comments
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()
 
 

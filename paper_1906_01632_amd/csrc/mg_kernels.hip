@@ -662,7 +662,9 @@ void launch_gauss_jordan(int n, double* M, int* piv, int* status, int S, const i
 // ---------------------------------------------------------------------------
 // bottom of the V-cycle in one launch: one workgroup per sample runs the smoothed
 // levels l0..n-2 of F and the dense coarse solve on level n-1, with workgroup
-// barriers between the sweeps (all levels are small: at most kFuseMaxN vertices)
+// barriers between the sweeps (all levels are small: at most kFuseMaxN vertices).
+// When the levels' vectors fit, they live in LDS for the whole launch, so that a sweep
+// waits only for its matrix reads.
 // ---------------------------------------------------------------------------
 constexpr int kFusedThreads = 1024;
 
