@@ -188,10 +188,11 @@ __device__ __forceinline__ void prolong_vertex(const Geom& gf, const Geom& gc, i
 // ---------------------------------------------------------------------------
 // one launch per colour sweep / transfer (large grids)
 // ---------------------------------------------------------------------------
-// Workgroups of one wave: the lanes are independent (no LDS, no barrier), and a launch
-// of few positions (a coarse level, a single sample) then spreads over more CUs than
-// with 256-lane workgroups (one 129^3 colour: 1072 workgroups instead of 268 on 256
-// CUs).  Same results; one 129^3 sample's V-cycle 0.90 -> 0.84 ms, batches unchanged.
+// The colour sweeps run in workgroups of one wave: the lanes are independent (no LDS,
+// no barrier), and a sweep over few positions (a coarse level, a single sample) then
+// spreads over more CUs than with 256-lane workgroups (one 129^3 colour: 1072
+// workgroups instead of 268 on 256 CUs).  The residual and the transfers, whose
+// neighbour reads lose locality in one-wave workgroups, keep 256 lanes.
 constexpr int kSweepBlock = 64;
 // Matrices of at most this many bytes (all samples of a level) are read with plain
 // loads: the small levels' matrices can stay in the last-level cache across sweeps
@@ -230,7 +231,7 @@ void launch_smooth(const Geom& g, int colour, const T* A, const T* Dinv, const T
 }
 
 template <typename T, bool NT>
-__global__ __launch_bounds__(kSweepBlock) void k_residual(Geom g, const T* A_all, const T* b_all,
+__global__ __launch_bounds__(kBlock) void k_residual(Geom g, const T* A_all, const T* b_all,
                                                      const T* x_all, T* r_all, const int* mask) {
   const int s = blockIdx.y;
   if (mask && !mask[s]) return;
@@ -244,13 +245,13 @@ __global__ __launch_bounds__(kSweepBlock) void k_residual(Geom g, const T* A_all
 template <typename T>
 void launch_residual(const Geom& g, const T* A, const T* b, const T* x, T* r, int S,
                      const int* mask, hipStream_t st) {
-  dim3 grid(ceil_div(g.off[8], kSweepBlock), S);
+  dim3 grid(ceil_div(g.off[8], kBlock), S);
   auto kern = stream_matrix<T>(g, S) ? k_residual<T, true> : k_residual<T, false>;
-  hipLaunchKernelGGL(kern, grid, dim3(kSweepBlock), 0, st, g, A, b, x, r, mask);
+  hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, st, g, A, b, x, r, mask);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kSweepBlock) void k_restrict(Geom gf, Geom gc, const T* rf_all, T* bc_all,
+__global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, const T* rf_all, T* bc_all,
                                                      T* xc_all, const int* mask) {
   const int s = blockIdx.y;
   if (mask && !mask[s]) return;
@@ -263,12 +264,12 @@ __global__ __launch_bounds__(kSweepBlock) void k_restrict(Geom gf, Geom gc, cons
 template <typename T>
 void launch_restrict(const Geom& gf, const Geom& gc, const T* rf, T* bc, T* xc, int S,
                      const int* mask, hipStream_t st) {
-  dim3 grid(ceil_div(gc.off[8], kSweepBlock), S);
-  hipLaunchKernelGGL(k_restrict<T>, grid, dim3(kSweepBlock), 0, st, gf, gc, rf, bc, xc, mask);
+  dim3 grid(ceil_div(gc.off[8], kBlock), S);
+  hipLaunchKernelGGL(k_restrict<T>, grid, dim3(kBlock), 0, st, gf, gc, rf, bc, xc, mask);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kSweepBlock) void k_prolong(Geom gf, Geom gc, const T* xc_all, T* xf_all,
+__global__ __launch_bounds__(kBlock) void k_prolong(Geom gf, Geom gc, const T* xc_all, T* xf_all,
                                                     const int* mask) {
   const int s = blockIdx.y;
   if (mask && !mask[s]) return;
@@ -281,8 +282,8 @@ __global__ __launch_bounds__(kSweepBlock) void k_prolong(Geom gf, Geom gc, const
 template <typename T>
 void launch_prolong(const Geom& gf, const Geom& gc, const T* xc, T* xf, int S, const int* mask,
                     hipStream_t st) {
-  dim3 grid(ceil_div(gf.off[8], kSweepBlock), S);
-  hipLaunchKernelGGL(k_prolong<T>, grid, dim3(kSweepBlock), 0, st, gf, gc, xc, xf, mask);
+  dim3 grid(ceil_div(gf.off[8], kBlock), S);
+  hipLaunchKernelGGL(k_prolong<T>, grid, dim3(kBlock), 0, st, gf, gc, xc, xf, mask);
 }
 
 // ---------------------------------------------------------------------------
@@ -388,7 +389,7 @@ void launch_smooth_f16(const Geom& g, int colour, const _Float16* A16, const flo
 }
 
 template <bool NT>
-__global__ __launch_bounds__(kSweepBlock) void k_residual_f16(Geom g, const _Float16* A_all,
+__global__ __launch_bounds__(kBlock) void k_residual_f16(Geom g, const _Float16* A_all,
                                                          const float* D_all, const float* bh_all,
                                                          const float* x_all, float* r_all,
                                                          const int* mask) {
@@ -437,10 +438,10 @@ __global__ __launch_bounds__(kSweepBlock) void k_residual_f16(Geom g, const _Flo
 
 void launch_residual_f16(const Geom& g, const _Float16* A16, const float* D32, const float* bh,
                          const float* x, float* r, int S, const int* mask, hipStream_t st) {
-  dim3 grid(ceil_div(g.off[8], kSweepBlock), S);
+  dim3 grid(ceil_div(g.off[8], kBlock), S);
   const bool stream = (double)S * kPlanes * g.off[8] * sizeof(_Float16) > kCachedMatrixBytes;
   auto kern = stream ? k_residual_f16<true> : k_residual_f16<false>;
-  hipLaunchKernelGGL(kern, grid, dim3(kSweepBlock), 0, st, g, A16, D32, bh, x, r, mask);
+  hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, st, g, A16, D32, bh, x, r, mask);
 }
 
 __global__ __launch_bounds__(kBlock) void k_to_colour_scaled(Geom g, const double* in_all,
