@@ -418,19 +418,51 @@ edf_status prof_flush(edf_problem* pb, Group& G) {
 // and 3 (nu1 + nu2) + 6 vector passes (b, x in and x out per smoothing sweep; b, x
 // in and r out for the residual; r into the restriction; x in and out for the
 // correction), plus the coarse right-hand side and solution and the dense inverse
+static_assert(zero_start_blocks(0) == 0 && zero_start_blocks(7) == 26, "zero-start stencil reads");
+static_assert(zero_start_blocks(0) + zero_start_blocks(1) + zero_start_blocks(2) +
+                      zero_start_blocks(3) + zero_start_blocks(4) + zero_start_blocks(5) +
+                      zero_start_blocks(6) + zero_start_blocks(7) ==
+                  8 * 13,
+              "each off-diagonal coupling is read from one of its two ends");
+
+// Algorithmic bytes per vertex of colour c of one smoother sweep.  A sweep reads the 27
+// stencil blocks, the block inverse, b and the vertex's own x and writes x (118 values);
+// the first forward sweep from x = 0 reads only the blocks of the colours already swept,
+// the block inverse and b, and writes x.  FP16 finest level: the 26 off-diagonal FP16
+// blocks, D^{-1} b, x in and out (FP32), from zero the swept colours' blocks, D^{-1} b
+// and x out.
+double sweep_bytes(int c, bool zero_start, bool fp16, size_t tsz) {
+  const int nb = zero_start_blocks(c);
+  if (fp16) return zero_start ? nb * 4 * 2 + 4 * 4 : 26 * 4 * 2 + 6 * 4;
+  return (zero_start ? 4.0 * nb + 8.0 : kPlanes + 10.0) * tsz;
+}
+
+// Algorithmic bytes of one V-cycle per sample: on every level above the coarsest, the
+// nu1 + nu2 sweeps (the first forward one from zero), the residual (stencil, b, x in,
+// r out; after a single sweep from zero only the blocks towards the colours swept later
+// and r out), r into the restriction and x in and out for the correction; then the dense
+// coarse inverse and its vectors.
 double vcycle_bytes(const Group& G, size_t tsz, int nu1, int nu2) {
-  const double sw = nu1 + nu2;
   double b = 0;
   for (int l = 0; l + 1 < G.L; ++l) {
-    if (l == 0 && G.lv[0].A16) {
-      // FP16 finest level: per sweep 26 FP16 blocks, D^{-1} b, x in and out; the
-      // residual reads the blocks, D (FP32), D^{-1} b and x and writes r; r into the
-      // restriction, x in and out for the correction (FP32 vectors)
-      b += (double)G.lv[0].g.N * (sw * (26 * 4 * 2 + 6 * 4) + (26 * 4 * 2 + 4 * 4 + 6 * 4) +
-                                  2 * 4 + 4 * 4);
-      continue;
+    const Geom& g = G.lv[l].g;
+    const bool h = l == 0 && G.lv[0].A16;
+    for (int c = 0; c < 8; ++c)
+      b += (double)g.cnt[c] * (nu1 * sweep_bytes(c, false, h, tsz) + nu2 * sweep_bytes(c, false, h, tsz));
+    if (nu1 > 0)
+      for (int c = 0; c < 8; ++c)
+        b += (double)g.cnt[c] * (sweep_bytes(c, true, h, tsz) - sweep_bytes(c, false, h, tsz));
+    if (h && nu1 == 1) {  // FP16 blocks towards the later colours, D (FP32), r out
+      for (int c = 0; c < 8; ++c)
+        b += (double)g.cnt[c] * ((26 - zero_start_blocks(c)) * 4 * 2 + 4 * 4 + 2 * 4 + 2 * 4 + 4 * 4);
+    } else if (h) {  // the residual reads the FP16 blocks, D (FP32), D^{-1} b and x and writes r
+      b += (double)g.N * ((26 * 4 * 2 + 4 * 4 + 6 * 4) + 2 * 4 + 4 * 4);
+    } else if (nu1 == 1) {
+      for (int c = 0; c < 8; ++c)
+        b += (double)g.cnt[c] * (4.0 * (26 - zero_start_blocks(c)) + 8.0) * tsz;
+    } else {
+      b += (double)g.N * (kPlanes + 12.0) * tsz;
     }
-    b += (double)G.lv[l].g.N * ((sw + 1.0) * kPlanes + sw * 4 + (3.0 * sw + 6.0) * 2) * tsz;
   }
   const double nc = G.n_coarse;
   return b + nc * nc * 8.0 + 2.0 * nc * tsz;
@@ -474,30 +506,28 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
   } else {
     launch_to_colour<T>(G.lv[0].g, in, b0, S, mask, st);
   }
-  // algorithmic bytes per vertex of the swept colour: 108 stencil + 4 block-inverse
-  // entries, b, own x read and written; FP16 finest level: the 26 off-diagonal blocks in
-  // FP16, D^{-1} b and x in FP32
-  auto smooth = [&](int l, const Level& L, int c, const T* b, T* x) {
+  // zs: the first forward sweep of the level, whose x is zero on entry
+  auto smooth = [&](int l, const Level& L, int c, const T* b, T* x, bool zs) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    const double per_vertex = (l == 0 && h0) ? 26.0 * 4 * 2 + 6.0 * 4 : 118.0 * sizeof(T);
+    const double per_vertex = sweep_bytes(c, zs, l == 0 && h0, sizeof(T));
     prof_pair(G, e0, e1, (double)L.g.cnt[c] * G.n_active * per_vertex, 0);
     if constexpr (std::is_same<T, float>::value) {
       if (l == 0 && h0) {
-        launch_smooth_f16(L.g, c, L.A16, (const float*)b, (float*)x, S, mask, st, e0, e1);
+        launch_smooth_f16(L.g, c, L.A16, (const float*)b, (float*)x, S, mask, st, e0, e1, zs);
         return;
       }
     }
-    launch_smooth<T>(L.g, c, stencil<T>(L), (const T*)L.Dinv, b, x, S, mask, st, e0, e1);
+    launch_smooth<T>(L.g, c, stencil<T>(L), (const T*)L.Dinv, b, x, S, mask, st, e0, e1, zs);
   };
   auto residual = [&](int l, const Level& L, const T* b, const T* x) {
     if constexpr (std::is_same<T, float>::value) {
       if (l == 0 && h0) {
         launch_residual_f16(L.g, L.A16, (const float*)L.Dinv, (const float*)b, (const float*)x,
-                            (float*)L.r, S, mask, st);
+                            (float*)L.r, S, mask, st, nu1 == 1);
         return;
       }
     }
-    launch_residual<T>(L.g, stencil<T>(L), b, x, (T*)L.r, S, mask, st);
+    launch_residual<T>(L.g, stencil<T>(L), b, x, (T*)L.r, S, mask, st, nu1 == 1);
   };
   auto bx = [&](int l, T*& b, T*& x) {
     b = l == 0 ? b0 : (T*)G.lv[l].b;
@@ -505,17 +535,21 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
   };
   // levels from l0 on run in one fused launch (one workgroup per sample)
   const int l0 = G.fuse_from >= 0 ? G.fuse_from : default_fuse_from(G);
-  if (l0 > 0) launch_fill<T>(x0, 2 * (size_t)G.lv[0].g.off[8], S, mask, T(0), st);
+  // every level starts from x = 0: the first forward sweep writes x at every vertex
+  // without reading it, so x needs clearing only without pre-smoothing
+  if (l0 > 0 && nu1 == 0) launch_fill<T>(x0, 2 * (size_t)G.lv[0].g.off[8], S, mask, T(0), st);
   for (int l = 0; l < l0; ++l) {
     Level& L = G.lv[l];
     T *b, *x;
     bx(l, b, x);
     for (int it = 0; it < nu1; ++it)
-      for (int c = 0; c < 8; ++c) smooth(l, L, c, b, x);
+      for (int c = 0; c < 8; ++c) smooth(l, L, c, b, x, it == 0);
     residual(l, L, b, x);
     T *bc, *xc;
     bx(l + 1, bc, xc);
-    launch_restrict<T>(L.g, G.lv[l + 1].g, (const T*)L.r, bc, xc, S, mask, st);
+    // x of the next level needs no clearing when its first sweep starts from zero or
+    // when it is the fused bottom's first level (cleared there)
+    launch_restrict<T>(L.g, G.lv[l + 1].g, (const T*)L.r, bc, nu1 > 0 ? nullptr : xc, S, mask, st);
   }
   {
     FusedLevels<T> F{};
@@ -555,7 +589,7 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
     bx(l + 1, bc, xc);
     launch_prolong<T>(L.g, G.lv[l + 1].g, xc, x, S, mask, st);
     for (int it = 0; it < nu2; ++it)
-      for (int c = 7; c >= 0; --c) smooth(l, L, c, b, x);
+      for (int c = 7; c >= 0; --c) smooth(l, L, c, b, x, false);
   }
   launch_from_colour<T>(G.lv[0].g, x0, out, S, mask, st);
 }

@@ -79,13 +79,41 @@ void launch_stencil_to_natural(const Geom& g, const double* A, double* out, hipS
 // ---------------------------------------------------------------------------
 // multigrid and stencil kernels (mg_kernels.hip), T = double or float
 // ---------------------------------------------------------------------------
+// Colour of the neighbour at offset (dx, dy, dz) of a vertex of colour col: an odd
+// offset along an axis flips that axis's parity bit.
+__host__ __device__ constexpr int nbr_colour(int col, int dx, int dy, int dz) {
+  return col ^ ((dx != 0) | ((dy != 0) << 1) | ((dz != 0) << 2));
+}
+
+// Whether the first forward sweep from x = 0 needs the neighbour of colour col at offset
+// (dx, dy, dz): only the colours already swept (below col) hold non-zero values; the
+// vertex itself and the colours above col are still zero and contribute nothing.
+__host__ __device__ constexpr bool zero_start_reads(int col, int dx, int dy, int dz) {
+  return nbr_colour(col, dx, dy, dz) < col;
+}
+
+// Number of 2x2 stencil blocks that sweep reads per vertex of colour col (0 for colour
+// 0, all 26 off-diagonal blocks for colour 7, 13 on average).
+__host__ __device__ constexpr int zero_start_blocks(int col) {
+  int n = 0;
+  for (int o = 0; o < 27; ++o)
+    if (zero_start_reads(col, o % 3 - 1, (o / 3) % 3 - 1, o / 9 - 1)) ++n;
+  return n;
+}
+
+// one block Gauss-Seidel sweep of one colour; zero_start: the first forward sweep of a
+// level whose x is zero on entry (reads only the colours already swept, writes x)
 template <typename T>
 void launch_smooth(const Geom& g, int colour, const T* A, const T* Dinv, const T* b, T* x, int S,
                    const int* mask, hipStream_t st, hipEvent_t ev0 = nullptr,
-                   hipEvent_t ev1 = nullptr);
+                   hipEvent_t ev1 = nullptr, bool zero_start = false);
+// r = b - A x, zero in Dirichlet rows; zero_sweep: x is the result of a single forward
+// sweep from x = 0, whose residual needs only the blocks towards the colours not yet swept
+// when each vertex was updated (b is not read)
 template <typename T>
 void launch_residual(const Geom& g, const T* A, const T* b, const T* x, T* r, int S,
-                     const int* mask, hipStream_t st);
+                     const int* mask, hipStream_t st, bool zero_sweep = false);
+// bc = R rf (full weighting, coarse row scaling); xc, when not null, cleared
 template <typename T>
 void launch_restrict(const Geom& gf, const Geom& gc, const T* rf, T* bc, T* xc, int S,
                      const int* mask, hipStream_t st);
@@ -100,10 +128,12 @@ void launch_scale_f16(const Geom& g, const float* A32, _Float16* A16, float* D32
                       const int* mask, hipStream_t st);
 // block Gauss-Seidel with A16: x_v = bh_v - sum_{o != diag} A16_vo x_{v+o}, bh = D^{-1} b
 void launch_smooth_f16(const Geom& g, int colour, const _Float16* A16, const float* bh, float* x,
-                       int S, const int* mask, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
+                       int S, const int* mask, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1,
+                       bool zero_start = false);
 // r = b - A x = D (bh - A16 x), zero in Dirichlet rows
 void launch_residual_f16(const Geom& g, const _Float16* A16, const float* D32, const float* bh,
-                         const float* x, float* r, int S, const int* mask, hipStream_t st);
+                         const float* x, float* r, int S, const int* mask, hipStream_t st,
+                         bool zero_sweep = false);
 // entry: bh = D^{-1} b, FP64 natural [N][2] -> FP32 colour-major [Np][2]
 void launch_to_colour_scaled(const Geom& g, const double* in, const float* D32, float* out, int S,
                              const int* mask, hipStream_t st);

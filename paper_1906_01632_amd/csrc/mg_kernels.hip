@@ -35,8 +35,11 @@ struct V2<float> {
 // kernel that runs the bottom of the V-cycle in one workgroup per sample.
 // ---------------------------------------------------------------------------
 
-// block Gauss-Seidel update of vertex q of colour col: x_v += D_v^{-1} (b - A x)_v
-template <typename T, bool NT>
+// block Gauss-Seidel update of vertex q of colour col: x_v += D_v^{-1} (b - A x)_v.
+// ZC >= 0: the first forward sweep of a V-cycle level, whose x is still zero, for
+// colour col = ZC: x_v = D_v^{-1} (b - A x)_v with the zero terms left out, so it reads
+// neither the vertex's own x nor the stencil blocks of the colours not yet swept.
+template <typename T, bool NT, int ZC = -1>
 __device__ __forceinline__ void smooth_vertex(const Geom& g, int col, int q, const T* A_s,
                                               const T* D_s, const T* b_s, T* x_s) {
   using T2 = typename V2<T>::type;
@@ -54,6 +57,7 @@ __device__ __forceinline__ void smooth_vertex(const Geom& g, int col, int q, con
     for (int dy = -1; dy <= 1; ++dy) {
 #pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
+        if (ZC >= 0 && !zero_start_reads(ZC, dx, dy, dz)) continue;
         const T2 xv = load_nbr(x, g, nm, dx, dy, dz);
         const Block2<T> a = load_block<NT>(A, nb_index(dx, dy, dz) * 4);
         r0 -= a.a00 * xv.x + a.a01 * xv.y;
@@ -62,9 +66,15 @@ __device__ __forceinline__ void smooth_vertex(const Geom& g, int col, int q, con
     }
   }
   const Block2<T> d = load_block<NT>(D_s + sidx<T>(t, 0, 4), 0);
-  T2 xv = x[t];
-  xv.x += d.a00 * r0 + d.a01 * r1;
-  xv.y += d.a10 * r0 + d.a11 * r1;
+  T2 xv;
+  if (ZC >= 0) {
+    xv.x = d.a00 * r0 + d.a01 * r1;
+    xv.y = d.a10 * r0 + d.a11 * r1;
+  } else {
+    xv = x[t];
+    xv.x += d.a00 * r0 + d.a01 * r1;
+    xv.y += d.a10 * r0 + d.a11 * r1;
+  }
   x[t] = xv;
 }
 
@@ -113,6 +123,68 @@ __device__ __forceinline__ void residual_vertex(const Geom& g, int t, const T* A
   reinterpret_cast<T2*>(r_s)[t] = out;
 }
 
+// Residual after a single forward sweep from x = 0, at position t of colour C < 7
+// (vertex i, j, k).  That sweep left D_v x_v + (sum over the neighbours of the colours
+// below C of A_vo x_{v+o}) = b_v, so r_v = -(sum over the neighbours of the colours above
+// C of A_vo x_{v+o}): only those stencil blocks are read, and neither b nor x_v.
+// Dirichlet rows are zero as in residual_vertex.
+template <typename T, bool NT, int C>
+__device__ __forceinline__ void residual_upper_vertex(const Geom& g, int t, int i, int j, int k,
+                                                      const T* A_s, const T* x_s, T* r_s) {
+  using T2 = typename V2<T>::type;
+  const NbrMap nm = nbr_map(g, C, i, j, k);
+  const T* A = A_s + sidx<T>(t, 0, kPlanes);
+  const T2* x = reinterpret_cast<const T2*>(x_s);
+  T a0 = 0, a1 = 0;
+  // one z-plane of neighbours at a time keeps the register count low; the planes above
+  // and below share their pattern of blocks
+  auto plane = [&](int dz, auto mz) {
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        if (nbr_colour(C, dx, dy, decltype(mz)::value) <= C) continue;
+        const T2 xv = load_nbr(x, g, nm, dx, dy, dz);
+        const Block2<T> a = load_block<NT>(A, nb_index(dx, dy, dz) * 4);
+        a0 += a.a00 * xv.x + a.a01 * xv.y;
+        a1 += a.a10 * xv.x + a.a11 * xv.y;
+      }
+    }
+  };
+#pragma unroll 1
+  for (int dz = -1; dz <= 1; dz += 2) plane(dz, std::integral_constant<int, 1>());
+  plane(0, std::integral_constant<int, 0>());
+  double cD;
+  T2 out;
+  out.x = is_pin(g, i, j, k) ? T(0) : -a0;
+  out.y = is_cdir(g, i, j, k, cD) ? T(0) : -a1;
+  reinterpret_cast<T2*>(r_s)[t] = out;
+}
+
+// residual_vertex after a single forward sweep from x = 0 (same result up to rounding)
+template <typename T, bool NT>
+__device__ __forceinline__ void residual_after_zero_sweep(const Geom& g, int t, const T* A_s,
+                                                          const T* x_s, T* r_s) {
+  using T2 = typename V2<T>::type;
+  int col, i, j, k;
+  if (!colour_decode_wave(g, t, col, i, j, k)) return;
+  switch (col) {
+    case 0: residual_upper_vertex<T, NT, 0>(g, t, i, j, k, A_s, x_s, r_s); break;
+    case 1: residual_upper_vertex<T, NT, 1>(g, t, i, j, k, A_s, x_s, r_s); break;
+    case 2: residual_upper_vertex<T, NT, 2>(g, t, i, j, k, A_s, x_s, r_s); break;
+    case 3: residual_upper_vertex<T, NT, 3>(g, t, i, j, k, A_s, x_s, r_s); break;
+    case 4: residual_upper_vertex<T, NT, 4>(g, t, i, j, k, A_s, x_s, r_s); break;
+    case 5: residual_upper_vertex<T, NT, 5>(g, t, i, j, k, A_s, x_s, r_s); break;
+    case 6: residual_upper_vertex<T, NT, 6>(g, t, i, j, k, A_s, x_s, r_s); break;
+    default: {  // colour 7, the last swept: zero residual
+      T2 z;
+      z.x = 0;
+      z.y = 0;
+      reinterpret_cast<T2*>(r_s)[t] = z;
+    }
+  }
+}
+
 // restriction b_c = (1/8) P^T r_f of the scaled residual at coarse position t (the
 // 1/8 converts the fine row scaling to the coarse one: rows are scaled by
 // 1/(hx hy hz)); also clears x_c
@@ -148,10 +220,12 @@ __device__ __forceinline__ void restrict_vertex(const Geom& gf, const Geom& gc, 
   out.x = is_pin(gc, I, J, K) ? T(0) : T(0.125) * a0;
   out.y = is_cdir(gc, I, J, K, cD) ? T(0) : T(0.125) * a1;
   reinterpret_cast<T2*>(bc_s)[t] = out;
-  T2 z;
-  z.x = 0;
-  z.y = 0;
-  reinterpret_cast<T2*>(xc_s)[t] = z;
+  if (xc_s) {  // the coarse correction starts from zero
+    T2 z;
+    z.x = 0;
+    z.y = 0;
+    reinterpret_cast<T2*>(xc_s)[t] = z;
+  }
 }
 
 // prolongation and correction x_f += P x_c (trilinear) at fine position t, none in
@@ -204,7 +278,8 @@ bool stream_matrix(const Geom& g, int S) {
   return (double)S * kPlanes * g.off[8] * sizeof(T) > kCachedMatrixBytes;
 }
 
-template <typename T, bool NT>
+// ZC: -1 for a sweep of any colour col, else the zero-start sweep of colour col = ZC
+template <typename T, bool NT, int ZC>
 __global__ __launch_bounds__(kSweepBlock) void k_smooth(Geom g, int col, const T* A_all, const T* Dinv_all,
                                                    const T* b_all, T* x_all, const int* mask) {
   const int s = blockIdx.y;
@@ -212,17 +287,37 @@ __global__ __launch_bounds__(kSweepBlock) void k_smooth(Geom g, int col, const T
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= g.cnt[col]) return;
   const size_t Np = g.off[8];
-  smooth_vertex<T, NT>(g, col, q, A_all + (size_t)s * kPlanes * Np, Dinv_all + (size_t)s * 4 * Np,
-                       b_all + (size_t)s * 2 * Np, x_all + (size_t)s * 2 * Np);
+  smooth_vertex<T, NT, ZC>(g, col, q, A_all + (size_t)s * kPlanes * Np,
+                           Dinv_all + (size_t)s * 4 * Np, b_all + (size_t)s * 2 * Np,
+                           x_all + (size_t)s * 2 * Np);
+}
+
+template <typename T, bool NT>
+auto smooth_kernel(int colour, bool zero_start) {
+  if (zero_start) {
+    switch (colour) {
+      case 0: return k_smooth<T, NT, 0>;
+      case 1: return k_smooth<T, NT, 1>;
+      case 2: return k_smooth<T, NT, 2>;
+      case 3: return k_smooth<T, NT, 3>;
+      case 4: return k_smooth<T, NT, 4>;
+      case 5: return k_smooth<T, NT, 5>;
+      case 6: return k_smooth<T, NT, 6>;
+      default: return k_smooth<T, NT, 7>;
+    }
+  }
+  return k_smooth<T, NT, -1>;
 }
 
 template <typename T>
 void launch_smooth(const Geom& g, int colour, const T* A, const T* Dinv, const T* b, T* x, int S,
-                   const int* mask, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+                   const int* mask, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1,
+                   bool zero_start) {
   const int n = g.cnt[colour];
   if (n <= 0) return;
   dim3 grid(ceil_div(n, kSweepBlock), S);
-  auto kern = stream_matrix<T>(g, S) ? k_smooth<T, true> : k_smooth<T, false>;
+  auto kern = stream_matrix<T>(g, S) ? smooth_kernel<T, true>(colour, zero_start)
+                                     : smooth_kernel<T, false>(colour, zero_start);
   if (ev0)  // timed launch: events recorded around this kernel only
     hipExtLaunchKernelGGL(kern, grid, dim3(kSweepBlock), 0, st, ev0, ev1, 0, g, colour, A, Dinv, b, x,
                           mask);
@@ -230,7 +325,8 @@ void launch_smooth(const Geom& g, int colour, const T* A, const T* Dinv, const T
     hipLaunchKernelGGL(kern, grid, dim3(kSweepBlock), 0, st, g, colour, A, Dinv, b, x, mask);
 }
 
-template <typename T, bool NT>
+// ZS: the level had a single pre-smoothing sweep, from x = 0
+template <typename T, bool NT, bool ZS>
 __global__ __launch_bounds__(kBlock) void k_residual(Geom g, const T* A_all, const T* b_all,
                                                      const T* x_all, T* r_all, const int* mask) {
   const int s = blockIdx.y;
@@ -238,15 +334,21 @@ __global__ __launch_bounds__(kBlock) void k_residual(Geom g, const T* A_all, con
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= g.off[8]) return;
   const size_t Np = g.off[8];
-  residual_vertex<T, NT>(g, t, A_all + (size_t)s * kPlanes * Np, b_all + (size_t)s * 2 * Np,
-                         x_all + (size_t)s * 2 * Np, r_all + (size_t)s * 2 * Np);
+  if (ZS)
+    residual_after_zero_sweep<T, NT>(g, t, A_all + (size_t)s * kPlanes * Np,
+                                     x_all + (size_t)s * 2 * Np, r_all + (size_t)s * 2 * Np);
+  else
+    residual_vertex<T, NT>(g, t, A_all + (size_t)s * kPlanes * Np, b_all + (size_t)s * 2 * Np,
+                           x_all + (size_t)s * 2 * Np, r_all + (size_t)s * 2 * Np);
 }
 
 template <typename T>
 void launch_residual(const Geom& g, const T* A, const T* b, const T* x, T* r, int S,
-                     const int* mask, hipStream_t st) {
+                     const int* mask, hipStream_t st, bool zero_sweep) {
   dim3 grid(ceil_div(g.off[8], kBlock), S);
-  auto kern = stream_matrix<T>(g, S) ? k_residual<T, true> : k_residual<T, false>;
+  const bool nt = stream_matrix<T>(g, S);
+  auto kern = zero_sweep ? (nt ? k_residual<T, true, true> : k_residual<T, false, true>)
+                         : (nt ? k_residual<T, true, false> : k_residual<T, false, false>);
   hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, st, g, A, b, x, r, mask);
 }
 
@@ -339,7 +441,8 @@ void launch_scale_f16(const Geom& g, const float* A32, _Float16* A16, float* D32
   hipLaunchKernelGGL(k_scale_f16, grid, dim3(kBlock), 0, st, g, A32, A16, D32, mask);
 }
 
-template <bool NT>
+// ZC as in k_smooth: -1, or the zero-start sweep of colour col = ZC
+template <bool NT, int ZC>
 __global__ __launch_bounds__(kSweepBlock) void k_smooth_f16(Geom g, int col, const _Float16* A_all,
                                                        const float* bh_all, float* x_all,
                                                        const int* mask) {
@@ -364,6 +467,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_smooth_f16(Geom g, int col, con
       for (int dx = -1; dx <= 1; ++dx) {
         const int o = nb_index(dx, dy, dz);
         if (o == kDiag) continue;  // the unit diagonal block
+        if (ZC >= 0 && !zero_start_reads(ZC, dx, dy, dz)) continue;
         const float2 xv = load_nbr(x, g, nm, dx, dy, dz);
         const Block2<float> a = load_block<NT>(A, o * 4);
         r0 -= a.a00 * xv.x + a.a01 * xv.y;
@@ -374,13 +478,32 @@ __global__ __launch_bounds__(kSweepBlock) void k_smooth_f16(Geom g, int col, con
   x[t] = make_float2(r0, r1);
 }
 
+template <bool NT>
+auto smooth_f16_kernel(int colour, bool zero_start) {
+  if (zero_start) {
+    switch (colour) {
+      case 0: return k_smooth_f16<NT, 0>;
+      case 1: return k_smooth_f16<NT, 1>;
+      case 2: return k_smooth_f16<NT, 2>;
+      case 3: return k_smooth_f16<NT, 3>;
+      case 4: return k_smooth_f16<NT, 4>;
+      case 5: return k_smooth_f16<NT, 5>;
+      case 6: return k_smooth_f16<NT, 6>;
+      default: return k_smooth_f16<NT, 7>;
+    }
+  }
+  return k_smooth_f16<NT, -1>;
+}
+
 void launch_smooth_f16(const Geom& g, int colour, const _Float16* A16, const float* bh, float* x,
-                       int S, const int* mask, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+                       int S, const int* mask, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1,
+                       bool zero_start) {
   const int n = g.cnt[colour];
   if (n <= 0) return;
   dim3 grid(ceil_div(n, kSweepBlock), S);
   const bool stream = (double)S * kPlanes * g.off[8] * sizeof(_Float16) > kCachedMatrixBytes;
-  auto kern = stream ? k_smooth_f16<true> : k_smooth_f16<false>;
+  auto kern = stream ? smooth_f16_kernel<true>(colour, zero_start)
+                     : smooth_f16_kernel<false>(colour, zero_start);
   if (ev0)
     hipExtLaunchKernelGGL(kern, grid, dim3(kSweepBlock), 0, st, ev0, ev1, 0, g, colour, A16, bh, x,
                           mask);
@@ -388,7 +511,44 @@ void launch_smooth_f16(const Geom& g, int colour, const _Float16* A16, const flo
     hipLaunchKernelGGL(kern, grid, dim3(kSweepBlock), 0, st, g, colour, A16, bh, x, mask);
 }
 
-template <bool NT>
+// r = D (bh - A16 x) after a single forward sweep from x = 0 at position t of colour
+// C < 7: that sweep left x_v = bh_v - (sum over the colours below C of A16_vo x_{v+o}), so
+// r_v = -D_v (sum over the colours above C of A16_vo x_{v+o})
+template <bool NT, int C>
+__device__ __forceinline__ void residual_f16_upper_vertex(const Geom& g, int t, int i, int j,
+                                                          int k, const _Float16* A_s,
+                                                          const float* D_s, const float* x_s,
+                                                          float* r_s) {
+  const NbrMap nm = nbr_map(g, C, i, j, k);
+  const _Float16* A = A_s + sidx<_Float16>(t, 0, kPlanes);
+  const float2* x = reinterpret_cast<const float2*>(x_s);
+  float a0 = 0.f, a1 = 0.f;
+  auto plane = [&](int dz, auto mz) {
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        if (nbr_colour(C, dx, dy, decltype(mz)::value) <= C) continue;
+        const float2 xv = load_nbr(x, g, nm, dx, dy, dz);
+        const Block2<float> a = load_block<NT>(A, nb_index(dx, dy, dz) * 4);
+        a0 += a.a00 * xv.x + a.a01 * xv.y;
+        a1 += a.a10 * xv.x + a.a11 * xv.y;
+      }
+    }
+  };
+#pragma unroll 1
+  for (int dz = -1; dz <= 1; dz += 2) plane(dz, std::integral_constant<int, 1>());
+  plane(0, std::integral_constant<int, 0>());
+  const Block2<float> d = load_block<NT>(D_s + sidx<float>(t, 0, 4), 0);
+  double cD;
+  float2 out;
+  out.x = is_pin(g, i, j, k) ? 0.f : -(d.a00 * a0 + d.a01 * a1);
+  out.y = is_cdir(g, i, j, k, cD) ? 0.f : -(d.a10 * a0 + d.a11 * a1);
+  reinterpret_cast<float2*>(r_s)[t] = out;
+}
+
+// ZS: the level had a single pre-smoothing sweep, from x = 0
+template <bool NT, bool ZS>
 __global__ __launch_bounds__(kBlock) void k_residual_f16(Geom g, const _Float16* A_all,
                                                          const float* D_all, const float* bh_all,
                                                          const float* x_all, float* r_all,
@@ -404,6 +564,22 @@ __global__ __launch_bounds__(kBlock) void k_residual_f16(Geom g, const _Float16*
   }
   int col, i, j, k;
   if (!colour_decode_wave(g, t, col, i, j, k)) return;
+  if (ZS) {
+    const _Float16* A = A_all + (size_t)s * kPlanes * Np;
+    const float* D = D_all + (size_t)s * 4 * Np;
+    const float* x = x_all + (size_t)s * 2 * Np;
+    float* r = r_all + (size_t)s * 2 * Np;
+    switch (col) {
+      case 0: residual_f16_upper_vertex<NT, 0>(g, t, i, j, k, A, D, x, r); break;
+      case 1: residual_f16_upper_vertex<NT, 1>(g, t, i, j, k, A, D, x, r); break;
+      case 2: residual_f16_upper_vertex<NT, 2>(g, t, i, j, k, A, D, x, r); break;
+      case 3: residual_f16_upper_vertex<NT, 3>(g, t, i, j, k, A, D, x, r); break;
+      case 4: residual_f16_upper_vertex<NT, 4>(g, t, i, j, k, A, D, x, r); break;
+      case 5: residual_f16_upper_vertex<NT, 5>(g, t, i, j, k, A, D, x, r); break;
+      default: residual_f16_upper_vertex<NT, 6>(g, t, i, j, k, A, D, x, r); break;
+    }
+    return;
+  }
   const NbrMap nm = nbr_map(g, col, i, j, k);
   const _Float16* A = A_all + (size_t)s * kPlanes * Np + sidx<_Float16>(t, 0, kPlanes);
   const float2* x = reinterpret_cast<const float2*>(x_all + (size_t)s * 2 * Np);
@@ -437,10 +613,12 @@ __global__ __launch_bounds__(kBlock) void k_residual_f16(Geom g, const _Float16*
 }
 
 void launch_residual_f16(const Geom& g, const _Float16* A16, const float* D32, const float* bh,
-                         const float* x, float* r, int S, const int* mask, hipStream_t st) {
+                         const float* x, float* r, int S, const int* mask, hipStream_t st,
+                         bool zero_sweep) {
   dim3 grid(ceil_div(g.off[8], kBlock), S);
   const bool stream = (double)S * kPlanes * g.off[8] * sizeof(_Float16) > kCachedMatrixBytes;
-  auto kern = stream ? k_residual_f16<true> : k_residual_f16<false>;
+  auto kern = zero_sweep ? (stream ? k_residual_f16<true, true> : k_residual_f16<false, true>)
+                         : (stream ? k_residual_f16<true, false> : k_residual_f16<false, false>);
   hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, st, g, A16, D32, bh, x, r, mask);
 }
 
@@ -789,9 +967,9 @@ void launch_vcycle_bottom(const FusedLevels<T>* F, size_t lds_bytes, int S, cons
 // explicit instantiations
 #define EDF_INST(T)                                                                              \
   template void launch_smooth<T>(const Geom&, int, const T*, const T*, const T*, T*, int,        \
-                                 const int*, hipStream_t, hipEvent_t, hipEvent_t);               \
+                                 const int*, hipStream_t, hipEvent_t, hipEvent_t, bool);         \
   template void launch_residual<T>(const Geom&, const T*, const T*, const T*, T*, int,           \
-                                   const int*, hipStream_t);                                     \
+                                   const int*, hipStream_t, bool);                               \
   template void launch_restrict<T>(const Geom&, const Geom&, const T*, T*, T*, int, const int*,  \
                                    hipStream_t);                                                 \
   template void launch_prolong<T>(const Geom&, const Geom&, const T*, T*, int, const int*,       \

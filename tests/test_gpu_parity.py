@@ -351,10 +351,30 @@ def test_concurrent_groups_give_the_serial_result():
         assert np.array_equal(out[1][0][s], out[0][0][s]), s
 
 
+def _zero_start_blocks(c):
+    """Stencil blocks of vertex colour c that a forward sweep from x = 0 needs: those of
+    the neighbours whose colour (c with the parity bit of each odd offset flipped) was
+    swept before c."""
+    n = 0
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                m = (dx != 0) | ((dy != 0) << 1) | ((dz != 0) << 2)
+                n += (c ^ m) < c
+    return n
+
+
+def _colour_counts(nx, ny, nz):
+    """Vertices of each colour (i % 2) + 2 (j % 2) + 4 (k % 2)."""
+    return [((nx + 1 - (c & 1)) // 2) * ((ny + 1 - ((c >> 1) & 1)) // 2)
+            * ((nz + 1 - (c >> 2)) // 2) for c in range(8)]
+
+
 def test_profile_counts_launches_and_algorithmic_bytes():
     """edf_profile: every smoother launch is counted with its algorithmic bytes (118
-    values per vertex of the swept colour and active sample), every 13th is timed, and
-    every V-cycle is timed."""
+    values per vertex of the swept colour and active sample; the first forward sweep of a
+    level, from x = 0, 4 per stencil block of an already swept neighbour colour plus 8),
+    every 13th is timed, and every V-cycle is timed."""
     nx, ny, nz, L, S = 33, 33, 9, 4, 2
     phys = synth.physics(2)
     pb = _problem(phys, [(nx, ny, nz, L, S)])
@@ -364,10 +384,17 @@ def test_profile_counts_launches_and_algorithmic_bytes():
     pb.profile(True)
     pb.apply_vcycle(0, DT, b)
     pr = pb.profile(False)
-    sizes = [(33 * 33 * 9), (17 * 17 * 5), (9 * 9 * 3)]
+    grids = [(33, 33, 9), (17, 17, 5), (9, 9, 3)]
+    assert sum(_zero_start_blocks(c) for c in range(8)) == 8 * 13
+    expect = 0
+    for g in grids:
+        cnt = _colour_counts(*g)
+        assert sum(cnt) == g[0] * g[1] * g[2]
+        expect += S * 8 * sum(n * (118 + 4 * _zero_start_blocks(c) + 8)
+                              for c, n in enumerate(cnt))
     assert pr["all_launches"] == 3 * 16
     assert pr["launches"] == len(range(0, 48, 13))
-    assert pr["all_bytes"] == sum(2 * n * S * 118 * 8 for n in sizes)
+    assert pr["all_bytes"] == expect
     assert pr["vcycles"] == 1 and pr["vcycle_ms"] > 0 and pr["ms"] > 0
     pb.destroy()
 
