@@ -80,6 +80,9 @@ struct Group {
   int min_fuse = 0;    // 1 when the finest level has an FP16 matrix (separate launches)
   void* fdesc = nullptr;  // device copy of the fused-bottom description (FusedLevels<T>)
   int fdesc_l0 = -1;      // the first fused level it describes (-1: not written yet)
+  // the matrices are the adjoint's transposed ones: their V-cycle keeps the general
+  // residual b - A x after the zero-start sweep
+  bool transposed = false;
   std::vector<double> tune_ms;  // V-cycle time per candidate fuse_from (autotuning)
   // per sample: halvings to start the next step with, steps since the last retry,
   // steps to wait before trying one halving less, whether this step is such a try
@@ -346,6 +349,7 @@ edf_status find_sample(edf_problem* pb, int sample, Group** G, int* local) {
 // ---------------------------------------------------------------------------
 edf_status assemble_all(edf_problem* pb, Group& G, const int* mask, const double* dts) {
   const bool mx = mixed(pb);
+  G.transposed = false;
   for (int l = 0; l < G.L; ++l) {
     Level& L = G.lv[l];
     if (l > 0) launch_inject(G.lv[l - 1].g, L.g, G.lv[l - 1].u, L.u, G.S, mask, G.st);
@@ -443,6 +447,7 @@ double sweep_bytes(int c, bool zero_start, bool fp16, size_t tsz) {
 // and r out), r into the restriction and x in and out for the correction; then the dense
 // coarse inverse and its vectors.
 double vcycle_bytes(const Group& G, size_t tsz, int nu1, int nu2) {
+  const bool zs_res = nu1 == 1 && !G.transposed;
   double b = 0;
   for (int l = 0; l + 1 < G.L; ++l) {
     const Geom& g = G.lv[l].g;
@@ -452,12 +457,12 @@ double vcycle_bytes(const Group& G, size_t tsz, int nu1, int nu2) {
     if (nu1 > 0)
       for (int c = 0; c < 8; ++c)
         b += (double)g.cnt[c] * (sweep_bytes(c, true, h, tsz) - sweep_bytes(c, false, h, tsz));
-    if (h && nu1 == 1) {  // FP16 blocks towards the later colours, D (FP32), r out
+    if (h && zs_res) {  // FP16 blocks towards the later colours, D (FP32), r out
       for (int c = 0; c < 8; ++c)
         b += (double)g.cnt[c] * ((26 - zero_start_blocks(c)) * 4 * 2 + 4 * 4 + 2 * 4 + 2 * 4 + 4 * 4);
     } else if (h) {  // the residual reads the FP16 blocks, D (FP32), D^{-1} b and x and writes r
       b += (double)g.N * ((26 * 4 * 2 + 4 * 4 + 6 * 4) + 2 * 4 + 4 * 4);
-    } else if (nu1 == 1) {
+    } else if (zs_res) {
       for (int c = 0; c < 8; ++c)
         b += (double)g.cnt[c] * (4.0 * (26 - zero_start_blocks(c)) + 8.0) * tsz;
     } else {
@@ -496,6 +501,9 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
   const int nu1 = pb->opts.nu_pre, nu2 = pb->opts.nu_post;
   T* b0 = (T*)G.lv[0].b;
   T* x0 = (T*)G.lv[0].x;
+  // residual from the blocks towards the later colours after a single zero-start sweep
+  // (equal to b - A x in exact arithmetic); the adjoint's transposed systems keep b - A x
+  const bool zs_res = nu1 == 1 && !G.transposed;
   // finest level with an FP16 matrix: b0 holds D^{-1} b (only for T = float)
   const bool h0 = std::is_same<T, float>::value && G.L >= 2 && G.lv[0].A16;
   if constexpr (std::is_same<T, float>::value) {
@@ -523,11 +531,11 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
     if constexpr (std::is_same<T, float>::value) {
       if (l == 0 && h0) {
         launch_residual_f16(L.g, L.A16, (const float*)L.Dinv, (const float*)b, (const float*)x,
-                            (float*)L.r, S, mask, st, nu1 == 1);
+                            (float*)L.r, S, mask, st, zs_res);
         return;
       }
     }
-    launch_residual<T>(L.g, stencil<T>(L), b, x, (T*)L.r, S, mask, st, nu1 == 1);
+    launch_residual<T>(L.g, stencil<T>(L), b, x, (T*)L.r, S, mask, st, zs_res);
   };
   auto bx = [&](int l, T*& b, T*& x) {
     b = l == 0 ? b0 : (T*)G.lv[l].b;
@@ -980,6 +988,7 @@ edf_status macro_step(edf_problem* pb, Group& G, double DT) {
 // ---------------------------------------------------------------------------
 edf_status assemble_all_transposed(edf_problem* pb, Group& G, const int* mask, const double* dts) {
   const bool mx = mixed(pb);
+  G.transposed = true;
   for (int l = 0; l < G.L; ++l) {
     Level& L = G.lv[l];
     if (l > 0) launch_inject(G.lv[l - 1].g, L.g, G.lv[l - 1].u, L.u, G.S, mask, G.st);

@@ -278,9 +278,11 @@ def test_vcycle_is_a_contraction(precision):
 
 @pytest.mark.parametrize("precision", [0, 1, 2])
 def test_vcycle_same_for_every_fused_bottom(precision):
-    """The V-cycle gives the same result whichever levels run in the fused bottom launch
-    (same per-vertex arithmetic in the same colour order), and set_tuning rejects levels
-    that do not fit the fused launch."""
+    """The V-cycle gives the same result whichever levels run in the fused bottom launch,
+    and set_tuning rejects levels that do not fit the fused launch.  Levels swept by
+    separate launches take the zero-start forms (first sweep from x = 0 reading only the
+    colours already swept, residual from the blocks towards the later colours); the fused
+    bottom takes the general forms (full stencil, r = b - A x): the two agree to rounding."""
     nx, ny, nz = 33, 33, 9
     phys = synth.physics(2)
     pb = _problem(phys, [(nx, ny, nz, 4, 3)], precision=precision)
