@@ -52,6 +52,10 @@ struct Group {
   // groups step concurrently, each from its own host thread on its own stream
   hipStream_t st = nullptr;
   int* h_int = nullptr;  // pinned host staging [S]
+  // the samples the V-cycle launches run over (device list, pinned host copy, count)
+  int* d_list = nullptr;
+  int* h_list = nullptr;
+  int n_list = 0;
   double* h_dbl = nullptr;
   KrylovScalars* h_ks = nullptr;
   // smoother and V-cycle timing: event pairs around every timed launch
@@ -291,6 +295,7 @@ edf_status alloc_group(edf_problem* pb, Group& G) {
   if ((s = dalloc(pb, &G.part, S * nb * 4))) return s;
   if ((s = dalloc(pb, &G.nmask, (size_t)S))) return s;
   if ((s = dalloc(pb, &G.active, (size_t)S))) return s;
+  if ((s = dalloc(pb, &G.d_list, (size_t)S))) return s;
   if ((s = dalloc(pb, &G.lsmask, (size_t)S))) return s;
   if ((s = dalloc(pb, &G.norms, (size_t)S))) return s;
   if ((s = dalloc(pb, &G.lam, (size_t)S))) return s;
@@ -476,6 +481,23 @@ double vcycle_bytes(const Group& G, size_t tsz, int nu1, int nu2) {
 // ---------------------------------------------------------------------------
 // one V-cycle: out = M^{-1} in (FP64 vectors of the scaled unknowns)
 // ---------------------------------------------------------------------------
+// The V-cycle's sample list: the samples s with flags[s] != 0, in order.  Called with the
+// group's stream idle (after a synchronisation), so the pinned copy feeds no pending copy.
+edf_status set_sample_list(edf_problem* pb, Group& G, const int* flags) {
+  int n = 0;
+  bool same = true;
+  for (int s = 0; s < G.S; ++s)
+    if (flags[s]) {
+      same = same && n < G.n_list && G.h_list[n] == s;
+      G.h_list[n++] = s;
+    }
+  if (same && n == G.n_list) return EDF_OK;
+  G.n_list = n;
+  if (n > 0)
+    EDF_TRY(hipMemcpyAsync(G.d_list, G.h_list, n * sizeof(int), hipMemcpyHostToDevice, G.st));
+  return EDF_OK;
+}
+
 // first level of the fused bottom of the V-cycle when not tuned: all levels of at
 // most kFuseMaxN vertices when the group has many samples (their workgroups run side
 // by side), else only the coarse solve (one workgroup per sample walks the levels
@@ -497,7 +519,11 @@ const float* stencil<float>(const Level& L) { return L.A32; }
 template <typename T>
 void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int* mask) {
   hipStream_t st = G.st;
-  const int S = G.S;
+  // launches run over the listed samples (mask still decides exactness); no list when it
+  // holds every sample
+  const int S = G.n_list;
+  const int* list = G.n_list < G.S ? G.d_list : nullptr;
+  if (S == 0) return;
   const int nu1 = pb->opts.nu_pre, nu2 = pb->opts.nu_post;
   T* b0 = (T*)G.lv[0].b;
   T* x0 = (T*)G.lv[0].x;
@@ -508,11 +534,11 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
   const bool h0 = std::is_same<T, float>::value && G.L >= 2 && G.lv[0].A16;
   if constexpr (std::is_same<T, float>::value) {
     if (h0)
-      launch_to_colour_scaled(G.lv[0].g, in, (const float*)G.lv[0].Dinv, (float*)b0, S, mask, st);
+      launch_to_colour_scaled(G.lv[0].g, in, (const float*)G.lv[0].Dinv, (float*)b0, S, mask, list, st);
     else
-      launch_to_colour<T>(G.lv[0].g, in, b0, S, mask, st);
+      launch_to_colour<T>(G.lv[0].g, in, b0, S, mask, list, st);
   } else {
-    launch_to_colour<T>(G.lv[0].g, in, b0, S, mask, st);
+    launch_to_colour<T>(G.lv[0].g, in, b0, S, mask, list, st);
   }
   // zs: the first forward sweep of the level, whose x is zero on entry
   auto smooth = [&](int l, const Level& L, int c, const T* b, T* x, bool zs) {
@@ -521,21 +547,21 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
     prof_pair(G, e0, e1, (double)L.g.cnt[c] * G.n_active * per_vertex, 0);
     if constexpr (std::is_same<T, float>::value) {
       if (l == 0 && h0) {
-        launch_smooth_f16(L.g, c, L.A16, (const float*)b, (float*)x, S, mask, st, e0, e1, zs);
+        launch_smooth_f16(L.g, c, L.A16, (const float*)b, (float*)x, S, mask, list, st, e0, e1, zs);
         return;
       }
     }
-    launch_smooth<T>(L.g, c, stencil<T>(L), (const T*)L.Dinv, b, x, S, mask, st, e0, e1, zs);
+    launch_smooth<T>(L.g, c, stencil<T>(L), (const T*)L.Dinv, b, x, S, mask, list, st, e0, e1, zs);
   };
   auto residual = [&](int l, const Level& L, const T* b, const T* x) {
     if constexpr (std::is_same<T, float>::value) {
       if (l == 0 && h0) {
         launch_residual_f16(L.g, L.A16, (const float*)L.Dinv, (const float*)b, (const float*)x,
-                            (float*)L.r, S, mask, st, zs_res);
+                            (float*)L.r, S, mask, list, st, zs_res);
         return;
       }
     }
-    launch_residual<T>(L.g, stencil<T>(L), b, x, (T*)L.r, S, mask, st, zs_res);
+    launch_residual<T>(L.g, stencil<T>(L), b, x, (T*)L.r, S, mask, list, st, zs_res);
   };
   auto bx = [&](int l, T*& b, T*& x) {
     b = l == 0 ? b0 : (T*)G.lv[l].b;
@@ -545,7 +571,7 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
   const int l0 = G.fuse_from >= 0 ? G.fuse_from : default_fuse_from(G);
   // every level starts from x = 0: the first forward sweep writes x at every vertex
   // without reading it, so x needs clearing only without pre-smoothing
-  if (l0 > 0 && nu1 == 0) launch_fill<T>(x0, 2 * (size_t)G.lv[0].g.off[8], S, mask, T(0), st);
+  if (l0 > 0 && nu1 == 0) launch_fill<T>(x0, 2 * (size_t)G.lv[0].g.off[8], G.S, mask, T(0), st);
   for (int l = 0; l < l0; ++l) {
     Level& L = G.lv[l];
     T *b, *x;
@@ -557,7 +583,7 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
     bx(l + 1, bc, xc);
     // x of the next level needs no clearing when its first sweep starts from zero or
     // when it is the fused bottom's first level (cleared there)
-    launch_restrict<T>(L.g, G.lv[l + 1].g, (const T*)L.r, bc, nu1 > 0 ? nullptr : xc, S, mask, st);
+    launch_restrict<T>(L.g, G.lv[l + 1].g, (const T*)L.r, bc, nu1 > 0 ? nullptr : xc, S, mask, list, st);
   }
   {
     FusedLevels<T> F{};
@@ -588,18 +614,18 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
       (void)hipStreamSynchronize(st);
       G.fdesc_l0 = l0;
     }
-    launch_vcycle_bottom<T>((const FusedLevels<T>*)G.fdesc, in_lds ? lds_bytes : 0, S, mask, st);
+    launch_vcycle_bottom<T>((const FusedLevels<T>*)G.fdesc, in_lds ? lds_bytes : 0, S, mask, list, st);
   }
   for (int l = l0 - 1; l >= 0; --l) {
     Level& L = G.lv[l];
     T *b, *x, *bc, *xc;
     bx(l, b, x);
     bx(l + 1, bc, xc);
-    launch_prolong<T>(L.g, G.lv[l + 1].g, xc, x, S, mask, st);
+    launch_prolong<T>(L.g, G.lv[l + 1].g, xc, x, S, mask, list, st);
     for (int it = 0; it < nu2; ++it)
       for (int c = 7; c >= 0; --c) smooth(l, L, c, b, x, false);
   }
-  launch_from_colour<T>(G.lv[0].g, x0, out, S, mask, st);
+  launch_from_colour<T>(G.lv[0].g, x0, out, S, mask, list, st);
 }
 
 void precondition(edf_problem* pb, Group& G, const double* in, double* out, const int* mask) {
@@ -631,6 +657,8 @@ edf_status bicgstab(edf_problem* pb, Group& G) {
     EDF_TRY(hipStreamSynchronize(st));
     G.n_active = 0;
     for (int s = 0; s < S; ++s) G.n_active += G.h_int[s] != 0;
+    edf_status e;
+    if ((e = set_sample_list(pb, G, G.h_int))) return e;
     return prof_flush(pb, G);
   };
   edf_status e;
@@ -638,14 +666,17 @@ edf_status bicgstab(edf_problem* pb, Group& G) {
   const int chunk = std::max(1, pb->opts.check_every);
   for (int it = 0; it < pb->opts.lin_max_it && G.n_active > 0; it += chunk) {
     for (int c = 0; c < chunk && it + c < pb->opts.lin_max_it; ++c) {
-      launch_bicg_p(n, G.kr, G.kv, G.kp, G.ks, S, G.active, st);
+      // the launches run over the samples active at the last count (a superset of those
+      // still active: the active flags gate the rest)
+      const SampleList sl{G.n_list < S ? G.d_list : nullptr, G.n_list};
+      launch_bicg_p(n, G.kr, G.kv, G.kp, G.ks, S, G.active, sl, st);
       precondition(pb, G, G.kp, G.kph, G.active);
-      launch_bicg_alpha(g0, A, G.kph, G.kv, G.krh, G.part, G.ks, S, G.active, st);
-      launch_bicg_s(n, G.kr, G.kv, G.ks_, G.part, G.ks, S, G.active, st);
+      launch_bicg_alpha(g0, A, G.kph, G.kv, G.krh, G.part, G.ks, S, G.active, sl, st);
+      launch_bicg_s(n, G.kr, G.kv, G.ks_, G.part, G.ks, S, G.active, sl, st);
       precondition(pb, G, G.ks_, G.ksh, G.active);
-      launch_bicg_omega(g0, A, G.ksh, G.ks_, G.kt, G.part, G.ks, S, G.active, st);
+      launch_bicg_omega(g0, A, G.ksh, G.ks_, G.kt, G.part, G.ks, S, G.active, sl, st);
       launch_bicg_update(n, G.kph, G.ksh, G.ks_, G.kt, G.krh, G.kx, G.kr, G.part, G.ks, G.active,
-                         S, G.active, st);
+                         S, G.active, sl, st);
     }
     if ((e = count_active())) return e;
   }
@@ -693,6 +724,7 @@ edf_status autotune_group(edf_problem* pb, Group& G) {
   std::vector<int> all(G.S, 1);
   edf_status e;
   if ((e = upload_ints(pb, G, G.nmask, all))) return e;
+  if ((e = set_sample_list(pb, G, all.data()))) return e;
   if ((e = assemble_all(pb, G, G.nmask, nullptr))) return e;
   launch_defect(G.lv[0].g, G.lv[0].ph, nullptr, G.lv[0].phi, G.lv[0].K, G.u, G.u, G.kp, G.S,
                 nullptr, st);
@@ -1292,6 +1324,7 @@ edf_status edf_create_problem(const edf_physics* phys, const edf_group_desc* gro
     const bool ok =
         hipStreamCreateWithFlags(&G.st, hipStreamNonBlocking) == hipSuccess &&
         hipHostMalloc((void**)&G.h_int, sizeof(int) * G.S) == hipSuccess &&
+        hipHostMalloc((void**)&G.h_list, sizeof(int) * G.S) == hipSuccess &&
         hipHostMalloc((void**)&G.h_dbl, sizeof(double) * G.S) == hipSuccess &&
         hipHostMalloc((void**)&G.h_ks, sizeof(KrylovScalars) * G.S) == hipSuccess;
     if (!ok || upload_initial(pb, G) != EDF_OK) {
@@ -1672,6 +1705,7 @@ edf_status edf_apply_vcycle(edf_problem* pb, int32_t group, double dt, const dou
   set_dt(pb, G, dt);
   std::vector<int> all(G.S, 1);
   if ((e = upload_ints(pb, G, G.nmask, all))) return e;
+  if ((e = set_sample_list(pb, G, all.data()))) return e;
   if ((e = assemble_all(pb, G, G.nmask, nullptr))) return e;
   EDF_TRY(hipMemcpyAsync(G.kp, x, G.S * G.n * sizeof(double), hipMemcpyHostToDevice, G.st));
   G.n_active = G.S;
@@ -1793,6 +1827,7 @@ void edf_destroy(edf_problem* pb) {
     }
     for (hipEvent_t e : G.prof_ev) (void)hipEventDestroy(e);
     if (G.h_int) (void)hipHostFree(G.h_int);
+    if (G.h_list) (void)hipHostFree(G.h_list);
     if (G.h_dbl) (void)hipHostFree(G.h_dbl);
     if (G.h_ks) (void)hipHostFree(G.h_ks);
   }

@@ -79,6 +79,12 @@ void launch_stencil_to_natural(const Geom& g, const double* A, double* out, hipS
 // ---------------------------------------------------------------------------
 // multigrid and stencil kernels (mg_kernels.hip), T = double or float
 // ---------------------------------------------------------------------------
+// The V-cycle launches take (S, mask, list): grid row y works on sample list[y] (or y when
+// list is null) for y < S, and returns at once when mask is set and mask[sample] is 0.
+// A list of the active samples keeps the launch from dispatching workgroups of finished
+// samples (70k one-wave workgroups cost about 14 us to dispatch even when they all
+// return at once).
+
 // Colour of the neighbour at offset (dx, dy, dz) of a vertex of colour col: an odd
 // offset along an axis flips that axis's parity bit.
 __host__ __device__ constexpr int nbr_colour(int col, int dx, int dy, int dz) {
@@ -105,21 +111,21 @@ __host__ __device__ constexpr int zero_start_blocks(int col) {
 // level whose x is zero on entry (reads only the colours already swept, writes x)
 template <typename T>
 void launch_smooth(const Geom& g, int colour, const T* A, const T* Dinv, const T* b, T* x, int S,
-                   const int* mask, hipStream_t st, hipEvent_t ev0 = nullptr,
+                   const int* mask, const int* list, hipStream_t st, hipEvent_t ev0 = nullptr,
                    hipEvent_t ev1 = nullptr, bool zero_start = false);
 // r = b - A x, zero in Dirichlet rows; zero_sweep: x is the result of a single forward
 // sweep from x = 0, whose residual needs only the blocks towards the colours not yet swept
 // when each vertex was updated (b is not read)
 template <typename T>
 void launch_residual(const Geom& g, const T* A, const T* b, const T* x, T* r, int S,
-                     const int* mask, hipStream_t st, bool zero_sweep = false);
+                     const int* mask, const int* list, hipStream_t st, bool zero_sweep = false);
 // bc = R rf (full weighting, coarse row scaling); xc, when not null, cleared
 template <typename T>
 void launch_restrict(const Geom& gf, const Geom& gc, const T* rf, T* bc, T* xc, int S,
-                     const int* mask, hipStream_t st);
+                     const int* mask, const int* list, hipStream_t st);
 template <typename T>
 void launch_prolong(const Geom& gf, const Geom& gc, const T* xc, T* xf, int S, const int* mask,
-                    hipStream_t st);
+                    const int* list, hipStream_t st);
 template <typename T>
 void launch_fill(T* x, size_t per_sample, int S, const int* mask, T value, hipStream_t st);
 // FP16 finest level (EDF_PREC_MIXED_F16): from the FP32 matrix A32, the block-scaled
@@ -128,22 +134,22 @@ void launch_scale_f16(const Geom& g, const float* A32, _Float16* A16, float* D32
                       const int* mask, hipStream_t st);
 // block Gauss-Seidel with A16: x_v = bh_v - sum_{o != diag} A16_vo x_{v+o}, bh = D^{-1} b
 void launch_smooth_f16(const Geom& g, int colour, const _Float16* A16, const float* bh, float* x,
-                       int S, const int* mask, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1,
-                       bool zero_start = false);
+                       int S, const int* mask, const int* list, hipStream_t st, hipEvent_t ev0,
+                       hipEvent_t ev1, bool zero_start = false);
 // r = b - A x = D (bh - A16 x), zero in Dirichlet rows
 void launch_residual_f16(const Geom& g, const _Float16* A16, const float* D32, const float* bh,
-                         const float* x, float* r, int S, const int* mask, hipStream_t st,
-                         bool zero_sweep = false);
+                         const float* x, float* r, int S, const int* mask, const int* list,
+                         hipStream_t st, bool zero_sweep = false);
 // entry: bh = D^{-1} b, FP64 natural [N][2] -> FP32 colour-major [Np][2]
 void launch_to_colour_scaled(const Geom& g, const double* in, const float* D32, float* out, int S,
-                             const int* mask, hipStream_t st);
+                             const int* mask, const int* list, hipStream_t st);
 // finest-level V-cycle entry and exit: FP64 natural [N][2] <-> T colour-major [Np][2]
 template <typename T>
 void launch_to_colour(const Geom& g, const double* in, T* out, int S, const int* mask,
-                      hipStream_t st);
+                      const int* list, hipStream_t st);
 template <typename T>
 void launch_from_colour(const Geom& g, const T* in, double* out, int S, const int* mask,
-                        hipStream_t st);
+                        const int* list, hipStream_t st);
 void launch_coarse_dense(const Geom& g, const double* A, double* M, int S, const int* mask,
                          hipStream_t st);
 void launch_gauss_jordan(int n, double* M, int* piv, int* status, int S, const int* mask,
@@ -174,7 +180,7 @@ struct FusedLevels {
 // lds_bytes: dynamic LDS of the launch (0 when the levels stay in device memory)
 template <typename T>
 void launch_vcycle_bottom(const FusedLevels<T>* F_dev, size_t lds_bytes, int S, const int* mask,
-                          hipStream_t st);
+                          const int* list, hipStream_t st);
 // LDS a workgroup of the fused bottom may take for the levels' vectors (0 when the device
 // does not allow more than the static part)
 template <typename T>
@@ -190,17 +196,28 @@ void launch_spmv(const Geom& g, const double* A, const double* x, double* y, int
 void launch_bicg_init(size_t n, const double* b, double* x, double* r, double* rh, double* p,
                       double* v, double* part, KrylovScalars* ks, const double* rtol, int* active,
                       int S, const int* mask, hipStream_t st);
+// The iteration's launches run grid row y over sample sl.idx[y] for y < sl.n (all S samples
+// when sl.idx is null); mask still gates every sample, and the per-sample reductions that
+// follow run over all S.
+struct SampleList {
+  const int* idx = nullptr;
+  int n = 0;
+  int rows(int S) const { return idx ? n : S; }
+};
 void launch_bicg_p(size_t n, const double* r, const double* v, double* p, const KrylovScalars* ks,
-                   int S, const int* mask, hipStream_t st);
+                   int S, const int* mask, SampleList sl, hipStream_t st);
 void launch_bicg_alpha(const Geom& g, const double* A, const double* ph, double* v, const double* rh,
-                       double* part, KrylovScalars* ks, int S, const int* mask, hipStream_t st);
+                       double* part, KrylovScalars* ks, int S, const int* mask, SampleList sl,
+                       hipStream_t st);
 void launch_bicg_s(size_t n, const double* r, const double* v, double* s, double* part,
-                   KrylovScalars* ks, int S, const int* mask, hipStream_t st);
+                   KrylovScalars* ks, int S, const int* mask, SampleList sl, hipStream_t st);
 void launch_bicg_omega(const Geom& g, const double* A, const double* sh, const double* s, double* t,
-                       double* part, KrylovScalars* ks, int S, const int* mask, hipStream_t st);
+                       double* part, KrylovScalars* ks, int S, const int* mask, SampleList sl,
+                       hipStream_t st);
 void launch_bicg_update(size_t n, const double* ph, const double* sh, const double* s,
                         const double* t, const double* rh, double* x, double* r, double* part,
-                        KrylovScalars* ks, int* active, int S, const int* mask, hipStream_t st);
+                        KrylovScalars* ks, int* active, int S, const int* mask, SampleList sl,
+                        hipStream_t st);
 // Newton helpers
 void launch_sq_norm(size_t n, const double* x, double* part, double* out, int S, const int* mask,
                     hipStream_t st);

@@ -47,8 +47,8 @@ enum DotMode { kDotNone = 0, kDotOne = 1, kDotTS = 2 };
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_spmv(Geom g, const double* A_all, const double* x_all,
                                                  double* y_all, const double* d_all, double* part,
-                                                 const int* mask) {
-  const int s = blockIdx.y;
+                                                 const int* mask, const int* list) {
+  const int s = list ? list[blockIdx.y] : blockIdx.y;
   if (mask && !mask[s]) return;
   // one thread per vertex in natural order: the Krylov vectors x, y, d are read and
   // written contiguously; the stencil rows of a wave's 64 vertices are two runs of 32
@@ -99,7 +99,7 @@ void launch_spmv(const Geom& g, const double* A, const double* x, double* y, int
                  const int* mask, hipStream_t st) {
   dim3 grid(ceil_div(g.N, kBlock), S);
   hipLaunchKernelGGL(k_spmv<kDotNone>, grid, dim3(kBlock), 0, st, g, A, x, y, (const double*)nullptr,
-                     (double*)nullptr, mask);
+                     (double*)nullptr, mask, (const int*)nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -221,8 +221,8 @@ void launch_bicg_init(size_t n, const double* b, double* x, double* r, double* r
 
 __global__ __launch_bounds__(kBlock) void k_bicg_p(size_t n, const double* r, const double* v,
                                                    double* p, const KrylovScalars* ks,
-                                                   const int* mask) {
-  const int s = blockIdx.y;
+                                                   const int* mask, const int* list) {
+  const int s = list ? list[blockIdx.y] : blockIdx.y;
   if (mask && !mask[s]) return;
   const double beta = ks[s].beta, omega = ks[s].omega;
   const size_t o = (size_t)s * n;
@@ -232,24 +232,25 @@ __global__ __launch_bounds__(kBlock) void k_bicg_p(size_t n, const double* r, co
 }
 
 void launch_bicg_p(size_t n, const double* r, const double* v, double* p, const KrylovScalars* ks,
-                   int S, const int* mask, hipStream_t st) {
-  hipLaunchKernelGGL(k_bicg_p, dim3(reduce_blocks(n), S), dim3(kBlock), 0, st, n, r, v, p, ks,
-                     mask);
+                   int S, const int* mask, SampleList sl, hipStream_t st) {
+  hipLaunchKernelGGL(k_bicg_p, dim3(reduce_blocks(n), sl.rows(S)), dim3(kBlock), 0, st, n, r, v,
+                     p, ks, mask, sl.idx);
 }
 
 void launch_bicg_alpha(const Geom& g, const double* A, const double* ph, double* v,
                        const double* rh, double* part, KrylovScalars* ks, int S, const int* mask,
-                       hipStream_t st) {
+                       SampleList sl, hipStream_t st) {
   const int nb = ceil_div(g.N, kBlock);
-  hipLaunchKernelGGL(k_spmv<kDotOne>, dim3(nb, S), dim3(kBlock), 0, st, g, A, ph, v, rh, part,
-                     mask);
+  hipLaunchKernelGGL(k_spmv<kDotOne>, dim3(nb, sl.rows(S)), dim3(kBlock), 0, st, g, A, ph, v, rh,
+                     part, mask, sl.idx);
   finalize(kAlpha, nb, part, ks, const_cast<int*>(mask), nullptr, S, st);  // mask is `active`
 }
 
 __global__ __launch_bounds__(kBlock) void k_bicg_s(size_t n, const double* r, const double* v,
                                                    double* sv, double* part,
-                                                   const KrylovScalars* ks, const int* mask) {
-  const int s = blockIdx.y;
+                                                   const KrylovScalars* ks, const int* mask,
+                                                   const int* list) {
+  const int s = list ? list[blockIdx.y] : blockIdx.y;
   if (mask && !mask[s]) return;
   const double alpha = ks[s].alpha;
   const size_t o = (size_t)s * n;
@@ -264,17 +265,19 @@ __global__ __launch_bounds__(kBlock) void k_bicg_s(size_t n, const double* r, co
 }
 
 void launch_bicg_s(size_t n, const double* r, const double* v, double* s, double* part,
-                   KrylovScalars* ks, int S, const int* mask, hipStream_t st) {
+                   KrylovScalars* ks, int S, const int* mask, SampleList sl, hipStream_t st) {
   const int nb = reduce_blocks(n);
-  hipLaunchKernelGGL(k_bicg_s, dim3(nb, S), dim3(kBlock), 0, st, n, r, v, s, part, ks, mask);
+  hipLaunchKernelGGL(k_bicg_s, dim3(nb, sl.rows(S)), dim3(kBlock), 0, st, n, r, v, s, part, ks,
+                     mask, sl.idx);
   finalize(kS, nb, part, ks, const_cast<int*>(mask), nullptr, S, st);
 }
 
 void launch_bicg_omega(const Geom& g, const double* A, const double* sh, const double* s,
                        double* t, double* part, KrylovScalars* ks, int S, const int* mask,
-                       hipStream_t st) {
+                       SampleList sl, hipStream_t st) {
   const int nb = ceil_div(g.N, kBlock);
-  hipLaunchKernelGGL(k_spmv<kDotTS>, dim3(nb, S), dim3(kBlock), 0, st, g, A, sh, t, s, part, mask);
+  hipLaunchKernelGGL(k_spmv<kDotTS>, dim3(nb, sl.rows(S)), dim3(kBlock), 0, st, g, A, sh, t, s,
+                     part, mask, sl.idx);
   finalize(kOmega, nb, part, ks, const_cast<int*>(mask), nullptr, S, st);
 }
 
@@ -282,8 +285,9 @@ __global__ __launch_bounds__(kBlock) void k_bicg_update(size_t n, const double* 
                                                         const double* sh, const double* sv,
                                                         const double* t, const double* rh,
                                                         double* x, double* r, double* part,
-                                                        const KrylovScalars* ks, const int* mask) {
-  const int s = blockIdx.y;
+                                                        const KrylovScalars* ks, const int* mask,
+                                                        const int* list) {
+  const int s = list ? list[blockIdx.y] : blockIdx.y;
   if (mask && !mask[s]) return;
   const double alpha = ks[s].alpha, omega = ks[s].omega;
   const size_t o = (size_t)s * n;
@@ -301,10 +305,11 @@ __global__ __launch_bounds__(kBlock) void k_bicg_update(size_t n, const double* 
 
 void launch_bicg_update(size_t n, const double* ph, const double* sh, const double* s,
                         const double* t, const double* rh, double* x, double* r, double* part,
-                        KrylovScalars* ks, int* active, int S, const int* mask, hipStream_t st) {
+                        KrylovScalars* ks, int* active, int S, const int* mask, SampleList sl,
+                        hipStream_t st) {
   const int nb = reduce_blocks(n);
-  hipLaunchKernelGGL(k_bicg_update, dim3(nb, S), dim3(kBlock), 0, st, n, ph, sh, s, t, rh, x, r,
-                     part, ks, mask);
+  hipLaunchKernelGGL(k_bicg_update, dim3(nb, sl.rows(S)), dim3(kBlock), 0, st, n, ph, sh, s, t, rh,
+                     x, r, part, ks, mask, sl.idx);
   finalize(kUpdate, nb, part, ks, active, nullptr, S, st);
 }
 

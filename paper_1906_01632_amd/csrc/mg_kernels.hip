@@ -281,8 +281,8 @@ bool stream_matrix(const Geom& g, int S) {
 // ZC: -1 for a sweep of any colour col, else the zero-start sweep of colour col = ZC
 template <typename T, bool NT, int ZC>
 __global__ __launch_bounds__(kSweepBlock) void k_smooth(Geom g, int col, const T* A_all, const T* Dinv_all,
-                                                   const T* b_all, T* x_all, const int* mask) {
-  const int s = blockIdx.y;
+                                                   const T* b_all, T* x_all, const int* mask, const int* list) {
+  const int s = list ? list[blockIdx.y] : blockIdx.y;
   if (mask && !mask[s]) return;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= g.cnt[col]) return;
@@ -311,7 +311,7 @@ auto smooth_kernel(int colour, bool zero_start) {
 
 template <typename T>
 void launch_smooth(const Geom& g, int colour, const T* A, const T* Dinv, const T* b, T* x, int S,
-                   const int* mask, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1,
+                   const int* mask, const int* list, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1,
                    bool zero_start) {
   const int n = g.cnt[colour];
   if (n <= 0) return;
@@ -320,16 +320,16 @@ void launch_smooth(const Geom& g, int colour, const T* A, const T* Dinv, const T
                                      : smooth_kernel<T, false>(colour, zero_start);
   if (ev0)  // timed launch: events recorded around this kernel only
     hipExtLaunchKernelGGL(kern, grid, dim3(kSweepBlock), 0, st, ev0, ev1, 0, g, colour, A, Dinv, b, x,
-                          mask);
+                          mask, list);
   else
-    hipLaunchKernelGGL(kern, grid, dim3(kSweepBlock), 0, st, g, colour, A, Dinv, b, x, mask);
+    hipLaunchKernelGGL(kern, grid, dim3(kSweepBlock), 0, st, g, colour, A, Dinv, b, x, mask, list);
 }
 
 // ZS: the level had a single pre-smoothing sweep, from x = 0
 template <typename T, bool NT, bool ZS>
 __global__ __launch_bounds__(kBlock) void k_residual(Geom g, const T* A_all, const T* b_all,
-                                                     const T* x_all, T* r_all, const int* mask) {
-  const int s = blockIdx.y;
+                                                     const T* x_all, T* r_all, const int* mask, const int* list) {
+  const int s = list ? list[blockIdx.y] : blockIdx.y;
   if (mask && !mask[s]) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= g.off[8]) return;
@@ -344,18 +344,18 @@ __global__ __launch_bounds__(kBlock) void k_residual(Geom g, const T* A_all, con
 
 template <typename T>
 void launch_residual(const Geom& g, const T* A, const T* b, const T* x, T* r, int S,
-                     const int* mask, hipStream_t st, bool zero_sweep) {
+                     const int* mask, const int* list, hipStream_t st, bool zero_sweep) {
   dim3 grid(ceil_div(g.off[8], kBlock), S);
   const bool nt = stream_matrix<T>(g, S);
   auto kern = zero_sweep ? (nt ? k_residual<T, true, true> : k_residual<T, false, true>)
                          : (nt ? k_residual<T, true, false> : k_residual<T, false, false>);
-  hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, st, g, A, b, x, r, mask);
+  hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, st, g, A, b, x, r, mask, list);
 }
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, const T* rf_all, T* bc_all,
-                                                     T* xc_all, const int* mask) {
-  const int s = blockIdx.y;
+                                                     T* xc_all, const int* mask, const int* list) {
+  const int s = list ? list[blockIdx.y] : blockIdx.y;
   if (mask && !mask[s]) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= gc.off[8]) return;
@@ -365,15 +365,15 @@ __global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, const T* 
 
 template <typename T>
 void launch_restrict(const Geom& gf, const Geom& gc, const T* rf, T* bc, T* xc, int S,
-                     const int* mask, hipStream_t st) {
+                     const int* mask, const int* list, hipStream_t st) {
   dim3 grid(ceil_div(gc.off[8], kBlock), S);
-  hipLaunchKernelGGL(k_restrict<T>, grid, dim3(kBlock), 0, st, gf, gc, rf, bc, xc, mask);
+  hipLaunchKernelGGL(k_restrict<T>, grid, dim3(kBlock), 0, st, gf, gc, rf, bc, xc, mask, list);
 }
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prolong(Geom gf, Geom gc, const T* xc_all, T* xf_all,
-                                                    const int* mask) {
-  const int s = blockIdx.y;
+                                                    const int* mask, const int* list) {
+  const int s = list ? list[blockIdx.y] : blockIdx.y;
   if (mask && !mask[s]) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= gf.off[8]) return;
@@ -383,9 +383,9 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Geom gf, Geom gc, const T* x
 
 template <typename T>
 void launch_prolong(const Geom& gf, const Geom& gc, const T* xc, T* xf, int S, const int* mask,
-                    hipStream_t st) {
+                    const int* list, hipStream_t st) {
   dim3 grid(ceil_div(gf.off[8], kBlock), S);
-  hipLaunchKernelGGL(k_prolong<T>, grid, dim3(kBlock), 0, st, gf, gc, xc, xf, mask);
+  hipLaunchKernelGGL(k_prolong<T>, grid, dim3(kBlock), 0, st, gf, gc, xc, xf, mask, list);
 }
 
 // ---------------------------------------------------------------------------
@@ -445,8 +445,8 @@ void launch_scale_f16(const Geom& g, const float* A32, _Float16* A16, float* D32
 template <bool NT, int ZC>
 __global__ __launch_bounds__(kSweepBlock) void k_smooth_f16(Geom g, int col, const _Float16* A_all,
                                                        const float* bh_all, float* x_all,
-                                                       const int* mask) {
-  const int s = blockIdx.y;
+                                                       const int* mask, const int* list) {
+  const int s = list ? list[blockIdx.y] : blockIdx.y;
   if (mask && !mask[s]) return;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= g.cnt[col]) return;
@@ -496,7 +496,8 @@ auto smooth_f16_kernel(int colour, bool zero_start) {
 }
 
 void launch_smooth_f16(const Geom& g, int colour, const _Float16* A16, const float* bh, float* x,
-                       int S, const int* mask, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1,
+                       int S, const int* mask, const int* list, hipStream_t st, hipEvent_t ev0,
+                       hipEvent_t ev1,
                        bool zero_start) {
   const int n = g.cnt[colour];
   if (n <= 0) return;
@@ -506,9 +507,9 @@ void launch_smooth_f16(const Geom& g, int colour, const _Float16* A16, const flo
                      : smooth_f16_kernel<false>(colour, zero_start);
   if (ev0)
     hipExtLaunchKernelGGL(kern, grid, dim3(kSweepBlock), 0, st, ev0, ev1, 0, g, colour, A16, bh, x,
-                          mask);
+                          mask, list);
   else
-    hipLaunchKernelGGL(kern, grid, dim3(kSweepBlock), 0, st, g, colour, A16, bh, x, mask);
+    hipLaunchKernelGGL(kern, grid, dim3(kSweepBlock), 0, st, g, colour, A16, bh, x, mask, list);
 }
 
 // r = D (bh - A16 x) after a single forward sweep from x = 0 at position t of colour
@@ -552,8 +553,8 @@ template <bool NT, bool ZS>
 __global__ __launch_bounds__(kBlock) void k_residual_f16(Geom g, const _Float16* A_all,
                                                          const float* D_all, const float* bh_all,
                                                          const float* x_all, float* r_all,
-                                                         const int* mask) {
-  const int s = blockIdx.y;
+                                                         const int* mask, const int* list) {
+  const int s = list ? list[blockIdx.y] : blockIdx.y;
   if (mask && !mask[s]) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const size_t Np = g.off[8];
@@ -613,19 +614,19 @@ __global__ __launch_bounds__(kBlock) void k_residual_f16(Geom g, const _Float16*
 }
 
 void launch_residual_f16(const Geom& g, const _Float16* A16, const float* D32, const float* bh,
-                         const float* x, float* r, int S, const int* mask, hipStream_t st,
-                         bool zero_sweep) {
+                         const float* x, float* r, int S, const int* mask, const int* list,
+                         hipStream_t st, bool zero_sweep) {
   dim3 grid(ceil_div(g.off[8], kBlock), S);
   const bool stream = (double)S * kPlanes * g.off[8] * sizeof(_Float16) > kCachedMatrixBytes;
   auto kern = zero_sweep ? (stream ? k_residual_f16<true, true> : k_residual_f16<false, true>)
                          : (stream ? k_residual_f16<true, false> : k_residual_f16<false, false>);
-  hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, st, g, A16, D32, bh, x, r, mask);
+  hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, st, g, A16, D32, bh, x, r, mask, list);
 }
 
 __global__ __launch_bounds__(kBlock) void k_to_colour_scaled(Geom g, const double* in_all,
                                                              const float* D_all, float* out_all,
-                                                             const int* mask) {
-  const int s = blockIdx.y;
+                                                             const int* mask, const int* list) {
+  const int s = list ? list[blockIdx.y] : blockIdx.y;
   if (mask && !mask[s]) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   int col, i, j, k;
@@ -642,9 +643,9 @@ __global__ __launch_bounds__(kBlock) void k_to_colour_scaled(Geom g, const doubl
 }
 
 void launch_to_colour_scaled(const Geom& g, const double* in, const float* D32, float* out, int S,
-                             const int* mask, hipStream_t st) {
+                             const int* mask, const int* list, hipStream_t st) {
   hipLaunchKernelGGL(k_to_colour_scaled, dim3(ceil_div(g.off[8], kBlock), S), dim3(kBlock), 0, st,
-                     g, in, D32, out, mask);
+                     g, in, D32, out, mask, list);
 }
 
 // ---------------------------------------------------------------------------
@@ -671,8 +672,8 @@ void launch_fill(T* x, size_t per_sample, int S, const int* mask, T value, hipSt
 // order [N][2]) to and from the V-cycle vectors (T, colour-major [Np][2])
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_to_colour(Geom g, const double* in_all, T* out_all,
-                                                      const int* mask) {
-  const int s = blockIdx.y;
+                                                      const int* mask, const int* list) {
+  const int s = list ? list[blockIdx.y] : blockIdx.y;
   if (mask && !mask[s]) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   int col, i, j, k;
@@ -687,8 +688,8 @@ __global__ __launch_bounds__(kBlock) void k_to_colour(Geom g, const double* in_a
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_from_colour(Geom g, const T* in_all, double* out_all,
-                                                        const int* mask) {
-  const int s = blockIdx.y;
+                                                        const int* mask, const int* list) {
+  const int s = list ? list[blockIdx.y] : blockIdx.y;
   if (mask && !mask[s]) return;
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= g.N) return;
@@ -701,16 +702,16 @@ __global__ __launch_bounds__(kBlock) void k_from_colour(Geom g, const T* in_all,
 
 template <typename T>
 void launch_to_colour(const Geom& g, const double* in, T* out, int S, const int* mask,
-                      hipStream_t st) {
+                      const int* list, hipStream_t st) {
   hipLaunchKernelGGL(k_to_colour<T>, dim3(ceil_div(g.off[8], kBlock), S), dim3(kBlock), 0, st, g,
-                     in, out, mask);
+                     in, out, mask, list);
 }
 
 template <typename T>
 void launch_from_colour(const Geom& g, const T* in, double* out, int S, const int* mask,
-                        hipStream_t st) {
+                        const int* list, hipStream_t st) {
   hipLaunchKernelGGL(k_from_colour<T>, dim3(ceil_div(g.N, kBlock), S), dim3(kBlock), 0, st, g,
-                     in, out, mask);
+                     in, out, mask, list);
 }
 
 // ---------------------------------------------------------------------------
@@ -854,11 +855,11 @@ constexpr int kFusedThreads = 1024;
 
 template <typename T>
 __global__ __launch_bounds__(kFusedThreads) void k_vcycle_bottom(const FusedLevels<T>* __restrict__ Fp,
-                                                                 const int* mask) {
+                                                                 const int* mask, const int* list) {
   // the levels' x, b and r in LDS when F.lds_off says so (the dynamic LDS of the launch)
   extern __shared__ double lds_vec[];
   const FusedLevels<T>& F = *Fp;
-  const int s = blockIdx.x;
+  const int s = list ? list[blockIdx.x] : blockIdx.x;
   if (mask && !mask[s]) return;
   const int tid = threadIdx.x, nt = blockDim.x;
   const bool in_lds = F.lds_off[0] >= 0;
@@ -960,27 +961,29 @@ size_t vcycle_bottom_lds_limit() {
 
 template <typename T>
 void launch_vcycle_bottom(const FusedLevels<T>* F, size_t lds_bytes, int S, const int* mask,
-                          hipStream_t st) {
-  hipLaunchKernelGGL(k_vcycle_bottom<T>, dim3(S), dim3(kFusedThreads), lds_bytes, st, F, mask);
+                          const int* list, hipStream_t st) {
+  hipLaunchKernelGGL(k_vcycle_bottom<T>, dim3(S), dim3(kFusedThreads), lds_bytes, st, F, mask,
+                     list);
 }
 
 // explicit instantiations
 #define EDF_INST(T)                                                                              \
   template void launch_smooth<T>(const Geom&, int, const T*, const T*, const T*, T*, int,        \
-                                 const int*, hipStream_t, hipEvent_t, hipEvent_t, bool);         \
+                                 const int*, const int*, hipStream_t, hipEvent_t, hipEvent_t,    \
+                                 bool);                                                          \
   template void launch_residual<T>(const Geom&, const T*, const T*, const T*, T*, int,           \
-                                   const int*, hipStream_t, bool);                               \
+                                   const int*, const int*, hipStream_t, bool);                   \
   template void launch_restrict<T>(const Geom&, const Geom&, const T*, T*, T*, int, const int*,  \
-                                   hipStream_t);                                                 \
+                                   const int*, hipStream_t);                                     \
   template void launch_prolong<T>(const Geom&, const Geom&, const T*, T*, int, const int*,       \
-                                  hipStream_t);                                                  \
+                                  const int*, hipStream_t);                                      \
   template void launch_fill<T>(T*, size_t, int, const int*, T, hipStream_t);                     \
   template void launch_to_colour<T>(const Geom&, const double*, T*, int, const int*,             \
-                                    hipStream_t);                                                \
+                                    const int*, hipStream_t);                                    \
   template void launch_from_colour<T>(const Geom&, const T*, double*, int, const int*,           \
-                                      hipStream_t);                                              \
+                                      const int*, hipStream_t);                                  \
   template void launch_vcycle_bottom<T>(const FusedLevels<T>*, size_t, int, const int*,         \
-                                        hipStream_t);                                            \
+                                        const int*, hipStream_t);                                \
   template size_t vcycle_bottom_lds_limit<T>();
 EDF_INST(double)
 EDF_INST(float)
