@@ -195,6 +195,9 @@ def main():
                     help="V-cycle precision: FP64, FP32, or FP32 with the finest matrix in FP16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--graph", action="store_true",
+                    help="capture each V-cycle launch configuration as a HIP graph and replay "
+                         "it (implies --no-profile: the roofline times single launches)")
     ap.add_argument("--forcing", type=int, default=1, choices=[0, 1],
                     help="1: Eisenstat-Walker tolerances for the Newton systems")
     ap.add_argument("--concurrent-groups", action="store_true",
@@ -244,7 +247,10 @@ def main():
                 newton_max_it=20,
                 precision={"f64": PREC_F64, "mixed": PREC_MIXED, "mixed16": PREC_MIXED_F16}[prec],
                 check_every=1,
-                forcing=args.forcing, concurrent_groups=int(args.concurrent_groups))
+                forcing=args.forcing, concurrent_groups=int(args.concurrent_groups),
+                graph_vcycle=int(args.graph))
+    if args.graph:
+        args.no_profile = True
     log(f"workload {wl.name}: groups {groups}, precision {prec}")
     t = time.perf_counter()
     pb = Problem(phys, groups, opts)
@@ -314,7 +320,8 @@ def main():
                    "lin_rtol": 1e-6, "lin_max_it": 100,
                    "forcing": "eisenstat-walker" if args.forcing else "fixed",
                    "fused_bottom_from_level": tuning,
-                   "concurrent_groups": bool(args.concurrent_groups)},
+                   "concurrent_groups": bool(args.concurrent_groups),
+                   "graph_vcycle": bool(args.graph)},
         "dof_timesteps_per_s": dofs * args.steps / el,
         "solver": {"newton_its_per_step": newton, "bicgstab_its_per_newton": lin,
                    "failed_samples_last_step": failed},

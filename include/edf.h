@@ -124,7 +124,12 @@ typedef struct {
                            /* kernels of different groups then share the GPU, which */
                            /* lengthens each one's measured duration); 0: one after */
                            /* the other                                             */
-  int32_t reserved[2];     /* must be zero                                         */
+  int32_t graph_vcycle;    /* 1: each V-cycle launch configuration is captured once  */
+                           /* as a HIP graph and replayed (same kernels, same order, */
+                           /* bitwise the same results; not while edf_profile is     */
+                           /* on, which times single launches); 0: launched one by  */
+                           /* one                                                   */
+  int32_t reserved[1];     /* must be zero                                         */
 } edf_solver_opts;
 
 typedef struct {

@@ -45,7 +45,7 @@ class SolverOpts(C.Structure):
                 ("nu_pre", C.c_int32), ("nu_post", C.c_int32), ("precision", C.c_int32),
                 ("check_every", C.c_int32), ("dt_max_halvings", C.c_int32),
                 ("forcing", C.c_int32), ("concurrent_groups", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
+                ("graph_vcycle", C.c_int32), ("reserved", C.c_int32 * 1)]
 
 
 class StepStats(C.Structure):
@@ -125,7 +125,7 @@ def _physics_c(phys: dict) -> PhysicsC:
 def default_options(**over) -> dict:
     o = dict(newton_rtol=1e-10, newton_atol=0.0, lin_rtol=1e-6, newton_max_it=20,
              ls_max_halvings=5, lin_max_it=200, nu_pre=1, nu_post=1, precision=PREC_F64,
-             check_every=4, dt_max_halvings=4, forcing=0, concurrent_groups=0)
+             check_every=4, dt_max_halvings=4, forcing=0, concurrent_groups=0, graph_vcycle=0)
     o.update(over)
     return o
 

@@ -84,6 +84,15 @@ struct Group {
   int min_fuse = 0;    // 1 when the finest level has an FP16 matrix (separate launches)
   void* fdesc = nullptr;  // device copy of the fused-bottom description (FusedLevels<T>)
   int fdesc_l0 = -1;      // the first fused level it describes (-1: not written yet)
+  // captured V-cycles (graph_vcycle): one executable graph per launch configuration
+  struct VGraph {
+    int l0, n_list, listed, zs;
+    const double* in;
+    double* out;
+    const int* mask;
+    hipGraphExec_t exec;
+  };
+  std::vector<VGraph> vgraphs;
   // the matrices are the adjoint's transposed ones: their V-cycle keeps the general
   // residual b - A x after the zero-start sweep
   bool transposed = false;
@@ -516,6 +525,54 @@ const double* stencil<double>(const Level& L) { return L.AV64 ? L.AV64 : L.A64; 
 template <>
 const float* stencil<float>(const Level& L) { return L.A32; }
 
+// the fused bottom's description for first fused level l0 (host side), and whether the
+// levels' vectors fit in the workgroup's LDS
+template <typename T>
+FusedLevels<T> fused_levels(const Group& G, int l0, size_t& lds_bytes, bool& in_lds) {
+  FusedLevels<T> F{};
+  F.n = G.L - l0;
+  F.nc = G.n_coarse;
+  F.Minv = G.Minv;
+  // the levels' x, b and r (three vectors of 2 Np_k) in LDS when they all fit
+  size_t lds_elems = 0;
+  for (int k = 0; k < F.n; ++k) {
+    const Level& L = G.lv[l0 + k];
+    F.g[k] = L.g;
+    const bool coarsest = l0 + k == G.L - 1;
+    F.A[k] = coarsest ? nullptr : stencil<T>(L);
+    F.D[k] = coarsest ? nullptr : (const T*)L.Dinv;
+    F.r[k] = coarsest ? nullptr : (T*)L.r;
+    F.b[k] = (T*)L.b;
+    F.x[k] = (T*)L.x;
+    F.lds_off[k] = (int)lds_elems;
+    lds_elems += 6 * (size_t)L.g.off[8];
+  }
+  lds_bytes = lds_elems * sizeof(T);
+  in_lds = lds_bytes <= vcycle_bottom_lds_limit<T>();
+  if (!in_lds)
+    for (int k = 0; k < F.n; ++k) F.lds_off[k] = -1;
+  return F;
+}
+
+// the device copy of the description; it changes only with the first fused level (and
+// the smoothing counts, fixed per problem)
+template <typename T>
+void ensure_fused_desc(edf_problem* pb, Group& G, int l0) {
+  if (G.fdesc_l0 == l0) return;
+  size_t lds_bytes;
+  bool in_lds;
+  FusedLevels<T> F = fused_levels<T>(G, l0, lds_bytes, in_lds);
+  F.nu1 = pb->opts.nu_pre;
+  F.nu2 = pb->opts.nu_post;
+  (void)hipMemcpyAsync(G.fdesc, &F, sizeof(F), hipMemcpyHostToDevice, G.st);
+  (void)hipStreamSynchronize(G.st);
+  G.fdesc_l0 = l0;
+}
+
+int first_fused_level(const Group& G) {
+  return G.fuse_from >= 0 ? G.fuse_from : default_fuse_from(G);
+}
+
 template <typename T>
 void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int* mask) {
   hipStream_t st = G.st;
@@ -568,7 +625,7 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
     x = l == 0 ? x0 : (T*)G.lv[l].x;
   };
   // levels from l0 on run in one fused launch (one workgroup per sample)
-  const int l0 = G.fuse_from >= 0 ? G.fuse_from : default_fuse_from(G);
+  const int l0 = first_fused_level(G);
   // every level starts from x = 0: the first forward sweep writes x at every vertex
   // without reading it, so x needs clearing only without pre-smoothing
   if (l0 > 0 && nu1 == 0) launch_fill<T>(x0, 2 * (size_t)G.lv[0].g.off[8], G.S, mask, T(0), st);
@@ -586,34 +643,10 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
     launch_restrict<T>(L.g, G.lv[l + 1].g, (const T*)L.r, bc, nu1 > 0 ? nullptr : xc, S, mask, list, st);
   }
   {
-    FusedLevels<T> F{};
-    F.n = G.L - l0;
-    F.nc = G.n_coarse;
-    F.nu1 = nu1;
-    F.nu2 = nu2;
-    F.Minv = G.Minv;
-    // the levels' x, b and r (three vectors of 2 Np_k) in LDS when they all fit
-    size_t lds_elems = 0;
-    for (int k = 0; k < F.n; ++k) {
-      const Level& L = G.lv[l0 + k];
-      F.g[k] = L.g;
-      const bool coarsest = l0 + k == G.L - 1;
-      F.A[k] = coarsest ? nullptr : stencil<T>(L);
-      F.D[k] = coarsest ? nullptr : (const T*)L.Dinv;
-      F.r[k] = coarsest ? nullptr : (T*)L.r;
-      bx(l0 + k, F.b[k], F.x[k]);
-      F.lds_off[k] = (int)lds_elems;
-      lds_elems += 6 * (size_t)L.g.off[8];
-    }
-    const size_t lds_bytes = lds_elems * sizeof(T);
-    const bool in_lds = lds_bytes <= vcycle_bottom_lds_limit<T>();
-    if (!in_lds)
-      for (int k = 0; k < F.n; ++k) F.lds_off[k] = -1;
-    if (G.fdesc_l0 != l0) {  // the description changes only with the first fused level
-      (void)hipMemcpyAsync(G.fdesc, &F, sizeof(F), hipMemcpyHostToDevice, st);
-      (void)hipStreamSynchronize(st);
-      G.fdesc_l0 = l0;
-    }
+    size_t lds_bytes = 0;
+    bool in_lds = false;
+    (void)fused_levels<T>(G, l0, lds_bytes, in_lds);
+    ensure_fused_desc<T>(pb, G, l0);  // a no-op inside a captured V-cycle (set up before)
     launch_vcycle_bottom<T>((const FusedLevels<T>*)G.fdesc, in_lds ? lds_bytes : 0, S, mask, list, st);
   }
   for (int l = l0 - 1; l >= 0; --l) {
@@ -628,10 +661,52 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
   launch_from_colour<T>(G.lv[0].g, x0, out, S, mask, list, st);
 }
 
+// The V-cycle as a captured graph: the same launches in the same order, replayed with one
+// graph launch.  A graph is captured the first time a launch configuration (first fused
+// level, number of listed samples, residual form, vectors) occurs and replayed after; the
+// kernels read the matrices, the sample list and the fused description at replay, so
+// reassembly and new lists need no new capture.  False when capturing fails (the caller
+// then runs the V-cycle eagerly).
+template <typename T>
+bool vcycle_graph(edf_problem* pb, Group& G, const double* in, double* out, const int* mask) {
+  const int l0 = first_fused_level(G);
+  ensure_fused_desc<T>(pb, G, l0);  // outside the capture: it copies and synchronises
+  const int listed = G.n_list < G.S, zs = pb->opts.nu_pre == 1 && !G.transposed;
+  for (const auto& v : G.vgraphs)
+    if (v.l0 == l0 && v.n_list == G.n_list && v.listed == listed && v.zs == zs && v.in == in &&
+        v.out == out && v.mask == mask)
+      return hipGraphLaunch(v.exec, G.st) == hipSuccess;
+  hipGraph_t graph = nullptr;
+  if (hipStreamBeginCapture(G.st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  vcycle<T>(pb, G, in, out, mask);
+  if (hipStreamEndCapture(G.st, &graph) != hipSuccess || !graph) {
+    (void)hipGetLastError();
+    return false;
+  }
+  hipGraphExec_t exec = nullptr;
+  const bool ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+  (void)hipGraphDestroy(graph);
+  if (!ok) {
+    (void)hipGetLastError();
+    return false;
+  }
+  G.vgraphs.push_back({l0, G.n_list, listed, zs, in, out, mask, exec});
+  return hipGraphLaunch(exec, G.st) == hipSuccess;
+}
+
 void precondition(edf_problem* pb, Group& G, const double* in, double* out, const int* mask) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const size_t tsz = mixed(pb) ? sizeof(float) : sizeof(double);
   const double bytes = vcycle_bytes(G, tsz, pb->opts.nu_pre, pb->opts.nu_post) * G.n_active;
+  // captured V-cycles when asked for and not profiling (the profile times single launches)
+  if (pb->opts.graph_vcycle && !G.prof_on && G.n_list > 0) {
+    if (mixed(pb) ? vcycle_graph<float>(pb, G, in, out, mask)
+                  : vcycle_graph<double>(pb, G, in, out, mask))
+      return;
+  }
   if (prof_pair(G, e0, e1, bytes, 1)) (void)hipEventRecord(e0, G.st);
   if (mixed(pb))
     vcycle<float>(pb, G, in, out, mask);
@@ -1286,8 +1361,9 @@ edf_status edf_create_problem(const edf_physics* phys, const edf_group_desc* gro
   if (opts->newton_max_it < 1 || opts->lin_max_it < 1 || opts->nu_pre < 1 || opts->nu_post < 0 ||
       opts->ls_max_halvings < 0 || !(opts->lin_rtol > 0) || !(opts->newton_rtol >= 0))
     return bad("invalid solver options");
-  for (int i = 0; i < 2; ++i)
-    if (opts->reserved[i] != 0) return bad("reserved options must be zero");
+  if (opts->reserved[0] != 0) return bad("reserved options must be zero");
+  if (opts->graph_vcycle != 0 && opts->graph_vcycle != 1)
+    return bad("graph_vcycle must be 0 or 1");
   if (opts->concurrent_groups != 0 && opts->concurrent_groups != 1)
     return bad("concurrent_groups must be 0 or 1");
   if (opts->forcing != 0 && opts->forcing != 1) return bad("forcing must be 0 or 1");
@@ -1826,6 +1902,7 @@ void edf_destroy(edf_problem* pb) {
       (void)hipStreamDestroy(G.st);
     }
     for (hipEvent_t e : G.prof_ev) (void)hipEventDestroy(e);
+    for (auto& v : G.vgraphs) (void)hipGraphExecDestroy(v.exec);
     if (G.h_int) (void)hipHostFree(G.h_int);
     if (G.h_list) (void)hipHostFree(G.h_list);
     if (G.h_dbl) (void)hipHostFree(G.h_dbl);

@@ -372,6 +372,38 @@ def _colour_counts(nx, ny, nz):
             * ((nz + 1 - (c >> 2)) // 2) for c in range(8)]
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_vcycle_gives_the_eager_result(precision):
+    """V-cycles captured as HIP graphs and replayed (graph_vcycle = 1) give bitwise the
+    states, solver counts and V-cycle outputs of the V-cycles launched one by one: three
+    steps of a mixed-resolution batch (each replaying the captured graphs many times, with
+    other launches and host synchronisations between the replays, and with the sample
+    list shrinking as samples converge), then two applications of one V-cycle."""
+    phys = synth.physics(2)
+    groups = [(17, 17, 5, 3, 3), (33, 33, 9, 4, 4)]
+    xi = _xi(2, 7, seed=23)
+    b = np.random.default_rng(9).standard_normal((4, 9, 33, 33, 2))
+    b[..., 1][:, -1] = 0.0
+    out = {}
+    for graph in (0, 1):
+        pb = _problem(phys, groups, precision=precision, graph_vcycle=graph, check_every=1,
+                      dt_max_halvings=4)
+        pb.set_parameters(xi)
+        sts = [pb.step(DT) for _ in range(3)]
+        ys = [pb.apply_vcycle(1, DT, b) for _ in range(2)]
+        out[graph] = ([pb.get_state(s) for s in range(7)],
+                      [[(x["status"], x["newton_its"], x["lin_its"], x["substeps"]) for x in st]
+                       for st in sts], ys)
+        pb.destroy()
+    print("lin its", [sum(x[2] for x in st) for st in out[1][1]], flush=True)
+    assert out[1][1] == out[0][1]
+    for s in range(7):
+        assert np.array_equal(out[1][0][s], out[0][0][s]), s
+    for y1, y0 in zip(out[1][2], out[0][2]):
+        assert np.array_equal(y1, y0)
+    assert np.array_equal(out[1][2][0], out[1][2][1])
+
+
 def test_profile_counts_launches_and_algorithmic_bytes():
     """edf_profile: every smoother launch is counted with its algorithmic bytes (118
     values per vertex of the swept colour and active sample; the first forward sweep of a
