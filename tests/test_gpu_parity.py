@@ -372,13 +372,14 @@ def _colour_counts(nx, ny, nz):
             * ((nz + 1 - (c >> 2)) // 2) for c in range(8)]
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_graph_vcycle_gives_the_eager_result(precision):
+@pytest.mark.parametrize("precision,concurrent", [(0, 0), (1, 0), (0, 1)])
+def test_graph_vcycle_gives_the_eager_result(precision, concurrent):
     """V-cycles captured as HIP graphs and replayed (graph_vcycle = 1) give bitwise the
     states, solver counts and V-cycle outputs of the V-cycles launched one by one: three
     steps of a mixed-resolution batch (each replaying the captured graphs many times, with
     other launches and host synchronisations between the replays, and with the sample
-    list shrinking as samples converge), then two applications of one V-cycle."""
+    list shrinking as samples converge), then two applications of one V-cycle; also with
+    the groups captured and replayed from their own host threads at the same time."""
     phys = synth.physics(2)
     groups = [(17, 17, 5, 3, 3), (33, 33, 9, 4, 4)]
     xi = _xi(2, 7, seed=23)
@@ -387,7 +388,7 @@ def test_graph_vcycle_gives_the_eager_result(precision):
     out = {}
     for graph in (0, 1):
         pb = _problem(phys, groups, precision=precision, graph_vcycle=graph, check_every=1,
-                      dt_max_halvings=4)
+                      dt_max_halvings=4, concurrent_groups=concurrent * graph)
         pb.set_parameters(xi)
         sts = [pb.step(DT) for _ in range(3)]
         ys = [pb.apply_vcycle(1, DT, b) for _ in range(2)]
