@@ -589,13 +589,21 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
   const bool zs_res = nu1 == 1 && !G.transposed;
   // finest level with an FP16 matrix: b0 holds D^{-1} b (only for T = float)
   const bool h0 = std::is_same<T, float>::value && G.L >= 2 && G.lv[0].A16;
+  const int l0 = first_fused_level(G);
+  // the first forward sweep from zero of colour 0 (x = D^{-1} b, no neighbours) is done by
+  // the kernel that writes the level's b: the entry permutation here, the restriction on
+  // the coarser levels swept by separate launches
+  const bool c0 = nu1 > 0;
   if constexpr (std::is_same<T, float>::value) {
     if (h0)
-      launch_to_colour_scaled(G.lv[0].g, in, (const float*)G.lv[0].Dinv, (float*)b0, S, mask, list, st);
+      launch_to_colour_scaled(G.lv[0].g, in, (const float*)G.lv[0].Dinv, (float*)b0,
+                              c0 && l0 > 0 ? (float*)x0 : nullptr, S, mask, list, st);
     else
-      launch_to_colour<T>(G.lv[0].g, in, b0, S, mask, list, st);
+      launch_to_colour<T>(G.lv[0].g, in, b0, c0 && l0 > 0 ? (const T*)G.lv[0].Dinv : nullptr,
+                          x0, S, mask, list, st);
   } else {
-    launch_to_colour<T>(G.lv[0].g, in, b0, S, mask, list, st);
+    launch_to_colour<T>(G.lv[0].g, in, b0, c0 && l0 > 0 ? (const T*)G.lv[0].Dinv : nullptr, x0,
+                        S, mask, list, st);
   }
   // zs: the first forward sweep of the level, whose x is zero on entry
   auto smooth = [&](int l, const Level& L, int c, const T* b, T* x, bool zs) {
@@ -625,7 +633,6 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
     x = l == 0 ? x0 : (T*)G.lv[l].x;
   };
   // levels from l0 on run in one fused launch (one workgroup per sample)
-  const int l0 = first_fused_level(G);
   // every level starts from x = 0: the first forward sweep writes x at every vertex
   // without reading it, so x needs clearing only without pre-smoothing
   if (l0 > 0 && nu1 == 0) launch_fill<T>(x0, 2 * (size_t)G.lv[0].g.off[8], G.S, mask, T(0), st);
@@ -634,13 +641,16 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
     T *b, *x;
     bx(l, b, x);
     for (int it = 0; it < nu1; ++it)
-      for (int c = 0; c < 8; ++c) smooth(l, L, c, b, x, it == 0);
+      for (int c = it == 0 && c0 ? 1 : 0; c < 8; ++c) smooth(l, L, c, b, x, it == 0);
     residual(l, L, b, x);
     T *bc, *xc;
     bx(l + 1, bc, xc);
-    // x of the next level needs no clearing when its first sweep starts from zero or
-    // when it is the fused bottom's first level (cleared there)
-    launch_restrict<T>(L.g, G.lv[l + 1].g, (const T*)L.r, bc, nu1 > 0 ? nullptr : xc, S, mask, list, st);
+    // x of the next level needs no clearing when its first sweep starts from zero (colour
+    // 0 of it done here) or when it is the fused bottom's first level (cleared there)
+    const bool next_swept = l + 1 < l0;
+    launch_restrict<T>(L.g, G.lv[l + 1].g, (const T*)L.r, bc,
+                       c0 ? (next_swept ? xc : nullptr) : xc,
+                       c0 && next_swept ? (const T*)G.lv[l + 1].Dinv : nullptr, S, mask, list, st);
   }
   {
     size_t lds_bytes = 0;

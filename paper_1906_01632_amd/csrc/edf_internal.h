@@ -119,10 +119,12 @@ void launch_smooth(const Geom& g, int colour, const T* A, const T* Dinv, const T
 template <typename T>
 void launch_residual(const Geom& g, const T* A, const T* b, const T* x, T* r, int S,
                      const int* mask, const int* list, hipStream_t st, bool zero_sweep = false);
-// bc = R rf (full weighting, coarse row scaling); xc, when not null, cleared
+// bc = R rf (full weighting, coarse row scaling); with Dc (the coarse block inverses) the
+// first forward sweep from zero of colour 0 into xc (x = Dc b on colour 0, the other
+// colours untouched), else xc, when not null, cleared
 template <typename T>
-void launch_restrict(const Geom& gf, const Geom& gc, const T* rf, T* bc, T* xc, int S,
-                     const int* mask, const int* list, hipStream_t st);
+void launch_restrict(const Geom& gf, const Geom& gc, const T* rf, T* bc, T* xc, const T* Dc,
+                     int S, const int* mask, const int* list, hipStream_t st);
 template <typename T>
 void launch_prolong(const Geom& gf, const Geom& gc, const T* xc, T* xf, int S, const int* mask,
                     const int* list, hipStream_t st);
@@ -141,12 +143,14 @@ void launch_residual_f16(const Geom& g, const _Float16* A16, const float* D32, c
                          const float* x, float* r, int S, const int* mask, const int* list,
                          hipStream_t st, bool zero_sweep = false);
 // entry: bh = D^{-1} b, FP64 natural [N][2] -> FP32 colour-major [Np][2]
-void launch_to_colour_scaled(const Geom& g, const double* in, const float* D32, float* out, int S,
-                             const int* mask, const int* list, hipStream_t st);
+// (x, when not null: the zero-start sweep of colour 0, x = bh there)
+void launch_to_colour_scaled(const Geom& g, const double* in, const float* D32, float* out,
+                             float* x, int S, const int* mask, const int* list, hipStream_t st);
 // finest-level V-cycle entry and exit: FP64 natural [N][2] <-> T colour-major [Np][2]
+// (D, when not null: the zero-start sweep of colour 0 into x, x = D b there)
 template <typename T>
-void launch_to_colour(const Geom& g, const double* in, T* out, int S, const int* mask,
-                      const int* list, hipStream_t st);
+void launch_to_colour(const Geom& g, const double* in, T* out, const T* D, T* x, int S,
+                      const int* mask, const int* list, hipStream_t st);
 template <typename T>
 void launch_from_colour(const Geom& g, const T* in, double* out, int S, const int* mask,
                         const int* list, hipStream_t st);

@@ -185,12 +185,27 @@ __device__ __forceinline__ void residual_after_zero_sweep(const Geom& g, int t, 
   }
 }
 
+// The first forward sweep from x = 0 of colour 0 reads no neighbour: x_v = D_v^{-1} b_v.
+// The kernel that writes b (the V-cycle entry, the restriction) does it on the spot.
+template <typename T>
+__device__ __forceinline__ void zero_start_colour0(const T* D_s, int t, typename V2<T>::type b,
+                                                   T* x_s) {
+  using T2 = typename V2<T>::type;
+  const Block2<T> d = load_block<false>(D_s + sidx<T>(t, 0, 4), 0);
+  T2 xv;
+  xv.x = d.a00 * b.x + d.a01 * b.y;
+  xv.y = d.a10 * b.x + d.a11 * b.y;
+  reinterpret_cast<T2*>(x_s)[t] = xv;
+}
+
 // restriction b_c = (1/8) P^T r_f of the scaled residual at coarse position t (the
 // 1/8 converts the fine row scaling to the coarse one: rows are scaled by
-// 1/(hx hy hz)); also clears x_c
+// 1/(hx hy hz)).  x_c: with Dc, the zero-start sweep of colour 0 (zero_start_colour0);
+// without, cleared when not null.
 template <typename T>
 __device__ __forceinline__ void restrict_vertex(const Geom& gf, const Geom& gc, int t,
-                                                const T* rf_s, T* bc_s, T* xc_s) {
+                                                const T* rf_s, T* bc_s, T* xc_s,
+                                                const T* Dc_s = nullptr) {
   using T2 = typename V2<T>::type;
   int cc, I, J, K;
   if (!colour_decode_wave(gc, t, cc, I, J, K)) return;
@@ -220,7 +235,9 @@ __device__ __forceinline__ void restrict_vertex(const Geom& gf, const Geom& gc, 
   out.x = is_pin(gc, I, J, K) ? T(0) : T(0.125) * a0;
   out.y = is_cdir(gc, I, J, K, cD) ? T(0) : T(0.125) * a1;
   reinterpret_cast<T2*>(bc_s)[t] = out;
-  if (xc_s) {  // the coarse correction starts from zero
+  if (Dc_s) {
+    if (cc == 0) zero_start_colour0<T>(Dc_s, t, out, xc_s);
+  } else if (xc_s) {  // the coarse correction starts from zero
     T2 z;
     z.x = 0;
     z.y = 0;
@@ -354,20 +371,25 @@ void launch_residual(const Geom& g, const T* A, const T* b, const T* x, T* r, in
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, const T* rf_all, T* bc_all,
-                                                     T* xc_all, const int* mask, const int* list) {
+                                                     T* xc_all, const T* Dc_all, const int* mask,
+                                                     const int* list) {
   const int s = list ? list[blockIdx.y] : blockIdx.y;
   if (mask && !mask[s]) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= gc.off[8]) return;
+  // x_c and D_c are optional: offset them only when given
   restrict_vertex<T>(gf, gc, t, rf_all + (size_t)s * 2 * gf.off[8],
-                     bc_all + (size_t)s * 2 * gc.off[8], xc_all + (size_t)s * 2 * gc.off[8]);
+                     bc_all + (size_t)s * 2 * gc.off[8],
+                     xc_all ? xc_all + (size_t)s * 2 * gc.off[8] : nullptr,
+                     Dc_all ? Dc_all + (size_t)s * 4 * gc.off[8] : nullptr);
 }
 
 template <typename T>
-void launch_restrict(const Geom& gf, const Geom& gc, const T* rf, T* bc, T* xc, int S,
-                     const int* mask, const int* list, hipStream_t st) {
+void launch_restrict(const Geom& gf, const Geom& gc, const T* rf, T* bc, T* xc, const T* Dc,
+                     int S, const int* mask, const int* list, hipStream_t st) {
   dim3 grid(ceil_div(gc.off[8], kBlock), S);
-  hipLaunchKernelGGL(k_restrict<T>, grid, dim3(kBlock), 0, st, gf, gc, rf, bc, xc, mask, list);
+  hipLaunchKernelGGL(k_restrict<T>, grid, dim3(kBlock), 0, st, gf, gc, rf, bc, xc, Dc, mask,
+                     list);
 }
 
 template <typename T>
@@ -625,7 +647,8 @@ void launch_residual_f16(const Geom& g, const _Float16* A16, const float* D32, c
 
 __global__ __launch_bounds__(kBlock) void k_to_colour_scaled(Geom g, const double* in_all,
                                                              const float* D_all, float* out_all,
-                                                             const int* mask, const int* list) {
+                                                             float* x_all, const int* mask,
+                                                             const int* list) {
   const int s = list ? list[blockIdx.y] : blockIdx.y;
   if (mask && !mask[s]) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -638,14 +661,17 @@ __global__ __launch_bounds__(kBlock) void k_to_colour_scaled(Geom g, const doubl
                d11 = d[soff<float>(3)];
   const double det = d00 * d11 - d01 * d10;
   const double id = det != 0.0 ? 1.0 / det : 0.0;
-  reinterpret_cast<float2*>(out_all)[(size_t)s * g.off[8] + t] =
+  const float2 bh =
       make_float2((float)((d11 * b.x - d01 * b.y) * id), (float)((d00 * b.y - d10 * b.x) * id));
+  reinterpret_cast<float2*>(out_all)[(size_t)s * g.off[8] + t] = bh;
+  // the zero-start sweep of colour 0 with the unit-diagonal FP16 matrix: x = bh
+  if (x_all && col == 0) reinterpret_cast<float2*>(x_all)[(size_t)s * g.off[8] + t] = bh;
 }
 
-void launch_to_colour_scaled(const Geom& g, const double* in, const float* D32, float* out, int S,
-                             const int* mask, const int* list, hipStream_t st) {
+void launch_to_colour_scaled(const Geom& g, const double* in, const float* D32, float* out,
+                             float* x, int S, const int* mask, const int* list, hipStream_t st) {
   hipLaunchKernelGGL(k_to_colour_scaled, dim3(ceil_div(g.off[8], kBlock), S), dim3(kBlock), 0, st,
-                     g, in, D32, out, mask, list);
+                     g, in, D32, out, x, mask, list);
 }
 
 // ---------------------------------------------------------------------------
@@ -672,7 +698,8 @@ void launch_fill(T* x, size_t per_sample, int S, const int* mask, T value, hipSt
 // order [N][2]) to and from the V-cycle vectors (T, colour-major [Np][2])
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_to_colour(Geom g, const double* in_all, T* out_all,
-                                                      const int* mask, const int* list) {
+                                                      const T* D_all, T* x_all, const int* mask,
+                                                      const int* list) {
   const int s = list ? list[blockIdx.y] : blockIdx.y;
   if (mask && !mask[s]) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -684,6 +711,8 @@ __global__ __launch_bounds__(kBlock) void k_to_colour(Geom g, const double* in_a
   b.x = (T)a.x;
   b.y = (T)a.y;
   reinterpret_cast<typename V2<T>::type*>(out_all)[(size_t)s * g.off[8] + t] = b;
+  if (D_all && col == 0)
+    zero_start_colour0<T>(D_all + (size_t)s * 4 * g.off[8], t, b, x_all + (size_t)s * 2 * g.off[8]);
 }
 
 template <typename T>
@@ -701,10 +730,10 @@ __global__ __launch_bounds__(kBlock) void k_from_colour(Geom g, const T* in_all,
 }
 
 template <typename T>
-void launch_to_colour(const Geom& g, const double* in, T* out, int S, const int* mask,
-                      const int* list, hipStream_t st) {
+void launch_to_colour(const Geom& g, const double* in, T* out, const T* D, T* x, int S,
+                      const int* mask, const int* list, hipStream_t st) {
   hipLaunchKernelGGL(k_to_colour<T>, dim3(ceil_div(g.off[8], kBlock), S), dim3(kBlock), 0, st, g,
-                     in, out, mask, list);
+                     in, out, D, x, mask, list);
 }
 
 template <typename T>
@@ -973,13 +1002,13 @@ void launch_vcycle_bottom(const FusedLevels<T>* F, size_t lds_bytes, int S, cons
                                  bool);                                                          \
   template void launch_residual<T>(const Geom&, const T*, const T*, const T*, T*, int,           \
                                    const int*, const int*, hipStream_t, bool);                   \
-  template void launch_restrict<T>(const Geom&, const Geom&, const T*, T*, T*, int, const int*,  \
-                                   const int*, hipStream_t);                                     \
+  template void launch_restrict<T>(const Geom&, const Geom&, const T*, T*, T*, const T*, int,    \
+                                   const int*, const int*, hipStream_t);                         \
   template void launch_prolong<T>(const Geom&, const Geom&, const T*, T*, int, const int*,       \
                                   const int*, hipStream_t);                                      \
   template void launch_fill<T>(T*, size_t, int, const int*, T, hipStream_t);                     \
-  template void launch_to_colour<T>(const Geom&, const double*, T*, int, const int*,             \
-                                    const int*, hipStream_t);                                    \
+  template void launch_to_colour<T>(const Geom&, const double*, T*, const T*, T*, int,           \
+                                    const int*, const int*, hipStream_t);                        \
   template void launch_from_colour<T>(const Geom&, const T*, double*, int, const int*,           \
                                       const int*, hipStream_t);                                  \
   template void launch_vcycle_bottom<T>(const FusedLevels<T>*, size_t, int, const int*,         \
