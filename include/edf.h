@@ -277,10 +277,16 @@ edf_status edf_apply_jacobian(edf_problem* pb, int32_t group, const double* x, d
  * out[6..7] = all smoother launches and their algorithmic bytes.
  * Smoother bytes per vertex of the swept colour and per active sample: 108 stencil +
  * 4 block-inverse entries + 2 right-hand side + 4 own-unknown reads and writes, times
- * the V-cycle precision.  V-cycle bytes per active sample: on every smoothed level
- * N_l ((s + 1) 108 + 4 s + 2 (3 s + 6)) values with s = nu_pre + nu_post (s sweeps and
- * the residual, s block-inverse reads, the vector passes) plus the dense coarse
- * inverse.  Synchronises the streams. */
+ * the V-cycle precision; the first forward sweep of a level starts from x = 0 and reads
+ * only the 4 n_c stencil values towards the colours already swept (n_c = 0, 2, 6, 8, 18,
+ * 20, 24, 26 for colours 0..7; colour 0 is done by the kernel that writes b, not by a
+ * smoother launch), the block inverse and b, and writes x.  V-cycle bytes per active
+ * sample: on every smoothed level its nu_pre + nu_post sweeps (the first from zero),
+ * the residual (108 stencil values, b, x in, r out; after a single pre-smoothing sweep
+ * only the 4 (26 - n_c) values towards the later colours and r out), r into the
+ * restriction and x in and out for the correction, plus the dense coarse inverse.
+ * Launches run over the samples still active in their BiCGStab.  Synchronises the
+ * streams. */
 edf_status edf_profile(edf_problem* pb, int32_t enable, double* out);
 
 /* Autotuning of the V-cycle (an implementation choice, not part of the method): the
