@@ -129,19 +129,58 @@ typedef struct {
                            /* bitwise the same results; not while edf_profile is     */
                            /* on, which times single launches); 0: launched one by  */
                            /* one                                                   */
-  int32_t reserved[1];     /* must be zero                                         */
+  int32_t substep_memory;  /* 0: every step first tries the full step length (so a  */
+                           /* step that converges is exactly one implicit-Euler     */
+                           /* step); 1: a sample starts a step with the number of   */
+                           /* sub-steps that worked for it in its previous step     */
+                           /* (fewer failed attempts, but the result then depends  */
+                           /* on the sample's history; see edf_step)                */
+  int32_t reserved[3];     /* must be zero                                         */
 } edf_solver_opts;
 
+/* Per-sample result of a step.  Counters named *_total run over every step since the
+ * sample was created or last given a state with edf_set_state. */
 typedef struct {
-  int32_t status;       /* EDF_SAMPLE_*                                            */
-  int32_t newton_its;   /* Newton iterations of the last step (all attempts)       */
-  int32_t lin_its;      /* BiCGStab iterations summed over those Newton iterations */
-  int32_t ls_halvings;  /* line-search halvings summed over them                   */
-  int32_t substeps;     /* the step was taken as this many equal sub-steps (2^h)   */
+  int32_t status;       /* EDF_SAMPLE_* of this step.  A sample whose step failed keeps */
+                        /* that status and its last good state in every later step: */
+                        /* it is not advanced again and is left out of the           */
+                        /* statistics until edf_set_state gives it a new state       */
+  int32_t newton_its;   /* Newton iterations of this step (all attempts)            */
+  int32_t lin_its;      /* BiCGStab iterations summed over those Newton iterations  */
+  int32_t ls_halvings;  /* line-search halvings summed over them                    */
+  int32_t substeps;     /* this step was taken as this many equal sub-steps (2^h)   */
+  int32_t retries;      /* attempts of this step that failed and were restarted     */
+                        /* with twice as many sub-steps                              */
+  int32_t steps_total;    /* steps completed                                        */
+  int32_t split_total;    /* of those, steps taken as more than one sub-step        */
+  int32_t substeps_total; /* implicit-Euler sub-steps completed                     */
+  int32_t retries_total;  /* failed and restarted attempts                          */
+  int32_t failed_step;    /* steps_total + 1 at the step that failed; 0: none       */
   int32_t reserved;
   double defect0;       /* ||F~|| at the start of the step (full step length)      */
   double defect;        /* ||F~|| at the end of the last sub-step                  */
+  /* Global conservation over this step, computed in FP64 on the device from the     */
+  /* states and the boundary rows (eqs. e_cont_eq and e_tran_eq summed over all      */
+  /* control volumes: interior face fluxes cancel in pairs and no-flow faces carry   */
+  /* none, so the change of the mass in the box equals what the Dirichlet vertices   */
+  /* exchange).  Salt: dM = sum_v m_v [rho(c) c - rho(c_old) c_old] over all          */
+  /* vertices and sub-steps, B = sum over sub-steps of dt_sub * (finite-volume salt   */
+  /* row at the c-Dirichlet vertices); liquid: dM = sum_v m_v [rho(c) - rho(c_old)], */
+  /* B = dt_sub * (finite-volume liquid row at the p-pinned vertices).  The error is  */
+  /* |dM - B| / (sum_v |m_v [..] change| + |B|) (0 when both are 0): the residual  */
+  /* left in the solved rows, relative to the mass moved.  0 for a failed step.      */
+  double salt_balance_err;
+  double liquid_balance_err;
 } edf_step_stats;
+
+/* Quantity of interest of the adjoint (kind 0, the only kind): the salt mass in the
+ * box [box[0],box[1]] x [box[2],box[3]] x [box[4],box[5]] (SI units, z = depth) at the
+ * final time. */
+typedef struct {
+  double box[6];
+  int32_t kind;
+  int32_t reserved;
+} edf_qoi;
 
 /* Creates a problem.  groups[n_groups] describe the resolution groups; every sample
  * starts from the initial state (pure water, p = rho0 g z, c = 1 on the patch).
@@ -154,32 +193,49 @@ edf_status edf_create_problem(const edf_physics* phys, const edf_group_desc* gro
 /* Sets the porosity/permeability parameters of every sample: xi is a host array
  * [S_total][phys.n_xi], row-major.  Computes phi and K on every grid level
  * (Section 2.2).  EDF_ERR_ARG if some |xi| > 1 or a resulting phi is not in (0,1)
- * or K is not finite and positive. */
+ * or K is not finite and positive; the fields are checked on every level before any
+ * is written, so the problem keeps its previous parameters then.  Clears every
+ * sample's sub-step history (opts.substep_memory), and any trajectory that
+ * edf_solve recorded for edf_adjoint. */
 edf_status edf_set_parameters(edf_problem* pb, const double* xi);
 
 /* Copies a state [N][2] (p, c) of one sample in or out; the array is in host memory
  * (is_device_ptr = 0) or device memory (1).  set_state also sets the previous-step
- * state to the same values. */
+ * state to the same values, and resets the sample: a failure of an earlier step is
+ * cleared (the sample is advanced again and counted in the statistics), its
+ * sub-step history and its *_total counters start afresh, and any recorded trajectory
+ * is dropped. */
 edf_status edf_set_state(edf_problem* pb, int32_t sample, const double* pc, int32_t is_device_ptr);
 edf_status edf_get_state(edf_problem* pb, int32_t sample, double* pc, int32_t is_device_ptr);
 
-/* Exactly one implicit-Euler step of length dt [s] for every sample (Section 2.3),
- * taken as 2^h equal implicit-Euler sub-steps of dt / 2^h (stats.substeps = 2^h).
- * h starts at the value that worked for the sample in its previous step (0 at
- * first; lowered by one after w steps without a retry, where w = 3 and doubles, up
- * to 64, whenever such a lowered start fails).  A sample whose Newton
- * iteration fails (iteration limit, no 100-fold residual reduction after 8
- * iterations, a non-finite or 1e4-fold grown residual, a converged state with c
- * outside [-0.05, 1.05], or, while h < opts.dt_max_halvings, a Newton system whose
- * BiCGStab residual ended above twice its tolerance) restarts the step from its state at the
- * start of the call
- * with h raised by one, up to opts.dt_max_halvings; after that its status is the
- * failure and its state is left unchanged.  stats, if not NULL, is a host array
- * [S_total].  Synchronises. */
+/* One time step of length dt [s] for every sample that has not failed (Section 2.3).
+ * With opts.substep_memory = 0 the step is one implicit-Euler step whenever Newton
+ * converges at the full length; only a sample whose attempt fails (iteration limit,
+ * no 100-fold residual reduction after 8 iterations, a non-finite or 1e4-fold grown
+ * residual, a converged state with c outside [-0.05, 1.05], or, while h <
+ * opts.dt_max_halvings, a Newton system whose BiCGStab residual ended above twice its
+ * tolerance) restarts the step from its state at the start of the call as 2^h equal
+ * implicit-Euler sub-steps of dt / 2^h with h raised by one (stats.substeps = 2^h,
+ * stats.retries counts the restarts), up to opts.dt_max_halvings.  With
+ * opts.substep_memory = 1, h starts at the value that worked for the sample in its
+ * previous step (lowered by one after w steps without a restart, where w = 3 and
+ * doubles, up to 64, whenever such a lowered start fails).  A sample that still fails
+ * at h = dt_max_halvings keeps its state from the start of the call and is marked
+ * failed: later steps leave it alone (stats.status keeps the failure) until
+ * edf_set_state resets it.  stats, if not NULL, is a host array [S_total], including
+ * the FP64 mass-balance errors of the step.  EDF_ERR_NO_CONVERGENCE when no sample is
+ * left that has not failed.  Synchronises. */
 edf_status edf_step(edf_problem* pb, double dt, edf_step_stats* stats);
 
-/* n_steps steps of length dt; stats (host [S_total] or NULL) describe the last step. */
-edf_status edf_solve(edf_problem* pb, double dt, int32_t n_steps, edf_step_stats* stats);
+/* n_steps steps of length dt, as edf_step; stats (host [S_total] or NULL) describe the
+ * last step.  checkpoint_every = k > 0 records the trajectory for edf_adjoint: every
+ * sample's state at steps 0, k, 2k, ... (before each segment of k steps) and the
+ * sub-step count of every step, in library-owned device memory of
+ * (ceil(n_steps / k) + 1) + (k + 1) states per sample (the second part holds the
+ * states of one segment while the adjoint recomputes it).  checkpoint_every = 0
+ * records nothing.  EDF_ERR_ARG for n_steps < 0 or checkpoint_every < 0. */
+edf_status edf_solve(edf_problem* pb, double dt, int32_t n_steps, int32_t checkpoint_every,
+                     edf_step_stats* stats);
 
 /* Weighted statistics of c over the samples (eqs. pdestat, numer_var; Section 3.2):
  * mean = sum w_i c_i, var = sum w_i (c_i - mean)^2, exceed = sum w_i [c_i > threshold].
@@ -187,8 +243,8 @@ edf_status edf_solve(edf_problem* pb, double dt, int32_t n_steps, edf_step_stats
  * in every group's grid.  weights: host [S_total] or NULL for 1/S_total; they are divided
  * by their sum, which must be positive, and may be signed (a multilevel estimator gives
  * the coarse partners of a level negative weights: var is then sum w c^2 - mean^2 and
- * may dip below zero).  Samples whose last step failed are left out and the weights of
- * the others renormalised.
+ * may dip below zero).  Samples that have failed (edf_step) are left out and the weights
+ * of the others renormalised.
  * mean, var, exceed: host arrays [cx*cy*cz].  Synchronises. */
 edf_status edf_moments(edf_problem* pb, int32_t cx, int32_t cy, int32_t cz, double threshold,
                        const double* weights, double* mean, double* var, double* exceed);
@@ -207,7 +263,9 @@ edf_status edf_moments(edf_problem* pb, int32_t cx, int32_t cy, int32_t cz, doub
  *   Q_beta = prod_j 1/(2 beta_j + 1);  mean = c_0;  var = sum_{beta != 0} Q_beta c_beta^2.
  * Outputs: *n_coef; coef (host [n_coef][cz][cy][cx] or NULL); mean, var (host
  * [cz][cy][cx]); kernel_ms (or NULL): duration of the projection kernel.  The
- * coefficients stay in the problem for edf_gpc_exceed.  Synchronises. */
+ * coefficients stay in the problem for edf_gpc_exceed.  Samples that have failed
+ * (edf_step) are left out and the weights of the others renormalised to their sum.
+ * Synchronises. */
 edf_status edf_gpc_project(edf_problem* pb, int32_t group, int32_t cx, int32_t cy, int32_t cz,
                            int32_t degree, int32_t truncation, const double* weights,
                            int32_t* n_coef, double* coef, double* mean, double* var,
@@ -225,21 +283,23 @@ edf_status edf_gpc_exceed(edf_problem* pb, int32_t n_points, const double* theta
                           double* prob, double* kernel_ms);
 
 /* Discrete adjoint (the gradient of a quantity of interest with respect to the field
- * parameters xi).  Runs n_steps implicit-Euler steps of length dt from the current
- * states (as edf_step, keeping a checkpoint at the start of every step; steps that
- * were split into sub-steps are recomputed from their checkpoint), then the adjoint
- * equations backwards: per step one BiCGStab solve with the transposed Jacobian,
+ * parameters xi) of the trajectory recorded by the last edf_solve with
+ * checkpoint_every = k > 0.  The adjoint equations run backwards through the steps:
+ * per implicit-Euler sub-step one BiCGStab solve with the transposed Jacobian,
  * preconditioned by the multigrid V-cycle of the transposed (frozen-flux) matrices.
- * The quantity is the salt mass in the box [box[0],box[1]] x [box[2],box[3]] x
- * [box[4],box[5]] (z = depth) at the final time,
+ * The states inside each segment of k steps are recomputed from the segment's
+ * checkpoint (the forward kernels give the same states bitwise; the recorded sub-step
+ * counts are replayed), one segment at a time from the last.  The quantity (edf_qoi,
+ * kind 0) is the salt mass in the box at the final time,
  *   J = sum_v sum_{e adjacent to v} phi_e |octant(e, v) ∩ box| rho(c_v) c_v,
  * the mass density phi rho c of eq. e_tran_eq integrated over the box with the
- * control volumes of the scheme.  Outputs (host): J[S_total], dJ_dxi[S_total][n_xi].
- * The states are left at the final time.  Needs a field model with parameters.
- * EDF_ERR_NO_CONVERGENCE if a forward step or an adjoint solve of some sample fails.
+ * control volumes of the scheme.  Outputs (host): J[S_total], dJ_dxi[S_total][n_xi]
+ * (NaN for a sample that failed during the recorded steps).  The states stay at the
+ * final time.  Needs a field model with parameters.  EDF_ERR_STATE without a recorded
+ * trajectory (or after edf_step, edf_set_state or edf_set_parameters changed the
+ * states or parameters since); EDF_ERR_NO_CONVERGENCE if an adjoint solve fails.
  * Uses opts.lin_rtol as the relative tolerance of the adjoint solves.  Synchronises. */
-edf_status edf_adjoint(edf_problem* pb, const double* box, double dt, int32_t n_steps, double* J,
-                       double* dJ_dxi);
+edf_status edf_adjoint(edf_problem* pb, const edf_qoi* qoi, double* J, double* dJ_dxi);
 
 /* Inspection entry points used by the parity tests. */
 

@@ -305,6 +305,37 @@ def jacobian(box: Box, coef, u, dt):
 
 
 # ---------------------------------------------------------------------------
+# Global conservation of one step (eqs. e_cont_eq and e_tran_eq summed over the box)
+# ---------------------------------------------------------------------------
+
+def mass_balance(box: Box, coef, u, u_old, dt):
+    """Salt and liquid mass balance of one implicit-Euler step from u_old to u.
+
+    Summing the FV rows (R9) over all vertices, every interior SCVF flux appears once
+    with each sign and no-flow faces carry none, so the storage change of the whole box
+    equals dt times the rows of the vertices whose equation is a Dirichlet condition
+    (the boundary exchange): salt rows at the c-Dirichlet vertices, liquid rows at the
+    pinned vertices.  Returns, per equation, the storage change dM, the sum of the
+    vertices' absolute storage changes, the exchange B and the relative error
+    |dM - B| / (sum |storage change| + |B|) (0 when both vanish)."""
+    ph = box.phys
+    Fl, Fs = fv_rows(box, coef, u, u_old, dt)
+    m = storage_weight(box, coef[0])
+    c, co = u[..., 1], u_old[..., 1]
+    Ss = m * (_rho(c, ph) * c - _rho(co, ph) * co)
+    Sl = m * (_rho(c, ph) - _rho(co, ph))
+    cmask, _ = box.dirichlet_c()
+    pmask = box.pinned_p()
+    out = {}
+    for name, S, F, mask in (("salt", Ss, Fs, cmask), ("liquid", Sl, Fl, pmask)):
+        dM, gross, B = float(S.sum()), float(np.abs(S).sum()), float(dt * F[mask].sum())
+        den = gross + abs(B)
+        out[name] = {"dM": dM, "gross": gross, "B": B,
+                     "err": abs(dM - B) / den if den > 0 else 0.0}
+    return out
+
+
+# ---------------------------------------------------------------------------
 # Scaling used for norms (a dimensionless "change of c per step" for FV rows)
 # ---------------------------------------------------------------------------
 

@@ -45,16 +45,25 @@ class SolverOpts(C.Structure):
                 ("nu_pre", C.c_int32), ("nu_post", C.c_int32), ("precision", C.c_int32),
                 ("check_every", C.c_int32), ("dt_max_halvings", C.c_int32),
                 ("forcing", C.c_int32), ("concurrent_groups", C.c_int32),
-                ("graph_vcycle", C.c_int32), ("reserved", C.c_int32 * 1)]
+                ("graph_vcycle", C.c_int32), ("substep_memory", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
 
 
 class StepStats(C.Structure):
     _fields_ = [("status", C.c_int32), ("newton_its", C.c_int32), ("lin_its", C.c_int32),
-                ("ls_halvings", C.c_int32), ("substeps", C.c_int32), ("reserved", C.c_int32),
-                ("defect0", C.c_double), ("defect", C.c_double)]
+                ("ls_halvings", C.c_int32), ("substeps", C.c_int32), ("retries", C.c_int32),
+                ("steps_total", C.c_int32), ("split_total", C.c_int32),
+                ("substeps_total", C.c_int32), ("retries_total", C.c_int32),
+                ("failed_step", C.c_int32), ("reserved", C.c_int32),
+                ("defect0", C.c_double), ("defect", C.c_double),
+                ("salt_balance_err", C.c_double), ("liquid_balance_err", C.c_double)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class QoiC(C.Structure):
+    _fields_ = [("box", C.c_double * 6), ("kind", C.c_int32), ("reserved", C.c_int32)]
 
 
 _lib = None
@@ -68,13 +77,13 @@ _SIGS = {
     "edf_set_state": [_P, C.c_int32, C.c_void_p, C.c_int32],
     "edf_get_state": [_P, C.c_int32, C.c_void_p, C.c_int32],
     "edf_step": [_P, C.c_double, C.POINTER(StepStats)],
-    "edf_solve": [_P, C.c_double, C.c_int32, C.POINTER(StepStats)],
+    "edf_solve": [_P, C.c_double, C.c_int32, C.c_int32, C.POINTER(StepStats)],
     "edf_moments": [_P, C.c_int32, C.c_int32, C.c_int32, C.c_double, _D, _D, _D, _D],
     "edf_residual": [_P, C.c_int32, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_int32],
     "edf_get_jacobian": [_P, C.c_int32, _D, C.c_double, C.c_int32, _D],
     "edf_apply_vcycle": [_P, C.c_int32, C.c_double, _D, _D],
     "edf_apply_jacobian": [_P, C.c_int32, _D, _D],
-    "edf_adjoint": [_P, _D, C.c_double, C.c_int32, _D, _D],
+    "edf_adjoint": [_P, C.POINTER(QoiC), _D, _D],
     "edf_gpc_project": [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _D,
                         C.POINTER(C.c_int32), _D, _D, _D, _D],
     "edf_gpc_exceed": [_P, C.c_int32, _D, C.c_double, _D, _D],
@@ -125,7 +134,8 @@ def _physics_c(phys: dict) -> PhysicsC:
 def default_options(**over) -> dict:
     o = dict(newton_rtol=1e-10, newton_atol=0.0, lin_rtol=1e-6, newton_max_it=20,
              ls_max_halvings=5, lin_max_it=200, nu_pre=1, nu_post=1, precision=PREC_F64,
-             check_every=4, dt_max_halvings=4, forcing=0, concurrent_groups=0, graph_vcycle=0)
+             check_every=4, dt_max_halvings=4, forcing=0, concurrent_groups=0, graph_vcycle=0,
+             substep_memory=0)
     o.update(over)
     return o
 
@@ -209,9 +219,12 @@ class Problem:
         self._check(self._lib.edf_step(self._h, float(dt), st))
         return [s.as_dict() for s in st]
 
-    def solve(self, dt: float, n_steps: int, stats: bool = True):
+    def solve(self, dt: float, n_steps: int, checkpoint_every: int = 0, stats: bool = True):
+        """n_steps steps (edf_solve); checkpoint_every > 0 records the trajectory for
+        adjoint().  Returns the last step's statistics."""
         st = (StepStats * self.S)() if stats else None
-        self._check(self._lib.edf_solve(self._h, float(dt), int(n_steps), st))
+        self._check(self._lib.edf_solve(self._h, float(dt), int(n_steps), int(checkpoint_every),
+                                        st))
         return [s.as_dict() for s in st] if stats else None
 
     def moments(self, common, threshold=0.5, weights=None):
@@ -263,15 +276,23 @@ class Problem:
                                              _dptr(prob), C.cast(C.pointer(ms), _D)))
         return prob.reshape(cz, cy, cx), ms.value
 
-    def adjoint(self, box, dt: float, n_steps: int):
-        """Salt mass J in `box` (x0, x1, y0, y1, z0, z1) after n_steps steps and dJ/dxi,
-        by the discrete adjoint (edf_adjoint).  Returns (J [S], dJ [S, n_xi])."""
-        b = np.ascontiguousarray(np.asarray(box, dtype=np.float64))
+    def adjoint(self, box):
+        """Salt mass J in `box` (x0, x1, y0, y1, z0, z1) at the end of the trajectory
+        recorded by the last solve(..., checkpoint_every > 0), and dJ/dxi by the discrete
+        adjoint (edf_adjoint).  Returns (J [S], dJ [S, n_xi])."""
+        q = QoiC()
+        for i, v in enumerate(box):
+            q.box[i] = float(v)
         J = np.empty(self.S)
         g = np.empty((self.S, self.n_xi))
-        self._check(self._lib.edf_adjoint(self._h, _dptr(b), float(dt), int(n_steps), _dptr(J),
-                                          _dptr(g)))
+        self._check(self._lib.edf_adjoint(self._h, C.byref(q), _dptr(J), _dptr(g)))
         return J, g
+
+    def gradient(self, box, dt: float, n_steps: int, checkpoint_every: int = 10):
+        """solve() with checkpoints, then adjoint(): (J, dJ/dxi) after n_steps steps."""
+        self.solve(dt, n_steps, checkpoint_every=min(max(1, checkpoint_every), max(n_steps, 1)),
+                   stats=False)
+        return self.adjoint(box)
 
     def residual(self, sample: int, u, u_old, dt: float):
         a = np.ascontiguousarray(np.asarray(u, dtype=np.float64).reshape(-1))

@@ -1,13 +1,15 @@
 """The library's discrete adjoint behind torch.autograd.
 
-ElderQoI.apply(xi, problem, box, dt, n_steps) returns, per sample, the salt mass in
-`box` after n_steps implicit-Euler steps of length dt from the problem's current
+ElderQoI.apply(xi, problem, box, dt, n_steps, checkpoint_every) returns, per sample, the
+salt mass in `box` after n_steps time steps of length dt from the problem's current
 states, with the porosity/permeability parameters xi [S_total, n_xi]; its backward
 multiplies the incoming gradient by dJ/dxi from edf_adjoint (one backward sweep with
-transposed-Jacobian multigrid solves).  Both values come from the same library call
-in forward.  The problem's states are restored after the call, so J is a function of
-xi alone for a fixed starting state.  Marshalling only: the time stepping and the
-adjoint run in the library's kernels.
+transposed-Jacobian multigrid solves over the trajectory that edf_solve recorded with a
+checkpoint every `checkpoint_every` steps).  Both values are computed in forward.
+edf_set_parameters clears the samples' sub-step history and the problem's states are
+restored (edf_set_state) after the call, so J is a function of xi alone for a fixed
+starting state.  Marshalling only: the time stepping and the adjoint run in the
+library's kernels.
 """
 import numpy as np
 import torch
@@ -15,12 +17,12 @@ import torch
 
 class ElderQoI(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, xi, problem, box, dt, n_steps):
+    def forward(ctx, xi, problem, box, dt, n_steps, checkpoint_every=10):
         x = xi.detach().to("cpu", torch.float64).numpy()
         saved = [problem.get_state(s) for s in range(problem.S)]
         try:
             problem.set_parameters(x)
-            J, dJ = problem.adjoint(box, dt, n_steps)
+            J, dJ = problem.gradient(box, dt, n_steps, checkpoint_every)
         finally:
             for s, u in enumerate(saved):
                 problem.set_state(s, u)
@@ -30,9 +32,9 @@ class ElderQoI(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_J):
         (dJ,) = ctx.saved_tensors
-        return grad_J[:, None] * dJ, None, None, None, None
+        return grad_J[:, None] * dJ, None, None, None, None, None
 
 
-def salt_mass(xi, problem, box, dt, n_steps):
+def salt_mass(xi, problem, box, dt, n_steps, checkpoint_every=10):
     """J(xi) [S_total] as a differentiable torch function (see ElderQoI)."""
-    return ElderQoI.apply(xi, problem, box, dt, n_steps)
+    return ElderQoI.apply(xi, problem, box, dt, n_steps, checkpoint_every)

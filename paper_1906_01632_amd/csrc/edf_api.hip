@@ -99,10 +99,21 @@ struct Group {
   std::vector<double> tune_ms;  // V-cycle time per candidate fuse_from (autotuning)
   // per sample: halvings to start the next step with, steps since the last retry,
   // steps to wait before trying one halving less, whether this step is such a try
+  // (opts.substep_memory)
   std::vector<int> h_start, clean, wait, probing;
-  // adjoint buffers (allocated on first use)
-  double* traj = nullptr;      // [S][traj_cap][n]: states at the start of every step
-  size_t traj_cap = 0;
+  // per sample: the failure status of the step that failed (EDF_SAMPLE_OK: none); a
+  // failed sample is not advanced again until edf_set_state resets it
+  std::vector<int> fail_status;
+  // FP64 mass balance of the current step: accumulators [S][8] and block partials
+  double* bal = nullptr;
+  double* bal_part = nullptr;
+  // trajectory recorded by edf_solve for edf_adjoint (allocated on first use)
+  double* ckpt = nullptr;      // [S][ckpt_cap][n]: states at steps 0, k, 2k, ... and the last
+  size_t ckpt_cap = 0;
+  double* seg = nullptr;       // [S][seg_cap][n]: the states of one segment of k steps
+  size_t seg_cap = 0;
+  std::vector<std::vector<int>> H;  // [step][S]: halvings of every recorded step
+  std::vector<int> traj_fail;       // [S]: the sample failed during the recorded steps
   double* sub = nullptr;       // [S][sub_cap][n]: the sub-step states of one step
   size_t sub_cap = 0;
   double* lam_next = nullptr;  // [S][n]
@@ -134,6 +145,15 @@ struct edf_problem {
   size_t gpc_icap = 0;
   double* gpc_pts = nullptr;  // exceedance points [Ns][M], then probabilities [Nc]
   size_t gpc_pcap = 0;
+  // the trajectory of the last edf_solve with checkpoint_every > 0, valid until a step,
+  // a new state or new parameters change it
+  bool traj_valid = false;
+  int traj_k = 0, traj_n = 0;
+  double traj_dt = 0.0;
+  // staging for edf_set_parameters: the new parameters are checked before they replace
+  // the current ones
+  double* dxi_new = nullptr;
+  int* bad = nullptr;  // [S_total] flags of the check
   // statistics buffers (allocated on first use)
   double* mom_f = nullptr;
   double* mom_w = nullptr;
@@ -246,6 +266,16 @@ bool f16_finest(const edf_problem* pb, const Group& G) {
   return pb->opts.precision == EDF_PREC_MIXED_F16 && G.L >= 2;
 }
 
+constexpr int kFirstWait = 3, kMaxWait = 64;
+
+// forget every sample's sub-step history (opts.substep_memory)
+void reset_history(Group& G) {
+  G.h_start.assign(G.S, 0);
+  G.clean.assign(G.S, 0);
+  G.wait.assign(G.S, kFirstWait);
+  G.probing.assign(G.S, 0);
+}
+
 // ---------------------------------------------------------------------------
 // allocation of one group
 // ---------------------------------------------------------------------------
@@ -322,7 +352,11 @@ edf_status alloc_group(edf_problem* pb, Group& G) {
   if ((s = dalloc(pb, &G.Minv, S * nc * nc))) return s;
   if ((s = dalloc(pb, &G.piv, S * nc))) return s;
   if ((s = dalloc(pb, &G.gj_status, (size_t)S))) return s;
+  if ((s = dalloc(pb, &G.bal, 8 * (size_t)S))) return s;
+  if ((s = dalloc(pb, &G.bal_part, 8 * (size_t)S * balance_blocks(G.lv[0].g)))) return s;
   G.stats.assign(S, edf_step_stats{});
+  G.fail_status.assign(S, EDF_SAMPLE_OK);
+  reset_history(G);
   return EDF_OK;
 }
 
@@ -1012,32 +1046,37 @@ edf_status newton_solve(edf_problem* pb, Group& G, const std::vector<int>& run,
 }
 
 // ---------------------------------------------------------------------------
-// one implicit-Euler step of length DT for every sample of a group.  A sample
-// whose Newton solve fails restarts the step from its saved state as 2^h equal
+// one time step of length DT for every sample of a group that has not failed.  A
+// sample whose Newton solve fails restarts the step from its saved state as 2^h equal
 // sub-steps of DT / 2^h (h <= dt_max_halvings); samples advance in lockstep, one
-// sub-step each per round, and finished samples are masked out.
+// sub-step each per round, and finished samples are masked out.  After every sub-step
+// that converged, the FP64 mass balance of that sub-step is added up on the device.
 // ---------------------------------------------------------------------------
-constexpr int kFirstWait = 3, kMaxWait = 64;
-
 edf_status macro_step(edf_problem* pb, Group& G, double DT) {
   hipStream_t st = G.st;
   const int S = G.S;
   set_dt(pb, G, DT);
   edf_status e;
   EDF_TRY(hipMemcpyAsync(G.u0, G.u, S * G.n * sizeof(double), hipMemcpyDeviceToDevice, st));
-  if ((int)G.h_start.size() != S) {
-    G.h_start.assign(S, 0);
-    G.clean.assign(S, 0);
-    G.wait.assign(S, kFirstWait);
-    G.probing.assign(S, 0);
-  }
-  std::vector<int> h(G.h_start), done(S, 0), running(S, 1), ok, why, restore(S), can_retry(S);
+  const bool memory = pb->opts.substep_memory != 0;
+  if ((int)G.h_start.size() != S) reset_history(G);
+  std::vector<int> h(S, 0), done(S, 0), running(S, 0), started(S, 0), ok, why, restore(S),
+      can_retry(S);
   std::vector<double> dts(S);
   for (int s = 0; s < S; ++s) {
-    h[s] = std::min(h[s], pb->opts.dt_max_halvings);
-    G.stats[s] = edf_step_stats{};
-    G.stats[s].substeps = 1 << h[s];
+    edf_step_stats& t = G.stats[s];
+    t.status = G.fail_status[s];
+    t.newton_its = t.lin_its = t.ls_halvings = t.retries = 0;
+    t.substeps = 0;
+    t.defect0 = t.defect = 0.0;
+    t.salt_balance_err = t.liquid_balance_err = 0.0;
+    if (G.fail_status[s] != EDF_SAMPLE_OK) continue;  // failed in an earlier step
+    running[s] = started[s] = 1;
+    h[s] = memory ? std::min(G.h_start[s], pb->opts.dt_max_halvings) : 0;
+    t.substeps = 1 << h[s];
   }
+  launch_fill<double>(G.bal, 8, S, nullptr, 0.0, st);
+  const Level& L0 = G.lv[0];
   bool first = true;
   for (;;) {
     bool any = false;
@@ -1052,6 +1091,14 @@ edf_status macro_step(edf_problem* pb, Group& G, double DT) {
     for (int s = 0; s < S; ++s) can_retry[s] = h[s] < pb->opts.dt_max_halvings;
     if ((e = newton_solve(pb, G, running, can_retry, ok, why, first))) return e;
     first = false;
+    // mass balance of the sub-steps that converged (u: their end, u_old: their start)
+    bool any_ok = false;
+    for (int s = 0; s < S; ++s) any_ok |= running[s] && ok[s];
+    if (any_ok) {
+      if ((e = upload_ints(pb, G, G.lsmask, ok))) return e;
+      launch_balance(L0.g, L0.ph, G.dts, L0.phi, L0.K, G.u, G.u_old, G.bal_part, G.bal, S,
+                     G.lsmask, st);
+    }
     bool any_restore = false;
     for (int s = 0; s < S; ++s) {
       restore[s] = 0;
@@ -1066,6 +1113,7 @@ edf_status macro_step(edf_problem* pb, Group& G, double DT) {
       if (h[s] < pb->opts.dt_max_halvings) {
         h[s] += 1;
         G.stats[s].substeps = 1 << h[s];
+        G.stats[s].retries += 1;
       } else {
         running[s] = 0;
         G.stats[s].status = why[s];
@@ -1074,29 +1122,55 @@ edf_status macro_step(edf_problem* pb, Group& G, double DT) {
     if (any_restore) {
       if ((e = upload_ints(pb, G, G.lsmask, restore))) return e;
       launch_masked_copy(G.n, G.u0, G.u, S, G.lsmask, st);
+      launch_fill<double>(G.bal, 8, S, G.lsmask, 0.0, st);  // the balance starts again too
     }
+  }
+  EDF_CHECK_LAUNCH();
+  std::vector<double> bal(8 * (size_t)S);
+  EDF_TRY(hipMemcpyAsync(bal.data(), G.bal, bal.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  EDF_TRY(hipStreamSynchronize(st));
+  for (int s = 0; s < S; ++s) {
+    if (!started[s]) continue;
+    edf_step_stats& t = G.stats[s];
+    t.retries_total += t.retries;
+    if (t.status != EDF_SAMPLE_OK) {  // failed: keeps its state from the start of the step
+      G.fail_status[s] = t.status;
+      t.failed_step = t.steps_total + 1;
+      continue;
+    }
+    t.steps_total += 1;
+    t.substeps_total += t.substeps;
+    t.split_total += t.substeps > 1;
+    // |dM - B| relative to the mass moved (the storage changes' absolute sum and B)
+    const double* b = &bal[8 * (size_t)s];
+    auto rel = [](double dM, double gross, double B) {
+      const double den = gross + std::fabs(B);
+      return den > 0.0 ? std::fabs(dM - B) / den : 0.0;
+    };
+    t.salt_balance_err = rel(b[0], b[1], b[4]);
+    t.liquid_balance_err = rel(b[2], b[3], b[5]);
   }
   // the next step starts with the sub-step count that worked; after `wait` steps
   // without a retry it tries one halving less, and every such try that fails
   // doubles `wait` (3 at first, at most kMaxWait)
-  for (int s = 0; s < S; ++s) {
-    if (G.stats[s].status != EDF_SAMPLE_OK) continue;
-    if (h[s] == G.h_start[s]) {
-      if (G.probing[s]) G.wait[s] = kFirstWait;
-      G.probing[s] = 0;
-      if (++G.clean[s] >= G.wait[s] && h[s] > 0) {
-        G.h_start[s] = h[s] - 1;
+  if (memory)
+    for (int s = 0; s < S; ++s) {
+      if (!started[s] || G.stats[s].status != EDF_SAMPLE_OK) continue;
+      if (h[s] == G.h_start[s]) {
+        if (G.probing[s]) G.wait[s] = kFirstWait;
+        G.probing[s] = 0;
+        if (++G.clean[s] >= G.wait[s] && h[s] > 0) {
+          G.h_start[s] = h[s] - 1;
+          G.clean[s] = 0;
+          G.probing[s] = 1;
+        }
+      } else {
+        if (G.probing[s]) G.wait[s] = std::min(2 * G.wait[s], kMaxWait);
+        G.probing[s] = 0;
+        G.h_start[s] = h[s];
         G.clean[s] = 0;
-        G.probing[s] = 1;
       }
-    } else {
-      if (G.probing[s]) G.wait[s] = std::min(2 * G.wait[s], kMaxWait);
-      G.probing[s] = 0;
-      G.h_start[s] = h[s];
-      G.clean[s] = 0;
     }
-  }
-  EDF_CHECK_LAUNCH();
   return EDF_OK;
 }
 
@@ -1134,12 +1208,32 @@ edf_status assemble_all_transposed(edf_problem* pb, Group& G, const int* mask, c
   return EDF_OK;
 }
 
-edf_status ensure_adjoint_buffers(edf_problem* pb, Group& G, int n_steps) {
+// buffers of a recorded trajectory of n_steps steps with a checkpoint every k steps
+edf_status ensure_trajectory_buffers(edf_problem* pb, Group& G, int n_steps, int k) {
   const size_t S = G.S, n = G.n;
   edf_status e;
-  if (G.traj_cap < (size_t)n_steps + 1) {
-    G.traj_cap = n_steps + 1;
-    if ((e = dalloc(pb, &G.traj, S * G.traj_cap * n))) return e;
+  const size_t nck = (size_t)ceil_div(n_steps, k) + 1;
+  if (G.ckpt_cap < nck) {
+    if (G.ckpt) (void)hipFree(G.ckpt);
+    G.ckpt = nullptr;
+    G.ckpt_cap = 0;
+    EDF_TRY(hipMalloc((void**)&G.ckpt, S * nck * n * sizeof(double)));
+    G.ckpt_cap = nck;
+  }
+  return EDF_OK;
+}
+
+// buffers of the backward sweep: one segment of k + 1 states, the sub-step states of one
+// step, the adjoint state and the transposition scratch
+edf_status ensure_adjoint_buffers(edf_problem* pb, Group& G, int k) {
+  const size_t S = G.S, n = G.n;
+  edf_status e;
+  if (G.seg_cap < (size_t)k + 1) {
+    if (G.seg) (void)hipFree(G.seg);
+    G.seg = nullptr;
+    G.seg_cap = 0;
+    EDF_TRY(hipMalloc((void**)&G.seg, S * ((size_t)k + 1) * n * sizeof(double)));
+    G.seg_cap = (size_t)k + 1;
   }
   const size_t kmax = (size_t(1) << pb->opts.dt_max_halvings) + 1;
   if (G.sub_cap < kmax) {
@@ -1172,118 +1266,161 @@ edf_status scatter(edf_problem* pb, Group& G, const double* src, double* buf, si
   return EDF_OK;
 }
 
-// forward over n_steps with a checkpoint at the start of every step, then the
-// adjoint sweep backwards; J[s] and dJ[s][4] of the group's samples
-edf_status adjoint_group(edf_problem* pb, Group& G, const QoiBox& box, double dt, int n_steps,
+// Replays sub-steps of one recorded step from the states in G.u: sample s takes its
+// sub-steps r = 1 .. r_end[s] of length dt / K[s] (K[s] = 0: left alone).  When to_sub,
+// the state after sub-step r is stored in slot r of G.sub.  The forward attempt at this
+// sub-step length converged, so no Krylov failure ended it: replaying without that check
+// takes the same path, and the deterministic kernels give the same states bitwise.
+edf_status replay_substeps(edf_problem* pb, Group& G, double dt, const std::vector<int>& K,
+                           const std::vector<int>& r_end, bool to_sub) {
+  const int S = G.S;
+  edf_status e;
+  std::vector<double> dts(S, dt);
+  std::vector<int> act(S), okv, why, idx(S);
+  int rmax = 0;
+  for (int s = 0; s < S; ++s) {
+    if (K[s] > 0) dts[s] = dt / K[s];
+    rmax = std::max(rmax, r_end[s]);
+  }
+  if (rmax == 0) return EDF_OK;
+  set_dt(pb, G, dt);
+  if ((e = upload_dbls(pb, G, G.dts, dts))) return e;
+  for (int r = 1; r <= rmax; ++r) {
+    for (int s = 0; s < S; ++s) act[s] = K[s] > 0 && r <= r_end[s];
+    if ((e = upload_ints(pb, G, G.nmask, act))) return e;
+    launch_masked_copy(G.n, G.u, G.u_old, S, G.nmask, G.st);
+    if ((e = newton_solve(pb, G, act, std::vector<int>(S, 0), okv, why, false))) return e;
+    for (int s = 0; s < S; ++s)
+      if (act[s] && !okv[s])
+        return fail(pb, EDF_ERR_STATE, "recomputation of a recorded sub-step failed for sample " +
+                                           std::to_string(G.s0 + s));
+    if (to_sub) {
+      for (int s = 0; s < S; ++s) idx[s] = act[s] ? r : -1;
+      if ((e = scatter(pb, G, G.u, G.sub, G.sub_cap, idx))) return e;
+    }
+  }
+  return EDF_OK;
+}
+
+// The backward sweep over the trajectory recorded by edf_solve (n steps of dt, a
+// checkpoint every k steps): segments from the last, each recomputed from its checkpoint
+// into G.seg, then its steps backwards, each through its sub-steps.  J[s] and dJ[s][4]
+// of the group's samples (NaN for samples that failed while the trajectory was recorded).
+edf_status adjoint_group(edf_problem* pb, Group& G, const QoiBox& box,
                          std::vector<double>& Jv, std::vector<double>& grad) {
   hipStream_t st = G.st;
   const int S = G.S;
+  const int k = pb->traj_k, n_steps = pb->traj_n;
+  const double dt = pb->traj_dt;
   edf_status e;
-  if ((e = ensure_adjoint_buffers(pb, G, n_steps))) return e;
+  if ((e = ensure_adjoint_buffers(pb, G, k))) return e;
   const Level& L0 = G.lv[0];
-  // forward with checkpoints; H[n][s] = halvings of step n
-  std::vector<std::vector<int>> H(n_steps, std::vector<int>(S, 0));
-  std::vector<int> idx(S, 0);
-  if ((e = scatter(pb, G, G.u, G.traj, G.traj_cap, idx))) return e;
-  for (int n = 0; n < n_steps; ++n) {
-    if ((e = macro_step(pb, G, dt))) return e;
-    for (int s = 0; s < S; ++s) {
-      if (G.stats[s].status != EDF_SAMPLE_OK)
-        return fail(pb, EDF_ERR_NO_CONVERGENCE,
-                    "forward step " + std::to_string(n) + " failed for sample " +
-                        std::to_string(G.s0 + s) + "; the adjoint needs every step");
-      int h = 0;
-      while ((1 << h) < G.stats[s].substeps) ++h;
-      H[n][s] = h;
-    }
-    std::fill(idx.begin(), idx.end(), n + 1);
-    if ((e = scatter(pb, G, G.u, G.traj, G.traj_cap, idx))) return e;
-  }
-  set_dt(pb, G, dt);
   FieldParams fp{pb->phys.lx, pb->phys.ly, pb->phys.lz, pb->phys.phi_mean, pb->phys.K_mean,
                  pb->phys.field_model, pb->phys.n_xi};
   const double* dxi = pb->dxi + (size_t)G.s0 * std::max(pb->phys.n_xi, 1);
   Jv.assign(S, 0.0);
   grad.assign(4 * (size_t)S, 0.0);
-  std::vector<double> hg(4 * S), dts(S), eta(S, pb->opts.lin_rtol);
-  std::vector<int> K(S), act(S), okv, why;
+  std::vector<double> hg(4 * S), eta(S, pb->opts.lin_rtol);
+  std::vector<int> K(S), act(S), idx(S), zero(S, 0), full(S);
+  const int n_seg = ceil_div(n_steps, k);
+  const int last_slot = n_seg;  // the final state (slot of step n_steps)
   bool first = true;
-  for (int n = n_steps - 1; n >= 0; --n) {
-    int kmax = 1;
-    for (int s = 0; s < S; ++s) {
-      K[s] = 1 << H[n][s];
-      kmax = std::max(kmax, K[s]);
-      dts[s] = dt / K[s];
-    }
-    // sub-step states of step n: slot 0 = checkpoint, slot K = next checkpoint, the
-    // others recomputed (the forward kernels are deterministic per sample)
-    std::fill(idx.begin(), idx.end(), n);
-    if ((e = gather(pb, G, G.traj, G.traj_cap, idx, G.u))) return e;
-    std::fill(idx.begin(), idx.end(), 0);
-    if ((e = scatter(pb, G, G.u, G.sub, G.sub_cap, idx))) return e;
-    if ((e = upload_dbls(pb, G, G.dts, dts))) return e;
-    for (int r = 1; r < kmax; ++r) {
-      for (int s = 0; s < S; ++s) act[s] = K[s] > r;
-      if ((e = upload_ints(pb, G, G.nmask, act))) return e;
-      launch_masked_copy(G.n, G.u, G.u_old, S, G.nmask, st);
-      // the forward attempt at this sub-step length succeeded, so no Krylov failure
-      // ended it: replaying without that check takes the same path
-      if ((e = newton_solve(pb, G, act, std::vector<int>(S, 0), okv, why, false))) return e;
-      for (int s = 0; s < S; ++s)
-        if (act[s] && !okv[s]) return fail(pb, EDF_ERR_STATE, "sub-step recomputation failed");
-      for (int s = 0; s < S; ++s) idx[s] = act[s] ? r : -1;
-      if ((e = scatter(pb, G, G.u, G.sub, G.sub_cap, idx))) return e;
-    }
-    std::fill(idx.begin(), idx.end(), n + 1);
-    if ((e = gather(pb, G, G.traj, G.traj_cap, idx, G.u))) return e;
-    for (int s = 0; s < S; ++s) idx[s] = K[s];
-    if ((e = scatter(pb, G, G.u, G.sub, G.sub_cap, idx))) return e;
-    // backward through the sub-steps, one round per sub-step position
-    for (int r = 0; r < kmax; ++r) {
+  for (int sg = n_seg - 1; sg >= 0; --sg) {
+    const int a = sg * k, b = std::min(n_steps, a + k);
+    // the segment's states: slot 0 from the checkpoint, slots 1 .. b-a-1 recomputed
+    // step by step, slot b-a from the next checkpoint (or the final state)
+    for (int s = 0; s < S; ++s) idx[s] = G.traj_fail[s] ? -1 : sg;
+    if ((e = gather(pb, G, G.ckpt, G.ckpt_cap, idx, G.u))) return e;
+    for (int s = 0; s < S; ++s) idx[s] = G.traj_fail[s] ? -1 : 0;
+    if ((e = scatter(pb, G, G.u, G.seg, G.seg_cap, idx))) return e;
+    for (int m = a; m + 1 < b; ++m) {
       for (int s = 0; s < S; ++s) {
-        act[s] = K[s] > r;
-        idx[s] = act[s] ? K[s] - r : -1;
+        K[s] = G.traj_fail[s] ? 0 : 1 << G.H[m][s];
+        full[s] = K[s];
       }
-      if ((e = gather(pb, G, G.sub, G.sub_cap, idx, G.u))) return e;
-      for (int s = 0; s < S; ++s) idx[s] = act[s] ? K[s] - r - 1 : -1;
-      if ((e = gather(pb, G, G.sub, G.sub_cap, idx, G.u_old))) return e;
-      if ((e = upload_ints(pb, G, G.nmask, act))) return e;
-      if (first) {  // J and dJ/du~ at the final state
-        const int nb = ceil_div(L0.g.N, kBlock);
-        launch_qoi(L0.g, L0.ph, box, L0.phi, G.u, G.F, G.part, S, nullptr, st);
-        launch_sum4(nb, G.part, G.g4, S, nullptr, st);
+      if ((e = replay_substeps(pb, G, dt, K, full, false))) return e;
+      for (int s = 0; s < S; ++s) idx[s] = G.traj_fail[s] ? -1 : m - a + 1;
+      if ((e = scatter(pb, G, G.u, G.seg, G.seg_cap, idx))) return e;
+    }
+    for (int s = 0; s < S; ++s) idx[s] = G.traj_fail[s] ? -1 : (b == n_steps ? last_slot : sg + 1);
+    if ((e = gather(pb, G, G.ckpt, G.ckpt_cap, idx, G.u))) return e;
+    for (int s = 0; s < S; ++s) idx[s] = G.traj_fail[s] ? -1 : b - a;
+    if ((e = scatter(pb, G, G.u, G.seg, G.seg_cap, idx))) return e;
+    for (int m = b - 1; m >= a; --m) {
+      int kmax = 0;
+      for (int s = 0; s < S; ++s) {
+        K[s] = G.traj_fail[s] ? 0 : 1 << G.H[m][s];
+        full[s] = std::max(K[s] - 1, 0);
+        kmax = std::max(kmax, K[s]);
+      }
+      // sub-step states of step m: slot 0 = the step's start, slot K = its end, the
+      // others recomputed
+      for (int s = 0; s < S; ++s) idx[s] = K[s] ? m - a : -1;
+      if ((e = gather(pb, G, G.seg, G.seg_cap, idx, G.u))) return e;
+      for (int s = 0; s < S; ++s) idx[s] = K[s] ? 0 : -1;
+      if ((e = scatter(pb, G, G.u, G.sub, G.sub_cap, idx))) return e;
+      if ((e = replay_substeps(pb, G, dt, K, full, true))) return e;
+      for (int s = 0; s < S; ++s) idx[s] = K[s] ? m - a + 1 : -1;
+      if ((e = gather(pb, G, G.seg, G.seg_cap, idx, G.u))) return e;
+      for (int s = 0; s < S; ++s) idx[s] = K[s] ? K[s] : -1;
+      if ((e = scatter(pb, G, G.u, G.sub, G.sub_cap, idx))) return e;
+      std::vector<double> dts(S, dt);
+      for (int s = 0; s < S; ++s)
+        if (K[s]) dts[s] = dt / K[s];
+      set_dt(pb, G, dt);
+      if ((e = upload_dbls(pb, G, G.dts, dts))) return e;
+      // backward through the sub-steps, one round per sub-step position
+      for (int r = 0; r < kmax; ++r) {
+        for (int s = 0; s < S; ++s) {
+          act[s] = K[s] > r;
+          idx[s] = act[s] ? K[s] - r : -1;
+        }
+        if ((e = gather(pb, G, G.sub, G.sub_cap, idx, G.u))) return e;
+        for (int s = 0; s < S; ++s) idx[s] = act[s] ? K[s] - r - 1 : -1;
+        if ((e = gather(pb, G, G.sub, G.sub_cap, idx, G.u_old))) return e;
+        if ((e = upload_ints(pb, G, G.nmask, act))) return e;
+        if (first) {  // J and dJ/du~ at the final state
+          const int nb = ceil_div(L0.g.N, kBlock);
+          launch_qoi(L0.g, L0.ph, box, L0.phi, G.u, G.F, G.part, S, G.nmask, st);
+          launch_sum4(nb, G.part, G.g4, S, G.nmask, st);
+          EDF_CHECK_LAUNCH();
+          EDF_TRY(hipMemcpyAsync(hg.data(), G.g4, 4 * S * sizeof(double), hipMemcpyDeviceToHost, st));
+          EDF_TRY(hipStreamSynchronize(st));
+          for (int s = 0; s < S; ++s) Jv[s] = act[s] ? hg[4 * s] : 0.0;
+        } else {
+          launch_adjoint_rhs(L0.g, L0.ph, L0.phi, G.u, G.lam_next, G.F, S, G.nmask, st);
+        }
+        if ((e = assemble_all_transposed(pb, G, G.nmask, G.dts))) return e;
+        if ((e = upload_dbls(pb, G, G.eta, eta))) return e;
+        if ((e = bicgstab(pb, G))) return e;
+        EDF_TRY(hipMemcpyAsync(G.h_ks, G.ks, S * sizeof(KrylovScalars), hipMemcpyDeviceToHost, st));
+        EDF_TRY(hipStreamSynchronize(st));
+        for (int s = 0; s < S; ++s)
+          if (act[s] && G.h_ks[s].state != 1 && G.h_ks[s].bb > 0)
+            return fail(pb, EDF_ERR_NO_CONVERGENCE,
+                        "adjoint BiCGStab did not converge for sample " + std::to_string(G.s0 + s));
+        const int nb = launch_param_grad(L0.g, L0.ph, G.dts, fp, dxi, L0.phi, L0.K, G.u, G.u_old,
+                                         G.kx, box, first ? 1 : 0, G.part, S, G.nmask, st);
+        launch_sum4(nb, G.part, G.g4, S, G.nmask, st);
+        launch_masked_copy(G.n, G.kx, G.lam_next, S, G.nmask, st);
         EDF_CHECK_LAUNCH();
         EDF_TRY(hipMemcpyAsync(hg.data(), G.g4, 4 * S * sizeof(double), hipMemcpyDeviceToHost, st));
         EDF_TRY(hipStreamSynchronize(st));
-        for (int s = 0; s < S; ++s) Jv[s] = hg[4 * s];
-      } else {
-        launch_adjoint_rhs(L0.g, L0.ph, L0.phi, G.u, G.lam_next, G.F, S, G.nmask, st);
+        for (int s = 0; s < S; ++s)
+          if (act[s])
+            for (int q = 0; q < 4; ++q) grad[4 * s + q] += hg[4 * s + q];
+        first = false;
       }
-      if ((e = assemble_all_transposed(pb, G, G.nmask, G.dts))) return e;
-      if ((e = upload_dbls(pb, G, G.eta, eta))) return e;
-      if ((e = bicgstab(pb, G))) return e;
-      EDF_TRY(hipMemcpyAsync(G.h_ks, G.ks, S * sizeof(KrylovScalars), hipMemcpyDeviceToHost, st));
-      EDF_TRY(hipStreamSynchronize(st));
-      for (int s = 0; s < S; ++s)
-        if (act[s] && G.h_ks[s].state != 1 && G.h_ks[s].bb > 0)
-          return fail(pb, EDF_ERR_NO_CONVERGENCE,
-                      "adjoint BiCGStab did not converge for sample " + std::to_string(G.s0 + s));
-      const int nb = launch_param_grad(L0.g, L0.ph, G.dts, fp, dxi, L0.phi, L0.K, G.u, G.u_old,
-                                       G.kx, box, first ? 1 : 0, G.part, S, G.nmask, st);
-      launch_sum4(nb, G.part, G.g4, S, G.nmask, st);
-      launch_masked_copy(G.n, G.kx, G.lam_next, S, G.nmask, st);
-      EDF_CHECK_LAUNCH();
-      EDF_TRY(hipMemcpyAsync(hg.data(), G.g4, 4 * S * sizeof(double), hipMemcpyDeviceToHost, st));
-      EDF_TRY(hipStreamSynchronize(st));
-      for (int s = 0; s < S; ++s)
-        if (act[s])
-          for (int m = 0; m < 4; ++m) grad[4 * s + m] += hg[4 * s + m];
-      first = false;
     }
   }
-  // leave the final state as the problem's state
-  std::fill(idx.begin(), idx.end(), n_steps);
-  if ((e = gather(pb, G, G.traj, G.traj_cap, idx, G.u))) return e;
+  for (int s = 0; s < S; ++s)
+    if (G.traj_fail[s]) {
+      Jv[s] = std::nan("");
+      for (int q = 0; q < 4; ++q) grad[4 * s + q] = std::nan("");
+    }
+  // leave the final states as the problem's states
+  for (int s = 0; s < S; ++s) idx[s] = last_slot;
+  if ((e = gather(pb, G, G.ckpt, G.ckpt_cap, idx, G.u))) return e;
   EDF_TRY(hipMemcpyAsync(G.u_old, G.u, G.S * G.n * sizeof(double), hipMemcpyDeviceToDevice, st));
   EDF_TRY(hipStreamSynchronize(st));
   return EDF_OK;
@@ -1431,32 +1568,38 @@ edf_status edf_set_parameters(edf_problem* pb, const double* xi) {
     if (!(std::fabs(xi[e]) <= 1.0)) return fail(pb, EDF_ERR_ARG, "|xi| > 1 or not finite");
   FieldParams fp{pb->phys.lx, pb->phys.ly, pb->phys.lz, pb->phys.phi_mean, pb->phys.K_mean,
                  pb->phys.field_model, nxi};
-  const size_t cnt = (size_t)pb->S_total * std::max(nxi, 1);
+  const size_t ld = std::max(nxi, 1);
+  const size_t cnt = (size_t)pb->S_total * ld;
   edf_status es;
   if (!pb->dxi && (es = dalloc(pb, &pb->dxi, cnt))) return es;
-  double* dxi = pb->dxi;
+  if (!pb->dxi_new && (es = dalloc(pb, &pb->dxi_new, cnt))) return es;
+  if (!pb->bad && (es = dalloc(pb, &pb->bad, (size_t)pb->S_total))) return es;
   std::vector<double> hx(cnt, 0.0);
   if (nxi > 0) std::memcpy(hx.data(), xi, (size_t)pb->S_total * nxi * sizeof(double));
-  EDF_TRY(hipMemcpyAsync(dxi, hx.data(), cnt * sizeof(double), hipMemcpyHostToDevice, pb->st));
+  // the fields of every level are checked from the staged parameters before anything
+  // of the problem changes
+  EDF_TRY(hipStreamSynchronize(pb->st));
+  EDF_TRY(hipMemcpyAsync(pb->dxi_new, hx.data(), cnt * sizeof(double), hipMemcpyHostToDevice, pb->st));
+  launch_fill<int>(pb->bad, (size_t)pb->S_total, 1, nullptr, 0, pb->st);
   for (Group& G : pb->groups)
     for (Level& L : G.lv)
-      launch_coefficients(L.g, fp, dxi + (size_t)G.s0 * std::max(nxi, 1), G.S, L.phi, L.K, pb->st);
+      launch_check_coefficients(L.g, fp, pb->dxi_new + (size_t)G.s0 * ld, G.S, pb->bad + G.s0, pb->st);
+  EDF_CHECK_LAUNCH();
+  std::vector<int> bad(pb->S_total);
+  EDF_TRY(hipMemcpyAsync(bad.data(), pb->bad, bad.size() * sizeof(int), hipMemcpyDeviceToHost, pb->st));
+  EDF_TRY(hipStreamSynchronize(pb->st));
+  for (int s = 0; s < pb->S_total; ++s)
+    if (bad[s])
+      return fail(pb, EDF_ERR_ARG, "sample " + std::to_string(s) +
+                                       ": porosity outside (0,1) or permeability not positive");
+  std::swap(pb->dxi, pb->dxi_new);
+  for (Group& G : pb->groups)
+    for (Level& L : G.lv)
+      launch_coefficients(L.g, fp, pb->dxi + (size_t)G.s0 * ld, G.S, L.phi, L.K, pb->st);
   EDF_CHECK_LAUNCH();
   EDF_TRY(hipStreamSynchronize(pb->st));
-  // range check of phi and K on the finest grids (host copy per group, chunked per sample)
-  for (Group& G : pb->groups) {
-    const Level& L = G.lv[0];
-    std::vector<double> ph(L.cells), kk(L.cells);
-    for (int s = 0; s < G.S; ++s) {
-      EDF_TRY(hipMemcpy(ph.data(), L.phi + s * L.cells, L.cells * sizeof(double),
-                        hipMemcpyDeviceToHost));
-      EDF_TRY(hipMemcpy(kk.data(), L.K + s * L.cells, L.cells * sizeof(double),
-                        hipMemcpyDeviceToHost));
-      for (size_t e = 0; e < L.cells; ++e)
-        if (!(ph[e] > 0.0 && ph[e] < 1.0) || !(kk[e] > 0.0 && std::isfinite(kk[e])))
-          return fail(pb, EDF_ERR_ARG, "porosity outside (0,1) or permeability not positive");
-    }
-  }
+  for (Group& G : pb->groups) reset_history(G);
+  pb->traj_valid = false;
   pb->params_set = true;
   return EDF_OK;
 }
@@ -1471,6 +1614,16 @@ edf_status edf_set_state(edf_problem* pb, int32_t sample, const double* pc, int3
   EDF_TRY(hipMemcpyAsync(G->u + s * G->n, pc, G->n * sizeof(double), k, pb->st));
   EDF_TRY(hipMemcpyAsync(G->u_old + s * G->n, pc, G->n * sizeof(double), k, pb->st));
   if (!is_dev) EDF_TRY(hipStreamSynchronize(pb->st));
+  // a new state resets the sample: no failure, no sub-step history, counters from zero
+  G->fail_status[s] = EDF_SAMPLE_OK;
+  G->stats[s] = edf_step_stats{};
+  if ((int)G->h_start.size() == G->S) {
+    G->h_start[s] = 0;
+    G->clean[s] = 0;
+    G->wait[s] = kFirstWait;
+    G->probing[s] = 0;
+  }
+  pb->traj_valid = false;
   return EDF_OK;
 }
 
@@ -1486,10 +1639,12 @@ edf_status edf_get_state(edf_problem* pb, int32_t sample, double* pc, int32_t is
   return EDF_OK;
 }
 
-edf_status edf_step(edf_problem* pb, double dt, edf_step_stats* stats) {
-  edf_status e;
-  if ((e = check_ready(pb))) return e;
-  if (!(dt > 0) || !std::isfinite(dt)) return fail(pb, EDF_ERR_ARG, "dt must be positive");
+}  // extern "C"
+
+namespace {
+
+// one step of every group (edf_step without touching the recorded trajectory)
+edf_status step_all(edf_problem* pb, double dt, edf_step_stats* stats) {
   EDF_TRY(hipStreamSynchronize(pb->st));  // work the caller queued before this step
   // the groups are independent and each steps on its own stream; with
   // concurrent_groups each also runs from its own host thread, so that one group's
@@ -1521,16 +1676,70 @@ edf_status edf_step(edf_problem* pb, double dt, edf_step_stats* stats) {
       if (stats) stats[G.s0 + s] = G.stats[s];
       all_failed &= G.stats[s].status != EDF_SAMPLE_OK;
     }
-  if (all_failed) return fail(pb, EDF_ERR_NO_CONVERGENCE, "every sample failed in this step");
+  if (all_failed) return fail(pb, EDF_ERR_NO_CONVERGENCE, "every sample has failed");
   return EDF_OK;
 }
 
-edf_status edf_solve(edf_problem* pb, double dt, int32_t n_steps, edf_step_stats* stats) {
+}  // namespace
+
+extern "C" {
+
+edf_status edf_step(edf_problem* pb, double dt, edf_step_stats* stats) {
+  edf_status e;
+  if ((e = check_ready(pb))) return e;
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(pb, EDF_ERR_ARG, "dt must be positive");
+  pb->traj_valid = false;
+  return step_all(pb, dt, stats);
+}
+
+edf_status edf_solve(edf_problem* pb, double dt, int32_t n_steps, int32_t checkpoint_every,
+                     edf_step_stats* stats) {
   edf_status e;
   if ((e = check_ready(pb))) return e;
   if (n_steps < 0) return fail(pb, EDF_ERR_ARG, "n_steps < 0");
-  for (int n = 0; n < n_steps; ++n)
-    if ((e = edf_step(pb, dt, n + 1 == n_steps ? stats : nullptr))) return e;
+  if (checkpoint_every < 0) return fail(pb, EDF_ERR_ARG, "checkpoint_every < 0");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(pb, EDF_ERR_ARG, "dt must be positive");
+  pb->traj_valid = false;
+  const int k = checkpoint_every;
+  const bool record = k > 0 && n_steps > 0;
+  if (record) {
+    EDF_TRY(hipStreamSynchronize(pb->st));
+    for (Group& G : pb->groups) {
+      if ((e = ensure_trajectory_buffers(pb, G, n_steps, k))) return e;
+      G.H.assign(n_steps, std::vector<int>(G.S, 0));
+      G.traj_fail.assign(G.S, 0);
+      for (int s = 0; s < G.S; ++s) G.traj_fail[s] = G.fail_status[s] != EDF_SAMPLE_OK;
+      if ((e = scatter(pb, G, G.u, G.ckpt, G.ckpt_cap, std::vector<int>(G.S, 0)))) return e;
+      EDF_TRY(hipStreamSynchronize(G.st));
+    }
+  }
+  for (int m = 0; m < n_steps; ++m) {
+    if ((e = step_all(pb, dt, m + 1 == n_steps ? stats : nullptr))) return e;
+    if (!record) continue;
+    for (Group& G : pb->groups) {
+      for (int s = 0; s < G.S; ++s) {
+        const edf_step_stats& t = G.stats[s];
+        if (t.status != EDF_SAMPLE_OK) {
+          G.traj_fail[s] = 1;
+          continue;
+        }
+        int h = 0;
+        while ((1 << h) < t.substeps) ++h;
+        G.H[m][s] = h;
+      }
+      if ((m + 1) % k == 0 || m + 1 == n_steps) {
+        const int slot = ceil_div(m + 1, k);
+        if ((e = scatter(pb, G, G.u, G.ckpt, G.ckpt_cap, std::vector<int>(G.S, slot)))) return e;
+        EDF_TRY(hipStreamSynchronize(G.st));
+      }
+    }
+  }
+  if (record) {
+    pb->traj_valid = true;
+    pb->traj_k = k;
+    pb->traj_n = n_steps;
+    pb->traj_dt = dt;
+  }
   EDF_TRY(hipStreamSynchronize(pb->st));
   return EDF_OK;
 }
@@ -1554,6 +1763,16 @@ edf_status edf_gpc_project(edf_problem* pb, int32_t group, int32_t cx, int32_t c
     return fail(pb, EDF_ERR_ARG, "common grid not nested in the group's grid");
   for (int i = 0; i < S; ++i)
     if (!std::isfinite(weights[i])) return fail(pb, EDF_ERR_ARG, "weights not finite");
+  // failed samples are left out, the others' weights renormalised to the same sum
+  std::vector<double> wv(weights, weights + S);
+  double w_all = 0.0, w_ok = 0.0;
+  for (int i = 0; i < S; ++i) {
+    w_all += wv[i];
+    if (G.fail_status[i] != EDF_SAMPLE_OK) wv[i] = 0.0;
+    w_ok += wv[i];
+  }
+  if (!(w_ok != 0.0)) return fail(pb, EDF_ERR_NO_CONVERGENCE, "no valid sample in the group");
+  for (double& x : wv) x *= w_all / w_ok;
   std::vector<int> idx;
   gpc_indices(M, degree, truncation, idx);
   const int nc = (int)idx.size() / M;
@@ -1578,7 +1797,7 @@ edf_status edf_gpc_project(edf_problem* pb, int32_t group, int32_t cx, int32_t c
   double* mv = F + S * Nc;
   EDF_TRY(hipMemcpyAsync(pb->gpc_ibuf, idx.data(), idx.size() * sizeof(int), hipMemcpyHostToDevice, st));
   EDF_TRY(hipMemcpyAsync(dQ, Q.data(), nc * sizeof(double), hipMemcpyHostToDevice, st));
-  EDF_TRY(hipMemcpyAsync(dw, weights, S * sizeof(double), hipMemcpyHostToDevice, st));
+  EDF_TRY(hipMemcpyAsync(dw, wv.data(), S * sizeof(double), hipMemcpyHostToDevice, st));
   launch_gather_common(g, cx, cy, cz, G.u, F, S, st);
   const int ldt = std::max(pb->phys.n_xi, 1);
   launch_gpc_weights(S, M, nc, pb->dxi + (size_t)G.s0 * ldt, ldt, dw, pb->gpc_ibuf, dQ, W, st);
@@ -1690,7 +1909,7 @@ edf_status edf_moments(edf_problem* pb, int32_t cx, int32_t cy, int32_t cz, doub
   for (Group& G : pb->groups)
     for (int s = 0; s < G.S; ++s) {
       const double ws = weights ? weights[G.s0 + s] : 1.0 / S;
-      w[G.s0 + s] = G.stats[s].status == EDF_SAMPLE_OK ? ws : 0.0;
+      w[G.s0 + s] = G.fail_status[s] == EDF_SAMPLE_OK ? ws : 0.0;
       sum += w[G.s0 + s];
     }
   if (!(sum > 0)) return fail(pb, EDF_ERR_NO_CONVERGENCE, "no valid sample");
@@ -1816,27 +2035,33 @@ edf_status edf_apply_jacobian(edf_problem* pb, int32_t group, const double* x, d
   return EDF_OK;
 }
 
-edf_status edf_adjoint(edf_problem* pb, const double* box, double dt, int32_t n_steps, double* J,
-                       double* dJ_dxi) {
+edf_status edf_adjoint(edf_problem* pb, const edf_qoi* qoi, double* J, double* dJ_dxi) {
   edf_status e;
   if ((e = check_ready(pb))) return e;
-  if (!box || !J || !dJ_dxi || !(dt > 0) || !std::isfinite(dt) || n_steps < 1)
-    return fail(pb, EDF_ERR_ARG, "bad adjoint arguments");
+  if (!qoi || !J || !dJ_dxi) return fail(pb, EDF_ERR_ARG, "bad adjoint arguments");
+  if (qoi->kind != 0) return fail(pb, EDF_ERR_ARG, "unknown quantity of interest");
   if (pb->phys.field_model == EDF_FIELD_CONST || pb->phys.n_xi < 1)
     return fail(pb, EDF_ERR_ARG, "the constant field has no parameters");
   QoiBox b;
   for (int i = 0; i < 6; ++i) {
-    if (!std::isfinite(box[i])) return fail(pb, EDF_ERR_ARG, "box not finite");
-    b.b[i] = box[i];
+    if (!std::isfinite(qoi->box[i])) return fail(pb, EDF_ERR_ARG, "box not finite");
+    b.b[i] = qoi->box[i];
   }
+  if (!pb->traj_valid)
+    return fail(pb, EDF_ERR_STATE, "no recorded trajectory: call edf_solve with checkpoint_every > 0 "
+                                   "(and nothing that changes states or parameters) first");
   const int nxi = pb->phys.n_xi;
   EDF_TRY(hipStreamSynchronize(pb->st));
   for (Group& G : pb->groups) {
     std::vector<double> Jv, gr;
-    if ((e = adjoint_group(pb, G, b, dt, n_steps, Jv, gr))) return e;
+    const std::vector<edf_step_stats> keep = G.stats;  // the replays count Newton work
+    e = adjoint_group(pb, G, b, Jv, gr);
+    G.stats = keep;
+    if (e) return e;
     for (int s = 0; s < G.S; ++s) {
       J[G.s0 + s] = Jv[s];
-      for (int m = 0; m < nxi; ++m) dJ_dxi[(size_t)(G.s0 + s) * nxi + m] = m < 4 ? gr[4 * s + m] : 0.0;
+      for (int m = 0; m < nxi; ++m)
+        dJ_dxi[(size_t)(G.s0 + s) * nxi + m] = m < 4 ? gr[4 * s + m] : 0.0;
     }
   }
   return EDF_OK;
@@ -1917,6 +2142,8 @@ void edf_destroy(edf_problem* pb) {
     if (G.h_list) (void)hipHostFree(G.h_list);
     if (G.h_dbl) (void)hipHostFree(G.h_dbl);
     if (G.h_ks) (void)hipHostFree(G.h_ks);
+    if (G.ckpt) (void)hipFree(G.ckpt);
+    if (G.seg) (void)hipFree(G.seg);
   }
   for (void* p : pb->allocs) (void)hipFree(p);
   if (pb->mom_f) (void)hipFree(pb->mom_f);

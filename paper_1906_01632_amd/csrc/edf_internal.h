@@ -59,10 +59,22 @@ __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; 
 // ---------------------------------------------------------------------------
 void launch_coefficients(const Geom& g, const FieldParams& fp, const double* xi, int S,
                          double* phi, double* K, hipStream_t st);
+// bad[s] |= 1 when some hexahedron of sample s would get phi outside (0, 1) or a K that
+// is not finite and positive (nothing is written)
+void launch_check_coefficients(const Geom& g, const FieldParams& fp, const double* xi, int S,
+                               int* bad, hipStream_t st);
 // dts: per-sample time steps [S] in device memory, or nullptr for ph.dt
 void launch_defect(const Geom& g, const Phys& ph, const double* dts, const double* phi,
                    const double* K, const double* u, const double* u_old, double* F, int S,
                    const int* mask, hipStream_t st);
+// FP64 mass balance of a (sub-)step: acc[s][0..5] += (salt storage change, its absolute
+// sum, liquid storage change, its absolute sum, dt x salt rows at the c-Dirichlet
+// vertices, dt x liquid rows at the pinned vertices) for the samples in mask; part is
+// scratch [S][balance_blocks(g)][8]
+int balance_blocks(const Geom& g);
+void launch_balance(const Geom& g, const Phys& ph, const double* dts, const double* phi,
+                    const double* K, const double* u, const double* u_old, double* part,
+                    double* acc, int S, const int* mask, hipStream_t st);
 void launch_assemble(const Geom& g, const Phys& ph, const double* dts, const double* phi,
                      const double* K, const double* u, double* A64, float* A32, int S,
                      const int* mask, hipStream_t st, bool frozen);

@@ -196,4 +196,27 @@ __device__ __forceinline__ bool is_pin(const Geom& g, int i, int j, int k) {
   return k == 0 && (i == 0 || i == g.nx - 1) && (j == 0 || j == g.ny - 1);
 }
 
+// Sums Q per-lane values over a workgroup of kBlock lanes and writes the Q block totals
+// to part[0..Q-1] (wave shuffles, then the waves' sums in a fixed order: deterministic).
+template <int Q>
+__device__ __forceinline__ void block_partial(double (&v)[Q], double* part) {
+  __shared__ double sh[Q][kBlock / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_down(v[q], off, 64);
+    if (lane == 0) sh[q][wave] = v[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      double a = 0.0;
+      for (int w = 0; w < kBlock / 64; ++w) a += sh[q][w];
+      part[q] = a;
+    }
+  }
+}
+
 }  // namespace edf

@@ -25,15 +25,9 @@ namespace edf {
 // ---------------------------------------------------------------------------
 // coefficient fields, one thread per hexahedron (Section 2.2)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_coefficients(Geom g, FieldParams fp, const double* xi,
-                                                         double* phi_all, double* K_all) {
-  const int s = blockIdx.y;
-  const int cx = g.nx - 1, cy = g.ny - 1, cz = g.nz - 1;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= cx * cy * cz) return;
-  const int i = e % cx, j = (e / cx) % cy, k = e / (cx * cy);
+__device__ __forceinline__ void field_value(const Geom& g, const FieldParams& fp, const double* q,
+                                            int i, int j, int k, double& phi_out, double& K_out) {
   const double x = (i + 0.5) * g.hx, y = (j + 0.5) * g.hy, z = (k + 0.5) * g.hz;
-  const double* q = xi + (size_t)s * (fp.n_xi > 0 ? fp.n_xi : 1);
   const double pm = fp.phi_mean;
   const double px = M_PI * x / fp.lx, py = M_PI * y / fp.ly, pz = M_PI * z / fp.lz;
   double phi = pm, logK_extra = 0.0;
@@ -60,6 +54,27 @@ __global__ __launch_bounds__(kBlock) void k_coefficients(Geom g, FieldParams fp,
     K = fp.K_mean * r * r * r * w * w;
     if (logK_extra != 0.0) K = exp(log(K) + logK_extra);
   }
+  phi_out = phi;
+  K_out = K;
+}
+
+// phi_all/K_all null: only check that phi lies in (0, 1) and K is finite and positive,
+// setting bad[s] for a sample with a hexahedron outside
+__global__ __launch_bounds__(kBlock) void k_coefficients(Geom g, FieldParams fp, const double* xi,
+                                                         double* phi_all, double* K_all,
+                                                         int* bad) {
+  const int s = blockIdx.y;
+  const int cx = g.nx - 1, cy = g.ny - 1, cz = g.nz - 1;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= cx * cy * cz) return;
+  const int i = e % cx, j = (e / cx) % cy, k = e / (cx * cy);
+  const double* q = xi + (size_t)s * (fp.n_xi > 0 ? fp.n_xi : 1);
+  double phi, K;
+  field_value(g, fp, q, i, j, k, phi, K);
+  if (bad) {
+    if (!(phi > 0.0 && phi < 1.0) || !(K > 0.0 && K < INFINITY)) atomicOr(bad + s, 1);
+    return;
+  }
   const size_t cells = (size_t)cx * cy * cz;
   phi_all[(size_t)s * cells + e] = phi;
   K_all[(size_t)s * cells + e] = K;
@@ -69,7 +84,15 @@ void launch_coefficients(const Geom& g, const FieldParams& fp, const double* xi,
                          double* phi, double* K, hipStream_t st) {
   const int cells = (g.nx - 1) * (g.ny - 1) * (g.nz - 1);
   dim3 grid(ceil_div(cells, kBlock), S);
-  hipLaunchKernelGGL(k_coefficients, grid, dim3(kBlock), 0, st, g, fp, xi, phi, K);
+  hipLaunchKernelGGL(k_coefficients, grid, dim3(kBlock), 0, st, g, fp, xi, phi, K, (int*)nullptr);
+}
+
+void launch_check_coefficients(const Geom& g, const FieldParams& fp, const double* xi, int S,
+                               int* bad, hipStream_t st) {
+  const int cells = (g.nx - 1) * (g.ny - 1) * (g.nz - 1);
+  dim3 grid(ceil_div(cells, kBlock), S);
+  hipLaunchKernelGGL(k_coefficients, grid, dim3(kBlock), 0, st, g, fp, xi, (double*)nullptr,
+                     (double*)nullptr, bad);
 }
 
 // ---------------------------------------------------------------------------
@@ -194,6 +217,32 @@ __device__ __forceinline__ Phys sample_phys(const Phys& ph, const double* dts, i
   return p;
 }
 
+// Finite-volume rows of vertex (i, j, k) before Dirichlet rows (R9 of the reading):
+// Fl, Fs = storage change over dt + outgoing face fluxes [kg/s]; m = the vertex's
+// porous volume m_v.  P, C: the 3x3x3 neighbourhood of the current state.
+__device__ __forceinline__ void fv_rows(const Geom& g, const Phys& ph, const double* phi,
+                                        const double* K, const double* P, const double* C,
+                                        double co, int i, int j, int k, double& Fl, double& Fs,
+                                        double& m) {
+  const FaceGeo fg = face_geo(g);
+  double msum = 0.0;
+  Fl = 0.0;
+  Fs = 0.0;
+  hex_residual<0, 0, 0>(g, i, j, k, phi, K, P, C, ph, fg, Fl, Fs, msum);
+  hex_residual<1, 0, 0>(g, i, j, k, phi, K, P, C, ph, fg, Fl, Fs, msum);
+  hex_residual<0, 1, 0>(g, i, j, k, phi, K, P, C, ph, fg, Fl, Fs, msum);
+  hex_residual<1, 1, 0>(g, i, j, k, phi, K, P, C, ph, fg, Fl, Fs, msum);
+  hex_residual<0, 0, 1>(g, i, j, k, phi, K, P, C, ph, fg, Fl, Fs, msum);
+  hex_residual<1, 0, 1>(g, i, j, k, phi, K, P, C, ph, fg, Fl, Fs, msum);
+  hex_residual<0, 1, 1>(g, i, j, k, phi, K, P, C, ph, fg, Fl, Fs, msum);
+  hex_residual<1, 1, 1>(g, i, j, k, phi, K, P, C, ph, fg, Fl, Fs, msum);
+  m = msum * (g.hx * g.hy * g.hz * 0.125);
+  const double c = C[kDiag];
+  const double rc = ph.rho0 + ph.drho * c, rco = ph.rho0 + ph.drho * co;
+  Fl += m * (rc - rco) / ph.dt;
+  Fs += m * (rc * c - rco * co) / ph.dt;
+}
+
 __global__ __launch_bounds__(kBlock) void k_defect(Geom g, Phys ph0, const double* dts,
                                                    const double* phi_all, const double* K_all,
                                                    const double* u_all, const double* uo_all,
@@ -211,25 +260,12 @@ __global__ __launch_bounds__(kBlock) void k_defect(Geom g, Phys ph0, const doubl
   const double2* uo = reinterpret_cast<const double2*>(uo_all) + (size_t)s * g.N;
   double P[27], C[27];
   load_neighbourhood(g, u, i, j, k, P, C);
-  const FaceGeo fg = face_geo(g);
-  double Fl = 0.0, Fs = 0.0, msum = 0.0;
-  hex_residual<0, 0, 0>(g, i, j, k, phi, K, P, C, ph, fg, Fl, Fs, msum);
-  hex_residual<1, 0, 0>(g, i, j, k, phi, K, P, C, ph, fg, Fl, Fs, msum);
-  hex_residual<0, 1, 0>(g, i, j, k, phi, K, P, C, ph, fg, Fl, Fs, msum);
-  hex_residual<1, 1, 0>(g, i, j, k, phi, K, P, C, ph, fg, Fl, Fs, msum);
-  hex_residual<0, 0, 1>(g, i, j, k, phi, K, P, C, ph, fg, Fl, Fs, msum);
-  hex_residual<1, 0, 1>(g, i, j, k, phi, K, P, C, ph, fg, Fl, Fs, msum);
-  hex_residual<0, 1, 1>(g, i, j, k, phi, K, P, C, ph, fg, Fl, Fs, msum);
-  hex_residual<1, 1, 1>(g, i, j, k, phi, K, P, C, ph, fg, Fl, Fs, msum);
-  const double m = msum * (g.hx * g.hy * g.hz * 0.125);
-  const double c = C[kDiag], co = uo[v].y;
-  const double rc = ph.rho0 + ph.drho * c, rco = ph.rho0 + ph.drho * co;
-  Fl += m * (rc - rco) / ph.dt;
-  Fs += m * (rc * c - rco * co) / ph.dt;
+  double Fl, Fs, m;
+  fv_rows(g, ph, phi, K, P, C, uo[v].y, i, j, k, Fl, Fs, m);
   double2 out;
   out.x = is_pin(g, i, j, k) ? P[kDiag] / ph.p_unit : ph.s_row * Fl;
   double cD;
-  out.y = is_cdir(g, i, j, k, cD) ? c - cD : ph.s_row * Fs;
+  out.y = is_cdir(g, i, j, k, cD) ? C[kDiag] - cD : ph.s_row * Fs;
   reinterpret_cast<double2*>(F_all)[(size_t)s * g.N + v] = out;
 }
 
@@ -238,6 +274,92 @@ void launch_defect(const Geom& g, const Phys& ph, const double* dts, const doubl
                    const int* mask, hipStream_t st) {
   dim3 grid(ceil_div(g.N, kBlock), S);
   hipLaunchKernelGGL(k_defect, grid, dim3(kBlock), 0, st, g, ph, dts, phi, K, u, u_old, F, mask);
+}
+
+// ---------------------------------------------------------------------------
+// Global mass balance of one (sub-)step in FP64 (eqs. e_cont_eq and e_tran_eq summed
+// over all control volumes).  Interior face fluxes cancel in pairs and the no-flow
+// faces carry none, so the storage change of the box equals dt times the rows of the
+// vertices whose equation is replaced by a Dirichlet condition: the salt rows of the
+// c-Dirichlet vertices and the liquid rows of the pinned vertices.  Per vertex and
+// sample: [0] salt storage change m_v (rho c - rho_old c_old), [1] its absolute value,
+// [2] liquid storage change m_v (rho - rho_old), [3] its absolute value, [4] dt x the
+// salt row at a c-Dirichlet vertex, [5] dt x the liquid row at a pinned vertex (kg).
+// Block totals go to part[s][b][0..7]; k_balance_add adds the samples' sums to
+// acc[s][0..7] in a fixed order.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_balance(Geom g, Phys ph0, const double* dts,
+                                                    const double* phi_all, const double* K_all,
+                                                    const double* u_all, const double* uo_all,
+                                                    double* part, const int* mask) {
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const Phys ph = sample_phys(ph0, dts, s);
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  double a[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (v < g.N) {
+    const int i = v % g.nx, j = (v / g.nx) % g.ny, k = v / (g.nx * g.ny);
+    const size_t cells = (size_t)(g.nx - 1) * (g.ny - 1) * (g.nz - 1);
+    const double* phi = phi_all + s * cells;
+    const double* K = K_all + s * cells;
+    const double2* u = reinterpret_cast<const double2*>(u_all) + (size_t)s * g.N;
+    const double2* uo = reinterpret_cast<const double2*>(uo_all) + (size_t)s * g.N;
+    double cD;
+    const bool cdir = is_cdir(g, i, j, k, cD), pin = is_pin(g, i, j, k);
+    const double c = u[v].y, co = uo[v].y;
+    double m;
+    if (cdir || pin) {
+      double P[27], C[27], Fl, Fs;
+      load_neighbourhood(g, u, i, j, k, P, C);
+      fv_rows(g, ph, phi, K, P, C, co, i, j, k, Fl, Fs, m);
+      if (cdir) a[4] = ph.dt * Fs;
+      if (pin) a[5] = ph.dt * Fl;
+    } else {
+      double msum = 0.0;
+#pragma unroll
+      for (int h = 0; h < 8; ++h) {
+        const int hi = i - (h & 1), hj = j - ((h >> 1) & 1), hk = k - (h >> 2);
+        if (hi < 0 || hj < 0 || hk < 0 || hi > g.nx - 2 || hj > g.ny - 2 || hk > g.nz - 2) continue;
+        msum += phi[hi + (size_t)(g.nx - 1) * (hj + (size_t)(g.ny - 1) * hk)];
+      }
+      m = msum * (g.hx * g.hy * g.hz * 0.125);
+    }
+    const double rc = ph.rho0 + ph.drho * c, rco = ph.rho0 + ph.drho * co;
+    a[0] = m * (rc * c - rco * co);
+    a[1] = fabs(a[0]);
+    a[2] = m * (rc - rco);
+    a[3] = fabs(a[2]);
+  }
+  block_partial<6>(a, part + ((size_t)s * gridDim.x + blockIdx.x) * 8);
+}
+
+__global__ __launch_bounds__(64) void k_balance_add(int nb, const double* part, double* acc,
+                                                    const int* mask) {
+  const int s = blockIdx.x;
+  if (mask && !mask[s]) return;
+  const int lane = threadIdx.x;
+  double q[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int b = lane; b < nb; b += 64)
+#pragma unroll
+    for (int e = 0; e < 6; ++e) q[e] += part[((size_t)s * nb + b) * 8 + e];
+#pragma unroll
+  for (int e = 0; e < 6; ++e)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) q[e] += __shfl_down(q[e], off, 64);
+  if (lane == 0)
+#pragma unroll
+    for (int e = 0; e < 6; ++e) acc[(size_t)s * 8 + e] += q[e];
+}
+
+int balance_blocks(const Geom& g) { return ceil_div(g.N, kBlock); }
+
+void launch_balance(const Geom& g, const Phys& ph, const double* dts, const double* phi,
+                    const double* K, const double* u, const double* u_old, double* part,
+                    double* acc, int S, const int* mask, hipStream_t st) {
+  const int nb = balance_blocks(g);
+  hipLaunchKernelGGL(k_balance, dim3(nb, S), dim3(kBlock), 0, st, g, ph, dts, phi, K, u, u_old,
+                     part, mask);
+  hipLaunchKernelGGL(k_balance_add, dim3(S), dim3(64), 0, st, nb, part, acc, mask);
 }
 
 // ---------------------------------------------------------------------------

@@ -18,27 +18,6 @@ int reduce_blocks(size_t n) {
   return (int)(b < 1 ? 1 : (b > kRedMax ? kRedMax : b));
 }
 
-template <int Q>
-__device__ __forceinline__ void block_partial(double (&v)[Q], double* part) {
-  __shared__ double sh[Q][kBlock / 64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_down(v[q], off, 64);
-    if (lane == 0) sh[q][wave] = v[q];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      double a = 0.0;
-      for (int w = 0; w < kBlock / 64; ++w) a += sh[q][w];
-      part[q] = a;
-    }
-  }
-}
-
 // ---------------------------------------------------------------------------
 // y = A x (FP64 stencil), optional fused dots: (d1, y) and (d2, y) or (y, y)
 // ---------------------------------------------------------------------------

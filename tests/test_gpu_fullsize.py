@@ -30,9 +30,24 @@ def _problem(phys, groups, **opts):
     return Problem(phys, groups, o)
 
 
-def _oracle_scaled_norm(box, coef, u, u_old):
-    F = elder.residual(box, coef, u, u_old, DT) * elder.row_scale(box, DT)
+def _oracle_scaled_norm(box, coef, u, u_old, dt=DT):
+    F = elder.residual(box, coef, u, u_old, dt) * elder.row_scale(box, dt)
     return float(np.linalg.norm(F))
+
+
+def _substep_states(phys, group, xi, sub, opts):
+    """The sub-step states of one sample's split step: the sample alone, stepped `sub`
+    times by DT / sub (each of those steps is the Newton solve of the split step's
+    sub-step, bitwise)."""
+    pb = _problem(phys, [group[:4] + (1,)], **opts)
+    pb.set_parameters(xi[None])
+    states = [pb.get_state(0)]
+    for _ in range(sub):
+        st = pb.step(DT / sub)
+        assert st[0]["status"] == 0 and st[0]["substeps"] == 1, st
+        states.append(pb.get_state(0))
+    pb.destroy()
+    return states
 
 
 def test_defect_parity_129_every_vertex():
@@ -73,10 +88,16 @@ def test_qmc_groups_step_solves_the_oracle_system():
         u0 = synth.initial_state(nx, ny, nz, phys)
         u = pb.get_state(s)
         sub = st[s]["substeps"]
-        if sub == 1:
-            r0 = _oracle_scaled_norm(box, coef, u0, u0)
-            r = _oracle_scaled_norm(box, coef, u, u0)
-            print(f"sample {s} {nx}x{ny}x{nz}: oracle |F~| {r:.3e} of {r0:.3e}", flush=True)
+        # a split step is replayed sub-step by sub-step; every sub-step's state zeroes the
+        # oracle's residual of that sub-step
+        states = [u0, u] if sub == 1 else _substep_states(
+            phys, groups[s // 2], xi[s], sub, dict(newton_rtol=wl.newton_rtol))
+        np.testing.assert_array_equal(states[-1], u)
+        for k in range(1, len(states)):
+            r0 = _oracle_scaled_norm(box, coef, states[k - 1], states[k - 1], DT / sub)
+            r = _oracle_scaled_norm(box, coef, states[k], states[k - 1], DT / sub)
+            print(f"sample {s} {nx}x{ny}x{nz} sub-step {k}/{sub}: oracle |F~| {r:.3e} of {r0:.3e}",
+                  flush=True)
             assert r <= 2 * wl.newton_rtol * r0 + 1e-10
         assert -0.05 <= u[..., 1].min() and u[..., 1].max() <= 1.05
         fields.append(stats.inject(u[..., 1], (33, 33, 9)))
@@ -85,6 +106,76 @@ def test_qmc_groups_step_solves_the_oracle_system():
     assert np.abs(mean - m).max() < 1e-14 and np.abs(var - v).max() < 1e-14
     assert np.abs(exc - e).max() < 1e-14
     pb.destroy()
+
+
+def test_single_129_cosine_field_step_solves_the_oracle_system():
+    """The plain single-sample FP64 path of the 129x129x33 workload (one cosine mode of
+    phi, Kozeny-Carman K, xi1 from the seed): its first step zeroes the oracle's residual
+    to the Newton tolerance (replayed sub-step by sub-step if it was split)."""
+    wl = synth.workload("elder129_f64")
+    phys = synth.physics(wl.field_model)
+    g = wl.groups[0]
+    group = (g.nx, g.ny, g.nz, g.levels, 1)
+    pb = _problem(phys, [group], newton_rtol=wl.newton_rtol)
+    pb.set_parameters(wl.xi)
+    st = pb.step(DT)
+    assert st[0]["status"] == 0, st
+    u = pb.get_state(0)
+    pb.destroy()
+    box = elder.Box(g.nx, g.ny, g.nz, phys)
+    coef = elder.coefficients(box, wl.xi[0])
+    sub = st[0]["substeps"]
+    states = ([synth.initial_state(g.nx, g.ny, g.nz, phys), u] if sub == 1 else
+              _substep_states(phys, group, wl.xi[0], sub, dict(newton_rtol=wl.newton_rtol)))
+    for k in range(1, len(states)):
+        r0 = _oracle_scaled_norm(box, coef, states[k - 1], states[k - 1], DT / sub)
+        r = _oracle_scaled_norm(box, coef, states[k], states[k - 1], DT / sub)
+        print(f"129 cosine field, xi1 = {wl.xi[0, 0]:.4f}, sub-step {k}/{sub}: |F~| {r:.3e} of "
+              f"{r0:.3e}", flush=True)
+        assert r <= 2 * wl.newton_rtol * r0 + 1e-10
+    assert -0.05 <= u[..., 1].min() and u[..., 1].max() <= 1.05
+
+
+def test_qmc_batch_mixed_precision_matches_fp64():
+    """A slice of the qMC workload (8 lattice samples of each of its three grids, in one
+    problem, the benchmark's options): two steps with the FP32 V-cycle, and with the
+    finest matrix in FP16, against the FP64 V-cycle.  Samples that took the same
+    sub-steps in both runs agree to 1e-6 relative L2 per field (the bar of the mixed
+    path); every state is admissible."""
+    wl = synth.workload("qmc512_mixedres")
+    phys = synth.physics(wl.field_model)
+    groups, xis, off = [], [], 0
+    for g in wl.groups:
+        groups.append((g.nx, g.ny, g.nz, g.levels, 8))
+        xis.append(wl.xi[off:off + 8])
+        off += g.samples
+    xi = np.concatenate(xis)
+    out = {}
+    for prec in (0, 1, 2):
+        pb = _problem(phys, groups, newton_rtol=wl.newton_rtol, precision=prec)
+        pb.set_parameters(xi)
+        subs = []
+        for _ in range(2):
+            st = pb.step(DT)
+            assert all(t["status"] == 0 for t in st), st
+            subs.append([t["substeps"] for t in st])
+        out[prec] = ([pb.get_state(s) for s in range(24)], np.array(subs))
+        pb.destroy()
+    compared = 0
+    for prec in (1, 2):
+        for s in range(24):
+            if not np.array_equal(out[prec][1][:, s], out[0][1][:, s]):
+                print(f"precision {prec} sample {s}: sub-steps {out[prec][1][:, s]} vs "
+                      f"{out[0][1][:, s]}, not compared", flush=True)
+                continue
+            compared += 1
+            for f in range(2):
+                a, b = out[prec][0][s][..., f], out[0][0][s][..., f]
+                rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+                assert rel <= 1e-6, (prec, s, f, rel)
+            assert -0.05 <= out[prec][0][s][..., 1].min() <= out[prec][0][s][..., 1].max() <= 1.05
+    print(f"{compared} of 48 mixed/FP64 sample pairs compared", flush=True)
+    assert compared >= 40
 
 
 def test_mixed_257_matches_fp64_and_solves_the_oracle_system():

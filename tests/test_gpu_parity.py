@@ -47,7 +47,7 @@ SHAPES = [((9, 9, 3), 2), ((17, 13, 5), 3), ((33, 33, 9), 4), ((41, 25, 9), 3)]
 
 
 @pytest.mark.parametrize("shape,levels", SHAPES)
-@pytest.mark.parametrize("model", [0, 2, 3])
+@pytest.mark.parametrize("model", [0, 1, 2, 3])
 def test_defect_matches_oracle(shape, levels, model):
     nx, ny, nz = shape
     phys = synth.physics(model)
@@ -108,7 +108,7 @@ def _oracle_stencil(box, coef, u):
 
 
 @pytest.mark.parametrize("shape,levels", SHAPES[:3])
-@pytest.mark.parametrize("model", [0, 2])
+@pytest.mark.parametrize("model", [0, 1, 2])
 def test_jacobian_matches_oracle_on_every_level(shape, levels, model):
     nx, ny, nz = shape
     phys = synth.physics(model)
@@ -129,7 +129,8 @@ def test_jacobian_matches_oracle_on_every_level(shape, levels, model):
 
 
 @pytest.mark.parametrize("shape,levels,model", [((9, 9, 3), 2, 0), ((17, 17, 5), 3, 2),
-                                                ((33, 33, 9), 4, 0), ((41, 25, 9), 3, 3)])
+                                                ((33, 33, 9), 4, 0), ((41, 25, 9), 3, 3),
+                                                ((33, 33, 9), 4, 1), ((17, 17, 5), 3, 1)])
 def test_one_step_from_initial_state(shape, levels, model):
     nx, ny, nz = shape
     phys = synth.physics(model)
@@ -171,8 +172,10 @@ def test_step_from_shared_later_state():
     pb.destroy()
 
 
-def test_short_trajectory_33():
-    """Three steps of the 33x33x9 deterministic box, the oracle stepping beside it."""
+def test_trajectory_33_twenty_steps():
+    """The plain-method workload in full: 20 one-month steps of the 33x33x9 deterministic
+    box, the oracle stepping beside it; every step's state within 1e-10 relative L2 per
+    field (the error of each step is printed)."""
     nx, ny, nz = 33, 33, 9
     phys = synth.physics(0)
     pb = _problem(phys, [(nx, ny, nz, 4, 1)])
@@ -180,7 +183,7 @@ def test_short_trajectory_33():
     box = elder.Box(nx, ny, nz, phys)
     coef = elder.coefficients(box, [])
     u = synth.initial_state(nx, ny, nz, phys)
-    for n in range(3):
+    for n in range(20):
         u = newton.newton_solve(box, coef, u, DT)
         pb.step(DT)
         got = pb.get_state(0)

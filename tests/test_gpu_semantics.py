@@ -1,0 +1,214 @@
+"""Step semantics of the library through the C-ABI: failed samples stay failed,
+cumulative counters, the FP64 mass balance, sub-step history, argument errors that
+leave the problem unchanged.  GPU."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import elder, newton, stats
+
+pytestmark = pytest.mark.gpu
+
+DT = synth.MONTH_S
+TIGHT = dict(newton_rtol=1e-13, newton_atol=0.0, lin_rtol=1e-12, lin_max_it=600,
+             newton_max_it=40, check_every=8)
+HARD = np.array([[0.0, 0.0, 0.0, 0.0], [0.9, 0.9, 0.9, 0.9]])  # sample 1: high K
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _problem(phys, groups, **opts):
+    from paper_1906_01632_amd import Problem
+    o = dict(TIGHT)
+    o.update(opts)
+    return Problem(phys, groups, o)
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def test_failed_sample_stays_failed_until_reset():
+    """Sample 1 cannot take a 4-month step without halving: it fails in step 1, keeps
+    its state, and is not advanced in step 2 (a 1-month step it could take); the
+    moments after step 2 hold sample 0 alone.  edf_set_state resets it, after which it
+    is advanced and counted again."""
+    nx, ny, nz = 17, 17, 5
+    phys = synth.physics(2)
+    pb = _problem(phys, [(nx, ny, nz, 3, 2)], dt_max_halvings=0)
+    pb.set_parameters(HARD)
+    u1_start = pb.get_state(1)
+    st = pb.step(4 * DT)
+    assert st[0]["status"] == 0 and st[1]["status"] != 0
+    assert st[1]["failed_step"] == 1 and st[1]["steps_total"] == 0
+    fail_code = st[1]["status"]
+    st = pb.step(DT)
+    assert st[0]["status"] == 0 and st[0]["steps_total"] == 2
+    assert st[1]["status"] == fail_code and st[1]["newton_its"] == 0 and st[1]["substeps"] == 0
+    assert st[1]["failed_step"] == 1
+    np.testing.assert_array_equal(pb.get_state(1), u1_start)
+    mean, var, _ = pb.moments((9, 9, 3))
+    c0 = stats.inject(pb.get_state(0)[..., 1], (9, 9, 3))
+    assert np.abs(mean - c0).max() < 1e-15 and np.abs(var).max() < 1e-30
+    # reset: a new state makes it a running sample again
+    pb.set_state(1, u1_start)
+    st = pb.step(DT)
+    assert st[1]["status"] == 0 and st[1]["failed_step"] == 0 and st[1]["steps_total"] == 1
+    box = elder.Box(nx, ny, nz, phys)
+    ref = newton.newton_solve(box, elder.coefficients(box, HARD[1]), u1_start, DT)
+    for f in range(2):
+        assert _rel(pb.get_state(1)[..., f], ref[..., f]) < 1e-10
+    pb.destroy()
+
+
+def test_every_sample_failed_is_an_error():
+    from paper_1906_01632_amd import EDFError
+    pb = _problem(synth.physics(2), [(17, 17, 5, 3, 1)], dt_max_halvings=0)
+    pb.set_parameters(HARD[1:])
+    with pytest.raises(EDFError, match="EDF_ERR_NO_CONVERGENCE"):
+        pb.step(4 * DT)
+    with pytest.raises(EDFError, match="EDF_ERR_NO_CONVERGENCE"):
+        pb.step(DT)  # still failed: nothing is left to advance
+    pb.destroy()
+
+
+def test_counters_over_split_steps():
+    """Retries, sub-steps and split steps are counted per step and in total."""
+    nx, ny, nz = 17, 17, 5
+    pb = _problem(synth.physics(2), [(nx, ny, nz, 3, 2)], dt_max_halvings=4)
+    pb.set_parameters(HARD)
+    a = pb.step(4 * DT)
+    b = pb.step(4 * DT)
+    for s in range(2):
+        assert a[s]["status"] == 0 and b[s]["status"] == 0
+        assert b[s]["steps_total"] == 2
+        assert b[s]["substeps_total"] == a[s]["substeps"] + b[s]["substeps"]
+        assert b[s]["split_total"] == (a[s]["substeps"] > 1) + (b[s]["substeps"] > 1)
+        assert b[s]["retries_total"] == a[s]["retries"] + b[s]["retries"]
+        # without sub-step memory every step starts at the full length
+        assert 2 ** a[s]["retries"] == a[s]["substeps"]
+    assert a[0]["substeps"] == 1 and a[1]["substeps"] >= 2
+    pb.destroy()
+
+
+def test_step_without_memory_is_one_euler_step_when_it_converges():
+    """After a step that needed sub-steps, the next (shorter) step of the same sample is
+    again tried whole (substep_memory = 0) and equals the oracle's single implicit-Euler
+    step from that state; with substep_memory = 1 it starts split."""
+    nx, ny, nz = 17, 17, 5
+    phys = synth.physics(2)
+    box = elder.Box(nx, ny, nz, phys)
+    res = {}
+    for memory in (0, 1):
+        pb = _problem(phys, [(nx, ny, nz, 3, 1)], dt_max_halvings=4, substep_memory=memory)
+        pb.set_parameters(HARD[1:])
+        assert pb.step(4 * DT)[0]["substeps"] >= 2
+        u = pb.get_state(0)
+        res[memory] = (pb.step(DT)[0], u, pb.get_state(0))
+        pb.destroy()
+    st, u, got = res[0]
+    assert st["substeps"] == 1
+    ref = newton.newton_solve(box, elder.coefficients(box, HARD[1]), u, DT)
+    for f in range(2):
+        assert _rel(got[..., f], ref[..., f]) < 1e-10
+    assert res[1][0]["substeps"] >= 2
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_mass_balance_matches_the_oracle_definition(precision):
+    """edf_step_stats' salt and liquid balance errors: tiny for tightly converged steps
+    (FP64 Newton also when the V-cycle runs in FP32), and, for a step stopped early
+    (Newton rtol 1e-2), equal to the oracle's mass_balance evaluated at the library's
+    own start and end states."""
+    nx, ny, nz = 17, 17, 5
+    phys = synth.physics(2)
+    xi = np.random.default_rng(12).uniform(-0.7, 0.7, (2, 4))
+    box = elder.Box(nx, ny, nz, phys)
+    for rtol, bound in ((1e-13, 1e-9), (1e-2, None)):
+        pb = _problem(phys, [(nx, ny, nz, 3, 2)], precision=precision, newton_rtol=rtol)
+        pb.set_parameters(xi)
+        pb.step(DT)  # a developed start state
+        u_old = [pb.get_state(s) for s in range(2)]
+        st = pb.step(DT)
+        for s in range(2):
+            assert st[s]["status"] == 0 and st[s]["substeps"] == 1
+            ref = elder.mass_balance(box, elder.coefficients(box, xi[s]), pb.get_state(s),
+                                     u_old[s], DT)
+            got = (st[s]["salt_balance_err"], st[s]["liquid_balance_err"])
+            want = (ref["salt"]["err"], ref["liquid"]["err"])
+            print(f"rtol {rtol} sample {s}: library {got}, oracle {want}", flush=True)
+            if bound is not None:
+                assert max(got) < bound and max(want) < bound
+            else:
+                assert min(want) > 1e-7  # a real imbalance, far above rounding
+                for g_, w_ in zip(got, want):
+                    assert abs(g_ - w_) <= 1e-6 * w_
+        pb.destroy()
+
+
+def test_mass_balance_sums_over_substeps():
+    """A step split into sub-steps: the balance is that of the whole step (storage from
+    the step's start to its end, boundary exchange summed over the sub-steps), small
+    when every sub-step converged."""
+    nx, ny, nz = 17, 17, 5
+    pb = _problem(synth.physics(2), [(nx, ny, nz, 3, 2)], dt_max_halvings=4)
+    pb.set_parameters(HARD)
+    st = pb.step(4 * DT)
+    assert st[1]["substeps"] >= 2
+    for s in range(2):
+        assert st[s]["salt_balance_err"] < 1e-9 and st[s]["liquid_balance_err"] < 1e-9
+    pb.destroy()
+
+
+def test_invalid_parameters_leave_the_fields_unchanged():
+    """A parameter point whose porosity leaves (0, 1) somewhere (phi_mean = 0.9 with a
+    +40 % mode) is rejected before any level's fields are written: the residual of a
+    fixed state is bitwise the one before the call."""
+    from paper_1906_01632_amd import EDFError
+    nx, ny, nz = 9, 9, 3
+    phys = synth.physics(2, phi_mean=0.9)
+    pb = _problem(phys, [(nx, ny, nz, 2, 1)])
+    pb.set_parameters(np.zeros((1, 4)))
+    u = synth.random_state(nx, ny, nz, phys, seed=3)
+    r0 = pb.residual(0, u, u, DT)
+    with pytest.raises(EDFError, match="EDF_ERR_ARG"):
+        pb.set_parameters(np.array([[1.0, 1.0, 0.0, 0.0]]))
+    np.testing.assert_array_equal(pb.residual(0, u, u, DT), r0)
+    pb.destroy()
+
+
+def test_gradient_does_not_depend_on_call_history():
+    """With sub-step memory on, a step that needed sub-steps raises the sample's
+    starting sub-step count; the autograd wrapper (edf_set_parameters clears the
+    history, edf_set_state restores the start) still gives the same J and dJ/dxi on
+    every call, equal to those of a fresh problem from the same state."""
+    import torch
+    from paper_1906_01632_amd import salt_mass
+    nx, ny, nz = 17, 17, 5
+    phys = synth.physics(2)
+    box = (200.0, 400.0, 200.0, 400.0, 0.0, 60.0)
+    pb = _problem(phys, [(nx, ny, nz, 3, 2)], dt_max_halvings=4, substep_memory=1)
+    pb.set_parameters(HARD)
+    assert pb.step(4 * DT)[1]["substeps"] >= 2   # sample 1 now starts split
+    u0 = [pb.get_state(s) for s in range(2)]
+    out = []
+    for _ in range(2):
+        xi = torch.tensor(HARD, dtype=torch.float64, requires_grad=True)
+        J = salt_mass(xi, pb, box, 2 * DT, 2, 1)
+        J.sum().backward()
+        out.append((J.detach().numpy().copy(), xi.grad.numpy().copy()))
+    pb.destroy()
+    fresh = _problem(phys, [(nx, ny, nz, 3, 2)], dt_max_halvings=4, substep_memory=1)
+    fresh.set_parameters(HARD)
+    for s in range(2):
+        fresh.set_state(s, u0[s])
+    Jf, gf = fresh.gradient(box, 2 * DT, 2, checkpoint_every=1)
+    fresh.destroy()
+    for J, g in out:
+        np.testing.assert_array_equal(J, Jf)
+        np.testing.assert_array_equal(g, gf)

@@ -62,6 +62,51 @@ def test_kozeny_carman_normalisation():
     assert 8.0 < r < 8.2
 
 
+def test_kozeny_carman_denominator():
+    """K at phi = 0.08 and 0.12 from the perturbed-field workload's law (phi/0.1)^3
+    ((1-0.1)/(1-phi))^2, hand-computed; the paper's printed phi^3/(1-phi^2) (normalised
+    the same way) differs by 2-4 % there, so the reading is pinned, not only K(E phi)."""
+    g = _load("field_values.json")["kozeny_carman"]
+    ph = synth.physics(1)
+    for phi, want, printed in zip(g["phi"], g["K_over_Kmean"], g["K_over_Kmean_printed_form"]):
+        got = elder.kozeny_carman(np.array(phi), ph) / ph["K_mean"]
+        assert got == pytest.approx(want, rel=1e-14)
+        assert abs(got - printed) > 0.02 * printed
+
+
+@pytest.mark.parametrize("model", [1, 2, 3])
+def test_field_models_at_exact_points(model):
+    """phi and K per hexahedron on small grids whose centroids make every trigonometric
+    factor exact (+-1/2, +-sqrt(2)/2, +-sqrt(3)/2, 0, 1), hand-computed from the field
+    formulas (model 3: the paper's eq. poro-paral3RVS).  The grids give the x, y and z
+    factors different values, so a swapped coordinate, a sin for a cos, a dropped
+    cross term or a wrong amplitude changes some entry."""
+    g = _load("field_values.json")[f"model{model}"]
+    nx, ny, nz = g["grid"]
+    box = elder.Box(nx, ny, nz, synth.physics(model))
+    np.testing.assert_allclose(box.xc[0, 0, :], g["centroid_x"], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(box.yc[0, :, 0], g["centroid_y"], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(box.zc[:, 0, 0], g["centroid_z"], rtol=0, atol=1e-12)
+    phi, K = elder.coefficients(box, g["xi"])
+    np.testing.assert_allclose(phi.ravel(), g["phi"], rtol=1e-14)
+    np.testing.assert_allclose(K.ravel(), g["K"], rtol=1e-13)
+
+
+@pytest.mark.parametrize("shape", [(33, 33, 9), (65, 65, 17)])
+def test_boundary_vertex_sets(shape):
+    """The closed top patch [150, 450]^2 (its edge vertices included), the bottom face and
+    the four pinned top corners, counted on the workloads' grids."""
+    g = _load("field_values.json")["patch_vertices"]["x".join(map(str, shape))]
+    box = elder.Box(*shape, synth.physics(0))
+    cmask, cval = box.dirichlet_c()
+    assert int((cmask & (cval == 1.0)).sum()) == g["patch"]
+    assert int((cmask & (cval == 0.0)).sum()) == g["bottom"]
+    assert int(cmask.sum()) == g["patch"] + g["bottom"]
+    assert int(box.pinned_p().sum()) == g["pinned_p"]
+    u0 = synth.initial_state(*shape, synth.physics(0))
+    assert int((u0[..., 1] == 1.0).sum()) == g["patch"]
+
+
 # -------------------------------------------------------------- jacobian ---
 
 @pytest.mark.parametrize("shape,model", [((5, 5, 2), 0), ((5, 5, 3), 2), ((7, 5, 3), 1),
@@ -275,6 +320,39 @@ def test_global_mass_balance(model):
     s = elder.row_scale(box, DT)[..., 0]
     assert np.abs((Fs * s)[~cmask]).max() < 1e-11
     assert np.abs((Fl * s)[~pmask]).max() < 1e-11
+    bal = elder.mass_balance(box, coef, u2, u1, DT)
+    assert bal["salt"]["dM"] == pytest.approx(dsalt, rel=1e-14)
+    assert bal["salt"]["err"] < 1e-9 and bal["liquid"]["err"] < 1e-9
+
+
+def test_mass_balance_detects_a_planted_imbalance():
+    """Adding salt by hand at one interior vertex with no Dirichlet vertex among its 27
+    neighbours (so no Dirichlet row sees it) changes the storage by m_v [rho(c+d)(c+d) - rho(c) c] with
+    m_v = phi hx hy hz (constant phi, all 8 octants) and leaves the boundary exchange
+    alone, so dM - B of mass_balance grows by exactly that amount; the liquid balance
+    grows by m_v (rho1 - rho0) d."""
+    ph = synth.physics(0)
+    nx, ny, nz = 9, 9, 7
+    box = elder.Box(nx, ny, nz, ph)
+    coef = elder.coefficients(box, [])
+    u0 = synth.initial_state(nx, ny, nz, ph)
+    u1 = newton.newton_solve(box, coef, u0, DT)
+    base = elder.mass_balance(box, coef, u1, u0, DT)
+    k, j, i, d = 3, 1, 4, 0.05   # no Dirichlet vertex among its 27 neighbours (checked)
+    cmask, _ = box.dirichlet_c()
+    near = cmask[max(k - 1, 0):k + 2, max(j - 1, 0):j + 2, max(i - 1, 0):i + 2]
+    assert not near.any() and not box.pinned_p()[k, j, i]
+    u2 = u1.copy()
+    u2[k, j, i, 1] += d
+    bal = elder.mass_balance(box, coef, u2, u0, DT)
+    m = ph["phi_mean"] * np.prod(box.h)
+    rho = lambda c: ph["rho0"] + (ph["rho1"] - ph["rho0"]) * c
+    c = u1[k, j, i, 1]
+    planted = m * (rho(c + d) * (c + d) - rho(c) * c)
+    for eq, amount in (("salt", planted), ("liquid", m * (ph["rho1"] - ph["rho0"]) * d)):
+        got = (bal[eq]["dM"] - bal[eq]["B"]) - (base[eq]["dM"] - base[eq]["B"])
+        assert got == pytest.approx(amount, rel=1e-9), eq
+        assert bal[eq]["err"] > 1e3 * base[eq]["err"]
 
 
 # ------------------------------------------------------------- symmetry ----
@@ -420,21 +498,23 @@ def test_qoi_weights_are_exact_volumes():
     assert gradient.qoi(box, coef, u) == pytest.approx(0.5 * rho * 0.3 * 200 * 200 * 50, rel=1e-13)
 
 
-def test_tangent_linear_gradient_matches_finite_differences():
+@pytest.mark.parametrize("model,xi", [(1, [0.7]), (2, [0.3, -0.5, 0.2, 0.6]), (3, [0.6, -0.4, 0.9])])
+def test_tangent_linear_gradient_matches_finite_differences(model, xi):
     """dJ/dxi from tangent-linear sensitivities equals central differences of the
-    forward map (h = 1e-6), over three steps of a 9x9x5 box with the 4-mode field."""
+    forward map (h = 1e-6), over three steps of a 9x9x5 box, for the one-mode, the
+    four-mode and the paper's three-variable field."""
     from oracle import gradient
-    ph = synth.physics(2)
+    ph = synth.physics(model)
     box = elder.Box(9, 9, 5, ph)
     S = (200.0, 400.0, 200.0, 400.0, 0.0, 60.0)
-    xi = np.array([0.3, -0.5, 0.2, 0.6])
+    xi = np.array(xi)
     u0 = synth.initial_state(9, 9, 5, ph)
     dts = [DT, DT, DT]
     J, g, _ = gradient.tangent_linear_gradient(box, xi, u0, dts, S)
     assert J > 0
     h = 1e-6
-    for m in range(4):
-        e = np.zeros(4)
+    for m in range(xi.size):
+        e = np.zeros(xi.size)
         e[m] = h
         Jp = gradient.qoi(box, elder.coefficients(box, xi + e),
                           gradient.forward(box, xi + e, u0, dts)[-1], S)
