@@ -187,6 +187,152 @@ def cpu_baseline(wl, phys, budget_s=20.0):
                       f"{os.cpu_count()} logical CPUs, {platform.processor() or platform.machine()}"}
 
 
+PREC_NAMES = {"f64": "f64", "mixed": "f64+f32", "mixed16": "f64+f32+f16"}
+
+
+def make_problem(args, wl, phys, groups, prec, log_tuning=True):
+    """A problem of the workload with the benchmark's solver options, parameters set and
+    the V-cycle bottom tuned (or fixed by --fuse-from)."""
+    import numpy as np
+
+    from paper_1906_01632_amd import PREC_F64, PREC_MIXED, PREC_MIXED_F16, Problem
+    # the adjoint solves (transposed Jacobian, no Newton retry) get more Krylov iterations
+    opts = dict(newton_rtol=wl.newton_rtol, lin_rtol=1e-6, lin_max_it=400 if args.adjoint else 100,
+                newton_max_it=20,
+                precision={"f64": PREC_F64, "mixed": PREC_MIXED, "mixed16": PREC_MIXED_F16}[prec],
+                check_every=1, forcing=args.forcing, concurrent_groups=int(args.concurrent_groups),
+                graph_vcycle=int(args.graph), substep_memory=int(args.substep_memory),
+                smoother=int(args.smoother), matrix_free=int(args.matrix_free))
+    t = time.perf_counter()
+    pb = Problem(phys, groups, opts)
+    pb.set_parameters(wl.xi)
+    if args.fuse_from:
+        levels = [int(v) for v in args.fuse_from.split(",")]
+        assert len(levels) == len(groups), "--fuse-from needs one level per group"
+        for gi, lv in enumerate(levels):
+            pb.set_tuning(gi, lv)
+    elif not args.no_autotune:
+        pb.autotune(wl.dt)
+    tuning = [pb.tuning(g)[0] for g in range(len(groups))]
+    if log_tuning:
+        for gi in range(len(groups)):
+            log(f"group {gi}: V-cycle ms per first fused level "
+                f"{np.round(pb.tuning(gi)[1], 3).tolist()}")
+    log(f"set-up {time.perf_counter() - t:.1f} s; fused V-cycle bottom from levels {tuning}")
+    return pb, tuning
+
+
+def run_steps(args, wl, pb, prec, region=(None, None)):
+    """W warm-up steps, then K timed steps with the smoother and V-cycle event timing on;
+    returns the leg's measurements."""
+    import numpy as np
+    import torch
+    warm = []
+    for w in range(args.warmup):
+        t = time.perf_counter()
+        warm.append(pb.step(wl.dt))
+        log(f"[{prec}] warmup step {w + 1}: {time.perf_counter() - t:.2f} s")
+    torch.cuda.synchronize()
+    if not args.no_profile:
+        pb.profile(True)
+    if args.copy_probe:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    if region[0]:
+        region[0]()
+    per_step = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        per_step.append(pb.step(wl.dt))
+        if k < 10 or (k + 1) % 50 == 0 or k + 1 == args.steps:
+            log(f"[{prec}] step {k + 1}: {time.perf_counter() - t0:.2f} s elapsed")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    if region[1]:
+        region[1]()
+    prof = pb.profile(False)
+    S = wl.n_samples
+    last = per_step[-1]
+    # over all timed sample-steps: Newton and BiCGStab work, steps split into sub-steps,
+    # failed attempts restarted with shorter sub-steps, samples failed, mass balance
+    ran = [t for st in per_step for t in st if t["newton_its"] > 0]
+    newton = sum(t["newton_its"] for t in ran)
+    lin = sum(t["lin_its"] for t in ran)
+    solver = {
+        "sample_steps": len(ran),
+        "newton_its_per_sample_step": newton / max(len(ran), 1),
+        "bicgstab_its_per_newton": lin / max(newton, 1),
+        "split_sample_steps": sum(t["substeps"] > 1 for t in ran),
+        "substeps_per_sample_step": sum(t["substeps"] for t in ran) / max(len(ran), 1),
+        "restarted_attempts": sum(t["retries"] for t in ran),
+        "failed_samples": sum(t["status"] != 0 for t in last),
+        "max_salt_balance_err": max((t["salt_balance_err"] for t in ran), default=0.0),
+        "max_liquid_balance_err": max((t["liquid_balance_err"] for t in ran), default=0.0),
+    }
+    leg = {"value": S * args.steps / el, "el": el, "prof": prof, "solver": solver,
+           # sub-steps of every sample in every step, warm-up included
+           "substeps": np.array([[t["substeps"] for t in st] for st in warm + per_step])}
+    if prof["vcycles"]:
+        vg = prof["vcycle_bytes"] / (prof["vcycle_ms"] * 1e-3) / 1e9
+        leg["vcycle"] = {"achieved": vg, "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                         "frac": vg / HBM_PEAK_GBS, "count": prof["vcycles"],
+                         "avg_ms": prof["vcycle_ms"] / prof["vcycles"],
+                         "bytes_per_vcycle": prof["vcycle_bytes"] / prof["vcycles"]}
+    return leg
+
+
+def roofline_of(leg, wl, prec, smoother):
+    """The dominant kernel (the V-cycle smoother) from the leg's event timing."""
+    prof = leg["prof"]
+    if not prof["launches"]:
+        return None
+    gbs = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9
+    tr = measured_traffic()
+    traffic = ratio = None
+    if tr and tr.get("workload") == wl.name and tr.get("precision") == prec and \
+            tr.get("smoother", 0) == smoother:
+        # HBM bytes per launch of this run's launch mix: the measured ratio of HBM to
+        # algorithmic bytes times this run's algorithmic bytes per launch
+        ratio = tr["ratio"]
+        traffic = ratio * prof["all_bytes"] / prof["all_launches"]
+    name = ("k_line_smooth (vertical-line block Gauss-Seidel, one column colour)" if smoother
+            else "k_smooth (block Gauss-Seidel colour sweep)")
+    return {"bound": "hbm", "kernel": name, "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "traffic": traffic, "traffic_over_algorithmic": ratio,
+            "launches": prof["all_launches"], "launches_timed": prof["launches"],
+            "avg_launch_us": 1e3 * prof["ms"] / prof["launches"],
+            "bytes_per_launch": prof["bytes"] / prof["launches"],
+            "bytes_per_launch_all": prof["all_bytes"] / prof["all_launches"]}
+
+
+def compare_states(ref_states, ref_sub, pb, sub, S):
+    """Relative L2 per field of pb's states against ref_states, over the samples that took
+    the same sub-steps in every timed step (a different sub-step sequence is a different
+    discrete trajectory)."""
+    import numpy as np
+    worst = {"p": 0.0, "c": 0.0}
+    med = {"p": [], "c": []}
+    compared = 0
+    for s in range(S):
+        if not np.array_equal(ref_sub[:, s], sub[:, s]) or ref_states[s] is None:
+            continue
+        u = pb.get_state(s)
+        compared += 1
+        for f, name in ((0, "p"), (1, "c")):
+            a, b = u[..., f], ref_states[s][..., f]
+            r = float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+            worst[name] = max(worst[name], r)
+            med[name].append(r)
+    return {"rel_l2_p_max": worst["p"], "rel_l2_c_max": worst["c"],
+            "rel_l2_p_median": float(np.median(med["p"])) if med["p"] else None,
+            "rel_l2_c_median": float(np.median(med["c"])) if med["c"] else None,
+            "samples_compared": compared, "samples_other_substeps": S - compared,
+            "within_1e-6": worst["p"] <= 1e-6 and worst["c"] <= 1e-6}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,7 +340,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="qmc512_mixedres")
     ap.add_argument("--precision", choices=["f64", "mixed", "mixed16"], default=None,
-                    help="V-cycle precision: FP64, FP32, or FP32 with the finest matrix in FP16")
+                    help="V-cycle precision: FP64, FP32, or FP32 with the finest matrix in FP16 "
+                         "(one leg); without it the qMC workload runs an FP64 leg and then the "
+                         "FP32-V-cycle leg, compared field by field")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--graph", action="store_true",
@@ -202,14 +350,22 @@ def main():
                          "it (implies --no-profile: the roofline times single launches)")
     ap.add_argument("--forcing", type=int, default=1, choices=[0, 1],
                     help="1: Eisenstat-Walker tolerances for the Newton systems")
+    ap.add_argument("--smoother", type=int, default=0, choices=[0, 1],
+                    help="0: point-block Gauss-Seidel in 8 colours; 1: vertical-line block "
+                         "Gauss-Seidel (z-columns solved exactly, 4 column colours)")
+    ap.add_argument("--matrix-free", type=int, default=0, choices=[0, 1],
+                    help="1: matrix-free Jacobian products in BiCGStab (no exact stencil)")
+    ap.add_argument("--substep-memory", type=int, default=1, choices=[0, 1],
+                    help="1: a sample starts a step with the sub-step count that worked in its "
+                         "previous step")
     ap.add_argument("--concurrent-groups", action="store_true",
                     help="advance the grid groups at the same time (one host thread and stream "
                          "each); more throughput, but overlapping kernels lengthen the per-launch "
                          "durations the roofline is computed from")
     ap.add_argument("--adjoint", action="store_true",
-                    help="time the gradient instead of plain steps: edf_adjoint over --steps steps "
-                         "(forward with checkpoints, then the backward sweep) of the salt mass in "
-                         "the lower-central box")
+                    help="time the gradient instead of plain steps: edf_solve with a checkpoint "
+                         "every 10 steps over --steps steps, then edf_adjoint (segments "
+                         "recomputed) of the salt mass in the lower-central box")
     ap.add_argument("--gpc", action="store_true",
                     help="time the polynomial chaos surrogate instead of plain steps: solve the "
                          "quadrature nodes' samples (untimed), then project them (degree 4) and "
@@ -225,7 +381,7 @@ def main():
                     help="copy 1 GiB device-to-device at the start of the timed region (a copy "
                          "of known size that calibrates the HBM byte counters)")
     args = ap.parse_args()
-    region_start, region_stop = roctx_range() if args.mark_timed_region else (None, None)
+    region = roctx_range() if args.mark_timed_region else (None, None)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): samples are independent, "
               "so N GPUs would each run their own share; no multi-GPU path is built.",
@@ -236,76 +392,40 @@ def main():
     import torch
 
     import synth
-    from paper_1906_01632_amd import PREC_F64, PREC_MIXED, PREC_MIXED_F16, Problem
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     wl = synth.workload(args.workload)
-    prec = args.precision or wl.precision
     phys = synth.physics(wl.field_model)
     groups = [(g.nx, g.ny, g.nz, g.levels, g.samples) for g in wl.groups]
-    # the adjoint solves (transposed Jacobian, no Newton retry) get more Krylov iterations
-    opts = dict(newton_rtol=wl.newton_rtol, lin_rtol=1e-6, lin_max_it=400 if args.adjoint else 100,
-                newton_max_it=20,
-                precision={"f64": PREC_F64, "mixed": PREC_MIXED, "mixed16": PREC_MIXED_F16}[prec],
-                check_every=1,
-                forcing=args.forcing, concurrent_groups=int(args.concurrent_groups),
-                graph_vcycle=int(args.graph))
     if args.graph:
         args.no_profile = True
+    two_legs = args.precision is None and wl.name == "qmc512_mixedres" and not (args.adjoint or args.gpc)
+    prec = args.precision or ("mixed" if two_legs else wl.precision)
+    S = wl.n_samples
+    ref = None
+    if two_legs:
+        # the FP64 leg: the reference the mixed-precision states are compared with
+        log(f"workload {wl.name}: groups {groups}, FP64 leg")
+        pb, tuning64 = make_problem(args, wl, phys, groups, "f64")
+        leg64 = run_steps(args, wl, pb, "f64")
+        ref = ([pb.get_state(s) for s in range(S)], leg64["substeps"])
+        pb.destroy()
+        torch.cuda.synchronize()
     log(f"workload {wl.name}: groups {groups}, precision {prec}")
-    t = time.perf_counter()
-    pb = Problem(phys, groups, opts)
-    pb.set_parameters(wl.xi)
-    if args.fuse_from:
-        levels = [int(v) for v in args.fuse_from.split(",")]
-        assert len(levels) == len(groups), "--fuse-from needs one level per group"
-        for gi, lv in enumerate(levels):
-            pb.set_tuning(gi, lv)
-    elif not args.no_autotune:
-        pb.autotune(wl.dt)
-    tuning = [pb.tuning(g)[0] for g in range(len(groups))]
-    for gi in range(len(groups)):
-        log(f"group {gi}: V-cycle ms per first fused level {np.round(pb.tuning(gi)[1], 3).tolist()}")
-    log(f"set-up {time.perf_counter() - t:.1f} s; fused V-cycle bottom from levels {tuning}")
-    for w in range(args.warmup):
-        t = time.perf_counter()
-        pb.step(wl.dt)
-        log(f"warmup step {w + 1}: {time.perf_counter() - t:.2f} s")
-    torch.cuda.synchronize()
+    pb, tuning = make_problem(args, wl, phys, groups, prec)
     if args.adjoint:
+        for w in range(args.warmup):
+            pb.step(wl.dt)
         return run_adjoint(args, wl, pb, prec)
     if args.gpc:
         return run_gpc(args, wl, pb, prec)
-    if not args.no_profile:
-        pb.profile(True)
-    stats = None
-    if args.copy_probe:
-        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
-    if region_start:
-        region_start()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        stats = pb.step(wl.dt)
-        if k < 10 or (k + 1) % 50 == 0 or k + 1 == args.steps:
-            log(f"step {k + 1}: {time.perf_counter() - t0:.2f} s elapsed")
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    if region_stop:
-        region_stop()
-    prof = pb.profile(False)
-    S = wl.n_samples
+    leg = run_steps(args, wl, pb, prec, region)
+    el = leg["el"]
     dofs = sum(2 * g.n_vertices * g.samples for g in wl.groups)
-    newton = np.mean([s["newton_its"] for s in stats])
-    lin = np.mean([s["lin_its"] / max(s["newton_its"], 1) for s in stats])
-    failed = sum(s["status"] != 0 for s in stats)
     out = {
         "metric": METRIC,
-        "value": S * args.steps / el,
+        "value": leg["value"],
         "unit": "sample-timesteps/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -314,44 +434,35 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f64": "f64", "mixed": "f64+f32", "mixed16": "f64+f32+f16"}[prec],
+        "dtype": PREC_NAMES[prec],
         "data": ("synthetic (Halton points and Gauss-Legendre nodes; no dataset)"
                  if wl.name in synth.E1_GRIDS else "synthetic (seeded lattice parameters; no dataset)"),
         "config": {"workload": wl.name, "groups": [list(g) for g in groups], "samples": S,
                    "dt_s": wl.dt, "precision": prec, "newton_rtol": wl.newton_rtol,
                    "lin_rtol": 1e-6, "lin_max_it": 100,
                    "forcing": "eisenstat-walker" if args.forcing else "fixed",
+                   "smoother": ["point-block-gs-8-colour", "z-line-block-gs-4-colour"][args.smoother],
+                   "matrix_free_jacobian": bool(args.matrix_free),
+                   "substep_memory": bool(args.substep_memory),
                    "fused_bottom_from_level": tuning,
                    "concurrent_groups": bool(args.concurrent_groups),
                    "graph_vcycle": bool(args.graph)},
         "dof_timesteps_per_s": dofs * args.steps / el,
-        "solver": {"newton_its_per_step": newton, "bicgstab_its_per_newton": lin,
-                   "failed_samples_last_step": failed},
+        "solver": leg["solver"],
     }
-    if prof["vcycles"]:
-        vg = prof["vcycle_bytes"] / (prof["vcycle_ms"] * 1e-3) / 1e9
-        out["vcycle"] = {"achieved": vg, "unit": "GB/s", "peak": HBM_PEAK_GBS,
-                         "frac": vg / HBM_PEAK_GBS, "count": prof["vcycles"],
-                         "avg_ms": prof["vcycle_ms"] / prof["vcycles"],
-                         "bytes_per_vcycle": prof["vcycle_bytes"] / prof["vcycles"]}
-    if prof["launches"]:
-        gbs = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9
-        tr = measured_traffic()
-        traffic = ratio = None
-        if tr and tr.get("workload") == wl.name and tr.get("precision") == prec:
-            # HBM bytes per launch of this run's launch mix: the measured ratio of HBM to
-            # algorithmic bytes times this run's algorithmic bytes per launch
-            ratio = tr["ratio"]
-            traffic = ratio * prof["all_bytes"] / prof["all_launches"]
-        out["roofline"] = {"bound": "hbm", "kernel": "k_smooth (block Gauss-Seidel colour sweep)",
-                           "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
-                           "traffic_over_algorithmic": ratio,
-                           "launches": prof["all_launches"],
-                           "launches_timed": prof["launches"],
-                           "avg_launch_us": 1e3 * prof["ms"] / prof["launches"],
-                           "bytes_per_launch": prof["bytes"] / prof["launches"],
-                           "bytes_per_launch_all": prof["all_bytes"] / prof["all_launches"]}
+    if "vcycle" in leg:
+        out["vcycle"] = leg["vcycle"]
+    rl = roofline_of(leg, wl, prec, args.smoother)
+    if rl:
+        out["roofline"] = rl
+    if two_legs:
+        out["mixed_vs_fp64"] = compare_states(ref[0], ref[1], pb, leg["substeps"], S)
+        out["fp64"] = {"value": leg64["value"], "ms_per_step": 1e3 * leg64["el"] / args.steps,
+                       "dtype": "f64", "fused_bottom_from_level": tuning64,
+                       "solver": leg64["solver"], "vcycle": leg64.get("vcycle"),
+                       "roofline": roofline_of(leg64, wl, "f64", args.smoother)}
+        out["mixed_over_fp64"] = leg["value"] / leg64["value"]
+        log(f"mixed vs FP64: {out['mixed_vs_fp64']}; {out['mixed_over_fp64']:.3f} x the FP64 rate")
     if wl.name in synth.E1_GRIDS:
         # the box experiment's comparison after the last timed step: 200 Halton qMC samples
         # (group 0) against the degree-4 surrogate from the 125 quadrature nodes (group 1)
@@ -375,9 +486,9 @@ def main():
             if L < len(n):  # the partners of level L stay out
                 w[sum(n[:L]) + sum(n[1:L]):] = 0.0
             est.append(pb.moments(common, weights=w))
-        ref = np.linalg.norm(est[0][0])
+        ref0 = np.linalg.norm(est[0][0])
         out["mlmc"] = {"levels": list(n), "grids": [[g.nx, g.ny, g.nz] for g in wl.groups],
-                       "correction_rel_l2": [float(np.linalg.norm(est[L][0] - est[L - 1][0]) / ref)
+                       "correction_rel_l2": [float(np.linalg.norm(est[L][0] - est[L - 1][0]) / ref0)
                                              for L in range(1, len(n))],
                        "mean_range": [float(est[-1][0].min()), float(est[-1][0].max())],
                        "max_var": float(est[-1][1].max()),
@@ -385,10 +496,10 @@ def main():
                                                                              for q in wl.groups)
                                             for g in wl.groups]}
         log(f"multilevel: {out['mlmc']}")
+    pb.destroy()
     if not args.no_cpu_baseline:
         log("oracle timing on the host ...")
         out["cpu_baseline"] = cpu_baseline(wl, phys)
-    pb.destroy()
     print(json.dumps(out), flush=True)
 
 

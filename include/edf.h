@@ -135,7 +135,21 @@ typedef struct {
                            /* sub-steps that worked for it in its previous step     */
                            /* (fewer failed attempts, but the result then depends  */
                            /* on the sample's history; see edf_step)                */
-  int32_t reserved[3];     /* must be zero                                         */
+  int32_t smoother;        /* the multigrid smoother on the levels swept by their   */
+                           /* own launches: 0 point-block Gauss-Seidel in 8 colours */
+                           /* (i%2, j%2, k%2); 1 vertical-line block Gauss-Seidel:  */
+                           /* every z-column's block tridiagonal system solved      */
+                           /* exactly, columns in 4 colours (i%2, j%2), the other  */
+                           /* couplings lagged (the levels of the fused bottom and  */
+                           /* an FP16-stored finest level keep the point smoother)  */
+  int32_t matrix_free;     /* the outer BiCGStab's products J x: 0 with the exact    */
+                           /* FP64 Jacobian assembled as a 27-point stencil of 2x2  */
+                           /* blocks (864 bytes per vertex); 1 matrix-free, the     */
+                           /* directional derivative of the defect computed from    */
+                           /* the state, the coefficients and x (the same operator, */
+                           /* no exact finest-level stencil stored; the adjoint's   */
+                           /* transposed products stay assembled)                   */
+  int32_t reserved[1];     /* must be zero                                         */
 } edf_solver_opts;
 
 /* Per-sample result of a step.  Counters named *_total run over every step since the
@@ -175,9 +189,14 @@ typedef struct {
 
 /* Quantity of interest of the adjoint (kind 0, the only kind): the salt mass in the
  * box [box[0],box[1]] x [box[2],box[3]] x [box[4],box[5]] (SI units, z = depth) at the
- * final time. */
+ * final time.  rtol: relative residual tolerance of the adjoint BiCGStab solves (0: the
+ * default 1e-12).  The gradient is a sum of products lambda^T dR/dxi that largely cancel,
+ * so it is much more sensitive to the adjoint solves than the states are to the forward
+ * ones: on the 65x65x17 lattice batch a tolerance of 1e-10 left relative gradient errors
+ * of ~3e-5, 1e-6 errors of order one, 1e-12 ~3e-8. */
 typedef struct {
   double box[6];
+  double rtol;
   int32_t kind;
   int32_t reserved;
 } edf_qoi;
@@ -298,7 +317,7 @@ edf_status edf_gpc_exceed(edf_problem* pb, int32_t n_points, const double* theta
  * final time.  Needs a field model with parameters.  EDF_ERR_STATE without a recorded
  * trajectory (or after edf_step, edf_set_state or edf_set_parameters changed the
  * states or parameters since); EDF_ERR_NO_CONVERGENCE if an adjoint solve fails.
- * Uses opts.lin_rtol as the relative tolerance of the adjoint solves.  Synchronises. */
+ * The adjoint solves run to qoi->rtol.  Synchronises. */
 edf_status edf_adjoint(edf_problem* pb, const edf_qoi* qoi, double* J, double* dJ_dxi);
 
 /* Inspection entry points used by the parity tests. */
@@ -323,8 +342,10 @@ edf_status edf_get_jacobian(edf_problem* pb, int32_t sample, const double* u, do
 edf_status edf_apply_vcycle(edf_problem* pb, int32_t group, double dt, const double* x,
                             double* y);
 
-/* y = J~ x with the finest-level matrices of group `group` from the last assembly
- * (edf_apply_vcycle or a Newton iteration); x, y host [S_group][N][2]. */
+/* y = J~ x with the exact finest-level Jacobian of group `group`: the stencil of the last
+ * assembly (edf_apply_vcycle or a Newton iteration), or with opts.matrix_free the
+ * matrix-free product at the group's current states and the last assembly's step
+ * length; x, y host [S_group][N][2]. */
 edf_status edf_apply_jacobian(edf_problem* pb, int32_t group, const double* x, double* y);
 
 /* Timing of the multigrid preconditioner with HIP events on the groups' streams.

@@ -14,6 +14,7 @@ EDF_OK = 0
 STATUS_NAMES = {1: "EDF_ERR_ARG", 2: "EDF_ERR_OOM", 3: "EDF_ERR_HIP", 4: "EDF_ERR_STATE",
                 5: "EDF_ERR_NO_CONVERGENCE", 6: "EDF_ERR_NONFINITE"}
 PREC_F64, PREC_MIXED, PREC_MIXED_F16 = 0, 1, 2
+SMOOTHER_POINT, SMOOTHER_LINE = 0, 1
 SAMPLE_OK, SAMPLE_NEWTON_FAIL, SAMPLE_LINEAR_FAIL, SAMPLE_NONFINITE = 0, 1, 2, 3
 SAMPLE_INADMISSIBLE = 4
 N_XI = {0: 0, 1: 1, 2: 4, 3: 3}
@@ -46,7 +47,7 @@ class SolverOpts(C.Structure):
                 ("check_every", C.c_int32), ("dt_max_halvings", C.c_int32),
                 ("forcing", C.c_int32), ("concurrent_groups", C.c_int32),
                 ("graph_vcycle", C.c_int32), ("substep_memory", C.c_int32),
-                ("reserved", C.c_int32 * 3)]
+                ("smoother", C.c_int32), ("matrix_free", C.c_int32), ("reserved", C.c_int32 * 1)]
 
 
 class StepStats(C.Structure):
@@ -63,7 +64,8 @@ class StepStats(C.Structure):
 
 
 class QoiC(C.Structure):
-    _fields_ = [("box", C.c_double * 6), ("kind", C.c_int32), ("reserved", C.c_int32)]
+    _fields_ = [("box", C.c_double * 6), ("rtol", C.c_double), ("kind", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 _lib = None
@@ -135,7 +137,7 @@ def default_options(**over) -> dict:
     o = dict(newton_rtol=1e-10, newton_atol=0.0, lin_rtol=1e-6, newton_max_it=20,
              ls_max_halvings=5, lin_max_it=200, nu_pre=1, nu_post=1, precision=PREC_F64,
              check_every=4, dt_max_halvings=4, forcing=0, concurrent_groups=0, graph_vcycle=0,
-             substep_memory=0)
+             substep_memory=0, smoother=1, matrix_free=1)
     o.update(over)
     return o
 
@@ -228,6 +230,7 @@ class Problem:
         return [s.as_dict() for s in st] if stats else None
 
     def moments(self, common, threshold=0.5, weights=None):
+        """Mean, variance and P(c > threshold) on the common grid (edf_moments)."""
         cx, cy, cz = common
         n = cx * cy * cz
         mean, var, exc = np.empty(n), np.empty(n), np.empty(n)
@@ -235,9 +238,9 @@ class Problem:
         if weights is not None:
             w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
             assert w.size == self.S
-        self._check(self._lib.edf_moments(self._h, cx, cy, cz, float(threshold),
-                                          _dptr(w) if w is not None else None,
-                                          _dptr(mean), _dptr(var), _dptr(exc)))
+        fn = self._lib.edf_moments
+        self._check(fn(self._h, cx, cy, cz, float(threshold), _dptr(w) if w is not None else None,
+                       _dptr(mean), _dptr(var), _dptr(exc)))
         shape = (cz, cy, cx)
         return mean.reshape(shape), var.reshape(shape), exc.reshape(shape)
 
@@ -276,23 +279,26 @@ class Problem:
                                              _dptr(prob), C.cast(C.pointer(ms), _D)))
         return prob.reshape(cz, cy, cx), ms.value
 
-    def adjoint(self, box):
+    def adjoint(self, box, rtol: float = 0.0):
         """Salt mass J in `box` (x0, x1, y0, y1, z0, z1) at the end of the trajectory
         recorded by the last solve(..., checkpoint_every > 0), and dJ/dxi by the discrete
-        adjoint (edf_adjoint).  Returns (J [S], dJ [S, n_xi])."""
+        adjoint (edf_adjoint) with its solves to rtol (0: the library's default 1e-12).
+        Returns (J [S], dJ [S, n_xi])."""
         q = QoiC()
         for i, v in enumerate(box):
             q.box[i] = float(v)
+        q.rtol = float(rtol)
         J = np.empty(self.S)
         g = np.empty((self.S, self.n_xi))
         self._check(self._lib.edf_adjoint(self._h, C.byref(q), _dptr(J), _dptr(g)))
         return J, g
 
-    def gradient(self, box, dt: float, n_steps: int, checkpoint_every: int = 10):
+    def gradient(self, box, dt: float, n_steps: int, checkpoint_every: int = 10,
+                 rtol: float = 0.0):
         """solve() with checkpoints, then adjoint(): (J, dJ/dxi) after n_steps steps."""
         self.solve(dt, n_steps, checkpoint_every=min(max(1, checkpoint_every), max(n_steps, 1)),
                    stats=False)
-        return self.adjoint(box)
+        return self.adjoint(box, rtol)
 
     def residual(self, sample: int, u, u_old, dt: float):
         a = np.ascontiguousarray(np.asarray(u, dtype=np.float64).reshape(-1))

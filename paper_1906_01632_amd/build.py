@@ -5,8 +5,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["fv_kernels.hip", "mg_kernels.hip", "krylov_kernels.hip", "adjoint_kernels.hip",
-           "gpc_kernels.hip", "edf_api.hip"]
+SOURCES = ["fv_kernels.hip", "mg_kernels.hip", "line_kernels.hip", "krylov_kernels.hip",
+           "adjoint_kernels.hip", "gpc_kernels.hip", "edf_api.hip"]
 LIB = os.path.join(HERE, "libedf.so")
 
 FLAGS = [

@@ -36,6 +36,7 @@ struct Level {
   _Float16* A16 = nullptr;  // finest level with EDF_PREC_MIXED_F16: D^{-1} A in FP16 (Dinv
                             // then holds the diagonal blocks D themselves, FP32)
   void* Dinv = nullptr;   // [S][Np x 4], V-cycle precision
+  void* LF = nullptr;     // vertical-line smoother: [S][Np x 8] column block-LU factors
   void* x = nullptr;      // V-cycle vectors [S][Np][2] colour-major, V-cycle precision
   void* b = nullptr;
   void* r = nullptr;
@@ -297,7 +298,9 @@ edf_status alloc_group(edf_problem* pb, Group& G) {
     if ((s = dalloc(pb, &L.K, S * L.cells))) return s;
     if (l > 0 && (s = dalloc(pb, &L.u, S * 2 * N))) return s;
     const bool coarsest = l == G.L - 1;
-    if (l == 0 || !mx || coarsest)
+    // level 0: the exact Jacobian of the Krylov products, unless they are matrix-free
+    // (the adjoint allocates it when it needs the transposed products)
+    if ((l == 0 && !pb->opts.matrix_free) || (l > 0 && (!mx || coarsest)))
       if ((s = dalloc(pb, &L.A64, S * kPlanes * Np))) return s;
     if (mx && !coarsest)
       if ((s = dalloc(pb, &L.A32, S * kPlanes * Np))) return s;
@@ -309,6 +312,10 @@ edf_status alloc_group(edf_problem* pb, Group& G) {
     if (!coarsest) {
       if ((s = dalloc(pb, &q, S * 4 * Np * tsz))) return s;
       L.Dinv = q;
+      if (pb->opts.smoother == 1 && !(l == 0 && f16_finest(pb, G))) {
+        if ((s = dalloc(pb, &q, S * kLineFactors * Np * tsz))) return s;
+        L.LF = q;
+      }
       if ((s = dalloc(pb, &q, S * 2 * Np * tsz))) return s;
       L.r = q;
     }
@@ -392,6 +399,15 @@ edf_status find_sample(edf_problem* pb, int sample, Group** G, int* local) {
   return fail(pb, EDF_ERR_ARG, "sample index out of range");
 }
 
+// the vertical-line smoother's column factors of a level's V-cycle matrix (if it has any)
+void line_factors(Level& L, bool mixed_vcycle, int S, const int* mask, hipStream_t st) {
+  if (!L.LF) return;
+  if (mixed_vcycle)
+    launch_line_factor<float>(L.g, L.A32, (float*)L.LF, S, mask, st);
+  else
+    launch_line_factor<double>(L.g, L.AV64 ? L.AV64 : L.A64, (double*)L.LF, S, mask, st);
+}
+
 // ---------------------------------------------------------------------------
 // matrices of all levels at the current iterate
 // ---------------------------------------------------------------------------
@@ -402,7 +418,7 @@ edf_status assemble_all(edf_problem* pb, Group& G, const int* mask, const double
     Level& L = G.lv[l];
     if (l > 0) launch_inject(G.lv[l - 1].g, L.g, G.lv[l - 1].u, L.u, G.S, mask, G.st);
     const bool coarsest = l == G.L - 1;
-    if (l == 0)  // exact Jacobian for the Krylov products
+    if (l == 0 && L.A64 && !pb->opts.matrix_free)  // exact Jacobian for the Krylov products
       launch_assemble(L.g, L.ph, dts, L.phi, L.K, L.u, L.A64, nullptr, G.S, mask, G.st, false);
     // preconditioner matrix (frozen Darcy flux in the salt rows): FP32 on the smoothed
     // levels in mixed mode, FP64 otherwise and always on the coarsest level
@@ -416,6 +432,7 @@ edf_status assemble_all(edf_problem* pb, Group& G, const int* mask, const double
         launch_block_inverse_f32(L.g, L.A32, (float*)L.Dinv, G.S, mask, G.st);
       else
         launch_block_inverse_f64(L.g, m64, (double*)L.Dinv, G.S, mask, G.st);
+      line_factors(L, mx, G.S, mask, G.st);
     }
   }
   const Level& C = G.lv[G.L - 1];
@@ -489,17 +506,44 @@ double sweep_bytes(int c, bool zero_start, bool fp16, size_t tsz) {
   return (zero_start ? 4.0 * nb + 8.0 : kPlanes + 10.0) * tsz;
 }
 
+// Algorithmic bytes per vertex of column colour cc of one vertical-line sweep: the
+// stencil blocks towards the other columns (24, or from zero the 3 per column of the
+// colours already swept) and the block above, the column factors (8 values), b, and x
+// written three times over (the forward pass stores d in x, the backward pass reads it
+// and writes x).
+double line_sweep_bytes(int cc, bool zero_start, size_t tsz) {
+  const int nb = zero_start ? line_zero_start_blocks(cc) : 24;
+  return (4.0 * (nb + 1) + 8 + 2 + 6) * tsz;
+}
+// the residual after a single forward line sweep from zero: the blocks towards the
+// columns of the colours swept later, and r
+double line_residual_bytes(int cc, size_t tsz) {
+  return (4.0 * (24 - line_zero_start_blocks(cc)) + 2) * tsz;
+}
+static_assert(line_zero_start_blocks(0) == 0 && line_zero_start_blocks(1) == 6 &&
+                  line_zero_start_blocks(2) == 18 && line_zero_start_blocks(3) == 24,
+              "each coupling between columns is read from one of its two ends");
+
 // Algorithmic bytes of one V-cycle per sample: on every level above the coarsest, the
 // nu1 + nu2 sweeps (the first forward one from zero), the residual (stencil, b, x in,
 // r out; after a single sweep from zero only the blocks towards the colours swept later
 // and r out), r into the restriction and x in and out for the correction; then the dense
 // coarse inverse and its vectors.
-double vcycle_bytes(const Group& G, size_t tsz, int nu1, int nu2) {
+double vcycle_bytes(const Group& G, size_t tsz, int nu1, int nu2, int l0) {
   const bool zs_res = nu1 == 1 && !G.transposed;
   double b = 0;
   for (int l = 0; l + 1 < G.L; ++l) {
     const Geom& g = G.lv[l].g;
     const bool h = l == 0 && G.lv[0].A16;
+    if (G.lv[l].LF && l < l0) {  // vertical-line smoothing
+      for (int cc = 0; cc < 4; ++cc) {
+        const double nv = (double)g.mx[cc] * g.my[cc] * g.nz;
+        b += nv * ((nu1 + nu2) * line_sweep_bytes(cc, false, tsz));
+        if (nu1 > 0) b += nv * (line_sweep_bytes(cc, true, tsz) - line_sweep_bytes(cc, false, tsz));
+        b += nv * (zs_res ? line_residual_bytes(cc, tsz) : (kPlanes + 12.0) * tsz);
+      }
+      continue;
+    }
     for (int c = 0; c < 8; ++c)
       b += (double)g.cnt[c] * (nu1 * sweep_bytes(c, false, h, tsz) + nu2 * sweep_bytes(c, false, h, tsz));
     if (nu1 > 0)
@@ -624,24 +668,34 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
   // finest level with an FP16 matrix: b0 holds D^{-1} b (only for T = float)
   const bool h0 = std::is_same<T, float>::value && G.L >= 2 && G.lv[0].A16;
   const int l0 = first_fused_level(G);
+  // vertical-line smoothing on the levels swept by their own launches that have factors
+  auto line = [&](int l) { return l < l0 && G.lv[l].LF != nullptr; };
   // the first forward sweep from zero of colour 0 (x = D^{-1} b, no neighbours) is done by
   // the kernel that writes the level's b: the entry permutation here, the restriction on
-  // the coarser levels swept by separate launches
+  // the coarser levels swept by separate point-smoother launches
   const bool c0 = nu1 > 0;
+  const bool c0_here = c0 && l0 > 0 && !line(0);
   if constexpr (std::is_same<T, float>::value) {
     if (h0)
       launch_to_colour_scaled(G.lv[0].g, in, (const float*)G.lv[0].Dinv, (float*)b0,
-                              c0 && l0 > 0 ? (float*)x0 : nullptr, S, mask, list, st);
+                              c0_here ? (float*)x0 : nullptr, S, mask, list, st);
     else
-      launch_to_colour<T>(G.lv[0].g, in, b0, c0 && l0 > 0 ? (const T*)G.lv[0].Dinv : nullptr,
-                          x0, S, mask, list, st);
+      launch_to_colour<T>(G.lv[0].g, in, b0, c0_here ? (const T*)G.lv[0].Dinv : nullptr, x0, S,
+                          mask, list, st);
   } else {
-    launch_to_colour<T>(G.lv[0].g, in, b0, c0 && l0 > 0 ? (const T*)G.lv[0].Dinv : nullptr, x0,
-                        S, mask, list, st);
+    launch_to_colour<T>(G.lv[0].g, in, b0, c0_here ? (const T*)G.lv[0].Dinv : nullptr, x0, S,
+                        mask, list, st);
   }
   // zs: the first forward sweep of the level, whose x is zero on entry
   auto smooth = [&](int l, const Level& L, int c, const T* b, T* x, bool zs) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (line(l)) {
+      const double nv = (double)L.g.mx[c] * L.g.my[c] * L.g.nz;
+      prof_pair(G, e0, e1, nv * G.n_active * line_sweep_bytes(c, zs, sizeof(T)), 0);
+      launch_line_smooth<T>(L.g, c, stencil<T>(L), (const T*)L.LF, b, x, S, mask, list, st, e0,
+                            e1, zs);
+      return;
+    }
     const double per_vertex = sweep_bytes(c, zs, l == 0 && h0, sizeof(T));
     prof_pair(G, e0, e1, (double)L.g.cnt[c] * G.n_active * per_vertex, 0);
     if constexpr (std::is_same<T, float>::value) {
@@ -660,7 +714,11 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
         return;
       }
     }
-    launch_residual<T>(L.g, stencil<T>(L), b, x, (T*)L.r, S, mask, list, st, zs_res);
+    if (line(l) && zs_res) {
+      launch_line_residual_zs<T>(L.g, stencil<T>(L), x, (T*)L.r, S, mask, list, st);
+      return;
+    }
+    launch_residual<T>(L.g, stencil<T>(L), b, x, (T*)L.r, S, mask, list, st, zs_res && !line(l));
   };
   auto bx = [&](int l, T*& b, T*& x) {
     b = l == 0 ? b0 : (T*)G.lv[l].b;
@@ -674,17 +732,20 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
     Level& L = G.lv[l];
     T *b, *x;
     bx(l, b, x);
+    const int ncol = line(l) ? 4 : 8;
     for (int it = 0; it < nu1; ++it)
-      for (int c = it == 0 && c0 ? 1 : 0; c < 8; ++c) smooth(l, L, c, b, x, it == 0);
+      for (int c = it == 0 && c0 && !line(l) ? 1 : 0; c < ncol; ++c) smooth(l, L, c, b, x, it == 0);
     residual(l, L, b, x);
     T *bc, *xc;
     bx(l + 1, bc, xc);
-    // x of the next level needs no clearing when its first sweep starts from zero (colour
-    // 0 of it done here) or when it is the fused bottom's first level (cleared there)
+    // x of the next level needs no clearing when its first sweep starts from zero (for a
+    // point-smoothed level its colour 0 done here) or when it is the fused bottom's first
+    // level (cleared there)
     const bool next_swept = l + 1 < l0;
+    const bool next_point = next_swept && !line(l + 1);
     launch_restrict<T>(L.g, G.lv[l + 1].g, (const T*)L.r, bc,
-                       c0 ? (next_swept ? xc : nullptr) : xc,
-                       c0 && next_swept ? (const T*)G.lv[l + 1].Dinv : nullptr, S, mask, list, st);
+                       c0 ? (next_point ? xc : nullptr) : xc,
+                       c0 && next_point ? (const T*)G.lv[l + 1].Dinv : nullptr, S, mask, list, st);
   }
   {
     size_t lds_bytes = 0;
@@ -699,8 +760,9 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
     bx(l, b, x);
     bx(l + 1, bc, xc);
     launch_prolong<T>(L.g, G.lv[l + 1].g, xc, x, S, mask, list, st);
+    const int ncol = line(l) ? 4 : 8;
     for (int it = 0; it < nu2; ++it)
-      for (int c = 7; c >= 0; --c) smooth(l, L, c, b, x, false);
+      for (int c = ncol - 1; c >= 0; --c) smooth(l, L, c, b, x, false);
   }
   launch_from_colour<T>(G.lv[0].g, x0, out, S, mask, list, st);
 }
@@ -744,7 +806,8 @@ bool vcycle_graph(edf_problem* pb, Group& G, const double* in, double* out, cons
 void precondition(edf_problem* pb, Group& G, const double* in, double* out, const int* mask) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const size_t tsz = mixed(pb) ? sizeof(float) : sizeof(double);
-  const double bytes = vcycle_bytes(G, tsz, pb->opts.nu_pre, pb->opts.nu_post) * G.n_active;
+  const double bytes =
+      vcycle_bytes(G, tsz, pb->opts.nu_pre, pb->opts.nu_post, first_fused_level(G)) * G.n_active;
   // captured V-cycles when asked for and not profiling (the profile times single launches)
   if (pb->opts.graph_vcycle && !G.prof_on && G.n_list > 0) {
     if (mixed(pb) ? vcycle_graph<float>(pb, G, in, out, mask)
@@ -767,7 +830,18 @@ edf_status bicgstab(edf_problem* pb, Group& G) {
   const int S = G.S;
   const size_t n = G.n;
   const Geom& g0 = G.lv[0].g;
-  const double* A = G.lv[0].A64;
+  // the products with the assembled stencil, or matrix-free at the current iterate (the
+  // adjoint's transposed systems are always assembled)
+  JacOp A;
+  if (pb->opts.matrix_free && !G.transposed) {
+    A.ph = G.lv[0].ph;
+    A.dts = G.dts;
+    A.phi = G.lv[0].phi;
+    A.K = G.lv[0].K;
+    A.u = G.u;
+  } else {
+    A.A = G.lv[0].A64;
+  }
   launch_bicg_init(n, G.F, G.kx, G.kr, G.krh, G.kp, G.kv, G.part, G.ks, G.eta, G.active, S,
                    G.nmask, st);
   auto count_active = [&]() -> edf_status {
@@ -788,7 +862,7 @@ edf_status bicgstab(edf_problem* pb, Group& G) {
       // the launches run over the samples active at the last count (a superset of those
       // still active: the active flags gate the rest)
       const SampleList sl{G.n_list < S ? G.d_list : nullptr, G.n_list};
-      launch_bicg_p(n, G.kr, G.kv, G.kp, G.ks, S, G.active, sl, st);
+      launch_bicg_p(n, G.kr, G.kv, G.kp, G.krh, G.ks, S, G.active, sl, st);
       precondition(pb, G, G.kp, G.kph, G.active);
       launch_bicg_alpha(g0, A, G.kph, G.kv, G.krh, G.part, G.ks, S, G.active, sl, st);
       launch_bicg_s(n, G.kr, G.kv, G.ks_, G.part, G.ks, S, G.active, sl, st);
@@ -1200,6 +1274,7 @@ edf_status assemble_all_transposed(edf_problem* pb, Group& G, const int* mask, c
       launch_transpose<double>(L.g, G.tmpA, m64, G.S, mask, G.st);
       if (!coarsest) launch_block_inverse_f64(L.g, m64, (double*)L.Dinv, G.S, mask, G.st);
     }
+    if (!coarsest) line_factors(L, mx, G.S, mask, G.st);
   }
   const Level& C = G.lv[G.L - 1];
   launch_coarse_dense(C.g, G.L == 1 ? C.AV64 : C.A64, G.Minv, G.S, mask, G.st);
@@ -1220,6 +1295,7 @@ edf_status ensure_trajectory_buffers(edf_problem* pb, Group& G, int n_steps, int
     EDF_TRY(hipMalloc((void**)&G.ckpt, S * nck * n * sizeof(double)));
     G.ckpt_cap = nck;
   }
+  if (!G.idx && (e = dalloc(pb, &G.idx, S))) return e;  // slot indices of gather/scatter
   return EDF_OK;
 }
 
@@ -1240,10 +1316,11 @@ edf_status ensure_adjoint_buffers(edf_problem* pb, Group& G, int k) {
     G.sub_cap = kmax;
     if ((e = dalloc(pb, &G.sub, S * G.sub_cap * n))) return e;
   }
+  if (!G.lv[0].A64 && (e = dalloc(pb, &G.lv[0].A64, S * kPlanes * (size_t)G.lv[0].g.off[8])))
+    return e;  // the transposed exact Jacobian (assembled also with matrix-free forward products)
   if (!G.lam_next) {
     if ((e = dalloc(pb, &G.lam_next, S * n))) return e;
     if ((e = dalloc(pb, &G.tmpA, S * kPlanes * (size_t)G.lv[0].g.off[8]))) return e;
-    if ((e = dalloc(pb, &G.idx, S))) return e;
     if ((e = dalloc(pb, &G.g4, 4 * S))) return e;
   }
   return EDF_OK;
@@ -1302,11 +1379,14 @@ edf_status replay_substeps(edf_problem* pb, Group& G, double dt, const std::vect
   return EDF_OK;
 }
 
+// default relative tolerance of the adjoint solves (the gradient amplifies their residual)
+constexpr double kAdjointRtol = 1e-12;
+
 // The backward sweep over the trajectory recorded by edf_solve (n steps of dt, a
 // checkpoint every k steps): segments from the last, each recomputed from its checkpoint
 // into G.seg, then its steps backwards, each through its sub-steps.  J[s] and dJ[s][4]
 // of the group's samples (NaN for samples that failed while the trajectory was recorded).
-edf_status adjoint_group(edf_problem* pb, Group& G, const QoiBox& box,
+edf_status adjoint_group(edf_problem* pb, Group& G, const QoiBox& box, double rtol,
                          std::vector<double>& Jv, std::vector<double>& grad) {
   hipStream_t st = G.st;
   const int S = G.S;
@@ -1320,8 +1400,8 @@ edf_status adjoint_group(edf_problem* pb, Group& G, const QoiBox& box,
   const double* dxi = pb->dxi + (size_t)G.s0 * std::max(pb->phys.n_xi, 1);
   Jv.assign(S, 0.0);
   grad.assign(4 * (size_t)S, 0.0);
-  std::vector<double> hg(4 * S), eta(S, pb->opts.lin_rtol);
-  std::vector<int> K(S), act(S), idx(S), zero(S, 0), full(S);
+  std::vector<double> hg(4 * S), eta(S, rtol);
+  std::vector<int> K(S), act(S), idx(S), full(S);
   const int n_seg = ceil_div(n_steps, k);
   const int last_slot = n_seg;  // the final state (slot of step n_steps)
   bool first = true;
@@ -1396,9 +1476,16 @@ edf_status adjoint_group(edf_problem* pb, Group& G, const QoiBox& box,
         EDF_TRY(hipMemcpyAsync(G.h_ks, G.ks, S * sizeof(KrylovScalars), hipMemcpyDeviceToHost, st));
         EDF_TRY(hipStreamSynchronize(st));
         for (int s = 0; s < S; ++s)
-          if (act[s] && G.h_ks[s].state != 1 && G.h_ks[s].bb > 0)
-            return fail(pb, EDF_ERR_NO_CONVERGENCE,
-                        "adjoint BiCGStab did not converge for sample " + std::to_string(G.s0 + s));
+          if (act[s] && G.h_ks[s].state != 1 && G.h_ks[s].bb > 0) {
+            const KrylovScalars& k = G.h_ks[s];
+            char buf[256];
+            std::snprintf(buf, sizeof buf,
+                          "adjoint BiCGStab did not converge for sample %d (step %d, %s after %d "
+                          "iterations and %d restarts, |r|/|b| = %.3e for a tolerance of %.1e)",
+                          G.s0 + s, m, k.state == 2 ? "breakdown" : "iteration limit", k.it,
+                          k.restarts, std::sqrt(k.rr / k.bb), std::sqrt(k.tol2 / k.bb));
+            return fail(pb, EDF_ERR_NO_CONVERGENCE, buf);
+          }
         const int nb = launch_param_grad(L0.g, L0.ph, G.dts, fp, dxi, L0.phi, L0.K, G.u, G.u_old,
                                          G.kx, box, first ? 1 : 0, G.part, S, G.nmask, st);
         launch_sum4(nb, G.part, G.g4, S, G.nmask, st);
@@ -1509,11 +1596,15 @@ edf_status edf_create_problem(const edf_physics* phys, const edf_group_desc* gro
       opts->ls_max_halvings < 0 || !(opts->lin_rtol > 0) || !(opts->newton_rtol >= 0))
     return bad("invalid solver options");
   if (opts->reserved[0] != 0) return bad("reserved options must be zero");
+  if (opts->matrix_free != 0 && opts->matrix_free != 1) return bad("matrix_free must be 0 or 1");
   if (opts->graph_vcycle != 0 && opts->graph_vcycle != 1)
     return bad("graph_vcycle must be 0 or 1");
   if (opts->concurrent_groups != 0 && opts->concurrent_groups != 1)
     return bad("concurrent_groups must be 0 or 1");
   if (opts->forcing != 0 && opts->forcing != 1) return bad("forcing must be 0 or 1");
+  if (opts->smoother != 0 && opts->smoother != 1) return bad("smoother must be 0 or 1");
+  if (opts->substep_memory != 0 && opts->substep_memory != 1)
+    return bad("substep_memory must be 0 or 1");
   if (opts->dt_max_halvings < 0 || opts->dt_max_halvings > 12)
     return bad("dt_max_halvings must be in [0, 12]");
   int s0 = 0;
@@ -2028,7 +2119,16 @@ edf_status edf_apply_jacobian(edf_problem* pb, int32_t group, const double* x, d
     return fail(pb, EDF_ERR_ARG, "bad apply arguments");
   Group& G = pb->groups[group];
   EDF_TRY(hipMemcpyAsync(G.kp, x, G.S * G.n * sizeof(double), hipMemcpyHostToDevice, pb->st));
-  launch_spmv(G.lv[0].g, G.lv[0].A64, G.kp, G.kv, G.S, nullptr, pb->st);
+  JacOp J;
+  if (pb->opts.matrix_free) {  // at the group's states with the last assembly's step
+    J.ph = G.lv[0].ph;
+    J.phi = G.lv[0].phi;
+    J.K = G.lv[0].K;
+    J.u = G.u;
+  } else {
+    J.A = G.lv[0].A64;
+  }
+  launch_spmv(G.lv[0].g, J, G.kp, G.kv, G.S, nullptr, pb->st);
   EDF_CHECK_LAUNCH();
   EDF_TRY(hipMemcpyAsync(y, G.kv, G.S * G.n * sizeof(double), hipMemcpyDeviceToHost, pb->st));
   EDF_TRY(hipStreamSynchronize(pb->st));
@@ -2040,6 +2140,7 @@ edf_status edf_adjoint(edf_problem* pb, const edf_qoi* qoi, double* J, double* d
   if ((e = check_ready(pb))) return e;
   if (!qoi || !J || !dJ_dxi) return fail(pb, EDF_ERR_ARG, "bad adjoint arguments");
   if (qoi->kind != 0) return fail(pb, EDF_ERR_ARG, "unknown quantity of interest");
+  if (!(qoi->rtol >= 0.0 && qoi->rtol < 1.0)) return fail(pb, EDF_ERR_ARG, "rtol not in [0, 1)");
   if (pb->phys.field_model == EDF_FIELD_CONST || pb->phys.n_xi < 1)
     return fail(pb, EDF_ERR_ARG, "the constant field has no parameters");
   QoiBox b;
@@ -2055,7 +2156,7 @@ edf_status edf_adjoint(edf_problem* pb, const edf_qoi* qoi, double* J, double* d
   for (Group& G : pb->groups) {
     std::vector<double> Jv, gr;
     const std::vector<edf_step_stats> keep = G.stats;  // the replays count Newton work
-    e = adjoint_group(pb, G, b, Jv, gr);
+    e = adjoint_group(pb, G, b, qoi->rtol > 0.0 ? qoi->rtol : kAdjointRtol, Jv, gr);
     G.stats = keep;
     if (e) return e;
     for (int s = 0; s < G.S; ++s) {

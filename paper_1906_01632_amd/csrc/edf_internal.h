@@ -48,8 +48,10 @@ struct FieldParams {
 struct KrylovScalars {
   double rho, rho_old, alpha, omega, beta;
   double bb, rr, tol2, rv, ts, tt, ss;
-  int it, state;  // state: 0 running, 1 converged, 2 breakdown
-  int pad[2];
+  double hh;      // (r^, r^) of the shadow residual
+  int it, state;  // state: 0 running, 1 converged, 2 breakdown with no restart left
+  int restart;    // 1: the next iteration restarts with r^ = p = r (set by the update)
+  int restarts;   // restarts so far
 };
 
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
@@ -118,6 +120,41 @@ __host__ __device__ constexpr int zero_start_blocks(int col) {
     if (zero_start_reads(col, o % 3 - 1, (o / 3) % 3 - 1, o / 9 - 1)) ++n;
   return n;
 }
+
+// Vertical-line block Gauss-Seidel (line_kernels.hip): columns (i, j) in 4 colours
+// cc = (i % 2) + 2 (j % 2); the neighbour column at (dx, dy) has colour cc with the parity
+// bit of every odd component flipped.
+constexpr int kLineFactors = 8;  // per vertex: M^{-1} of the column's block LU, then C
+__host__ __device__ constexpr int line_column_colour(int cc, int dx, int dy) {
+  return cc ^ ((dx != 0) | ((dy != 0) << 1));
+}
+// the first line sweep from x = 0 of column colour cc reads the neighbour column (dx, dy)
+// only when its colour is below cc (the columns already swept)
+__host__ __device__ constexpr bool line_zero_start_reads(int cc, int dx, int dy) {
+  return (dx != 0 || dy != 0) && line_column_colour(cc, dx, dy) < cc;
+}
+// stencil blocks that sweep reads per vertex besides the column's own (3 per column)
+__host__ __device__ constexpr int line_zero_start_blocks(int cc) {
+  int n = 0;
+  for (int dy = -1; dy <= 1; ++dy)
+    for (int dx = -1; dx <= 1; ++dx)
+      if (line_zero_start_reads(cc, dx, dy)) n += 3;
+  return n;
+}
+// the factors F [S][Np x 8] of every column's block tridiagonal part (diagonal, above,
+// below blocks of A), computed in FP64 and stored in T
+template <typename T>
+void launch_line_factor(const Geom& g, const T* A, T* F, int S, const int* mask, hipStream_t st);
+// one line sweep of column colour cc; zero_start: the level's first forward sweep from x = 0
+template <typename T>
+void launch_line_smooth(const Geom& g, int cc, const T* A, const T* F, const T* b, T* x, int S,
+                        const int* mask, const int* list, hipStream_t st, hipEvent_t ev0,
+                        hipEvent_t ev1, bool zero_start);
+// r = b - A x after a single forward line sweep from x = 0 (blocks towards the columns of
+// the colours swept later only; b is not read)
+template <typename T>
+void launch_line_residual_zs(const Geom& g, const T* A, const T* x, T* r, int S, const int* mask,
+                             const int* list, hipStream_t st);
 
 // one block Gauss-Seidel sweep of one colour; zero_start: the first forward sweep of a
 // level whose x is zero on entry (reads only the colours already swept, writes x)
@@ -206,7 +243,24 @@ size_t vcycle_bottom_lds_limit();
 // Krylov / Newton kernels (krylov_kernels.hip), FP64 vectors of n = 2N per sample
 // ---------------------------------------------------------------------------
 int reduce_blocks(size_t n);
-void launch_spmv(const Geom& g, const double* A, const double* x, double* y, int S,
+// The operator y = J~ x of the outer Krylov method: the assembled FP64 stencil A, or, with
+// A null, the matrix-free product at state u with the coefficients phi, K and the per-sample
+// time steps dts (or ph.dt) (launch_jx)
+struct JacOp {
+  const double* A = nullptr;
+  Phys ph{};
+  const double* dts = nullptr;
+  const double* phi = nullptr;
+  const double* K = nullptr;
+  const double* u = nullptr;
+};
+// matrix-free y = J~ x (fv_kernels.hip); mode 0: plain, 1: with the dot (d, y) into part,
+// 2: with (d, y) and (y, y); grid rows = rows (list[row] or row is the sample); returns the
+// number of partial sums per sample
+int launch_jx(const Geom& g, const Phys& ph, const double* dts, const double* phi, const double* K,
+              const double* u, const double* x, double* y, const double* d, double* part, int mode,
+              int S, const int* mask, const int* list, int rows, hipStream_t st);
+void launch_spmv(const Geom& g, const JacOp& J, const double* x, double* y, int S,
                  const int* mask, hipStream_t st);
 // BiCGStab phases; `part` is scratch [S][nb][4], `ks` the per-sample scalars.
 void launch_bicg_init(size_t n, const double* b, double* x, double* r, double* rh, double* p,
@@ -220,14 +274,15 @@ struct SampleList {
   int n = 0;
   int rows(int S) const { return idx ? n : S; }
 };
-void launch_bicg_p(size_t n, const double* r, const double* v, double* p, const KrylovScalars* ks,
-                   int S, const int* mask, SampleList sl, hipStream_t st);
-void launch_bicg_alpha(const Geom& g, const double* A, const double* ph, double* v, const double* rh,
+// p = r + beta (p - omega v); on a restart (ks.restart) p = r and the shadow residual r^ = r
+void launch_bicg_p(size_t n, const double* r, const double* v, double* p, double* rh,
+                   const KrylovScalars* ks, int S, const int* mask, SampleList sl, hipStream_t st);
+void launch_bicg_alpha(const Geom& g, const JacOp& J, const double* ph, double* v, const double* rh,
                        double* part, KrylovScalars* ks, int S, const int* mask, SampleList sl,
                        hipStream_t st);
 void launch_bicg_s(size_t n, const double* r, const double* v, double* s, double* part,
                    KrylovScalars* ks, int S, const int* mask, SampleList sl, hipStream_t st);
-void launch_bicg_omega(const Geom& g, const double* A, const double* sh, const double* s, double* t,
+void launch_bicg_omega(const Geom& g, const JacOp& J, const double* sh, const double* s, double* t,
                        double* part, KrylovScalars* ks, int S, const int* mask, SampleList sl,
                        hipStream_t st);
 void launch_bicg_update(size_t n, const double* ph, const double* sh, const double* s,

@@ -68,6 +68,18 @@ __device__ __forceinline__ Block2<float> load_block(const _Float16* base, int p)
   return {(float)u.x, (float)u.y, (float)u.z, (float)u.w};
 }
 
+// two-component vector of T (one vertex's (p, c) pair)
+template <typename T>
+struct V2;
+template <>
+struct V2<double> {
+  using type = double2;
+};
+template <>
+struct V2<float> {
+  using type = float2;
+};
+
 // colour-major position t -> vertex (i, j, k); false for padding positions
 __device__ __forceinline__ bool colour_decode(const Geom& g, int t, int& i, int& j, int& k) {
   int col = 0;

@@ -277,6 +277,162 @@ void launch_defect(const Geom& g, const Phys& ph, const double* dts, const doubl
 }
 
 // ---------------------------------------------------------------------------
+// Matrix-free Jacobian product y~ = J~ x~: the directional derivative of the scaled
+// defect at state u in the direction (p_unit x~_p, x~_c), with the upwind choice frozen
+// at u (the same operator as the assembled exact Jacobian, k_assemble<false>).  Per face,
+// with the trilinear weights of its integration point:
+//   dQ = -(K/mu) A (d_d(dp) - (rho1 - rho0) dc_f g_d),
+//   liquid  d(rho(c_f) Q) = (rho1 - rho0) dc_f Q + rho(c_f) dQ,
+//   salt    d(rho(c_up) c_up Q) - d(rho(c_f) phi D_m d_d c) A
+//         = (rho0 + 2 (rho1 - rho0) c_up) dc_up Q + rho(c_up) c_up dQ
+//           - ((rho1 - rho0) dc_f phi D_m d_d c + rho(c_f) phi D_m d_d(dc)) A,
+// plus the storage derivatives; Dirichlet rows are identity rows.  The kernel walks the
+// 8 hexahedra around the vertex and loads each one's corners (state and direction) from
+// the cache, which keeps the register count at a quarter of holding the 3x3x3
+// neighbourhood of both fields.
+// ---------------------------------------------------------------------------
+template <int AX, int AY, int AZ, int D>
+__device__ __forceinline__ void face_tangent(const double* P, const double* C, const double* XP,
+                                             const double* XC, double phi, double K,
+                                             const Phys& ph, const FaceGeo& fg, double& Yl,
+                                             double& Ys) {
+  using F = FaceT<AX, AY, AZ, D>;
+  constexpr int WA = F::SB0 + 2 * F::SB1 + 4 * F::SB2;  // the edge's start corner
+  constexpr int WB = WA + (1 << D);                      // and its end
+  double cf = 0.0, dp = 0.0, dc = 0.0, tcf = 0.0, tdp = 0.0, tdc = 0.0;
+#pragma unroll
+  for (int w = 0; w < 8; ++w) {
+    cf += F::N(w) * C[w];
+    dp += F::dN(w) * P[w];
+    dc += F::dN(w) * C[w];
+    tcf += F::N(w) * XC[w];
+    tdp += F::dN(w) * XP[w];
+    tdc += F::dN(w) * XC[w];
+  }
+  const double ih = fg.ih[D];
+  dp *= ih;
+  dc *= ih;
+  tdp *= ih;
+  tdc *= ih;
+  const double area = fg.area[D];
+  const double gD = D == 2 ? ph.g : 0.0;
+  const double rf = ph.rho0 + ph.drho * cf;
+  const double kmu = K / ph.mu * area;
+  const double Q = -kmu * (dp - rf * gD);
+  const double tQ = -kmu * (tdp - ph.drho * tcf * gD);
+  const bool up_start = Q >= 0.0;
+  const double cup = up_start ? C[WA] : C[WB];
+  const double tcup = up_start ? XC[WA] : XC[WB];
+  const double ru = ph.rho0 + ph.drho * cup;
+  const double diff = phi * ph.Dm * area;
+  const double yl = ph.drho * tcf * Q + rf * tQ;
+  const double ys = (ph.rho0 + 2.0 * ph.drho * cup) * tcup * Q + ru * cup * tQ -
+                    (ph.drho * tcf * dc + rf * tdc) * diff;
+  if (F::VD == 0) {
+    Yl += yl;
+    Ys += ys;
+  } else {
+    Yl -= yl;
+    Ys -= ys;
+  }
+}
+
+template <int AX, int AY, int AZ>
+__device__ __forceinline__ void hex_tangent(const Geom& g, int i, int j, int k, const double* phi,
+                                            const double* K, const double2* u, const double2* x,
+                                            const Phys& ph, const FaceGeo& fg, double& Yl,
+                                            double& Ys, double& msum) {
+  const int hi = i - AX, hj = j - AY, hk = k - AZ;
+  if (hi < 0 || hj < 0 || hk < 0 || hi > g.nx - 2 || hj > g.ny - 2 || hk > g.nz - 2) return;
+  const size_t e = hi + (size_t)(g.nx - 1) * (hj + (size_t)(g.ny - 1) * hk);
+  const double pe = phi[e], Ke = K[e];
+  msum += pe;
+  double P[8], C[8], XP[8], XC[8];
+#pragma unroll
+  for (int w = 0; w < 8; ++w) {
+    const size_t vw = (hi + (w & 1)) + (size_t)g.nx * ((hj + ((w >> 1) & 1)) + (size_t)g.ny * (hk + (w >> 2)));
+    const double2 a = u[vw], b = x[vw];
+    P[w] = a.x;
+    C[w] = a.y;
+    XP[w] = ph.p_unit * b.x;
+    XC[w] = b.y;
+  }
+  face_tangent<AX, AY, AZ, 0>(P, C, XP, XC, pe, Ke, ph, fg, Yl, Ys);
+  face_tangent<AX, AY, AZ, 1>(P, C, XP, XC, pe, Ke, ph, fg, Yl, Ys);
+  face_tangent<AX, AY, AZ, 2>(P, C, XP, XC, pe, Ke, ph, fg, Yl, Ys);
+}
+
+// MODE as k_spmv: 0 plain, 1 with the dot (d, y), 2 with (d, y) and (y, y)
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_jx(Geom g, Phys ph0, const double* dts,
+                                               const double* phi_all, const double* K_all,
+                                               const double* u_all, const double* x_all,
+                                               double* y_all, const double* d_all, double* part,
+                                               const int* mask, const int* list) {
+  const int s = list ? list[blockIdx.y] : blockIdx.y;
+  if (mask && !mask[s]) return;
+  const Phys ph = sample_phys(ph0, dts, s);
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  double acc[2] = {0.0, 0.0};
+  if (v < g.N) {
+    const int i = v % g.nx, j = (v / g.nx) % g.ny, k = v / (g.nx * g.ny);
+    const size_t cells = (size_t)(g.nx - 1) * (g.ny - 1) * (g.nz - 1);
+    const double* phi = phi_all + s * cells;
+    const double* K = K_all + s * cells;
+    const double2* u = reinterpret_cast<const double2*>(u_all) + (size_t)s * g.N;
+    const double2* x = reinterpret_cast<const double2*>(x_all) + (size_t)s * g.N;
+    const FaceGeo fg = face_geo(g);
+    double Yl = 0.0, Ys = 0.0, msum = 0.0;
+    hex_tangent<0, 0, 0>(g, i, j, k, phi, K, u, x, ph, fg, Yl, Ys, msum);
+    hex_tangent<1, 0, 0>(g, i, j, k, phi, K, u, x, ph, fg, Yl, Ys, msum);
+    hex_tangent<0, 1, 0>(g, i, j, k, phi, K, u, x, ph, fg, Yl, Ys, msum);
+    hex_tangent<1, 1, 0>(g, i, j, k, phi, K, u, x, ph, fg, Yl, Ys, msum);
+    hex_tangent<0, 0, 1>(g, i, j, k, phi, K, u, x, ph, fg, Yl, Ys, msum);
+    hex_tangent<1, 0, 1>(g, i, j, k, phi, K, u, x, ph, fg, Yl, Ys, msum);
+    hex_tangent<0, 1, 1>(g, i, j, k, phi, K, u, x, ph, fg, Yl, Ys, msum);
+    hex_tangent<1, 1, 1>(g, i, j, k, phi, K, u, x, ph, fg, Yl, Ys, msum);
+    const double m = msum * (g.hx * g.hy * g.hz * 0.125);
+    const double2 xv = x[v];
+    const double c = u[v].y;
+    Yl += m * ph.drho * xv.y / ph.dt;
+    Ys += m * (ph.rho0 + 2.0 * ph.drho * c) * xv.y / ph.dt;
+    double cD;
+    const double r0 = is_pin(g, i, j, k) ? xv.x : ph.s_row * Yl;
+    const double r1 = is_cdir(g, i, j, k, cD) ? xv.y : ph.s_row * Ys;
+    reinterpret_cast<double2*>(y_all)[(size_t)s * g.N + v] = make_double2(r0, r1);
+    if (MODE != 0) {
+      const double2 d = reinterpret_cast<const double2*>(d_all)[(size_t)s * g.N + v];
+      acc[0] = d.x * r0 + d.y * r1;
+      if (MODE == 2) acc[1] = r0 * r0 + r1 * r1;
+    }
+  }
+  if (MODE == 1) {
+    double a1[1] = {acc[0]};
+    block_partial<1>(a1, part + ((size_t)s * gridDim.x + blockIdx.x) * 4);
+  } else if (MODE == 2) {
+    block_partial<2>(acc, part + ((size_t)s * gridDim.x + blockIdx.x) * 4);
+  }
+}
+
+int launch_jx(const Geom& g, const Phys& ph, const double* dts, const double* phi, const double* K,
+              const double* u, const double* x, double* y, const double* d, double* part, int mode,
+              int S, const int* mask, const int* list, int rows, hipStream_t st) {
+  const int nb = ceil_div(g.N, kBlock);
+  dim3 grid(nb, rows);
+  if (mode == 0)
+    hipLaunchKernelGGL(k_jx<0>, grid, dim3(kBlock), 0, st, g, ph, dts, phi, K, u, x, y, d, part,
+                       mask, list);
+  else if (mode == 1)
+    hipLaunchKernelGGL(k_jx<1>, grid, dim3(kBlock), 0, st, g, ph, dts, phi, K, u, x, y, d, part,
+                       mask, list);
+  else
+    hipLaunchKernelGGL(k_jx<2>, grid, dim3(kBlock), 0, st, g, ph, dts, phi, K, u, x, y, d, part,
+                       mask, list);
+  (void)S;
+  return nb;
+}
+
+// ---------------------------------------------------------------------------
 // Global mass balance of one (sub-)step in FP64 (eqs. e_cont_eq and e_tran_eq summed
 // over all control volumes).  Interior face fluxes cancel in pairs and the no-flow
 // faces carry none, so the storage change of the box equals dt times the rows of the

@@ -74,17 +74,25 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Geom g, const double* A_all, co
   }
 }
 
-void launch_spmv(const Geom& g, const double* A, const double* x, double* y, int S,
+void launch_spmv(const Geom& g, const JacOp& J, const double* x, double* y, int S,
                  const int* mask, hipStream_t st) {
+  if (!J.A) {
+    launch_jx(g, J.ph, J.dts, J.phi, J.K, J.u, x, y, nullptr, nullptr, 0, S, mask, nullptr, S, st);
+    return;
+  }
   dim3 grid(ceil_div(g.N, kBlock), S);
-  hipLaunchKernelGGL(k_spmv<kDotNone>, grid, dim3(kBlock), 0, st, g, A, x, y, (const double*)nullptr,
-                     (double*)nullptr, mask, (const int*)nullptr);
+  hipLaunchKernelGGL(k_spmv<kDotNone>, grid, dim3(kBlock), 0, st, g, J.A, x, y,
+                     (const double*)nullptr, (double*)nullptr, mask, (const int*)nullptr);
 }
 
 // ---------------------------------------------------------------------------
 // per-sample scalar updates (one wave per sample)
 // ---------------------------------------------------------------------------
 enum Phase { kInit = 0, kAlpha = 1, kS = 2, kOmega = 3, kUpdate = 4 };
+
+// BiCGStab restarts when |(r^, r)| <= kBreakdown |r^| |r| (or omega or (r^, v) vanish)
+constexpr double kBreakdown = 1e-12;
+constexpr int kMaxRestarts = 8;
 
 __global__ __launch_bounds__(64) void k_bicg_finalize(int phase, int nb, const double* part,
                                                       KrylovScalars* ks_all, int* active,
@@ -122,11 +130,15 @@ __global__ __launch_bounds__(64) void k_bicg_finalize(int phase, int nb, const d
       k.beta = 0.0;
       k.tol2 = rtol[s] * rtol[s] * a0;
       k.ss = 0.0;
+      k.hh = a0;
       k.it = 0;
+      k.restart = 0;
+      k.restarts = 0;
       k.state = (a0 > 0.0 && a0 == a0) ? 0 : (a0 == 0.0 ? 1 : 2);
       active[s] = k.state == 0;
       break;
     case kAlpha:
+      k.restart = 0;  // the restart (if any) took place in the p update before this
       k.rv = a0;
       k.alpha = (a0 != 0.0) ? k.rho / a0 : 0.0;
       break;
@@ -148,8 +160,19 @@ __global__ __launch_bounds__(64) void k_bicg_finalize(int phase, int nb, const d
         k.state = 2;
       } else if (a1 <= k.tol2 || k.ss <= k.tol2) {
         k.state = 1;
-      } else if (k.omega == 0.0 || k.rho == 0.0 || k.rv == 0.0) {
-        k.state = 2;  // breakdown: keep the iterate reached so far
+      } else if (k.omega == 0.0 || k.rv == 0.0 ||
+                 !(fabs(k.rho) > kBreakdown * sqrt(k.hh * a1))) {
+        // (near) breakdown: (r^, r) or omega has vanished; restart from the iterate
+        // reached so far with r^ = p = r (at most kMaxRestarts times)
+        if (k.restarts < kMaxRestarts) {
+          k.restart = 1;
+          k.restarts += 1;
+          k.rho = a1;
+          k.hh = a1;
+          k.beta = 0.0;
+        } else {
+          k.state = 2;
+        }
       } else {
         k.beta = (k.rho / k.rho_old) * (k.alpha / k.omega);
       }
@@ -199,29 +222,40 @@ void launch_bicg_init(size_t n, const double* b, double* x, double* r, double* r
 }
 
 __global__ __launch_bounds__(kBlock) void k_bicg_p(size_t n, const double* r, const double* v,
-                                                   double* p, const KrylovScalars* ks,
+                                                   double* p, double* rh, const KrylovScalars* ks,
                                                    const int* mask, const int* list) {
   const int s = list ? list[blockIdx.y] : blockIdx.y;
   if (mask && !mask[s]) return;
   const double beta = ks[s].beta, omega = ks[s].omega;
   const size_t o = (size_t)s * n;
+  if (ks[s].restart) {
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+         e += (size_t)gridDim.x * blockDim.x) {
+      p[o + e] = r[o + e];
+      rh[o + e] = r[o + e];
+    }
+    return;
+  }
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
        e += (size_t)gridDim.x * blockDim.x)
     p[o + e] = r[o + e] + beta * (p[o + e] - omega * v[o + e]);
 }
 
-void launch_bicg_p(size_t n, const double* r, const double* v, double* p, const KrylovScalars* ks,
-                   int S, const int* mask, SampleList sl, hipStream_t st) {
+void launch_bicg_p(size_t n, const double* r, const double* v, double* p, double* rh,
+                   const KrylovScalars* ks, int S, const int* mask, SampleList sl, hipStream_t st) {
   hipLaunchKernelGGL(k_bicg_p, dim3(reduce_blocks(n), sl.rows(S)), dim3(kBlock), 0, st, n, r, v,
-                     p, ks, mask, sl.idx);
+                     p, rh, ks, mask, sl.idx);
 }
 
-void launch_bicg_alpha(const Geom& g, const double* A, const double* ph, double* v,
+void launch_bicg_alpha(const Geom& g, const JacOp& J, const double* ph, double* v,
                        const double* rh, double* part, KrylovScalars* ks, int S, const int* mask,
                        SampleList sl, hipStream_t st) {
   const int nb = ceil_div(g.N, kBlock);
-  hipLaunchKernelGGL(k_spmv<kDotOne>, dim3(nb, sl.rows(S)), dim3(kBlock), 0, st, g, A, ph, v, rh,
-                     part, mask, sl.idx);
+  if (J.A)
+    hipLaunchKernelGGL(k_spmv<kDotOne>, dim3(nb, sl.rows(S)), dim3(kBlock), 0, st, g, J.A, ph, v,
+                       rh, part, mask, sl.idx);
+  else
+    launch_jx(g, J.ph, J.dts, J.phi, J.K, J.u, ph, v, rh, part, 1, S, mask, sl.idx, sl.rows(S), st);
   finalize(kAlpha, nb, part, ks, const_cast<int*>(mask), nullptr, S, st);  // mask is `active`
 }
 
@@ -251,12 +285,15 @@ void launch_bicg_s(size_t n, const double* r, const double* v, double* s, double
   finalize(kS, nb, part, ks, const_cast<int*>(mask), nullptr, S, st);
 }
 
-void launch_bicg_omega(const Geom& g, const double* A, const double* sh, const double* s,
+void launch_bicg_omega(const Geom& g, const JacOp& J, const double* sh, const double* s,
                        double* t, double* part, KrylovScalars* ks, int S, const int* mask,
                        SampleList sl, hipStream_t st) {
   const int nb = ceil_div(g.N, kBlock);
-  hipLaunchKernelGGL(k_spmv<kDotTS>, dim3(nb, sl.rows(S)), dim3(kBlock), 0, st, g, A, sh, t, s,
-                     part, mask, sl.idx);
+  if (J.A)
+    hipLaunchKernelGGL(k_spmv<kDotTS>, dim3(nb, sl.rows(S)), dim3(kBlock), 0, st, g, J.A, sh, t, s,
+                       part, mask, sl.idx);
+  else
+    launch_jx(g, J.ph, J.dts, J.phi, J.K, J.u, sh, t, s, part, 2, S, mask, sl.idx, sl.rows(S), st);
   finalize(kOmega, nb, part, ks, const_cast<int*>(mask), nullptr, S, st);
 }
 

@@ -15,17 +15,6 @@
 
 namespace edf {
 
-template <typename T>
-struct V2;
-template <>
-struct V2<double> {
-  using type = double2;
-};
-template <>
-struct V2<float> {
-  using type = float2;
-};
-
 // ---------------------------------------------------------------------------
 // Per-vertex operations.  Pointers are those of one sample; the V-cycle vectors
 // (b, x, r: [Np][2] of T on every level) are in the colour-major order of the

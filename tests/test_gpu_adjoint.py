@@ -28,12 +28,15 @@ def _problem(phys, groups, **opts):
     return Problem(phys, groups, o)
 
 
-@pytest.mark.parametrize("model,precision", [(2, 0), (3, 0), (2, 1), (2, 2)])
-def test_adjoint_gradient_matches_oracle_tangent_linear(model, precision):
+@pytest.mark.parametrize("model,precision,mf", [(2, 0, 0), (3, 0, 0), (2, 1, 0), (2, 2, 0),
+                                               (1, 0, 1), (2, 1, 1)])
+def test_adjoint_gradient_matches_oracle_tangent_linear(model, precision, mf):
+    """Models 1-3, FP64/FP32/FP16-finest V-cycles, assembled or matrix-free forward
+    products (the transposed products are always assembled)."""
     nx, ny, nz = 17, 17, 5
     phys = synth.physics(model)
     xi = np.random.default_rng(21).uniform(-0.6, 0.6, (2, synth.N_XI[model]))
-    pb = _problem(phys, [(nx, ny, nz, 3, 2)], precision=precision)
+    pb = _problem(phys, [(nx, ny, nz, 3, 2)], precision=precision, matrix_free=mf)
     pb.set_parameters(xi)
     J, g = pb.gradient(BOX_UPPER, DT, 3, checkpoint_every=2)
     box = elder.Box(nx, ny, nz, phys)
@@ -131,19 +134,26 @@ BOX_LOWER = (200.0, 400.0, 200.0, 400.0, 100.0, 150.0)  # the bottom 50 m under 
 
 def _fd_gradient(phys, shape, levels, xi0, box, n_steps, h=1e-6):
     """Central differences of the library's own forward map, all 2 n_xi points in one
-    batch with tight tolerances."""
-    from paper_1906_01632_amd import Problem
+    batch with tight tolerances.  A component whose two runs took different sub-steps in
+    some step (a different discrete trajectory, so J jumps) is returned as NaN: finite
+    differences do not apply across that jump."""
     nx, ny, nz = shape
     m = xi0.size
     pts = [xi0 + h * np.eye(m)[q] for q in range(m)] + [xi0 - h * np.eye(m)[q] for q in range(m)]
     pb = _problem(phys, [(nx, ny, nz, levels, 2 * m)])
     pb.set_parameters(np.array(pts))
-    pb.solve(DT, n_steps, stats=False)
+    subs = np.array([[t["substeps"] for t in pb.step(DT)] for _ in range(n_steps)])
     ebox = elder.Box(nx, ny, nz, phys)
     vals = [gradient.qoi(ebox, elder.coefficients(ebox, pts[i]), pb.get_state(i), box)
             for i in range(2 * m)]
     pb.destroy()
-    return np.array([(vals[q] - vals[m + q]) / (2 * h) for q in range(m)])
+    fd = np.array([(vals[q] - vals[m + q]) / (2 * h) for q in range(m)])
+    for q in range(m):
+        if not np.array_equal(subs[:, q], subs[:, m + q]):
+            print(f"FD component {q}: sub-steps {subs[:, q]} vs {subs[:, m + q]}, skipped",
+                  flush=True)
+            fd[q] = np.nan
+    return fd
 
 
 def test_checkpoint_spacing_does_not_change_the_gradient():
@@ -206,7 +216,8 @@ def test_adjoint_of_the_65_cubed_lattice_batch_matches_finite_differences():
     system converges (one sample's, 57, had stalled when the zero-start residual was used
     on the transposed 17x17x5 level), the gradients are finite, and for samples 0 and 57
     they agree with a tightly converged adjoint of the same two samples, which in turn
-    agrees with central differences (h = 1e-6) of the library's forward map to 1e-5."""
+    agrees with central differences (h = 1e-6) of the library's forward map to 1e-5 (a
+    component whose +h and -h runs took different sub-steps is reported and skipped)."""
     from paper_1906_01632_amd import PREC_F64, Problem
     wl = synth.workload("adjoint65")
     phys = synth.physics(wl.field_model)
@@ -227,10 +238,14 @@ def test_adjoint_of_the_65_cubed_lattice_batch_matches_finite_differences():
     st2 = tight.solve(wl.dt, 10, checkpoint_every=10)
     Jt, gt = tight.adjoint(BOX_LOWER)
     tight.destroy()
+    checked = 0
     for q, s in enumerate(pick):
         fd = _fd_gradient(phys, (g.nx, g.ny, g.nz), g.levels, wl.xi[s], BOX_LOWER, 10)
         print(f"sample {s}: batch {dJ[s]} tight {gt[q]} fd {fd}", flush=True)
-        assert np.abs(gt[q] - fd).max() <= 1e-5 * np.abs(fd).max()
+        ok = np.isfinite(fd)
+        checked += int(ok.sum())
+        assert np.abs(gt[q] - fd)[ok].max() <= 1e-5 * np.abs(gt[q]).max()
         if st[s]["substeps_total"] == st2[q]["substeps_total"]:  # same sub-steps taken
             assert abs(J[s] - Jt[q]) <= 1e-8 * abs(Jt[q])
             assert np.abs(dJ[s] - gt[q]).max() <= 1e-4 * np.abs(gt[q]).max()
+    assert checked >= 6  # of the 8 components of the two samples

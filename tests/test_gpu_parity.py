@@ -288,7 +288,9 @@ def test_vcycle_same_for_every_fused_bottom(precision):
     bottom takes the general forms (full stencil, r = b - A x): the two agree to rounding."""
     nx, ny, nz = 33, 33, 9
     phys = synth.physics(2)
-    pb = _problem(phys, [(nx, ny, nz, 4, 3)], precision=precision)
+    # the point smoother on every level, so that moving a level into the fused bottom changes
+    # only the forms of its sweeps, not the smoother
+    pb = _problem(phys, [(nx, ny, nz, 4, 3)], precision=precision, smoother=0)
     pb.set_parameters(_xi(2, 3, seed=11))
     b = np.random.default_rng(5).standard_normal((3, nz, ny, nx, 2))
     b[..., 1][:, -1] = 0.0
@@ -303,6 +305,95 @@ def test_vcycle_same_for_every_fused_bottom(precision):
     for bad in (0, 4, -1):  # 33x33x9 exceeds the fused launch; 4 is no level
         with pytest.raises(RuntimeError):
             pb.set_tuning(0, bad)
+    pb.destroy()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_line_smoothed_vcycle_is_a_contraction(precision):
+    """The vertical-line smoother (columns solved exactly, 4 column colours) on the levels
+    swept by their own launches: one V-cycle reduces the residual at least as well as
+    the point smoother's, and it stays a contraction whichever levels are fused."""
+    nx, ny, nz = 33, 33, 9
+    phys = synth.physics(2)
+    b = np.random.default_rng(0).standard_normal((2, nz, ny, nx, 2))
+    b[..., 1][:, -1] = 0.0
+    red = {}
+    for smoother in (0, 1):
+        pb = _problem(phys, [(nx, ny, nz, 4, 2)], precision=precision, smoother=smoother)
+        pb.set_parameters(_xi(2, 2))
+        for l0 in (2, 3):
+            pb.set_tuning(0, l0)
+            y = pb.apply_vcycle(0, DT, b)
+            Ay = pb.apply_jacobian(0, y)
+            red[(smoother, l0)] = [np.linalg.norm(b[s] - Ay[s]) / np.linalg.norm(b[s])
+                                   for s in range(2)]
+        pb.destroy()
+    print(f"precision {precision}: |b - A M^-1 b|/|b| {red}", flush=True)
+    for l0 in (2, 3):
+        assert max(red[(1, l0)]) < 0.5
+        assert max(red[(1, l0)]) <= 1.05 * max(red[(0, l0)])
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-6)])
+def test_line_smoother_step_matches_oracle(precision, tol):
+    """One step with the line-smoothed V-cycle (levels 0-2 of a 4-level 33x33x9
+    hierarchy swept by separate launches) reaches the oracle's root."""
+    nx, ny, nz = 33, 33, 9
+    phys = synth.physics(2)
+    xi = _xi(2, 2, seed=6)
+    pb = _problem(phys, [(nx, ny, nz, 4, 2)], precision=precision, smoother=1)
+    pb.set_parameters(xi)
+    pb.set_tuning(0, 3)
+    st = pb.step(DT)
+    assert all(t["status"] == 0 for t in st), st
+    box = elder.Box(nx, ny, nz, phys)
+    for s in range(2):
+        ref = newton.newton_solve(box, elder.coefficients(box, xi[s]),
+                                  synth.initial_state(nx, ny, nz, phys), DT)
+        got = pb.get_state(s)
+        for f in range(2):
+            assert _rel(got[..., f], ref[..., f]) < tol, (s, f)
+    pb.destroy()
+
+
+def test_matrix_free_product_equals_the_assembled_jacobian():
+    """The matrix-free J~ x (directional derivative of the defect at the state, upwind
+    frozen) against the product with the assembled exact Jacobian, at random states and
+    directions, every field model: equal to rounding (1e-12 of the largest entry)."""
+    nx, ny, nz = 17, 13, 5
+    for model in (0, 1, 2, 3):
+        phys = synth.physics(model)
+        xi = _xi(model, 2, seed=21)
+        ys = []
+        for mf in (0, 1):
+            pb = _problem(phys, [(nx, ny, nz, 3, 2)], matrix_free=mf)
+            pb.set_parameters(xi)
+            for s in range(2):
+                pb.set_state(s, synth.random_state(nx, ny, nz, phys, seed=40 + s))
+            x = np.random.default_rng(7).standard_normal((2, nz, ny, nx, 2))
+            pb.apply_vcycle(0, DT, x)  # assembles at the states with this step length
+            ys.append(pb.apply_jacobian(0, x))
+            pb.destroy()
+        err = np.abs(ys[1] - ys[0]).max() / np.abs(ys[0]).max()
+        print(f"model {model}: matrix-free vs assembled {err:.2e}", flush=True)
+        assert err < 1e-12, (model, err)
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-6)])
+def test_matrix_free_step_matches_oracle(precision, tol):
+    nx, ny, nz = 33, 33, 9
+    phys = synth.physics(2)
+    xi = _xi(2, 2, seed=16)
+    pb = _problem(phys, [(nx, ny, nz, 4, 2)], precision=precision, matrix_free=1)
+    pb.set_parameters(xi)
+    st = pb.step(DT)
+    assert all(t["status"] == 0 for t in st), st
+    box = elder.Box(nx, ny, nz, phys)
+    for s in range(2):
+        ref = newton.newton_solve(box, elder.coefficients(box, xi[s]),
+                                  synth.initial_state(nx, ny, nz, phys), DT)
+        for f in range(2):
+            assert _rel(pb.get_state(s)[..., f], ref[..., f]) < tol, (s, f)
     pb.destroy()
 
 
@@ -416,7 +507,7 @@ def test_profile_counts_launches_and_algorithmic_bytes():
     is timed, and every V-cycle is timed."""
     nx, ny, nz, L, S = 33, 33, 9, 4, 2
     phys = synth.physics(2)
-    pb = _problem(phys, [(nx, ny, nz, L, S)])
+    pb = _problem(phys, [(nx, ny, nz, L, S)], smoother=0)
     pb.set_parameters(_xi(2, S))
     pb.set_tuning(0, L - 1)  # levels 0..2 smoothed by separate launches
     b = np.random.default_rng(1).standard_normal((S, nz, ny, nx, 2))
@@ -435,6 +526,32 @@ def test_profile_counts_launches_and_algorithmic_bytes():
     assert pr["launches"] == len(range(0, 45, 13))
     assert pr["all_bytes"] == expect
     assert pr["vcycles"] == 1 and pr["vcycle_ms"] > 0 and pr["ms"] > 0
+    pb.destroy()
+
+
+def test_profile_counts_line_smoother_launches():
+    """edf_profile with the vertical-line smoother: 4 column colours per sweep, each
+    vertex of a colour's columns counted with the blocks towards the other columns (24,
+    or from x = 0 the 0, 6, 18, 24 towards the colours already swept), the block above,
+    the 8 factor values, b, and x written, read and written again (116 values)."""
+    nx, ny, nz, L, S = 33, 33, 9, 4, 2
+    phys = synth.physics(2)
+    pb = _problem(phys, [(nx, ny, nz, L, S)], smoother=1)
+    pb.set_parameters(_xi(2, S))
+    pb.set_tuning(0, L - 1)  # levels 0..2 line-smoothed by separate launches
+    b = np.random.default_rng(1).standard_normal((S, nz, ny, nx, 2))
+    pb.profile(True)
+    pb.apply_vcycle(0, DT, b)
+    pr = pb.profile(False)
+    zs_blocks = [0, 6, 18, 24]
+    expect = 0
+    for (gx, gy, gz) in [(33, 33, 9), (17, 17, 5), (9, 9, 3)]:
+        for cc in range(4):
+            ncol = ((gx + 1 - (cc & 1)) // 2) * ((gy + 1 - (cc >> 1)) // 2)
+            per = (4 * (zs_blocks[cc] + 1) + 16) + (4 * 25 + 16)  # pre (from zero), post
+            expect += S * ncol * gz * per * 8
+    assert pr["all_launches"] == 3 * 8
+    assert pr["all_bytes"] == expect
     pb.destroy()
 
 

@@ -124,7 +124,7 @@ def test_mass_balance_matches_the_oracle_definition(precision):
     """edf_step_stats' salt and liquid balance errors: tiny for tightly converged steps
     (FP64 Newton also when the V-cycle runs in FP32), and, for a step stopped early
     (Newton rtol 1e-2), equal to the oracle's mass_balance evaluated at the library's
-    own start and end states."""
+    own start and end states (to 1e-6 relative where the error is above rounding)."""
     nx, ny, nz = 17, 17, 5
     phys = synth.physics(2)
     xi = np.random.default_rng(12).uniform(-0.7, 0.7, (2, 4))
@@ -145,9 +145,14 @@ def test_mass_balance_matches_the_oracle_definition(precision):
             if bound is not None:
                 assert max(got) < bound and max(want) < bound
             else:
-                assert min(want) > 1e-7  # a real imbalance, far above rounding
+                # the salt balance is off by the residual Newton left (far above rounding);
+                # the liquid rows converge at once and stay at the rounding level
+                assert want[0] > 1e-8
                 for g_, w_ in zip(got, want):
-                    assert abs(g_ - w_) <= 1e-6 * w_
+                    if w_ > 1e-12:
+                        assert abs(g_ - w_) <= 1e-6 * w_
+                    else:
+                        assert g_ < 1e-12
         pb.destroy()
 
 
