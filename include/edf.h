@@ -268,6 +268,21 @@ edf_status edf_solve(edf_problem* pb, double dt, int32_t n_steps, int32_t checkp
 edf_status edf_moments(edf_problem* pb, int32_t cx, int32_t cy, int32_t cz, double threshold,
                        const double* weights, double* mean, double* var, double* exceed);
 
+/* edf_moments for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same statistics,
+ * bitwise, with no hipMalloc, hipFree or other allocating call.  Its working memory
+ * (weights, failure flags, the three output fields and the injected c fields of as
+ * many samples at a time as fit) lives in a fixed 16 MiB device array of the library,
+ * one per GPU, held until the process ends; the samples are taken in chunks in sample
+ * order, so the sums are those of edf_moments.  Limit: 2^21 doubles, i.e.
+ * 3 cx cy cz + cx cy cz + S_total (+ alignment) must fit: EDF_ERR_ARG beyond that (use
+ * edf_moments).  Every call on a GPU shares that GPU's array: calls that overlap on one
+ * GPU (two host threads, or two streams) race and must be serialised by the caller.
+ * Arguments, outputs and errors as edf_moments.  Synchronises. */
+edf_status edf_moments_noalloc(edf_problem* pb, int32_t cx, int32_t cy, int32_t cz,
+                               double threshold, const double* weights, double* mean,
+                               double* var, double* exceed);
+
 /* Polynomial chaos surrogate of c from the samples of group `group` (Section 3.1,
  * eqs. PCEdecom2, PCEcoef, PCEcoef2, var; appendix).  The samples are the quadrature
  * nodes: theta_i = xi_i (the parameters of edf_set_parameters, M = n_xi in [1, 4]), with

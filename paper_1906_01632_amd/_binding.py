@@ -81,6 +81,7 @@ _SIGS = {
     "edf_step": [_P, C.c_double, C.POINTER(StepStats)],
     "edf_solve": [_P, C.c_double, C.c_int32, C.c_int32, C.POINTER(StepStats)],
     "edf_moments": [_P, C.c_int32, C.c_int32, C.c_int32, C.c_double, _D, _D, _D, _D],
+    "edf_moments_noalloc": [_P, C.c_int32, C.c_int32, C.c_int32, C.c_double, _D, _D, _D, _D],
     "edf_residual": [_P, C.c_int32, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_int32],
     "edf_get_jacobian": [_P, C.c_int32, _D, C.c_double, C.c_int32, _D],
     "edf_apply_vcycle": [_P, C.c_int32, C.c_double, _D, _D],
@@ -229,8 +230,9 @@ class Problem:
                                         st))
         return [s.as_dict() for s in st] if stats else None
 
-    def moments(self, common, threshold=0.5, weights=None):
-        """Mean, variance and P(c > threshold) on the common grid (edf_moments)."""
+    def moments(self, common, threshold=0.5, weights=None, noalloc=False):
+        """Mean, variance and P(c > threshold) on the common grid (edf_moments, or
+        edf_moments_noalloc, which allocates no device memory)."""
         cx, cy, cz = common
         n = cx * cy * cz
         mean, var, exc = np.empty(n), np.empty(n), np.empty(n)
@@ -238,7 +240,7 @@ class Problem:
         if weights is not None:
             w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
             assert w.size == self.S
-        fn = self._lib.edf_moments
+        fn = self._lib.edf_moments_noalloc if noalloc else self._lib.edf_moments
         self._check(fn(self._h, cx, cy, cz, float(threshold), _dptr(w) if w is not None else None,
                        _dptr(mean), _dptr(var), _dptr(exc)))
         shape = (cz, cy, cx)

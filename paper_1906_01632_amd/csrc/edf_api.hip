@@ -1549,6 +1549,40 @@ edf_status grow(edf_problem* pb, T** buf, size_t* cap, size_t need) {
   return EDF_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch memory of edf_moments_noalloc: a file-scope device array (every device the
+// library runs on holds its own copy until the process ends).  Host code never uses the
+// array's name as an address: each device's copy is located once, with that device
+// current, when the first problem is created on it, and that address is used after.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchDoubles = size_t(1) << 21;  // 16 MiB
+constexpr int kMaxDevices = 64;
+}  // namespace
+namespace edf {
+// external linkage: the device array must stay in the code object although no kernel
+// names it (kernels receive its address as an argument)
+__device__ __align__(256) double scratch[kScratchDoubles];
+}  // namespace edf
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+std::string g_scratch_err[kMaxDevices];
+
+void locate_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[device] || !g_scratch_err[device].empty()) return;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    g_scratch_err[device] = std::string("hipGetSymbolAddress of the scratch array failed: ") +
+                            hipGetErrorString(e);
+    return;
+  }
+  g_scratch[device] = static_cast<double*>(p);
+}
+
 edf_status check_ready(edf_problem* pb) {
   if (!pb) return EDF_ERR_ARG;
   if (!pb->params_set) return fail(pb, EDF_ERR_STATE, "edf_set_parameters has not been called");
@@ -1577,6 +1611,7 @@ edf_status edf_create_problem(const edf_physics* phys, const edf_group_desc* gro
     delete pb;
     return EDF_ERR_HIP;
   }
+  locate_scratch(pb->device);  // once per device (edf_moments_noalloc)
   const edf_physics& P = *phys;
   auto bad = [&](const std::string& m) {
     std::fprintf(stderr, "edf_create_problem: %s\n", m.c_str());
@@ -2024,6 +2059,72 @@ edf_status edf_moments(edf_problem* pb, int32_t cx, int32_t cy, int32_t cz, doub
   EDF_TRY(hipMemcpyAsync(var, out + Nc, Nc * sizeof(double), hipMemcpyDeviceToHost, pb->st));
   EDF_TRY(hipMemcpyAsync(exceed, out + 2 * Nc, Nc * sizeof(double), hipMemcpyDeviceToHost, pb->st));
   EDF_TRY(hipStreamSynchronize(pb->st));
+  return EDF_OK;
+}
+
+edf_status edf_moments_noalloc(edf_problem* pb, int32_t cx, int32_t cy, int32_t cz,
+                               double threshold, const double* weights, double* mean, double* var,
+                               double* exceed) {
+  if (!pb || !mean || !var || !exceed) return EDF_ERR_ARG;
+  if (cx < 2 || cy < 2 || cz < 2) return fail(pb, EDF_ERR_ARG, "common grid too small");
+  for (Group& G : pb->groups) {
+    const Geom& g = G.lv[0].g;
+    if ((g.nx - 1) % (cx - 1) || (g.ny - 1) % (cy - 1) || (g.nz - 1) % (cz - 1))
+      return fail(pb, EDF_ERR_ARG, "common grid not nested in every group");
+  }
+  const size_t Nc = (size_t)cx * cy * cz;
+  const int S = pb->S_total;
+  // scratch layout (doubles): weights [S], failure flags [S] (ints), their sum, the three
+  // output fields [3 Nc], then the c fields of a chunk of samples [chunk][Nc]
+  auto up32 = [](size_t a) { return (a + 31) / 32 * 32; };
+  const size_t o_w = 0, o_flag = up32(S), o_sum = o_flag + up32((S + 1) / 2), o_out = o_sum + 32,
+               o_f = o_out + up32(3 * Nc);
+  if (o_f + Nc > kScratchDoubles)
+    return fail(pb, EDF_ERR_ARG,
+                "edf_moments_noalloc: " + std::to_string(S) + " samples and a common grid of " +
+                    std::to_string(Nc) + " vertices need more than its scratch of " +
+                    std::to_string(kScratchDoubles) + " doubles (use edf_moments)");
+  double* base = (pb->device >= 0 && pb->device < kMaxDevices) ? g_scratch[pb->device] : nullptr;
+  if (!base)
+    return fail(pb, EDF_ERR_HIP, pb->device >= 0 && pb->device < kMaxDevices
+                                     ? g_scratch_err[pb->device]
+                                     : std::string("device index beyond the scratch table"));
+  const int chunk = (int)std::min<size_t>((kScratchDoubles - o_f) / Nc, (size_t)S);
+  hipStream_t st = pb->st;
+  double* w = base + o_w;
+  int* flag = reinterpret_cast<int*>(base + o_flag);
+  double* out = base + o_out;
+  double* f = base + o_f;
+  // the weights (the caller's, or 1/S) and the failure flags, normalised on the device in
+  // sample order as edf_moments does it on the host
+  if (weights)
+    EDF_TRY(hipMemcpyAsync(w, weights, S * sizeof(double), hipMemcpyHostToDevice, st));
+  else
+    launch_fill<double>(w, (size_t)S, 1, nullptr, 1.0 / S, st);
+  for (Group& G : pb->groups)
+    EDF_TRY(hipMemcpyAsync(flag + G.s0, G.fail_status.data(), G.S * sizeof(int),
+                           hipMemcpyHostToDevice, st));
+  launch_normalise_weights(S, w, flag, base + o_sum, st);
+  double sum = 0.0;
+  EDF_TRY(hipMemcpyAsync(&sum, base + o_sum, sizeof(double), hipMemcpyDeviceToHost, st));
+  EDF_TRY(hipStreamSynchronize(st));
+  if (!(sum > 0)) return fail(pb, EDF_ERR_NO_CONVERGENCE, "no valid sample");
+  for (int pass = 0; pass < 2; ++pass)
+    for (int s0 = 0; s0 < S; s0 += chunk) {
+      const int n = std::min(chunk, S - s0);
+      for (Group& G : pb->groups) {  // the chunk's samples of every group, in sample order
+        const int a = std::max(s0, G.s0), b = std::min(s0 + n, G.s0 + G.S);
+        if (a < b)
+          launch_gather_common(G.lv[0].g, cx, cy, cz, G.u + (size_t)(a - G.s0) * G.n,
+                               f + (size_t)(a - s0) * Nc, b - a, st);
+      }
+      launch_moments_chunk(pass, (int)Nc, s0, n, f, w, threshold, out, out + Nc, out + 2 * Nc, st);
+    }
+  EDF_CHECK_LAUNCH();
+  EDF_TRY(hipMemcpyAsync(mean, out, Nc * sizeof(double), hipMemcpyDeviceToHost, st));
+  EDF_TRY(hipMemcpyAsync(var, out + Nc, Nc * sizeof(double), hipMemcpyDeviceToHost, st));
+  EDF_TRY(hipMemcpyAsync(exceed, out + 2 * Nc, Nc * sizeof(double), hipMemcpyDeviceToHost, st));
+  EDF_TRY(hipStreamSynchronize(st));
   return EDF_OK;
 }
 

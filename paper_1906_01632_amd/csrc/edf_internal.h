@@ -298,6 +298,12 @@ void launch_masked_copy(size_t n, const double* a, double* b, int S, const int* 
                         hipStream_t st);
 void launch_gather_common(const Geom& gf, int cx, int cy, int cz, const double* u, double* out,
                           int S, hipStream_t st);
+// chunked form of launch_moments (pass 0: mean and exceedance, pass 1: variance), the
+// fields of samples s0 .. s0 + n - 1 in f [n][Nc]; bitwise the unchunked sums
+void launch_moments_chunk(int pass, int Nc, int s0, int n, const double* f, const double* w,
+                          double thr, double* mean, double* var, double* exc, hipStream_t st);
+// w[s] = 0 where flag[s], then w /= sum(w) (sample order); *sum_out = the sum
+void launch_normalise_weights(int S, double* w, const int* flag, double* sum_out, hipStream_t st);
 void launch_moments(int Nc, int S, const double* f, const double* w, double thr, double* mean,
                     double* var, double* exc, hipStream_t st);
 

@@ -509,6 +509,61 @@ __global__ __launch_bounds__(kBlock) void k_moments(int Nc, int S, const double*
   exc[v] = e;
 }
 
+// The same sums taken over the samples in chunks (fields f [n][Nc] of the samples s0 ..
+// s0 + n - 1, weights w indexed by sample), each chunk added to the running sums in sample
+// order, so that the result is bitwise that of k_moments.  Pass 0: mean and exceedance;
+// pass 1 (after every chunk of pass 0): the variance about the finished mean.
+__global__ __launch_bounds__(kBlock) void k_moments_chunk(int pass, int Nc, int s0, int n,
+                                                          const double* f, const double* w,
+                                                          double thr, double* mean, double* var,
+                                                          double* exc) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= Nc) return;
+  if (pass == 0) {
+    double m = s0 == 0 ? 0.0 : mean[v], e = s0 == 0 ? 0.0 : exc[v];
+    for (int s = 0; s < n; ++s) {
+      const double c = f[(size_t)s * Nc + v];
+      m += w[s0 + s] * c;
+      e += (c > thr) ? w[s0 + s] : 0.0;
+    }
+    mean[v] = m;
+    exc[v] = e;
+  } else {
+    const double m = mean[v];
+    double q = s0 == 0 ? 0.0 : var[v];
+    for (int s = 0; s < n; ++s) {
+      const double d = m - f[(size_t)s * Nc + v];
+      q += w[s0 + s] * d * d;
+    }
+    var[v] = q;
+  }
+}
+
+void launch_moments_chunk(int pass, int Nc, int s0, int n, const double* f, const double* w,
+                          double thr, double* mean, double* var, double* exc, hipStream_t st) {
+  hipLaunchKernelGGL(k_moments_chunk, dim3(ceil_div(Nc, kBlock)), dim3(kBlock), 0, st, pass, Nc,
+                     s0, n, f, w, thr, mean, var, exc);
+}
+
+// weights of the statistics in place: w[s] = 0 for a failed sample (flag[s] != 0), then
+// every weight divided by their sum, taken in sample order (as the host does it for
+// edf_moments); *sum_out = that sum.  One thread: S is the number of samples.
+__global__ void k_normalise_weights(int S, double* w, const int* flag, double* sum_out) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double sum = 0.0;
+  for (int s = 0; s < S; ++s) {
+    if (flag[s]) w[s] = 0.0;
+    sum += w[s];
+  }
+  if (sum > 0.0)
+    for (int s = 0; s < S; ++s) w[s] /= sum;
+  *sum_out = sum;
+}
+
+void launch_normalise_weights(int S, double* w, const int* flag, double* sum_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_normalise_weights, dim3(1), dim3(1), 0, st, S, w, flag, sum_out);
+}
+
 void launch_moments(int Nc, int S, const double* f, const double* w, double thr, double* mean,
                     double* var, double* exc, hipStream_t st) {
   hipLaunchKernelGGL(k_moments, dim3(ceil_div(Nc, kBlock)), dim3(kBlock), 0, st, Nc, S, f, w, thr,
