@@ -40,18 +40,19 @@ def roctx_range():
     return (lambda: None), (lambda: None)
 
 
-# the smoother kernel, its device helpers and the structures it takes: the measured HBM
-# traffic per launch is reported only while their code is unchanged
-KERNEL_SOURCES = ("mg_kernels.hip", "fv_common.h", "edf_internal.h")
+# the smoother kernels, their device helpers and the structures they take: the measured
+# HBM traffic per launch is reported only while their code is unchanged
+KERNEL_SOURCES = {0: ("mg_kernels.hip", "fv_common.h", "edf_internal.h"),
+                  1: ("line_kernels.hip", "fv_common.h", "edf_internal.h")}
 
 
-def kernel_digest():
-    """sha256 of the code of KERNEL_SOURCES: comments and blank space are left out, so
+def kernel_digest(names):
+    """sha256 of the code of the named sources: comments and blank space are left out, so
     that a change of wording does not void a measurement while any change of code does."""
     import hashlib
     import re
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in names:
         with open(os.path.join(ROOT, "paper_1906_01632_amd", "csrc", name)) as f:
             src = f.read()
         src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)   # block comments
@@ -60,18 +61,18 @@ def kernel_digest():
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(smoother):
     """Ratio of measured HBM bytes to algorithmic bytes per smoother launch, from the
     committed rocprofv3 FETCH_SIZE / WRITE_SIZE measurement, or None when the kernel
     sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", "k_smooth_traffic.json")
+    path = os.path.join(ROOT, "profiles", "smoother_traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f)
-        digest = kernel_digest()
+        digest = kernel_digest(KERNEL_SOURCES[smoother])
     except OSError:
         return None
-    if rec.get("kernel_sources_sha256") != digest:
+    if rec.get("smoother") != smoother or rec.get("kernel_sources_sha256") != digest:
         return None
     return rec
 
@@ -206,8 +207,9 @@ def make_problem(args, wl, phys, groups, prec, log_tuning=True):
     t = time.perf_counter()
     pb = Problem(phys, groups, opts)
     pb.set_parameters(wl.xi)
-    if args.fuse_from:
-        levels = [int(v) for v in args.fuse_from.split(",")]
+    fuse = args.fuse_from_fp64 if (prec == "f64" and args.fuse_from_fp64) else args.fuse_from
+    if fuse:
+        levels = [int(v) for v in fuse.split(",")]
         assert len(levels) == len(groups), "--fuse-from needs one level per group"
         for gi, lv in enumerate(levels):
             pb.set_tuning(gi, lv)
@@ -285,27 +287,38 @@ def run_steps(args, wl, pb, prec, region=(None, None)):
 
 
 def roofline_of(leg, wl, prec, smoother):
-    """The dominant kernel (the V-cycle smoother) from the leg's event timing."""
+    """The dominant kernel (the V-cycle smoother) from the leg's event timing.  The figure
+    is that of the launches whose algorithmic bytes exceed the 256 MiB last-level cache
+    (MALL), so that cache hits of small launches cannot pass for HBM bandwidth; the figure
+    over every timed launch is reported beside it."""
     prof = leg["prof"]
     if not prof["launches"]:
         return None
-    gbs = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9
-    tr = measured_traffic()
+    large = prof["large_launches"] > 0
+    n, ms, b = ((prof["large_launches"], prof["large_ms"], prof["large_bytes"]) if large
+                else (prof["launches"], prof["ms"], prof["bytes"]))
+    gbs = b / (ms * 1e-3) / 1e9
+    gbs_all = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9
+    tr = measured_traffic(smoother)
     traffic = ratio = None
-    if tr and tr.get("workload") == wl.name and tr.get("precision") == prec and \
-            tr.get("smoother", 0) == smoother:
+    if tr and tr.get("workload") == wl.name and tr.get("precision") == prec:
         # HBM bytes per launch of this run's launch mix: the measured ratio of HBM to
-        # algorithmic bytes times this run's algorithmic bytes per launch
-        ratio = tr["ratio"]
-        traffic = ratio * prof["all_bytes"] / prof["all_launches"]
-    name = ("k_line_smooth (vertical-line block Gauss-Seidel, one column colour)" if smoother
+        # algorithmic bytes (over the large launches) times this run's algorithmic bytes
+        # per large launch
+        ratio = tr["ratio_large"] if large else tr["ratio"]
+        traffic = ratio * (prof["large_all_bytes"] / prof["large_all_launches"] if large
+                           else prof["all_bytes"] / prof["all_launches"])
+    name = ("k_line_sweep (vertical-line block Gauss-Seidel, one column colour)" if smoother
             else "k_smooth (block Gauss-Seidel colour sweep)")
     return {"bound": "hbm", "kernel": name, "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": gbs / HBM_PEAK_GBS, "traffic": traffic, "traffic_over_algorithmic": ratio,
-            "launches": prof["all_launches"], "launches_timed": prof["launches"],
-            "avg_launch_us": 1e3 * prof["ms"] / prof["launches"],
-            "bytes_per_launch": prof["bytes"] / prof["launches"],
-            "bytes_per_launch_all": prof["all_bytes"] / prof["all_launches"]}
+            "launches": "working set > 256 MiB" if large else "all",
+            "launches_timed": n, "avg_launch_us": 1e3 * ms / n, "bytes_per_launch": b / n,
+            "all_launches": {"achieved": gbs_all, "frac": gbs_all / HBM_PEAK_GBS,
+                             "launches_timed": prof["launches"],
+                             "launches_in_run": prof["all_launches"],
+                             "avg_launch_us": 1e3 * prof["ms"] / prof["launches"],
+                             "bytes_per_launch": prof["bytes"] / prof["launches"]}}
 
 
 def compare_states(ref_states, ref_sub, pb, sub, S):
@@ -350,10 +363,10 @@ def main():
                          "it (implies --no-profile: the roofline times single launches)")
     ap.add_argument("--forcing", type=int, default=1, choices=[0, 1],
                     help="1: Eisenstat-Walker tolerances for the Newton systems")
-    ap.add_argument("--smoother", type=int, default=0, choices=[0, 1],
+    ap.add_argument("--smoother", type=int, default=1, choices=[0, 1],
                     help="0: point-block Gauss-Seidel in 8 colours; 1: vertical-line block "
                          "Gauss-Seidel (z-columns solved exactly, 4 column colours)")
-    ap.add_argument("--matrix-free", type=int, default=0, choices=[0, 1],
+    ap.add_argument("--matrix-free", type=int, default=1, choices=[0, 1],
                     help="1: matrix-free Jacobian products in BiCGStab (no exact stencil)")
     ap.add_argument("--substep-memory", type=int, default=1, choices=[0, 1],
                     help="1: a sample starts a step with the sub-step count that worked in its "
@@ -375,6 +388,8 @@ def main():
     ap.add_argument("--fuse-from", default=None,
                     help="first fused V-cycle level per group, comma separated (instead of "
                          "autotuning; e.g. to repeat a run's launch configuration under a profiler)")
+    ap.add_argument("--fuse-from-fp64", default=None,
+                    help="as --fuse-from, for the FP64 leg of the two-leg default run")
     ap.add_argument("--mark-timed-region", action="store_true",
                     help="mark the timed steps with a roctx range (rocprofv3 --marker-trace)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -409,7 +424,15 @@ def main():
         log(f"workload {wl.name}: groups {groups}, FP64 leg")
         pb, tuning64 = make_problem(args, wl, phys, groups, "f64")
         leg64 = run_steps(args, wl, pb, "f64")
-        ref = ([pb.get_state(s) for s in range(S)], leg64["substeps"])
+        # the reference of the precision comparison: one more FP64 step from the states
+        # reached, with every sample's sub-step history cleared (edf_set_state), so that the
+        # mixed leg can take the same step from the same states
+        end64 = [pb.get_state(s) for s in range(S)]
+        for s in range(S):
+            pb.set_state(s, end64[s])
+        st64 = pb.step(wl.dt)
+        ref = (end64, leg64["substeps"], [pb.get_state(s) for s in range(S)],
+               np.array([[t["substeps"] for t in st64]]))
         pb.destroy()
         torch.cuda.synchronize()
     log(f"workload {wl.name}: groups {groups}, precision {prec}")
@@ -456,13 +479,27 @@ def main():
     if rl:
         out["roofline"] = rl
     if two_legs:
-        out["mixed_vs_fp64"] = compare_states(ref[0], ref[1], pb, leg["substeps"], S)
+        # context: the two trajectories after W + K steps (the fingering instability
+        # amplifies the solvers' tolerance-level differences over the months)
+        traj = compare_states(ref[0], ref[1], pb, leg["substeps"], S)
+        # the comparison proper: one step of each precision from the same states
+        for s in range(S):
+            pb.set_state(s, ref[0][s])
+        st = pb.step(wl.dt)
+        out["mixed_vs_fp64"] = compare_states(ref[2], ref[3], pb,
+                                              np.array([[t["substeps"] for t in st]]), S)
+        out["mixed_vs_fp64"]["what"] = ("one step of each precision from the FP64 states after "
+                                        f"{args.warmup + args.steps} steps, per sample and field")
+        out["mixed_vs_fp64_trajectory"] = dict(traj, what=f"the two runs after {args.warmup + args.steps} "
+                                               "steps each (context: trajectories of this unstable "
+                                               "flow amplify tolerance-level differences)")
         out["fp64"] = {"value": leg64["value"], "ms_per_step": 1e3 * leg64["el"] / args.steps,
                        "dtype": "f64", "fused_bottom_from_level": tuning64,
                        "solver": leg64["solver"], "vcycle": leg64.get("vcycle"),
                        "roofline": roofline_of(leg64, wl, "f64", args.smoother)}
         out["mixed_over_fp64"] = leg["value"] / leg64["value"]
-        log(f"mixed vs FP64: {out['mixed_vs_fp64']}; {out['mixed_over_fp64']:.3f} x the FP64 rate")
+        log(f"mixed vs FP64, one step from shared states: {out['mixed_vs_fp64']}; trajectories: "
+            f"{out['mixed_vs_fp64_trajectory']}; {out['mixed_over_fp64']:.3f} x the FP64 rate")
     if wl.name in synth.E1_GRIDS:
         # the box experiment's comparison after the last timed step: 200 Halton qMC samples
         # (group 0) against the degree-4 surrogate from the 125 quadrature nodes (group 1)

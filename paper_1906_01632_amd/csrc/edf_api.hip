@@ -46,7 +46,11 @@ struct Level {
 struct ProfRec {
   int pair, kind;  // kind 0: one smoother launch, 1: one whole V-cycle
   double bytes;    // algorithmic bytes
+  bool large;      // a smoother launch of more than kLargeLaunch bytes
 };
+// launches that move more than this are beyond the 256 MiB last-level cache, so their
+// bandwidth is HBM bandwidth; smaller ones may partly hit the cache
+constexpr double kLargeLaunch = 256.0 * 1024 * 1024;
 
 struct Group {
   edf_group_desc d{};
@@ -63,8 +67,11 @@ struct Group {
   bool prof_on = false;
   std::vector<hipEvent_t> prof_ev;
   std::vector<ProfRec> prof_pending;
-  double prof_count[2] = {0, 0}, prof_ms[2] = {0, 0}, prof_bytes[2] = {0, 0};
-  double prof_all_count = 0, prof_all_bytes = 0;  // every smoother launch, timed or not
+  // [0] timed smoother launches, [1] V-cycles, [2] the timed smoother launches whose
+  // algorithmic bytes exceed kLargeLaunch (working sets beyond the last-level cache)
+  double prof_count[3] = {0, 0, 0}, prof_ms[3] = {0, 0, 0}, prof_bytes[3] = {0, 0, 0};
+  // every smoother launch, timed or not: all of them, and those beyond kLargeLaunch
+  double prof_all_count[2] = {0, 0}, prof_all_bytes[2] = {0, 0};
   long long prof_tick = 0;
   int S = 0, s0 = 0, L = 0;
   std::vector<Level> lv;
@@ -452,9 +459,14 @@ constexpr int kProfStride = 13;
 
 bool prof_pair(Group& G, hipEvent_t& a, hipEvent_t& b, double bytes, int kind) {
   if (!G.prof_on) return false;
+  const bool large = kind == 0 && bytes > kLargeLaunch;
   if (kind == 0) {
-    G.prof_all_count += 1;
-    G.prof_all_bytes += bytes;
+    G.prof_all_count[0] += 1;
+    G.prof_all_bytes[0] += bytes;
+    if (large) {
+      G.prof_all_count[1] += 1;
+      G.prof_all_bytes[1] += bytes;
+    }
     if (G.prof_tick++ % kProfStride != 0) return false;
   }
   const size_t k = G.prof_pending.size();
@@ -465,7 +477,7 @@ bool prof_pair(Group& G, hipEvent_t& a, hipEvent_t& b, double bytes, int kind) {
   }
   a = G.prof_ev[2 * k];
   b = G.prof_ev[2 * k + 1];
-  G.prof_pending.push_back({(int)k, kind, bytes});
+  G.prof_pending.push_back({(int)k, kind, bytes, large});
   return true;
 }
 
@@ -477,6 +489,11 @@ edf_status prof_flush(edf_problem* pb, Group& G) {
     G.prof_count[r.kind] += 1;
     G.prof_ms[r.kind] += ms;
     G.prof_bytes[r.kind] += r.bytes;
+    if (r.large) {
+      G.prof_count[2] += 1;
+      G.prof_ms[2] += ms;
+      G.prof_bytes[2] += r.bytes;
+    }
   }
   G.prof_pending.clear();
   return EDF_OK;
@@ -2306,7 +2323,7 @@ edf_status edf_profile(edf_problem* pb, int32_t enable, double* out) {
   if (!pb) return EDF_ERR_ARG;
   edf_status e;
   if (out)
-    for (int q = 0; q < 8; ++q) out[q] = 0.0;
+    for (int q = 0; q < 13; ++q) out[q] = 0.0;
   for (Group& G : pb->groups) {
     if ((e = prof_flush(pb, G))) return e;
     if (out) {
@@ -2315,12 +2332,17 @@ edf_status edf_profile(edf_problem* pb, int32_t enable, double* out) {
         out[3 * k + 1] += G.prof_ms[k];
         out[3 * k + 2] += G.prof_bytes[k];
       }
-      out[6] += G.prof_all_count;
-      out[7] += G.prof_all_bytes;
+      out[6] += G.prof_all_count[0];
+      out[7] += G.prof_all_bytes[0];
+      out[8] += G.prof_count[2];
+      out[9] += G.prof_ms[2];
+      out[10] += G.prof_bytes[2];
+      out[11] += G.prof_all_count[1];
+      out[12] += G.prof_all_bytes[1];
     }
     if (enable) {
-      for (int k = 0; k < 2; ++k) G.prof_count[k] = G.prof_ms[k] = G.prof_bytes[k] = 0;
-      G.prof_all_count = G.prof_all_bytes = 0;
+      for (int k = 0; k < 3; ++k) G.prof_count[k] = G.prof_ms[k] = G.prof_bytes[k] = 0;
+      for (int k = 0; k < 2; ++k) G.prof_all_count[k] = G.prof_all_bytes[k] = 0;
       G.prof_tick = 0;
     }
     G.prof_on = enable != 0;
