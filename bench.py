@@ -61,10 +61,10 @@ def kernel_digest(names):
     return h.hexdigest()
 
 
-def measured_traffic(smoother):
-    """Ratio of measured HBM bytes to algorithmic bytes per smoother launch, from the
-    committed rocprofv3 FETCH_SIZE / WRITE_SIZE measurement, or None when the kernel
-    sources changed since it was taken."""
+def measured_traffic(smoother, wl_name, prec):
+    """The committed rocprofv3 FETCH_SIZE / WRITE_SIZE measurement of the smoother for this
+    workload and precision (ratios of HBM to algorithmic bytes per launch), or None when
+    there is none or the kernel sources changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "smoother_traffic.json")
     try:
         with open(path) as f:
@@ -72,8 +72,236 @@ def measured_traffic(smoother):
         digest = kernel_digest(KERNEL_SOURCES[smoother])
     except OSError:
         return None
-    if rec.get("smoother") != smoother or rec.get("kernel_sources_sha256") != digest:
+    if rec.get("smoother") != smoother or rec.get("kernel_sources_sha256") != digest or \
+            rec.get("workload") != wl_name:
         return None
+    return rec.get("precisions", {}).get(prec)
+
+
+# ---------------------------------------------------------------------------------------
+# Summaries of rocprofv3 CSV output (host only; `--summarise-trace`, `--summarise-counters`)
+# ---------------------------------------------------------------------------------------
+LARGE_LAUNCH = 256 * 1024 * 1024   # working sets beyond the 256 MiB last-level cache
+ZERO_START_BLOCKS = (0, 6, 18, 24)  # line sweep from zero: blocks read per column colour
+JX_FLOPS = 2300.0    # k_jx: FP64 flops per interior vertex (FMA = 2) of the compiled loop
+JX_BYTES = 80.0      # k_jx: u, x, y, d (16 B each) + phi and K (8 B each) per vertex
+
+
+def _levels(wl):
+    """(nx, ny, nz) of every level of every group of the workload."""
+    out = []
+    for q in wl.groups:
+        for l in range(q.levels):
+            f = 1 << l
+            out.append(((q.nx - 1) // f + 1, (q.ny - 1) // f + 1, (q.nz - 1) // f + 1))
+    return out
+
+
+def _par(n, p):
+    """indices of parity p among n."""
+    return (n - p + 1) // 2
+
+
+def _line_tables(wl):
+    """(workgroups along x, threads per workgroup) -> {(columns, nz)} of the line-smoother
+    launches of the workload's levels (k_line_sweep: 16 columns per 256-thread workgroup,
+    the column-walk fallback k_line_smooth: 64 per 64), and padded colour-major size ->
+    (level, per-colour-of-columns vertex counts) for the residual launches."""
+    sweep, resid = {}, {}
+    for nx, ny, nz in _levels(wl):
+        for cc in range(4):
+            nc = _par(nx, cc & 1) * _par(ny, cc >> 1)
+            sweep.setdefault((-(-nc // 16), 256), set()).add((nc, nz))
+            sweep.setdefault((-(-nc // 64), 64), set()).add((nc, nz))
+        pad = sum(-(-(_par(nx, c & 1) * _par(ny, c >> 1 & 1) * _par(nz, c >> 2)) // 64) * 64
+                  for c in range(8))
+        per_cc = [_par(nx, cc & 1) * _par(ny, cc >> 1) * nz for cc in range(4)]
+        resid.setdefault(-(-pad // 256) * 256, set()).add(tuple(per_cc))
+    return sweep, resid
+
+
+def _dispatch_bytes(name, bx, wx, gx, rows, sweep, resid):
+    """Algorithmic bytes of one smoother or residual dispatch (the library's count), or
+    None for other kernels and ambiguous grids."""
+    import re
+    m = re.search(r"k_line_(?:sweep|smooth)<(float|double), (?:true|false), (-?\d+)>", name)
+    if m:
+        cand = sweep.get((bx, wx), set())
+        if len(cand) != 1:
+            return None
+        (nc, nz), = cand
+        nb = 24 if int(m.group(2)) < 0 else ZERO_START_BLOCKS[int(m.group(2))]
+        return rows * nc * nz * (4 * (nb + 1) + 16) * (4 if m.group(1) == "float" else 8)
+    m = re.search(r"k_line_residual_zs<(float|double), (?:true|false)>", name)
+    if m:
+        cand = resid.get(gx, set())
+        if len(cand) != 1:
+            return None
+        per_cc, = cand
+        t = 4 if m.group(1) == "float" else 8
+        return rows * t * sum(n * (4 * (24 - ZERO_START_BLOCKS[cc]) + 2) for cc, n in enumerate(per_cc))
+    return None
+
+
+def _csv(d, suffix):
+    import glob
+    f = glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)
+    if not f:
+        raise SystemExit(f"no *{suffix} under {d}")
+    import csv
+    with open(f[0]) as fh:
+        return list(csv.DictReader(fh))
+
+
+def _col(row, name):
+    for c in row:
+        if c.replace("-", "_").lower() == name.lower():
+            return row[c]
+    return None
+
+
+def summarise_trace(d, leg, wl):
+    """Markdown summary of a `rocprofv3 --kernel-trace --marker-trace` run of this script
+    with --mark-timed-region: per-kernel totals inside the leg's "timed steps" range, the
+    GPU busy share, algorithmic GB/s of the smoother (all launches and those beyond 256 MiB),
+    of the residual and of the matrix-free product (with its FP64 TFLOP/s), and the
+    histogram of active samples per launch."""
+    import collections
+    rows = _csv(d, "kernel_trace.csv")
+    ranges = sorted((int(_col(r, "Start_Timestamp")), int(_col(r, "End_Timestamp")))
+                    for r in _csv(d, "marker_api_trace.csv") if "timed steps" in str(r))
+    t0, t1 = ranges[leg]
+    sel = [r for r in rows if int(_col(r, "Start_Timestamp")) >= t0 and int(_col(r, "End_Timestamp")) <= t1]
+    short = lambda n: n.split("(")[0].replace("void ", "").replace("edf::", "")
+    out = [f"timed-steps range {leg} of {len(ranges)}"]
+    tot = collections.defaultdict(lambda: [0, 0.0])
+    iv = []
+    for r in sel:
+        s, e = int(_col(r, "Start_Timestamp")), int(_col(r, "End_Timestamp"))
+        tot[short(_col(r, "Kernel_Name"))][0] += 1
+        tot[short(_col(r, "Kernel_Name"))][1] += (e - s) * 1e-3
+        iv.append((s, e))
+    iv.sort()
+    busy, cs, ce = 0, None, None
+    for s, e in iv:
+        if ce is None or s > ce:
+            if ce is not None:
+                busy += ce - cs
+            cs, ce = s, e
+        else:
+            ce = max(ce, e)
+    if ce is not None:
+        busy += ce - cs
+    allms = sum(v[1] for v in tot.values()) * 1e-3
+    out.append(f"timed region {(t1 - t0) * 1e-6:.1f} ms, GPU busy {busy * 1e-6:.1f} ms "
+               f"({100 * busy / (t1 - t0):.1f} %), kernel time {allms:.1f} ms")
+    out += ["", "| kernel | calls | avg us | total ms | % of kernel time |", "|---|---|---|---|---|"]
+    for k, (n, us) in sorted(tot.items(), key=lambda kv: -kv[1][1])[:25]:
+        out.append(f"| `{k}` | {n} | {us / n:.2f} | {us * 1e-3:.1f} | {100 * us * 1e-3 / allms:.1f} |")
+    sweep, resid = _line_tables(wl)
+    fin = {}
+    for q in wl.groups:   # k_jx grid: nx ny ceil(nz / 8) threads in 256-thread workgroups
+        fin[-(-q.nx * q.ny * -(-q.nz // 8) // 256) * 256] = q.nx * q.ny * q.nz
+    agg = collections.defaultdict(lambda: [0, 0.0, 0.0, 0.0])
+    hist = collections.defaultdict(collections.Counter)
+    for r in sel:
+        name = _col(r, "Kernel_Name")
+        k = short(name)
+        dur = (int(_col(r, "End_Timestamp")) - int(_col(r, "Start_Timestamp"))) * 1e-9
+        gx, gy = int(_col(r, "Grid_Size_X")), int(_col(r, "Grid_Size_Y"))
+        wx = int(_col(r, "Workgroup_Size_X"))
+        b = _dispatch_bytes(name, gx // wx, wx, gx, gy, sweep, resid)
+        if b is not None:
+            base = k.split("<")[0]
+            for key in (base + " (all)",) + ((base + " (> 256 MiB)",) if b > LARGE_LAUNCH else ()):
+                a = agg[key]; a[0] += 1; a[1] += dur; a[2] += b
+        if k.startswith("k_jx") and gx in fin:
+            a = agg["k_jx (finest grids)"]; a[0] += 1; a[1] += dur
+            a[2] += JX_BYTES * fin[gx] * gy; a[3] += JX_FLOPS * fin[gx] * gy
+        if k.startswith(("k_line_sweep", "k_jx", "k_line_residual_zs")):
+            hist[(k.split("<")[0], gx)][gy] += 1
+    out += ["", "| kernel | dispatches | avg us | MB per dispatch | GB/s (algorithmic) | frac of 8 TB/s | FP64 TFLOP/s |",
+            "|---|---|---|---|---|---|---|"]
+    for k, (n, sec, b, f) in sorted(agg.items()):
+        tf = f"{f / sec / 1e12:.1f} ({f / sec / 78.6e12:.3f} of 78.6)" if f else "-"
+        out.append(f"| {k} | {n} | {1e6 * sec / n:.1f} | {b / n / 1e6:.1f} | {b / sec / 1e9:.0f} | "
+                   f"{b / sec / 8e12:.3f} | {tf} |")
+    out += ["", "active samples per launch (grid rows), by kernel and grid x:"]
+    edges = [1, 2, 4, 8, 16, 32, 64, 128, 256]
+    for (name, x), c in sorted(hist.items(), key=lambda kv: -sum(kv[1].values()))[:10]:
+        n = sum(c.values())
+        parts = []
+        for lo, hi in zip(edges, edges[1:] + [10 ** 9]):
+            m = sum(v for rr, v in c.items() if lo <= rr < hi)
+            parts.append(f"{lo}-{hi - 1 if hi < 10 ** 9 else 'up'}: {100 * m / n:.0f}%")
+        out.append(f"- {name} grid x {x}: {n} dispatches; " + ", ".join(parts))
+    return "\n".join(out)
+
+
+def _counter_run(d, regex, sweep, resid):
+    """Counter totals of one `rocprofv3 --pmc C --kernel-trace` run of this script with
+    --copy-probe: (KiB the probe's copy dispatches read or wrote, accumulators of the
+    matching dispatches after it: all, and those beyond 256 MiB of algorithmic bytes)."""
+    import re
+    times, grids = {}, {}
+    for r in _csv(d, "kernel_trace.csv"):
+        di = int(_col(r, "Dispatch_Id"))
+        times[di] = (int(_col(r, "Start_Timestamp")), int(_col(r, "End_Timestamp")), _col(r, "Kernel_Name"))
+        gx, wx = int(_col(r, "Grid_Size_X")), int(_col(r, "Workgroup_Size_X"))
+        grids[di] = (gx // wx, wx, gx, int(_col(r, "Grid_Size_Y")))
+    per = {}
+    for r in _csv(d, "counter_collection.csv"):
+        di = int(_col(r, "Dispatch_Id"))
+        per[di] = per.get(di, 0.0) + float(_col(r, "Counter_Value"))
+    # the probe: copy dispatches with 0.2 s or more of idle time before and after them
+    order = sorted(times, key=lambda x: times[x][0])
+    probe = []
+    for n, di in enumerate(order):
+        if "copyBuffer" not in times[di][2] or (n and times[di][0] - times[order[n - 1]][1] < 0.2e9):
+            continue
+        grp, m = [di], n + 1
+        while m < len(order) and "copyBuffer" in times[order[m]][2] and \
+                times[order[m]][0] - times[order[m - 1]][1] < 0.2e9:
+            grp.append(order[m])
+            m += 1
+        if m == len(order) or times[order[m]][0] - times[order[m - 1]][1] >= 0.2e9:
+            probe = grp
+    if not probe:
+        raise SystemExit(f"no isolated copy probe in {d}")
+    acc = {"all": [0, 0.0, 0.0], "large": [0, 0.0, 0.0]}
+    for di in order:
+        if times[di][0] <= times[probe[-1]][0] or not re.search(regex, times[di][2]):
+            continue
+        bx, wx, gx, gy = grids[di]
+        b = _dispatch_bytes(times[di][2], bx, wx, gx, gy, sweep, resid)
+        if b is None:
+            continue
+        for k in ("all",) + (("large",) if b > LARGE_LAUNCH else ()):
+            acc[k][0] += 1; acc[k][1] += per.get(di, 0.0); acc[k][2] += b
+    return sum(per.get(di, 0.0) for di in probe), len(probe), acc
+
+
+def summarise_counters(fetch_dir, write_dir, wl, precision, smoother, command):
+    """The smoother's HBM traffic per launch over its algorithmic bytes, from a FETCH_SIZE
+    and a WRITE_SIZE run, each scaled by what the same counter reads for the probe's 1 GiB
+    device copy (1 GiB read, 1 GiB written)."""
+    sweep, resid = _line_tables(wl)
+    regex = r"k_line_sweep" if smoother else r"k_smooth<"
+    rec = {"precision": precision, "command": command}
+    runs = {}
+    for cname, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        kib, n, acc = _counter_run(d, regex, sweep, resid)
+        runs[cname] = (1024.0 * 1024.0 / kib, acc)
+        rec[cname] = {"probe_kib": kib, "probe_dispatches": n, "scale": 1024.0 * 1024.0 / kib}
+    for k in ("all", "large"):
+        (fs, fa), (ws, wa) = runs["FETCH_SIZE"], runs["WRITE_SIZE"]
+        if not fa[k][0] or not wa[k][0]:
+            continue
+        fetch = fs * fa[k][1] * 1024.0 / fa[k][0]
+        write = ws * wa[k][1] * 1024.0 / wa[k][0]
+        rec[k] = {"dispatches": fa[k][0], "algorithmic_bytes_per_dispatch": fa[k][2] / fa[k][0],
+                  "hbm_fetch_bytes_per_dispatch": fetch, "hbm_write_bytes_per_dispatch": write,
+                  "ratio": fs * fa[k][1] * 1024.0 / fa[k][2] + ws * wa[k][1] * 1024.0 / wa[k][2]}
     return rec
 
 
@@ -238,10 +466,14 @@ def run_steps(args, wl, pb, prec, region=(None, None)):
     if not args.no_profile:
         pb.profile(True)
     if args.copy_probe:
+        # idle gaps of 0.25 s on both sides set the probe's dispatches apart in a trace
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        time.sleep(0.25)
         b.copy_(a)
         torch.cuda.synchronize()
+        time.sleep(0.25)
         del a, b
     if region[0]:
         region[0]()
@@ -299,13 +531,13 @@ def roofline_of(leg, wl, prec, smoother):
                 else (prof["launches"], prof["ms"], prof["bytes"]))
     gbs = b / (ms * 1e-3) / 1e9
     gbs_all = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9
-    tr = measured_traffic(smoother)
+    tr = measured_traffic(smoother, wl.name, prec)
     traffic = ratio = None
-    if tr and tr.get("workload") == wl.name and tr.get("precision") == prec:
+    if tr and tr.get("large" if large else "all"):
         # HBM bytes per launch of this run's launch mix: the measured ratio of HBM to
         # algorithmic bytes (over the large launches) times this run's algorithmic bytes
         # per large launch
-        ratio = tr["ratio_large"] if large else tr["ratio"]
+        ratio = tr["large" if large else "all"]["ratio"]
         traffic = ratio * (prof["large_all_bytes"] / prof["large_all_launches"] if large
                            else prof["all_bytes"] / prof["all_launches"])
     name = ("k_line_sweep (vertical-line block Gauss-Seidel, one column colour)" if smoother
@@ -395,7 +627,49 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="copy 1 GiB device-to-device at the start of the timed region (a copy "
                          "of known size that calibrates the HBM byte counters)")
+    ap.add_argument("--summarise-trace", metavar="DIR", default=None,
+                    help="summarise the CSV of a rocprofv3 --kernel-trace --marker-trace run of "
+                         "this script (with --mark-timed-region) and exit; no GPU is used")
+    ap.add_argument("--leg", type=int, default=-1,
+                    help="with --summarise-trace: which timed-steps range (0: FP64 leg, 1: mixed)")
+    ap.add_argument("--summarise-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    default=None,
+                    help="HBM traffic of the smoother from rocprofv3 --pmc FETCH_SIZE and "
+                         "WRITE_SIZE runs (each with --kernel-trace) of this script with "
+                         "--copy-probe; added to --summary-out under --precision; no GPU is used")
+    ap.add_argument("--summary-out", default=None)
+    ap.add_argument("--profile-command", default="",
+                    help="with --summarise-counters: the command that made the counter runs")
     args = ap.parse_args()
+    if args.summarise_trace or args.summarise_counters:
+        import synth
+        wl = synth.workload(args.workload)
+        if args.summarise_trace:
+            print(summarise_trace(args.summarise_trace, args.leg, wl))
+            return
+        prec = args.precision or "mixed"
+        rec = summarise_counters(*args.summarise_counters, wl, prec, args.smoother,
+                                 args.profile_command)
+        digest = kernel_digest(KERNEL_SOURCES[args.smoother])
+        full = {}
+        if args.summary_out and os.path.exists(args.summary_out):
+            with open(args.summary_out) as f:
+                full = json.load(f)
+        if (full.get("smoother"), full.get("workload"), full.get("kernel_sources_sha256")) != \
+                (args.smoother, wl.name, digest):
+            full = {"kernel": ("k_line_sweep<T, NT, ZC>, all instances" if args.smoother
+                               else "k_smooth<T, NT, ZC>, all instances"),
+                    "smoother": args.smoother, "workload": wl.name,
+                    "kernel_sources": ["paper_1906_01632_amd/csrc/" + n
+                                       for n in KERNEL_SOURCES[args.smoother]],
+                    "kernel_sources_sha256": digest, "precisions": {}}
+        full["precisions"][prec] = rec
+        text = json.dumps(full, indent=1)
+        if args.summary_out:
+            with open(args.summary_out, "w") as f:
+                f.write(text + "\n")
+        print(text)
+        return
     region = roctx_range() if args.mark_timed_region else (None, None)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): samples are independent, "

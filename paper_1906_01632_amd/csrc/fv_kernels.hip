@@ -286,16 +286,24 @@ void launch_defect(const Geom& g, const Phys& ph, const double* dts, const doubl
 //   salt    d(rho(c_up) c_up Q) - d(rho(c_f) phi D_m d_d c) A
 //         = (rho0 + 2 (rho1 - rho0) c_up) dc_up Q + rho(c_up) c_up dQ
 //           - ((rho1 - rho0) dc_f phi D_m d_d c + rho(c_f) phi D_m d_d(dc)) A,
-// plus the storage derivatives; Dirichlet rows are identity rows.  The kernel walks the
-// 8 hexahedra around the vertex and loads each one's corners (state and direction) from
-// the cache, which keeps the register count at a quarter of holding the 3x3x3
-// neighbourhood of both fields.
+// plus the storage derivatives; Dirichlet rows are identity rows.
+//
+// One thread walks a segment of a vertical column (i, j) upwards, one layer of
+// hexahedra (between planes L and L + 1) at a time.  Of each of the (up to) 4 hexahedra
+// around the column in the layer it loads the 8 corners (state and direction, cache
+// resident) and evaluates the faces through the column's two vertices in the layer: the
+// vertical edge's face once (outflow of the lower vertex, inflow of the upper), and the x
+// and y faces at either end, 5 faces per hexahedron and layer.  The lower vertex is then
+// complete; the upper one carries its part into the next layer.
 // ---------------------------------------------------------------------------
+// linearised liquid and salt flux (yl, ys) out of the start vertex of the edge of the
+// face of direction D through corner (AX, AY, AZ) of a hexahedron with corner values
+// P, C (state) and XP, XC (direction, pressure in physical units); kmu = K / mu
 template <int AX, int AY, int AZ, int D>
-__device__ __forceinline__ void face_tangent(const double* P, const double* C, const double* XP,
-                                             const double* XC, double phi, double K,
-                                             const Phys& ph, const FaceGeo& fg, double& Yl,
-                                             double& Ys) {
+__device__ __forceinline__ void face_tangent_flux(const double* P, const double* C,
+                                                  const double* XP, const double* XC, double phi,
+                                                  double kmu, const Phys& ph, const FaceGeo& fg,
+                                                  double& yl, double& ys) {
   using F = FaceT<AX, AY, AZ, D>;
   constexpr int WA = F::SB0 + 2 * F::SB1 + 4 * F::SB2;  // the edge's start corner
   constexpr int WB = WA + (1 << D);                      // and its end
@@ -317,18 +325,29 @@ __device__ __forceinline__ void face_tangent(const double* P, const double* C, c
   const double area = fg.area[D];
   const double gD = D == 2 ? ph.g : 0.0;
   const double rf = ph.rho0 + ph.drho * cf;
-  const double kmu = K / ph.mu * area;
-  const double Q = -kmu * (dp - rf * gD);
-  const double tQ = -kmu * (tdp - ph.drho * tcf * gD);
+  const double ka = kmu * area;
+  const double Q = -ka * (dp - rf * gD);
+  const double tQ = -ka * (tdp - ph.drho * tcf * gD);
   const bool up_start = Q >= 0.0;
   const double cup = up_start ? C[WA] : C[WB];
   const double tcup = up_start ? XC[WA] : XC[WB];
   const double ru = ph.rho0 + ph.drho * cup;
   const double diff = phi * ph.Dm * area;
-  const double yl = ph.drho * tcf * Q + rf * tQ;
-  const double ys = (ph.rho0 + 2.0 * ph.drho * cup) * tcup * Q + ru * cup * tQ -
-                    (ph.drho * tcf * dc + rf * tdc) * diff;
-  if (F::VD == 0) {
+  yl = ph.drho * tcf * Q + rf * tQ;
+  ys = (ph.rho0 + 2.0 * ph.drho * cup) * tcup * Q + ru * cup * tQ -
+       (ph.drho * tcf * dc + rf * tdc) * diff;
+}
+
+// the same flux added to the rows of the vertex at corner (AX, AY, AZ): out of it when it
+// is the edge's start, into it otherwise
+template <int AX, int AY, int AZ, int D>
+__device__ __forceinline__ void face_tangent(const double* P, const double* C, const double* XP,
+                                             const double* XC, double phi, double kmu,
+                                             const Phys& ph, const FaceGeo& fg, double& Yl,
+                                             double& Ys) {
+  double yl, ys;
+  face_tangent_flux<AX, AY, AZ, D>(P, C, XP, XC, phi, kmu, ph, fg, yl, ys);
+  if (FaceT<AX, AY, AZ, D>::VD == 0) {
     Yl += yl;
     Ys += ys;
   } else {
@@ -337,74 +356,161 @@ __device__ __forceinline__ void face_tangent(const double* P, const double* C, c
   }
 }
 
-template <int AX, int AY, int AZ>
-__device__ __forceinline__ void hex_tangent(const Geom& g, int i, int j, int k, const double* phi,
-                                            const double* K, const double2* u, const double2* x,
-                                            const Phys& ph, const FaceGeo& fg, double& Yl,
-                                            double& Ys, double& msum) {
-  const int hi = i - AX, hj = j - AY, hk = k - AZ;
-  if (hi < 0 || hj < 0 || hk < 0 || hi > g.nx - 2 || hj > g.ny - 2 || hk > g.nz - 2) return;
-  const size_t e = hi + (size_t)(g.nx - 1) * (hj + (size_t)(g.ny - 1) * hk);
-  const double pe = phi[e], Ke = K[e];
-  msum += pe;
+// Hexahedron of the layer with the column at its corner (AX, AY) (AX = 1: the hexahedron
+// on the column's -x side) whose corner (0, 0, 0) is vertex v0: adds the faces through
+// the lower vertex to (Ll, Sl) when lo, and those through the upper vertex to (Lu, Su)
+// when hi.
+template <int AX, int AY>
+__device__ __forceinline__ void layer_hex(const Geom& g, const double2* u, const double2* x,
+                                          int v0, double pe, double kmu, const Phys& ph,
+                                          const FaceGeo& fg, bool lo, bool hi, double& Ll,
+                                          double& Sl, double& Lu, double& Su) {
   double P[8], C[8], XP[8], XC[8];
+  const int plane = g.nx * g.ny;
 #pragma unroll
   for (int w = 0; w < 8; ++w) {
-    const size_t vw = (hi + (w & 1)) + (size_t)g.nx * ((hj + ((w >> 1) & 1)) + (size_t)g.ny * (hk + (w >> 2)));
-    const double2 a = u[vw], b = x[vw];
+    const int v = v0 + (w & 1) + g.nx * (w >> 1 & 1) + plane * (w >> 2);
+    const double2 a = u[v], b = x[v];
     P[w] = a.x;
     C[w] = a.y;
     XP[w] = ph.p_unit * b.x;
     XC[w] = b.y;
   }
-  face_tangent<AX, AY, AZ, 0>(P, C, XP, XC, pe, Ke, ph, fg, Yl, Ys);
-  face_tangent<AX, AY, AZ, 1>(P, C, XP, XC, pe, Ke, ph, fg, Yl, Ys);
-  face_tangent<AX, AY, AZ, 2>(P, C, XP, XC, pe, Ke, ph, fg, Yl, Ys);
+  double yl, ys;  // the vertical edge's face: out of the lower vertex, into the upper
+  face_tangent_flux<AX, AY, 0, 2>(P, C, XP, XC, pe, kmu, ph, fg, yl, ys);
+  Ll += yl;
+  Sl += ys;
+  Lu -= yl;
+  Su -= ys;
+  if (lo) {
+    face_tangent<AX, AY, 0, 0>(P, C, XP, XC, pe, kmu, ph, fg, Ll, Sl);
+    face_tangent<AX, AY, 0, 1>(P, C, XP, XC, pe, kmu, ph, fg, Ll, Sl);
+  }
+  if (hi) {
+    face_tangent<AX, AY, 1, 0>(P, C, XP, XC, pe, kmu, ph, fg, Lu, Su);
+    face_tangent<AX, AY, 1, 1>(P, C, XP, XC, pe, kmu, ph, fg, Lu, Su);
+  }
 }
 
-// MODE as k_spmv: 0 plain, 1 with the dot (d, y), 2 with (d, y) and (y, y)
+struct ColumnCtx {
+  int i, j, s;
+  bool ex0, ex1, ey0, ey1;  // hexahedra on the -x / +x / -y / +y side of the column exist
+  double inv_mu, inv_dt;
+};
+
+// layer L (between planes L and L + 1): the lower vertex's rows (Ll, Sl) and porosity
+// sum ml gain this layer's part; (Lu, Su) and mu_ are set to the upper vertex's part
+__device__ __forceinline__ void column_layer(const Geom& g, const ColumnCtx& cx, const double* phi,
+                                             const double* K, const double2* u, const double2* x,
+                                             int L, const Phys& ph, const FaceGeo& fg, bool lo,
+                                             bool hi, double& Ll, double& Sl, double& ml,
+                                             double& Lu, double& Su, double& mu_) {
+  const int rx = g.nx - 1;
+  const int e0 = rx * ((g.ny - 1) * L) + cx.i + rx * cx.j;      // hexahedron (i, j, L)
+  const int v0 = cx.i + g.nx * (cx.j + g.ny * L);               // vertex (i, j, L)
+  double msum = 0.0;
+  Lu = 0.0;
+  Su = 0.0;
+  if (cx.ex1 && cx.ey1) {
+    msum += phi[e0];
+    layer_hex<0, 0>(g, u, x, v0, phi[e0], K[e0] * cx.inv_mu, ph, fg, lo, hi, Ll, Sl, Lu, Su);
+  }
+  if (cx.ex0 && cx.ey1) {
+    const int e = e0 - 1;
+    msum += phi[e];
+    layer_hex<1, 0>(g, u, x, v0 - 1, phi[e], K[e] * cx.inv_mu, ph, fg, lo, hi, Ll, Sl, Lu, Su);
+  }
+  if (cx.ex1 && cx.ey0) {
+    const int e = e0 - rx;
+    msum += phi[e];
+    layer_hex<0, 1>(g, u, x, v0 - g.nx, phi[e], K[e] * cx.inv_mu, ph, fg, lo, hi, Ll, Sl, Lu,
+                    Su);
+  }
+  if (cx.ex0 && cx.ey0) {
+    const int e = e0 - rx - 1;
+    msum += phi[e];
+    layer_hex<1, 1>(g, u, x, v0 - g.nx - 1, phi[e], K[e] * cx.inv_mu, ph, fg, lo, hi, Ll, Sl,
+                    Lu, Su);
+  }
+  ml += msum;
+  mu_ = msum;
+}
+
+// the finished rows of vertex (i, j, k): storage derivatives, Dirichlet identity rows,
+// the product written and the dots accumulated
+template <int MODE>
+__device__ __forceinline__ void column_vertex(const Geom& g, const ColumnCtx& cx, const Phys& ph,
+                                              const double2* u, const double2* x, double2* y,
+                                              const double2* d, int k, double Yl, double Ys,
+                                              double msum, double (&acc)[2]) {
+  const int v = cx.i + g.nx * (cx.j + g.ny * k);
+  const double m = msum * (g.hx * g.hy * g.hz * 0.125);
+  const double2 xv = x[v];
+  const double c = u[v].y;
+  Yl += m * ph.drho * xv.y * cx.inv_dt;
+  Ys += m * (ph.rho0 + 2.0 * ph.drho * c) * xv.y * cx.inv_dt;
+  double cD;
+  const double r0 = is_pin(g, cx.i, cx.j, k) ? xv.x : ph.s_row * Yl;
+  const double r1 = is_cdir(g, cx.i, cx.j, k, cD) ? xv.y : ph.s_row * Ys;
+  y[v] = make_double2(r0, r1);
+  if (MODE != 0) {
+    const double2 dv = d[v];
+    acc[0] += dv.x * r0 + dv.y * r1;
+    if (MODE == 2) acc[1] += r0 * r0 + r1 * r1;
+  }
+}
+
+// MODE as k_spmv: 0 plain, 1 with the dot (d, y), 2 with (d, y) and (y, y).  Thread t of a
+// sample row takes column t % (nx ny) and the segment t / (nx ny) of nseg equal segments
+// of the column's nz vertices.
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_jx(Geom g, Phys ph0, const double* dts,
                                                const double* phi_all, const double* K_all,
                                                const double* u_all, const double* x_all,
                                                double* y_all, const double* d_all, double* part,
-                                               const int* mask, const int* list) {
+                                               const int* mask, const int* list, int nseg) {
   const int s = list ? list[blockIdx.y] : blockIdx.y;
   if (mask && !mask[s]) return;
   const Phys ph = sample_phys(ph0, dts, s);
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ncol = g.nx * g.ny;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
   double acc[2] = {0.0, 0.0};
-  if (v < g.N) {
-    const int i = v % g.nx, j = (v / g.nx) % g.ny, k = v / (g.nx * g.ny);
+  if (t < ncol * nseg) {
+    ColumnCtx cx;
+    cx.s = s;
+    const int q = t % ncol, seg = t / ncol;
+    cx.i = q % g.nx;
+    cx.j = q / g.nx;
+    cx.ex0 = cx.i > 0;
+    cx.ex1 = cx.i < g.nx - 1;
+    cx.ey0 = cx.j > 0;
+    cx.ey1 = cx.j < g.ny - 1;
+    cx.inv_mu = 1.0 / ph.mu;
+    cx.inv_dt = 1.0 / ph.dt;
+    const int k0 = (seg * g.nz) / nseg, k1 = ((seg + 1) * g.nz) / nseg;  // vertices [k0, k1)
     const size_t cells = (size_t)(g.nx - 1) * (g.ny - 1) * (g.nz - 1);
     const double* phi = phi_all + s * cells;
     const double* K = K_all + s * cells;
     const double2* u = reinterpret_cast<const double2*>(u_all) + (size_t)s * g.N;
     const double2* x = reinterpret_cast<const double2*>(x_all) + (size_t)s * g.N;
+    double2* y = reinterpret_cast<double2*>(y_all) + (size_t)s * g.N;
+    const double2* d = MODE ? reinterpret_cast<const double2*>(d_all) + (size_t)s * g.N : nullptr;
     const FaceGeo fg = face_geo(g);
-    double Yl = 0.0, Ys = 0.0, msum = 0.0;
-    hex_tangent<0, 0, 0>(g, i, j, k, phi, K, u, x, ph, fg, Yl, Ys, msum);
-    hex_tangent<1, 0, 0>(g, i, j, k, phi, K, u, x, ph, fg, Yl, Ys, msum);
-    hex_tangent<0, 1, 0>(g, i, j, k, phi, K, u, x, ph, fg, Yl, Ys, msum);
-    hex_tangent<1, 1, 0>(g, i, j, k, phi, K, u, x, ph, fg, Yl, Ys, msum);
-    hex_tangent<0, 0, 1>(g, i, j, k, phi, K, u, x, ph, fg, Yl, Ys, msum);
-    hex_tangent<1, 0, 1>(g, i, j, k, phi, K, u, x, ph, fg, Yl, Ys, msum);
-    hex_tangent<0, 1, 1>(g, i, j, k, phi, K, u, x, ph, fg, Yl, Ys, msum);
-    hex_tangent<1, 1, 1>(g, i, j, k, phi, K, u, x, ph, fg, Yl, Ys, msum);
-    const double m = msum * (g.hx * g.hy * g.hz * 0.125);
-    const double2 xv = x[v];
-    const double c = u[v].y;
-    Yl += m * ph.drho * xv.y / ph.dt;
-    Ys += m * (ph.rho0 + 2.0 * ph.drho * c) * xv.y / ph.dt;
-    double cD;
-    const double r0 = is_pin(g, i, j, k) ? xv.x : ph.s_row * Yl;
-    const double r1 = is_cdir(g, i, j, k, cD) ? xv.y : ph.s_row * Ys;
-    reinterpret_cast<double2*>(y_all)[(size_t)s * g.N + v] = make_double2(r0, r1);
-    if (MODE != 0) {
-      const double2 d = reinterpret_cast<const double2*>(d_all)[(size_t)s * g.N + v];
-      acc[0] = d.x * r0 + d.y * r1;
-      if (MODE == 2) acc[1] = r0 * r0 + r1 * r1;
+    const int L0 = k0 > 0 ? k0 - 1 : 0, L1 = k1 - 1 < g.nz - 2 ? k1 - 1 : g.nz - 2;
+    // rows of the next vertex up (the layers below it done) and its porosity sum
+    double Yl = 0.0, Ys = 0.0, ms = 0.0;
+#pragma unroll 1
+    for (int L = L0; L <= L1; ++L) {
+      const bool lo = L >= k0, hi = L + 1 < k1;
+      double Lu, Su, mu_;
+      column_layer(g, cx, phi, K, u, x, L, ph, fg, lo, hi, Yl, Ys, ms, Lu, Su, mu_);
+      if (lo) column_vertex<MODE>(g, cx, ph, u, x, y, d, L, Yl, Ys, ms, acc);
+      Yl = Lu;
+      Ys = Su;
+      ms = mu_;
     }
+    // the top vertex has no layer above it
+    if (k1 == g.nz) column_vertex<MODE>(g, cx, ph, u, x, y, d, g.nz - 1, Yl, Ys, ms, acc);
   }
   if (MODE == 1) {
     double a1[1] = {acc[0]};
@@ -414,20 +520,31 @@ __global__ __launch_bounds__(kBlock) void k_jx(Geom g, Phys ph0, const double* d
   }
 }
 
+// vertices per column segment: short enough that a few active samples still give the
+// device many waves, long enough that the plane loaded twice per segment stays a small
+// part of the work
+constexpr int kJxSegment = 8;
+
+int jx_blocks(const Geom& g) {
+  const int nseg = ceil_div(g.nz, kJxSegment);
+  return ceil_div(g.nx * g.ny * nseg, kBlock);
+}
+
 int launch_jx(const Geom& g, const Phys& ph, const double* dts, const double* phi, const double* K,
               const double* u, const double* x, double* y, const double* d, double* part, int mode,
               int S, const int* mask, const int* list, int rows, hipStream_t st) {
-  const int nb = ceil_div(g.N, kBlock);
+  const int nseg = ceil_div(g.nz, kJxSegment);
+  const int nb = jx_blocks(g);
   dim3 grid(nb, rows);
   if (mode == 0)
     hipLaunchKernelGGL(k_jx<0>, grid, dim3(kBlock), 0, st, g, ph, dts, phi, K, u, x, y, d, part,
-                       mask, list);
+                       mask, list, nseg);
   else if (mode == 1)
     hipLaunchKernelGGL(k_jx<1>, grid, dim3(kBlock), 0, st, g, ph, dts, phi, K, u, x, y, d, part,
-                       mask, list);
+                       mask, list, nseg);
   else
     hipLaunchKernelGGL(k_jx<2>, grid, dim3(kBlock), 0, st, g, ph, dts, phi, K, u, x, y, d, part,
-                       mask, list);
+                       mask, list, nseg);
   (void)S;
   return nb;
 }

@@ -250,12 +250,13 @@ void launch_bicg_p(size_t n, const double* r, const double* v, double* p, double
 void launch_bicg_alpha(const Geom& g, const JacOp& J, const double* ph, double* v,
                        const double* rh, double* part, KrylovScalars* ks, int S, const int* mask,
                        SampleList sl, hipStream_t st) {
-  const int nb = ceil_div(g.N, kBlock);
+  int nb = ceil_div(g.N, kBlock);
   if (J.A)
     hipLaunchKernelGGL(k_spmv<kDotOne>, dim3(nb, sl.rows(S)), dim3(kBlock), 0, st, g, J.A, ph, v,
                        rh, part, mask, sl.idx);
   else
-    launch_jx(g, J.ph, J.dts, J.phi, J.K, J.u, ph, v, rh, part, 1, S, mask, sl.idx, sl.rows(S), st);
+    nb = launch_jx(g, J.ph, J.dts, J.phi, J.K, J.u, ph, v, rh, part, 1, S, mask, sl.idx,
+                   sl.rows(S), st);
   finalize(kAlpha, nb, part, ks, const_cast<int*>(mask), nullptr, S, st);  // mask is `active`
 }
 
@@ -288,12 +289,13 @@ void launch_bicg_s(size_t n, const double* r, const double* v, double* s, double
 void launch_bicg_omega(const Geom& g, const JacOp& J, const double* sh, const double* s,
                        double* t, double* part, KrylovScalars* ks, int S, const int* mask,
                        SampleList sl, hipStream_t st) {
-  const int nb = ceil_div(g.N, kBlock);
+  int nb = ceil_div(g.N, kBlock);
   if (J.A)
     hipLaunchKernelGGL(k_spmv<kDotTS>, dim3(nb, sl.rows(S)), dim3(kBlock), 0, st, g, J.A, sh, t, s,
                        part, mask, sl.idx);
   else
-    launch_jx(g, J.ph, J.dts, J.phi, J.K, J.u, sh, t, s, part, 2, S, mask, sl.idx, sl.rows(S), st);
+    nb = launch_jx(g, J.ph, J.dts, J.phi, J.K, J.u, sh, t, s, part, 2, S, mask, sl.idx,
+                   sl.rows(S), st);
   finalize(kOmega, nb, part, ks, const_cast<int*>(mask), nullptr, S, st);
 }
 

@@ -359,24 +359,25 @@ def test_line_smoother_step_matches_oracle(precision, tol):
 def test_matrix_free_product_equals_the_assembled_jacobian():
     """The matrix-free J~ x (directional derivative of the defect at the state, upwind
     frozen) against the product with the assembled exact Jacobian, at random states and
-    directions, every field model: equal to rounding (1e-12 of the largest entry)."""
-    nx, ny, nz = 17, 13, 5
-    for model in (0, 1, 2, 3):
-        phys = synth.physics(model)
-        xi = _xi(model, 2, seed=21)
-        ys = []
-        for mf in (0, 1):
-            pb = _problem(phys, [(nx, ny, nz, 3, 2)], matrix_free=mf)
-            pb.set_parameters(xi)
-            for s in range(2):
-                pb.set_state(s, synth.random_state(nx, ny, nz, phys, seed=40 + s))
-            x = np.random.default_rng(7).standard_normal((2, nz, ny, nx, 2))
-            pb.apply_vcycle(0, DT, x)  # assembles at the states with this step length
-            ys.append(pb.apply_jacobian(0, x))
-            pb.destroy()
-        err = np.abs(ys[1] - ys[0]).max() / np.abs(ys[0]).max()
-        print(f"model {model}: matrix-free vs assembled {err:.2e}", flush=True)
-        assert err < 1e-12, (model, err)
+    directions, every field model: equal to rounding (1e-12 of the largest entry).  The
+    second shape has columns of 19 vertices, walked in 3 segments."""
+    for (nx, ny, nz, levels), models in (((17, 13, 5, 3), (0, 1, 2, 3)), ((11, 9, 19, 2), (1, 2))):
+        for model in models:
+            phys = synth.physics(model)
+            xi = _xi(model, 2, seed=21)
+            ys = []
+            for mf in (0, 1):
+                pb = _problem(phys, [(nx, ny, nz, levels, 2)], matrix_free=mf)
+                pb.set_parameters(xi)
+                for s in range(2):
+                    pb.set_state(s, synth.random_state(nx, ny, nz, phys, seed=40 + s))
+                x = np.random.default_rng(7).standard_normal((2, nz, ny, nx, 2))
+                pb.apply_vcycle(0, DT, x)  # assembles at the states with this step length
+                ys.append(pb.apply_jacobian(0, x))
+                pb.destroy()
+            err = np.abs(ys[1] - ys[0]).max() / np.abs(ys[0]).max()
+            print(f"{nx}x{ny}x{nz} model {model}: matrix-free vs assembled {err:.2e}", flush=True)
+            assert err < 1e-12, (model, err)
 
 
 @pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-6)])
