@@ -83,7 +83,7 @@ def measured_traffic(smoother, wl_name, prec):
 # ---------------------------------------------------------------------------------------
 LARGE_LAUNCH = 256 * 1024 * 1024   # working sets beyond the 256 MiB last-level cache
 ZERO_START_BLOCKS = (0, 6, 18, 24)  # line sweep from zero: blocks read per column colour
-JX_FLOPS = 2300.0    # k_jx: FP64 flops per interior vertex (FMA = 2) of the compiled loop
+JX_FLOPS = 1902.0    # k_jx: FP64 operations per interior vertex of the compiled loop (FMA = 2)
 JX_BYTES = 80.0      # k_jx: u, x, y, d (16 B each) + phi and K (8 B each) per vertex
 
 
@@ -631,7 +631,8 @@ def main():
                     help="summarise the CSV of a rocprofv3 --kernel-trace --marker-trace run of "
                          "this script (with --mark-timed-region) and exit; no GPU is used")
     ap.add_argument("--leg", type=int, default=-1,
-                    help="with --summarise-trace: which timed-steps range (0: FP64 leg, 1: mixed)")
+                    help="with --summarise-trace: which timed-steps range (in the default "
+                         "two-leg run 0: the FP64 leg, 1: the mixed leg; -1: the last)")
     ap.add_argument("--summarise-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     default=None,
                     help="HBM traffic of the smoother from rocprofv3 --pmc FETCH_SIZE and "
@@ -697,7 +698,7 @@ def main():
         # the FP64 leg: the reference the mixed-precision states are compared with
         log(f"workload {wl.name}: groups {groups}, FP64 leg")
         pb, tuning64 = make_problem(args, wl, phys, groups, "f64")
-        leg64 = run_steps(args, wl, pb, "f64")
+        leg64 = run_steps(args, wl, pb, "f64", region)
         # the reference of the precision comparison: one more FP64 step from the states
         # reached, with every sample's sub-step history cleared (edf_set_state), so that the
         # mixed leg can take the same step from the same states

@@ -268,6 +268,16 @@ edf_status edf_solve(edf_problem* pb, double dt, int32_t n_steps, int32_t checkp
 edf_status edf_moments(edf_problem* pb, int32_t cx, int32_t cy, int32_t cz, double threshold,
                        const double* weights, double* mean, double* var, double* exceed);
 
+/* The statistics of edf_moments over the samples of one resolution group at that group's
+ * own resolution (every vertex of its grid, no injection): the per-group estimates of
+ * eqs. pdestat and numer_var, e.g. the 129^3 group's mean and variance at 129^3 in a
+ * problem that also holds coarser groups.  weights: host [S of the group] (in the group's
+ * sample order) or NULL for equal weights; normalised and masked for failed samples as in
+ * edf_moments.  mean, var, exceed: host arrays [nz][ny][nx] of the group's grid.
+ * EDF_ERR_ARG for a group index out of range.  Synchronises. */
+edf_status edf_group_moments(edf_problem* pb, int32_t group, double threshold,
+                             const double* weights, double* mean, double* var, double* exceed);
+
 /* edf_moments for callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): the same statistics,
  * bitwise, with no hipMalloc, hipFree or other allocating call.  Its working memory

@@ -82,6 +82,7 @@ _SIGS = {
     "edf_solve": [_P, C.c_double, C.c_int32, C.c_int32, C.POINTER(StepStats)],
     "edf_moments": [_P, C.c_int32, C.c_int32, C.c_int32, C.c_double, _D, _D, _D, _D],
     "edf_moments_noalloc": [_P, C.c_int32, C.c_int32, C.c_int32, C.c_double, _D, _D, _D, _D],
+    "edf_group_moments": [_P, C.c_int32, C.c_double, _D, _D, _D, _D],
     "edf_residual": [_P, C.c_int32, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_int32],
     "edf_get_jacobian": [_P, C.c_int32, _D, C.c_double, C.c_int32, _D],
     "edf_apply_vcycle": [_P, C.c_int32, C.c_double, _D, _D],
@@ -244,6 +245,22 @@ class Problem:
         self._check(fn(self._h, cx, cy, cz, float(threshold), _dptr(w) if w is not None else None,
                        _dptr(mean), _dptr(var), _dptr(exc)))
         shape = (cz, cy, cx)
+        return mean.reshape(shape), var.reshape(shape), exc.reshape(shape)
+
+    def group_moments(self, group: int, threshold=0.5, weights=None):
+        """Mean, variance and P(c > threshold) of one group's samples on the group's own
+        grid (edf_group_moments); weights in the group's sample order."""
+        nx, ny, nz = self.groups[group][:3]
+        n = nx * ny * nz
+        mean, var, exc = np.empty(n), np.empty(n), np.empty(n)
+        w = None
+        if weights is not None:
+            w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
+            assert w.size == self.groups[group][4]
+        self._check(self._lib.edf_group_moments(self._h, int(group), float(threshold),
+                                                _dptr(w) if w is not None else None,
+                                                _dptr(mean), _dptr(var), _dptr(exc)))
+        shape = (nz, ny, nx)
         return mean.reshape(shape), var.reshape(shape), exc.reshape(shape)
 
     def gpc_project(self, group: int, common, degree: int, weights, truncation: int = 0,

@@ -2036,25 +2036,28 @@ edf_status edf_gpc_exceed(edf_problem* pb, int32_t n_points, const double* theta
   return EDF_OK;
 }
 
-edf_status edf_moments(edf_problem* pb, int32_t cx, int32_t cy, int32_t cz, double threshold,
-                       const double* weights, double* mean, double* var, double* exceed) {
-  if (!pb || !mean || !var || !exceed) return EDF_ERR_ARG;
-  if (cx < 2 || cy < 2 || cz < 2) return fail(pb, EDF_ERR_ARG, "common grid too small");
-  for (Group& G : pb->groups) {
-    const Geom& g = G.lv[0].g;
-    if ((g.nx - 1) % (cx - 1) || (g.ny - 1) % (cy - 1) || (g.nz - 1) % (cz - 1))
-      return fail(pb, EDF_ERR_ARG, "common grid not nested in every group");
-  }
+namespace {
+// the statistics of edf_moments over the samples of every group (only < 0) or of group
+// `only` alone; weights are indexed like those samples
+edf_status moments_over(edf_problem* pb, int only, int32_t cx, int32_t cy, int32_t cz,
+                        double threshold, const double* weights, double* mean, double* var,
+                        double* exceed) {
   const size_t Nc = (size_t)cx * cy * cz;
-  const int S = pb->S_total;
+  int S = 0;
+  for (int gi = 0; gi < (int)pb->groups.size(); ++gi)
+    if (only < 0 || gi == only) S += pb->groups[gi].S;
   std::vector<double> w(S);
   double sum = 0.0;
-  for (Group& G : pb->groups)
-    for (int s = 0; s < G.S; ++s) {
-      const double ws = weights ? weights[G.s0 + s] : 1.0 / S;
-      w[G.s0 + s] = G.fail_status[s] == EDF_SAMPLE_OK ? ws : 0.0;
-      sum += w[G.s0 + s];
+  int o = 0;
+  for (int gi = 0; gi < (int)pb->groups.size(); ++gi) {
+    if (only >= 0 && gi != only) continue;
+    const Group& G = pb->groups[gi];
+    for (int s = 0; s < G.S; ++s, ++o) {
+      const double ws = weights ? weights[o] : 1.0 / S;
+      w[o] = G.fail_status[s] == EDF_SAMPLE_OK ? ws : 0.0;
+      sum += w[o];
     }
+  }
   if (!(sum > 0)) return fail(pb, EDF_ERR_NO_CONVERGENCE, "no valid sample");
   for (double& x : w) x /= sum;
   const size_t need = Nc * (S + 3) + S;
@@ -2068,8 +2071,13 @@ edf_status edf_moments(edf_problem* pb, int32_t cx, int32_t cy, int32_t cz, doub
   double* dw = f + Nc * S;
   double* out = dw + S;
   EDF_TRY(hipMemcpyAsync(dw, w.data(), S * sizeof(double), hipMemcpyHostToDevice, pb->st));
-  for (Group& G : pb->groups)
-    launch_gather_common(G.lv[0].g, cx, cy, cz, G.u, f + (size_t)G.s0 * Nc, G.S, pb->st);
+  o = 0;
+  for (int gi = 0; gi < (int)pb->groups.size(); ++gi) {
+    if (only >= 0 && gi != only) continue;
+    const Group& G = pb->groups[gi];
+    launch_gather_common(G.lv[0].g, cx, cy, cz, G.u, f + (size_t)o * Nc, G.S, pb->st);
+    o += G.S;
+  }
   launch_moments((int)Nc, S, f, dw, threshold, out, out + Nc, out + 2 * Nc, pb->st);
   EDF_CHECK_LAUNCH();
   EDF_TRY(hipMemcpyAsync(mean, out, Nc * sizeof(double), hipMemcpyDeviceToHost, pb->st));
@@ -2077,6 +2085,28 @@ edf_status edf_moments(edf_problem* pb, int32_t cx, int32_t cy, int32_t cz, doub
   EDF_TRY(hipMemcpyAsync(exceed, out + 2 * Nc, Nc * sizeof(double), hipMemcpyDeviceToHost, pb->st));
   EDF_TRY(hipStreamSynchronize(pb->st));
   return EDF_OK;
+}
+}  // namespace
+
+edf_status edf_moments(edf_problem* pb, int32_t cx, int32_t cy, int32_t cz, double threshold,
+                       const double* weights, double* mean, double* var, double* exceed) {
+  if (!pb || !mean || !var || !exceed) return EDF_ERR_ARG;
+  if (cx < 2 || cy < 2 || cz < 2) return fail(pb, EDF_ERR_ARG, "common grid too small");
+  for (Group& G : pb->groups) {
+    const Geom& g = G.lv[0].g;
+    if ((g.nx - 1) % (cx - 1) || (g.ny - 1) % (cy - 1) || (g.nz - 1) % (cz - 1))
+      return fail(pb, EDF_ERR_ARG, "common grid not nested in every group");
+  }
+  return moments_over(pb, -1, cx, cy, cz, threshold, weights, mean, var, exceed);
+}
+
+edf_status edf_group_moments(edf_problem* pb, int32_t group, double threshold,
+                             const double* weights, double* mean, double* var, double* exceed) {
+  if (!pb || !mean || !var || !exceed) return EDF_ERR_ARG;
+  if (group < 0 || group >= (int)pb->groups.size())
+    return fail(pb, EDF_ERR_ARG, "group index out of range");
+  const Geom& g = pb->groups[group].lv[0].g;
+  return moments_over(pb, group, g.nx, g.ny, g.nz, threshold, weights, mean, var, exceed);
 }
 
 edf_status edf_moments_noalloc(edf_problem* pb, int32_t cx, int32_t cy, int32_t cz,

@@ -196,6 +196,24 @@ __device__ __forceinline__ V load_nbr(const V* x, const Geom& g, const NbrMap& m
                                      u * (unsigned)sizeof(V));
 }
 
+// XCD-aware tile order.  The workgroups of a launch go to the device's 8 XCDs in turn
+// (linear workgroup id bx + by gx modulo 8), and each XCD has its own L2.  Workgroup bx of
+// grid row by takes a tile such that each XCD works through one contiguous range of the
+// row's gx tiles (a bijection of [0, gx)): the tiles of neighbouring grid rows, which
+// gather the same neighbour values, then share one L2 instead of fetching those values
+// into several.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile(int bx, int by, int gx) {
+  const int c0 = (int)(((long long)by * gx) % kXcds);  // the XCD of the row's first workgroup
+  const int xcd = (c0 + bx) % kXcds;
+  int start = 0;  // tiles of the XCDs before this one
+  for (int x = 0; x < xcd; ++x) {
+    const int f = (x - c0 + kXcds) % kXcds;  // first workgroup of the row on XCD x
+    start += f < gx ? (gx - 1 - f) / kXcds + 1 : 0;
+  }
+  return start + (bx - (xcd - c0 + kXcds) % kXcds) / kXcds;
+}
+
 // salt Dirichlet vertex (closed top patch: c = 1; bottom: c = 0)
 __device__ __forceinline__ bool is_cdir(const Geom& g, int i, int j, int k, double& value) {
   if (k == g.nz - 1) { value = 0.0; return true; }

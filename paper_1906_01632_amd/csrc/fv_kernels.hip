@@ -299,6 +299,38 @@ void launch_defect(const Geom& g, const Phys& ph, const double* dts, const doubl
 // linearised liquid and salt flux (yl, ys) out of the start vertex of the edge of the
 // face of direction D through corner (AX, AY, AZ) of a hexahedron with corner values
 // P, C (state) and XP, XC (direction, pressure in physical units); kmu = K / mu
+// the linearised fluxes of a face of direction D from the values at its integration
+// point: c, and the D-derivatives of p and c (not yet divided by h_D), of the state and of
+// the direction (t*); c and the direction's c at the edge's start (cA, xA) and end (cB, xB)
+template <int D>
+__device__ __forceinline__ void face_flux(double cf, double dp, double dc, double tcf, double tdp,
+                                          double tdc, double cA, double cB, double xA, double xB,
+                                          double phi, double kmu, const Phys& ph,
+                                          const FaceGeo& fg, double& yl, double& ys) {
+  const double ih = fg.ih[D];
+  dp *= ih;
+  dc *= ih;
+  tdp *= ih;
+  tdc *= ih;
+  const double area = fg.area[D];
+  const double gD = D == 2 ? ph.g : 0.0;
+  const double rf = ph.rho0 + ph.drho * cf;
+  const double ka = kmu * area;
+  const double Q = -ka * (dp - rf * gD);
+  const double tQ = -ka * (tdp - ph.drho * tcf * gD);
+  const bool up_start = Q >= 0.0;
+  const double cup = up_start ? cA : cB;
+  const double tcup = up_start ? xA : xB;
+  const double ru = ph.rho0 + ph.drho * cup;
+  const double diff = phi * ph.Dm * area;
+  yl = ph.drho * tcf * Q + rf * tQ;
+  ys = (ph.rho0 + 2.0 * ph.drho * cup) * tcup * Q + ru * cup * tQ -
+       (ph.drho * tcf * dc + rf * tdc) * diff;
+}
+
+// linearised liquid and salt flux (yl, ys) out of the start vertex of the edge of the
+// face of direction D through corner (AX, AY, AZ) of a hexahedron with corner values
+// P, C (state) and XP, XC (direction, pressure in physical units); kmu = K / mu
 template <int AX, int AY, int AZ, int D>
 __device__ __forceinline__ void face_tangent_flux(const double* P, const double* C,
                                                   const double* XP, const double* XC, double phi,
@@ -317,42 +349,62 @@ __device__ __forceinline__ void face_tangent_flux(const double* P, const double*
     tdp += F::dN(w) * XP[w];
     tdc += F::dN(w) * XC[w];
   }
-  const double ih = fg.ih[D];
-  dp *= ih;
-  dc *= ih;
-  tdp *= ih;
-  tdc *= ih;
-  const double area = fg.area[D];
-  const double gD = D == 2 ? ph.g : 0.0;
-  const double rf = ph.rho0 + ph.drho * cf;
-  const double ka = kmu * area;
-  const double Q = -ka * (dp - rf * gD);
-  const double tQ = -ka * (tdp - ph.drho * tcf * gD);
-  const bool up_start = Q >= 0.0;
-  const double cup = up_start ? C[WA] : C[WB];
-  const double tcup = up_start ? XC[WA] : XC[WB];
-  const double ru = ph.rho0 + ph.drho * cup;
-  const double diff = phi * ph.Dm * area;
-  yl = ph.drho * tcf * Q + rf * tQ;
-  ys = (ph.rho0 + 2.0 * ph.drho * cup) * tcup * Q + ru * cup * tQ -
-       (ph.drho * tcf * dc + rf * tdc) * diff;
+  face_flux<D>(cf, dp, dc, tcf, tdp, tdc, C[WA], C[WB], XC[WA], XC[WB], phi, kmu, ph, fg, yl, ys);
 }
 
-// the same flux added to the rows of the vertex at corner (AX, AY, AZ): out of it when it
-// is the edge's start, into it otherwise
-template <int AX, int AY, int AZ, int D>
-__device__ __forceinline__ void face_tangent(const double* P, const double* C, const double* XP,
-                                             const double* XC, double phi, double kmu,
-                                             const Phys& ph, const FaceGeo& fg, double& Yl,
-                                             double& Ys) {
-  double yl, ys;
-  face_tangent_flux<AX, AY, AZ, D>(P, C, XP, XC, phi, kmu, ph, fg, yl, ys);
-  if (FaceT<AX, AY, AZ, D>::VD == 0) {
-    Yl += yl;
-    Ys += ys;
-  } else {
-    Yl -= yl;
-    Ys -= ys;
+// corner index of a hexahedron's corner a along direction D (0: x, 1: y), b across it
+// horizontally, z vertically
+template <int D>
+__host__ __device__ constexpr int hcorner(int a, int b, int z) {
+  return D == 0 ? a + 2 * b + 4 * z : b + 2 * a + 4 * z;
+}
+
+// The two faces of direction D (0: x, 1: y) through the vertical edge of a hexahedron at
+// its corner (AX, AY), at the lower (z = 0) and the upper (z = 1) plane.  Their
+// integration points share the position across D, so the trilinear values are formed in
+// stages: sums and differences along D of the 4 edges of direction D, then the weights
+// 3/4 (the near edge) and 1/4 across D, then 3/4 and 1/4 in z for each face.  The faces'
+// fluxes go out of (into) the column's vertex when it is the edge's start (end), to
+// (Ll, Sl) for the lower face when lo and to (Lu, Su) for the upper one when hi.
+template <int D, int AX, int AY>
+__device__ __forceinline__ void horizontal_faces(const double* P, const double* C,
+                                                 const double* XP, const double* XC, double pe,
+                                                 double kmu, const Phys& ph, const FaceGeo& fg,
+                                                 bool lo, bool hi, double& Ll, double& Sl,
+                                                 double& Lu, double& Su) {
+  constexpr int at = D == 0 ? AY : AX;  // the column's position across D
+  constexpr int VD = D == 0 ? AX : AY;  // 0: the column's vertex is the edges' start
+  double Tc[2], Tdc[2], Tdp[2], Ttc[2], Ttdc[2], Ttdp[2];
+#pragma unroll
+  for (int z = 0; z < 2; ++z) {
+    const int n1 = hcorner<D>(1, at, z), n0 = hcorner<D>(0, at, z);
+    const int f1 = hcorner<D>(1, 1 - at, z), f0 = hcorner<D>(0, 1 - at, z);
+    Tc[z] = 0.375 * (C[n1] + C[n0]) + 0.125 * (C[f1] + C[f0]);
+    Tdc[z] = 0.75 * (C[n1] - C[n0]) + 0.25 * (C[f1] - C[f0]);
+    Tdp[z] = 0.75 * (P[n1] - P[n0]) + 0.25 * (P[f1] - P[f0]);
+    Ttc[z] = 0.375 * (XC[n1] + XC[n0]) + 0.125 * (XC[f1] + XC[f0]);
+    Ttdc[z] = 0.75 * (XC[n1] - XC[n0]) + 0.25 * (XC[f1] - XC[f0]);
+    Ttdp[z] = 0.75 * (XP[n1] - XP[n0]) + 0.25 * (XP[f1] - XP[f0]);
+  }
+#pragma unroll
+  for (int sz = 0; sz < 2; ++sz) {
+    if (!(sz ? hi : lo)) continue;
+    const int o = 1 - sz;
+    const int wa = hcorner<D>(0, at, sz), wb = hcorner<D>(1, at, sz);
+    double yl, ys;
+    face_flux<D>(0.75 * Tc[sz] + 0.25 * Tc[o], 0.75 * Tdp[sz] + 0.25 * Tdp[o],
+                 0.75 * Tdc[sz] + 0.25 * Tdc[o], 0.75 * Ttc[sz] + 0.25 * Ttc[o],
+                 0.75 * Ttdp[sz] + 0.25 * Ttdp[o], 0.75 * Ttdc[sz] + 0.25 * Ttdc[o], C[wa],
+                 C[wb], XC[wa], XC[wb], pe, kmu, ph, fg, yl, ys);
+    double& L = sz ? Lu : Ll;
+    double& S = sz ? Su : Sl;
+    if (VD == 0) {
+      L += yl;
+      S += ys;
+    } else {
+      L -= yl;
+      S -= ys;
+    }
   }
 }
 
@@ -382,14 +434,8 @@ __device__ __forceinline__ void layer_hex(const Geom& g, const double2* u, const
   Sl += ys;
   Lu -= yl;
   Su -= ys;
-  if (lo) {
-    face_tangent<AX, AY, 0, 0>(P, C, XP, XC, pe, kmu, ph, fg, Ll, Sl);
-    face_tangent<AX, AY, 0, 1>(P, C, XP, XC, pe, kmu, ph, fg, Ll, Sl);
-  }
-  if (hi) {
-    face_tangent<AX, AY, 1, 0>(P, C, XP, XC, pe, kmu, ph, fg, Lu, Su);
-    face_tangent<AX, AY, 1, 1>(P, C, XP, XC, pe, kmu, ph, fg, Lu, Su);
-  }
+  horizontal_faces<0, AX, AY>(P, C, XP, XC, pe, kmu, ph, fg, lo, hi, Ll, Sl, Lu, Su);
+  horizontal_faces<1, AX, AY>(P, C, XP, XC, pe, kmu, ph, fg, lo, hi, Ll, Sl, Lu, Su);
 }
 
 struct ColumnCtx {

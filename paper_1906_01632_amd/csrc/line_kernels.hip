@@ -179,7 +179,7 @@ __global__ __launch_bounds__(kLineThreads) void k_line_sweep(Geom g, int cc, con
   const int s = list ? list[blockIdx.y] : blockIdx.y;
   if (mask && !mask[s]) return;
   const int mx = g.mx[cc], ncol = mx * g.my[cc];
-  const int q0 = blockIdx.x * kLineCols;
+  const int q0 = xcd_tile(blockIdx.x, blockIdx.y, gridDim.x) * kLineCols;
   const int nz = g.nz;
   const size_t Np = g.off[8];
   const T* A = A_all + (size_t)s * kPlanes * Np;
@@ -370,7 +370,7 @@ __global__ __launch_bounds__(kBlock) void k_line_residual_zs(Geom g, const T* A_
   using T2 = typename V2<T>::type;
   const int s = list ? list[blockIdx.y] : blockIdx.y;
   if (mask && !mask[s]) return;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = xcd_tile(blockIdx.x, blockIdx.y, gridDim.x) * kBlock + threadIdx.x;
   if (t >= g.off[8]) return;
   int col, i, j, k;
   if (!colour_decode_wave(g, t, col, i, j, k)) return;

@@ -231,7 +231,8 @@ def test_runs_are_deterministic():
 
 def test_mixed_resolution_groups_and_moments():
     """Two resolution groups in one problem; pooled moments on the common grid equal
-    the oracle's statistics of the same injected fields."""
+    the oracle's statistics of the same injected fields, and each group's own moments at
+    its own resolution those of its fields."""
     phys = synth.physics(2)
     xi = synth.lattice_points(16, 4, seed=2)[:6]
     pb = _problem(phys, [(9, 9, 3, 2, 4), (17, 17, 5, 3, 2)], newton_rtol=1e-10, lin_rtol=1e-8)
@@ -249,6 +250,17 @@ def test_mixed_resolution_groups_and_moments():
     mean_w, var_w, _ = pb.moments((9, 9, 3), weights=w)
     m, v, _ = stats.moments(np.array(fields), weights=w / w.sum())
     assert np.abs(mean_w - m).max() < 1e-14 and np.abs(var_w - v).max() < 1e-14
+    # each group's statistics at its own resolution (edf_group_moments)
+    for gi, members, shape in ((0, range(4), (9, 9, 3)), (1, range(4, 6), (17, 17, 5))):
+        own = np.array([pb.get_state(s)[..., 1] for s in members])
+        for wg in (None, np.arange(1, len(own) + 1, dtype=float)):
+            mean_g, var_g, exc_g = pb.group_moments(gi, threshold=0.5, weights=wg)
+            assert mean_g.shape == shape[::-1]
+            m, v, e = stats.moments(own, weights=None if wg is None else wg / wg.sum(),
+                                    threshold=0.5)
+            assert np.abs(mean_g - m).max() < 1e-14
+            assert np.abs(var_g - v).max() < 1e-14
+            assert np.abs(exc_g - e).max() < 1e-14
     # each group stepped exactly like the oracle
     for s, (nx, ny, nz) in [(0, (9, 9, 3)), (5, (17, 17, 5))]:
         box = elder.Box(nx, ny, nz, phys)
