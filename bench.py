@@ -431,7 +431,8 @@ def make_problem(args, wl, phys, groups, prec, log_tuning=True):
                 precision={"f64": PREC_F64, "mixed": PREC_MIXED, "mixed16": PREC_MIXED_F16}[prec],
                 check_every=1, forcing=args.forcing, concurrent_groups=int(args.concurrent_groups),
                 graph_vcycle=int(args.graph), substep_memory=int(args.substep_memory),
-                smoother=int(args.smoother), matrix_free=int(args.matrix_free))
+                smoother=int(args.smoother), matrix_free=int(args.matrix_free),
+                predictor=int(args.predictor) if not args.adjoint else 0)
     t = time.perf_counter()
     pb = Problem(phys, groups, opts)
     pb.set_parameters(wl.xi)
@@ -502,6 +503,7 @@ def run_steps(args, wl, pb, prec, region=(None, None)):
         "split_sample_steps": sum(t["substeps"] > 1 for t in ran),
         "substeps_per_sample_step": sum(t["substeps"] for t in ran) / max(len(ran), 1),
         "restarted_attempts": sum(t["retries"] for t in ran),
+        "extrapolated_starts": sum(t["predicted"] for t in ran),
         "failed_samples": sum(t["status"] != 0 for t in last),
         "max_salt_balance_err": max((t["salt_balance_err"] for t in ran), default=0.0),
         "max_liquid_balance_err": max((t["liquid_balance_err"] for t in ran), default=0.0),
@@ -603,6 +605,9 @@ def main():
     ap.add_argument("--substep-memory", type=int, default=1, choices=[0, 1],
                     help="1: a sample starts a step with the sub-step count that worked in its "
                          "previous step")
+    ap.add_argument("--predictor", type=int, default=1, choices=[0, 1],
+                    help="1: Newton starts a step from the extrapolation 2 u^n - u^{n-1} where "
+                         "its defect is smaller (same stopping test)")
     ap.add_argument("--concurrent-groups", action="store_true",
                     help="advance the grid groups at the same time (one host thread and stream "
                          "each); more throughput, but overlapping kernels lengthen the per-launch "
@@ -742,6 +747,7 @@ def main():
                    "smoother": ["point-block-gs-8-colour", "z-line-block-gs-4-colour"][args.smoother],
                    "matrix_free_jacobian": bool(args.matrix_free),
                    "substep_memory": bool(args.substep_memory),
+                   "newton_predictor": bool(args.predictor),
                    "fused_bottom_from_level": tuning,
                    "concurrent_groups": bool(args.concurrent_groups),
                    "graph_vcycle": bool(args.graph)},

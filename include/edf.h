@@ -149,7 +149,16 @@ typedef struct {
                            /* the state, the coefficients and x (the same operator, */
                            /* no exact finest-level stencil stored; the adjoint's   */
                            /* transposed products stay assembled)                   */
-  int32_t reserved[1];     /* must be zero                                         */
+  int32_t predictor;       /* Newton's starting point of a step: 0 the state at the */
+                           /* start of the step; 1 also the linear extrapolation    */
+                           /* 2 u^n - u^{n-1} of the sample's last two states when  */
+                           /* its previous step was one implicit-Euler step of the  */
+                           /* same length, taken when its scaled defect is the      */
+                           /* smaller.  The stopping test stays relative to the     */
+                           /* defect at the start of the step, so the step reaches  */
+                           /* the same tolerance with fewer Newton iterations.      */
+                           /* Not used while edf_solve records a trajectory (the    */
+                           /* adjoint recomputes those steps from checkpoints)      */
 } edf_solver_opts;
 
 /* Per-sample result of a step.  Counters named *_total run over every step since the
@@ -170,7 +179,8 @@ typedef struct {
   int32_t substeps_total; /* implicit-Euler sub-steps completed                     */
   int32_t retries_total;  /* failed and restarted attempts                          */
   int32_t failed_step;    /* steps_total + 1 at the step that failed; 0: none       */
-  int32_t reserved;
+  int32_t predicted;      /* 1: Newton started this step from the extrapolation     */
+                          /* 2 u^n - u^{n-1} (opts.predictor)                       */
   double defect0;       /* ||F~|| at the start of the step (full step length)      */
   double defect;        /* ||F~|| at the end of the last sub-step                  */
   /* Global conservation over this step, computed in FP64 on the device from the     */

@@ -84,6 +84,10 @@ struct Group {
   int *nmask = nullptr, *active = nullptr, *lsmask = nullptr;
   double *norms = nullptr, *lam = nullptr, *dts = nullptr, *crange = nullptr, *eta = nullptr;
   double* u0 = nullptr;  // state at the start of the current step (restart point)
+  // opts.predictor: the state at the start of the previous step, and that step's length
+  // per sample when it was one implicit-Euler step (0: no usable history)
+  double* u_prev = nullptr;
+  std::vector<double> pred_dt;
   double* Minv = nullptr;
   int *piv = nullptr, *gj_status = nullptr;
   int n_coarse = 0;
@@ -156,6 +160,7 @@ struct edf_problem {
   // the trajectory of the last edf_solve with checkpoint_every > 0, valid until a step,
   // a new state or new parameters change it
   bool traj_valid = false;
+  bool recording = false;  // edf_solve is recording a trajectory (no extrapolated starts)
   int traj_k = 0, traj_n = 0;
   double traj_dt = 0.0;
   // staging for edf_set_parameters: the new parameters are checked before they replace
@@ -282,6 +287,7 @@ void reset_history(Group& G) {
   G.clean.assign(G.S, 0);
   G.wait.assign(G.S, kFirstWait);
   G.probing.assign(G.S, 0);
+  G.pred_dt.assign(G.S, 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -356,6 +362,7 @@ edf_status alloc_group(edf_problem* pb, Group& G) {
   if ((s = dalloc(pb, &G.eta, (size_t)S))) return s;
   if ((s = dalloc(pb, &G.crange, 2 * (size_t)S))) return s;
   if ((s = dalloc(pb, &G.u0, S * n))) return s;
+  if (pb->opts.predictor && (s = dalloc(pb, &G.u_prev, S * n))) return s;
   {
     char* q;
     if ((s = dalloc(pb, &q, sizeof(FusedLevels<double>)))) return s;
@@ -984,7 +991,8 @@ constexpr double kSlowDrop = 1e-2;      // ... without this reduction of ||F~||
 
 edf_status newton_solve(edf_problem* pb, Group& G, const std::vector<int>& run,
                         const std::vector<int>& can_retry, std::vector<int>& ok,
-                        std::vector<int>& why, bool first_attempt) {
+                        std::vector<int>& why, bool first_attempt,
+                        const std::vector<int>* extrapolate = nullptr) {
   hipStream_t st = G.st;
   const int S = G.S;
   const edf_solver_opts& o = pb->opts;
@@ -997,13 +1005,38 @@ edf_status newton_solve(edf_problem* pb, Group& G, const std::vector<int>& run,
   if ((e = read_norms(pb, G, G.F, G.nmask, r))) return e;
   r0 = r;
   std::vector<int> nm(run), ls(S), acc(S);
+  // extrapolated start (opts.predictor) for the samples flagged in `extrapolate`: Newton
+  // starts from 2 u^n - u^{n-1} where its scaled defect is below that of u^n; r0 stays the
+  // defect at u^n, so the stopping test asks for the same accuracy
+  if (extrapolate) {
+    bool any_x = false;
+    for (int s = 0; s < S; ++s) {
+      ls[s] = run[s] && (*extrapolate)[s] && std::isfinite(r[s]);
+      any_x |= ls[s] != 0;
+    }
+    if (any_x) {
+      if ((e = upload_ints(pb, G, G.lsmask, ls))) return e;
+      launch_extrapolate(G.n, G.u, G.u_prev, G.ut, S, G.lsmask, st);
+      launch_defect(L0.g, L0.ph, G.dts, L0.phi, L0.K, G.ut, G.u_old, G.Ft, S, G.lsmask, st);
+      std::vector<double> rx;
+      if ((e = read_norms(pb, G, G.Ft, G.lsmask, rx))) return e;
+      for (int s = 0; s < S; ++s) {
+        acc[s] = ls[s] && rx[s] < r[s];
+        if (acc[s]) r[s] = rx[s];
+        if (first_attempt && run[s]) G.stats[s].predicted = acc[s];
+      }
+      if ((e = upload_ints(pb, G, G.lsmask, acc))) return e;
+      launch_masked_copy(G.n, G.ut, G.u, S, G.lsmask, st);
+      launch_masked_copy(G.n, G.Ft, G.F, S, G.lsmask, st);
+    }
+  }
   std::vector<double> lam(S), eta(S, o.lin_rtol), r_prev(S, 0.0);
   ok.assign(S, 0);
   why.assign(S, EDF_SAMPLE_OK);
   for (int s = 0; s < S; ++s) {
     if (!run[s]) continue;
     if (first_attempt) G.stats[s].defect0 = r0[s];
-    G.stats[s].defect = r0[s];
+    G.stats[s].defect = r[s];
     if (!std::isfinite(r0[s])) {
       why[s] = EDF_SAMPLE_NONFINITE;
       nm[s] = 0;
@@ -1159,6 +1192,7 @@ edf_status macro_step(edf_problem* pb, Group& G, double DT) {
     t.status = G.fail_status[s];
     t.newton_its = t.lin_its = t.ls_halvings = t.retries = 0;
     t.substeps = 0;
+    t.predicted = 0;
     t.defect0 = t.defect = 0.0;
     t.salt_balance_err = t.liquid_balance_err = 0.0;
     if (G.fail_status[s] != EDF_SAMPLE_OK) continue;  // failed in an earlier step
@@ -1169,6 +1203,12 @@ edf_status macro_step(edf_problem* pb, Group& G, double DT) {
   launch_fill<double>(G.bal, 8, S, nullptr, 0.0, st);
   const Level& L0 = G.lv[0];
   bool first = true;
+  // extrapolated Newton starts (opts.predictor): the samples whose previous step was one
+  // implicit-Euler step of this length and that try the full length now
+  std::vector<int> extrap(S, 0);
+  const bool predict = G.u_prev && !pb->recording;
+  if (predict)
+    for (int s = 0; s < S; ++s) extrap[s] = running[s] && h[s] == 0 && G.pred_dt[s] == DT;
   for (;;) {
     bool any = false;
     for (int s = 0; s < S; ++s) {
@@ -1180,7 +1220,9 @@ edf_status macro_step(edf_problem* pb, Group& G, double DT) {
     if ((e = upload_ints(pb, G, G.nmask, running))) return e;
     launch_masked_copy(G.n, G.u, G.u_old, S, G.nmask, st);
     for (int s = 0; s < S; ++s) can_retry[s] = h[s] < pb->opts.dt_max_halvings;
-    if ((e = newton_solve(pb, G, running, can_retry, ok, why, first))) return e;
+    if ((e = newton_solve(pb, G, running, can_retry, ok, why, first,
+                          first && predict ? &extrap : nullptr)))
+      return e;
     first = false;
     // mass balance of the sub-steps that converged (u: their end, u_old: their start)
     bool any_ok = false;
@@ -1240,6 +1282,17 @@ edf_status macro_step(edf_problem* pb, Group& G, double DT) {
     };
     t.salt_balance_err = rel(b[0], b[1], b[4]);
     t.liquid_balance_err = rel(b[2], b[3], b[5]);
+  }
+  // history of the extrapolated start: this step's start state for the samples that took
+  // it as one implicit-Euler step
+  if (G.u_prev) {
+    std::vector<int> keep(S, 0);
+    for (int s = 0; s < S; ++s) {
+      keep[s] = started[s] && G.stats[s].status == EDF_SAMPLE_OK && G.stats[s].substeps == 1;
+      G.pred_dt[s] = keep[s] ? DT : 0.0;
+    }
+    if ((e = upload_ints(pb, G, G.lsmask, keep))) return e;
+    launch_masked_copy(G.n, G.u0, G.u_prev, S, G.lsmask, st);
   }
   // the next step starts with the sub-step count that worked; after `wait` steps
   // without a retry it tries one halving less, and every such try that fails
@@ -1647,7 +1700,7 @@ edf_status edf_create_problem(const edf_physics* phys, const edf_group_desc* gro
   if (opts->newton_max_it < 1 || opts->lin_max_it < 1 || opts->nu_pre < 1 || opts->nu_post < 0 ||
       opts->ls_max_halvings < 0 || !(opts->lin_rtol > 0) || !(opts->newton_rtol >= 0))
     return bad("invalid solver options");
-  if (opts->reserved[0] != 0) return bad("reserved options must be zero");
+  if (opts->predictor != 0 && opts->predictor != 1) return bad("predictor must be 0 or 1");
   if (opts->matrix_free != 0 && opts->matrix_free != 1) return bad("matrix_free must be 0 or 1");
   if (opts->graph_vcycle != 0 && opts->graph_vcycle != 1)
     return bad("graph_vcycle must be 0 or 1");
@@ -1765,6 +1818,7 @@ edf_status edf_set_state(edf_problem* pb, int32_t sample, const double* pc, int3
     G->clean[s] = 0;
     G->wait[s] = kFirstWait;
     G->probing[s] = 0;
+    G->pred_dt[s] = 0.0;
   }
   pb->traj_valid = false;
   return EDF_OK;
@@ -1856,6 +1910,12 @@ edf_status edf_solve(edf_problem* pb, double dt, int32_t n_steps, int32_t checkp
       EDF_TRY(hipStreamSynchronize(G.st));
     }
   }
+  // the recorded steps start Newton from the state (the adjoint recomputes them so)
+  struct Recording {
+    edf_problem* pb;
+    ~Recording() { pb->recording = false; }
+  } rec_guard{pb};
+  pb->recording = record;
   for (int m = 0; m < n_steps; ++m) {
     if ((e = step_all(pb, dt, m + 1 == n_steps ? stats : nullptr))) return e;
     if (!record) continue;

@@ -296,6 +296,9 @@ void launch_axpy_state(size_t N, const double* u, const double* d, const double*
                        double* out, int S, const int* mask, hipStream_t st);
 void launch_masked_copy(size_t n, const double* a, double* b, int S, const int* mask,
                         hipStream_t st);
+// out = 2 u - u_prev for the masked samples
+void launch_extrapolate(size_t n, const double* u, const double* u_prev, double* out, int S,
+                        const int* mask, hipStream_t st);
 void launch_gather_common(const Geom& gf, int cx, int cy, int cz, const double* u, double* out,
                           int S, hipStream_t st);
 // chunked form of launch_moments (pass 0: mean and exceedance, pass 1: variance), the

@@ -467,6 +467,25 @@ void launch_masked_copy(size_t n, const double* a, double* b, int S, const int* 
                      mask);
 }
 
+// out = 2 u - u_prev: the linear extrapolation of a sample's last two states (Newton's
+// starting point candidate of the next step)
+__global__ __launch_bounds__(kBlock) void k_extrapolate(size_t n, const double* u,
+                                                        const double* u_prev, double* out,
+                                                        const int* mask) {
+  const int s = blockIdx.y;
+  if (mask && !mask[s]) return;
+  const size_t o = (size_t)s * n;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x)
+    out[o + e] = 2.0 * u[o + e] - u_prev[o + e];
+}
+
+void launch_extrapolate(size_t n, const double* u, const double* u_prev, double* out, int S,
+                        const int* mask, hipStream_t st) {
+  hipLaunchKernelGGL(k_extrapolate, dim3(reduce_blocks(n), S), dim3(kBlock), 0, st, n, u, u_prev,
+                     out, mask);
+}
+
 // ---------------------------------------------------------------------------
 // statistics over samples (Section 3: eqs. pdestat, numer_var; Section 3.2)
 // ---------------------------------------------------------------------------
