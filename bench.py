@@ -429,7 +429,7 @@ def make_problem(args, wl, phys, groups, prec, log_tuning=True):
     opts = dict(newton_rtol=wl.newton_rtol, lin_rtol=1e-6, lin_max_it=400 if args.adjoint else 100,
                 newton_max_it=20,
                 precision={"f64": PREC_F64, "mixed": PREC_MIXED, "mixed16": PREC_MIXED_F16}[prec],
-                check_every=1, forcing=args.forcing, concurrent_groups=int(args.concurrent_groups),
+                check_every=1, forcing=args.forcing, concurrent_groups=args.concurrent_groups,
                 graph_vcycle=int(args.graph), substep_memory=int(args.substep_memory),
                 smoother=int(args.smoother), matrix_free=int(args.matrix_free),
                 predictor=int(args.predictor) if not args.adjoint else 0)
@@ -608,10 +608,12 @@ def main():
     ap.add_argument("--predictor", type=int, default=1, choices=[0, 1],
                     help="1: Newton starts a step from the extrapolation 2 u^n - u^{n-1} where "
                          "its defect is smaller (same stopping test)")
-    ap.add_argument("--concurrent-groups", action="store_true",
-                    help="advance the grid groups at the same time (one host thread and stream "
-                         "each); more throughput, but overlapping kernels lengthen the per-launch "
-                         "durations the roofline is computed from")
+    ap.add_argument("--concurrent-groups", type=int, default=2, choices=[0, 1, 2],
+                    help="0: the grid groups one after the other; 1: at the same time, one host "
+                         "thread and stream each (overlapping kernels lengthen the per-launch "
+                         "durations the roofline is computed from); 2: one host thread each on a "
+                         "shared stream, the V-cycles of the groups inside BiCGStab run together, "
+                         "each level the groups share swept by one launch over all their samples")
     ap.add_argument("--adjoint", action="store_true",
                     help="time the gradient instead of plain steps: edf_solve with a checkpoint "
                          "every 10 steps over --steps steps, then edf_adjoint (segments "
@@ -749,7 +751,7 @@ def main():
                    "substep_memory": bool(args.substep_memory),
                    "newton_predictor": bool(args.predictor),
                    "fused_bottom_from_level": tuning,
-                   "concurrent_groups": bool(args.concurrent_groups),
+                   "concurrent_groups": args.concurrent_groups,
                    "graph_vcycle": bool(args.graph)},
         "dof_timesteps_per_s": dofs * args.steps / el,
         "solver": leg["solver"],

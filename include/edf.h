@@ -119,11 +119,19 @@ typedef struct {
   int32_t forcing;         /* 0: every Newton system solved to lin_rtol; 1: to the  */
                            /* Eisenstat-Walker forcing term (choice 2, gamma 0.9,   */
                            /* at most 0.1, at least lin_rtol)                       */
-  int32_t concurrent_groups; /* 1: edf_step advances the groups at the same time,  */
-                           /* one host thread and stream each (more throughput;     */
-                           /* kernels of different groups then share the GPU, which */
-                           /* lengthens each one's measured duration); 0: one after */
-                           /* the other                                             */
+  int32_t concurrent_groups; /* 0: edf_step advances the groups one after the other; */
+                           /* 1: at the same time, one host thread and stream each  */
+                           /* (kernels of different groups then share the GPU, which */
+                           /* lengthens each one's measured duration); 2: one host  */
+                           /* thread each on one shared stream, and the V-cycles of */
+                           /* the groups inside BiCGStab run together: every level  */
+                           /* that groups share (same grid, same role in the cycle, */
+                           /* the groups' samples side by side in one allocation)   */
+                           /* is swept by one launch over all their listed samples, */
+                           /* and groups whose fused bottoms cover the same grids   */
+                           /* share its launch (bitwise the results of 0; Section 4 */
+                           /* runs the scenarios independently, here they also      */
+                           /* share launches).  graph_vcycle is not used in mode 2  */
   int32_t graph_vcycle;    /* 1: each V-cycle launch configuration is captured once  */
                            /* as a HIP graph and replayed (same kernels, same order, */
                            /* bitwise the same results; not while edf_profile is     */

@@ -5,9 +5,11 @@
 // decisions (convergence, line search) that need host control.
 #include <algorithm>
 #include <cmath>
+#include <condition_variable>
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -40,6 +42,9 @@ struct Level {
   void* x = nullptr;      // V-cycle vectors [S][Np][2] colour-major, V-cycle precision
   void* b = nullptr;
   void* r = nullptr;
+  // the group's first sample in the allocations this level shares with the levels of
+  // other groups on the same grid (V-cycle arrays; see plan_pools)
+  int slot = 0;
 };
 
 // one timed launch (edf_profile)
@@ -54,6 +59,9 @@ constexpr double kLargeLaunch = 256.0 * 1024 * 1024;
 
 struct Group {
   edf_group_desc d{};
+  std::vector<int> slots;  // Level::slot of every level, planned before allocation
+  long list_ver = 0;       // bumped whenever the V-cycle sample list changes
+  bool in_krylov = false;  // inside BiCGStab (merged V-cycles, concurrent_groups = 2)
   // groups step concurrently, each from its own host thread on its own stream
   hipStream_t st = nullptr;
   int* h_int = nullptr;  // pinned host staging [S]
@@ -135,6 +143,18 @@ struct Group {
   std::vector<edf_step_stats> stats;
 };
 
+// a group's request for one V-cycle, out = M^{-1} in (merged V-cycles)
+struct MergeReq {
+  Group* G;
+  const double* in;
+  double* out;
+  const int* mask;
+  bool done = false;
+};
+
+// arrays of a V-cycle level that live in the shared allocations of its grid
+enum PoolKind { kPoolVA64, kPoolA32, kPoolDinv, kPoolLF, kPoolR, kPoolB, kPoolX, kPoolMinv };
+
 }  // namespace
 
 struct edf_problem {
@@ -167,6 +187,34 @@ struct edf_problem {
   // the current ones
   double* dxi_new = nullptr;
   int* bad = nullptr;  // [S_total] flags of the check
+  // V-cycle arrays of levels on equal grids share one allocation per array kind, the
+  // groups' samples side by side (slots), so that one launch can serve several groups
+  struct Pool {
+    int nx, ny, nz, kind;
+    size_t per_sample;
+    char* base;
+  };
+  std::vector<Pool> pools;
+  std::map<std::tuple<int, int, int>, int> pool_slots;  // slots per grid
+  // merged V-cycles (concurrent_groups = 2): the groups' host threads meet before each
+  // V-cycle; when every group inside BiCGStab has arrived, one of them launches the
+  // V-cycles of all, one launch per shared grid level
+  std::mutex mg_mu;
+  std::condition_variable mg_cv;
+  int mg_in = 0;                       // groups inside BiCGStab
+  std::vector<MergeReq*> mg_wait;
+  struct ListBuf {
+    std::vector<long> key;   // the (group, level) pairs it serves
+    std::vector<long> vkey;  // their list versions and counts when it was built
+    int* d = nullptr;
+    int n = 0;
+  };
+  std::vector<ListBuf> mg_lists;
+  struct BottomDesc {
+    std::vector<long> key;
+    void* d = nullptr;
+  };
+  std::vector<BottomDesc> mg_bottoms;
   // statistics buffers (allocated on first use)
   double* mom_f = nullptr;
   double* mom_w = nullptr;
@@ -293,6 +341,66 @@ void reset_history(Group& G) {
 // ---------------------------------------------------------------------------
 // allocation of one group
 // ---------------------------------------------------------------------------
+// Slots of the shared V-cycle allocations: for every grid, the groups that have a level
+// on it, ordered by decreasing finest grid (then by group index), take consecutive slots.
+// A group with a level on a grid has levels on every coarser grid of its hierarchy, so the
+// groups of a grid come first on the next coarser one: a group's samples then have the
+// same slots on consecutive levels whenever the groups' hierarchies are nested, which the
+// merged restriction and prolongation need (it is checked before merging).
+void plan_pools(edf_problem* pb) {
+  std::map<std::tuple<int, int, int>, std::vector<int>> parts;
+  const int ng = (int)pb->groups.size();
+  for (int gi = 0; gi < ng; ++gi) {
+    Group& G = pb->groups[gi];
+    G.slots.assign(G.L, 0);
+    int nx = G.d.nx, ny = G.d.ny, nz = G.d.nz;
+    for (int l = 0; l < G.L; ++l) {
+      parts[{nx, ny, nz}].push_back(gi);
+      nx = (nx - 1) / 2 + 1;
+      ny = (ny - 1) / 2 + 1;
+      nz = (nz - 1) / 2 + 1;
+    }
+  }
+  for (auto& kv : parts) {
+    std::vector<int>& v = kv.second;
+    std::stable_sort(v.begin(), v.end(), [&](int a, int b) {
+      const edf_group_desc &da = pb->groups[a].d, &db = pb->groups[b].d;
+      return (long long)da.nx * da.ny * da.nz > (long long)db.nx * db.ny * db.nz;
+    });
+    int off = 0;
+    for (int gi : v) {
+      Group& G = pb->groups[gi];
+      int nx = G.d.nx, ny = G.d.ny, nz = G.d.nz;
+      for (int l = 0; l < G.L; ++l) {
+        if (std::make_tuple(nx, ny, nz) == kv.first) G.slots[l] = off;
+        nx = (nx - 1) / 2 + 1;
+        ny = (ny - 1) / 2 + 1;
+        nz = (nz - 1) / 2 + 1;
+      }
+      off += G.S;
+    }
+    pb->pool_slots[kv.first] = off;
+  }
+}
+
+// the array of `kind` (bytes per sample) of level l of G, in its grid's shared allocation
+edf_status take(edf_problem* pb, const Group& G, int l, int kind, size_t bytes, char** out) {
+  const Geom& g = G.lv[l].g;
+  for (const edf_problem::Pool& P : pb->pools)
+    if (P.nx == g.nx && P.ny == g.ny && P.nz == g.nz && P.kind == kind) {
+      if (P.per_sample != bytes) return fail(pb, EDF_ERR_STATE, "shared allocation size mismatch");
+      *out = P.base + (size_t)G.lv[l].slot * bytes;
+      return EDF_OK;
+    }
+  const size_t slots = pb->pool_slots[std::make_tuple(g.nx, g.ny, g.nz)];
+  char* q;
+  edf_status s;
+  if ((s = dalloc(pb, &q, slots * bytes))) return s;
+  pb->pools.push_back({g.nx, g.ny, g.nz, kind, bytes, q});
+  *out = q + (size_t)G.lv[l].slot * bytes;
+  return EDF_OK;
+}
+
 edf_status alloc_group(edf_problem* pb, Group& G) {
   const edf_physics& P = pb->phys;
   const int S = G.S;
@@ -307,34 +415,44 @@ edf_status alloc_group(edf_problem* pb, Group& G) {
     L.cells = (size_t)(nx - 1) * (ny - 1) * (nz - 1);
     const size_t N = L.g.N, Np = L.g.off[8];
     edf_status s;
+    L.slot = G.slots[l];
     if ((s = dalloc(pb, &L.phi, S * L.cells))) return s;
     if ((s = dalloc(pb, &L.K, S * L.cells))) return s;
     if (l > 0 && (s = dalloc(pb, &L.u, S * 2 * N))) return s;
     const bool coarsest = l == G.L - 1;
     // level 0: the exact Jacobian of the Krylov products, unless they are matrix-free
     // (the adjoint allocates it when it needs the transposed products)
-    if ((l == 0 && !pb->opts.matrix_free) || (l > 0 && (!mx || coarsest)))
+    if (l == 0 && !pb->opts.matrix_free)
       if ((s = dalloc(pb, &L.A64, S * kPlanes * Np))) return s;
-    if (mx && !coarsest)
-      if ((s = dalloc(pb, &L.A32, S * kPlanes * Np))) return s;
+    // the V-cycle arrays: in the shared allocations of the level's grid
+    char* q;
+    if (l > 0 && (!mx || coarsest)) {
+      if ((s = take(pb, G, l, kPoolVA64, kPlanes * Np * sizeof(double), &q))) return s;
+      L.A64 = reinterpret_cast<double*>(q);
+    }
+    if (mx && !coarsest) {
+      if ((s = take(pb, G, l, kPoolA32, kPlanes * Np * sizeof(float), &q))) return s;
+      L.A32 = reinterpret_cast<float*>(q);
+    }
     if (l == 0 && f16_finest(pb, G))
       if ((s = dalloc(pb, &L.A16, S * kPlanes * Np))) return s;
-    if (l == 0 && (!mx || coarsest))
-      if ((s = dalloc(pb, &L.AV64, S * kPlanes * Np))) return s;
-    char* q;
+    if (l == 0 && (!mx || coarsest)) {
+      if ((s = take(pb, G, l, kPoolVA64, kPlanes * Np * sizeof(double), &q))) return s;
+      L.AV64 = reinterpret_cast<double*>(q);
+    }
     if (!coarsest) {
-      if ((s = dalloc(pb, &q, S * 4 * Np * tsz))) return s;
+      if ((s = take(pb, G, l, kPoolDinv, 4 * Np * tsz, &q))) return s;
       L.Dinv = q;
       if (pb->opts.smoother == 1 && !(l == 0 && f16_finest(pb, G))) {
-        if ((s = dalloc(pb, &q, S * kLineFactors * Np * tsz))) return s;
+        if ((s = take(pb, G, l, kPoolLF, kLineFactors * Np * tsz, &q))) return s;
         L.LF = q;
       }
-      if ((s = dalloc(pb, &q, S * 2 * Np * tsz))) return s;
+      if ((s = take(pb, G, l, kPoolR, 2 * Np * tsz, &q))) return s;
       L.r = q;
     }
-    if ((s = dalloc(pb, &q, S * 2 * Np * tsz))) return s;
+    if ((s = take(pb, G, l, kPoolB, 2 * Np * tsz, &q))) return s;
     L.b = q;
-    if ((s = dalloc(pb, &q, S * 2 * Np * tsz))) return s;
+    if ((s = take(pb, G, l, kPoolX, 2 * Np * tsz, &q))) return s;
     L.x = q;
     nx = (nx - 1) / 2 + 1;
     ny = (ny - 1) / 2 + 1;
@@ -370,7 +488,11 @@ edf_status alloc_group(edf_problem* pb, Group& G) {
   }
   G.n_coarse = 2 * G.lv[G.L - 1].g.N;
   const size_t nc = G.n_coarse;
-  if ((s = dalloc(pb, &G.Minv, S * nc * nc))) return s;
+  {
+    char* q;
+    if ((s = take(pb, G, G.L - 1, kPoolMinv, nc * nc * sizeof(double), &q))) return s;
+    G.Minv = reinterpret_cast<double*>(q);
+  }
   if ((s = dalloc(pb, &G.piv, S * nc))) return s;
   if ((s = dalloc(pb, &G.gj_status, (size_t)S))) return s;
   if ((s = dalloc(pb, &G.bal, 8 * (size_t)S))) return s;
@@ -604,6 +726,7 @@ edf_status set_sample_list(edf_problem* pb, Group& G, const int* flags) {
     }
   if (same && n == G.n_list) return EDF_OK;
   G.n_list = n;
+  ++G.list_ver;
   if (n > 0)
     EDF_TRY(hipMemcpyAsync(G.d_list, G.h_list, n * sizeof(int), hipMemcpyHostToDevice, G.st));
   return EDF_OK;
@@ -827,7 +950,372 @@ bool vcycle_graph(edf_problem* pb, Group& G, const double* in, double* out, cons
   return hipGraphLaunch(exec, G.st) == hipSuccess;
 }
 
+// ---------------------------------------------------------------------------
+// merged V-cycles (concurrent_groups = 2): the V-cycles of several groups in one pass,
+// every level that groups share (same grid, same role in the cycle) swept by one launch
+// over all their listed samples.  The per-sample arithmetic is that of vcycle(): the
+// same kernels on the same slots, so the results are bitwise those of separate cycles.
+// ---------------------------------------------------------------------------
+const int* sample_list(const Group& G) { return G.n_list < G.S ? G.d_list : nullptr; }
+
+// start of a shared allocation, from a level's pointer into it
+const char* pool_base(const void* p, int slot, size_t per_sample) {
+  return p ? static_cast<const char*>(p) - (size_t)slot * per_sample : nullptr;
+}
+
+// one launch's list over the pairs (G, l): the slots of the groups' listed samples,
+// rebuilt on the device when a group's list changed since the last use
+const int* merged_list(edf_problem* pb, const std::vector<std::pair<Group*, int>>& parts,
+                       int& rows, hipStream_t st) {
+  std::vector<long> key, vkey;
+  ListSegs L{};
+  rows = 0;
+  for (const auto& pr : parts) {
+    Group* G = pr.first;
+    key.push_back((long)(intptr_t)G);
+    key.push_back(pr.second);
+    vkey.push_back(G->list_ver);
+    vkey.push_back(G->n_list);
+    L.seg[L.nseg++] = {sample_list(*G), G->n_list, G->lv[pr.second].slot, rows};
+    rows += G->n_list;
+  }
+  edf_problem::ListBuf* buf = nullptr;
+  for (auto& b : pb->mg_lists)
+    if (b.key == key) buf = &b;
+  if (!buf) {
+    const Geom& g = parts[0].first->lv[parts[0].second].g;
+    int* d = nullptr;
+    if (dalloc(pb, &d, (size_t)pb->pool_slots[std::make_tuple(g.nx, g.ny, g.nz)])) return nullptr;
+    pb->mg_lists.push_back({key, {}, d, 0});
+    buf = &pb->mg_lists.back();
+  }
+  if (buf->vkey != vkey) {
+    launch_concat_lists(L, rows, buf->d, st);
+    buf->vkey = vkey;
+    buf->n = rows;
+  }
+  return buf->d;
+}
+
+template <typename T>
+void vcycle_merged(edf_problem* pb, const std::vector<MergeReq*>& R) {
+  std::vector<MergeReq*> W;
+  for (MergeReq* r : R)
+    if (r->G->n_list > 0) W.push_back(r);
+  if (W.empty()) return;
+  // cycles the merged pass does not cover run one by one: a single group, the adjoint's
+  // transposed systems (general residual), an FP16 finest level, more than kMaxListSegs
+  bool plain = W.size() == 1 || W.size() > (size_t)kMaxListSegs;
+  for (MergeReq* r : W)
+    plain = plain || r->G->transposed || (std::is_same<T, float>::value && r->G->lv[0].A16);
+  if (plain) {
+    for (MergeReq* r : W) vcycle<T>(pb, *r->G, r->in, r->out, r->mask);
+    return;
+  }
+  Group& G0 = *W[0]->G;
+  hipStream_t st = G0.st;  // the groups share one stream in this mode
+  const int nu1 = pb->opts.nu_pre, nu2 = pb->opts.nu_post;
+  const bool zs_res = nu1 == 1;
+  const bool c0 = nu1 > 0;
+  const size_t tsz = sizeof(T);
+  hipEvent_t ve0 = nullptr, ve1 = nullptr;
+  {
+    double bytes = 0;
+    for (MergeReq* r : W)
+      bytes += vcycle_bytes(*r->G, tsz, nu1, nu2, first_fused_level(*r->G)) * r->G->n_active;
+    if (prof_pair(G0, ve0, ve1, bytes, 1)) (void)hipEventRecord(ve0, st);
+  }
+  auto l0of = [&](const Group* G) { return first_fused_level(*G); };
+  auto line = [&](const Group* G, int l) { return l < l0of(G) && G->lv[l].LF != nullptr; };
+  auto mask_of = [&](const Group* G) -> const int* {
+    for (MergeReq* r : W)
+      if (r->G == G) return r->mask;
+    return nullptr;
+  };
+  // entry permutations (per group)
+  for (MergeReq* r : W) {
+    Group& G = *r->G;
+    const int l0 = l0of(&G);
+    const bool c0_here = c0 && l0 > 0 && !line(&G, 0);
+    launch_to_colour<T>(G.lv[0].g, r->in, (T*)G.lv[0].b,
+                        c0_here ? (const T*)G.lv[0].Dinv : nullptr, (T*)G.lv[0].x, G.n_list,
+                        r->mask, sample_list(G), st);
+  }
+  // the swept levels, grouped by grid and role: (nx, ny, nz, line, next swept, next point)
+  struct Station {
+    std::tuple<int, int, int, int, int, int> key;
+    long long N;
+    std::vector<std::pair<Group*, int>> parts;
+  };
+  std::vector<Station> stations;
+  for (MergeReq* r : W) {
+    Group* G = r->G;
+    for (int l = 0; l < l0of(G); ++l) {
+      const Geom& g = G->lv[l].g;
+      const bool ln = line(G, l), nsw = l + 1 < l0of(G), npt = nsw && !line(G, l + 1);
+      auto key = std::make_tuple(g.nx, g.ny, g.nz, (int)ln, (int)nsw, (int)npt);
+      Station* at = nullptr;
+      for (Station& q : stations)
+        if (q.key == key) at = &q;
+      if (!at) {
+        stations.push_back({key, (long long)g.N, {}});
+        at = &stations.back();
+      }
+      at->parts.push_back({G, l});
+    }
+  }
+  std::stable_sort(stations.begin(), stations.end(),
+                   [](const Station& a, const Station& b) { return a.N > b.N; });
+  // whether the pairs' arrays lie in common allocations at their slots (and their next
+  // level's at the same slots), so that one launch over slots serves them all
+  auto aligned = [&](const std::vector<std::pair<Group*, int>>& parts) {
+    if (parts.size() < 2 || parts.size() > (size_t)kMaxListSegs) return false;
+    const Level& A = parts[0].first->lv[parts[0].second];
+    const Level& Ac = parts[0].first->lv[parts[0].second + 1];
+    const size_t Np = A.g.off[8], Npc = Ac.g.off[8];
+    for (const auto& pr : parts) {
+      const Level& L = pr.first->lv[pr.second];
+      const Level& Lc = pr.first->lv[pr.second + 1];
+      if (L.slot != Lc.slot) return false;
+      const int s = L.slot, a = A.slot;
+      auto same = [&](const void* p, const void* q, size_t per) {
+        return pool_base(p, s, per) == pool_base(q, a, per);
+      };
+      if (!same(stencil<T>(L), stencil<T>(A), kPlanes * Np * tsz) ||
+          !same(L.Dinv, A.Dinv, 4 * Np * tsz) || !same(L.LF, A.LF, kLineFactors * Np * tsz) ||
+          !same(L.b, A.b, 2 * Np * tsz) || !same(L.x, A.x, 2 * Np * tsz) ||
+          !same(L.r, A.r, 2 * Np * tsz) || !same(Lc.b, Ac.b, 2 * Npc * tsz) ||
+          !same(Lc.x, Ac.x, 2 * Npc * tsz) || !same(Lc.Dinv, Ac.Dinv, 4 * Npc * tsz))
+        return false;
+    }
+    return true;
+  };
+  // a launch target: the arrays at slot 0 of the shared allocations (merged) or the
+  // group's own arrays (one pair), the rows and list of the launch, active samples
+  struct Target {
+    const Level* L;
+    const Level* Lc;
+    const T* A;
+    const T* F;
+    const T* D;
+    T *b, *x, *r, *bc, *xc;
+    const T* Dc;
+    int rows;
+    const int* list;
+    const int* mask;
+    double active;
+    bool ln, npt, nsw;
+  };
+  auto target = [&](const std::vector<std::pair<Group*, int>>& parts, bool merge) {
+    std::vector<Target> out;
+    auto one = [&](Group* G, int l, int slot, int rows, const int* list, const int* mask,
+                   double active) {
+      const Level& L = G->lv[l];
+      const Level& Lc = G->lv[l + 1];
+      const size_t Np = L.g.off[8], Npc = Lc.g.off[8];
+      auto at = [&](const void* p, size_t per) {
+        return p ? (char*)pool_base(p, L.slot, per) + (size_t)slot * per : nullptr;
+      };
+      auto atc = [&](const void* p, size_t per) {
+        return p ? (char*)pool_base(p, Lc.slot, per) + (size_t)slot * per : nullptr;
+      };
+      Target t{&L, &Lc,
+               (const T*)at(stencil<T>(L), kPlanes * Np * tsz),
+               (const T*)at(L.LF, kLineFactors * Np * tsz),
+               (const T*)at(L.Dinv, 4 * Np * tsz),
+               (T*)at(L.b, 2 * Np * tsz), (T*)at(L.x, 2 * Np * tsz), (T*)at(L.r, 2 * Np * tsz),
+               (T*)atc(Lc.b, 2 * Npc * tsz), (T*)atc(Lc.x, 2 * Npc * tsz),
+               (const T*)atc(Lc.Dinv, 4 * Npc * tsz),
+               rows, list, mask, active, line(G, l), false, l + 1 < l0of(G)};
+      t.npt = t.nsw && !line(G, l + 1);
+      out.push_back(t);
+    };
+    if (merge) {
+      int rows = 0;
+      const int* list = merged_list(pb, parts, rows, st);
+      double active = 0;
+      for (const auto& pr : parts) active += pr.first->n_active;
+      // slot 0 of the shared allocations; the list holds slots; the groups' active flags
+      // are not in slot order, so the listed samples (those active at the last count)
+      // are all swept, as within a chunk of BiCGStab iterations
+      one(parts[0].first, parts[0].second, 0, rows, list, nullptr, active);
+    } else {
+      for (const auto& pr : parts) {
+        Group* G = pr.first;
+        one(G, pr.second, G->lv[pr.second].slot, G->n_list, sample_list(*G), mask_of(G),
+            (double)G->n_active);
+      }
+    }
+    return out;
+  };
+  auto smooth = [&](const Target& t, int c, const T* b, T* x, bool zs) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const Geom& g = t.L->g;
+    if (t.ln) {
+      const double nv = (double)g.mx[c] * g.my[c] * g.nz;
+      prof_pair(G0, e0, e1, nv * t.active * line_sweep_bytes(c, zs, tsz), 0);
+      launch_line_smooth<T>(g, c, t.A, t.F, b, x, t.rows, t.mask, t.list, st, e0, e1, zs);
+      return;
+    }
+    prof_pair(G0, e0, e1, (double)g.cnt[c] * t.active * sweep_bytes(c, zs, false, tsz), 0);
+    launch_smooth<T>(g, c, t.A, t.D, b, x, t.rows, t.mask, t.list, st, e0, e1, zs);
+  };
+  std::vector<std::vector<Target>> plan(stations.size());
+  for (size_t q = 0; q < stations.size(); ++q) {
+    plan[q] = target(stations[q].parts, aligned(stations[q].parts));
+    for (const Target& t : plan[q]) {
+      const int ncol = t.ln ? 4 : 8;
+      for (int it = 0; it < nu1; ++it)
+        for (int c = it == 0 && c0 && !t.ln ? 1 : 0; c < ncol; ++c) smooth(t, c, t.b, t.x, it == 0);
+      if (t.ln && zs_res)
+        launch_line_residual_zs<T>(t.L->g, t.A, t.x, t.r, t.rows, t.mask, t.list, st);
+      else
+        launch_residual<T>(t.L->g, t.A, t.b, t.x, t.r, t.rows, t.mask, t.list, st,
+                           zs_res && !t.ln);
+      launch_restrict<T>(t.L->g, t.Lc->g, t.r, t.bc, c0 ? (t.npt ? t.xc : nullptr) : t.xc,
+                         c0 && t.npt ? t.Dc : nullptr, t.rows, t.mask, t.list, st);
+    }
+  }
+  // the fused bottoms: groups whose fused levels lie on the same grids share one launch
+  {
+    std::vector<std::vector<Group*>> classes;
+    for (MergeReq* r : W) {
+      Group* G = r->G;
+      bool placed = false;
+      for (auto& c : classes) {
+        Group* H = c[0];
+        const int a = l0of(G), b = l0of(H);
+        bool same = G->L - a == H->L - b && c.size() < (size_t)kMaxListSegs;
+        for (int k = 0; same && a + k < G->L; ++k) {
+          const Level &X = G->lv[a + k], &Y = H->lv[b + k];
+          const size_t Np = X.g.off[8];
+          same = X.g.nx == Y.g.nx && X.g.ny == Y.g.ny && X.g.nz == Y.g.nz &&
+                 X.slot == G->lv[a].slot && Y.slot == H->lv[b].slot &&
+                 pool_base(X.b, X.slot, 2 * Np * tsz) == pool_base(Y.b, Y.slot, 2 * Np * tsz) &&
+                 pool_base(X.x, X.slot, 2 * Np * tsz) == pool_base(Y.x, Y.slot, 2 * Np * tsz) &&
+                 pool_base(X.r, X.slot, 2 * Np * tsz) == pool_base(Y.r, Y.slot, 2 * Np * tsz) &&
+                 pool_base(X.Dinv, X.slot, 4 * Np * tsz) ==
+                     pool_base(Y.Dinv, Y.slot, 4 * Np * tsz) &&
+                 (a + k == G->L - 1 ||
+                  pool_base(stencil<T>(X), X.slot, kPlanes * Np * tsz) ==
+                      pool_base(stencil<T>(Y), Y.slot, kPlanes * Np * tsz));
+        }
+        const size_t nc2 = (size_t)G->n_coarse * G->n_coarse * sizeof(double);
+        same = same && G->n_coarse == H->n_coarse &&
+               pool_base(G->Minv, G->lv[G->L - 1].slot, nc2) ==
+                   pool_base(H->Minv, H->lv[H->L - 1].slot, nc2);
+        if (same) {
+          c.push_back(G);
+          placed = true;
+          break;
+        }
+      }
+      if (!placed) classes.push_back({G});
+    }
+    for (auto& c : classes) {
+      Group* G = c[0];
+      const int l0 = l0of(G);
+      size_t lds_bytes = 0;
+      bool in_lds = false;
+      if (c.size() == 1) {
+        (void)fused_levels<T>(*G, l0, lds_bytes, in_lds);
+        ensure_fused_desc<T>(pb, *G, l0);
+        launch_vcycle_bottom<T>((const FusedLevels<T>*)G->fdesc, in_lds ? lds_bytes : 0,
+                                G->n_list, mask_of(G), sample_list(*G), st);
+        continue;
+      }
+      FusedLevels<T> F = fused_levels<T>(*G, l0, lds_bytes, in_lds);
+      F.nu1 = nu1;
+      F.nu2 = nu2;
+      for (int k = 0; k < F.n; ++k) {
+        const Level& X = G->lv[l0 + k];
+        const size_t Np = X.g.off[8];
+        F.A[k] = (const T*)pool_base(F.A[k], X.slot, kPlanes * Np * tsz);
+        F.D[k] = (const T*)pool_base(F.D[k], X.slot, 4 * Np * tsz);
+        F.r[k] = (T*)pool_base(F.r[k], X.slot, 2 * Np * tsz);
+        F.b[k] = (T*)pool_base(F.b[k], X.slot, 2 * Np * tsz);
+        F.x[k] = (T*)pool_base(F.x[k], X.slot, 2 * Np * tsz);
+      }
+      F.Minv = (const double*)pool_base(F.Minv, G->lv[G->L - 1].slot,
+                                        (size_t)G->n_coarse * G->n_coarse * sizeof(double));
+      std::vector<long> key = {F.n, F.nc, F.nu1, F.nu2, (long)(intptr_t)F.Minv};
+      for (int k = 0; k < F.n; ++k)
+        for (long v : {(long)F.lds_off[k], (long)F.g[k].nx, (long)F.g[k].ny, (long)F.g[k].nz,
+                       (long)(intptr_t)F.A[k], (long)(intptr_t)F.D[k], (long)(intptr_t)F.x[k],
+                       (long)(intptr_t)F.b[k], (long)(intptr_t)F.r[k]})
+          key.push_back(v);
+      void* desc = nullptr;
+      for (auto& d : pb->mg_bottoms)
+        if (d.key == key) desc = d.d;
+      if (!desc) {
+        char* q = nullptr;
+        if (dalloc(pb, &q, sizeof(F))) return;
+        (void)hipMemcpyAsync(q, &F, sizeof(F), hipMemcpyHostToDevice, st);
+        (void)hipStreamSynchronize(st);
+        pb->mg_bottoms.push_back({key, q});
+        desc = q;
+      }
+      std::vector<std::pair<Group*, int>> parts;
+      for (Group* H : c) parts.push_back({H, l0of(H)});
+      int rows = 0;
+      const int* list = merged_list(pb, parts, rows, st);
+      launch_vcycle_bottom<T>((const FusedLevels<T>*)desc, in_lds ? lds_bytes : 0, rows,
+                              nullptr, list, st);
+    }
+  }
+  for (size_t q = stations.size(); q-- > 0;)
+    for (const Target& t : plan[q]) {
+      launch_prolong<T>(t.L->g, t.Lc->g, t.xc, t.x, t.rows, t.mask, t.list, st);
+      const int ncol = t.ln ? 4 : 8;
+      for (int it = 0; it < nu2; ++it)
+        for (int c = ncol - 1; c >= 0; --c) smooth(t, c, t.b, t.x, false);
+    }
+  for (MergeReq* r : W) {
+    Group& G = *r->G;
+    launch_from_colour<T>(G.lv[0].g, (const T*)G.lv[0].x, r->out, G.n_list, r->mask,
+                          sample_list(G), st);
+  }
+  if (ve1) (void)hipEventRecord(ve1, st);
+}
+
+// with every group inside BiCGStab waiting (mg_mu held): their V-cycles in one pass
+void merged_run(edf_problem* pb) {
+  std::vector<MergeReq*> R;
+  R.swap(pb->mg_wait);
+  if (mixed(pb))
+    vcycle_merged<float>(pb, R);
+  else
+    vcycle_merged<double>(pb, R);
+  for (MergeReq* r : R) r->done = true;
+  pb->mg_cv.notify_all();
+}
+
+void krylov_enter(edf_problem* pb, Group& G) {
+  if (pb->opts.concurrent_groups != 2) return;
+  std::lock_guard<std::mutex> lk(pb->mg_mu);
+  ++pb->mg_in;
+  G.in_krylov = true;
+}
+
+void krylov_leave(edf_problem* pb, Group& G) {
+  if (!G.in_krylov) return;
+  std::lock_guard<std::mutex> lk(pb->mg_mu);
+  --pb->mg_in;
+  G.in_krylov = false;
+  if (!pb->mg_wait.empty() && (int)pb->mg_wait.size() >= pb->mg_in) merged_run(pb);
+}
+
 void precondition(edf_problem* pb, Group& G, const double* in, double* out, const int* mask) {
+  if (G.in_krylov) {  // wait for the other groups inside BiCGStab, or run all their cycles
+    MergeReq r{&G, in, out, mask};
+    std::unique_lock<std::mutex> lk(pb->mg_mu);
+    pb->mg_wait.push_back(&r);
+    if ((int)pb->mg_wait.size() >= pb->mg_in)
+      merged_run(pb);
+    else
+      pb->mg_cv.wait(lk, [&] { return r.done; });
+    return;
+  }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const size_t tsz = mixed(pb) ? sizeof(float) : sizeof(double);
   const double bytes =
@@ -850,6 +1338,12 @@ void precondition(edf_problem* pb, Group& G, const double* in, double* out, cons
 // BiCGStab on A x = F~ for the samples in G.nmask; x in G.kx
 // ---------------------------------------------------------------------------
 edf_status bicgstab(edf_problem* pb, Group& G) {
+  krylov_enter(pb, G);
+  struct Leave {
+    edf_problem* pb;
+    Group& G;
+    ~Leave() { krylov_leave(pb, G); }
+  } leave{pb, G};
   hipStream_t st = G.st;
   const int S = G.S;
   const size_t n = G.n;
@@ -1704,8 +2198,8 @@ edf_status edf_create_problem(const edf_physics* phys, const edf_group_desc* gro
   if (opts->matrix_free != 0 && opts->matrix_free != 1) return bad("matrix_free must be 0 or 1");
   if (opts->graph_vcycle != 0 && opts->graph_vcycle != 1)
     return bad("graph_vcycle must be 0 or 1");
-  if (opts->concurrent_groups != 0 && opts->concurrent_groups != 1)
-    return bad("concurrent_groups must be 0 or 1");
+  if (opts->concurrent_groups < 0 || opts->concurrent_groups > 2)
+    return bad("concurrent_groups must be 0, 1 or 2");
   if (opts->forcing != 0 && opts->forcing != 1) return bad("forcing must be 0 or 1");
   if (opts->smoother != 0 && opts->smoother != 1) return bad("smoother must be 0 or 1");
   if (opts->substep_memory != 0 && opts->substep_memory != 1)
@@ -1731,6 +2225,7 @@ edf_status edf_create_problem(const edf_physics* phys, const edf_group_desc* gro
     pb->groups.push_back(G);
   }
   pb->S_total = s0;
+  plan_pools(pb);
   for (Group& G : pb->groups) {
     edf_status s = alloc_group(pb, G);
     if (s) {
@@ -1739,9 +2234,12 @@ edf_status edf_create_problem(const edf_physics* phys, const edf_group_desc* gro
       return s;
     }
   }
+  const bool shared_stream = opts->concurrent_groups == 2;
   for (Group& G : pb->groups) {
     const bool ok =
-        hipStreamCreateWithFlags(&G.st, hipStreamNonBlocking) == hipSuccess &&
+        (shared_stream && &G != &pb->groups[0]
+             ? (G.st = pb->groups[0].st) != nullptr
+             : hipStreamCreateWithFlags(&G.st, hipStreamNonBlocking) == hipSuccess) &&
         hipHostMalloc((void**)&G.h_int, sizeof(int) * G.S) == hipSuccess &&
         hipHostMalloc((void**)&G.h_list, sizeof(int) * G.S) == hipSuccess &&
         hipHostMalloc((void**)&G.h_dbl, sizeof(double) * G.S) == hipSuccess &&
@@ -2445,10 +2943,12 @@ const char* edf_last_error(const edf_problem* pb) { return pb ? pb->err.c_str() 
 void edf_destroy(edf_problem* pb) {
   if (!pb) return;
   if (pb->st) (void)hipStreamSynchronize(pb->st);
+  std::vector<hipStream_t> destroyed;  // groups may share one stream (concurrent_groups = 2)
   for (Group& G : pb->groups) {
-    if (G.st) {
+    if (G.st && std::find(destroyed.begin(), destroyed.end(), G.st) == destroyed.end()) {
       (void)hipStreamSynchronize(G.st);
       (void)hipStreamDestroy(G.st);
+      destroyed.push_back(G.st);
     }
     for (hipEvent_t e : G.prof_ev) (void)hipEventDestroy(e);
     for (auto& v : G.vgraphs) (void)hipGraphExecDestroy(v.exec);

@@ -296,6 +296,20 @@ void launch_axpy_state(size_t N, const double* u, const double* d, const double*
                        double* out, int S, const int* mask, hipStream_t st);
 void launch_masked_copy(size_t n, const double* a, double* b, int S, const int* mask,
                         hipStream_t st);
+// A launch over the samples of several groups whose levels share one grid and one
+// allocation (slots of the groups side by side): its list is built on the device from the
+// groups' own lists, segment q contributing off_q + src_q[j] (j < n_q; src_q null: j) at
+// dst[at_q + j]
+constexpr int kMaxListSegs = 8;
+struct ListSeg {
+  const int* src;
+  int n, off, at;
+};
+struct ListSegs {
+  ListSeg seg[kMaxListSegs];
+  int nseg;
+};
+void launch_concat_lists(const ListSegs& L, int total, int* dst, hipStream_t st);
 // out = 2 u - u_prev for the masked samples
 void launch_extrapolate(size_t n, const double* u, const double* u_prev, double* out, int S,
                         const int* mask, hipStream_t st);

@@ -467,6 +467,24 @@ void launch_masked_copy(size_t n, const double* a, double* b, int S, const int* 
                      mask);
 }
 
+// the sample list of a launch over several groups' levels of one grid: segment q gives
+// the slots off_q + src_q[j] (or off_q + j when src_q is null), j < n_q, one after the other
+__global__ __launch_bounds__(kBlock) void k_concat_lists(ListSegs L, int* dst) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int q = 0; q < L.nseg; ++q) {
+    if (i < L.seg[q].n) {
+      dst[L.seg[q].at + i] = L.seg[q].off + (L.seg[q].src ? L.seg[q].src[i] : i);
+      return;
+    }
+    i -= L.seg[q].n;
+  }
+}
+
+void launch_concat_lists(const ListSegs& L, int total, int* dst, hipStream_t st) {
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_concat_lists, dim3(ceil_div(total, kBlock)), dim3(kBlock), 0, st, L, dst);
+}
+
 // out = 2 u - u_prev: the linear extrapolation of a sample's last two states (Newton's
 // starting point candidate of the next step)
 __global__ __launch_bounds__(kBlock) void k_extrapolate(size_t n, const double* u,

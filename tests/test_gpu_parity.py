@@ -438,26 +438,42 @@ def test_autotuned_step_matches_default():
     assert _rel(out[1], out[0]) < 1e-12
 
 
-def test_concurrent_groups_give_the_serial_result():
-    """Groups advanced at the same time (one host thread and stream each) reach bitwise
-    the states and statistics of groups advanced one after the other."""
+@pytest.mark.parametrize("conc,precision,groups", [
+    (1, 0, [(9, 9, 3, 2, 3), (17, 17, 5, 3, 2), (33, 33, 9, 4, 2)]),
+    (2, 0, [(9, 9, 3, 2, 3), (17, 17, 5, 3, 2), (33, 33, 9, 4, 2)]),
+    (2, 1, [(9, 9, 3, 2, 3), (17, 17, 5, 3, 2), (33, 33, 9, 4, 2)]),
+    (2, 0, [(17, 13, 5, 3, 3), (33, 33, 9, 4, 2), (33, 33, 9, 3, 2)])])
+def test_concurrent_groups_give_the_serial_result(conc, precision, groups):
+    """Groups advanced at the same time reach bitwise the states and solver counts of groups
+    advanced one after the other: with one host thread and stream each (1), and with one
+    thread each on a shared stream where the V-cycles of the groups inside BiCGStab run
+    together, each level that groups share (same grid, same role) swept by one launch over
+    all their samples (2).  The last grid set has levels that do not line up (a 17x13x5
+    group, two 33x33x9 groups whose hierarchies end at different depths), which run as
+    separate launches.  Merging only removes launches: with edf_profile on, the merged
+    run counts no more smoother launches than the serial one."""
     phys = synth.physics(2)
-    groups = [(9, 9, 3, 2, 3), (17, 17, 5, 3, 2), (33, 33, 9, 4, 2)]
-    xi = _xi(2, 7, seed=21)
+    S = sum(g[4] for g in groups)
+    xi = _xi(2, S, seed=21)
     xi[3] = 0.9  # a high-permeability sample that needs sub-steps at 4 months
-    out = {}
-    for conc in (0, 1):
-        pb = _problem(phys, groups, concurrent_groups=conc, dt_max_halvings=4)
+    out, launches = {}, {}
+    for c in (0, conc):
+        pb = _problem(phys, groups, concurrent_groups=c, dt_max_halvings=4, precision=precision,
+                      check_every=1)
         pb.set_parameters(xi)
+        pb.profile(True)
         sts = [pb.step(4 * DT) for _ in range(2)]
-        out[conc] = ([pb.get_state(s) for s in range(7)],
-                     [[(x["status"], x["newton_its"], x["lin_its"], x["substeps"]) for x in st]
-                      for st in sts])
+        launches[c] = pb.profile(False)["all_launches"]
+        out[c] = ([pb.get_state(s) for s in range(S)],
+                  [[(x["status"], x["newton_its"], x["lin_its"], x["substeps"]) for x in st]
+                   for st in sts])
         pb.destroy()
-    print("sub-steps", [x[3] for x in out[1][1][1]], flush=True)
-    assert out[1][1] == out[0][1]
-    for s in range(7):
-        assert np.array_equal(out[1][0][s], out[0][0][s]), s
+    print("sub-steps", [x[3] for x in out[conc][1][1]], "smoother launches", launches,
+          flush=True)
+    assert out[conc][1] == out[0][1]
+    for s in range(S):
+        assert np.array_equal(out[conc][0][s], out[0][0][s]), s
+    assert launches[conc] <= launches[0]
 
 
 def _zero_start_blocks(c):
