@@ -103,20 +103,24 @@ def _par(n, p):
 
 
 def _line_tables(wl):
-    """(workgroups along x, threads per workgroup) -> {(columns, nz)} of the line-smoother
-    launches of the workload's levels (k_line_sweep: 16 columns per 256-thread workgroup,
-    the column-walk fallback k_line_smooth: 64 per 64), and padded colour-major size ->
-    (level, per-colour-of-columns vertex counts) for the residual launches."""
+    """(workgroups along x, threads per workgroup, columns per workgroup) -> {(columns, nz)}
+    of the line-smoother launches of the workload's levels (k_line_sweep: 8, 16 or 32
+    columns per 256-thread workgroup, the column-walk fallback k_line_smooth: 64 per 64),
+    and padded colour-major size -> (level, per-colour-of-columns vertex counts) for the
+    residual launches."""
     sweep, resid = {}, {}
     for nx, ny, nz in _levels(wl):
         for cc in range(4):
             nc = _par(nx, cc & 1) * _par(ny, cc >> 1)
-            sweep.setdefault((-(-nc // 16), 256), set()).add((nc, nz))
-            sweep.setdefault((-(-nc // 64), 64), set()).add((nc, nz))
-        pad = sum(-(-(_par(nx, c & 1) * _par(ny, c >> 1 & 1) * _par(nz, c >> 2)) // 64) * 64
-                  for c in range(8))
+            for cols in (8, 16, 32):
+                sweep.setdefault((-(-nc // cols), 256, cols), set()).add((nc, nz))
+            sweep.setdefault((-(-nc // 64), 64, 64), set()).add((nc, nz))
+        # k_line_residual_zs runs in slab order: 8 slabs of every colour's 64-position
+        # tiles, workgroups of 4 tiles, the grid a multiple of 8 workgroups
+        T = [-(-(_par(nx, c & 1) * _par(ny, c >> 1 & 1) * _par(nz, c >> 2)) // 64) for c in range(8)]
+        most = max(sum((x + 1) * t // 8 - x * t // 8 for t in T) for x in range(8))
         per_cc = [_par(nx, cc & 1) * _par(ny, cc >> 1) * nz for cc in range(4)]
-        resid.setdefault(-(-pad // 256) * 256, set()).add(tuple(per_cc))
+        resid.setdefault(8 * -(-most // 4) * 256, set()).add(tuple(per_cc))
     return sweep, resid
 
 
@@ -124,14 +128,16 @@ def _dispatch_bytes(name, bx, wx, gx, rows, sweep, resid):
     """Algorithmic bytes of one smoother or residual dispatch (the library's count), or
     None for other kernels and ambiguous grids."""
     import re
-    m = re.search(r"k_line_(?:sweep|smooth)<(float|double), (?:true|false), (-?\d+)>", name)
+    m = re.search(r"k_line_(sweep|smooth)<(float|double), (?:true|false), (-?\d+)(?:, (\d+))?>",
+                  name)
     if m:
-        cand = sweep.get((bx, wx), set())
+        cols = int(m.group(4)) if m.group(4) else 64
+        cand = sweep.get((bx, wx, cols), set())
         if len(cand) != 1:
             return None
         (nc, nz), = cand
-        nb = 24 if int(m.group(2)) < 0 else ZERO_START_BLOCKS[int(m.group(2))]
-        return rows * nc * nz * (4 * (nb + 1) + 16) * (4 if m.group(1) == "float" else 8)
+        nb = 24 if int(m.group(3)) < 0 else ZERO_START_BLOCKS[int(m.group(3))]
+        return rows * nc * nz * (4 * (nb + 1) + 16) * (4 if m.group(2) == "float" else 8)
     m = re.search(r"k_line_residual_zs<(float|double), (?:true|false)>", name)
     if m:
         cand = resid.get(gx, set())
@@ -443,12 +449,13 @@ def make_problem(args, wl, phys, groups, prec, log_tuning=True):
         for gi, lv in enumerate(levels):
             pb.set_tuning(gi, lv)
     elif not args.no_autotune:
-        pb.autotune(wl.dt)
+        pb.autotune(wl.dt, cache=args.tuning_cache)
     tuning = [pb.tuning(g)[0] for g in range(len(groups))]
     if log_tuning:
         for gi in range(len(groups)):
             log(f"group {gi}: V-cycle ms per first fused level "
-                f"{np.round(pb.tuning(gi)[1], 3).tolist()}")
+                f"{np.round(pb.tuning(gi)[1], 3).tolist()}; line-sweep columns per "
+                f"workgroup by level {pb.line_tiles(gi)}")
     log(f"set-up {time.perf_counter() - t:.1f} s; fused V-cycle bottom from levels {tuning}")
     return pb, tuning
 
@@ -629,6 +636,10 @@ def main():
                          "autotuning; e.g. to repeat a run's launch configuration under a profiler)")
     ap.add_argument("--fuse-from-fp64", default=None,
                     help="as --fuse-from, for the FP64 leg of the two-leg default run")
+    ap.add_argument("--tuning-cache", default=None,
+                    help="JSON file of V-cycle tunings (fused bottom, line-sweep tile shapes) by "
+                         "groups, precision, smoother and device: applied when it holds this "
+                         "problem's key, else tuned and stored")
     ap.add_argument("--mark-timed-region", action="store_true",
                     help="mark the timed steps with a roctx range (rocprofv3 --marker-trace)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -725,6 +736,7 @@ def main():
         return run_adjoint(args, wl, pb, prec)
     if args.gpc:
         return run_gpc(args, wl, pb, prec)
+    tiles = [pb.line_tiles(g) for g in range(len(groups))]
     leg = run_steps(args, wl, pb, prec, region)
     el = leg["el"]
     dofs = sum(2 * g.n_vertices * g.samples for g in wl.groups)
@@ -751,6 +763,7 @@ def main():
                    "substep_memory": bool(args.substep_memory),
                    "newton_predictor": bool(args.predictor),
                    "fused_bottom_from_level": tuning,
+                   "line_sweep_columns_per_workgroup": tiles,
                    "concurrent_groups": args.concurrent_groups,
                    "graph_vcycle": bool(args.graph)},
         "dof_timesteps_per_s": dofs * args.steps / el,

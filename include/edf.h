@@ -422,12 +422,17 @@ edf_status edf_profile(edf_problem* pb, int32_t enable, double* out);
 
 /* Autotuning of the V-cycle (an implementation choice, not part of the method): the
  * coarse levels of every group can run in one launch with one workgroup per sample
- * (the fused bottom), which saves launches but walks the levels one after the other.
- * This call assembles the Newton matrices at the current states with time step dt,
- * times three V-cycles per group for every admissible first fused level, twice over,
- * and keeps the fastest (the better of its two timings counts for each).  States are not changed.  Without it (or edf_set_tuning) a group of
- * >= 64 samples fuses all levels of <= 4096 vertices, a smaller group only the
- * coarse solve.  EDF_ERR_STATE before edf_set_parameters, EDF_ERR_ARG for dt <= 0. */
+ * (the fused bottom), which saves launches but walks the levels one after the other,
+ * and the vertical-line sweep of each level swept by its own launches has a tile shape
+ * (8, 16 or 32 columns per 256-thread workgroup: LDS per workgroup against rows gathered
+ * per wave).  This call assembles the Newton matrices at the current states with time
+ * step dt, times three V-cycles per group for every admissible first fused level, twice
+ * over, and keeps the fastest (the better of its two timings counts for each); then, level
+ * by level from the finest, every tile shape the level's LDS allows in the same way.
+ * States are not changed.  Without it (or edf_set_tuning) a group of >= 64 samples fuses
+ * all levels of <= 4096 vertices, a smaller group only the coarse solve, and line sweeps
+ * take 16 columns per workgroup.  EDF_ERR_STATE before edf_set_parameters, EDF_ERR_ARG
+ * for dt <= 0. */
 edf_status edf_autotune(edf_problem* pb, double dt);
 
 /* The V-cycle configuration of group `group`: *fuse_from = first level run in the
@@ -440,6 +445,16 @@ edf_status edf_get_tuning(edf_problem* pb, int32_t group, int32_t* fuse_from, do
  * from fuse_from on has at most 4096 vertices, at most 6 levels are fused, and
  * fuse_from <= n_levels - 1 (the coarsest level alone is always allowed). */
 edf_status edf_set_tuning(edf_problem* pb, int32_t group, int32_t fuse_from);
+
+/* Tile shapes of the vertical-line sweeps of group `group` (see edf_autotune):
+ * cols (host int32_t[n_levels]) = columns per workgroup of each level's k_line_sweep, 0
+ * for a level without line smoothing (the coarsest, an FP16 finest level, the point
+ * smoother).  edf_set_line_tiles fixes them (e.g. from a saved tuning); EDF_ERR_ARG,
+ * with nothing changed, unless every entry is 0 exactly where the level has no line
+ * smoothing and otherwise 8, 16 or 32 with 10 x nz x cols values in at most 64 KiB of
+ * LDS.  Tile shapes do not change results (each column is computed the same way). */
+edf_status edf_get_line_tiles(edf_problem* pb, int32_t group, int32_t* cols);
+edf_status edf_set_line_tiles(edf_problem* pb, int32_t group, const int32_t* cols);
 
 const char* edf_last_error(const edf_problem* pb);
 void edf_destroy(edf_problem* pb); /* NULL is allowed */

@@ -3,6 +3,7 @@ runs in the library's HIP kernels).  Names follow the C-ABI in include/edf.h."""
 from __future__ import annotations
 
 import ctypes as C
+import json
 import os
 
 import numpy as np
@@ -94,6 +95,8 @@ _SIGS = {
     "edf_autotune": [_P, C.c_double],
     "edf_get_tuning": [_P, C.c_int32, C.POINTER(C.c_int32), _D],
     "edf_set_tuning": [_P, C.c_int32, C.c_int32],
+    "edf_get_line_tiles": [_P, C.c_int32, C.POINTER(C.c_int32)],
+    "edf_set_line_tiles": [_P, C.c_int32, C.POINTER(C.c_int32)],
     "edf_profile": [_P, C.c_int32, _D],
     "edf_last_error": [_P],
     "edf_destroy": [_P],
@@ -363,8 +366,52 @@ class Problem:
                 "large_bytes": float(out[10]), "large_all_launches": int(out[11]),
                 "large_all_bytes": float(out[12])}
 
-    def autotune(self, dt: float):
+    def tuning_key(self) -> str:
+        """What a V-cycle tuning depends on: the groups, the V-cycle's precision, smoother
+        and sweep counts, and the device."""
+        try:
+            import torch
+            dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "none"
+        except Exception:
+            dev = "unknown"
+        o = self.opts
+        return json.dumps({"groups": [list(g) for g in self.groups], "precision": o["precision"],
+                           "smoother": o["smoother"], "nu": [o["nu_pre"], o["nu_post"]],
+                           "device": dev}, sort_keys=True)
+
+    def autotune(self, dt: float, cache: str | None = None):
+        """edf_autotune; with `cache` (a JSON file), a tuning stored there under this
+        problem's tuning_key() is applied instead, and a new one is stored."""
+        key = self.tuning_key()
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+            if key in table:
+                for g, rec in enumerate(table[key]):
+                    self.set_tuning(g, rec["fuse_from"])
+                    self.set_line_tiles(g, rec["line_tiles"])
+                return False
         self._check(self._lib.edf_autotune(self._h, float(dt)))
+        if cache:
+            table[key] = [{"fuse_from": self.tuning(g)[0], "line_tiles": self.line_tiles(g),
+                           "vcycle_ms": [float(v) for v in self.tuning(g)[1]]}
+                          for g in range(len(self.groups))]
+            with open(cache, "w") as f:
+                json.dump(table, f, indent=1)
+        return True
+
+    def line_tiles(self, group: int):
+        """Columns per workgroup of each level's line sweep (0: no line smoothing)."""
+        L = self.groups[group][3]
+        out = (C.c_int32 * L)()
+        self._check(self._lib.edf_get_line_tiles(self._h, group, out))
+        return [int(v) for v in out]
+
+    def set_line_tiles(self, group: int, cols):
+        L = self.groups[group][3]
+        arr = (C.c_int32 * L)(*[int(v) for v in cols])
+        self._check(self._lib.edf_set_line_tiles(self._h, group, arr))
 
     def tuning(self, group: int):
         """(first fused level, V-cycle ms per candidate level or -1) of a group."""

@@ -45,6 +45,7 @@ struct Level {
   // the group's first sample in the allocations this level shares with the levels of
   // other groups on the same grid (V-cycle arrays; see plan_pools)
   int slot = 0;
+  int line_cols = 16;  // tile shape of the line sweep: columns per workgroup (autotuned)
 };
 
 // one timed launch (edf_profile)
@@ -840,7 +841,7 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
       const double nv = (double)L.g.mx[c] * L.g.my[c] * L.g.nz;
       prof_pair(G, e0, e1, nv * G.n_active * line_sweep_bytes(c, zs, sizeof(T)), 0);
       launch_line_smooth<T>(L.g, c, stencil<T>(L), (const T*)L.LF, b, x, S, mask, list, st, e0,
-                            e1, zs);
+                            e1, zs, L.line_cols);
       return;
     }
     const double per_vertex = sweep_bytes(c, zs, l == 0 && h0, sizeof(T));
@@ -1154,7 +1155,8 @@ void vcycle_merged(edf_problem* pb, const std::vector<MergeReq*>& R) {
     if (t.ln) {
       const double nv = (double)g.mx[c] * g.my[c] * g.nz;
       prof_pair(G0, e0, e1, nv * t.active * line_sweep_bytes(c, zs, tsz), 0);
-      launch_line_smooth<T>(g, c, t.A, t.F, b, x, t.rows, t.mask, t.list, st, e0, e1, zs);
+      launch_line_smooth<T>(g, c, t.A, t.F, b, x, t.rows, t.mask, t.list, st, e0, e1, zs,
+                            t.L->line_cols);
       return;
     }
     prof_pair(G0, e0, e1, (double)g.cnt[c] * t.active * sweep_bytes(c, zs, false, tsz), 0);
@@ -1464,8 +1466,36 @@ edf_status autotune_group(edf_problem* pb, Group& G) {
   int best_l0 = G.L - 1;
   for (int l0 = first_fusable(G); l0 < G.L; ++l0)
     if (G.tune_ms[l0] < G.tune_ms[best_l0]) best_l0 = l0;
-  G.prof_on = was_on;
   G.fuse_from = best_l0;
+  // tile shape of the line sweep on every level swept by its own launches, finest first
+  // (coordinate descent: the other levels keep their current choice); each candidate's
+  // time is the better of two timings of three V-cycles
+  const bool mx = mixed(pb);
+  for (int l = 0; l < best_l0; ++l) {
+    Level& L = G.lv[l];
+    if (!L.LF) continue;
+    double best = -1.0;
+    int best_c = L.line_cols;
+    for (int c : {8, 16, 32}) {
+      if (!(mx ? line_cols_valid<float>(L.g, c) : line_cols_valid<double>(L.g, c))) continue;
+      L.line_cols = c;
+      for (int pass = 0; pass < 2; ++pass) {
+        precondition(pb, G, G.kp, G.kph, G.nmask);
+        EDF_TRY(hipEventRecord(a, st));
+        for (int r = 0; r < 3; ++r) precondition(pb, G, G.kp, G.kph, G.nmask);
+        EDF_TRY(hipEventRecord(b, st));
+        EDF_TRY(hipEventSynchronize(b));
+        float ms = 0.f;
+        EDF_TRY(hipEventElapsedTime(&ms, a, b));
+        if (best < 0 || ms / 3.0 < best) {
+          best = ms / 3.0;
+          best_c = c;
+        }
+      }
+    }
+    L.line_cols = best_c;
+  }
+  G.prof_on = was_on;
   EDF_TRY(hipEventDestroy(a));
   EDF_TRY(hipEventDestroy(b));
   EDF_CHECK_LAUNCH();
@@ -2904,6 +2934,33 @@ edf_status edf_set_tuning(edf_problem* pb, int32_t group, int32_t fuse_from) {
     return fail(pb, EDF_ERR_ARG, "fuse_from must lie between the first level of at most 4096 "
                                  "vertices (at most 6 fused levels) and the coarsest level");
   G.fuse_from = fuse_from;
+  return EDF_OK;
+}
+
+edf_status edf_get_line_tiles(edf_problem* pb, int32_t group, int32_t* cols) {
+  if (!pb || !cols || group < 0 || group >= (int)pb->groups.size())
+    return fail(pb, EDF_ERR_ARG, "bad tile arguments");
+  const Group& G = pb->groups[group];
+  for (int l = 0; l < G.L; ++l) cols[l] = G.lv[l].LF ? G.lv[l].line_cols : 0;
+  return EDF_OK;
+}
+
+edf_status edf_set_line_tiles(edf_problem* pb, int32_t group, const int32_t* cols) {
+  if (!pb || !cols || group < 0 || group >= (int)pb->groups.size())
+    return fail(pb, EDF_ERR_ARG, "bad tile arguments");
+  Group& G = pb->groups[group];
+  const bool mx = mixed(pb);
+  for (int l = 0; l < G.L; ++l) {
+    if (!G.lv[l].LF) {
+      if (cols[l] != 0) return fail(pb, EDF_ERR_ARG, "a level without line smoothing takes 0");
+      continue;
+    }
+    if (!(mx ? line_cols_valid<float>(G.lv[l].g, cols[l])
+             : line_cols_valid<double>(G.lv[l].g, cols[l])))
+      return fail(pb, EDF_ERR_ARG, "columns per workgroup must be 8, 16 or 32 and fit the LDS");
+  }
+  for (int l = 0; l < G.L; ++l)
+    if (G.lv[l].LF) G.lv[l].line_cols = cols[l];
   return EDF_OK;
 }
 

@@ -145,11 +145,18 @@ __host__ __device__ constexpr int line_zero_start_blocks(int cc) {
 // below blocks of A), computed in FP64 and stored in T
 template <typename T>
 void launch_line_factor(const Geom& g, const T* A, T* F, int S, const int* mask, hipStream_t st);
-// one line sweep of column colour cc; zero_start: the level's first forward sweep from x = 0
+// one line sweep of column colour cc; zero_start: the level's first forward sweep from x = 0;
+// cols: columns per workgroup (8, 16 or 32; an invalid choice falls back to 16), the tile
+// shape the autotuner picks per level
 template <typename T>
 void launch_line_smooth(const Geom& g, int cc, const T* A, const T* F, const T* b, T* x, int S,
                         const int* mask, const int* list, hipStream_t st, hipEvent_t ev0,
-                        hipEvent_t ev1, bool zero_start);
+                        hipEvent_t ev1, bool zero_start, int cols = 16);
+// LDS of one k_line_sweep workgroup at most (the column walk takes deeper grids)
+constexpr size_t kLineLdsMax = 64 * 1024;
+// whether cols columns per workgroup is a tile shape k_line_sweep offers for this grid
+template <typename T>
+bool line_cols_valid(const Geom& g, int cols);
 // r = b - A x after a single forward line sweep from x = 0 (blocks towards the columns of
 // the colours swept later only; b is not read)
 template <typename T>

@@ -214,6 +214,40 @@ __device__ __forceinline__ int xcd_tile(int bx, int by, int gx) {
   return start + (bx - (xcd - c0 + kXcds) % kXcds) / kXcds;
 }
 
+// Slab order of a level's 64-position tiles for kernels whose work differs by colour.
+// Each colour's tiles are cut into kXcds slabs (positions run through k/2 slowest, so
+// slab x of every colour covers about the same depth range); XCD x takes slab x of every
+// colour, which gives every XCD the same mix of colours and keeps its neighbour gathers
+// in its own depth range.  With gridDim.x a multiple of kXcds, workgroup bx runs on XCD
+// bx % kXcds whatever its grid row.  Tile e of slab x -> (colour, tile within the colour);
+// false past the slab's end.
+__host__ __device__ __forceinline__ int slab_tiles(const Geom& g, int c, int x) {
+  const int T = (g.off[c + 1] - g.off[c]) / kTile;
+  return ((x + 1) * T) / kXcds - (x * T) / kXcds;
+}
+__device__ __forceinline__ bool slab_tile(const Geom& g, int x, int e, int& col, int& tile) {
+  for (int c = 0; c < 8; ++c) {
+    const int n = slab_tiles(g, c, x);
+    if (e < n) {
+      col = c;
+      tile = (x * ((g.off[c + 1] - g.off[c]) / kTile)) / kXcds + e;
+      return true;
+    }
+    e -= n;
+  }
+  return false;
+}
+// workgroups of kBlock threads along x for a launch in slab order
+inline int slab_blocks(const Geom& g) {
+  int most = 0;
+  for (int x = 0; x < kXcds; ++x) {
+    int n = 0;
+    for (int c = 0; c < 8; ++c) n += slab_tiles(g, c, x);
+    most = n > most ? n : most;
+  }
+  return kXcds * ceil_div(most, kBlock / kTile);
+}
+
 // salt Dirichlet vertex (closed top patch: c = 1; bottom: c = 0)
 __device__ __forceinline__ bool is_cdir(const Geom& g, int i, int j, int k, double& value) {
   if (k == g.nz - 1) { value = 0.0; return true; }

@@ -154,21 +154,22 @@ __global__ __launch_bounds__(64) void k_line_smooth(Geom g, int cc, const T* A_a
 }
 
 // ---------------------------------------------------------------------------
-// The same sweep with the work split by what depends on what: a workgroup takes kLineCols
+// The same sweep with the work split by what depends on what: a workgroup takes COLS
 // consecutive columns of colour cc.  Phase 1 (all 4 waves, every (column, k) at once):
 // r_k = b_k - (the other columns' couplings) A x, then e_k = M_k^{-1} r_k, G_k = M_k^{-1} L_k
 // and C_k go to LDS.  Phase 2 (one lane per column): the recurrences d_k = e_k - G_k d_{k-1}
 // (downwards) and x_k = d_k - C_k x_{k+1} (upwards, written to x), which touch LDS only.  The
-// rows of one k-parity share a vertex colour, so each wave takes 4 rows of one parity
-// (k, k + 2, k + 4, k + 6) and its neighbour colours stay wave-uniform.  The per-thread
-// column walk above serialises the neighbour gathers of a whole column in one lane, which
-// leaves the GPU idle when few samples are active.
+// rows of one k-parity share a vertex colour, so each wave takes 64 / COLS rows of one
+// parity (k, k + 2, ...) and its neighbour colours stay wave-uniform.  COLS (8, 16 or 32)
+// trades the LDS of a workgroup (10 values per row and column) against the rows a wave
+// gathers at once; the autotuner picks it per level.  The per-thread column walk above
+// serialises the neighbour gathers of a whole column in one lane, which leaves the GPU
+// idle when few samples are active.
 // ---------------------------------------------------------------------------
-constexpr int kLineCols = 16;          // columns per workgroup
-constexpr int kLineThreads = 256;      // 4 waves; a wave covers 16 columns x 4 rows
+constexpr int kLineThreads = 256;      // 4 waves
 constexpr int kLineVals = 10;          // per (row, column) in LDS: e (2), G (4), C (4)
 
-template <typename T, bool NT, int ZC>
+template <typename T, bool NT, int ZC, int COLS>
 __global__ __launch_bounds__(kLineThreads) void k_line_sweep(Geom g, int cc, const T* A_all,
                                                              const T* F_all, const T* b_all,
                                                              T* x_all, const int* mask,
@@ -179,7 +180,8 @@ __global__ __launch_bounds__(kLineThreads) void k_line_sweep(Geom g, int cc, con
   const int s = list ? list[blockIdx.y] : blockIdx.y;
   if (mask && !mask[s]) return;
   const int mx = g.mx[cc], ncol = mx * g.my[cc];
-  const int q0 = xcd_tile(blockIdx.x, blockIdx.y, gridDim.x) * kLineCols;
+  constexpr int RPW = 64 / COLS;  // rows per wave
+  const int q0 = xcd_tile(blockIdx.x, blockIdx.y, gridDim.x) * COLS;
   const int nz = g.nz;
   const size_t Np = g.off[8];
   const T* A = A_all + (size_t)s * kPlanes * Np;
@@ -187,15 +189,15 @@ __global__ __launch_bounds__(kLineThreads) void k_line_sweep(Geom g, int cc, con
   const T2* b = reinterpret_cast<const T2*>(b_all + (size_t)s * 2 * Np);
   T2* x = reinterpret_cast<T2*>(x_all + (size_t)s * 2 * Np);
   // LDS, value-major so that the lanes of a row read consecutive words: [value][k][column]
-  auto L_at = [&](int v, int k, int c) -> T& { return lds[((size_t)v * nz + k) * kLineCols + c]; };
+  auto L_at = [&](int v, int k, int c) -> T& { return lds[((size_t)v * nz + k) * COLS + c]; };
   // the wave index as a scalar, so that the rows' colour is known to be wave-uniform
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int cl = lane & (kLineCols - 1), rsub = lane >> 4;  // column, row within the wave
+  const int cl = lane % COLS, rsub = lane / COLS;  // column, row within the wave
   const int n_even = (nz + 1) / 2, n_odd = nz / 2;
-  const int g_even = (n_even + 3) / 4, g_odd = (n_odd + 3) / 4;  // groups of 4 rows
+  const int g_even = (n_even + RPW - 1) / RPW, g_odd = (n_odd + RPW - 1) / RPW;  // row groups
   for (int grp = wave; grp < g_even + g_odd; grp += kLineThreads / 64) {
     const int par = grp < g_even ? 0 : 1;
-    const int m = 4 * (par ? grp - g_even : grp) + rsub;
+    const int m = RPW * (par ? grp - g_even : grp) + rsub;
     const int k = par + 2 * m;
     const int q = q0 + cl;
     if (k >= nz || q >= ncol) continue;
@@ -237,7 +239,7 @@ __global__ __launch_bounds__(kLineThreads) void k_line_sweep(Geom g, int cc, con
     L_at(9, k, cl) = c.a11;
   }
   __syncthreads();
-  if (threadIdx.x >= kLineCols) return;
+  if (threadIdx.x >= COLS) return;
   const int q = q0 + threadIdx.x;
   if (q >= ncol) return;
   const int c = threadIdx.x;
@@ -263,24 +265,36 @@ __global__ __launch_bounds__(kLineThreads) void k_line_sweep(Geom g, int cc, con
   }
 }
 
-template <typename T, bool NT>
-auto line_sweep_kernel(int cc, bool zero_start) {
+template <typename T, bool NT, int COLS>
+auto line_sweep_kernel_c(int cc, bool zero_start) {
   if (zero_start) {
     switch (cc) {
-      case 0: return k_line_sweep<T, NT, 0>;
-      case 1: return k_line_sweep<T, NT, 1>;
-      case 2: return k_line_sweep<T, NT, 2>;
-      default: return k_line_sweep<T, NT, 3>;
+      case 0: return k_line_sweep<T, NT, 0, COLS>;
+      case 1: return k_line_sweep<T, NT, 1, COLS>;
+      case 2: return k_line_sweep<T, NT, 2, COLS>;
+      default: return k_line_sweep<T, NT, 3, COLS>;
     }
   }
-  return k_line_sweep<T, NT, -1>;
+  return k_line_sweep<T, NT, -1, COLS>;
 }
 
-// LDS of one workgroup of k_line_sweep (the column walk is used beyond this size)
-constexpr size_t kLineLdsMax = 64 * 1024;
+template <typename T, bool NT>
+auto line_sweep_kernel(int cc, bool zero_start, int cols) {
+  switch (cols) {
+    case 8: return line_sweep_kernel_c<T, NT, 8>(cc, zero_start);
+    case 32: return line_sweep_kernel_c<T, NT, 32>(cc, zero_start);
+    default: return line_sweep_kernel_c<T, NT, 16>(cc, zero_start);
+  }
+}
+
 template <typename T>
-size_t line_sweep_lds(const Geom& g) {
-  return (size_t)kLineVals * g.nz * kLineCols * sizeof(T);
+size_t line_sweep_lds(const Geom& g, int cols) {
+  return (size_t)kLineVals * g.nz * cols * sizeof(T);
+}
+
+template <typename T>
+bool line_cols_valid(const Geom& g, int cols) {
+  return (cols == 8 || cols == 16 || cols == 32) && line_sweep_lds<T>(g, cols) <= kLineLdsMax;
 }
 
 template <typename T, bool NT>
@@ -303,15 +317,16 @@ constexpr double kLineCachedBytes = 128.0 * 1024 * 1024;
 template <typename T>
 void launch_line_smooth(const Geom& g, int cc, const T* A, const T* F, const T* b, T* x, int S,
                         const int* mask, const int* list, hipStream_t st, hipEvent_t ev0,
-                        hipEvent_t ev1, bool zero_start) {
+                        hipEvent_t ev1, bool zero_start, int cols) {
   const int n = g.mx[cc] * g.my[cc];
   if (n <= 0) return;
   const bool nt = (double)S * kPlanes * g.off[8] * sizeof(T) > kLineCachedBytes;
-  const size_t lds = line_sweep_lds<T>(g);
+  if (!line_cols_valid<T>(g, cols)) cols = 16;
+  const size_t lds = line_sweep_lds<T>(g, cols);
   if (lds <= kLineLdsMax) {
-    dim3 grid(ceil_div(n, kLineCols), S);
-    auto kern = nt ? line_sweep_kernel<T, true>(cc, zero_start)
-                   : line_sweep_kernel<T, false>(cc, zero_start);
+    dim3 grid(ceil_div(n, cols), S);
+    auto kern = nt ? line_sweep_kernel<T, true>(cc, zero_start, cols)
+                   : line_sweep_kernel<T, false>(cc, zero_start, cols);
     if (ev0)
       hipExtLaunchKernelGGL(kern, grid, dim3(kLineThreads), lds, st, ev0, ev1, 0, g, cc, A, F, b, x,
                             mask, list);
@@ -370,10 +385,18 @@ __global__ __launch_bounds__(kBlock) void k_line_residual_zs(Geom g, const T* A_
   using T2 = typename V2<T>::type;
   const int s = list ? list[blockIdx.y] : blockIdx.y;
   if (mask && !mask[s]) return;
-  const int t = xcd_tile(blockIdx.x, blockIdx.y, gridDim.x) * kBlock + threadIdx.x;
-  if (t >= g.off[8]) return;
-  int col, i, j, k;
-  if (!colour_decode_wave(g, t, col, i, j, k)) return;
+  // slab order: the colours' work differs (24, 18, 6, 0 blocks for column colours 0-3),
+  // so every XCD takes the same share of each colour
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int col, tile;
+  if (!slab_tile(g, blockIdx.x % kXcds, (blockIdx.x / kXcds) * (kBlock / kTile) + wave, col,
+                 tile))
+    return;
+  const int place = tile * kTile + (threadIdx.x & 63);
+  if (place >= g.cnt[col]) return;
+  const int t = g.off[col] + place;
+  int i, j, k;
+  colour_decode_in(g, col, place, i, j, k);
   const size_t Np = g.off[8];
   const T* A = A_all + (size_t)s * kPlanes * Np;
   const T* x = x_all + (size_t)s * 2 * Np;
@@ -394,7 +417,7 @@ __global__ __launch_bounds__(kBlock) void k_line_residual_zs(Geom g, const T* A_
 template <typename T>
 void launch_line_residual_zs(const Geom& g, const T* A, const T* x, T* r, int S, const int* mask,
                              const int* list, hipStream_t st) {
-  dim3 grid(ceil_div(g.off[8], kBlock), S);
+  dim3 grid(slab_blocks(g), S);
   const bool nt = (double)S * kPlanes * g.off[8] * sizeof(T) > kLineCachedBytes;
   auto kern = nt ? k_line_residual_zs<T, true> : k_line_residual_zs<T, false>;
   hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, st, g, A, x, r, mask, list);
@@ -404,7 +427,8 @@ void launch_line_residual_zs(const Geom& g, const T* A, const T* x, T* r, int S,
   template void launch_line_factor<T>(const Geom&, const T*, T*, int, const int*, hipStream_t);  \
   template void launch_line_smooth<T>(const Geom&, int, const T*, const T*, const T*, T*, int,   \
                                       const int*, const int*, hipStream_t, hipEvent_t,           \
-                                      hipEvent_t, bool);                                         \
+                                      hipEvent_t, bool, int);                                    \
+  template bool line_cols_valid<T>(const Geom&, int);                                            \
   template void launch_line_residual_zs<T>(const Geom&, const T*, const T*, T*, int,            \
                                            const int*, const int*, hipStream_t);
 EDF_LINE_INST(double)

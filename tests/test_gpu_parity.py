@@ -692,3 +692,38 @@ def test_sample_failure_is_reported_and_left_out_of_moments():
     c0 = stats.inject(pb.get_state(0)[..., 1], (9, 9, 3))
     assert np.abs(mean - c0).max() < 1e-15 and np.abs(var).max() < 1e-30
     pb.destroy()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_line_tile_shapes_give_the_same_vcycle(precision, tmp_path):
+    """The line sweep's tile shapes (8, 16, 32 columns per workgroup) compute every column
+    the same way: one V-cycle gives bitwise the same output with each shape.  Invalid
+    shapes are rejected with nothing changed, and an autotuning stored in a JSON cache is
+    applied again by a second problem of the same key."""
+    from paper_1906_01632_amd import EDFError
+    phys = synth.physics(2)
+    groups = [(33, 33, 9, 4, 3)]
+    b = np.random.default_rng(5).standard_normal((3, 9, 33, 33, 2))
+    b[..., 1][:, -1] = 0.0
+    pb = _problem(phys, groups, precision=precision)
+    pb.set_parameters(_xi(2, 3, seed=4))
+    pb.set_tuning(0, 3)  # levels 0-2 swept by their own launches
+    ys = {}
+    for c in (8, 16, 32):
+        pb.set_line_tiles(0, [c, c, c, 0])
+        assert pb.line_tiles(0) == [c, c, c, 0]
+        ys[c] = pb.apply_vcycle(0, DT, b)
+    assert np.array_equal(ys[8], ys[16]) and np.array_equal(ys[32], ys[16])
+    for bad in ([12, 16, 16, 0], [16, 16, 16, 8]):
+        with pytest.raises(EDFError):
+            pb.set_line_tiles(0, bad)
+    assert pb.line_tiles(0) == [32, 32, 32, 0]
+    cache = str(tmp_path / "tuning.json")
+    assert pb.autotune(DT, cache=cache) is True
+    tuned = (pb.tuning(0)[0], pb.line_tiles(0))
+    pb.destroy()
+    pb2 = _problem(phys, groups, precision=precision)
+    pb2.set_parameters(_xi(2, 3, seed=4))
+    assert pb2.autotune(DT, cache=cache) is False
+    assert (pb2.tuning(0)[0], pb2.line_tiles(0)) == tuned
+    pb2.destroy()
