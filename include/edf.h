@@ -118,7 +118,8 @@ typedef struct {
                            /* sub-steps, h = 1..dt_max_halvings (0: no retry)       */
   int32_t forcing;         /* 0: every Newton system solved to lin_rtol; 1: to the  */
                            /* Eisenstat-Walker forcing term (choice 2, gamma 0.9,   */
-                           /* at most 0.1, at least lin_rtol)                       */
+                           /* 0.5 at the first iteration and at most 0.5, at least  */
+                           /* lin_rtol)                                             */
   int32_t concurrent_groups; /* 0: edf_step advances the groups one after the other; */
                            /* 1: at the same time, one host thread and stream each  */
                            /* (kernels of different groups then share the GPU, which */
@@ -427,8 +428,10 @@ edf_status edf_profile(edf_problem* pb, int32_t enable, double* out);
  * (8, 16 or 32 columns per 256-thread workgroup: LDS per workgroup against rows gathered
  * per wave).  This call assembles the Newton matrices at the current states with time
  * step dt, times three V-cycles per group for every admissible first fused level, twice
- * over, and keeps the fastest (the better of its two timings counts for each); then, level
- * by level from the finest, every tile shape the level's LDS allows in the same way.
+ * over, and keeps the fastest (the better of its two timings counts for each); with
+ * concurrent_groups = 2 (merged V-cycles) the number of fused levels is chosen for all
+ * groups together (the least summed time), so that their bottoms share one launch; then,
+ * level by level from the finest, every tile shape the level's LDS allows in the same way.
  * States are not changed.  Without it (or edf_set_tuning) a group of >= 64 samples fuses
  * all levels of <= 4096 vertices, a smaller group only the coarse solve, and line sweeps
  * take 16 columns per workgroup.  EDF_ERR_STATE before edf_set_parameters, EDF_ERR_ARG

@@ -1432,7 +1432,7 @@ void set_dt(edf_problem* pb, Group& G, double dt) {
 // autotuning of the fused V-cycle bottom: with the matrices of the current state,
 // time three V-cycles for every candidate first fused level and keep the fastest
 // ---------------------------------------------------------------------------
-edf_status autotune_group(edf_problem* pb, Group& G) {
+edf_status autotune_group(edf_problem* pb, Group& G, bool fuse, bool tiles) {
   hipStream_t st = G.st;
   std::vector<int> all(G.S, 1);
   edf_status e;
@@ -1447,11 +1447,11 @@ edf_status autotune_group(edf_problem* pb, Group& G) {
   const bool was_on = G.prof_on;
   G.prof_on = false;
   G.n_active = G.S;
-  G.tune_ms.assign(G.L, -1.0);
+  if (fuse) G.tune_ms.assign(G.L, -1.0);
   // two passes over the candidates, each timing three V-cycles after a warm-up one; a
   // candidate's time is the smaller of its two, so that a slow first pass (caches,
   // clocks) does not decide
-  for (int pass = 0; pass < 2; ++pass)
+  for (int pass = 0; pass < 2 && fuse; ++pass)
     for (int l0 = first_fusable(G); l0 < G.L; ++l0) {
       G.fuse_from = l0;
       precondition(pb, G, G.kp, G.kph, G.nmask);  // warm-up
@@ -1464,14 +1464,18 @@ edf_status autotune_group(edf_problem* pb, Group& G) {
       if (G.tune_ms[l0] < 0 || ms / 3.0 < G.tune_ms[l0]) G.tune_ms[l0] = ms / 3.0;
     }
   int best_l0 = G.L - 1;
-  for (int l0 = first_fusable(G); l0 < G.L; ++l0)
-    if (G.tune_ms[l0] < G.tune_ms[best_l0]) best_l0 = l0;
-  G.fuse_from = best_l0;
+  if (fuse) {
+    for (int l0 = first_fusable(G); l0 < G.L; ++l0)
+      if (G.tune_ms[l0] < G.tune_ms[best_l0]) best_l0 = l0;
+    G.fuse_from = best_l0;
+  } else {
+    best_l0 = first_fused_level(G);
+  }
   // tile shape of the line sweep on every level swept by its own launches, finest first
   // (coordinate descent: the other levels keep their current choice); each candidate's
   // time is the better of two timings of three V-cycles
   const bool mx = mixed(pb);
-  for (int l = 0; l < best_l0; ++l) {
+  for (int l = 0; l < best_l0 && tiles; ++l) {
     Level& L = G.lv[l];
     if (!L.LF) continue;
     double best = -1.0;
@@ -1509,6 +1513,7 @@ edf_status autotune_group(edf_problem* pb, Group& G) {
 // sample converged to an admissible state (0 <= c <= 1 up to kRangeTol).
 // ---------------------------------------------------------------------------
 constexpr double kRangeTol = 0.05;      // admissible overshoot of c beyond [0, 1]
+constexpr double kEtaMax = 0.5;         // largest Eisenstat-Walker forcing term
 constexpr double kDivergence = 1e4;     // give up when ||F~|| grows by this factor
 constexpr int kSlowIts = 8;             // give up after this many iterations ...
 constexpr double kSlowDrop = 1e-2;      // ... without this reduction of ||F~||
@@ -1582,21 +1587,21 @@ edf_status newton_solve(edf_problem* pb, Group& G, const std::vector<int>& run,
     }
     if (!any) break;
     // relative tolerance of this Newton system: fixed, or the Eisenstat-Walker forcing
-    // term (choice 2: 0.9 (r_k / r_{k-1})^2, safeguarded, at most 0.1), never asking for
-    // more than half of what is left to the Newton target
+    // term (choice 2: 0.9 (r_k / r_{k-1})^2, safeguarded, at most kEtaMax), never asking
+    // for more than half of what is left to the Newton target
     for (int s = 0; s < S; ++s) {
       if (!nm[s] || o.forcing == 0) continue;
-      double et = 0.1;
+      double et = kEtaMax;
       if (it > 0) {
         const double q = r[s] / r_prev[s];
         et = 0.9 * q * q;
         const double prev = 0.9 * eta[s] * eta[s];
         if (prev > 0.1) et = std::max(et, prev);
       }
-      et = std::min(et, 0.1);
+      et = std::min(et, kEtaMax);
       const double target = std::max(o.newton_rtol * r0[s], o.newton_atol);
       et = std::max(et, 0.5 * target / r[s]);
-      eta[s] = std::max(std::min(et, 0.1), o.lin_rtol);
+      eta[s] = std::max(std::min(et, kEtaMax), o.lin_rtol);
     }
     for (int s = 0; s < S; ++s) r_prev[s] = r[s];
     if ((e = upload_dbls(pb, G, G.eta, eta))) return e;
@@ -2909,9 +2914,31 @@ edf_status edf_autotune(edf_problem* pb, double dt) {
   if (e) return e;
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(pb, EDF_ERR_ARG, "dt must be positive");
   EDF_TRY(hipStreamSynchronize(pb->st));
+  const bool joint = pb->opts.concurrent_groups == 2 && pb->groups.size() > 1;
   for (Group& G : pb->groups) {
     set_dt(pb, G, dt);
-    if ((e = autotune_group(pb, G))) return fail(pb, e, "autotuning failed");
+    if ((e = autotune_group(pb, G, true, !joint))) return fail(pb, e, "autotuning failed");
+  }
+  if (joint) {
+    // merged V-cycles share a bottom launch only between groups that fuse the same
+    // grids: one number d of fused levels for all groups (their coarsest grids are the
+    // same whenever their hierarchies line up), the d with the least summed time
+    int dmax = 1 << 30;
+    for (Group& G : pb->groups) dmax = std::min(dmax, G.L - first_fusable(G));
+    int best_d = 1;
+    double best = -1.0;
+    for (int d = 1; d <= dmax; ++d) {
+      double t = 0.0;
+      for (Group& G : pb->groups) t += G.tune_ms[G.L - d];
+      if (best < 0 || t < best) {
+        best = t;
+        best_d = d;
+      }
+    }
+    for (Group& G : pb->groups) {
+      G.fuse_from = G.L - best_d;
+      if ((e = autotune_group(pb, G, false, true))) return fail(pb, e, "autotuning failed");
+    }
   }
   return EDF_OK;
 }

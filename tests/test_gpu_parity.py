@@ -727,3 +727,28 @@ def test_line_tile_shapes_give_the_same_vcycle(precision, tmp_path):
     assert pb2.autotune(DT, cache=cache) is False
     assert (pb2.tuning(0)[0], pb2.line_tiles(0)) == tuned
     pb2.destroy()
+
+
+def test_joint_tuning_gives_groups_one_fused_bottom():
+    """With merged V-cycles (concurrent_groups = 2) the autotuner fuses the same number of
+    levels in every group (the groups' coarse grids are the same), so that their bottoms
+    share one launch; the tuned problem steps to bitwise the result of the serial one."""
+    phys = synth.physics(2)
+    groups = [(17, 17, 5, 3, 3), (33, 33, 9, 4, 2)]
+    xi = _xi(2, 5, seed=31)
+    pb = _problem(phys, groups, concurrent_groups=2, check_every=1)
+    pb.set_parameters(xi)
+    pb.autotune(DT)
+    fused = [g[3] - pb.tuning(i)[0] for i, g in enumerate(groups)]
+    assert fused[0] == fused[1], fused
+    pb.step(DT)
+    got = [pb.get_state(s) for s in range(5)]
+    pb.destroy()
+    ref = _problem(phys, groups, check_every=1)
+    ref.set_parameters(xi)
+    for i, g in enumerate(groups):
+        ref.set_tuning(i, g[3] - fused[i])
+    ref.step(DT)
+    for s in range(5):
+        assert np.array_equal(ref.get_state(s), got[s]), s
+    ref.destroy()
