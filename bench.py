@@ -466,7 +466,7 @@ def make_problem(args, wl, phys, groups, prec, log_tuning=True):
                 graph_vcycle=int(args.graph), substep_memory=int(args.substep_memory),
                 smoother=int(args.smoother), matrix_free=int(args.matrix_free),
                 predictor=int(args.predictor) if not args.adjoint else 0,
-                nu_pre=args.nu[0], nu_post=args.nu[1])
+                nu_pre=args.nu[0], nu_post=args.nu[1], lag_preconditioner=args.lag_preconditioner)
     t = time.perf_counter()
     pb = Problem(phys, groups, opts)
     pb.set_parameters(wl.xi)
@@ -642,6 +642,9 @@ def main():
                          "previous step")
     ap.add_argument("--nu", type=int, nargs=2, default=[1, 1], metavar=("PRE", "POST"),
                     help="smoothing sweeps before and after the coarse correction")
+    ap.add_argument("--lag-preconditioner", type=int, default=0, choices=[0, 1],
+                    help="1: assemble the V-cycle's matrices only at the first Newton iteration "
+                         "of each (sub-)step attempt")
     ap.add_argument("--predictor", type=int, default=1, choices=[0, 1],
                     help="1: Newton starts a step from the extrapolation 2 u^n - u^{n-1} where "
                          "its defect is smaller (same stopping test)")
@@ -793,6 +796,7 @@ def main():
                    "substep_memory": bool(args.substep_memory),
                    "newton_predictor": bool(args.predictor),
                    "smoothing_sweeps": list(args.nu),
+                   "lagged_preconditioner": bool(args.lag_preconditioner),
                    "fused_bottom_from_level": tuning,
                    "line_sweep_columns_per_workgroup": tiles,
                    "concurrent_groups": args.concurrent_groups,

@@ -168,6 +168,14 @@ typedef struct {
                            /* the same tolerance with fewer Newton iterations.      */
                            /* Not used while edf_solve records a trajectory (the    */
                            /* adjoint recomputes those steps from checkpoints)      */
+  int32_t lag_preconditioner; /* 0: the V-cycle's matrices (every level) and their    */
+                           /* block inverses, line factors and coarse inverse are   */
+                           /* re-assembled at every Newton iteration (Section 5.1);  */
+                           /* 1: only at the first Newton iteration of each attempt */
+                           /* of a (sub-)step, then kept (the outer products stay    */
+                           /* the exact Jacobian at the current iterate, so Newton  */
+                           /* and its result are unchanged; only the preconditioner */
+                           /* lags)                                                  */
 } edf_solver_opts;
 
 /* Per-sample result of a step.  Counters named *_total run over every step since the

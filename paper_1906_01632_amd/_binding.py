@@ -48,7 +48,8 @@ class SolverOpts(C.Structure):
                 ("check_every", C.c_int32), ("dt_max_halvings", C.c_int32),
                 ("forcing", C.c_int32), ("concurrent_groups", C.c_int32),
                 ("graph_vcycle", C.c_int32), ("substep_memory", C.c_int32),
-                ("smoother", C.c_int32), ("matrix_free", C.c_int32), ("predictor", C.c_int32)]
+                ("smoother", C.c_int32), ("matrix_free", C.c_int32), ("predictor", C.c_int32),
+                ("lag_preconditioner", C.c_int32)]
 
 
 class StepStats(C.Structure):
@@ -142,7 +143,8 @@ def default_options(**over) -> dict:
     o = dict(newton_rtol=1e-10, newton_atol=0.0, lin_rtol=1e-6, newton_max_it=20,
              ls_max_halvings=5, lin_max_it=200, nu_pre=1, nu_post=1, precision=PREC_F64,
              check_every=4, dt_max_halvings=4, forcing=0, concurrent_groups=0, graph_vcycle=0,
-             substep_memory=0, smoother=1, matrix_free=1, predictor=0)
+             substep_memory=0, smoother=1, matrix_free=1, predictor=0,
+             lag_preconditioner=0)
     o.update(over)
     return o
 

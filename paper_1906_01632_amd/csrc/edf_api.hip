@@ -1606,7 +1606,8 @@ edf_status newton_solve(edf_problem* pb, Group& G, const std::vector<int>& run,
     for (int s = 0; s < S; ++s) r_prev[s] = r[s];
     if ((e = upload_dbls(pb, G, G.eta, eta))) return e;
     if ((e = upload_ints(pb, G, G.nmask, nm))) return e;
-    if ((e = assemble_all(pb, G, G.nmask, G.dts))) return e;
+    if (it == 0 || !o.lag_preconditioner)
+      if ((e = assemble_all(pb, G, G.nmask, G.dts))) return e;
     if ((e = bicgstab(pb, G))) return e;
     // BiCGStab statistics and the size of the Newton update
     EDF_TRY(hipMemcpyAsync(G.h_ks, G.ks, S * sizeof(KrylovScalars), hipMemcpyDeviceToHost, st));
@@ -2230,6 +2231,8 @@ edf_status edf_create_problem(const edf_physics* phys, const edf_group_desc* gro
       opts->ls_max_halvings < 0 || !(opts->lin_rtol > 0) || !(opts->newton_rtol >= 0))
     return bad("invalid solver options");
   if (opts->predictor != 0 && opts->predictor != 1) return bad("predictor must be 0 or 1");
+  if (opts->lag_preconditioner != 0 && opts->lag_preconditioner != 1)
+    return bad("lag_preconditioner must be 0 or 1");
   if (opts->matrix_free != 0 && opts->matrix_free != 1) return bad("matrix_free must be 0 or 1");
   if (opts->graph_vcycle != 0 && opts->graph_vcycle != 1)
     return bad("graph_vcycle must be 0 or 1");

@@ -260,3 +260,26 @@ def test_extrapolated_start_reaches_the_oracle_root_in_fewer_iterations():
             got = states1[n][s]
             errs = [_rel(got[..., f], u[..., f]) for f in range(2)]
             assert max(errs) < 1e-10, (s, n, errs)
+
+
+def test_lagged_preconditioner_reaches_the_oracle_root():
+    """opts.lag_preconditioner: the V-cycle matrices are assembled once per (sub-)step
+    attempt and kept through its Newton iterations; the outer products stay the exact
+    Jacobian, so 4 steps stay within 1e-10 of the oracle's states (inexact Newton as in
+    the benchmark, Newton tolerance 1e-13)."""
+    nx, ny, nz = 17, 17, 5
+    phys = synth.physics(2)
+    xi = np.random.default_rng(22).uniform(-1, 1, (2, 4))
+    box = elder.Box(nx, ny, nz, phys)
+    pb = _problem(phys, [(nx, ny, nz, 3, 2)], lag_preconditioner=1, forcing=1)
+    pb.set_parameters(xi)
+    us = [synth.initial_state(nx, ny, nz, phys) for _ in range(2)]
+    for n in range(4):
+        st = pb.step(DT)
+        for s in range(2):
+            assert st[s]["status"] == 0 and st[s]["substeps"] == 1
+            us[s] = newton.newton_solve(box, elder.coefficients(box, xi[s]), us[s], DT)
+            got = pb.get_state(s)
+            errs = [_rel(got[..., f], us[s][..., f]) for f in range(2)]
+            assert max(errs) < 1e-10, (n, s, errs)
+    pb.destroy()
