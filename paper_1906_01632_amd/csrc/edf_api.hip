@@ -1010,7 +1010,16 @@ void vcycle_merged(edf_problem* pb, const std::vector<MergeReq*>& R) {
   for (MergeReq* r : W)
     plain = plain || r->G->transposed || (std::is_same<T, float>::value && r->G->lv[0].A16);
   if (plain) {
-    for (MergeReq* r : W) vcycle<T>(pb, *r->G, r->in, r->out, r->mask);
+    for (MergeReq* r : W) {
+      Group& G = *r->G;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      const double bytes =
+          vcycle_bytes(G, sizeof(T), pb->opts.nu_pre, pb->opts.nu_post, first_fused_level(G)) *
+          G.n_active;
+      if (prof_pair(G, e0, e1, bytes, 1)) (void)hipEventRecord(e0, G.st);
+      vcycle<T>(pb, G, r->in, r->out, r->mask);
+      if (e1) (void)hipEventRecord(e1, G.st);
+    }
     return;
   }
   Group& G0 = *W[0]->G;
