@@ -249,3 +249,20 @@ def test_adjoint_of_the_65_cubed_lattice_batch_matches_finite_differences():
             assert abs(J[s] - Jt[q]) <= 1e-8 * abs(Jt[q])
             assert np.abs(dJ[s] - gt[q]).max() <= 1e-4 * np.abs(gt[q]).max()
     assert checked >= 6  # of the 8 components of the two samples
+
+
+def test_merged_groups_give_the_serial_gradient():
+    """With merged V-cycles (concurrent_groups = 2) the forward steps of two nested groups
+    share launches and the adjoint's transposed solves run group by group: J and dJ/dxi
+    are bitwise those of the serial mode."""
+    phys = synth.physics(2)
+    groups = [(9, 9, 3, 2, 2), (17, 17, 5, 3, 2)]
+    xi = np.random.default_rng(7).uniform(-0.6, 0.6, (4, 4))
+    out = {}
+    for conc in (0, 2):
+        pb = _problem(phys, groups, concurrent_groups=conc, check_every=1)
+        pb.set_parameters(xi)
+        out[conc] = pb.gradient(BOX_UPPER, DT, 3, checkpoint_every=2)
+        pb.destroy()
+    assert np.array_equal(out[2][0], out[0][0])
+    assert np.array_equal(out[2][1], out[0][1])
