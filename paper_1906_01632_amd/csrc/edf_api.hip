@@ -444,7 +444,7 @@ edf_status alloc_group(edf_problem* pb, Group& G) {
     if (!coarsest) {
       if ((s = take(pb, G, l, kPoolDinv, 4 * Np * tsz, &q))) return s;
       L.Dinv = q;
-      if (pb->opts.smoother == 1 && !(l == 0 && f16_finest(pb, G))) {
+      if (pb->opts.smoother == 1) {
         if ((s = take(pb, G, l, kPoolLF, kLineFactors * Np * tsz, &q))) return s;
         L.LF = q;
       }
@@ -539,7 +539,9 @@ edf_status find_sample(edf_problem* pb, int sample, Group** G, int* local) {
 // the vertical-line smoother's column factors of a level's V-cycle matrix (if it has any)
 void line_factors(Level& L, bool mixed_vcycle, int S, const int* mask, hipStream_t st) {
   if (!L.LF) return;
-  if (mixed_vcycle)
+  if (L.A16)  // FP16 finest level: the columns of the scaled matrix D^{-1} A
+    launch_line_factor_f16(L.g, L.A16, (float*)L.LF, S, mask, st);
+  else if (mixed_vcycle)
     launch_line_factor<float>(L.g, L.A32, (float*)L.LF, S, mask, st);
   else
     launch_line_factor<double>(L.g, L.AV64 ? L.AV64 : L.A64, (double*)L.LF, S, mask, st);
@@ -667,6 +669,15 @@ double line_sweep_bytes(int cc, bool zero_start, size_t tsz) {
 double line_residual_bytes(int cc, size_t tsz) {
   return (4.0 * (24 - line_zero_start_blocks(cc)) + 2) * tsz;
 }
+// FP16-stored finest level: 8 bytes per 2x2 block, the FP32 factors, D^{-1} b and x (FP32);
+// its residual also reads the FP32 diagonal blocks D to unscale
+double line_sweep_bytes_f16(int cc, bool zero_start) {
+  const int nb = zero_start ? line_zero_start_blocks(cc) : 24;
+  return 8.0 * (nb + 1) + (8 + 2 + 6) * 4.0;
+}
+double line_residual_bytes_f16(int cc) {
+  return 8.0 * (24 - line_zero_start_blocks(cc)) + (4 + 2) * 4.0;
+}
 static_assert(line_zero_start_blocks(0) == 0 && line_zero_start_blocks(1) == 6 &&
                   line_zero_start_blocks(2) == 18 && line_zero_start_blocks(3) == 24,
               "each coupling between columns is read from one of its two ends");
@@ -683,11 +694,18 @@ double vcycle_bytes(const Group& G, size_t tsz, int nu1, int nu2, int l0) {
     const Geom& g = G.lv[l].g;
     const bool h = l == 0 && G.lv[0].A16;
     if (G.lv[l].LF && l < l0) {  // vertical-line smoothing
+      auto sweep = [&](int cc, bool zs) {
+        return h ? line_sweep_bytes_f16(cc, zs) : line_sweep_bytes(cc, zs, tsz);
+      };
       for (int cc = 0; cc < 4; ++cc) {
         const double nv = (double)g.mx[cc] * g.my[cc] * g.nz;
-        b += nv * ((nu1 + nu2) * line_sweep_bytes(cc, false, tsz));
-        if (nu1 > 0) b += nv * (line_sweep_bytes(cc, true, tsz) - line_sweep_bytes(cc, false, tsz));
-        b += nv * (zs_res ? line_residual_bytes(cc, tsz) : (kPlanes + 12.0) * tsz);
+        b += nv * ((nu1 + nu2) * sweep(cc, false));
+        if (nu1 > 0) b += nv * (sweep(cc, true) - sweep(cc, false));
+        if (h)  // the residual reads the FP16 blocks, D, D^{-1} b and x (general) or the
+                // blocks towards the later columns and D (after one sweep from zero)
+          b += nv * (zs_res ? line_residual_bytes_f16(cc) : (26 * 4 * 2 + 4 * 4 + 6 * 4 + 2 * 4));
+        else
+          b += nv * (zs_res ? line_residual_bytes(cc, tsz) : (kPlanes + 12.0) * tsz);
       }
       continue;
     }
@@ -839,6 +857,14 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (line(l)) {
       const double nv = (double)L.g.mx[c] * L.g.my[c] * L.g.nz;
+      if constexpr (std::is_same<T, float>::value) {
+        if (l == 0 && h0) {  // FP16 blocks of the scaled system, b = D^{-1} b
+          prof_pair(G, e0, e1, nv * G.n_active * line_sweep_bytes_f16(c, zs), 0);
+          launch_line_smooth_f16(L.g, c, L.A16, (const float*)L.LF, (const float*)b, (float*)x, S,
+                                 mask, list, st, e0, e1, zs, L.line_cols);
+          return;
+        }
+      }
       prof_pair(G, e0, e1, nv * G.n_active * line_sweep_bytes(c, zs, sizeof(T)), 0);
       launch_line_smooth<T>(L.g, c, stencil<T>(L), (const T*)L.LF, b, x, S, mask, list, st, e0,
                             e1, zs, L.line_cols);
@@ -857,8 +883,12 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
   auto residual = [&](int l, const Level& L, const T* b, const T* x) {
     if constexpr (std::is_same<T, float>::value) {
       if (l == 0 && h0) {
-        launch_residual_f16(L.g, L.A16, (const float*)L.Dinv, (const float*)b, (const float*)x,
-                            (float*)L.r, S, mask, list, st, zs_res);
+        if (line(l) && zs_res)  // after one line sweep from zero: the later columns' blocks
+          launch_line_residual_zs_f16(L.g, L.A16, (const float*)L.Dinv, (const float*)x,
+                                      (float*)L.r, S, mask, list, st);
+        else  // general r = D (D^{-1} b - A16 x), or after one point sweep from zero
+          launch_residual_f16(L.g, L.A16, (const float*)L.Dinv, (const float*)b, (const float*)x,
+                              (float*)L.r, S, mask, list, st, zs_res && !line(l));
         return;
       }
     }

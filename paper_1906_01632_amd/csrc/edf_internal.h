@@ -152,6 +152,18 @@ template <typename T>
 void launch_line_smooth(const Geom& g, int cc, const T* A, const T* F, const T* b, T* x, int S,
                         const int* mask, const int* list, hipStream_t st, hipEvent_t ev0,
                         hipEvent_t ev1, bool zero_start, int cols = 16);
+// The same three for an FP16-stored finest level of the FP32 V-cycle: the matrix is
+// D^{-1} A (identity diagonal blocks) and b holds D^{-1} b; the factors (FP32) are those of
+// the scaled columns, and the residual is unscaled with the FP32 diagonal blocks D
+void launch_line_factor_f16(const Geom& g, const _Float16* A, float* F, int S, const int* mask,
+                            hipStream_t st);
+void launch_line_smooth_f16(const Geom& g, int cc, const _Float16* A, const float* F,
+                            const float* b, float* x, int S, const int* mask, const int* list,
+                            hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, bool zero_start,
+                            int cols);
+void launch_line_residual_zs_f16(const Geom& g, const _Float16* A, const float* D, const float* x,
+                                 float* r, int S, const int* mask, const int* list,
+                                 hipStream_t st);
 // LDS of one k_line_sweep workgroup at most (the column walk takes deeper grids)
 constexpr size_t kLineLdsMax = 64 * 1024;
 // whether cols columns per workgroup is a tile shape k_line_sweep offers for this grid

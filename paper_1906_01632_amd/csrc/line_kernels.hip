@@ -13,7 +13,14 @@
 // mx = g.mx[cc], my = g.my[cc]; its vertex at height k has vertex colour cc + 4 (k & 1)
 // and place q + mx my (k >> 1) in that colour (mx and my depend on the x and y parity
 // only), so for a fixed k the columns of a wave read consecutive stencil rows.
+//
+// The matrix is stored in M: the vectors' type T, or FP16 on a finest level of the
+// FP32 V-cycle (EDF_PREC_MIXED_F16).  The FP16 matrix is D^{-1} A, scaled by its
+// diagonal-block inverses (identity diagonal blocks, O(1) entries), and b holds D^{-1} b,
+// so the sweep solves the same system scaled row by row; its residual is unscaled by D.
 #include <hip/hip_ext.h>
+
+#include <type_traits>
 
 #include "fv_common.h"
 
@@ -31,8 +38,8 @@ __device__ __forceinline__ int line_pos(const Geom& g, int cc, int q, int k) {
 // block LU of each column's tridiagonal part, from the top: M_k = D_k - L_k C_{k-1},
 // C_k = M_k^{-1} U_k (C_{-1} = 0); F[0..3] = M_k^{-1}, F[4..7] = C_k, computed in FP64
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(64) void k_line_factor(Geom g, const T* A_all, T* F_all,
+template <typename M, typename T>
+__global__ __launch_bounds__(64) void k_line_factor(Geom g, const M* A_all, T* F_all,
                                                     const int* mask) {
   const int s = blockIdx.y;
   if (mask && !mask[s]) return;
@@ -40,19 +47,23 @@ __global__ __launch_bounds__(64) void k_line_factor(Geom g, const T* A_all, T* F
   const int q = blockIdx.x * 64 + threadIdx.x;
   if (q >= g.mx[cc] * g.my[cc]) return;
   const size_t Np = g.off[8];
-  const T* A = A_all + (size_t)s * kPlanes * Np;
+  const M* A = A_all + (size_t)s * kPlanes * Np;
   T* F = F_all + (size_t)s * kLineFactors * Np;
+  // the FP16 matrix is scaled by its diagonal-block inverses: its diagonal blocks are I
+  constexpr bool unit = std::is_same<M, _Float16>::value;
   double c00 = 0.0, c01 = 0.0, c10 = 0.0, c11 = 0.0;
   for (int k = 0; k < g.nz; ++k) {
     const int t = line_pos<T>(g, cc, q, k);
-    const T* a = A + sidx<T>(t, 0, kPlanes);
-    auto val = [&](int o, int e) { return (double)a[soff<T>(o * 4 + e)]; };
+    const M* a = A + sidx<M>(t, 0, kPlanes);
+    auto val = [&](int o, int e) { return (double)a[soff<M>(o * 4 + e)]; };
     const double l00 = val(kLineL, 0), l01 = val(kLineL, 1), l10 = val(kLineL, 2),
                  l11 = val(kLineL, 3);
-    const double m00 = val(kDiag, 0) - (l00 * c00 + l01 * c10);
-    const double m01 = val(kDiag, 1) - (l00 * c01 + l01 * c11);
-    const double m10 = val(kDiag, 2) - (l10 * c00 + l11 * c10);
-    const double m11 = val(kDiag, 3) - (l10 * c01 + l11 * c11);
+    const double d00 = unit ? 1.0 : val(kDiag, 0), d01 = unit ? 0.0 : val(kDiag, 1),
+                 d10 = unit ? 0.0 : val(kDiag, 2), d11 = unit ? 1.0 : val(kDiag, 3);
+    const double m00 = d00 - (l00 * c00 + l01 * c10);
+    const double m01 = d01 - (l00 * c01 + l01 * c11);
+    const double m10 = d10 - (l10 * c00 + l11 * c10);
+    const double m11 = d11 - (l10 * c01 + l11 * c11);
     const double det = m00 * m11 - m01 * m10;
     const double id = det != 0.0 ? 1.0 / det : 0.0;
     const double i00 = m11 * id, i01 = -m01 * id, i10 = -m10 * id, i11 = m00 * id;
@@ -74,10 +85,20 @@ __global__ __launch_bounds__(64) void k_line_factor(Geom g, const T* A_all, T* F
   }
 }
 
+template <typename M, typename T>
+void launch_line_factor_m(const Geom& g, const M* A, T* F, int S, const int* mask, hipStream_t st) {
+  dim3 grid(ceil_div(g.mx[0] * g.my[0], 64), S, 4);
+  hipLaunchKernelGGL((k_line_factor<M, T>), grid, dim3(64), 0, st, g, A, F, mask);
+}
+
 template <typename T>
 void launch_line_factor(const Geom& g, const T* A, T* F, int S, const int* mask, hipStream_t st) {
-  dim3 grid(ceil_div(g.mx[0] * g.my[0], 64), S, 4);
-  hipLaunchKernelGGL(k_line_factor<T>, grid, dim3(64), 0, st, g, A, F, mask);
+  launch_line_factor_m<T, T>(g, A, F, S, mask, st);
+}
+
+void launch_line_factor_f16(const Geom& g, const _Float16* A, float* F, int S, const int* mask,
+                            hipStream_t st) {
+  launch_line_factor_m<_Float16, float>(g, A, F, S, mask, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -87,8 +108,8 @@ void launch_line_factor(const Geom& g, const T* A, T* F, int S, const int* mask,
 // x_k = d_k - C_k x_{k+1}).  ZC >= 0: the first forward sweep of a level whose x is zero
 // on entry, for cc = ZC: only the columns of the colours already swept are read.
 // ---------------------------------------------------------------------------
-template <typename T, bool NT, int ZC>
-__global__ __launch_bounds__(64) void k_line_smooth(Geom g, int cc, const T* A_all,
+template <typename T, typename M, bool NT, int ZC>
+__global__ __launch_bounds__(64) void k_line_smooth(Geom g, int cc, const M* A_all,
                                                     const T* F_all, const T* b_all, T* x_all,
                                                     const int* mask, const int* list) {
   using T2 = typename V2<T>::type;
@@ -99,7 +120,7 @@ __global__ __launch_bounds__(64) void k_line_smooth(Geom g, int cc, const T* A_a
   if (q >= mx * g.my[cc]) return;
   const int i = 2 * (q % mx) + (cc & 1), j = 2 * (q / mx) + (cc >> 1);
   const size_t Np = g.off[8];
-  const T* A = A_all + (size_t)s * kPlanes * Np;
+  const M* A = A_all + (size_t)s * kPlanes * Np;
   const T* F = F_all + (size_t)s * kLineFactors * Np;
   const T2* b = reinterpret_cast<const T2*>(b_all + (size_t)s * 2 * Np);
   T2* x = reinterpret_cast<T2*>(x_all + (size_t)s * 2 * Np);
@@ -108,7 +129,7 @@ __global__ __launch_bounds__(64) void k_line_smooth(Geom g, int cc, const T* A_a
     const int col = cc + 4 * (k & 1);
     const int t = line_pos<T>(g, cc, q, k);
     const NbrMap nm = nbr_map(g, col, i, j, k);
-    const T* a = A + sidx<T>(t, 0, kPlanes);
+    const M* a = A + sidx<M>(t, 0, kPlanes);
     const T2 bv = b[t];
     T r0 = bv.x, r1 = bv.y;
 #pragma unroll
@@ -169,8 +190,8 @@ __global__ __launch_bounds__(64) void k_line_smooth(Geom g, int cc, const T* A_a
 constexpr int kLineThreads = 256;      // 4 waves
 constexpr int kLineVals = 10;          // per (row, column) in LDS: e (2), G (4), C (4)
 
-template <typename T, bool NT, int ZC, int COLS>
-__global__ __launch_bounds__(kLineThreads) void k_line_sweep(Geom g, int cc, const T* A_all,
+template <typename T, typename M, bool NT, int ZC, int COLS>
+__global__ __launch_bounds__(kLineThreads) void k_line_sweep(Geom g, int cc, const M* A_all,
                                                              const T* F_all, const T* b_all,
                                                              T* x_all, const int* mask,
                                                              const int* list) {
@@ -184,7 +205,7 @@ __global__ __launch_bounds__(kLineThreads) void k_line_sweep(Geom g, int cc, con
   const int q0 = xcd_tile(blockIdx.x, blockIdx.y, gridDim.x) * COLS;
   const int nz = g.nz;
   const size_t Np = g.off[8];
-  const T* A = A_all + (size_t)s * kPlanes * Np;
+  const M* A = A_all + (size_t)s * kPlanes * Np;
   const T* F = F_all + (size_t)s * kLineFactors * Np;
   const T2* b = reinterpret_cast<const T2*>(b_all + (size_t)s * 2 * Np);
   T2* x = reinterpret_cast<T2*>(x_all + (size_t)s * 2 * Np);
@@ -205,7 +226,7 @@ __global__ __launch_bounds__(kLineThreads) void k_line_sweep(Geom g, int cc, con
     const int col = cc + 4 * par;  // the same for the whole wave
     const int t = line_pos<T>(g, cc, q, k);
     const NbrMap nm = nbr_map(g, col, i, j, k);
-    const T* a = A + sidx<T>(t, 0, kPlanes);
+    const M* a = A + sidx<M>(t, 0, kPlanes);
     const T2 bv = b[t];
     T r0 = bv.x, r1 = bv.y;
 #pragma unroll
@@ -265,25 +286,25 @@ __global__ __launch_bounds__(kLineThreads) void k_line_sweep(Geom g, int cc, con
   }
 }
 
-template <typename T, bool NT, int COLS>
+template <typename T, typename M, bool NT, int COLS>
 auto line_sweep_kernel_c(int cc, bool zero_start) {
   if (zero_start) {
     switch (cc) {
-      case 0: return k_line_sweep<T, NT, 0, COLS>;
-      case 1: return k_line_sweep<T, NT, 1, COLS>;
-      case 2: return k_line_sweep<T, NT, 2, COLS>;
-      default: return k_line_sweep<T, NT, 3, COLS>;
+      case 0: return k_line_sweep<T, M, NT, 0, COLS>;
+      case 1: return k_line_sweep<T, M, NT, 1, COLS>;
+      case 2: return k_line_sweep<T, M, NT, 2, COLS>;
+      default: return k_line_sweep<T, M, NT, 3, COLS>;
     }
   }
-  return k_line_sweep<T, NT, -1, COLS>;
+  return k_line_sweep<T, M, NT, -1, COLS>;
 }
 
-template <typename T, bool NT>
+template <typename T, typename M, bool NT>
 auto line_sweep_kernel(int cc, bool zero_start, int cols) {
   switch (cols) {
-    case 8: return line_sweep_kernel_c<T, NT, 8>(cc, zero_start);
-    case 32: return line_sweep_kernel_c<T, NT, 32>(cc, zero_start);
-    default: return line_sweep_kernel_c<T, NT, 16>(cc, zero_start);
+    case 8: return line_sweep_kernel_c<T, M, NT, 8>(cc, zero_start);
+    case 32: return line_sweep_kernel_c<T, M, NT, 32>(cc, zero_start);
+    default: return line_sweep_kernel_c<T, M, NT, 16>(cc, zero_start);
   }
 }
 
@@ -297,36 +318,36 @@ bool line_cols_valid(const Geom& g, int cols) {
   return (cols == 8 || cols == 16 || cols == 32) && line_sweep_lds<T>(g, cols) <= kLineLdsMax;
 }
 
-template <typename T, bool NT>
+template <typename T, typename M, bool NT>
 auto line_smooth_kernel(int cc, bool zero_start) {
   if (zero_start) {
     switch (cc) {
-      case 0: return k_line_smooth<T, NT, 0>;
-      case 1: return k_line_smooth<T, NT, 1>;
-      case 2: return k_line_smooth<T, NT, 2>;
-      default: return k_line_smooth<T, NT, 3>;
+      case 0: return k_line_smooth<T, M, NT, 0>;
+      case 1: return k_line_smooth<T, M, NT, 1>;
+      case 2: return k_line_smooth<T, M, NT, 2>;
+      default: return k_line_smooth<T, M, NT, 3>;
     }
   }
-  return k_line_smooth<T, NT, -1>;
+  return k_line_smooth<T, M, NT, -1>;
 }
 
 // matrices of more than this many bytes (all samples of a level) are streamed with
 // non-temporal loads, as in the point smoother
 constexpr double kLineCachedBytes = 128.0 * 1024 * 1024;
 
-template <typename T>
-void launch_line_smooth(const Geom& g, int cc, const T* A, const T* F, const T* b, T* x, int S,
-                        const int* mask, const int* list, hipStream_t st, hipEvent_t ev0,
-                        hipEvent_t ev1, bool zero_start, int cols) {
+template <typename T, typename M>
+void launch_line_smooth_m(const Geom& g, int cc, const M* A, const T* F, const T* b, T* x, int S,
+                          const int* mask, const int* list, hipStream_t st, hipEvent_t ev0,
+                          hipEvent_t ev1, bool zero_start, int cols) {
   const int n = g.mx[cc] * g.my[cc];
   if (n <= 0) return;
-  const bool nt = (double)S * kPlanes * g.off[8] * sizeof(T) > kLineCachedBytes;
+  const bool nt = (double)S * kPlanes * g.off[8] * sizeof(M) > kLineCachedBytes;
   if (!line_cols_valid<T>(g, cols)) cols = 16;
   const size_t lds = line_sweep_lds<T>(g, cols);
   if (lds <= kLineLdsMax) {
     dim3 grid(ceil_div(n, cols), S);
-    auto kern = nt ? line_sweep_kernel<T, true>(cc, zero_start, cols)
-                   : line_sweep_kernel<T, false>(cc, zero_start, cols);
+    auto kern = nt ? line_sweep_kernel<T, M, true>(cc, zero_start, cols)
+                   : line_sweep_kernel<T, M, false>(cc, zero_start, cols);
     if (ev0)
       hipExtLaunchKernelGGL(kern, grid, dim3(kLineThreads), lds, st, ev0, ev1, 0, g, cc, A, F, b, x,
                             mask, list);
@@ -335,12 +356,27 @@ void launch_line_smooth(const Geom& g, int cc, const T* A, const T* F, const T* 
     return;
   }
   dim3 grid(ceil_div(n, 64), S);
-  auto kern = nt ? line_smooth_kernel<T, true>(cc, zero_start)
-                 : line_smooth_kernel<T, false>(cc, zero_start);
+  auto kern = nt ? line_smooth_kernel<T, M, true>(cc, zero_start)
+                 : line_smooth_kernel<T, M, false>(cc, zero_start);
   if (ev0)
     hipExtLaunchKernelGGL(kern, grid, dim3(64), 0, st, ev0, ev1, 0, g, cc, A, F, b, x, mask, list);
   else
     hipLaunchKernelGGL(kern, grid, dim3(64), 0, st, g, cc, A, F, b, x, mask, list);
+}
+
+template <typename T>
+void launch_line_smooth(const Geom& g, int cc, const T* A, const T* F, const T* b, T* x, int S,
+                        const int* mask, const int* list, hipStream_t st, hipEvent_t ev0,
+                        hipEvent_t ev1, bool zero_start, int cols) {
+  launch_line_smooth_m<T, T>(g, cc, A, F, b, x, S, mask, list, st, ev0, ev1, zero_start, cols);
+}
+
+void launch_line_smooth_f16(const Geom& g, int cc, const _Float16* A, const float* F,
+                            const float* b, float* x, int S, const int* mask, const int* list,
+                            hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, bool zero_start,
+                            int cols) {
+  launch_line_smooth_m<float, _Float16>(g, cc, A, F, b, x, S, mask, list, st, ev0, ev1,
+                                        zero_start, cols);
 }
 
 // ---------------------------------------------------------------------------
@@ -349,12 +385,13 @@ void launch_line_smooth(const Geom& g, int cc, const T* A, const T* F, const T* 
 // colours below cc) = b, so r = -(sum over the neighbours in columns of colours above cc
 // of A x); the last column colour (3) has zero residual.  Dirichlet rows are zero.
 // ---------------------------------------------------------------------------
-template <typename T, bool NT, int CC>
+template <typename T, typename M, bool NT, int CC>
 __device__ __forceinline__ void line_residual_upper(const Geom& g, int t, int col, int i, int j,
-                                                    int k, const T* A_s, const T* x_s, T* r_s) {
+                                                    int k, const M* A_s, const T* D_s,
+                                                    const T* x_s, T* r_s) {
   using T2 = typename V2<T>::type;
   const NbrMap nm = nbr_map(g, col, i, j, k);
-  const T* A = A_s + sidx<T>(t, 0, kPlanes);
+  const M* A = A_s + sidx<M>(t, 0, kPlanes);
   const T2* x = reinterpret_cast<const T2*>(x_s);
   T a0 = 0, a1 = 0;
 #pragma unroll 1  // one z-plane of neighbours at a time keeps the register count low
@@ -371,6 +408,12 @@ __device__ __forceinline__ void line_residual_upper(const Geom& g, int t, int co
       }
     }
   }
+  if (D_s) {  // the scaled system's residual back to the unscaled rows: r = D (D^{-1} r)
+    const Block2<T> d = load_block<false>(D_s + sidx<T>(t, 0, 4), 0);
+    const T s0 = d.a00 * a0 + d.a01 * a1, s1 = d.a10 * a0 + d.a11 * a1;
+    a0 = s0;
+    a1 = s1;
+  }
   double cD;
   T2 out;
   out.x = is_pin(g, i, j, k) ? T(0) : -a0;
@@ -378,10 +421,11 @@ __device__ __forceinline__ void line_residual_upper(const Geom& g, int t, int co
   reinterpret_cast<T2*>(r_s)[t] = out;
 }
 
-template <typename T, bool NT>
-__global__ __launch_bounds__(kBlock) void k_line_residual_zs(Geom g, const T* A_all,
-                                                             const T* x_all, T* r_all,
-                                                             const int* mask, const int* list) {
+template <typename T, typename M, bool NT>
+__global__ __launch_bounds__(kBlock) void k_line_residual_zs(Geom g, const M* A_all,
+                                                             const T* D_all, const T* x_all,
+                                                             T* r_all, const int* mask,
+                                                             const int* list) {
   using T2 = typename V2<T>::type;
   const int s = list ? list[blockIdx.y] : blockIdx.y;
   if (mask && !mask[s]) return;
@@ -398,13 +442,14 @@ __global__ __launch_bounds__(kBlock) void k_line_residual_zs(Geom g, const T* A_
   int i, j, k;
   colour_decode_in(g, col, place, i, j, k);
   const size_t Np = g.off[8];
-  const T* A = A_all + (size_t)s * kPlanes * Np;
+  const M* A = A_all + (size_t)s * kPlanes * Np;
+  const T* D = D_all ? D_all + (size_t)s * 4 * Np : nullptr;
   const T* x = x_all + (size_t)s * 2 * Np;
   T* r = r_all + (size_t)s * 2 * Np;
   switch (col & 3) {
-    case 0: line_residual_upper<T, NT, 0>(g, t, col, i, j, k, A, x, r); break;
-    case 1: line_residual_upper<T, NT, 1>(g, t, col, i, j, k, A, x, r); break;
-    case 2: line_residual_upper<T, NT, 2>(g, t, col, i, j, k, A, x, r); break;
+    case 0: line_residual_upper<T, M, NT, 0>(g, t, col, i, j, k, A, D, x, r); break;
+    case 1: line_residual_upper<T, M, NT, 1>(g, t, col, i, j, k, A, D, x, r); break;
+    case 2: line_residual_upper<T, M, NT, 2>(g, t, col, i, j, k, A, D, x, r); break;
     default: {
       T2 z;
       z.x = 0;
@@ -414,13 +459,25 @@ __global__ __launch_bounds__(kBlock) void k_line_residual_zs(Geom g, const T* A_
   }
 }
 
+template <typename T, typename M>
+void launch_line_residual_zs_m(const Geom& g, const M* A, const T* D, const T* x, T* r, int S,
+                               const int* mask, const int* list, hipStream_t st) {
+  dim3 grid(slab_blocks(g), S);
+  const bool nt = (double)S * kPlanes * g.off[8] * sizeof(M) > kLineCachedBytes;
+  auto kern = nt ? k_line_residual_zs<T, M, true> : k_line_residual_zs<T, M, false>;
+  hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, st, g, A, D, x, r, mask, list);
+}
+
 template <typename T>
 void launch_line_residual_zs(const Geom& g, const T* A, const T* x, T* r, int S, const int* mask,
                              const int* list, hipStream_t st) {
-  dim3 grid(slab_blocks(g), S);
-  const bool nt = (double)S * kPlanes * g.off[8] * sizeof(T) > kLineCachedBytes;
-  auto kern = nt ? k_line_residual_zs<T, true> : k_line_residual_zs<T, false>;
-  hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, st, g, A, x, r, mask, list);
+  launch_line_residual_zs_m<T, T>(g, A, nullptr, x, r, S, mask, list, st);
+}
+
+void launch_line_residual_zs_f16(const Geom& g, const _Float16* A, const float* D, const float* x,
+                                 float* r, int S, const int* mask, const int* list,
+                                 hipStream_t st) {
+  launch_line_residual_zs_m<float, _Float16>(g, A, D, x, r, S, mask, list, st);
 }
 
 #define EDF_LINE_INST(T)                                                                        \

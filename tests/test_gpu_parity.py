@@ -320,7 +320,7 @@ def test_vcycle_same_for_every_fused_bottom(precision):
     pb.destroy()
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_line_smoothed_vcycle_is_a_contraction(precision):
     """The vertical-line smoother (columns solved exactly, 4 column colours) on the levels
     swept by their own launches: one V-cycle reduces the residual at least as well as
@@ -346,10 +346,11 @@ def test_line_smoothed_vcycle_is_a_contraction(precision):
         assert max(red[(1, l0)]) <= 1.05 * max(red[(0, l0)])
 
 
-@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-6)])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-6), (2, 1e-6)])
 def test_line_smoother_step_matches_oracle(precision, tol):
     """One step with the line-smoothed V-cycle (levels 0-2 of a 4-level 33x33x9
-    hierarchy swept by separate launches) reaches the oracle's root."""
+    hierarchy swept by separate launches; with precision 2 the finest level's lines are
+    swept over its FP16 scaled matrix) reaches the oracle's root."""
     nx, ny, nz = 33, 33, 9
     phys = synth.physics(2)
     xi = _xi(2, 2, seed=6)
@@ -694,7 +695,7 @@ def test_sample_failure_is_reported_and_left_out_of_moments():
     pb.destroy()
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_line_tile_shapes_give_the_same_vcycle(precision, tmp_path):
     """The line sweep's tile shapes (8, 16, 32 columns per workgroup) compute every column
     the same way: one V-cycle gives bitwise the same output with each shape.  Invalid
