@@ -769,8 +769,11 @@ const double* stencil<double>(const Level& L) { return L.AV64 ? L.AV64 : L.A64; 
 template <>
 const float* stencil<float>(const Level& L) { return L.A32; }
 
-// the fused bottom's description for first fused level l0 (host side), and whether the
-// levels' vectors fit in the workgroup's LDS
+// the fused bottom's description for first fused level l0 (host side), whether the
+// levels' vectors fit in the workgroup's LDS, and the dynamic LDS of its launch: the
+// vectors when they fit, and the values of one line sweep of the largest line-smoothed
+// level (levels with line factors are swept by lines, as those swept by their own
+// launches; point sweeps if even those values do not fit)
 template <typename T>
 FusedLevels<T> fused_levels(const Group& G, int l0, size_t& lds_bytes, bool& in_lds) {
   FusedLevels<T> F{};
@@ -778,23 +781,35 @@ FusedLevels<T> fused_levels(const Group& G, int l0, size_t& lds_bytes, bool& in_
   F.nc = G.n_coarse;
   F.Minv = G.Minv;
   // the levels' x, b and r (three vectors of 2 Np_k) in LDS when they all fit
-  size_t lds_elems = 0;
+  size_t lds_elems = 0, scr = 0;
   for (int k = 0; k < F.n; ++k) {
     const Level& L = G.lv[l0 + k];
     F.g[k] = L.g;
     const bool coarsest = l0 + k == G.L - 1;
     F.A[k] = coarsest ? nullptr : stencil<T>(L);
     F.D[k] = coarsest ? nullptr : (const T*)L.Dinv;
+    F.LF[k] = coarsest || L.A16 ? nullptr : (const T*)L.LF;
     F.r[k] = coarsest ? nullptr : (T*)L.r;
     F.b[k] = (T*)L.b;
     F.x[k] = (T*)L.x;
     F.lds_off[k] = (int)lds_elems;
     lds_elems += 6 * (size_t)L.g.off[8];
+    if (F.LF[k]) {
+      int most = 0;
+      for (int cc = 0; cc < 4; ++cc) most = std::max(most, L.g.mx[cc] * L.g.my[cc]);
+      scr = std::max(scr, (size_t)kLineVals * L.g.nz * most);
+    }
   }
-  lds_bytes = lds_elems * sizeof(T);
-  in_lds = lds_bytes <= vcycle_bottom_lds_limit<T>();
-  if (!in_lds)
+  const size_t limit = vcycle_bottom_lds_limit<T>();
+  in_lds = (lds_elems + scr) * sizeof(T) <= limit;
+  if (in_lds) {
+    F.line_lds = scr ? (int)lds_elems : -1;
+    lds_bytes = (lds_elems + scr) * sizeof(T);
+  } else {
     for (int k = 0; k < F.n; ++k) F.lds_off[k] = -1;
+    F.line_lds = scr && scr * sizeof(T) <= limit ? 0 : -1;
+    lds_bytes = F.line_lds == 0 ? scr * sizeof(T) : 0;
+  }
   return F;
 }
 
@@ -930,7 +945,7 @@ void vcycle(edf_problem* pb, Group& G, const double* in, double* out, const int*
     bool in_lds = false;
     (void)fused_levels<T>(G, l0, lds_bytes, in_lds);
     ensure_fused_desc<T>(pb, G, l0);  // a no-op inside a captured V-cycle (set up before)
-    launch_vcycle_bottom<T>((const FusedLevels<T>*)G.fdesc, in_lds ? lds_bytes : 0, S, mask, list, st);
+    launch_vcycle_bottom<T>((const FusedLevels<T>*)G.fdesc, lds_bytes, S, mask, list, st);
   }
   for (int l = l0 - 1; l >= 0; --l) {
     Level& L = G.lv[l];
@@ -1237,6 +1252,8 @@ void vcycle_merged(edf_problem* pb, const std::vector<MergeReq*>& R) {
                  pool_base(X.r, X.slot, 2 * Np * tsz) == pool_base(Y.r, Y.slot, 2 * Np * tsz) &&
                  pool_base(X.Dinv, X.slot, 4 * Np * tsz) ==
                      pool_base(Y.Dinv, Y.slot, 4 * Np * tsz) &&
+                 pool_base(X.LF, X.slot, kLineFactors * Np * tsz) ==
+                     pool_base(Y.LF, Y.slot, kLineFactors * Np * tsz) &&
                  (a + k == G->L - 1 ||
                   pool_base(stencil<T>(X), X.slot, kPlanes * Np * tsz) ==
                       pool_base(stencil<T>(Y), Y.slot, kPlanes * Np * tsz));
@@ -1261,7 +1278,7 @@ void vcycle_merged(edf_problem* pb, const std::vector<MergeReq*>& R) {
       if (c.size() == 1) {
         (void)fused_levels<T>(*G, l0, lds_bytes, in_lds);
         ensure_fused_desc<T>(pb, *G, l0);
-        launch_vcycle_bottom<T>((const FusedLevels<T>*)G->fdesc, in_lds ? lds_bytes : 0,
+        launch_vcycle_bottom<T>((const FusedLevels<T>*)G->fdesc, lds_bytes,
                                 G->n_list, mask_of(G), sample_list(*G), st);
         continue;
       }
@@ -1273,16 +1290,18 @@ void vcycle_merged(edf_problem* pb, const std::vector<MergeReq*>& R) {
         const size_t Np = X.g.off[8];
         F.A[k] = (const T*)pool_base(F.A[k], X.slot, kPlanes * Np * tsz);
         F.D[k] = (const T*)pool_base(F.D[k], X.slot, 4 * Np * tsz);
+        F.LF[k] = (const T*)pool_base(F.LF[k], X.slot, kLineFactors * Np * tsz);
         F.r[k] = (T*)pool_base(F.r[k], X.slot, 2 * Np * tsz);
         F.b[k] = (T*)pool_base(F.b[k], X.slot, 2 * Np * tsz);
         F.x[k] = (T*)pool_base(F.x[k], X.slot, 2 * Np * tsz);
       }
       F.Minv = (const double*)pool_base(F.Minv, G->lv[G->L - 1].slot,
                                         (size_t)G->n_coarse * G->n_coarse * sizeof(double));
-      std::vector<long> key = {F.n, F.nc, F.nu1, F.nu2, (long)(intptr_t)F.Minv};
+      std::vector<long> key = {F.n, F.nc, F.nu1, F.nu2, F.line_lds, (long)(intptr_t)F.Minv};
       for (int k = 0; k < F.n; ++k)
         for (long v : {(long)F.lds_off[k], (long)F.g[k].nx, (long)F.g[k].ny, (long)F.g[k].nz,
-                       (long)(intptr_t)F.A[k], (long)(intptr_t)F.D[k], (long)(intptr_t)F.x[k],
+                       (long)(intptr_t)F.A[k], (long)(intptr_t)F.D[k], (long)(intptr_t)F.LF[k],
+                       (long)(intptr_t)F.x[k],
                        (long)(intptr_t)F.b[k], (long)(intptr_t)F.r[k]})
           key.push_back(v);
       void* desc = nullptr;
@@ -1300,7 +1319,7 @@ void vcycle_merged(edf_problem* pb, const std::vector<MergeReq*>& R) {
       for (Group* H : c) parts.push_back({H, l0of(H)});
       int rows = 0;
       const int* list = merged_list(pb, parts, rows, st);
-      launch_vcycle_bottom<T>((const FusedLevels<T>*)desc, in_lds ? lds_bytes : 0, rows,
+      launch_vcycle_bottom<T>((const FusedLevels<T>*)desc, lds_bytes, rows,
                               nullptr, list, st);
     }
   }

@@ -125,6 +125,7 @@ __host__ __device__ constexpr int zero_start_blocks(int col) {
 // cc = (i % 2) + 2 (j % 2); the neighbour column at (dx, dy) has colour cc with the parity
 // bit of every odd component flipped.
 constexpr int kLineFactors = 8;  // per vertex: M^{-1} of the column's block LU, then C
+constexpr int kLineVals = 10;    // per (row, column) of a line sweep in LDS: e (2), G (4), C (4)
 __host__ __device__ constexpr int line_column_colour(int cc, int dx, int dy) {
   return cc ^ ((dx != 0) | ((dy != 0) << 1));
 }
@@ -241,15 +242,21 @@ struct FusedLevels {
   // b at + 2 Np, r at + 4 Np) instead of in x/b/r; only the first level's b is read from
   // and its x written back to device memory.  All levels or none are in LDS.
   int lds_off[kMaxFused];
+  // line_lds >= 0: the levels with line factors LF[k] are swept by vertical lines (as the
+  // levels swept by their own launches), with the per-(row, column) values of a sweep in
+  // LDS at element line_lds; the others (LF[k] null) by points
+  int line_lds;
   Geom g[kMaxFused];
   const T* A[kMaxFused];
   const T* D[kMaxFused];
+  const T* LF[kMaxFused];
   T* x[kMaxFused];
   T* b[kMaxFused];
   T* r[kMaxFused];
   const double* Minv;
 };
-// lds_bytes: dynamic LDS of the launch (0 when the levels stay in device memory)
+// lds_bytes: dynamic LDS of the launch (the levels' vectors when they are kept there, and
+// the line sweeps' values)
 template <typename T>
 void launch_vcycle_bottom(const FusedLevels<T>* F_dev, size_t lds_bytes, int S, const int* mask,
                           const int* list, hipStream_t st);

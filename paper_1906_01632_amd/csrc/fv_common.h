@@ -248,6 +248,16 @@ inline int slab_blocks(const Geom& g) {
   return kXcds * ceil_div(most, kBlock / kTile);
 }
 
+// Vertical lines (z-columns) of the line smoother: the blocks of a column's tridiagonal
+// part and the colour-major position of its vertex at height k.  Column q of column
+// colour cc is (i, j) = (2 (q % mx) + (cc & 1), 2 (q / mx) + (cc >> 1)), mx = g.mx[cc]; its
+// vertex at height k has vertex colour cc + 4 (k & 1) and place q + mx my (k >> 1) there.
+constexpr int kLineL = 4;   // nb_index(0, 0, -1): the vertex above (smaller depth)
+constexpr int kLineU = 22;  // nb_index(0, 0, +1): the vertex below
+__device__ __forceinline__ int line_pos(const Geom& g, int cc, int q, int k) {
+  return g.off[cc + 4 * (k & 1)] + q + g.mx[cc] * g.my[cc] * (k >> 1);
+}
+
 // salt Dirichlet vertex (closed top patch: c = 1; bottom: c = 0)
 __device__ __forceinline__ bool is_cdir(const Geom& g, int i, int j, int k, double& value) {
   if (k == g.nz - 1) { value = 0.0; return true; }

@@ -26,13 +26,6 @@
 
 namespace edf {
 
-constexpr int kLineL = 4;   // nb_index(0, 0, -1): the vertex above (smaller depth)
-constexpr int kLineU = 22;  // nb_index(0, 0, +1): the vertex below
-
-template <typename T>
-__device__ __forceinline__ int line_pos(const Geom& g, int cc, int q, int k) {
-  return g.off[cc + 4 * (k & 1)] + q + g.mx[cc] * g.my[cc] * (k >> 1);
-}
 
 // ---------------------------------------------------------------------------
 // block LU of each column's tridiagonal part, from the top: M_k = D_k - L_k C_{k-1},
@@ -53,7 +46,7 @@ __global__ __launch_bounds__(64) void k_line_factor(Geom g, const M* A_all, T* F
   constexpr bool unit = std::is_same<M, _Float16>::value;
   double c00 = 0.0, c01 = 0.0, c10 = 0.0, c11 = 0.0;
   for (int k = 0; k < g.nz; ++k) {
-    const int t = line_pos<T>(g, cc, q, k);
+    const int t = line_pos(g, cc, q, k);
     const M* a = A + sidx<M>(t, 0, kPlanes);
     auto val = [&](int o, int e) { return (double)a[soff<M>(o * 4 + e)]; };
     const double l00 = val(kLineL, 0), l01 = val(kLineL, 1), l10 = val(kLineL, 2),
@@ -127,7 +120,7 @@ __global__ __launch_bounds__(64) void k_line_smooth(Geom g, int cc, const M* A_a
   T d0 = 0, d1 = 0;
   for (int k = 0; k < g.nz; ++k) {
     const int col = cc + 4 * (k & 1);
-    const int t = line_pos<T>(g, cc, q, k);
+    const int t = line_pos(g, cc, q, k);
     const NbrMap nm = nbr_map(g, col, i, j, k);
     const M* a = A + sidx<M>(t, 0, kPlanes);
     const T2 bv = b[t];
@@ -160,7 +153,7 @@ __global__ __launch_bounds__(64) void k_line_smooth(Geom g, int cc, const M* A_a
   }
   T y0 = 0, y1 = 0;
   for (int k = g.nz - 1; k >= 0; --k) {
-    const int t = line_pos<T>(g, cc, q, k);
+    const int t = line_pos(g, cc, q, k);
     const Block2<T> c = load_block<NT>(F + sidx<T>(t, 0, kLineFactors), 4);
     const T2 dv = x[t];
     const T n0 = dv.x - (c.a00 * y0 + c.a01 * y1);
@@ -188,7 +181,6 @@ __global__ __launch_bounds__(64) void k_line_smooth(Geom g, int cc, const M* A_a
 // idle when few samples are active.
 // ---------------------------------------------------------------------------
 constexpr int kLineThreads = 256;      // 4 waves
-constexpr int kLineVals = 10;          // per (row, column) in LDS: e (2), G (4), C (4)
 
 template <typename T, typename M, bool NT, int ZC, int COLS>
 __global__ __launch_bounds__(kLineThreads) void k_line_sweep(Geom g, int cc, const M* A_all,
@@ -224,7 +216,7 @@ __global__ __launch_bounds__(kLineThreads) void k_line_sweep(Geom g, int cc, con
     if (k >= nz || q >= ncol) continue;
     const int i = 2 * (q % mx) + (cc & 1), j = 2 * (q / mx) + (cc >> 1);
     const int col = cc + 4 * par;  // the same for the whole wave
-    const int t = line_pos<T>(g, cc, q, k);
+    const int t = line_pos(g, cc, q, k);
     const NbrMap nm = nbr_map(g, col, i, j, k);
     const M* a = A + sidx<M>(t, 0, kPlanes);
     const T2 bv = b[t];
@@ -282,7 +274,7 @@ __global__ __launch_bounds__(kLineThreads) void k_line_sweep(Geom g, int cc, con
     T2 o;
     o.x = n0;
     o.y = n1;
-    x[line_pos<T>(g, cc, q, k)] = o;
+    x[line_pos(g, cc, q, k)] = o;
   }
 }
 

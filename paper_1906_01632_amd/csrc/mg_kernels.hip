@@ -871,6 +871,88 @@ void launch_gauss_jordan(int n, double* M, int* piv, int* status, int S, const i
 // ---------------------------------------------------------------------------
 constexpr int kFusedThreads = 1024;
 
+// One vertical-line sweep of column colour cc inside the fused bottom (the workgroup's
+// threads over the level's columns): first every (column, k) at once, r_k = b_k - (the
+// other columns' couplings) A x and e_k = M_k^{-1} r_k, G_k = M_k^{-1} L_k, C_k into the
+// LDS values scr [10][nz][columns]; then one thread per column runs d_k = e_k - G_k d_{k-1}
+// and x_k = d_k - C_k x_{k+1}.  The rows of each k-parity are taken in a loop of their own,
+// so that the vertex colour (cc + 4 parity) is the same across a wave.  The same
+// arithmetic as k_line_sweep, as a phase of the fused launch.
+template <typename T>
+__device__ __forceinline__ void bottom_line_sweep(const Geom& g, int cc, const T* A, const T* F,
+                                                  const T* b_s, T* x_s, T* scr, int tid, int nt) {
+  using T2 = typename V2<T>::type;
+  const int mx = g.mx[cc], ncol = mx * g.my[cc], nz = g.nz;
+  auto L_at = [&](int v, int k, int c) -> T& { return scr[((size_t)v * nz + k) * ncol + c]; };
+  const T2* b = reinterpret_cast<const T2*>(b_s);
+  T2* x = reinterpret_cast<T2*>(x_s);
+  for (int par = 0; par < 2; ++par) {
+    const int rows = par ? nz / 2 : (nz + 1) / 2;
+    const int col = cc + 4 * par;
+    for (int idx = tid; idx < ncol * rows; idx += nt) {
+      const int q = idx % ncol, k = par + 2 * (idx / ncol);
+      const int i = 2 * (q % mx) + (cc & 1), j = 2 * (q / mx) + (cc >> 1);
+      const int t = line_pos(g, cc, q, k);
+      const NbrMap nm = nbr_map(g, col, i, j, k);
+      const T* a = A + sidx<T>(t, 0, kPlanes);
+      const T2 bv = b[t];
+      T r0 = bv.x, r1 = bv.y;
+#pragma unroll
+      for (int dz = -1; dz <= 1; ++dz) {
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+#pragma unroll
+          for (int dx = -1; dx <= 1; ++dx) {
+            if (dx == 0 && dy == 0) continue;  // the column itself: solved below
+            const T2 xv = load_nbr(x, g, nm, dx, dy, dz);
+            const Block2<T> blk = load_block<false>(a, nb_index(dx, dy, dz) * 4);
+            r0 -= blk.a00 * xv.x + blk.a01 * xv.y;
+            r1 -= blk.a10 * xv.x + blk.a11 * xv.y;
+          }
+        }
+      }
+      const Block2<T> l = load_block<false>(a, kLineL * 4);
+      const T* f = F + sidx<T>(t, 0, kLineFactors);
+      const Block2<T> mi = load_block<false>(f, 0);
+      const Block2<T> c = load_block<false>(f, 4);
+      L_at(0, k, q) = mi.a00 * r0 + mi.a01 * r1;
+      L_at(1, k, q) = mi.a10 * r0 + mi.a11 * r1;
+      L_at(2, k, q) = mi.a00 * l.a00 + mi.a01 * l.a10;
+      L_at(3, k, q) = mi.a00 * l.a01 + mi.a01 * l.a11;
+      L_at(4, k, q) = mi.a10 * l.a00 + mi.a11 * l.a10;
+      L_at(5, k, q) = mi.a10 * l.a01 + mi.a11 * l.a11;
+      L_at(6, k, q) = c.a00;
+      L_at(7, k, q) = c.a01;
+      L_at(8, k, q) = c.a10;
+      L_at(9, k, q) = c.a11;
+    }
+  }
+  __syncthreads();
+  for (int q = tid; q < ncol; q += nt) {
+    T d0 = 0, d1 = 0;
+    for (int k = 0; k < nz; ++k) {  // d_k = e_k - G_k d_{k-1}, kept in place of e_k
+      const T n0 = L_at(0, k, q) - (L_at(2, k, q) * d0 + L_at(3, k, q) * d1);
+      const T n1 = L_at(1, k, q) - (L_at(4, k, q) * d0 + L_at(5, k, q) * d1);
+      d0 = n0;
+      d1 = n1;
+      L_at(0, k, q) = n0;
+      L_at(1, k, q) = n1;
+    }
+    T y0 = 0, y1 = 0;
+    for (int k = nz - 1; k >= 0; --k) {  // x_k = d_k - C_k x_{k+1}
+      const T n0 = L_at(0, k, q) - (L_at(6, k, q) * y0 + L_at(7, k, q) * y1);
+      const T n1 = L_at(1, k, q) - (L_at(8, k, q) * y0 + L_at(9, k, q) * y1);
+      y0 = n0;
+      y1 = n1;
+      T2 o;
+      o.x = n0;
+      o.y = n1;
+      x[line_pos(g, cc, q, k)] = o;
+    }
+  }
+  __syncthreads();
+}
+
 template <typename T>
 __global__ __launch_bounds__(kFusedThreads) void k_vcycle_bottom(const FusedLevels<T>* __restrict__ Fp,
                                                                  const int* mask, const int* list) {
@@ -893,6 +975,10 @@ __global__ __launch_bounds__(kFusedThreads) void k_vcycle_bottom(const FusedLeve
   auto Rv = [&](int l) {
     return in_lds ? lds + F.lds_off[l] + 4 * F.g[l].off[8] : F.r[l] + (size_t)s * 2 * F.g[l].off[8];
   };
+  // vertical-line smoothing of the levels with line factors (LF), points otherwise
+  auto line = [&](int l) { return F.line_lds >= 0 && F.LF[l] != nullptr; };
+  auto LF = [&](int l) { return F.LF[l] + (size_t)s * kLineFactors * F.g[l].off[8]; };
+  T* scr = lds + (F.line_lds >= 0 ? F.line_lds : 0);
   const int last = F.n - 1;
   // x = 0 on the first fused level (the finer levels' restriction clears the others);
   // in LDS the first level's right-hand side is brought in from device memory
@@ -903,12 +989,17 @@ __global__ __launch_bounds__(kFusedThreads) void k_vcycle_bottom(const FusedLeve
   __syncthreads();
   for (int l = 0; l < last; ++l) {
     const Geom& g = F.g[l];
-    for (int it = 0; it < F.nu1; ++it)
+    for (int it = 0; it < F.nu1; ++it) {
+      if (line(l)) {
+        for (int cc = 0; cc < 4; ++cc) bottom_line_sweep<T>(g, cc, A(l), LF(l), B(l), X(l), scr, tid, nt);
+        continue;
+      }
       for (int c = 0; c < 8; ++c) {
         for (int q = tid; q < g.cnt[c]; q += nt)
           smooth_vertex<T, false>(g, c, q, A(l), D(l), B(l), X(l));
         __syncthreads();
       }
+    }
     for (int t = tid; t < g.off[8]; t += nt)
       residual_vertex<T, false>(g, t, A(l), B(l), X(l), Rv(l));
     __syncthreads();
@@ -944,12 +1035,17 @@ __global__ __launch_bounds__(kFusedThreads) void k_vcycle_bottom(const FusedLeve
     const Geom& g = F.g[l];
     for (int t = tid; t < g.off[8]; t += nt) prolong_vertex<T>(g, F.g[l + 1], t, X(l + 1), X(l));
     __syncthreads();
-    for (int it = 0; it < F.nu2; ++it)
+    for (int it = 0; it < F.nu2; ++it) {
+      if (line(l)) {
+        for (int cc = 3; cc >= 0; --cc) bottom_line_sweep<T>(g, cc, A(l), LF(l), B(l), X(l), scr, tid, nt);
+        continue;
+      }
       for (int c = 7; c >= 0; --c) {
         for (int q = tid; q < g.cnt[c]; q += nt)
           smooth_vertex<T, false>(g, c, q, A(l), D(l), B(l), X(l));
         __syncthreads();
       }
+    }
   }
   if (in_lds)  // the first level's correction goes back for the finer level's prolongation
     for (int e = tid; e < 2 * F.g[0].off[8]; e += nt)

@@ -291,18 +291,20 @@ def test_vcycle_is_a_contraction(precision):
     pb.destroy()
 
 
-@pytest.mark.parametrize("precision", [0, 1, 2])
-def test_vcycle_same_for_every_fused_bottom(precision):
+@pytest.mark.parametrize("precision,smoother", [(0, 0), (1, 0), (2, 0), (0, 1), (1, 1), (2, 1)])
+def test_vcycle_same_for_every_fused_bottom(precision, smoother):
     """The V-cycle gives the same result whichever levels run in the fused bottom launch,
     and set_tuning rejects levels that do not fit the fused launch.  Levels swept by
     separate launches take the zero-start forms (first sweep from x = 0 reading only the
     colours already swept, residual from the blocks towards the later colours); the fused
-    bottom takes the general forms (full stencil, r = b - A x): the two agree to rounding."""
+    bottom takes the general forms (full stencil, r = b - A x): the two agree to rounding.
+    The fused bottom sweeps its levels with the same smoother, points (0) or vertical
+    lines (1), as the levels swept by their own launches."""
     nx, ny, nz = 33, 33, 9
     phys = synth.physics(2)
-    # the point smoother on every level, so that moving a level into the fused bottom changes
+    # the same smoother on every level, so that moving a level into the fused bottom changes
     # only the forms of its sweeps, not the smoother
-    pb = _problem(phys, [(nx, ny, nz, 4, 3)], precision=precision, smoother=0)
+    pb = _problem(phys, [(nx, ny, nz, 4, 3)], precision=precision, smoother=smoother)
     pb.set_parameters(_xi(2, 3, seed=11))
     b = np.random.default_rng(5).standard_normal((3, nz, ny, nx, 2))
     b[..., 1][:, -1] = 0.0
