@@ -128,24 +128,28 @@ def _dispatch_bytes(name, bx, wx, gx, rows, sweep, resid):
     """Algorithmic bytes of one smoother or residual dispatch (the library's count), or
     None for other kernels and ambiguous grids."""
     import re
-    m = re.search(r"k_line_(sweep|smooth)<(float|double), (?:true|false), (-?\d+)(?:, (\d+))?>",
-                  name)
-    if m:
-        cols = int(m.group(4)) if m.group(4) else 64
+    size = {"float": 4, "double": 8, "_Float16": 2}
+    m = re.search(r"k_line_(sweep|smooth)<(float|double), (float|double|_Float16), (?:true|false), "
+                  r"(-?\d+)(?:, (\d+))?>", name)
+    if m:  # vectors in T (group 2), matrix in M (group 3)
+        cols = int(m.group(5)) if m.group(5) else 64
         cand = sweep.get((bx, wx, cols), set())
         if len(cand) != 1:
             return None
         (nc, nz), = cand
-        nb = 24 if int(m.group(3)) < 0 else ZERO_START_BLOCKS[int(m.group(3))]
-        return rows * nc * nz * (4 * (nb + 1) + 16) * (4 if m.group(2) == "float" else 8)
-    m = re.search(r"k_line_residual_zs<(float|double), (?:true|false)>", name)
+        nb = 24 if int(m.group(4)) < 0 else ZERO_START_BLOCKS[int(m.group(4))]
+        t, mt = size[m.group(2)], size[m.group(3)]
+        return rows * nc * nz * (4 * (nb + 1) * mt + 16 * t)
+    m = re.search(r"k_line_residual_zs<(float|double), (float|double|_Float16), (?:true|false)>", name)
     if m:
         cand = resid.get(gx, set())
         if len(cand) != 1:
             return None
         per_cc, = cand
-        t = 4 if m.group(1) == "float" else 8
-        return rows * t * sum(n * (4 * (24 - ZERO_START_BLOCKS[cc]) + 2) for cc, n in enumerate(per_cc))
+        t, mt = size[m.group(1)], size[m.group(2)]
+        unscale = 4 * t if mt == 2 else 0  # the FP16 matrix's residual reads D
+        return rows * sum(n * (4 * (24 - ZERO_START_BLOCKS[cc]) * mt + 2 * t + unscale)
+                          for cc, n in enumerate(per_cc))
     return None
 
 
