@@ -149,9 +149,9 @@ typedef struct {
                            /* (i%2, j%2, k%2); 1 vertical-line block Gauss-Seidel:  */
                            /* every z-column's block tridiagonal system solved      */
                            /* exactly, columns in 4 colours (i%2, j%2), the other  */
-                           /* couplings lagged (the levels of the fused bottom keep */
-                           /* the point smoother; an FP16-stored finest level is    */
-                           /* swept by lines of its scaled matrix D^-1 A)           */
+                           /* couplings lagged (the levels of the fused bottom are  */
+                           /* swept the same way inside its launch; an FP16-stored  */
+                           /* finest level by lines of its scaled matrix D^-1 A)    */
   int32_t matrix_free;     /* the outer BiCGStab's products J x: 0 with the exact    */
                            /* FP64 Jacobian assembled as a 27-point stencil of 2x2  */
                            /* blocks (864 bytes per vertex); 1 matrix-free, the     */
@@ -460,10 +460,11 @@ edf_status edf_set_tuning(edf_problem* pb, int32_t group, int32_t fuse_from);
 
 /* Tile shapes of the vertical-line sweeps of group `group` (see edf_autotune):
  * cols (host int32_t[n_levels]) = columns per workgroup of each level's k_line_sweep, 0
- * for a level without line smoothing (the coarsest, the point smoother).  edf_set_line_tiles fixes them (e.g. from a saved tuning); EDF_ERR_ARG,
- * with nothing changed, unless every entry is 0 exactly where the level has no line
- * smoothing and otherwise 8, 16 or 32 with 10 x nz x cols values in at most 64 KiB of
- * LDS.  Tile shapes do not change results (each column is computed the same way). */
+ * for a level without line smoothing (the coarsest, the point smoother).
+ * edf_set_line_tiles fixes them (e.g. from a saved tuning); EDF_ERR_ARG, with nothing
+ * changed, unless every entry is 0 exactly where the level has no line smoothing and
+ * otherwise 8, 16 or 32 with 10 x nz x cols values in at most 64 KiB of LDS.  Tile shapes
+ * do not change results (each column is computed the same way). */
 edf_status edf_get_line_tiles(edf_problem* pb, int32_t group, int32_t* cols);
 edf_status edf_set_line_tiles(edf_problem* pb, int32_t group, const int32_t* cols);
 
