@@ -556,6 +556,12 @@ def run_steps(args, wl, pb, prec, region=(None, None)):
                          "frac": vg / HBM_PEAK_GBS, "count": prof["vcycles"],
                          "avg_ms": prof["vcycle_ms"] / prof["vcycles"],
                          "bytes_per_vcycle": prof["vcycle_bytes"] / prof["vcycles"]}
+        if prof["large_vcycles"]:
+            # V-cycles whose algorithmic bytes exceed the 256 MiB last-level cache
+            lg = prof["large_vcycle_bytes"] / (prof["large_vcycle_ms"] * 1e-3) / 1e9
+            leg["vcycle"]["beyond_256MiB"] = {
+                "achieved": lg, "frac": lg / HBM_PEAK_GBS, "count": prof["large_vcycles"],
+                "share_of_vcycle_time": prof["large_vcycle_ms"] / prof["vcycle_ms"]}
     return leg
 
 

@@ -405,13 +405,14 @@ edf_status edf_apply_jacobian(edf_problem* pb, int32_t group, const double* x, d
  * edf_profile(pb, 1, out) starts: every 13th smoother launch (the dominant kernel,
  * block Gauss-Seidel over one colour; the stride runs through colours, levels and
  * sweeps alike) and every whole V-cycle is bracketed by events; edf_profile(pb, 0,
- * out) stops.  Both fill out (if not NULL, host double[13]) with totals since the last
+ * out) stops.  Both fill out (if not NULL, host double[16]) with totals since the last
  * start: out[0..2] = timed smoother launches, their summed kernel time [ms] and
  * algorithmic bytes; out[3..5] = V-cycles, summed time [ms], algorithmic bytes;
  * out[6..7] = all smoother launches and their algorithmic bytes; out[8..10] = the timed
  * smoother launches of more than 256 MiB of algorithmic bytes (working sets beyond the
  * last-level cache, whose bandwidth is HBM bandwidth), their time and bytes;
- * out[11..12] = all such launches and their bytes.  With the vertical-line smoother the
+ * out[11..12] = all such launches and their bytes; out[13..15] = the V-cycles of more than
+ * 256 MiB of algorithmic bytes, their time and bytes.  With the vertical-line smoother the
  * smoother launches are its column sweeps: per vertex of the swept columns and active
  * sample 24 stencil blocks towards the other columns (the first sweep from zero: 0, 6,
  * 18, 24 for column colours 0..3) and the block above, 8 factor values, b, and x written,

@@ -359,14 +359,15 @@ class Problem:
     def profile(self, enable: bool):
         """Starts (True) or stops (False) event timing of the smoother launches and of
         whole V-cycles; returns the totals since the last start."""
-        out = np.zeros(13)
+        out = np.zeros(16)
         self._check(self._lib.edf_profile(self._h, int(bool(enable)), _dptr(out)))
         return {"launches": int(out[0]), "ms": float(out[1]), "bytes": float(out[2]),
                 "vcycles": int(out[3]), "vcycle_ms": float(out[4]), "vcycle_bytes": float(out[5]),
                 "all_launches": int(out[6]), "all_bytes": float(out[7]),
                 "large_launches": int(out[8]), "large_ms": float(out[9]),
                 "large_bytes": float(out[10]), "large_all_launches": int(out[11]),
-                "large_all_bytes": float(out[12])}
+                "large_all_bytes": float(out[12]), "large_vcycles": int(out[13]),
+                "large_vcycle_ms": float(out[14]), "large_vcycle_bytes": float(out[15])}
 
     def tuning_key(self) -> str:
         """What a V-cycle tuning depends on: the groups, the V-cycle's precision, smoother

@@ -78,7 +78,7 @@ struct Group {
   std::vector<ProfRec> prof_pending;
   // [0] timed smoother launches, [1] V-cycles, [2] the timed smoother launches whose
   // algorithmic bytes exceed kLargeLaunch (working sets beyond the last-level cache)
-  double prof_count[3] = {0, 0, 0}, prof_ms[3] = {0, 0, 0}, prof_bytes[3] = {0, 0, 0};
+  double prof_count[4] = {0, 0, 0, 0}, prof_ms[4] = {0, 0, 0, 0}, prof_bytes[4] = {0, 0, 0, 0};
   // every smoother launch, timed or not: all of them, and those beyond kLargeLaunch
   double prof_all_count[2] = {0, 0}, prof_all_bytes[2] = {0, 0};
   long long prof_tick = 0;
@@ -591,7 +591,7 @@ constexpr int kProfStride = 13;
 
 bool prof_pair(Group& G, hipEvent_t& a, hipEvent_t& b, double bytes, int kind) {
   if (!G.prof_on) return false;
-  const bool large = kind == 0 && bytes > kLargeLaunch;
+  const bool large = bytes > kLargeLaunch;
   if (kind == 0) {
     G.prof_all_count[0] += 1;
     G.prof_all_bytes[0] += bytes;
@@ -621,10 +621,11 @@ edf_status prof_flush(edf_problem* pb, Group& G) {
     G.prof_count[r.kind] += 1;
     G.prof_ms[r.kind] += ms;
     G.prof_bytes[r.kind] += r.bytes;
-    if (r.large) {
-      G.prof_count[2] += 1;
-      G.prof_ms[2] += ms;
-      G.prof_bytes[2] += r.bytes;
+    if (r.large) {  // [2]: smoother launches, [3]: V-cycles beyond the last-level cache
+      const int q = r.kind == 0 ? 2 : 3;
+      G.prof_count[q] += 1;
+      G.prof_ms[q] += ms;
+      G.prof_bytes[q] += r.bytes;
     }
   }
   G.prof_pending.clear();
@@ -3056,7 +3057,7 @@ edf_status edf_profile(edf_problem* pb, int32_t enable, double* out) {
   if (!pb) return EDF_ERR_ARG;
   edf_status e;
   if (out)
-    for (int q = 0; q < 13; ++q) out[q] = 0.0;
+    for (int q = 0; q < 16; ++q) out[q] = 0.0;
   for (Group& G : pb->groups) {
     if ((e = prof_flush(pb, G))) return e;
     if (out) {
@@ -3072,9 +3073,12 @@ edf_status edf_profile(edf_problem* pb, int32_t enable, double* out) {
       out[10] += G.prof_bytes[2];
       out[11] += G.prof_all_count[1];
       out[12] += G.prof_all_bytes[1];
+      out[13] += G.prof_count[3];
+      out[14] += G.prof_ms[3];
+      out[15] += G.prof_bytes[3];
     }
     if (enable) {
-      for (int k = 0; k < 3; ++k) G.prof_count[k] = G.prof_ms[k] = G.prof_bytes[k] = 0;
+      for (int k = 0; k < 4; ++k) G.prof_count[k] = G.prof_ms[k] = G.prof_bytes[k] = 0;
       for (int k = 0; k < 2; ++k) G.prof_all_count[k] = G.prof_all_bytes[k] = 0;
       G.prof_tick = 0;
     }

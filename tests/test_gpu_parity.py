@@ -558,6 +558,8 @@ def test_profile_counts_launches_and_algorithmic_bytes():
     assert pr["launches"] == len(range(0, 45, 13))
     assert pr["all_bytes"] == expect
     assert pr["vcycles"] == 1 and pr["vcycle_ms"] > 0 and pr["ms"] > 0
+    # two 33x33x9 samples: no launch and no V-cycle beyond the 256 MiB last-level cache
+    assert pr["large_vcycles"] == 0 and pr["large_all_launches"] == 0
     pb.destroy()
 
 
