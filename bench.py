@@ -83,7 +83,8 @@ def measured_traffic(smoother, wl_name, prec):
 # ---------------------------------------------------------------------------------------
 LARGE_LAUNCH = 256 * 1024 * 1024   # working sets beyond the 256 MiB last-level cache
 ZERO_START_BLOCKS = (0, 6, 18, 24)  # line sweep from zero: blocks read per column colour
-JX_FLOPS = 1902.0    # k_jx: FP64 operations per interior vertex of the compiled loop (FMA = 2)
+JX_FLOPS = 967.0     # k_jx: FP64 operations per hexahedron of the compiled loop and the rows
+                     # of its vertex (FMA = 2): one hexahedron per interior vertex
 JX_BYTES = 80.0      # k_jx: u, x, y, d (16 B each) + phi and K (8 B each) per vertex
 
 
@@ -210,8 +211,8 @@ def summarise_trace(d, leg, wl):
         out.append(f"| `{k}` | {n} | {us / n:.2f} | {us * 1e-3:.1f} | {100 * us * 1e-3 / allms:.1f} |")
     sweep, resid = _line_tables(wl)
     fin = {}
-    for q in wl.groups:   # k_jx grid: nx ny ceil(nz / 8) threads in 256-thread workgroups
-        fin[-(-q.nx * q.ny * -(-q.nz // 8) // 256) * 256] = q.nx * q.ny * q.nz
+    for q in wl.groups:   # k_jx grid: tiles of 15 x 15 vertex columns x ceil(nz / 8) segments
+        fin[-(-q.nx // 15) * -(-q.ny // 15) * -(-q.nz // 8) * 256] = q.nx * q.ny * q.nz
     agg = collections.defaultdict(lambda: [0, 0.0, 0.0, 0.0])
     hist = collections.defaultdict(collections.Counter)
     for r in sel:

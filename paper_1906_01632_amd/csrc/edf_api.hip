@@ -469,7 +469,9 @@ edf_status alloc_group(edf_problem* pb, Group& G) {
     if ((s = dalloc(pb, v, S * n))) return s;
   G.lv[0].u = G.u;
   if ((s = dalloc(pb, &G.ks, (size_t)S))) return s;
-  const size_t nb = std::max<size_t>(reduce_blocks(n), ceil_div(G.lv[0].g.off[8], kBlock));
+  const size_t nb = std::max<size_t>(
+      {(size_t)reduce_blocks(n), (size_t)ceil_div(G.lv[0].g.off[8], kBlock),
+       (size_t)jx_blocks(G.lv[0].g)});
   if ((s = dalloc(pb, &G.part, S * nb * 4))) return s;
   if ((s = dalloc(pb, &G.nmask, (size_t)S))) return s;
   if ((s = dalloc(pb, &G.active, (size_t)S))) return s;

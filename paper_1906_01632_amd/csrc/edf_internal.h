@@ -286,6 +286,8 @@ struct JacOp {
 int launch_jx(const Geom& g, const Phys& ph, const double* dts, const double* phi, const double* K,
               const double* u, const double* x, double* y, const double* d, double* part, int mode,
               int S, const int* mask, const int* list, int rows, hipStream_t st);
+// the partial sums per sample that launch_jx writes on grid g
+int jx_blocks(const Geom& g);
 void launch_spmv(const Geom& g, const JacOp& J, const double* x, double* y, int S,
                  const int* mask, hipStream_t st);
 // BiCGStab phases; `part` is scratch [S][nb][4], `ks` the per-sample scalars.

@@ -288,17 +288,17 @@ void launch_defect(const Geom& g, const Phys& ph, const double* dts, const doubl
 //           - ((rho1 - rho0) dc_f phi D_m d_d c + rho(c_f) phi D_m d_d(dc)) A,
 // plus the storage derivatives; Dirichlet rows are identity rows.
 //
-// One thread walks a segment of a vertical column (i, j) upwards, one layer of
-// hexahedra (between planes L and L + 1) at a time.  Of each of the (up to) 4 hexahedra
-// around the column in the layer it loads the 8 corners (state and direction, cache
-// resident) and evaluates the faces through the column's two vertices in the layer: the
-// vertical edge's face once (outflow of the lower vertex, inflow of the upper), and the x
-// and y faces at either end, 5 faces per hexahedron and layer.  The lower vertex is then
-// complete; the upper one carries its part into the next layer.
+// Every face is linearised once, by the hexahedron that holds it (12 per hexahedron).  A
+// workgroup takes a tile of kHexT x kHexT hexahedron columns and walks a segment of
+// layers upwards; per layer each thread evaluates its hexahedron's faces direction by
+// direction (sums and differences along the direction over the 4 edges, then the
+// bilinear weights 3/4 and 1/4 across it) and adds each face's fluxes to the edge's start
+// corner and subtracts them from its end corner.  The corners in the layer's lower plane
+// are then complete (the hexahedron below carried its upper ones up), go to LDS, and the
+// thread of each of the tile's inner kHexV x kHexV vertex columns sums the 4 hexahedra
+// around its vertex and finishes the rows.  Neighbouring tiles overlap by one hexahedron
+// column.
 // ---------------------------------------------------------------------------
-// linearised liquid and salt flux (yl, ys) out of the start vertex of the edge of the
-// face of direction D through corner (AX, AY, AZ) of a hexahedron with corner values
-// P, C (state) and XP, XC (direction, pressure in physical units); kmu = K / mu
 // the linearised fluxes of a face of direction D from the values at its integration
 // point: c, and the D-derivatives of p and c (not yet divided by h_D), of the state and of
 // the direction (t*); c and the direction's c at the edge's start (cA, xA) and end (cB, xB)
@@ -328,235 +328,197 @@ __device__ __forceinline__ void face_flux(double cf, double dp, double dc, doubl
        (ph.drho * tcf * dc + rf * tdc) * diff;
 }
 
-// linearised liquid and salt flux (yl, ys) out of the start vertex of the edge of the
-// face of direction D through corner (AX, AY, AZ) of a hexahedron with corner values
-// P, C (state) and XP, XC (direction, pressure in physical units); kmu = K / mu
-template <int AX, int AY, int AZ, int D>
-__device__ __forceinline__ void face_tangent_flux(const double* P, const double* C,
-                                                  const double* XP, const double* XC, double phi,
-                                                  double kmu, const Phys& ph, const FaceGeo& fg,
-                                                  double& yl, double& ys) {
-  using F = FaceT<AX, AY, AZ, D>;
-  constexpr int WA = F::SB0 + 2 * F::SB1 + 4 * F::SB2;  // the edge's start corner
-  constexpr int WB = WA + (1 << D);                      // and its end
-  double cf = 0.0, dp = 0.0, dc = 0.0, tcf = 0.0, tdp = 0.0, tdc = 0.0;
-#pragma unroll
-  for (int w = 0; w < 8; ++w) {
-    cf += F::N(w) * C[w];
-    dp += F::dN(w) * P[w];
-    dc += F::dN(w) * C[w];
-    tcf += F::N(w) * XC[w];
-    tdp += F::dN(w) * XP[w];
-    tdc += F::dN(w) * XC[w];
-  }
-  face_flux<D>(cf, dp, dc, tcf, tdp, tdc, C[WA], C[WB], XC[WA], XC[WB], phi, kmu, ph, fg, yl, ys);
-}
-
-// corner index of a hexahedron's corner a along direction D (0: x, 1: y), b across it
-// horizontally, z vertically
+// corner index of the point at position t along direction D and (a, b) along the other
+// two directions in increasing order
 template <int D>
-__host__ __device__ constexpr int hcorner(int a, int b, int z) {
-  return D == 0 ? a + 2 * b + 4 * z : b + 2 * a + 4 * z;
+__host__ __device__ constexpr int ecorner(int t, int a, int b) {
+  return D == 0 ? t + 2 * a + 4 * b : (D == 1 ? a + 2 * t + 4 * b : a + 2 * b + 4 * t);
 }
 
-// The two faces of direction D (0: x, 1: y) through the vertical edge of a hexahedron at
-// its corner (AX, AY), at the lower (z = 0) and the upper (z = 1) plane.  Their
-// integration points share the position across D, so the trilinear values are formed in
-// stages: sums and differences along D of the 4 edges of direction D, then the weights
-// 3/4 (the near edge) and 1/4 across D, then 3/4 and 1/4 in z for each face.  The faces'
-// fluxes go out of (into) the column's vertex when it is the edge's start (end), to
-// (Ll, Sl) for the lower face when lo and to (Lu, Su) for the upper one when hi.
-template <int D, int AX, int AY>
-__device__ __forceinline__ void horizontal_faces(const double* P, const double* C,
-                                                 const double* XP, const double* XC, double pe,
-                                                 double kmu, const Phys& ph, const FaceGeo& fg,
-                                                 bool lo, bool hi, double& Ll, double& Sl,
-                                                 double& Lu, double& Su) {
-  constexpr int at = D == 0 ? AY : AX;  // the column's position across D
-  constexpr int VD = D == 0 ? AX : AY;  // 0: the column's vertex is the edges' start
-  double Tc[2], Tdc[2], Tdp[2], Ttc[2], Ttdc[2], Ttdp[2];
+// the 4 faces of direction D of a hexahedron with corner values P, C, XP, XC: fluxes
+// added to (al, as) at each edge's start corner and subtracted at its end corner
+template <int D>
+__device__ __forceinline__ void hex_direction(const double* P, const double* C, const double* XP,
+                                              const double* XC, double pe, double kmu,
+                                              const Phys& ph, const FaceGeo& fg, double (&al)[8],
+                                              double (&as)[8]) {
+  // per edge e = a + 2 b: sums and differences along D
+  double sc[4], dc[4], dp[4], sx[4], dxc[4], dxp[4];
 #pragma unroll
-  for (int z = 0; z < 2; ++z) {
-    const int n1 = hcorner<D>(1, at, z), n0 = hcorner<D>(0, at, z);
-    const int f1 = hcorner<D>(1, 1 - at, z), f0 = hcorner<D>(0, 1 - at, z);
-    Tc[z] = 0.375 * (C[n1] + C[n0]) + 0.125 * (C[f1] + C[f0]);
-    Tdc[z] = 0.75 * (C[n1] - C[n0]) + 0.25 * (C[f1] - C[f0]);
-    Tdp[z] = 0.75 * (P[n1] - P[n0]) + 0.25 * (P[f1] - P[f0]);
-    Ttc[z] = 0.375 * (XC[n1] + XC[n0]) + 0.125 * (XC[f1] + XC[f0]);
-    Ttdc[z] = 0.75 * (XC[n1] - XC[n0]) + 0.25 * (XC[f1] - XC[f0]);
-    Ttdp[z] = 0.75 * (XP[n1] - XP[n0]) + 0.25 * (XP[f1] - XP[f0]);
+  for (int e = 0; e < 4; ++e) {
+    const int w0 = ecorner<D>(0, e & 1, e >> 1), w1 = ecorner<D>(1, e & 1, e >> 1);
+    sc[e] = C[w1] + C[w0];
+    dc[e] = C[w1] - C[w0];
+    dp[e] = P[w1] - P[w0];
+    sx[e] = XC[w1] + XC[w0];
+    dxc[e] = XC[w1] - XC[w0];
+    dxp[e] = XP[w1] - XP[w0];
+  }
+  // weights across D: 3/4 for the face's own edge, 1/4 for the other, per coordinate,
+  // first along a, then along b; the mean along D halves the sums
+  double tc[4], tdc[4], tdp[4], tx[4], tdxc[4], tdxp[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int o = e ^ 1;
+    tc[e] = 0.375 * sc[e] + 0.125 * sc[o];
+    tdc[e] = 0.75 * dc[e] + 0.25 * dc[o];
+    tdp[e] = 0.75 * dp[e] + 0.25 * dp[o];
+    tx[e] = 0.375 * sx[e] + 0.125 * sx[o];
+    tdxc[e] = 0.75 * dxc[e] + 0.25 * dxc[o];
+    tdxp[e] = 0.75 * dxp[e] + 0.25 * dxp[o];
   }
 #pragma unroll
-  for (int sz = 0; sz < 2; ++sz) {
-    if (!(sz ? hi : lo)) continue;
-    const int o = 1 - sz;
-    const int wa = hcorner<D>(0, at, sz), wb = hcorner<D>(1, at, sz);
+  for (int e = 0; e < 4; ++e) {
+    const int o = e ^ 2;
+    const int w0 = ecorner<D>(0, e & 1, e >> 1), w1 = ecorner<D>(1, e & 1, e >> 1);
     double yl, ys;
-    face_flux<D>(0.75 * Tc[sz] + 0.25 * Tc[o], 0.75 * Tdp[sz] + 0.25 * Tdp[o],
-                 0.75 * Tdc[sz] + 0.25 * Tdc[o], 0.75 * Ttc[sz] + 0.25 * Ttc[o],
-                 0.75 * Ttdp[sz] + 0.25 * Ttdp[o], 0.75 * Ttdc[sz] + 0.25 * Ttdc[o], C[wa],
-                 C[wb], XC[wa], XC[wb], pe, kmu, ph, fg, yl, ys);
-    double& L = sz ? Lu : Ll;
-    double& S = sz ? Su : Sl;
-    if (VD == 0) {
-      L += yl;
-      S += ys;
-    } else {
-      L -= yl;
-      S -= ys;
-    }
+    face_flux<D>(0.75 * tc[e] + 0.25 * tc[o], 0.75 * tdp[e] + 0.25 * tdp[o],
+                 0.75 * tdc[e] + 0.25 * tdc[o], 0.75 * tx[e] + 0.25 * tx[o],
+                 0.75 * tdxp[e] + 0.25 * tdxp[o], 0.75 * tdxc[e] + 0.25 * tdxc[o], C[w0], C[w1],
+                 XC[w0], XC[w1], pe, kmu, ph, fg, yl, ys);
+    al[w0] += yl;
+    as[w0] += ys;
+    al[w1] -= yl;
+    as[w1] -= ys;
   }
 }
 
-// Hexahedron of the layer with the column at its corner (AX, AY) (AX = 1: the hexahedron
-// on the column's -x side) whose corner (0, 0, 0) is vertex v0: adds the faces through
-// the lower vertex to (Ll, Sl) when lo, and those through the upper vertex to (Lu, Su)
-// when hi.
-template <int AX, int AY>
-__device__ __forceinline__ void layer_hex(const Geom& g, const double2* u, const double2* x,
-                                          int v0, double pe, double kmu, const Phys& ph,
-                                          const FaceGeo& fg, bool lo, bool hi, double& Ll,
-                                          double& Sl, double& Lu, double& Su) {
-  double P[8], C[8], XP[8], XC[8];
-  const int plane = g.nx * g.ny;
+// the state and the direction (pressure in physical units) at the corners w0 ... w0 + 3
+// of the hexahedron column's plane k
+__device__ __forceinline__ void hex_plane(const Geom& g, const double2* u, const double2* x,
+                                          int hi, int hj, int k, double p_unit, int w0, double* P,
+                                          double* C, double* XP, double* XC) {
 #pragma unroll
-  for (int w = 0; w < 8; ++w) {
-    const int v = v0 + (w & 1) + g.nx * (w >> 1 & 1) + plane * (w >> 2);
+  for (int w = 0; w < 4; ++w) {
+    const int v = hi + (w & 1) + g.nx * (hj + (w >> 1) + g.ny * k);
     const double2 a = u[v], b = x[v];
-    P[w] = a.x;
-    C[w] = a.y;
-    XP[w] = ph.p_unit * b.x;
-    XC[w] = b.y;
+    P[w0 + w] = a.x;
+    C[w0 + w] = a.y;
+    XP[w0 + w] = p_unit * b.x;
+    XC[w0 + w] = b.y;
   }
-  double yl, ys;  // the vertical edge's face: out of the lower vertex, into the upper
-  face_tangent_flux<AX, AY, 0, 2>(P, C, XP, XC, pe, kmu, ph, fg, yl, ys);
-  Ll += yl;
-  Sl += ys;
-  Lu -= yl;
-  Su -= ys;
-  horizontal_faces<0, AX, AY>(P, C, XP, XC, pe, kmu, ph, fg, lo, hi, Ll, Sl, Lu, Su);
-  horizontal_faces<1, AX, AY>(P, C, XP, XC, pe, kmu, ph, fg, lo, hi, Ll, Sl, Lu, Su);
 }
 
-struct ColumnCtx {
-  int i, j, s;
-  bool ex0, ex1, ey0, ey1;  // hexahedra on the -x / +x / -y / +y side of the column exist
-  double inv_mu, inv_dt;
-};
-
-// layer L (between planes L and L + 1): the lower vertex's rows (Ll, Sl) and porosity
-// sum ml gain this layer's part; (Lu, Su) and mu_ are set to the upper vertex's part
-__device__ __forceinline__ void column_layer(const Geom& g, const ColumnCtx& cx, const double* phi,
-                                             const double* K, const double2* u, const double2* x,
-                                             int L, const Phys& ph, const FaceGeo& fg, bool lo,
-                                             bool hi, double& Ll, double& Sl, double& ml,
-                                             double& Lu, double& Su, double& mu_) {
-  const int rx = g.nx - 1;
-  const int e0 = rx * ((g.ny - 1) * L) + cx.i + rx * cx.j;      // hexahedron (i, j, L)
-  const int v0 = cx.i + g.nx * (cx.j + g.ny * L);               // vertex (i, j, L)
-  double msum = 0.0;
-  Lu = 0.0;
-  Su = 0.0;
-  if (cx.ex1 && cx.ey1) {
-    msum += phi[e0];
-    layer_hex<0, 0>(g, u, x, v0, phi[e0], K[e0] * cx.inv_mu, ph, fg, lo, hi, Ll, Sl, Lu, Su);
-  }
-  if (cx.ex0 && cx.ey1) {
-    const int e = e0 - 1;
-    msum += phi[e];
-    layer_hex<1, 0>(g, u, x, v0 - 1, phi[e], K[e] * cx.inv_mu, ph, fg, lo, hi, Ll, Sl, Lu, Su);
-  }
-  if (cx.ex1 && cx.ey0) {
-    const int e = e0 - rx;
-    msum += phi[e];
-    layer_hex<0, 1>(g, u, x, v0 - g.nx, phi[e], K[e] * cx.inv_mu, ph, fg, lo, hi, Ll, Sl, Lu,
-                    Su);
-  }
-  if (cx.ex0 && cx.ey0) {
-    const int e = e0 - rx - 1;
-    msum += phi[e];
-    layer_hex<1, 1>(g, u, x, v0 - g.nx - 1, phi[e], K[e] * cx.inv_mu, ph, fg, lo, hi, Ll, Sl,
-                    Lu, Su);
-  }
-  ml += msum;
-  mu_ = msum;
-}
-
-// the finished rows of vertex (i, j, k): storage derivatives, Dirichlet identity rows,
-// the product written and the dots accumulated
+// the finished rows of vertex (i, j, k) from the sums of its faces' fluxes (Yl, Ys) and of
+// the porosity of the hexahedra around it: storage derivatives, Dirichlet identity rows,
+// the product written to *yv and the dots accumulated; xv, c, dv: the direction, the
+// state's c and (MODE != 0) the dot vector at the vertex
 template <int MODE>
-__device__ __forceinline__ void column_vertex(const Geom& g, const ColumnCtx& cx, const Phys& ph,
-                                              const double2* u, const double2* x, double2* y,
-                                              const double2* d, int k, double Yl, double Ys,
-                                              double msum, double (&acc)[2]) {
-  const int v = cx.i + g.nx * (cx.j + g.ny * k);
+__device__ __forceinline__ void vertex_rows(const Geom& g, const Phys& ph, int i, int j, int k,
+                                            double inv_dt, double2 xv, double c, double2 dv,
+                                            double Yl, double Ys, double msum, double2* yv,
+                                            double (&acc)[2]) {
   const double m = msum * (g.hx * g.hy * g.hz * 0.125);
-  const double2 xv = x[v];
-  const double c = u[v].y;
-  Yl += m * ph.drho * xv.y * cx.inv_dt;
-  Ys += m * (ph.rho0 + 2.0 * ph.drho * c) * xv.y * cx.inv_dt;
+  Yl += m * ph.drho * xv.y * inv_dt;
+  Ys += m * (ph.rho0 + 2.0 * ph.drho * c) * xv.y * inv_dt;
   double cD;
-  const double r0 = is_pin(g, cx.i, cx.j, k) ? xv.x : ph.s_row * Yl;
-  const double r1 = is_cdir(g, cx.i, cx.j, k, cD) ? xv.y : ph.s_row * Ys;
-  y[v] = make_double2(r0, r1);
+  const double r0 = is_pin(g, i, j, k) ? xv.x : ph.s_row * Yl;
+  const double r1 = is_cdir(g, i, j, k, cD) ? xv.y : ph.s_row * Ys;
+  *yv = make_double2(r0, r1);
   if (MODE != 0) {
-    const double2 dv = d[v];
     acc[0] += dv.x * r0 + dv.y * r1;
     if (MODE == 2) acc[1] += r0 * r0 + r1 * r1;
   }
 }
 
-// MODE as k_spmv: 0 plain, 1 with the dot (d, y), 2 with (d, y) and (y, y).  Thread t of a
-// sample row takes column t % (nx ny) and the segment t / (nx ny) of nseg equal segments
-// of the column's nz vertices.
+constexpr int kHexT = 16;         // hexahedron columns per tile side
+constexpr int kHexV = kHexT - 1;  // vertex columns finished per tile side
+static_assert(kHexT * kHexT == kBlock, "one hexahedron column per thread");
+
+// MODE as k_spmv: 0 plain, 1 with the dot (d, y), 2 with (d, y) and (y, y).  Workgroup b
+// of a sample row takes tile b % (ntx nty) (hexahedron columns from 15 tx - 1 and
+// 15 ty - 1; thread t the column (t % 16, t / 16) in it) and the segment b / (ntx nty) of
+// nseg equal segments of the nz vertices.
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_jx(Geom g, Phys ph0, const double* dts,
                                                const double* phi_all, const double* K_all,
                                                const double* u_all, const double* x_all,
                                                double* y_all, const double* d_all, double* part,
-                                               const int* mask, const int* list, int nseg) {
+                                               const int* mask, const int* list, int nseg, int ntx,
+                                               int nty) {
+  __shared__ double2 ex[2][4][kBlock];  // per layer parity: the corners' rows of each thread
+  __shared__ double exm[2][kBlock];     // and its porosity sum
   const int s = list ? list[blockIdx.y] : blockIdx.y;
   if (mask && !mask[s]) return;
   const Phys ph = sample_phys(ph0, dts, s);
-  const int ncol = g.nx * g.ny;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int tiles = ntx * nty;
+  const int seg = blockIdx.x / tiles, tile = blockIdx.x - seg * tiles;
+  const int ty = tile / ntx, tx = tile - ty * ntx;
+  const int tid = threadIdx.x, ta = tid % kHexT, tb = tid / kHexT;
+  const int hi = tx * kHexV - 1 + ta, hj = ty * kHexV - 1 + tb;  // hexahedron column
+  const bool hex = hi >= 0 && hi <= g.nx - 2 && hj >= 0 && hj <= g.ny - 2;
+  // the vertex column (hi, hj) is finished here when its 4 hexahedron columns are in the tile
+  const bool vert = ta >= 1 && tb >= 1 && hi < g.nx && hj < g.ny;
+  const double inv_mu = 1.0 / ph.mu, inv_dt = 1.0 / ph.dt;
+  const int k0 = (seg * g.nz) / nseg, k1 = ((seg + 1) * g.nz) / nseg;  // vertices [k0, k1)
+  const int cells = (g.nx - 1) * (g.ny - 1) * (g.nz - 1);
+  const double* phi = phi_all + (size_t)s * cells;
+  const double* K = K_all + (size_t)s * cells;
+  const double2* u = reinterpret_cast<const double2*>(u_all) + (size_t)s * g.N;
+  const double2* x = reinterpret_cast<const double2*>(x_all) + (size_t)s * g.N;
+  double2* y = reinterpret_cast<double2*>(y_all) + (size_t)s * g.N;
+  const double2* d = MODE ? reinterpret_cast<const double2*>(d_all) + (size_t)s * g.N : nullptr;
+  const FaceGeo fg = face_geo(g);
+  const int L0 = k0 > 0 ? k0 - 1 : 0, L1 = k1 - 1 < g.nz - 2 ? k1 - 1 : g.nz - 2;
+  double P[8], C[8], XP[8], XC[8];
+  if (hex) hex_plane(g, u, x, hi, hj, L0, ph.p_unit, 0, P, C, XP, XC);
+  // the upper corners' rows of the hexahedron below and its porosity
+  double cl[4] = {0.0, 0.0, 0.0, 0.0}, cs[4] = {0.0, 0.0, 0.0, 0.0}, cm = 0.0;
   double acc[2] = {0.0, 0.0};
-  if (t < ncol * nseg) {
-    ColumnCtx cx;
-    cx.s = s;
-    const int q = t % ncol, seg = t / ncol;
-    cx.i = q % g.nx;
-    cx.j = q / g.nx;
-    cx.ex0 = cx.i > 0;
-    cx.ex1 = cx.i < g.nx - 1;
-    cx.ey0 = cx.j > 0;
-    cx.ey1 = cx.j < g.ny - 1;
-    cx.inv_mu = 1.0 / ph.mu;
-    cx.inv_dt = 1.0 / ph.dt;
-    const int k0 = (seg * g.nz) / nseg, k1 = ((seg + 1) * g.nz) / nseg;  // vertices [k0, k1)
-    const size_t cells = (size_t)(g.nx - 1) * (g.ny - 1) * (g.nz - 1);
-    const double* phi = phi_all + s * cells;
-    const double* K = K_all + s * cells;
-    const double2* u = reinterpret_cast<const double2*>(u_all) + (size_t)s * g.N;
-    const double2* x = reinterpret_cast<const double2*>(x_all) + (size_t)s * g.N;
-    double2* y = reinterpret_cast<double2*>(y_all) + (size_t)s * g.N;
-    const double2* d = MODE ? reinterpret_cast<const double2*>(d_all) + (size_t)s * g.N : nullptr;
-    const FaceGeo fg = face_geo(g);
-    const int L0 = k0 > 0 ? k0 - 1 : 0, L1 = k1 - 1 < g.nz - 2 ? k1 - 1 : g.nz - 2;
-    // rows of the next vertex up (the layers below it done) and its porosity sum
-    double Yl = 0.0, Ys = 0.0, ms = 0.0;
+  // the rows of vertex (hi, hj, k) from the 4 hexahedron columns around it (this thread's
+  // corner 0, its -x neighbour's corner 1, -y: corner 2, -x -y: corner 3), then finished
+  auto finish = [&](int k) {
+    const int p = k & 1;
+    const double2 r0 = ex[p][0][tid], r1 = ex[p][1][tid - 1], r2 = ex[p][2][tid - kHexT],
+                  r3 = ex[p][3][tid - kHexT - 1];
+    const double ms =
+        exm[p][tid] + exm[p][tid - 1] + exm[p][tid - kHexT] + exm[p][tid - kHexT - 1];
+    const int v = hi + g.nx * (hj + g.ny * k);
+    const double2 xv = x[v], dv = MODE ? d[v] : make_double2(0.0, 0.0);
+    vertex_rows<MODE>(g, ph, hi, hj, k, inv_dt, xv, u[v].y, dv, r0.x + r1.x + r2.x + r3.x,
+                      r0.y + r1.y + r2.y + r3.y, ms, y + v, acc);
+  };
 #pragma unroll 1
-    for (int L = L0; L <= L1; ++L) {
-      const bool lo = L >= k0, hi = L + 1 < k1;
-      double Lu, Su, mu_;
-      column_layer(g, cx, phi, K, u, x, L, ph, fg, lo, hi, Yl, Ys, ms, Lu, Su, mu_);
-      if (lo) column_vertex<MODE>(g, cx, ph, u, x, y, d, L, Yl, Ys, ms, acc);
-      Yl = Lu;
-      Ys = Su;
-      ms = mu_;
+  for (int L = L0; L <= L1; ++L) {
+    double al[8], as[8], pe = 0.0;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) al[w] = as[w] = 0.0;
+    if (hex) {
+      const int e = hi + (g.nx - 1) * (hj + (g.ny - 1) * L);
+      pe = phi[e];
+      const double kmu = K[e] * inv_mu;
+      hex_plane(g, u, x, hi, hj, L + 1, ph.p_unit, 4, P, C, XP, XC);
+      hex_direction<0>(P, C, XP, XC, pe, kmu, ph, fg, al, as);
+      hex_direction<1>(P, C, XP, XC, pe, kmu, ph, fg, al, as);
+      hex_direction<2>(P, C, XP, XC, pe, kmu, ph, fg, al, as);
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        P[w] = P[w + 4];
+        C[w] = C[w + 4];
+        XP[w] = XP[w + 4];
+        XC[w] = XC[w + 4];
+      }
     }
-    // the top vertex has no layer above it
-    if (k1 == g.nz) column_vertex<MODE>(g, cx, ph, u, x, y, d, g.nz - 1, Yl, Ys, ms, acc);
+    const int p = L & 1;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      ex[p][w][tid] = make_double2(cl[w] + al[w], cs[w] + as[w]);
+      cl[w] = al[w + 4];
+      cs[w] = as[w + 4];
+    }
+    exm[p][tid] = cm + pe;
+    cm = pe;
+    __syncthreads();
+    if (vert && L >= k0) finish(L);
+  }
+  // the top plane has only the hexahedra below it
+  if (k1 == g.nz) {
+    const int p = (g.nz - 1) & 1;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) ex[p][w][tid] = make_double2(cl[w], cs[w]);
+    exm[p][tid] = cm;
+    __syncthreads();
+    if (vert) finish(g.nz - 1);
   }
   if (MODE == 1) {
     double a1[1] = {acc[0]};
@@ -567,30 +529,30 @@ __global__ __launch_bounds__(kBlock) void k_jx(Geom g, Phys ph0, const double* d
 }
 
 // vertices per column segment: short enough that a few active samples still give the
-// device many waves, long enough that the plane loaded twice per segment stays a small
-// part of the work
+// device many workgroups, long enough that the layer evaluated twice (below each
+// segment's first vertex) stays a small part of the work
 constexpr int kJxSegment = 8;
 
 int jx_blocks(const Geom& g) {
-  const int nseg = ceil_div(g.nz, kJxSegment);
-  return ceil_div(g.nx * g.ny * nseg, kBlock);
+  return ceil_div(g.nx, kHexV) * ceil_div(g.ny, kHexV) * ceil_div(g.nz, kJxSegment);
 }
 
 int launch_jx(const Geom& g, const Phys& ph, const double* dts, const double* phi, const double* K,
               const double* u, const double* x, double* y, const double* d, double* part, int mode,
               int S, const int* mask, const int* list, int rows, hipStream_t st) {
   const int nseg = ceil_div(g.nz, kJxSegment);
+  const int ntx = ceil_div(g.nx, kHexV), nty = ceil_div(g.ny, kHexV);
   const int nb = jx_blocks(g);
   dim3 grid(nb, rows);
   if (mode == 0)
     hipLaunchKernelGGL(k_jx<0>, grid, dim3(kBlock), 0, st, g, ph, dts, phi, K, u, x, y, d, part,
-                       mask, list, nseg);
+                       mask, list, nseg, ntx, nty);
   else if (mode == 1)
     hipLaunchKernelGGL(k_jx<1>, grid, dim3(kBlock), 0, st, g, ph, dts, phi, K, u, x, y, d, part,
-                       mask, list, nseg);
+                       mask, list, nseg, ntx, nty);
   else
     hipLaunchKernelGGL(k_jx<2>, grid, dim3(kBlock), 0, st, g, ph, dts, phi, K, u, x, y, d, part,
-                       mask, list, nseg);
+                       mask, list, nseg, ntx, nty);
   (void)S;
   return nb;
 }

@@ -375,8 +375,10 @@ def test_matrix_free_product_equals_the_assembled_jacobian():
     """The matrix-free J~ x (directional derivative of the defect at the state, upwind
     frozen) against the product with the assembled exact Jacobian, at random states and
     directions, every field model: equal to rounding (1e-12 of the largest entry).  The
-    second shape has columns of 19 vertices, walked in 3 segments."""
-    for (nx, ny, nz, levels), models in (((17, 13, 5, 3), (0, 1, 2, 3)), ((11, 9, 19, 2), (1, 2))):
+    second shape has columns of 19 vertices, walked in 3 segments; the third spans 4 x 2
+    tiles of hexahedron columns (a ragged last tile each way) and 2 segments."""
+    for (nx, ny, nz, levels), models in (((17, 13, 5, 3), (0, 1, 2, 3)), ((11, 9, 19, 2), (1, 2)),
+                                         ((49, 29, 13, 3), (2, 3))):
         for model in models:
             phys = synth.physics(model)
             xi = _xi(model, 2, seed=21)
