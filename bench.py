@@ -467,7 +467,8 @@ def make_problem(args, wl, phys, groups, prec, log_tuning=True):
     opts = dict(newton_rtol=wl.newton_rtol, lin_rtol=1e-6, lin_max_it=400 if args.adjoint else 100,
                 newton_max_it=20,
                 precision={"f64": PREC_F64, "mixed": PREC_MIXED, "mixed16": PREC_MIXED_F16}[prec],
-                check_every=1, forcing=args.forcing, concurrent_groups=args.concurrent_groups,
+                check_every=args.check_every, forcing=args.forcing,
+                concurrent_groups=args.concurrent_groups,
                 graph_vcycle=int(args.graph), substep_memory=int(args.substep_memory),
                 smoother=int(args.smoother), matrix_free=int(args.matrix_free),
                 predictor=int(args.predictor) if not args.adjoint else 0,
@@ -653,6 +654,9 @@ def main():
                          "previous step")
     ap.add_argument("--nu", type=int, nargs=2, default=[1, 1], metavar=("PRE", "POST"),
                     help="smoothing sweeps before and after the coarse correction")
+    ap.add_argument("--check-every", type=int, default=1,
+                    help="BiCGStab iterations between the host's checks of which samples are "
+                         "still active (launches run over the samples active at the last check)")
     ap.add_argument("--lag-preconditioner", type=int, default=0, choices=[0, 1],
                     help="1: assemble the V-cycle's matrices only at the first Newton iteration "
                          "of each (sub-)step attempt")
@@ -807,6 +811,7 @@ def main():
                    "substep_memory": bool(args.substep_memory),
                    "newton_predictor": bool(args.predictor),
                    "smoothing_sweeps": list(args.nu),
+                   "bicgstab_check_every": args.check_every,
                    "lagged_preconditioner": bool(args.lag_preconditioner),
                    "fused_bottom_from_level": tuning,
                    "line_sweep_columns_per_workgroup": tiles,
