@@ -1,0 +1,178 @@
+"""Host logic of the benchmark's measurement (CPU): the zero-start block counts, the
+algorithmic bytes it assigns to a traced smoother dispatch, the calibration of the HBM
+counters by the copy probe, and the source digest that voids a stale measurement."""
+import csv
+import json
+import math
+import os
+
+import pytest
+
+import bench
+import synth
+
+
+def _column_colour(i, j):
+    return (i % 2) + 2 * (j % 2)
+
+
+def test_zero_start_block_counts_follow_from_the_stencil():
+    """After a line sweep from zero, the columns of a colour read only the neighbouring
+    columns swept before them (3 blocks each: the vertex below, level, above); counted
+    here over the 8 neighbouring columns of a column of every colour."""
+    counts = []
+    for cc in range(4):
+        i, j = cc & 1, cc >> 1
+        earlier = sum(1 for dx in (-1, 0, 1) for dy in (-1, 0, 1)
+                      if (dx or dy) and _column_colour(i + dx + 2, j + dy + 2) < cc)
+        counts.append(3 * earlier)
+    assert tuple(counts) == bench.ZERO_START_BLOCKS
+
+
+def test_levels_halve_the_intervals():
+    wl = synth.workload("qmc512_mixedres")
+    lv = bench._levels(wl)
+    assert lv[:4] == [(33, 33, 9), (17, 17, 5), (9, 9, 3), (5, 5, 2)]
+    assert lv[-6:] == [(129, 129, 33), (65, 65, 17), (33, 33, 9), (17, 17, 5), (9, 9, 3),
+                       (5, 5, 2)]
+
+
+def _unique_sweep_key(sweep, nc, nz, cols):
+    keys = [k for k, v in sweep.items() if (nc, nz) in v and k[2] == cols and len(v) == 1]
+    assert keys, (nc, nz, cols)
+    return keys[0]
+
+
+@pytest.mark.parametrize("t,m,zc,tb,mb", [("float", "float", -1, 4, 4),
+                                          ("double", "double", -1, 8, 8),
+                                          ("float", "float", 2, 4, 4),
+                                          ("float", "_Float16", 3, 4, 2)])
+def test_dispatch_bytes_of_a_traced_line_sweep(t, m, zc, tb, mb):
+    """A dispatch named as rocprofv3 prints it, on the 129x129x33 grid (the column colour
+    the sweep form belongs to), 32 columns per workgroup, 3 active samples: per vertex of
+    the colour's columns the blocks read (4 values each) plus 16 vector values."""
+    wl = synth.workload("qmc512_mixedres")
+    sweep, resid = bench._line_tables(wl)
+    cc = max(zc, 0)
+    nc, nz = (65 - (cc & 1)) * (65 - (cc >> 1)), 33
+    bx, wx, cols = _unique_sweep_key(sweep, nc, nz, 32)
+    assert (bx, wx) == (math.ceil(nc / 32), 256)
+    name = f"void edf::k_line_sweep<{t}, {m}, true, {zc}, 32>(edf::Geom, {t} const*, int)"
+    nb = 24 if zc < 0 else bench.ZERO_START_BLOCKS[zc]
+    got = bench._dispatch_bytes(name, bx, wx, bx * wx, 3, sweep, resid)
+    assert got == 3 * nc * nz * (4 * (nb + 1) * mb + 16 * tb)
+
+
+def test_dispatch_bytes_ignore_other_kernels_and_ambiguous_grids():
+    wl = synth.workload("qmc512_mixedres")
+    sweep, resid = bench._line_tables(wl)
+    assert bench._dispatch_bytes("void edf::k_jx<1>(edf::Geom)", 1, 256, 256, 1, sweep,
+                                 resid) is None
+    ambiguous = [k for k, v in sweep.items() if len(v) > 1 and k[1] == 256]
+    if ambiguous:
+        bx, wx, cols = ambiguous[0]
+        name = f"void edf::k_line_sweep<float, float, true, -1, {cols}>(edf::Geom)"
+        assert bench._dispatch_bytes(name, bx, wx, bx * wx, 1, sweep, resid) is None
+
+
+def _write_run(d, dispatches, counters):
+    os.makedirs(d, exist_ok=True)
+    with open(os.path.join(d, "run_kernel_trace.csv"), "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp",
+                    "Grid_Size_X", "Workgroup_Size_X", "Grid_Size_Y"])
+        for row in dispatches:
+            w.writerow(row)
+    with open(os.path.join(d, "run_counter_collection.csv"), "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Dispatch_Id", "Counter_Name", "Counter_Value"])
+        for di, v in counters.items():
+            w.writerow([di, "C", v])
+
+
+def test_counter_summary_is_calibrated_by_the_isolated_copy_probe(tmp_path):
+    """A sweep dispatch before the probe, the probe (a 1 GiB copy alone in 0.2 s of idle
+    time either side; FETCH_SIZE counts it as 524,288 KiB, WRITE_SIZE as 1,048,576 KiB),
+    then two sweep dispatches and another kernel: only the two count, scaled by 2 and 1."""
+    wl = synth.workload("qmc512_mixedres")
+    sweep, _ = bench._line_tables(wl)
+    nc, nz = 65 * 65, 33
+    bx, wx, cols = _unique_sweep_key(sweep, nc, nz, 32)
+    name = "void edf::k_line_sweep<float, float, true, -1, 32>(edf::Geom, float const*)"
+    s = 10 ** 9  # ns
+    disp = [(1, name, 0, s // 10, bx * wx, wx, 8),
+            (2, "__amd_rocclr_copyBuffer", 2 * s, 2 * s + s // 100, 4096, 256, 1),
+            (3, name, 3 * s, 3 * s + s // 1000, bx * wx, wx, 8),
+            (4, "void edf::k_restrict<float>(edf::Geom)", 3 * s + s // 500, 3 * s + s // 400,
+             256, 256, 8),
+            (5, name, 3 * s + s // 100, 3 * s + s // 90, bx * wx, wx, 16)]
+    alg = [8 * nc * nz * 464, 16 * nc * nz * 464]
+    fetch = {1: 7.0, 2: 524288.0, 3: 0.55 * alg[0] / 1024, 4: 3.0, 5: 0.5 * alg[1] / 1024}
+    write = {1: 7.0, 2: 1048576.0, 3: 0.02 * alg[0] / 1024, 4: 3.0, 5: 0.01 * alg[1] / 1024}
+    _write_run(str(tmp_path / "F"), disp, fetch)
+    _write_run(str(tmp_path / "W"), disp, write)
+    rec = bench.summarise_counters(str(tmp_path / "F"), str(tmp_path / "W"), wl, "mixed", 1,
+                                   "cmd")
+    assert rec["FETCH_SIZE"]["scale"] == pytest.approx(2.0)
+    assert rec["WRITE_SIZE"]["scale"] == pytest.approx(1.0)
+    a = rec["all"]
+    assert a["dispatches"] == 2
+    assert a["algorithmic_bytes_per_dispatch"] == pytest.approx(sum(alg) / 2)
+    hbm = 2.0 * (0.55 * alg[0] + 0.5 * alg[1]) + (0.02 * alg[0] + 0.01 * alg[1])
+    assert a["ratio"] == pytest.approx(hbm / sum(alg))
+    # both launches exceed 256 MiB of algorithmic bytes
+    assert rec["large"]["dispatches"] == 2
+
+
+def test_counter_summary_needs_an_isolated_probe(tmp_path):
+    wl = synth.workload("qmc512_mixedres")
+    name = "void edf::k_line_sweep<float, float, true, -1, 32>(edf::Geom)"
+    disp = [(1, name, 0, 100, 256, 256, 1),
+            (2, "__amd_rocclr_copyBuffer", 200, 300, 4096, 256, 1),  # no idle time around it
+            (3, name, 400, 500, 256, 256, 1)]
+    _write_run(str(tmp_path / "F"), disp, {1: 1.0, 2: 1.0, 3: 1.0})
+    _write_run(str(tmp_path / "W"), disp, {1: 1.0, 2: 1.0, 3: 1.0})
+    with pytest.raises(SystemExit):
+        bench.summarise_counters(str(tmp_path / "F"), str(tmp_path / "W"), wl, "mixed", 1, "c")
+
+
+def _fake_root(tmp_path, body):
+    csrc = tmp_path / "paper_1906_01632_amd" / "csrc"
+    csrc.mkdir(parents=True, exist_ok=True)
+    for name in bench.KERNEL_SOURCES[1]:
+        (csrc / name).write_text(body)
+    return str(tmp_path)
+
+
+def test_digest_ignores_comments_and_spacing_but_not_code(tmp_path, monkeypatch):
+    code = "int f(int a) {\n  return a + 1;  // one more\n}\n/* block */\n"
+    monkeypatch.setattr(bench, "ROOT", _fake_root(tmp_path / "a", code))
+    d0 = bench.kernel_digest(bench.KERNEL_SOURCES[1])
+    monkeypatch.setattr(bench, "ROOT", _fake_root(tmp_path / "b", "int f(int a)   {\n"
+                                                  "  // reworded\n  return a + 1;\n}\n"))
+    assert bench.kernel_digest(bench.KERNEL_SOURCES[1]) == d0
+    monkeypatch.setattr(bench, "ROOT", _fake_root(tmp_path / "c",
+                                                  "int f(int a) { return a + 2; }"))
+    assert bench.kernel_digest(bench.KERNEL_SOURCES[1]) != d0
+
+
+def test_measured_traffic_is_void_once_the_smoother_changes(tmp_path, monkeypatch):
+    root = _fake_root(tmp_path, "int g() { return 0; }")
+    monkeypatch.setattr(bench, "ROOT", root)
+    rec = {"smoother": 1, "workload": "qmc512_mixedres",
+           "kernel_sources_sha256": bench.kernel_digest(bench.KERNEL_SOURCES[1]),
+           "precisions": {"mixed": {"large": {"ratio": 1.05}}}}
+    os.makedirs(os.path.join(root, "profiles"))
+    with open(os.path.join(root, "profiles", "smoother_traffic.json"), "w") as f:
+        json.dump(rec, f)
+    assert bench.measured_traffic(1, "qmc512_mixedres", "mixed") == {"large": {"ratio": 1.05}}
+    assert bench.measured_traffic(1, "mixed257", "mixed") is None
+    (tmp_path / "paper_1906_01632_amd" / "csrc" / "line_kernels.hip").write_text(
+        "int g() { return 1; }")
+    assert bench.measured_traffic(1, "qmc512_mixedres", "mixed") is None
+
+
+def test_committed_traffic_matches_the_committed_smoother():
+    """The ratios in profiles/ were taken on the smoother code in the tree."""
+    assert bench.measured_traffic(1, "qmc512_mixedres", "mixed") is not None
+    assert bench.measured_traffic(1, "qmc512_mixedres", "f64") is not None
