@@ -176,3 +176,41 @@ def test_committed_traffic_matches_the_committed_smoother():
     """The ratios in profiles/ were taken on the smoother code in the tree."""
     assert bench.measured_traffic(1, "qmc512_mixedres", "mixed") is not None
     assert bench.measured_traffic(1, "qmc512_mixedres", "f64") is not None
+
+
+def test_trace_summary_selects_the_leg_and_counts_busy_time_once(tmp_path):
+    """Two marked ranges of timed steps; the summary of the second counts only its
+    kernels, overlapping kernels once in the busy time, and gives the matrix-free product
+    (launched as tiles of 15 x 15 vertex columns times segments of 8 vertices, 256 threads
+    each) its 80 B per vertex of the 129x129x33 group."""
+    wl = synth.workload("qmc512_mixedres")
+    d = tmp_path / "trace"
+    d.mkdir()
+    us = 1000  # ns
+    jx_grid = 9 * 9 * 5 * 256
+    kernels = [  # id, name, start, end, grid x, workgroup x, grid y
+        (1, "void edf::k_bicg_p(unsigned long)", 10 * us, 20 * us, 256, 256, 4),
+        (2, "void edf::k_bicg_p(unsigned long)", 110 * us, 130 * us, 256, 256, 4),
+        (3, "void edf::k_jx<1>(edf::Geom, edf::Phys)", 120 * us, 160 * us, jx_grid, 256, 2),
+        (4, "void edf::k_bicg_s(unsigned long)", 170 * us, 180 * us, 256, 256, 4),
+        (5, "void edf::k_bicg_s(unsigned long)", 300 * us, 310 * us, 256, 256, 4)]
+    with open(d / "t_kernel_trace.csv", "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp",
+                    "Grid_Size_X", "Workgroup_Size_X", "Grid_Size_Y"])
+        w.writerows(kernels)
+    with open(d / "t_marker_api_trace.csv", "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Function", "Start_Timestamp", "End_Timestamp"])
+        w.writerow(["timed steps", 0, 50 * us])
+        w.writerow(["timed steps", 100 * us, 200 * us])
+    out = bench.summarise_trace(str(d), 1, wl)
+    assert "timed-steps range 1 of 2" in out
+    # busy: [110, 160] and [170, 180] us = 60 us of a 100 us range
+    assert "GPU busy 0.1 ms (60.0 %)" in out
+    assert "| `k_bicg_p` | 1 |" in out and "| `k_bicg_s` | 1 |" in out
+    row = [l for l in out.split("\n") if l.startswith("| k_jx (finest grids)")]
+    assert len(row) == 1
+    cells = [c.strip() for c in row[0].split("|")]
+    assert cells[2] == "1" and float(cells[3]) == pytest.approx(40.0)
+    assert float(cells[4]) == pytest.approx(bench.JX_BYTES * 129 * 129 * 33 * 2 / 1e6, rel=1e-3)
