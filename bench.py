@@ -189,8 +189,9 @@ def summarise_trace(d, leg, wl):
     iv = []
     for r in sel:
         s, e = int(_col(r, "Start_Timestamp")), int(_col(r, "End_Timestamp"))
-        tot[short(_col(r, "Kernel_Name"))][0] += 1
-        tot[short(_col(r, "Kernel_Name"))][1] += (e - s) * 1e-3
+        k = short(_readable_name(_col(r, "Kernel_Name")))
+        tot[k][0] += 1
+        tot[k][1] += (e - s) * 1e-3
         iv.append((s, e))
     iv.sort()
     busy, cs, ce = 0, None, None
@@ -216,7 +217,7 @@ def summarise_trace(d, leg, wl):
     agg = collections.defaultdict(lambda: [0, 0.0, 0.0, 0.0])
     hist = collections.defaultdict(collections.Counter)
     for r in sel:
-        name = _col(r, "Kernel_Name")
+        name = _readable_name(_col(r, "Kernel_Name"))
         k = short(name)
         dur = (int(_col(r, "End_Timestamp")) - int(_col(r, "Start_Timestamp"))) * 1e-9
         gx, gy = int(_col(r, "Grid_Size_X")), int(_col(r, "Grid_Size_Y"))
@@ -249,23 +250,25 @@ def summarise_trace(d, leg, wl):
     return "\n".join(out)
 
 
-def _counter_run(d, regex, sweep, resid):
-    """Counter totals of one `rocprofv3 --pmc C --kernel-trace` run of this script with
-    --copy-probe: (KiB the probe's copy dispatches read or wrote, accumulators of the
-    matching dispatches after it: all, and those beyond 256 MiB of algorithmic bytes)."""
+def _readable_name(name):
+    """rocprofv3 leaves the _Float16 instances of the line kernels mangled; their demangled
+    form (as for the other instances), or the name unchanged."""
     import re
-    times, grids = {}, {}
-    for r in _csv(d, "kernel_trace.csv"):
-        di = int(_col(r, "Dispatch_Id"))
-        times[di] = (int(_col(r, "Start_Timestamp")), int(_col(r, "End_Timestamp")), _col(r, "Kernel_Name"))
-        gx, wx = int(_col(r, "Grid_Size_X")), int(_col(r, "Workgroup_Size_X"))
-        grids[di] = (gx // wx, wx, gx, int(_col(r, "Grid_Size_Y")))
-    per = {}
-    for r in _csv(d, "counter_collection.csv"):
-        di = int(_col(r, "Dispatch_Id"))
-        per[di] = per.get(di, 0.0) + float(_col(r, "Counter_Value"))
-    # the probe: copy dispatches with 0.2 s or more of idle time before and after them
-    order = sorted(times, key=lambda x: times[x][0])
+    flag = {"0": "false", "1": "true"}
+    m = re.search(r"k_line_(sweep|smooth)IfDF16_Lb([01])ELi(n?\d+)E(?:Li(\d+)E)?E", name)
+    if m:
+        zc = m.group(3).replace("n", "-")
+        cols = f", {m.group(4)}" if m.group(4) else ""
+        return f"void edf::k_line_{m.group(1)}<float, _Float16, {flag[m.group(2)]}, {zc}{cols}>()"
+    m = re.search(r"k_line_residual_zsIfDF16_Lb([01])EE", name)
+    if m:
+        return f"void edf::k_line_residual_zs<float, _Float16, {flag[m.group(1)]}>()"
+    return name
+
+
+def _probe(order, times):
+    """The copy probe's dispatches: the last group of copy dispatches with 0.2 s or more
+    of idle time before and after it (order: dispatch ids by start time)."""
     probe = []
     for n, di in enumerate(order):
         if "copyBuffer" not in times[di][2] or (n and times[di][0] - times[order[n - 1]][1] < 0.2e9):
@@ -277,6 +280,35 @@ def _counter_run(d, regex, sweep, resid):
             m += 1
         if m == len(order) or times[order[m]][0] - times[order[m - 1]][1] >= 0.2e9:
             probe = grp
+    return probe
+
+
+def _load_counter_run(d):
+    """(times, grids, per-dispatch counter totals) of one `rocprofv3 --pmc C --kernel-trace`
+    run: times[id] = (start, end, readable name), grids[id] = (workgroups along x,
+    workgroup size, grid x, grid y)."""
+    times, grids = {}, {}
+    for r in _csv(d, "kernel_trace.csv"):
+        di = int(_col(r, "Dispatch_Id"))
+        times[di] = (int(_col(r, "Start_Timestamp")), int(_col(r, "End_Timestamp")),
+                     _readable_name(_col(r, "Kernel_Name")))
+        gx, wx = int(_col(r, "Grid_Size_X")), int(_col(r, "Workgroup_Size_X"))
+        grids[di] = (gx // wx, wx, gx, int(_col(r, "Grid_Size_Y")))
+    per = {}
+    for r in _csv(d, "counter_collection.csv"):
+        di = int(_col(r, "Dispatch_Id"))
+        per[di] = per.get(di, 0.0) + float(_col(r, "Counter_Value"))
+    return times, grids, per
+
+
+def _counter_run(d, regex, sweep, resid):
+    """Counter totals of one `rocprofv3 --pmc C --kernel-trace` run of this script with
+    --copy-probe: (KiB the probe's copy dispatches read or wrote, accumulators of the
+    matching dispatches after it: all, and those beyond 256 MiB of algorithmic bytes)."""
+    import re
+    times, grids, per = _load_counter_run(d)
+    order = sorted(times, key=lambda x: times[x][0])
+    probe = _probe(order, times)
     if not probe:
         raise SystemExit(f"no isolated copy probe in {d}")
     acc = {"all": [0, 0.0, 0.0], "large": [0, 0.0, 0.0]}
@@ -314,6 +346,95 @@ def summarise_counters(fetch_dir, write_dir, wl, precision, smoother, command):
                   "hbm_fetch_bytes_per_dispatch": fetch, "hbm_write_bytes_per_dispatch": write,
                   "ratio": fs * fa[k][1] * 1024.0 / fa[k][2] + ws * wa[k][1] * 1024.0 / wa[k][2]}
     return rec
+
+
+def counter_table(fetch_dir, write_dir, wl, by_matrix=False):
+    """Markdown per-kernel HBM traffic of a FETCH_SIZE and a WRITE_SIZE run (each with
+    --kernel-trace, of this script with --copy-probe): per kernel the dispatches after the
+    probe, counted bytes (each counter scaled by what it reads for the probe's 1 GiB copy),
+    the library's algorithmic bytes where it has them, their ratio and the counted GB/s
+    over the fetch run's durations.  by_matrix: the line kernels split by the matrix type
+    (FP16 / FP32) and a column of the share of kernel time; else launches beyond 256 MiB
+    in rows of their own and the matrix-free product's bytes per finest grid."""
+    import re
+    sweep, resid = _line_tables(wl)
+    short = lambda n: n.split("(")[0].replace("void ", "").replace("edf::", "")
+    out, runs = [], {}
+    for tag, d in (("fetch", fetch_dir), ("write", write_dir)):
+        times, grids, per = _load_counter_run(d)
+        order = sorted(times, key=lambda x: times[x][0])
+        probe = _probe(order, times)
+        if not probe:
+            raise SystemExit(f"no isolated copy probe in {d}")
+        kib = sum(per.get(x, 0.0) for x in probe)
+        if not by_matrix:
+            out.append(f"{tag} probe dispatches {len(probe)} KiB {kib}")
+        scale = 1024.0 * 1024.0 / kib
+        acc = {}
+        for di in order:
+            if times[di][0] <= times[probe[-1]][0]:
+                continue
+            name = times[di][2]
+            bx, wx, gx, gy = grids[di]
+            b = _dispatch_bytes(name, bx, wx, gx, gy, sweep, resid)
+            base = re.sub(r"<.*", "", short(name))
+            if by_matrix and base in ("k_line_sweep", "k_line_residual_zs"):
+                keys = (base + (" (FP16 matrix)" if "_Float16" in name else " (FP32 matrix)"),)
+            elif by_matrix:
+                keys = (base,)
+            else:
+                keys = (base,) + ((base + " (>256MiB)",) if b and b > LARGE_LAUNCH else ())
+            for k in keys:
+                a = acc.setdefault(k, [0, 0.0, 0.0, 0.0])
+                a[0] += 1
+                a[1] += per.get(di, 0.0) * 1024 * scale
+                a[2] += b or 0.0
+                a[3] += (times[di][1] - times[di][0]) * 1e-9
+        runs[tag] = (scale, acc, times, grids, per)
+    (fs, fa, ft, fg, fp), (ws, wa, wt, wg, wp) = runs["fetch"], runs["write"]
+    if by_matrix:
+        tot = sum(v[3] for v in fa.values())
+        out += ["| kernel | dispatches | % of kernel time | fetch MB/disp | write MB/disp | "
+                "algorithmic MB/disp | (fetch+write)/alg | counted HBM GB/s |",
+                "|---|---|---|---|---|---|---|---|"]
+        for k in sorted(fa, key=lambda k: -fa[k][3])[:14]:
+            n, fb, ab, t = fa[k]
+            wb = wa.get(k, [1, 0.0])[1] / max(wa.get(k, [1])[0], 1) * n
+            r = f"{(fb + wb) / ab:.3f}" if ab else "-"
+            out.append(f"| {k} | {n} | {100 * t / tot:.1f} | {fb / n / 1e6:.1f} | {wb / n / 1e6:.1f} | "
+                       f"{ab / n / 1e6:.1f} | {r} | {(fb + wb) / t / 1e9:.0f} |")
+        return "\n".join(out)
+    out += [f"probe scales: fetch {fs:.3f}, write {ws:.3f}",
+            "| kernel | dispatches | fetch MB/disp | write MB/disp | algorithmic MB/disp | "
+            "(fetch+write)/alg | HBM GB/s (counted, fetch run durations) |",
+            "|---|---|---|---|---|---|---|"]
+    for k in sorted(fa, key=lambda k: -fa[k][1])[:22]:
+        n, f, b, t = fa[k]
+        w = wa.get(k, [0, 0.0, 0.0, 0.0])[1]
+        ratio = (f + w) / b if b else float("nan")
+        out.append(f"| {k} | {n} | {f / n / 1e6:.2f} | {w / max(wa.get(k, [1])[0], 1) / 1e6:.2f} | "
+                   f"{b / n / 1e6:.2f} | {ratio:.3f} | {(f + w) / t / 1e9 if t else 0:.0f} |")
+    # the matrix-free product: JX_BYTES per vertex of its finest grid (tiles of 15 x 15
+    # vertex columns times segments of 8 vertices, 256 threads each)
+    fin = {}
+    for q in wl.groups:
+        fin[-(-q.nx // 15) * -(-q.ny // 15) * -(-q.nz // 8) * 256] = q.nx * q.ny * q.nz
+    for tag, (scale, _, times, grids, per) in (("fetch", runs["fetch"]), ("write", runs["write"])):
+        tj = {}
+        for di, (t0, t1, name) in times.items():
+            if "k_jx" not in name or grids[di][2] not in fin:
+                continue
+            gx, gy = grids[di][2], grids[di][3]
+            a = tj.setdefault(gx, [0, 0.0, 0.0, 0.0])
+            a[0] += 1
+            a[1] += per.get(di, 0.0) * 1024 * scale
+            a[2] += JX_BYTES * fin[gx] * gy
+            a[3] += (t1 - t0) * 1e-9
+        for gx, (n, c, b, t) in sorted(tj.items()):
+            out.append(f"k_jx {tag} grid {gx} ({fin[gx]} vertices): {n} dispatches, counted "
+                       f"{c / n / 1e6:.1f} MB, algorithmic {b / n / 1e6:.1f} MB per dispatch, "
+                       f"ratio {c / b:.2f}, {c / t / 1e9:.0f} GB/s")
+    return "\n".join(out)
 
 
 # quantity of interest of the gradient workload: salt mass in the bottom 50 m under
@@ -704,15 +825,24 @@ def main():
                     help="HBM traffic of the smoother from rocprofv3 --pmc FETCH_SIZE and "
                          "WRITE_SIZE runs (each with --kernel-trace) of this script with "
                          "--copy-probe; added to --summary-out under --precision; no GPU is used")
+    ap.add_argument("--counters-table", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    default=None,
+                    help="per-kernel HBM traffic (markdown) of the same two counter runs; "
+                         "no GPU is used")
+    ap.add_argument("--by-matrix", action="store_true",
+                    help="with --counters-table: line kernels split by matrix type")
     ap.add_argument("--summary-out", default=None)
     ap.add_argument("--profile-command", default="",
                     help="with --summarise-counters: the command that made the counter runs")
     args = ap.parse_args()
-    if args.summarise_trace or args.summarise_counters:
+    if args.summarise_trace or args.summarise_counters or args.counters_table:
         import synth
         wl = synth.workload(args.workload)
         if args.summarise_trace:
             print(summarise_trace(args.summarise_trace, args.leg, wl))
+            return
+        if args.counters_table:
+            print(counter_table(*args.counters_table, wl, args.by_matrix))
             return
         prec = args.precision or "mixed"
         rec = summarise_counters(*args.summarise_counters, wl, prec, args.smoother,

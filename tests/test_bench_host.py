@@ -214,3 +214,82 @@ def test_trace_summary_selects_the_leg_and_counts_busy_time_once(tmp_path):
     cells = [c.strip() for c in row[0].split("|")]
     assert cells[2] == "1" and float(cells[3]) == pytest.approx(40.0)
     assert float(cells[4]) == pytest.approx(bench.JX_BYTES * 129 * 129 * 33 * 2 / 1e6, rel=1e-3)
+
+
+def test_mangled_fp16_instances_read_as_their_template_arguments():
+    """rocprofv3 prints the _Float16 instances of the line kernels mangled."""
+    assert bench._readable_name(
+        "_ZN3edf12k_line_sweepIfDF16_Lb1ELin1ELi32EEEvNS_4GeomEiPKT0_PKT_S7_PS5_PKiSA_") == \
+        "void edf::k_line_sweep<float, _Float16, true, -1, 32>()"
+    assert bench._readable_name(
+        "_ZN3edf12k_line_sweepIfDF16_Lb0ELi3ELi8EEEvNS_4GeomEiPKT0_PKT_S7_PS5_PKiSA_") == \
+        "void edf::k_line_sweep<float, _Float16, false, 3, 8>()"
+    assert bench._readable_name(
+        "_ZN3edf13k_line_smoothIfDF16_Lb1ELi2EEEvNS_4GeomEiPKT0_PKT_S7_PS5_PKiSA_") == \
+        "void edf::k_line_smooth<float, _Float16, true, 2>()"
+    assert bench._readable_name(
+        "_ZN3edf18k_line_residual_zsIfDF16_Lb0EEEvNS_4GeomEPKT0_PKT_S7_PS5_PKiSA_") == \
+        "void edf::k_line_residual_zs<float, _Float16, false>()"
+    plain = "void edf::k_line_sweep<float, float, true, -1, 32>(edf::Geom)"
+    assert bench._readable_name(plain) == plain
+
+
+def _table_runs(tmp_path, sweep_names):
+    wl = synth.workload("qmc512_mixedres")
+    sweep, _ = bench._line_tables(wl)
+    nc, nz = 65 * 65, 33
+    bx, wx, cols = _unique_sweep_key(sweep, nc, nz, 32)
+    s = 10 ** 9
+    jx_grid = 9 * 9 * 5 * 256
+    disp = [(1, "__amd_rocclr_copyBuffer", s, s + s // 100, 4096, 256, 1)]
+    fetch, write = {1: 524288.0}, {1: 1048576.0}
+    t = 2 * s
+    for n, name in enumerate(sweep_names):
+        disp.append((2 + n, name, t, t + s // 1000, bx * wx, wx, 8))
+        fetch[2 + n], write[2 + n] = 400000.0 * (n + 1), 10000.0
+        t += s // 100
+    disp.append((9, "void edf::k_jx<1>(edf::Geom, edf::Phys)", t, t + s // 2000, jx_grid, 256, 4))
+    fetch[9], write[9] = 300000.0, 40000.0
+    _write_run(str(tmp_path / "F"), disp, fetch)
+    _write_run(str(tmp_path / "W"), disp, write)
+    return wl, nc, nz
+
+
+def test_counter_table_rows_and_the_matrix_free_product(tmp_path):
+    f32 = "void edf::k_line_sweep<float, float, true, -1, 32>(edf::Geom)"
+    wl, nc, nz = _table_runs(tmp_path, [f32, f32])
+    out = bench.counter_table(str(tmp_path / "F"), str(tmp_path / "W"), wl)
+    lines = out.split("\n")
+    assert lines[0] == "fetch probe dispatches 1 KiB 524288.0"
+    assert "probe scales: fetch 2.000, write 1.000" in lines
+    row = [l for l in lines if l.startswith("| k_line_sweep |")][0].split("|")
+    alg = 8 * nc * nz * (4 * 25 * 4 + 16 * 4)
+    fetch = 2.0 * (400000.0 + 800000.0) * 1024 / 2
+    write = 10000.0 * 1024
+    assert int(row[2]) == 2
+    assert float(row[3]) == pytest.approx(fetch / 1e6, abs=0.01)
+    assert float(row[4]) == pytest.approx(write / 1e6, abs=0.01)
+    assert float(row[5]) == pytest.approx(alg / 1e6, abs=0.01)
+    assert float(row[6]) == pytest.approx((fetch + write) / alg, abs=1e-3)
+    assert any(l.startswith("| k_line_sweep (>256MiB) | 2 |") for l in lines)
+    jx = [l for l in lines if l.startswith("k_jx fetch grid 103680 (549153 vertices)")]
+    assert len(jx) == 1
+    assert f"algorithmic {bench.JX_BYTES * 549153 * 4 / 1e6:.1f} MB per dispatch" in jx[0]
+    assert f"counted {2.0 * 300000.0 * 1024 / 1e6:.1f} MB" in jx[0]
+
+
+def test_counter_table_by_matrix_type(tmp_path):
+    f16 = "_ZN3edf12k_line_sweepIfDF16_Lb1ELin1ELi32EEEvNS_4GeomEiPKT0_PKT_S7_PS5_PKiSA_"
+    f32 = "void edf::k_line_sweep<float, float, true, -1, 32>(edf::Geom)"
+    wl, nc, nz = _table_runs(tmp_path, [f16, f32])
+    out = bench.counter_table(str(tmp_path / "F"), str(tmp_path / "W"), wl, by_matrix=True)
+    rows = {l.split("|")[1].strip(): l.split("|") for l in out.split("\n")
+            if l.startswith("| k_")}
+    assert set(rows) == {"k_line_sweep (FP16 matrix)", "k_line_sweep (FP32 matrix)", "k_jx"}
+    for key, mb, counted in (("k_line_sweep (FP16 matrix)", 2, 400000.0),
+                             ("k_line_sweep (FP32 matrix)", 4, 800000.0)):
+        r = rows[key]
+        alg = 8 * nc * nz * (4 * 25 * mb + 16 * 4)
+        assert float(r[6]) == pytest.approx(alg / 1e6, abs=0.1)
+        assert float(r[7]) == pytest.approx((2.0 * counted + 10000.0) * 1024 / alg, abs=1e-3)
+    assert rows["k_jx"][7].strip() == "-"
