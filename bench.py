@@ -125,6 +125,13 @@ def _line_tables(wl):
     return sweep, resid
 
 
+def _jx_grids(wl):
+    """grid x of the matrix-free product's launches on each group's finest grid (tiles of
+    15 x 15 vertex columns times segments of 8 vertices, 256 threads each) -> vertices."""
+    return {-(-q.nx // 15) * -(-q.ny // 15) * -(-q.nz // 8) * 256: q.nx * q.ny * q.nz
+            for q in wl.groups}
+
+
 def _dispatch_bytes(name, bx, wx, gx, rows, sweep, resid):
     """Algorithmic bytes of one smoother or residual dispatch (the library's count), or
     None for other kernels and ambiguous grids."""
@@ -211,9 +218,7 @@ def summarise_trace(d, leg, wl):
     for k, (n, us) in sorted(tot.items(), key=lambda kv: -kv[1][1])[:25]:
         out.append(f"| `{k}` | {n} | {us / n:.2f} | {us * 1e-3:.1f} | {100 * us * 1e-3 / allms:.1f} |")
     sweep, resid = _line_tables(wl)
-    fin = {}
-    for q in wl.groups:   # k_jx grid: tiles of 15 x 15 vertex columns x ceil(nz / 8) segments
-        fin[-(-q.nx // 15) * -(-q.ny // 15) * -(-q.nz // 8) * 256] = q.nx * q.ny * q.nz
+    fin = _jx_grids(wl)
     agg = collections.defaultdict(lambda: [0, 0.0, 0.0, 0.0])
     hist = collections.defaultdict(collections.Counter)
     for r in sel:
@@ -414,11 +419,8 @@ def counter_table(fetch_dir, write_dir, wl, by_matrix=False):
         ratio = (f + w) / b if b else float("nan")
         out.append(f"| {k} | {n} | {f / n / 1e6:.2f} | {w / max(wa.get(k, [1])[0], 1) / 1e6:.2f} | "
                    f"{b / n / 1e6:.2f} | {ratio:.3f} | {(f + w) / t / 1e9 if t else 0:.0f} |")
-    # the matrix-free product: JX_BYTES per vertex of its finest grid (tiles of 15 x 15
-    # vertex columns times segments of 8 vertices, 256 threads each)
-    fin = {}
-    for q in wl.groups:
-        fin[-(-q.nx // 15) * -(-q.ny // 15) * -(-q.nz // 8) * 256] = q.nx * q.ny * q.nz
+    # the matrix-free product: JX_BYTES per vertex of its finest grid
+    fin = _jx_grids(wl)
     for tag, (scale, _, times, grids, per) in (("fetch", runs["fetch"]), ("write", runs["write"])):
         tj = {}
         for di, (t0, t1, name) in times.items():
